@@ -1,0 +1,224 @@
+/*
+ * sgsolve -- intrusive stochastic Galerkin (SG) solver for the log-normal
+ * Poisson problem on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of arXiv 2310.14649, "Multilevel Scalable Solvers for
+ * Stochastic Linear and Nonlinear Problems": the Galerkin projection of
+ * -div(c(x,xi) grad u) = f onto a Hermite chaos (Sec. 2.1), solved by
+ * flexible GMRES preconditioned with a two-grid restricted additive Schwarz
+ * cycle whose coarse problem is handled by algebraic multigrid (Sec. 3).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * - All entry points are C functions returning an int status: SG_OK (0),
+ *   SG_NOT_CONVERGED (1, outputs and statistics still valid) or a negative
+ *   error code.  sg_last_error() returns a thread-local message for the last
+ *   failing call of the calling thread.  No C++ exception crosses the ABI.
+ * - "device" pointers are HIP device allocations of the current device
+ *   (e.g. torch tensors' data_ptr()); "host" pointers are ordinary memory.
+ *   The library never frees caller memory.
+ * - SG fields are row-major [n x P] FP64 arrays: X[a*P + k] is the k-th PCE
+ *   coefficient at unknown a (the vector-PDE layout of Sec. 2.1).
+ * - Handles (sg_basis, sg_op, sg_ras, sg_amg) are opaque and own their
+ *   device memory (allocated in the *_setup / build / assemble call, freed by
+ *   the matching sg_destroy_*).  They must be used on the device that was
+ *   current when they were created.
+ * - stream is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *   that only launch kernels are asynchronous on that stream; setup calls and
+ *   solve calls synchronise the stream before returning.
+ * - Calls sharing a handle must not run concurrently on different streams.
+ */
+#ifndef SGSOLVE_H
+#define SGSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SG_OK = 0,
+    SG_NOT_CONVERGED = 1,
+    SG_ERR_INVALID_ARG = -1,   /* bad size, null pointer, inconsistent handles */
+    SG_ERR_HIP = -2,           /* a HIP runtime call failed                     */
+    SG_ERR_NUMERIC = -3,       /* non-SPD local block, NaN/Inf in a reduction   */
+    SG_ERR_UNSUPPORTED = -4,   /* a size beyond a compiled limit                */
+    SG_ERR_WORKSPACE = -5      /* workspace too small                           */
+};
+
+typedef enum { SG_FP64 = 0, SG_FP32 = 1, SG_BF16 = 2 } sg_prec;
+
+typedef enum {
+    SG_COARSE_NONE = 0,        /* one-level RAS only                             */
+    SG_COARSE_MEAN_EXACT = 1,  /* (C_0 (x) G_0)^{-1}: exact mean-based coarse     */
+    SG_COARSE_AMG = 2          /* one smoothed-aggregation V(1,1) cycle on A_c    */
+} sg_coarse_kind;
+
+typedef struct sg_basis sg_basis;
+typedef struct sg_op sg_op;
+typedef struct sg_ras sg_ras;
+typedef struct sg_amg sg_amg;
+
+const char* sg_last_error(void);
+int sg_version(void);
+
+/* ------------------------------------------------------------------------
+ * sg_build_triples -- Hermite chaos basis and the triple-product tensor
+ * m_ijk = <Psi_i Psi_j Psi_k> of Eq. Galerkin_L_exp, keeping only non-zero
+ * entries (Sec. 2.1: only the non-zero multiplication-tensor entries are
+ * stored).  Psi_alpha = prod_m He_{alpha_m}(xi_m), probabilists' Hermite,
+ * un-normalised (<Psi_alpha^2> = alpha!).  Multi-indices with |alpha| <= p
+ * are ordered by total degree, then descending lexicographically; the input
+ * basis (|alpha| <= p_in, L_in = (M+p_in)!/(M! p_in!) terms, the count
+ * under Eq. inputpc) is the prefix of the output basis (P terms).
+ * i runs over the input basis, j and k over the output basis.
+ * The values are integers (exact in FP64), computed on the device.
+ * Limits: 0 <= M <= 8, 0 <= p_in <= p_out <= 4, P <= 128.
+ * Errors: SG_ERR_INVALID_ARG for out-of-range arguments.
+ * ---------------------------------------------------------------------- */
+int sg_build_triples(int M, int p_in, int p_out, sg_basis** out);
+int sg_basis_info(const sg_basis* b, int* P, int* L_in, int* n_triples);
+/* host outputs: alpha [P*M] int32, ijk [T*3] int32 (i,j,k), val [T] FP64.
+ * Triples are sorted by k, then i, then j.  Any pointer may be NULL. */
+int sg_basis_export(const sg_basis* b, int32_t* alpha, int32_t* ijk, double* val);
+void sg_destroy_basis(sg_basis* b);
+
+/* ------------------------------------------------------------------------
+ * sg_assemble -- the SG operator of Eq. Galerkin_L_exp on a P1 mesh.
+ * Inputs (all host, copied):
+ *   xy  [n_vert*2]   vertex coordinates
+ *   tri [n_tri*3]    counter-clockwise vertex triples
+ *   dof [n_vert]     unknown number of each vertex, -1 = Dirichlet (u = 0)
+ *   n                number of unknowns (max dof + 1)
+ *   g0  [n_tri]      mean of the Gaussian field at element centroids
+ *   g   [M*n_tri]    KL modes g_m at element centroids (row m contiguous)
+ * The device evaluates the log-normal input PCE (Eq. inputlogn, with the
+ * mean exp(g0 + |g|^2/2)) c_i = c0 prod_m g_m^{alpha_m}/alpha_m! at each
+ * centroid, and assembles one stiffness matrix per input term,
+ *   K_i[a,b] = sum_T c_i(x_T) |T| grad phi_a . grad phi_b,
+ * on one shared CSR pattern (entries whose geometric weight is zero in
+ * every element are left out), plus the load F[a] = sum_T |T|/3 (f = 1).
+ * Errors: SG_ERR_INVALID_ARG (degenerate or clockwise triangle, bad dof).
+ * ---------------------------------------------------------------------- */
+int sg_assemble(const sg_basis* b, int n_vert, const double* xy, int n_tri,
+                const int32_t* tri, const int32_t* dof, int n,
+                const double* g0, const double* g, sg_op** out, void* stream);
+int sg_op_info(const sg_op* op, int* n, int* P, int* L_in, int64_t* nnz);
+/* device output B [n*P]: the right-hand side b_k = f <Psi_k>, i.e. F in
+ * column 0 and zeros elsewhere (Eq. Galerkin_L_exp). */
+int sg_op_rhs(const sg_op* op, double* B, void* stream);
+/* host outputs: rowptr [n+1], col [nnz], vals [nnz*L_in] (entry-major). */
+int sg_op_export(const sg_op* op, int64_t* rowptr, int32_t* col, double* vals);
+void sg_destroy_op(sg_op* op);
+
+/* ------------------------------------------------------------------------
+ * sg_matvec -- Y = sum_i K_i X G_i, (G_i)_{kj} = m_ijk: the SG operator of
+ * Eq. Galerkin_L_exp in the vector-PDE layout (Eqs. linearVecPDE,
+ * Ajklinear).  X, Y: device [n*P] FP64, must not alias.  Asynchronous.
+ * ---------------------------------------------------------------------- */
+int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
+
+/* ------------------------------------------------------------------------
+ * ras_setup / ras_apply -- one-level restricted additive Schwarz, Eq. RASsto:
+ *   Z = sum_s R_s^T D_s (R_s K_0 R_s^T)^{-1} (R_s R) G_0^{-1}
+ * owner [n] (host): subdomain of every unknown (0..n_sub-1, D_s = owned).
+ * Subdomain s grows by `overlap` layers of mesh-graph neighbours.  The local
+ * solve is mean-based (K_0 and G_0 = diag(alpha!)), exact up to rounding:
+ * each local matrix is factored on the device as a block-tridiagonal matrix
+ * over breadth-first level sets, keeping the inverse of every Schur
+ * complement in `prec` (FP64, FP32 or BF16; FP32 accumulation for the low
+ * precisions).  Level sets wider than 64 nodes give SG_ERR_UNSUPPORTED; a
+ * non-positive pivot gives SG_ERR_NUMERIC.
+ * ras_apply: R, Z device [n*P] FP64, must not alias.  Asynchronous.
+ * ---------------------------------------------------------------------- */
+int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap,
+              sg_prec prec, sg_ras** out, void* stream);
+/* host outputs (any may be NULL): number of local nodes per subdomain
+ * [n_sub], number of level sets per subdomain [n_sub], and the total bytes
+ * of stored Schur-complement inverses. */
+int ras_info(const sg_ras* r, int32_t* n_local, int32_t* n_levels, int64_t* factor_bytes);
+int ras_apply(const sg_ras* r, const double* R, double* Z, void* stream);
+void sg_destroy_ras(sg_ras* r);
+
+/* ------------------------------------------------------------------------
+ * amg_setup / amg_vcycle -- the coarse problem of the two-grid cycle
+ * (Eq. coarse, A_c = R_0 A R_0^T) with the Nicolaides coarse space
+ * Z_s = R_s^T D_s 1 of the subdomains of `ras`, so that
+ *   A_c = sum_i (Z^T K_i Z) (x) G_i      (coarse vectors [n_sub*P]).
+ * kind SG_COARSE_MEAN_EXACT: x_c = (C_0 (x) G_0)^{-1} b_c, exact.
+ * kind SG_COARSE_AMG: one V(1,1) cycle of smoothed aggregation on A_c
+ * (strength theta = 0.08 on the mean-mode entries, three-pass greedy
+ * aggregation, prolongator smoothing with omega = (4/3)/rho(D^{-1}A),
+ * <= 4 levels / <= 8 block-nodes, damped block-Jacobi omega_s = 2/3 whose
+ * block inverses are stored in `prec`, coarsest level exact in FP64).
+ * b_c, x_c: device [n_sub*P] FP64.  Asynchronous.
+ * ---------------------------------------------------------------------- */
+int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec prec,
+              sg_amg** out, void* stream);
+/* host outputs: number of levels, and block-nodes per level [4]; agg, if
+ * not NULL, receives the first-level aggregate of every subdomain [n_sub]
+ * (-1 when there is a single level). */
+int amg_info(const sg_amg* a, int* n_levels, int32_t* nodes_per_level, int32_t* agg);
+int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream);
+/* r_c = Z^T R (sum over owned nodes) and Y += Z e_c.  Asynchronous. */
+int sg_coarse_restrict(const sg_amg* a, const double* R, double* r_c, void* stream);
+int sg_coarse_prolong_add(const sg_amg* a, const double* e_c, double* Y, void* stream);
+void sg_destroy_amg(sg_amg* a);
+
+/* ------------------------------------------------------------------------
+ * Two-grid preconditioner, Eq. RAS_2L read as the cycle the text describes
+ * (the printed Q P Q^{-1} term equals P^T):
+ *   z1 = w M r,  z2 = z1 + Q (r - A z1),  z = z2 + w M (r - A z2),
+ * M = ras, Q = Z (coarse solve of `amg`) Z^T, w = the smoother damping.
+ * amg may be NULL (one-level: z = w M r).  ws: device workspace of at
+ * least sg_precond_workspace_bytes(op, amg).  R, Z device [n*P], no alias.
+ * ---------------------------------------------------------------------- */
+size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg);
+int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
+                     const double* R, double* Z, void* ws, size_t ws_bytes, void* stream);
+/* Damping of the smoother: rho = power estimate of rho(M A) (`its`
+ * iterations from the all-ones field); omega = min(1, 1.6/rho).  Synchronous. */
+int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho,
+                        double* omega, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * fgmres_solve -- right-preconditioned flexible GMRES(m) (the outer solver
+ * of Secs. 3-4) in FP64: modified Gram-Schmidt Arnoldi, Givens rotations,
+ * stopping test |g_{j+1}| <= rtol ||b|| (relative to the right-hand side),
+ * confirmed by the true residual ||b - A x||; restart from x otherwise.
+ * x holds the initial guess on entry and the solution on return (device).
+ * ras/amg may be NULL (no preconditioner / one-level).  ws: device
+ * workspace of at least fgmres_workspace_bytes(op, amg, restart).
+ * Returns SG_OK, SG_NOT_CONVERGED (max_it reached) or an error.
+ * Synchronous; the host reads one residual estimate per iteration.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int restart;        /* m (>= 1)                                   */
+    int max_it;         /* total Arnoldi steps allowed                */
+    double rtol;        /* relative to ||b||                          */
+    double omega;       /* smoother damping (<= 0: estimate it)       */
+} sg_krylov_opts;
+
+typedef struct {
+    int iterations;
+    int restarts;
+    int converged;
+    double true_relres;      /* ||b - A x|| / ||b|| at return          */
+    double omega;            /* damping used                           */
+    double ms_solve;         /* wall time of the Krylov loop            */
+    double* history;         /* host, may be NULL: estimate / ||b||     */
+    int history_cap;         /* entries available in history            */
+    int history_len;         /* entries written                         */
+} sg_krylov_stats;
+
+size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart);
+int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
+                 const double* b, double* x, const sg_krylov_opts* opts,
+                 sg_krylov_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGSOLVE_H */

@@ -1,0 +1,288 @@
+"""ctypes binding of ``libsgsolve.so``: one Python function per C entry
+point, same names, argument marshalling only (host arrays are NumPy, device
+arrays are torch tensors on the current HIP device).  Every numerical step
+runs in the library's kernels; there is no fallback: importing the library
+fails loudly when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgsolve.so")
+
+SG_OK, SG_NOT_CONVERGED = 0, 1
+SG_FP64, SG_FP32, SG_BF16 = 0, 1, 2
+SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG = 0, 1, 2
+PREC = {"fp64": SG_FP64, "fp32": SG_FP32, "bf16": SG_BF16}
+
+_vp = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_f64p = C.POINTER(C.c_double)
+
+
+class SgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sgsolve error {code}: {msg}")
+        self.code = code
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_it", C.c_int), ("rtol", C.c_double),
+                ("omega", C.c_double)]
+
+
+class KrylovStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("true_relres", C.c_double), ("omega", C.c_double), ("ms_solve", C.c_double),
+                ("history", _f64p), ("history_cap", C.c_int), ("history_len", C.c_int)]
+
+
+_SIGS = {
+    "sg_last_error": (C.c_char_p, []),
+    "sg_version": (C.c_int, []),
+    "sg_build_triples": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(_vp)]),
+    "sg_basis_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "sg_basis_export": (C.c_int, [_vp, _i32p, _i32p, _f64p]),
+    "sg_destroy_basis": (None, [_vp]),
+    "sg_assemble": (C.c_int, [_vp, C.c_int, _f64p, C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p,
+                              C.POINTER(_vp), _vp]),
+    "sg_op_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int64)]),
+    "sg_op_rhs": (C.c_int, [_vp, _vp, _vp]),
+    "sg_op_export": (C.c_int, [_vp, _i64p, _i32p, _f64p]),
+    "sg_destroy_op": (None, [_vp]),
+    "sg_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "ras_setup": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
+    "ras_info": (C.c_int, [_vp, _i32p, _i32p, _i64p]),
+    "ras_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_destroy_ras": (None, [_vp]),
+    "amg_setup": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
+    "amg_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i32p, _i32p]),
+    "amg_vcycle": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_coarse_restrict": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_coarse_prolong_add": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_destroy_amg": (None, [_vp]),
+    "sg_precond_workspace_bytes": (C.c_size_t, [_vp, _vp]),
+    "sg_precond_apply": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "sg_smoother_damping": (C.c_int, [_vp, _vp, C.c_int, _f64p, _f64p, _vp, C.c_size_t, _vp]),
+    "fgmres_workspace_bytes": (C.c_size_t, [_vp, _vp, C.c_int]),
+    "fgmres_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(KrylovOpts),
+                               C.POINTER(KrylovStats), _vp, C.c_size_t, _vp]),
+}
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SgError(rc, lib().sg_last_error().decode())
+    return rc
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _dev(t) -> C.c_void_p:
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> C.c_void_p:
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- basis
+def sg_build_triples(M: int, p_in: int, p_out: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().sg_build_triples(M, p_in, p_out, C.byref(h)))
+    return h
+
+
+def sg_basis_info(b):
+    P, L, T = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().sg_basis_info(b, C.byref(P), C.byref(L), C.byref(T)))
+    return P.value, L.value, T.value
+
+
+def sg_basis_export(b, M: int):
+    P, L, T = sg_basis_info(b)
+    alpha = np.zeros(P * max(M, 1), dtype=np.int32)
+    ijk = np.zeros(T * 3, dtype=np.int32)
+    val = np.zeros(T, dtype=np.float64)
+    _check(lib().sg_basis_export(b, _ptr(alpha, C.c_int32), _ptr(ijk, C.c_int32),
+                                 _ptr(val, C.c_double)))
+    return alpha[:P * M].reshape(P, M), ijk.reshape(T, 3), val
+
+
+def sg_destroy_basis(b):
+    lib().sg_destroy_basis(b)
+
+
+# ---------------------------------------------------------------- operator
+def sg_assemble(basis, xy: np.ndarray, tri: np.ndarray, dof: np.ndarray, n: int,
+                g0: np.ndarray, g: np.ndarray, stream=None) -> C.c_void_p:
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    dof = np.ascontiguousarray(dof, dtype=np.int32)
+    g0 = np.ascontiguousarray(g0, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    h = C.c_void_p()
+    gp = _ptr(g, C.c_double) if g.size else None
+    _check(lib().sg_assemble(basis, xy.shape[0], _ptr(xy, C.c_double), tri.shape[0],
+                             _ptr(tri, C.c_int32), _ptr(dof, C.c_int32), n,
+                             _ptr(g0, C.c_double), gp, C.byref(h), _stream(stream)))
+    return h
+
+
+def sg_op_info(op):
+    n, P, L, nnz = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
+    _check(lib().sg_op_info(op, C.byref(n), C.byref(P), C.byref(L), C.byref(nnz)))
+    return n.value, P.value, L.value, nnz.value
+
+
+def sg_op_rhs(op, B, stream=None):
+    _check(lib().sg_op_rhs(op, _dev(B), _stream(stream)))
+
+
+def sg_op_export(op):
+    n, P, L, nnz = sg_op_info(op)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(nnz, dtype=np.int32)
+    vals = np.zeros(nnz * L, dtype=np.float64)
+    _check(lib().sg_op_export(op, _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
+                              _ptr(vals, C.c_double)))
+    return rowptr, col, vals.reshape(nnz, L)
+
+
+def sg_destroy_op(op):
+    lib().sg_destroy_op(op)
+
+
+def sg_matvec(op, X, Y, stream=None):
+    _check(lib().sg_matvec(op, _dev(X), _dev(Y), _stream(stream)))
+
+
+# ---------------------------------------------------------------- RAS
+def ras_setup(op, owner: np.ndarray, n_sub: int, overlap: int, prec: int = SG_FP64,
+              stream=None):
+    owner = np.ascontiguousarray(owner, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().ras_setup(op, _ptr(owner, C.c_int32), n_sub, overlap, prec, C.byref(h),
+                           _stream(stream)))
+    return h
+
+
+def ras_info(r, n_sub: int):
+    nloc = np.zeros(n_sub, dtype=np.int32)
+    nlev = np.zeros(n_sub, dtype=np.int32)
+    fb = C.c_int64()
+    _check(lib().ras_info(r, _ptr(nloc, C.c_int32), _ptr(nlev, C.c_int32), C.byref(fb)))
+    return nloc, nlev, fb.value
+
+
+def ras_apply(r, R, Z, stream=None):
+    _check(lib().ras_apply(r, _dev(R), _dev(Z), _stream(stream)))
+
+
+def sg_destroy_ras(r):
+    lib().sg_destroy_ras(r)
+
+
+# ---------------------------------------------------------------- coarse
+def amg_setup(op, ras, kind: int = SG_COARSE_AMG, prec: int = SG_FP64, stream=None):
+    h = C.c_void_p()
+    _check(lib().amg_setup(op, ras, kind, prec, C.byref(h), _stream(stream)))
+    return h
+
+
+def amg_info(a, n_sub: int):
+    nl = C.c_int()
+    nodes = np.zeros(8, dtype=np.int32)
+    agg = np.zeros(n_sub, dtype=np.int32)
+    _check(lib().amg_info(a, C.byref(nl), _ptr(nodes, C.c_int32), _ptr(agg, C.c_int32)))
+    return nl.value, nodes[:nl.value], agg
+
+
+def amg_vcycle(a, b_c, x_c, stream=None):
+    _check(lib().amg_vcycle(a, _dev(b_c), _dev(x_c), _stream(stream)))
+
+
+def sg_coarse_restrict(a, R, r_c, stream=None):
+    _check(lib().sg_coarse_restrict(a, _dev(R), _dev(r_c), _stream(stream)))
+
+
+def sg_coarse_prolong_add(a, e_c, Y, stream=None):
+    _check(lib().sg_coarse_prolong_add(a, _dev(e_c), _dev(Y), _stream(stream)))
+
+
+def sg_destroy_amg(a):
+    lib().sg_destroy_amg(a)
+
+
+# ---------------------------------------------------------------- solver
+def sg_precond_workspace_bytes(op, amg) -> int:
+    return int(lib().sg_precond_workspace_bytes(op, amg))
+
+
+def sg_precond_apply(op, ras, amg, omega: float, R, Z, ws, stream=None):
+    nbytes = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().sg_precond_apply(op, ras, amg, omega, _dev(R), _dev(Z), _dev(ws), nbytes,
+                                  _stream(stream)))
+
+
+def sg_smoother_damping(op, ras, its, ws, stream=None):
+    rho, om = C.c_double(), C.c_double()
+    _check(lib().sg_smoother_damping(op, ras, its, C.byref(rho), C.byref(om), _dev(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)))
+    return rho.value, om.value
+
+
+def fgmres_workspace_bytes(op, amg, restart: int) -> int:
+    return int(lib().fgmres_workspace_bytes(op, amg, restart))
+
+
+def fgmres_solve(op, ras, amg, b, x, restart: int, max_it: int, rtol: float, omega: float,
+                 ws, history_cap: int = 4096, stream=None):
+    opts = KrylovOpts(restart, max_it, rtol, omega)
+    hist = np.zeros(history_cap, dtype=np.float64)
+    st = KrylovStats()
+    st.history = _ptr(hist, C.c_double)
+    st.history_cap = history_cap
+    rc = _check(lib().fgmres_solve(op, ras, amg, _dev(b), _dev(x), C.byref(opts), C.byref(st),
+                                   _dev(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return dict(status=rc, iterations=st.iterations, restarts=st.restarts,
+                converged=bool(st.converged), true_relres=st.true_relres, omega=st.omega,
+                ms_solve=st.ms_solve, history=hist[:st.history_len].copy())

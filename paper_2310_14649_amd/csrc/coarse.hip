@@ -1,0 +1,684 @@
+// Coarse problem of the two-grid cycle (Eq. coarse, A_c = R_0 A R_0^T) with
+// the Nicolaides coarse space: one vector per subdomain and PCE mode, the
+// indicator of the nodes the subdomain owns.  Then
+//     A_c = sum_i (Z^T K_i Z) (x) G_i =: sum_i C_i (x) G_i,
+// the same Kronecker-sum structure as the fine operator on the graph of
+// subdomains.  C_i is summed on the device from the fine values in a fixed
+// order.  Two coarse solvers:
+//   * mean-based exact: (C_0 (x) G_0)^{-1}, a dense n_sub x n_sub inverse;
+//   * one V(1,1) cycle of smoothed-aggregation AMG on A_c (the paper's
+//     2GV3 coarse solve uses BoomerAMG; its parameters are not given, so the
+//     fixed definition below is used).  The hierarchy is built on the host
+//     in FP64 (block-sparse matrices with dense P x P blocks, a few hundred
+//     block-nodes); the cycle runs on the device.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+
+namespace sg {
+namespace amgc {
+constexpr double kTheta = 0.08;
+constexpr double kOmegaS = 2.0 / 3.0;
+constexpr int kMaxLevels = 4;
+constexpr int kMinNodes = 8;
+constexpr int kPowerIts = 15;
+}  // namespace amgc
+
+// Host block-sparse matrix with dense P x P row-major blocks.
+struct Bsr {
+    int nr = 0, nc = 0, P = 0;
+    std::vector<int32_t> ptr, col;
+    std::vector<double> val;
+    double* blk(size_t q) { return val.data() + q * (size_t)P * P; }
+    const double* blk(size_t q) const { return val.data() + q * (size_t)P * P; }
+};
+
+struct AmgLevel {
+    int nn = 0;
+    DevBuf<int32_t> a_ptr, a_col, p_ptr, p_col, r_ptr, r_col;
+    DevBuf<double> a_val, p_val, r_val, dinv64, x, b, r;
+    DevBuf<float> dinv32;
+    DevBuf<uint16_t> dinv16;
+};
+
+}  // namespace sg
+
+struct sg_amg {
+    int device = 0;
+    sg_coarse_kind kind = SG_COARSE_AMG;
+    sg_prec prec = SG_FP64;
+    int n = 0, n_sub = 0, P = 0, L = 0;
+    sg::DevBuf<int32_t> own_ptr, own_nodes, owner;
+    sg::DevBuf<double> afact;
+    sg::DevBuf<double> c0inv;                 // mean-exact
+    std::vector<sg::AmgLevel> lev;            // AMG levels (last = coarsest)
+    sg::DevBuf<double> coarsest_inv;
+    int coarsest_n = 0;
+    std::vector<int32_t> h_nodes, h_agg0;
+    std::vector<double> h_omegas;
+};
+
+namespace sg {
+namespace {
+
+constexpr int kBlk = 128;   // threads per block-row kernel (P <= 128)
+
+__global__ void coarse_entries_kernel(int64_t nce, int L, const int64_t* __restrict__ cptr,
+                                      const int64_t* __restrict__ fine,
+                                      const double* __restrict__ vals, double* __restrict__ C) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nce * L) return;
+    int64_t ce = idx / L;
+    int i = (int)(idx - ce * L);
+    double acc = 0.0;
+    for (int64_t q = cptr[ce]; q < cptr[ce + 1]; ++q) acc += vals[fine[q] * L + i];
+    C[idx] = acc;
+}
+
+// r_c[s, k] = sum over owned nodes a of R[a, k]; fixed-order partial sums.
+__global__ __launch_bounds__(256) void restrict_kernel(int P, const int32_t* __restrict__ own_ptr,
+                                                       const int32_t* __restrict__ own_nodes,
+                                                       const double* __restrict__ R,
+                                                       double* __restrict__ rc) {
+    __shared__ double part[256];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int stripes = 256 / P;
+    const int k = tid % P, st = tid / P;
+    double acc = 0.0;
+    if (st < stripes)
+        for (int q = own_ptr[s] + st; q < own_ptr[s + 1]; q += stripes)
+            acc += R[(size_t)own_nodes[q] * P + k];
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < P) {
+        double t = 0.0;
+        for (int w = 0; w < stripes; ++w) t += part[w * P + tid];
+        rc[(size_t)s * P + tid] = t;
+    }
+}
+
+__global__ void prolong_add_kernel(int64_t total, int P, const int32_t* __restrict__ owner,
+                                   const double* __restrict__ ec, double* __restrict__ Y) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t a = idx / P;
+    int k = (int)(idx - a * P);
+    Y[idx] += ec[(size_t)owner[a] * P + k];
+}
+
+// x[s, k] = sum_t C0inv[s, t] b[t, k] / alpha_k!
+__global__ void mean_exact_kernel(int ns, int P, const double* __restrict__ inv,
+                                  const double* __restrict__ afact, const double* __restrict__ b,
+                                  double* __restrict__ x) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ns * P) return;
+    int s = idx / P, k = idx - (idx / P) * P;
+    double acc = 0.0;
+    for (int t = 0; t < ns; ++t) acc += inv[(size_t)s * ns + t] * b[(size_t)t * P + k];
+    x[idx] = acc / afact[k];
+}
+
+// y = beta * c + alpha * A x   (block-sparse, dense P x P blocks); one
+// work-group per block-row, thread k owns output row k.
+__global__ __launch_bounds__(kBlk) void bsr_mv_kernel(int P, const int32_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ x, double* y,
+                                                      double alpha, double beta, const double* c) {
+    const int s = blockIdx.x;
+    for (int k = threadIdx.x; k < P; k += kBlk) {
+        double acc = 0.0;
+        for (int q = ptr[s]; q < ptr[s + 1]; ++q) {
+            const double* blk = val + (size_t)q * P * P + (size_t)k * P;
+            const double* xv = x + (size_t)col[q] * P;
+            for (int j = 0; j < P; ++j) acc = fma(blk[j], xv[j], acc);
+        }
+        const size_t o = (size_t)s * P + k;
+        double v = alpha * acc;
+        if (beta != 0.0) v = fma(beta, c[o], v);
+        y[o] = v;
+    }
+}
+
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// x_s = beta * x_s + omega * D_s^{-1} r_s  (block-Jacobi), D^{-1} in TS.
+template <class TS>
+__global__ __launch_bounds__(kBlk) void jacobi_kernel(int P, const TS* __restrict__ dinv,
+                                                      const double* __restrict__ r, double* x,
+                                                      double omega, double beta) {
+    const int s = blockIdx.x;
+    for (int k = threadIdx.x; k < P; k += kBlk) {
+        const TS* blk = dinv + (size_t)s * P * P + (size_t)k * P;
+        const double* rv = r + (size_t)s * P;
+        double acc = 0.0;
+        if constexpr (sizeof(TS) == 8) {
+            for (int j = 0; j < P; ++j) acc = fma((double)blk[j], rv[j], acc);
+        } else {
+            float f = 0.0f;
+            for (int j = 0; j < P; ++j) {
+                float d;
+                if constexpr (sizeof(TS) == 4) d = (float)blk[j];
+                else d = bf16_to_f((uint16_t)blk[j]);
+                f = fmaf(d, (float)rv[j], f);
+            }
+            acc = (double)f;
+        }
+        const size_t o = (size_t)s * P + k;
+        x[o] = (beta != 0.0 ? beta * x[o] : 0.0) + omega * acc;
+    }
+}
+
+__global__ void dense_mv_kernel(int N, const double* __restrict__ A, const double* __restrict__ b,
+                                double* __restrict__ x) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int j = 0; j < N; ++j) acc = fma(A[(size_t)i * N + j], b[j], acc);
+    x[i] = acc;
+}
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- host FP64
+// In-place inverse of a dense SPD-or-general N x N matrix (Gauss-Jordan with
+// partial pivoting).  Throws SG_ERR_NUMERIC on a zero pivot.
+void invert_dense(std::vector<double>& A, int N) {
+    std::vector<int> perm(N);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<double> I((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) I[(size_t)i * N + i] = 1.0;
+    for (int k = 0; k < N; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < N; ++i)
+            if (std::fabs(A[(size_t)i * N + k]) > std::fabs(A[(size_t)piv * N + k])) piv = i;
+        double pv = A[(size_t)piv * N + k];
+        if (!(std::fabs(pv) > 0.0) || !std::isfinite(pv))
+            SG_THROW(SG_ERR_NUMERIC, "singular block in the coarse hierarchy");
+        if (piv != k)
+            for (int j = 0; j < N; ++j) {
+                std::swap(A[(size_t)k * N + j], A[(size_t)piv * N + j]);
+                std::swap(I[(size_t)k * N + j], I[(size_t)piv * N + j]);
+            }
+        double ip = 1.0 / A[(size_t)k * N + k];
+        for (int j = 0; j < N; ++j) {
+            A[(size_t)k * N + j] *= ip;
+            I[(size_t)k * N + j] *= ip;
+        }
+        for (int i = 0; i < N; ++i) {
+            if (i == k) continue;
+            double f = A[(size_t)i * N + k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < N; ++j) {
+                A[(size_t)i * N + j] -= f * A[(size_t)k * N + j];
+                I[(size_t)i * N + j] -= f * I[(size_t)k * N + j];
+            }
+        }
+    }
+    A.swap(I);
+}
+
+// C (+)= A * B for dense P x P blocks
+inline void gemm_acc(int P, const double* A, const double* B, double* C) {
+    for (int i = 0; i < P; ++i)
+        for (int k = 0; k < P; ++k) {
+            double a = A[(size_t)i * P + k];
+            if (a == 0.0) continue;
+            const double* b = B + (size_t)k * P;
+            double* c = C + (size_t)i * P;
+            for (int j = 0; j < P; ++j) c[j] += a * b[j];
+        }
+}
+
+Bsr bsr_mul(const Bsr& A, const Bsr& B) {
+    const int P = A.P;
+    Bsr C;
+    C.nr = A.nr; C.nc = B.nc; C.P = P;
+    C.ptr.assign(A.nr + 1, 0);
+    std::vector<double> acc;
+    for (int s = 0; s < A.nr; ++s) {
+        std::map<int, size_t> slot;
+        std::vector<double> blocks;
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
+            int t = A.col[q];
+            for (int q2 = B.ptr[t]; q2 < B.ptr[t + 1]; ++q2) {
+                int u = B.col[q2];
+                auto it = slot.find(u);
+                size_t idx;
+                if (it == slot.end()) {
+                    idx = slot.size();
+                    slot[u] = idx;
+                    blocks.resize((idx + 1) * (size_t)P * P, 0.0);
+                } else {
+                    idx = it->second;
+                }
+                gemm_acc(P, A.blk(q), B.blk(q2), blocks.data() + idx * (size_t)P * P);
+            }
+        }
+        for (auto& kv : slot) {
+            C.col.push_back(kv.first);
+            C.val.insert(C.val.end(), blocks.begin() + kv.second * (size_t)P * P,
+                         blocks.begin() + (kv.second + 1) * (size_t)P * P);
+        }
+        C.ptr[s + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+Bsr bsr_transpose(const Bsr& A) {
+    const int P = A.P;
+    Bsr T;
+    T.nr = A.nc; T.nc = A.nr; T.P = P;
+    T.ptr.assign(A.nc + 1, 0);
+    for (int q = 0; q < (int)A.col.size(); ++q) T.ptr[A.col[q] + 1]++;
+    for (int i = 0; i < A.nc; ++i) T.ptr[i + 1] += T.ptr[i];
+    T.col.resize(A.col.size());
+    T.val.resize(A.val.size());
+    std::vector<int32_t> fill(T.ptr.begin(), T.ptr.end() - 1);
+    for (int s = 0; s < A.nr; ++s)
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
+            int d = fill[A.col[q]]++;
+            T.col[d] = s;
+            const double* src = A.blk(q);
+            double* dst = T.blk(d);
+            for (int i = 0; i < P; ++i)
+                for (int j = 0; j < P; ++j) dst[(size_t)j * P + i] = src[(size_t)i * P + j];
+        }
+    return T;
+}
+
+void bsr_apply(const Bsr& A, const std::vector<double>& x, std::vector<double>& y) {
+    const int P = A.P;
+    y.assign((size_t)A.nr * P, 0.0);
+    for (int s = 0; s < A.nr; ++s)
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
+            const double* b = A.blk(q);
+            const double* xv = x.data() + (size_t)A.col[q] * P;
+            for (int i = 0; i < P; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < P; ++j) acc += b[(size_t)i * P + j] * xv[j];
+                y[(size_t)s * P + i] += acc;
+            }
+        }
+}
+
+std::vector<int> aggregate(const Bsr& A) {
+    const int nn = A.nr;
+    std::vector<double> diag(nn, 0.0);
+    for (int s = 0; s < nn; ++s)
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q)
+            if (A.col[q] == s) diag[s] = std::fabs(A.blk(q)[0]);
+    std::vector<std::vector<std::pair<int, double>>> nb(nn);
+    for (int s = 0; s < nn; ++s)
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
+            int t = A.col[q];
+            double v = A.blk(q)[0];
+            if (t != s && v != 0.0 && std::fabs(v) >= amgc::kTheta * std::sqrt(diag[s] * diag[t]))
+                nb[s].push_back({t, std::fabs(v)});
+        }
+    std::vector<int> agg(nn, -1);
+    int na = 0;
+    for (int i = 0; i < nn; ++i) {      // pass 1
+        if (agg[i] >= 0) continue;
+        bool free_nb = true;
+        for (auto& p : nb[i]) free_nb &= agg[p.first] < 0;
+        if (!free_nb) continue;
+        agg[i] = na;
+        for (auto& p : nb[i]) agg[p.first] = na;
+        ++na;
+    }
+    std::vector<int> snap = agg;
+    for (int i = 0; i < nn; ++i) {      // pass 2
+        if (agg[i] >= 0) continue;
+        int best = -1;
+        double bv = -1.0;
+        for (auto& p : nb[i])
+            if (snap[p.first] >= 0 && p.second > bv) { best = p.first; bv = p.second; }
+        if (best >= 0) agg[i] = snap[best];
+    }
+    for (int i = 0; i < nn; ++i) {      // pass 3
+        if (agg[i] >= 0) continue;
+        agg[i] = na;
+        for (auto& p : nb[i])
+            if (agg[p.first] < 0) agg[p.first] = na;
+        ++na;
+    }
+    return agg;
+}
+
+void upload_bsr(const Bsr& A, DevBuf<int32_t>& ptr, DevBuf<int32_t>& col, DevBuf<double>& val,
+                hipStream_t s) {
+    ptr.upload(A.ptr, s);
+    col.upload(A.col, s);
+    val.upload(A.val, s);
+}
+
+}  // namespace
+
+void amg_vcycle_level(const sg_amg* a, int l, const double* b, double* x, hipStream_t s) {
+    const int P = a->P;
+    const AmgLevel& L = a->lev[l];
+    if (l == (int)a->lev.size() - 1) {
+        int N = a->coarsest_n;
+        dense_mv_kernel<<<(N + 127) / 128, 128, 0, s>>>(N, a->coarsest_inv.p, b, x);
+        HIP_LAUNCH_OK();
+        return;
+    }
+    const AmgLevel& C = a->lev[l + 1];
+    auto jacobi = [&](const double* r, double beta) {
+        if (a->prec == SG_FP64)
+            jacobi_kernel<double><<<L.nn, kBlk, 0, s>>>(P, L.dinv64.p, r, x, amgc::kOmegaS, beta);
+        else if (a->prec == SG_FP32)
+            jacobi_kernel<float><<<L.nn, kBlk, 0, s>>>(P, L.dinv32.p, r, x, amgc::kOmegaS, beta);
+        else
+            jacobi_kernel<uint16_t><<<L.nn, kBlk, 0, s>>>(P, L.dinv16.p, r, x, amgc::kOmegaS, beta);
+        HIP_LAUNCH_OK();
+    };
+    jacobi(b, 0.0);
+    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    HIP_LAUNCH_OK();
+    bsr_mv_kernel<<<C.nn, kBlk, 0, s>>>(P, L.r_ptr.p, L.r_col.p, L.r_val.p, L.r.p, C.b.p, 1.0, 0.0,
+                                        nullptr);
+    HIP_LAUNCH_OK();
+    amg_vcycle_level(a, l + 1, C.b.p, C.x.p, s);
+    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, C.x.p, x, 1.0, 1.0, x);
+    HIP_LAUNCH_OK();
+    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    HIP_LAUNCH_OK();
+    jacobi(L.r.p, 1.0);
+}
+
+void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
+    if (a->kind == SG_COARSE_MEAN_EXACT) {
+        int tot = a->n_sub * a->P;
+        mean_exact_kernel<<<(tot + 127) / 128, 128, 0, s>>>(a->n_sub, a->P, a->c0inv.p, a->afact.p,
+                                                             b, x);
+        HIP_LAUNCH_OK();
+    } else {
+        amg_vcycle_level(a, 0, b, x, s);
+    }
+}
+
+int amg_nsub(const sg_amg* a) { return a->n_sub; }
+int amg_device(const sg_amg* a) { return a->device; }
+
+void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s) {
+    restrict_kernel<<<a->n_sub, 256, 0, s>>>(a->P, a->own_ptr.p, a->own_nodes.p, R, rc);
+    HIP_LAUNCH_OK();
+}
+
+void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s) {
+    int64_t tot = (int64_t)a->n * a->P;
+    prolong_add_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, a->P, a->owner.p, ec, Y);
+    HIP_LAUNCH_OK();
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec prec,
+              sg_amg** out, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && ras && out, "null argument");
+        SG_REQUIRE(kind == SG_COARSE_MEAN_EXACT || kind == SG_COARSE_AMG, "bad coarse kind");
+        SG_REQUIRE(prec == SG_FP64 || prec == SG_FP32 || prec == SG_BF16, "bad precision");
+        SG_REQUIRE(op->P <= kBlk, "P=%d exceeds %d in the coarse solver", op->P, kBlk);
+        check_device(op->device);
+        SG_REQUIRE(ras_device(ras) == op->device, "ras and op on different devices");
+        hipStream_t s = as_stream(stream);
+        const int n = op->n, P = op->P, L = op->L;
+        const int ns = ras_nsub(ras);
+        const std::vector<int32_t>& owner = ras_owner(ras);
+        SG_REQUIRE((int)owner.size() == n, "ras built for another operator");
+        SG_REQUIRE(256 / P >= 1, "P too large for the restriction kernel");
+        auto a = std::make_unique<sg_amg>();
+        a->device = op->device; a->kind = kind; a->prec = prec;
+        a->n = n; a->n_sub = ns; a->P = P; a->L = L;
+
+        // owned-node lists and owner map
+        std::vector<int32_t> own_ptr(ns + 1, 0), own_nodes(n);
+        for (int q = 0; q < n; ++q) own_ptr[owner[q] + 1]++;
+        for (int q = 0; q < ns; ++q) own_ptr[q + 1] += own_ptr[q];
+        {
+            std::vector<int32_t> fill(own_ptr.begin(), own_ptr.end() - 1);
+            for (int q = 0; q < n; ++q) own_nodes[fill[owner[q]]++] = q;
+        }
+        a->own_ptr.upload(own_ptr, s);
+        a->own_nodes.upload(own_nodes, s);
+        a->owner.upload(owner, s);
+        a->afact.upload(op->h_afact, s);
+
+        // coarse pattern and the fine entries of every coarse entry
+        std::vector<std::pair<int64_t, int64_t>> keyed;   // (coarse key, fine entry)
+        keyed.reserve(op->nnz);
+        for (int r = 0; r < n; ++r)
+            for (int e = op->h_rowptr[r]; e < op->h_rowptr[r + 1]; ++e)
+                keyed.push_back({(int64_t)owner[r] * ns + owner[op->h_col[e]], (int64_t)e});
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const auto& x, const auto& y) { return x.first < y.first; });
+        std::vector<int32_t> cptr_row(ns + 1, 0), ccol;
+        std::vector<int64_t> cptr(1, 0), cfine;
+        for (size_t q = 0; q < keyed.size();) {
+            size_t q1 = q;
+            while (q1 < keyed.size() && keyed[q1].first == keyed[q].first) cfine.push_back(keyed[q1++].second);
+            ccol.push_back((int32_t)(keyed[q].first % ns));
+            cptr_row[keyed[q].first / ns + 1]++;
+            cptr.push_back((int64_t)cfine.size());
+            q = q1;
+        }
+        for (int q = 0; q < ns; ++q) cptr_row[q + 1] += cptr_row[q];
+        const int64_t nce = (int64_t)ccol.size();
+        DevBuf<int64_t> d_cptr, d_cfine;
+        DevBuf<double> d_C(nce * L);
+        d_cptr.upload(cptr, s);
+        d_cfine.upload(cfine, s);
+        coarse_entries_kernel<<<(unsigned)((nce * L + 255) / 256), 256, 0, s>>>(
+            nce, L, d_cptr.p, d_cfine.p, op->vals.p, d_C.p);
+        HIP_LAUNCH_OK();
+        std::vector<double> C((size_t)nce * L);
+        d_C.download(C.data(), C.size(), s);
+        HIP_OK(hipStreamSynchronize(s));
+
+        if (kind == SG_COARSE_MEAN_EXACT) {
+            std::vector<double> C0((size_t)ns * ns, 0.0);
+            for (int r = 0; r < ns; ++r)
+                for (int q = cptr_row[r]; q < cptr_row[r + 1]; ++q)
+                    C0[(size_t)r * ns + ccol[q]] = C[(size_t)q * L];
+            invert_dense(C0, ns);
+            a->c0inv.upload(C0, s);
+            a->h_nodes = {ns};
+            a->h_agg0.assign(ns, -1);
+            HIP_OK(hipStreamSynchronize(s));
+            *out = a.release();
+            return SG_OK;
+        }
+
+        // level 0 block matrix: block (s,t) = sum_i C_i[s,t] G_i
+        const sg_basis& B = op->basis;
+        Bsr A;
+        A.nr = A.nc = ns; A.P = P;
+        A.ptr = cptr_row;
+        A.col = ccol;
+        A.val.assign((size_t)nce * P * P, 0.0);
+        for (int64_t q = 0; q < nce; ++q) {
+            double* blk = A.blk(q);
+            for (int t = 0; t < B.T; ++t)
+                blk[(size_t)B.tk[t] * P + B.tj[t]] += C[(size_t)q * L + B.ti[t]] * B.tv[t];
+        }
+        std::vector<Bsr> As{A}, Ps;
+        std::vector<std::vector<double>> Dinvs;
+        while ((int)As.size() < amgc::kMaxLevels && As.back().nr > amgc::kMinNodes) {
+            const Bsr& Al = As.back();
+            std::vector<int> agg = aggregate(Al);
+            int na = *std::max_element(agg.begin(), agg.end()) + 1;
+            if (na >= Al.nr) break;
+            if (As.size() == 1) a->h_agg0.assign(agg.begin(), agg.end());
+            // block-diagonal inverse
+            std::vector<double> Dinv((size_t)Al.nr * P * P);
+            for (int r = 0; r < Al.nr; ++r) {
+                bool found = false;
+                for (int q = Al.ptr[r]; q < Al.ptr[r + 1]; ++q)
+                    if (Al.col[q] == r) {
+                        std::vector<double> D(Al.blk(q), Al.blk(q) + (size_t)P * P);
+                        invert_dense(D, P);
+                        std::copy(D.begin(), D.end(), Dinv.begin() + (size_t)r * P * P);
+                        found = true;
+                    }
+                if (!found) SG_THROW(SG_ERR_NUMERIC, "missing diagonal block");
+            }
+            // spectral radius of D^{-1} A by power iteration from ones
+            std::vector<double> v((size_t)Al.nr * P, 1.0), w, dw((size_t)Al.nr * P);
+            double nv = std::sqrt((double)v.size());
+            for (auto& e : v) e /= nv;
+            double rho = 0.0;
+            for (int it = 0; it < amgc::kPowerIts; ++it) {
+                bsr_apply(Al, v, w);
+                for (int r = 0; r < Al.nr; ++r)
+                    for (int i = 0; i < P; ++i) {
+                        double acc = 0.0;
+                        for (int j = 0; j < P; ++j)
+                            acc += Dinv[(size_t)r * P * P + (size_t)i * P + j] * w[(size_t)r * P + j];
+                        dw[(size_t)r * P + i] = acc;
+                    }
+                double nw = 0.0;
+                for (double e : dw) nw += e * e;
+                rho = std::sqrt(nw);
+                for (size_t q = 0; q < v.size(); ++q) v[q] = dw[q] / rho;
+            }
+            const double omega = (4.0 / 3.0) / rho;
+            a->h_omegas.push_back(omega);
+            // tentative prolongator and its smoothing P = T - omega D^{-1} A T
+            std::vector<int> sizes(na, 0);
+            for (int r = 0; r < Al.nr; ++r) sizes[agg[r]]++;
+            Bsr Tm;
+            Tm.nr = Al.nr; Tm.nc = na; Tm.P = P;
+            Tm.ptr.resize(Al.nr + 1);
+            Tm.val.assign((size_t)Al.nr * P * P, 0.0);
+            for (int r = 0; r < Al.nr; ++r) {
+                Tm.ptr[r] = r;
+                Tm.col.push_back(agg[r]);
+                double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
+                for (int i = 0; i < P; ++i) Tm.blk(r)[(size_t)i * P + i] = sc;
+            }
+            Tm.ptr[Al.nr] = Al.nr;
+            Bsr AT = bsr_mul(Al, Tm);
+            Bsr Pm = AT;
+            for (int r = 0; r < Al.nr; ++r)
+                for (int q = AT.ptr[r]; q < AT.ptr[r + 1]; ++q) {
+                    std::vector<double> prod((size_t)P * P, 0.0);
+                    gemm_acc(P, Dinv.data() + (size_t)r * P * P, AT.blk(q), prod.data());
+                    double* dst = Pm.blk(q);
+                    for (size_t e = 0; e < prod.size(); ++e) dst[e] = -omega * prod[e];
+                    if (AT.col[q] == agg[r]) {
+                        double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
+                        for (int i = 0; i < P; ++i) dst[(size_t)i * P + i] += sc;
+                    }
+                }
+            Bsr AP = bsr_mul(Al, Pm);
+            Bsr Pt = bsr_transpose(Pm);
+            Bsr Ac = bsr_mul(Pt, AP);
+            Dinvs.push_back(std::move(Dinv));
+            Ps.push_back(std::move(Pm));
+            As.push_back(std::move(Ac));
+        }
+        if (a->h_agg0.empty()) a->h_agg0.assign(ns, -1);
+        const int nl = (int)As.size();
+        a->lev.resize(nl);
+        for (int l = 0; l < nl; ++l) {
+            AmgLevel& Lv = a->lev[l];
+            Lv.nn = As[l].nr;
+            a->h_nodes.push_back(As[l].nr);
+            Lv.x.alloc((size_t)Lv.nn * P);
+            Lv.b.alloc((size_t)Lv.nn * P);
+            Lv.r.alloc((size_t)Lv.nn * P);
+            if (l < nl - 1) {
+                upload_bsr(As[l], Lv.a_ptr, Lv.a_col, Lv.a_val, s);
+                upload_bsr(Ps[l], Lv.p_ptr, Lv.p_col, Lv.p_val, s);
+                upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s);
+                if (prec == SG_FP64) {
+                    Lv.dinv64.upload(Dinvs[l], s);
+                } else if (prec == SG_FP32) {
+                    std::vector<float> f(Dinvs[l].begin(), Dinvs[l].end());
+                    Lv.dinv32.upload(f, s);
+                } else {
+                    std::vector<uint16_t> h(Dinvs[l].size());
+                    for (size_t q = 0; q < h.size(); ++q) h[q] = host_bf16((float)Dinvs[l][q]);
+                    Lv.dinv16.upload(h, s);
+                }
+            }
+            HIP_OK(hipStreamSynchronize(s));
+        }
+        // coarsest: dense FP64 inverse
+        {
+            const Bsr& Ac = As.back();
+            const int N = Ac.nr * P;
+            std::vector<double> D((size_t)N * N, 0.0);
+            for (int r = 0; r < Ac.nr; ++r)
+                for (int q = Ac.ptr[r]; q < Ac.ptr[r + 1]; ++q)
+                    for (int i = 0; i < P; ++i)
+                        for (int j = 0; j < P; ++j)
+                            D[(size_t)(r * P + i) * N + Ac.col[q] * P + j] = Ac.blk(q)[(size_t)i * P + j];
+            invert_dense(D, N);
+            a->coarsest_inv.upload(D, s);
+            a->coarsest_n = N;
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        *out = a.release();
+        return SG_OK;
+    });
+}
+
+int amg_info(const sg_amg* a, int* n_levels, int32_t* nodes_per_level, int32_t* agg) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a != nullptr, "amg is NULL");
+        if (n_levels) *n_levels = (int)a->h_nodes.size();
+        if (nodes_per_level)
+            for (size_t l = 0; l < a->h_nodes.size(); ++l) nodes_per_level[l] = a->h_nodes[l];
+        if (agg) std::memcpy(agg, a->h_agg0.data(), a->n_sub * sizeof(int32_t));
+        return SG_OK;
+    });
+}
+
+int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a && b_c && x_c, "null argument");
+        SG_REQUIRE(b_c != x_c, "b_c and x_c must not alias");
+        check_device(a->device);
+        coarse_solve(a, b_c, x_c, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int sg_coarse_restrict(const sg_amg* a, const double* R, double* r_c, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a && R && r_c, "null argument");
+        check_device(a->device);
+        coarse_restrict(a, R, r_c, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int sg_coarse_prolong_add(const sg_amg* a, const double* e_c, double* Y, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a && e_c && Y, "null argument");
+        check_device(a->device);
+        coarse_prolong_add(a, e_c, Y, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+void sg_destroy_amg(sg_amg* a) { delete a; }
+
+}  // extern "C"

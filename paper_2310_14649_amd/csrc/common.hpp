@@ -1,0 +1,194 @@
+// Internal helpers shared by the sgsolve translation units: error
+// propagation across the C ABI, device buffers, and the handle layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sgsolve.h"
+
+namespace sg {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const char* msg);
+
+#define SG_THROW(code, ...)                                                  \
+    do {                                                                     \
+        char _b[512];                                                        \
+        std::snprintf(_b, sizeof(_b), __VA_ARGS__);                          \
+        throw ::sg::Error((code), _b);                                       \
+    } while (0)
+
+#define SG_REQUIRE(cond, ...)                                                \
+    do {                                                                     \
+        if (!(cond)) SG_THROW(SG_ERR_INVALID_ARG, __VA_ARGS__);              \
+    } while (0)
+
+#define HIP_OK(expr)                                                         \
+    do {                                                                     \
+        hipError_t _e = (expr);                                              \
+        if (_e != hipSuccess)                                                \
+            SG_THROW(SG_ERR_HIP, "%s failed: %s (%s:%d)", #expr,             \
+                     hipGetErrorString(_e), __FILE__, __LINE__);             \
+    } while (0)
+
+#define HIP_LAUNCH_OK() HIP_OK(hipGetLastError())
+
+// Run `body` and translate exceptions into status codes at the ABI edge.
+template <class F>
+int guarded(F&& body) {
+    try {
+        return body();
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return SG_ERR_INVALID_ARG;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return SG_ERR_INVALID_ARG;
+    }
+}
+
+// Owning device allocation.
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) HIP_OK(hipMalloc(&p, count * sizeof(T)));
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const T* h, size_t count, hipStream_t s) {
+        if (count > n) alloc(count);
+        if (count) HIP_OK(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
+    void download(T* h, size_t count, hipStream_t s) const {
+        if (count) HIP_OK(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int current_device() {
+    int d = 0;
+    HIP_OK(hipGetDevice(&d));
+    return d;
+}
+
+inline void check_device(int dev) {
+    if (current_device() != dev)
+        SG_THROW(SG_ERR_INVALID_ARG, "handle created on device %d used on device %d", dev,
+                 current_device());
+}
+
+// Triple-product table on the device, sorted by k: for output mode k the
+// triples are [kptr[k], kptr[k+1]); tij packs i*P + j; tval = m_ijk.
+struct TriplesDev {
+    int P = 0, L = 0, T = 0;
+    DevBuf<int32_t> kptr, tij;
+    DevBuf<double> tval;
+};
+
+// A "Kronecker-sum" operator Y = sum_i A_i X G_i on a CSR pattern with L
+// values per entry (entry-major).  Used for the fine SG operator and for the
+// first coarse level.
+struct KronCsr {
+    int n = 0;
+    int64_t nnz = 0;
+    int max_row = 0;
+    const int32_t* rowptr = nullptr;   // device, n+1 (int32: nnz < 2^31)
+    const int32_t* col = nullptr;      // device
+    const double* vals = nullptr;      // device, nnz*L
+};
+
+}  // namespace sg
+
+struct sg_basis {
+    int M = 0, p_in = 0, p = 0, P = 0, L = 0, T = 0;
+    std::vector<int32_t> alpha;                 // P*M
+    std::vector<int32_t> ti, tj, tk;            // sorted by (k, i, j)
+    std::vector<double> tv;
+    std::vector<double> afact;                  // <Psi_k^2> = alpha!
+};
+
+struct sg_op {
+    int device = 0;
+    int n = 0, P = 0, L = 0, M = 0;
+    int64_t nnz = 0;
+    int max_row = 0;
+    sg::DevBuf<int32_t> rowptr, col;
+    sg::DevBuf<double> vals;         // nnz*L
+    sg::DevBuf<double> F;            // n
+    sg::DevBuf<double> afact;        // P
+    sg::TriplesDev tr;
+    // host copies used by the setup of the preconditioner
+    std::vector<int32_t> h_rowptr, h_col;
+    std::vector<int64_t> h_graph_ptr;           // mesh graph (overlap growth)
+    std::vector<int32_t> h_graph_col;
+    std::vector<double> h_afact;
+    sg_basis basis;
+
+    sg::KronCsr csr() const {
+        sg::KronCsr k;
+        k.n = n; k.nnz = nnz; k.max_row = max_row;
+        k.rowptr = rowptr.p; k.col = col.p; k.vals = vals.p;
+        return k;
+    }
+};
+
+namespace sg {
+// matvec.hip: Y = alpha * (sum_i A_i X G_i) + beta * C  (C may equal Y).
+void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X, double* Y,
+                 double alpha, double beta, const double* C, hipStream_t s);
+// triples.hip: upload a basis' triple table.
+void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s);
+}  // namespace sg
+
+struct sg_ras;
+struct sg_amg;
+namespace sg {
+// ras.hip: Z[owned] = beta * Z[owned] + omega * RAS(R)[owned]
+void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
+                  hipStream_t s);
+const std::vector<int32_t>& ras_owner(const sg_ras* r);
+int ras_nsub(const sg_ras* r);
+int ras_device(const sg_ras* r);
+int ras_n(const sg_ras* r);
+// coarse.hip
+void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s);
+void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s);
+void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
+int amg_nsub(const sg_amg* a);
+int amg_device(const sg_amg* a);
+}  // namespace sg

@@ -1,0 +1,455 @@
+// Two-grid preconditioner application (Eq. RAS_2L as the cycle the text
+// describes) and right-preconditioned flexible GMRES(m) in FP64 (the outer
+// solver of Secs. 3-4).
+//
+// Arnoldi uses modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i for
+// i = 0..j in order.  Each step of that loop is one kernel that first reduces
+// the previous dot product's per-block partial sums (every block sums them in
+// the same fixed order, so every block sees the same h_ij and results are
+// bitwise reproducible), then updates its slice of w and forms the partial
+// sums of the next dot product in the same pass.  The Hessenberg column, the
+// Givens rotations and the residual estimate stay on the device; the host
+// reads one scalar per iteration.
+#include "common.hpp"
+
+#include <chrono>
+#include <cmath>
+
+namespace sg {
+namespace {
+
+constexpr int kVT = 256;      // threads per vector block
+constexpr int kMaxRedBlocks = 1024;
+
+inline int red_blocks(int64_t N) {
+    int64_t b = (N + kVT * 4 - 1) / (kVT * 4);
+    if (b < 1) b = 1;
+    if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+    return (int)b;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = kVT / 2; o > 0; o >>= 1) {
+        if (tid < o) sh[tid] += sh[tid + o];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Sum of nb partials in a fixed order (identical in every block).
+__device__ inline double reduce_partials(const double* part, int nb, double* sh) {
+    double a = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kVT) a += part[q];
+    return block_sum(a, sh);
+}
+
+__global__ __launch_bounds__(kVT) void dot_partial_kernel(int64_t N, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          double* __restrict__ part) {
+    __shared__ double sh[kVT];
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVT)
+        a = fma(x[i], y[i], a);
+    double s = block_sum(a, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kVT) void reduce_kernel(int nb, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    __shared__ double sh[kVT];
+    double s = reduce_partials(part, nb, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// w -= h v_i with h = sum(part_in); part_out = partial <w, v_next> (or <w,w>).
+__global__ __launch_bounds__(kVT) void mgs_kernel(int64_t N, int nb, double* __restrict__ w,
+                                                  const double* __restrict__ vi,
+                                                  const double* __restrict__ vnext,
+                                                  const double* __restrict__ part_in,
+                                                  double* __restrict__ part_out,
+                                                  double* __restrict__ hslot) {
+    __shared__ double sh[kVT];
+    const double h = reduce_partials(part_in, nb, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) hslot[0] = h;
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVT) {
+        const double wi = fma(-h, vi[i], w[i]);
+        w[i] = wi;
+        a = fma(wi, vnext ? vnext[i] : wi, a);
+    }
+    double s = block_sum(a, sh);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+}
+
+// h_{j+1,j} = ||w||, v_{j+1} = w / h  (or 0 and the breakdown flag).
+__global__ __launch_bounds__(kVT) void normalize_kernel(int64_t N, int nb,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ vnext,
+                                                        const double* __restrict__ part,
+                                                        double* __restrict__ hslot,
+                                                        double* __restrict__ flag) {
+    __shared__ double sh[kVT];
+    const double nrm = sqrt(reduce_partials(part, nb, sh));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hslot[0] = nrm;
+        flag[0] = (nrm == 0.0) ? 1.0 : 0.0;
+    }
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVT)
+        vnext[i] = w[i] * inv;
+}
+
+// Apply the previous rotations to column j, form rotation j, update g.
+// ld = m+1 (column-major H).
+__global__ void givens_kernel(int j, int ld, double* __restrict__ H, double* __restrict__ cs,
+                              double* __restrict__ sn, double* __restrict__ g,
+                              double* __restrict__ est) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* h = H + (size_t)j * ld;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double den = hypot(h[j], h[j + 1]);
+    double c = 1.0, s = 0.0;
+    if (den > 0.0) { c = h[j] / den; s = h[j + 1] / den; }
+    cs[j] = c;
+    sn[j] = s;
+    h[j] = den;
+    h[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    est[0] = fabs(g[j + 1]);
+}
+
+// y = R^{-1} g for the k x k upper-triangular rotated Hessenberg.
+__global__ void trisolve_kernel(int k, int ld, const double* __restrict__ H,
+                                const double* __restrict__ g, double* __restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int c = i + 1; c < k; ++c) acc -= H[(size_t)c * ld + i] * y[c];
+        y[i] = acc / H[(size_t)i * ld + i];
+    }
+}
+
+// x += sum_i y_i Z_i  (Z_i stored with stride ld >= N)
+__global__ __launch_bounds__(kVT) void multi_axpy_kernel(int64_t N, int64_t ld, int k,
+                                                         const double* __restrict__ y,
+                                                         const double* __restrict__ Zb,
+                                                         double* __restrict__ x) {
+    __shared__ double ys[64];
+    for (int q = threadIdx.x; q < k; q += kVT) ys[q] = y[q];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVT) {
+        double acc = x[i];
+        for (int q = 0; q < k; ++q) acc = fma(ys[q], Zb[(size_t)q * ld + i], acc);
+        x[i] = acc;
+    }
+}
+
+__global__ void scale_kernel(int64_t N, double a, const double* x, double* y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+
+__global__ void fill_kernel(int64_t N, double v, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = v;
+}
+
+__global__ void init_cycle_kernel(int m1, double beta, double* __restrict__ g) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m1) g[i] = (i == 0) ? beta : 0.0;
+}
+
+inline unsigned grid_for(int64_t N) {
+    int64_t b = (N + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+struct Vec {
+    static void scale(int64_t N, double a, const double* x, double* y, hipStream_t s) {
+        scale_kernel<<<grid_for(N), 256, 0, s>>>(N, a, x, y);
+        HIP_LAUNCH_OK();
+    }
+    static void fill(int64_t N, double v, double* y, hipStream_t s) {
+        fill_kernel<<<grid_for(N), 256, 0, s>>>(N, v, y);
+        HIP_LAUNCH_OK();
+    }
+};
+
+// Host-visible dot product (synchronous).
+double host_dot(int64_t N, const double* x, const double* y, double* part, double* scal,
+                hipStream_t s) {
+    const int nb = red_blocks(N);
+    dot_partial_kernel<<<nb, kVT, 0, s>>>(N, x, y, part);
+    HIP_LAUNCH_OK();
+    reduce_kernel<<<1, kVT, 0, s>>>(nb, part, scal);
+    HIP_LAUNCH_OK();
+    double h = 0.0;
+    HIP_OK(hipMemcpyAsync(&h, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return h;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// workspace needed by the preconditioner: T [N], rc [ns*P], ec [ns*P]
+size_t precond_ws(const sg_op* op, const sg_amg* amg) {
+    size_t N = (size_t)op->n * op->P;
+    size_t b = align_up(N * 8);
+    if (amg) b += 2 * align_up((size_t)amg_nsub(amg) * op->P * 8);
+    return b;
+}
+
+void precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
+                   const double* R, double* Z, char* ws, hipStream_t s) {
+    const int64_t N = (int64_t)op->n * op->P;
+    if (!ras) {
+        HIP_OK(hipMemcpyAsync(Z, R, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    ras_apply_ex(ras, R, Z, omega, 0.0, s);                          // z1 = w M r
+    if (!amg) return;
+    double* T = reinterpret_cast<double*>(ws);
+    double* rc = reinterpret_cast<double*>(ws + align_up(N * 8));
+    double* ec = reinterpret_cast<double*>(ws + align_up(N * 8) +
+                                           align_up((size_t)amg_nsub(amg) * op->P * 8));
+    const KronCsr A = op->csr();
+    kron_matvec(A, op->L, op->tr, Z, T, -1.0, 1.0, R, s);            // t = r - A z1
+    coarse_restrict(amg, T, rc, s);
+    coarse_solve(amg, rc, ec, s);
+    coarse_prolong_add(amg, ec, Z, s);                               // z2 = z1 + Q t
+    kron_matvec(A, op->L, op->tr, Z, T, -1.0, 1.0, R, s);            // t = r - A z2
+    ras_apply_ex(ras, T, Z, omega, 1.0, s);                          // z = z2 + w M t
+}
+
+}  // namespace
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg) {
+    if (!op) return 0;
+    return precond_ws(op, amg);
+}
+
+static void check_set(const sg_op* op, const sg_ras* ras, const sg_amg* amg) {
+    SG_REQUIRE(op != nullptr, "op is NULL");
+    check_device(op->device);
+    if (ras) {
+        SG_REQUIRE(ras_device(ras) == op->device, "ras on another device");
+        SG_REQUIRE(ras_n(ras) == op->n, "ras built for another operator");
+    }
+    if (amg) {
+        SG_REQUIRE(ras != nullptr, "a coarse solver needs the RAS smoother");
+        SG_REQUIRE(amg_device(amg) == op->device, "amg on another device");
+        SG_REQUIRE(amg_nsub(amg) == ras_nsub(ras), "amg and ras disagree on subdomains");
+    }
+}
+
+int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
+                     const double* R, double* Z, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, amg);
+        SG_REQUIRE(R && Z && R != Z, "R, Z must be distinct non-null");
+        SG_REQUIRE(ras != nullptr, "ras is NULL");
+        if (amg) {
+            if (!ws || ws_bytes < precond_ws(op, amg))
+                SG_THROW(SG_ERR_WORKSPACE, "precond workspace too small (%zu < %zu)", ws_bytes,
+                         precond_ws(op, amg));
+        }
+        precond_apply(op, ras, amg, omega, R, Z, reinterpret_cast<char*>(ws), as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho_out,
+                        double* omega_out, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, nullptr);
+        SG_REQUIRE(ras != nullptr, "ras is NULL");
+        SG_REQUIRE(its >= 1, "its must be >= 1");
+        const int64_t N = (int64_t)op->n * op->P;
+        const size_t need = 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8) + 256;
+        if (!ws || ws_bytes < need)
+            SG_THROW(SG_ERR_WORKSPACE, "damping workspace too small (%zu < %zu)", ws_bytes, need);
+        hipStream_t s = as_stream(stream);
+        char* p = reinterpret_cast<char*>(ws);
+        double* v = reinterpret_cast<double*>(p);
+        double* w = reinterpret_cast<double*>(p + align_up(N * 8));
+        double* part = reinterpret_cast<double*>(p + 2 * align_up(N * 8));
+        double* scal = reinterpret_cast<double*>(p + 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8));
+        Vec::fill(N, 1.0 / std::sqrt((double)N), v, s);
+        double rho = 0.0;
+        const KronCsr A = op->csr();
+        for (int it = 0; it < its; ++it) {
+            kron_matvec(A, op->L, op->tr, v, w, 1.0, 0.0, nullptr, s);
+            ras_apply_ex(ras, w, v, 1.0, 0.0, s);
+            rho = std::sqrt(host_dot(N, v, v, part, scal, s));
+            if (!(rho > 0.0) || !std::isfinite(rho)) SG_THROW(SG_ERR_NUMERIC, "power iteration broke down");
+            Vec::scale(N, 1.0 / rho, v, v, s);
+        }
+        if (rho_out) *rho_out = rho;
+        if (omega_out) *omega_out = std::min(1.0, 1.6 / rho);
+        HIP_OK(hipStreamSynchronize(s));
+        return SG_OK;
+    });
+}
+
+size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart) {
+    if (!op || restart < 1) return 0;
+    const size_t N = (size_t)op->n * op->P;
+    const size_t m = (size_t)restart;
+    size_t b = align_up(N * 8) * (2 * m + 2);                 // V (m+1), Z (m), w
+    b += precond_ws(op, amg);
+    b += 2 * align_up(kMaxRedBlocks * 8);                     // partial sums
+    b += align_up((m + 1) * m * 8) + 4 * align_up((m + 1) * 8) + align_up(64);
+    // the damping estimate reuses the front of the workspace
+    const size_t damp = 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8) + 256;
+    return b > damp ? b : damp;
+}
+
+int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const double* b, double* x,
+                 const sg_krylov_opts* opts, sg_krylov_stats* stats, void* ws, size_t ws_bytes,
+                 void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, amg);
+        SG_REQUIRE(b && x && opts, "null argument");
+        SG_REQUIRE(b != x, "b and x must not alias");
+        const int m = opts->restart;
+        SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
+        SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
+        SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
+        const size_t need = fgmres_workspace_bytes(op, amg, m);
+        if (!ws || ws_bytes < need)
+            SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
+        hipStream_t s = as_stream(stream);
+        const int64_t N = (int64_t)op->n * op->P;
+        const size_t vb = align_up(N * 8);
+        char* p = reinterpret_cast<char*>(ws);
+        double* V = reinterpret_cast<double*>(p);                         // (m+1) vectors
+        double* Zb = reinterpret_cast<double*>(p + vb * (m + 1));         // m vectors
+        double* w = reinterpret_cast<double*>(p + vb * (2 * m + 1));
+        char* pws = p + vb * (2 * m + 2);
+        char* q = pws + precond_ws(op, amg);
+        double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
+        double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
+        double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
+        double* cs = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+        double* sn = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+        double* g = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+        double* y = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+        double* scal = reinterpret_cast<double*>(q);                      // est, flag, dot
+        double* part[2] = {part0, part1};
+        const int nb = red_blocks(N);
+        const KronCsr A = op->csr();
+
+        double omega = opts->omega;
+        if (ras && !(omega > 0.0)) {
+            double rho = 0.0;
+            int rc = sg_smoother_damping(op, ras, 15, &rho, &omega, ws, ws_bytes, stream);
+            if (rc != SG_OK) SG_THROW(rc, "%s", sg_last_error());
+        }
+        if (!(omega > 0.0)) omega = 1.0;
+
+        auto t0 = std::chrono::steady_clock::now();
+        const double bnorm = std::sqrt(host_dot(N, b, b, part0, scal + 2, s));
+        int its = 0, restarts = 0, hist = 0;
+        bool converged = false;
+        auto push_hist = [&](double v) {
+            if (stats && stats->history && hist < stats->history_cap) stats->history[hist] = v;
+            ++hist;
+        };
+        double relres = 0.0;
+        if (bnorm == 0.0) {
+            Vec::fill(N, 0.0, x, s);
+            converged = true;
+        } else {
+            if (!std::isfinite(bnorm)) SG_THROW(SG_ERR_NUMERIC, "right-hand side is not finite");
+            const double target = opts->rtol * bnorm;
+            kron_matvec(A, op->L, op->tr, x, V, -1.0, 1.0, b, s);          // r0 = b - A x0
+            double beta = std::sqrt(host_dot(N, V, V, part0, scal + 2, s));
+            if (!std::isfinite(beta)) SG_THROW(SG_ERR_NUMERIC, "initial residual is not finite");
+            relres = beta / bnorm;
+            push_hist(relres);
+            if (beta <= target) converged = true;
+            while (!converged && its < opts->max_it) {
+                init_cycle_kernel<<<1, 128, 0, s>>>(m + 1, beta, g);
+                HIP_LAUNCH_OK();
+                Vec::scale(N, 1.0 / beta, V, V, s);
+                int jd = 0;
+                double hs[2] = {0.0, 0.0};
+                for (int j = 0; j < m; ++j) {
+                    double* vj = V + (size_t)j * (vb / 8);
+                    double* zj = Zb + (size_t)j * (vb / 8);
+                    precond_apply(op, ras, amg, omega, vj, zj, pws, s);
+                    kron_matvec(A, op->L, op->tr, zj, w, 1.0, 0.0, nullptr, s);
+                    dot_partial_kernel<<<nb, kVT, 0, s>>>(N, w, V, part[0]);
+                    HIP_LAUNCH_OK();
+                    double* hcol = H + (size_t)j * (m + 1);
+                    for (int i = 0; i <= j; ++i) {
+                        const double* vi = V + (size_t)i * (vb / 8);
+                        const double* vn = (i < j) ? V + (size_t)(i + 1) * (vb / 8) : nullptr;
+                        mgs_kernel<<<nb, kVT, 0, s>>>(N, nb, w, vi, vn, part[i & 1],
+                                                      part[(i + 1) & 1], hcol + i);
+                        HIP_LAUNCH_OK();
+                    }
+                    double* vnext = V + (size_t)(j + 1) * (vb / 8);
+                    normalize_kernel<<<nb, kVT, 0, s>>>(N, nb, w, vnext, part[(j + 1) & 1],
+                                                        hcol + j + 1, scal + 1);
+                    HIP_LAUNCH_OK();
+                    givens_kernel<<<1, 1, 0, s>>>(j, m + 1, H, cs, sn, g, scal);
+                    HIP_LAUNCH_OK();
+                    HIP_OK(hipMemcpyAsync(hs, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                    HIP_OK(hipStreamSynchronize(s));
+                    ++its;
+                    jd = j + 1;
+                    if (!std::isfinite(hs[0]))
+                        SG_THROW(SG_ERR_NUMERIC, "Arnoldi produced a non-finite value");
+                    relres = hs[0] / bnorm;
+                    push_hist(relres);
+                    if (hs[0] <= target || hs[1] != 0.0 || its >= opts->max_it) break;
+                }
+                trisolve_kernel<<<1, 1, 0, s>>>(jd, m + 1, H, g, y);
+                HIP_LAUNCH_OK();
+                multi_axpy_kernel<<<grid_for(N), kVT, 0, s>>>(N, (int64_t)(vb / 8), jd, y, Zb, x);
+                HIP_LAUNCH_OK();
+                kron_matvec(A, op->L, op->tr, x, V, -1.0, 1.0, b, s);      // true residual
+                beta = std::sqrt(host_dot(N, V, V, part0, scal + 2, s));
+                relres = beta / bnorm;
+                if (beta <= target) { converged = true; break; }
+                if (!std::isfinite(beta)) SG_THROW(SG_ERR_NUMERIC, "residual is not finite");
+                ++restarts;
+            }
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        auto t1 = std::chrono::steady_clock::now();
+        if (stats) {
+            stats->iterations = its;
+            stats->restarts = restarts;
+            stats->converged = converged ? 1 : 0;
+            stats->true_relres = relres;
+            stats->omega = omega;
+            stats->ms_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
+        }
+        return converged ? SG_OK : SG_NOT_CONVERGED;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,537 @@
+// One-level restricted additive Schwarz (Eq. RASsto) with mean-based local
+// solves:  Z = sum_s R_s^T D_s (R_s K_0 R_s^T)^{-1} (R_s R) G_0^{-1}.
+//
+// Local factorisation.  The nodes of each overlapping subdomain are ordered
+// by breadth-first level sets of the local matrix graph (from a
+// pseudo-peripheral node), which makes R_s K_0 R_s^T block tridiagonal:
+// level l only couples to levels l-1 and l+1.  Its block LDL^T factor is
+//   S_0 = A_00,  S_l = A_ll - B_l S_{l-1}^{-1} B_l^T,   B_l = A_{l,l-1},
+// and the device keeps S_l^{-1} (dense, at most 64 x 64) for every level.
+// A solve is a forward sweep  y_l = r_l - B_l z_{l-1},  z_l = S_l^{-1} y_l
+// and a backward sweep  x_l = z_l - S_l^{-1} (B_{l+1}^T x_{l+1}).
+// This is an exact solve of the mean-based local problem (the same map as a
+// dense Cholesky solve, up to rounding) while storing sum_l b_l^2 entries
+// instead of n_s^2.  Inverses are stored in FP64, FP32 or BF16; the low
+// precisions accumulate in FP32.
+//
+// One work-group per (subdomain, column chunk): the P right-hand-side
+// columns of a local solve are independent (G_0 is diagonal).
+#include "common.hpp"
+
+#include <algorithm>
+#include <numeric>
+
+struct sg_ras {
+    int device = 0;
+    int n = 0, P = 0, L = 0, n_sub = 0, overlap = 0, max_b = 0;
+    sg_prec prec = SG_FP64;
+    int64_t total_local = 0, n_lev = 0, sinv_count = 0;
+    std::vector<int32_t> h_nlocal, h_nlev, h_owner;
+    std::vector<int32_t> h_own_ptr, h_own_nodes;   // owned nodes per subdomain
+    sg::DevBuf<int32_t> sub_node_off, sub_lev_off, lev_start, lev_size, gnode, owned, lrow_ptr,
+        lcol;
+    sg::DevBuf<int64_t> sinv_off;
+    sg::DevBuf<double> lval, sinv64, zs, afact;
+    sg::DevBuf<float> sinv32;
+    sg::DevBuf<uint16_t> sinv16;
+};
+
+namespace sg {
+
+constexpr int kRasThreads = 256;
+constexpr int kMaxLevel = 64;
+constexpr int kColChunk = 40;
+
+namespace {
+
+__device__ inline uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <class TS> struct Load;
+template <> struct Load<double> {
+    using Acc = double;
+    static __device__ double get(const double* p, int64_t i) { return p[i]; }
+};
+template <> struct Load<float> {
+    using Acc = float;
+    static __device__ float get(const float* p, int64_t i) { return p[i]; }
+};
+template <> struct Load<uint16_t> {
+    using Acc = float;
+    static __device__ float get(const uint16_t* p, int64_t i) { return from_bf16(p[i]); }
+};
+
+__global__ void gather_k0_kernel(int64_t m, int L, const int64_t* __restrict__ ent,
+                                 const double* __restrict__ vals, double* __restrict__ out) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) out[q] = vals[ent[q] * L];
+}
+
+// Block-tridiagonal factorisation, one work-group per subdomain.
+__global__ __launch_bounds__(kRasThreads) void ras_factor_kernel(
+    const int32_t* __restrict__ sub_node_off, const int32_t* __restrict__ sub_lev_off,
+    const int32_t* __restrict__ lev_start, const int32_t* __restrict__ lev_size,
+    const int64_t* __restrict__ sinv_off, const int32_t* __restrict__ lrow_ptr,
+    const int32_t* __restrict__ lcol, const double* __restrict__ lval, double* __restrict__ sinv64,
+    float* __restrict__ sinv32, uint16_t* __restrict__ sinv16, int prec, int* __restrict__ status) {
+    extern __shared__ __align__(16) double fsm[];
+    double* S = fsm;                          // b x b (current level)
+    double* Sp = fsm + kMaxLevel * kMaxLevel; // previous level's inverse
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int node0 = sub_node_off[s];
+    const int lv0 = sub_lev_off[s], lv1 = sub_lev_off[s + 1];
+    for (int lv = lv0; lv < lv1; ++lv) {
+        const int st = lev_start[lv], b = lev_size[lv];
+        const int stp = lv > lv0 ? lev_start[lv - 1] : 0;
+        const int bp = lv > lv0 ? lev_size[lv - 1] : 0;
+        for (int q = tid; q < b * b; q += kRasThreads) S[q] = 0.0;
+        __syncthreads();
+        for (int r = tid; r < b; r += kRasThreads) {
+            const int row = node0 + st + r;
+            for (int q = lrow_ptr[row]; q < lrow_ptr[row + 1]; ++q) {
+                const int c = lcol[q];
+                if (c >= st && c < st + b) S[r * b + (c - st)] = lval[q];
+            }
+        }
+        __syncthreads();
+        if (bp > 0) {
+            for (int q = tid; q < b * b; q += kRasThreads) {
+                const int r = q / b, c = q - (q / b) * b;
+                const int rr = node0 + st + r, rc = node0 + st + c;
+                double acc = 0.0;
+                for (int q1 = lrow_ptr[rr]; q1 < lrow_ptr[rr + 1]; ++q1) {
+                    const int p = lcol[q1] - stp;
+                    if (p < 0 || p >= bp) continue;
+                    const double v1 = lval[q1];
+                    for (int q2 = lrow_ptr[rc]; q2 < lrow_ptr[rc + 1]; ++q2) {
+                        const int pp = lcol[q2] - stp;
+                        if (pp < 0 || pp >= bp) continue;
+                        acc = fma(v1 * Sp[p * bp + pp], lval[q2], acc);
+                    }
+                }
+                S[q] -= acc;
+            }
+            __syncthreads();
+        }
+        // in-place Gauss-Jordan inversion of the SPD Schur complement
+        for (int k = 0; k < b; ++k) {
+            const double piv = S[k * b + k];
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                if (tid == 0) status[0] = 1;
+                return;   // uniform: every thread read the same pivot
+            }
+            const double ip = 1.0 / piv;
+            for (int q = tid; q < b * b; q += kRasThreads) {
+                const int i = q / b, j = q - (q / b) * b;
+                if (i != k && j != k) S[q] = fma(-S[i * b + k] * ip, S[k * b + j], S[q]);
+            }
+            __syncthreads();
+            for (int q = tid; q < b; q += kRasThreads) {
+                if (q != k) {
+                    S[k * b + q] *= ip;
+                    S[q * b + k] = -S[q * b + k] * ip;
+                } else {
+                    S[k * b + k] = ip;
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t off = sinv_off[lv];
+        for (int q = tid; q < b * b; q += kRasThreads) {
+            const double v = S[q];
+            sinv64[off + q] = v;
+            if (prec == SG_FP32) sinv32[off + q] = (float)v;
+            if (prec == SG_BF16) sinv16[off + q] = to_bf16((float)v);
+            Sp[q] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!   per chunk.
+template <class TS>
+__global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
+    int P, int KC, const int32_t* __restrict__ sub_node_off, const int32_t* __restrict__ sub_lev_off,
+    const int32_t* __restrict__ lev_start, const int32_t* __restrict__ lev_size,
+    const int64_t* __restrict__ sinv_off, const TS* __restrict__ sinv,
+    const int32_t* __restrict__ gnode, const int32_t* __restrict__ owned,
+    const int32_t* __restrict__ lrow_ptr, const int32_t* __restrict__ lcol,
+    const double* __restrict__ lval, const double* __restrict__ afact,
+    const double* __restrict__ R, double* Z, double* __restrict__ zs, double omega, double beta) {
+    using Acc = typename Load<TS>::Acc;
+    extern __shared__ __align__(16) double asm_[];
+    double* buf0 = asm_;
+    double* buf1 = asm_ + kMaxLevel * KC;
+    double* buf2 = asm_ + 2 * kMaxLevel * KC;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int k0 = blockIdx.y * KC;
+    const int kc = min(KC, P - k0);
+    const int node0 = sub_node_off[s];
+    const int lv0 = sub_lev_off[s], lv1 = sub_lev_off[s + 1];
+
+    double* Y = buf0;      // work
+    double* Zc = buf1;     // current level result
+    double* Zp = buf2;     // previous level result
+    // forward sweep
+    for (int lv = lv0; lv < lv1; ++lv) {
+        const int st = lev_start[lv], b = lev_size[lv];
+        const int stp = lv > lv0 ? lev_start[lv - 1] : 0;
+        const int bp = lv > lv0 ? lev_size[lv - 1] : 0;
+        for (int q = tid; q < b * kc; q += kRasThreads) {
+            const int r = q / kc, k = q - (q / kc) * kc;
+            const int row = node0 + st + r;
+            double y = R[(size_t)gnode[row] * P + k0 + k];
+            if (bp > 0)
+                for (int e = lrow_ptr[row]; e < lrow_ptr[row + 1]; ++e) {
+                    const int c = lcol[e] - stp;
+                    if (c >= 0 && c < bp) y = fma(-lval[e], Zp[c * kc + k], y);
+                }
+            Y[q] = y;
+        }
+        __syncthreads();
+        const int64_t off = sinv_off[lv];
+        for (int q = tid; q < b * kc; q += kRasThreads) {
+            const int r = q / kc, k = q - (q / kc) * kc;
+            Acc acc = 0;
+            for (int c = 0; c < b; ++c)
+                acc += Load<TS>::get(sinv, off + (int64_t)r * b + c) * (Acc)Y[c * kc + k];
+            Zc[q] = (double)acc;
+            zs[(size_t)(node0 + st + r) * P + k0 + k] = (double)acc;
+        }
+        __syncthreads();
+        double* t = Zp; Zp = Zc; Zc = t;
+    }
+    // backward sweep: Zp holds x of the last level
+    {
+        const int lv = lv1 - 1;
+        const int st = lev_start[lv], b = lev_size[lv];
+        for (int q = tid; q < b * kc; q += kRasThreads) {
+            const int r = q / kc, k = q - (q / kc) * kc;
+            const int row = node0 + st + r;
+            if (owned[row]) {
+                const size_t o = (size_t)gnode[row] * P + k0 + k;
+                const double v = omega * Zp[q] / afact[k0 + k];
+                Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
+            }
+        }
+    }
+    double* Xn = Zp;     // x of level lv+1
+    double* T = Y;
+    double* Xc = Zc;
+    for (int lv = lv1 - 2; lv >= lv0; --lv) {
+        const int st = lev_start[lv], b = lev_size[lv];
+        const int stn = lev_start[lv + 1], bn = lev_size[lv + 1];
+        for (int q = tid; q < b * kc; q += kRasThreads) {
+            const int r = q / kc, k = q - (q / kc) * kc;
+            const int row = node0 + st + r;
+            double t = 0.0;
+            for (int e = lrow_ptr[row]; e < lrow_ptr[row + 1]; ++e) {
+                const int c = lcol[e] - stn;
+                if (c >= 0 && c < bn) t = fma(lval[e], Xn[c * kc + k], t);
+            }
+            T[q] = t;
+        }
+        __syncthreads();
+        const int64_t off = sinv_off[lv];
+        for (int q = tid; q < b * kc; q += kRasThreads) {
+            const int r = q / kc, k = q - (q / kc) * kc;
+            const int row = node0 + st + r;
+            Acc acc = 0;
+            for (int c = 0; c < b; ++c)
+                acc += Load<TS>::get(sinv, off + (int64_t)r * b + c) * (Acc)T[c * kc + k];
+            const double x = zs[(size_t)row * P + k0 + k] - (double)acc;
+            Xc[q] = x;
+            if (owned[row]) {
+                const size_t o = (size_t)gnode[row] * P + k0 + k;
+                const double v = omega * x / afact[k0 + k];
+                Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
+            }
+        }
+        __syncthreads();
+        double* t2 = Xn; Xn = Xc; Xc = t2;
+    }
+}
+
+}  // namespace
+
+void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
+                  hipStream_t s) {
+    const int KC = std::min(r->P, kColChunk);
+    dim3 grid(r->n_sub, (r->P + KC - 1) / KC);
+    size_t lds = (size_t)3 * kMaxLevel * KC * sizeof(double);
+#define SG_RAS_ARGS                                                                             \
+    r->P, KC, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p
+#define SG_RAS_TAIL                                                                            \
+    r->gnode.p, r->owned.p, r->lrow_ptr.p, r->lcol.p, r->lval.p, r->afact.p, R, Z, r->zs.p, omega, \
+        beta
+    if (r->prec == SG_FP64)
+        ras_apply_kernel<double><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv64.p, SG_RAS_TAIL);
+    else if (r->prec == SG_FP32)
+        ras_apply_kernel<float><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv32.p, SG_RAS_TAIL);
+    else
+        ras_apply_kernel<uint16_t><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv16.p, SG_RAS_TAIL);
+#undef SG_RAS_ARGS
+#undef SG_RAS_TAIL
+    HIP_LAUNCH_OK();
+}
+
+namespace {
+
+// Breadth-first levels of the local graph from `start`; unvisited
+// components are appended (restarting from their smallest global id).
+int bfs_levels(const std::vector<std::vector<int>>& adj, int start,
+               const std::vector<int32_t>& gid, std::vector<int>& level_of) {
+    const int m = (int)adj.size();
+    level_of.assign(m, -1);
+    int nlev = 0;
+    std::vector<int> frontier{start}, next;
+    level_of[start] = 0;
+    int visited = 1;
+    while (true) {
+        while (!frontier.empty()) {
+            ++nlev;
+            next.clear();
+            for (int v : frontier)
+                for (int w : adj[v])
+                    if (level_of[w] < 0) {
+                        level_of[w] = nlev;
+                        next.push_back(w);
+                        ++visited;
+                    }
+            frontier.swap(next);
+        }
+        if (visited == m) break;
+        int best = -1;
+        for (int v = 0; v < m; ++v)
+            if (level_of[v] < 0 && (best < 0 || gid[v] < gid[best])) best = v;
+        level_of[best] = nlev;
+        frontier.assign(1, best);
+        ++visited;
+    }
+    return nlev;
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_prec prec,
+              sg_ras** out, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && owner && out, "null argument");
+        SG_REQUIRE(n_sub >= 1 && n_sub <= op->n, "n_sub=%d invalid", n_sub);
+        SG_REQUIRE(overlap >= 0 && overlap <= 16, "overlap=%d invalid", overlap);
+        SG_REQUIRE(prec == SG_FP64 || prec == SG_FP32 || prec == SG_BF16, "bad precision");
+        check_device(op->device);
+        hipStream_t s = as_stream(stream);
+        const int n = op->n;
+        auto r = std::make_unique<sg_ras>();
+        r->device = op->device;
+        r->n = n; r->P = op->P; r->L = op->L; r->n_sub = n_sub; r->overlap = overlap;
+        r->prec = prec;
+        r->h_owner.assign(owner, owner + n);
+        std::vector<int32_t> cnt(n_sub, 0);
+        for (int a = 0; a < n; ++a) {
+            SG_REQUIRE(owner[a] >= 0 && owner[a] < n_sub, "owner[%d]=%d out of range", a, owner[a]);
+            cnt[owner[a]]++;
+        }
+        for (int q = 0; q < n_sub; ++q) SG_REQUIRE(cnt[q] > 0, "subdomain %d owns no node", q);
+        r->h_own_ptr.assign(n_sub + 1, 0);
+        for (int q = 0; q < n_sub; ++q) r->h_own_ptr[q + 1] = r->h_own_ptr[q] + cnt[q];
+        r->h_own_nodes.resize(n);
+        {
+            std::vector<int32_t> fill(r->h_own_ptr.begin(), r->h_own_ptr.end() - 1);
+            for (int a = 0; a < n; ++a) r->h_own_nodes[fill[owner[a]]++] = a;
+        }
+
+        std::vector<int32_t> sub_node_off(1, 0), sub_lev_off(1, 0), lev_start, lev_size, gnode,
+            owned, lrow_ptr(1, 0), lcol;
+        std::vector<int64_t> lent, sinv_off;
+        int64_t sinv_count = 0;
+        std::vector<int32_t> stamp(n, -1), local_id(n, -1);
+        r->h_nlocal.resize(n_sub);
+        r->h_nlev.resize(n_sub);
+        int max_b = 0;
+        for (int sd = 0; sd < n_sub; ++sd) {
+            // overlap growth in the mesh graph
+            std::vector<int32_t> nodes(r->h_own_nodes.begin() + r->h_own_ptr[sd],
+                                       r->h_own_nodes.begin() + r->h_own_ptr[sd + 1]);
+            for (int a : nodes) stamp[a] = sd;
+            size_t f0 = 0;
+            for (int d = 0; d < overlap; ++d) {
+                size_t f1 = nodes.size();
+                for (size_t q = f0; q < f1; ++q) {
+                    int a = nodes[q];
+                    for (int64_t e = op->h_graph_ptr[a]; e < op->h_graph_ptr[a + 1]; ++e) {
+                        int b = op->h_graph_col[e];
+                        if (stamp[b] != sd) { stamp[b] = sd; nodes.push_back(b); }
+                    }
+                }
+                f0 = f1;
+            }
+            const int m = (int)nodes.size();
+            std::sort(nodes.begin(), nodes.end());
+            for (int q = 0; q < m; ++q) local_id[nodes[q]] = q;
+            // local matrix graph (pattern of K_0 restricted to the subdomain)
+            std::vector<std::vector<int>> adj(m);
+            for (int q = 0; q < m; ++q) {
+                int a = nodes[q];
+                for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e) {
+                    int b = op->h_col[e];
+                    if (b != a && stamp[b] == sd) adj[q].push_back(local_id[b]);
+                }
+            }
+            // pseudo-peripheral start (George-Liu), from the smallest global id
+            std::vector<int> lvl;
+            int start = 0;
+            int ecc = bfs_levels(adj, start, nodes, lvl);
+            for (int it = 0; it < 8; ++it) {
+                int last = *std::max_element(lvl.begin(), lvl.end());
+                int cand = -1;
+                for (int q = 0; q < m; ++q)
+                    if (lvl[q] == last &&
+                        (cand < 0 || adj[q].size() < adj[cand].size() ||
+                         (adj[q].size() == adj[cand].size() && nodes[q] < nodes[cand])))
+                        cand = q;
+                std::vector<int> l2;
+                int e2 = bfs_levels(adj, cand, nodes, l2);
+                if (e2 <= ecc) break;
+                ecc = e2; start = cand; lvl.swap(l2);
+            }
+            bfs_levels(adj, start, nodes, lvl);
+            int nl = *std::max_element(lvl.begin(), lvl.end()) + 1;
+            std::vector<int> order(m);
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int x, int y) { return lvl[x] < lvl[y]; });
+            std::vector<int> pos(m);
+            for (int q = 0; q < m; ++q) pos[order[q]] = q;
+            // levels
+            int q = 0;
+            for (int l = 0; l < nl; ++l) {
+                int st = q;
+                while (q < m && lvl[order[q]] == l) ++q;
+                int b = q - st;
+                if (b > kMaxLevel)
+                    SG_THROW(SG_ERR_UNSUPPORTED,
+                             "subdomain %d: level set of %d nodes exceeds %d", sd, b, kMaxLevel);
+                max_b = std::max(max_b, b);
+                lev_start.push_back(st);
+                lev_size.push_back(b);
+                sinv_off.push_back(sinv_count);
+                sinv_count += (int64_t)b * b;
+            }
+            // local CSR in level order
+            for (int qq = 0; qq < m; ++qq) {
+                int a = nodes[order[qq]];
+                gnode.push_back(a);
+                owned.push_back(owner[a] == sd ? 1 : 0);
+                std::vector<std::pair<int, int64_t>> ents;
+                for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e) {
+                    int b = op->h_col[e];
+                    if (stamp[b] == sd) ents.push_back({pos[local_id[b]], (int64_t)e});
+                }
+                std::sort(ents.begin(), ents.end());
+                for (auto& pe : ents) {
+                    lcol.push_back(pe.first);
+                    lent.push_back(pe.second);
+                }
+                lrow_ptr.push_back((int32_t)lcol.size());
+            }
+            sub_node_off.push_back((int32_t)gnode.size());
+            sub_lev_off.push_back((int32_t)lev_start.size());
+            r->h_nlocal[sd] = m;
+            r->h_nlev[sd] = nl;
+            for (int a : nodes) local_id[a] = -1;
+        }
+        r->total_local = (int64_t)gnode.size();
+        r->n_lev = (int64_t)lev_start.size();
+        r->sinv_count = sinv_count;
+        r->max_b = max_b;
+        SG_REQUIRE(lcol.size() < (size_t)INT32_MAX, "local pattern too large");
+
+        r->sub_node_off.upload(sub_node_off, s);
+        r->sub_lev_off.upload(sub_lev_off, s);
+        r->lev_start.upload(lev_start, s);
+        r->lev_size.upload(lev_size, s);
+        r->sinv_off.upload(sinv_off, s);
+        r->gnode.upload(gnode, s);
+        r->owned.upload(owned, s);
+        r->lrow_ptr.upload(lrow_ptr, s);
+        r->lcol.upload(lcol, s);
+        r->afact.upload(op->h_afact, s);
+        DevBuf<int64_t> d_lent;
+        d_lent.upload(lent, s);
+        r->lval.alloc(lent.size());
+        int64_t mm = (int64_t)lent.size();
+        gather_k0_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(mm, op->L, d_lent.p,
+                                                                       op->vals.p, r->lval.p);
+        HIP_LAUNCH_OK();
+        r->sinv64.alloc(sinv_count);
+        if (prec == SG_FP32) r->sinv32.alloc(sinv_count);
+        if (prec == SG_BF16) r->sinv16.alloc(sinv_count);
+        r->zs.alloc((size_t)r->total_local * r->P);
+        DevBuf<int> d_status(1);
+        HIP_OK(hipMemsetAsync(d_status.p, 0, sizeof(int), s));
+        size_t lds = (size_t)2 * kMaxLevel * kMaxLevel * sizeof(double);
+        int max_lds = 0;
+        HIP_OK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                     op->device));
+        if ((size_t)max_lds < lds)
+            SG_THROW(SG_ERR_UNSUPPORTED, "device offers %d bytes of LDS per block, need %zu",
+                     max_lds, lds);
+        ras_factor_kernel<<<n_sub, kRasThreads, lds, s>>>(
+            r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p,
+            r->lrow_ptr.p, r->lcol.p, r->lval.p, r->sinv64.p, r->sinv32.p, r->sinv16.p, (int)prec,
+            d_status.p);
+        HIP_LAUNCH_OK();
+        int status = 0;
+        d_status.download(&status, 1, s);
+        HIP_OK(hipStreamSynchronize(s));
+        if (status) SG_THROW(SG_ERR_NUMERIC, "non-positive pivot in a subdomain factorisation");
+        *out = r.release();
+        return SG_OK;
+    });
+}
+
+int ras_info(const sg_ras* r, int32_t* n_local, int32_t* n_levels, int64_t* factor_bytes) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r != nullptr, "ras is NULL");
+        if (n_local) std::memcpy(n_local, r->h_nlocal.data(), r->n_sub * sizeof(int32_t));
+        if (n_levels) std::memcpy(n_levels, r->h_nlev.data(), r->n_sub * sizeof(int32_t));
+        if (factor_bytes) {
+            int64_t per = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
+            *factor_bytes = r->sinv_count * per;
+        }
+        return SG_OK;
+    });
+}
+
+int ras_apply(const sg_ras* r, const double* R, double* Z, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r && R && Z, "null argument");
+        SG_REQUIRE(R != Z, "R and Z must not alias");
+        check_device(r->device);
+        ras_apply_ex(r, R, Z, 1.0, 0.0, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+void sg_destroy_ras(sg_ras* r) { delete r; }
+
+}  // extern "C"
+
+namespace sg {
+const std::vector<int32_t>& ras_owner(const sg_ras* r) { return r->h_owner; }
+int ras_nsub(const sg_ras* r) { return r->n_sub; }
+int ras_device(const sg_ras* r) { return r->device; }
+int ras_n(const sg_ras* r) { return r->n; }
+}  // namespace sg

@@ -1,0 +1,102 @@
+"""Handle lifetimes for one SG problem on the GPU.
+
+``GpuSG`` only sequences C-ABI calls (basis -> operator -> RAS -> coarse
+solver -> FGMRES) and owns the torch buffers they write into; all
+arithmetic happens in ``libsgsolve.so``.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import binding as B
+from .inputs import Problem
+
+COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_COARSE_AMG}
+
+
+class GpuSG:
+    def __init__(self, pr: Problem, prec: str = "fp64", coarse: str = "amg",
+                 overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
+                 n_sub: Optional[int] = None, stream=None):
+        import torch
+        self.torch = torch
+        self.pr = pr
+        self.stream = stream
+        self.basis = self.op = self.ras = self.amg = None
+        m = pr.mesh
+        self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
+        self.op = B.sg_assemble(self.basis, m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, stream=stream)
+        self.n, self.P, self.L, self.nnz = B.sg_op_info(self.op)
+        dev = torch.device("cuda")
+        self.b = torch.empty(self.n * self.P, dtype=torch.float64, device=dev)
+        B.sg_op_rhs(self.op, self.b, stream=stream)
+        self.owner = pr.owner if owner is None else owner
+        self.n_sub = pr.n_sub if n_sub is None else n_sub
+        self.overlap = pr.overlap if overlap is None else overlap
+        self.prec = prec
+        self.coarse = coarse
+        self.ras = B.ras_setup(self.op, self.owner, self.n_sub, self.overlap, B.PREC[prec],
+                               stream=stream)
+        if coarse != "none":
+            self.amg = B.amg_setup(self.op, self.ras, COARSE[coarse], B.PREC[prec], stream=stream)
+        self._ws = None
+        self._ws_restart = None
+
+    def new_vec(self, fill: float = 0.0):
+        return self.torch.full((self.n * self.P,), fill, dtype=self.torch.float64, device="cuda")
+
+    def workspace(self, restart: int):
+        if self._ws is None or self._ws_restart != restart:
+            nbytes = B.fgmres_workspace_bytes(self.op, self.amg, restart)
+            self._ws = self.torch.empty((nbytes + 7) // 8, dtype=self.torch.float64, device="cuda")
+            self._ws_restart = restart
+        return self._ws
+
+    def precond_workspace(self):
+        nbytes = max(B.sg_precond_workspace_bytes(self.op, self.amg), 8)
+        return self.torch.empty((nbytes + 7) // 8, dtype=self.torch.float64, device="cuda")
+
+    def damping(self, its: int = 15):
+        N = self.n * self.P
+        ws = self.torch.empty(2 * N + 4096, dtype=self.torch.float64, device="cuda")
+        return B.sg_smoother_damping(self.op, self.ras, its, ws, stream=self.stream)
+
+    def solve(self, restart: int, rtol: float, max_it: int = 2000, omega: float = 0.0,
+              x0=None, use_precond: bool = True):
+        x = self.new_vec() if x0 is None else x0.clone()
+        ras = self.ras if use_precond else None
+        amg = self.amg if use_precond else None
+        ws = self.workspace(restart) if use_precond else self.torch.empty(
+            (B.fgmres_workspace_bytes(self.op, None, restart) + 7) // 8, dtype=self.torch.float64,
+            device="cuda")
+        info = B.fgmres_solve(self.op, ras, amg, self.b, x, restart, max_it, rtol, omega, ws,
+                              stream=self.stream)
+        return x, info
+
+    def close(self):
+        if self.amg is not None:
+            B.sg_destroy_amg(self.amg)
+            self.amg = None
+        if self.ras is not None:
+            B.sg_destroy_ras(self.ras)
+            self.ras = None
+        if self.op is not None:
+            B.sg_destroy_op(self.op)
+            self.op = None
+        if self.basis is not None:
+            B.sg_destroy_basis(self.basis)
+            self.basis = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,325 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by
+element on the same seeded inputs.
+
+Tolerances (FP64 paths): assembly and the SG matvec are sums of a handful
+of products, so 1e-13 relative to the largest entry covers any summation
+order; RAS, the V-cycle and the two-grid cycle are fixed linear maps whose
+factorisations differ from the oracle's only in rounding (condition numbers
+< 1e4 at these sizes), hence 1e-10; converged FGMRES solutions are compared
+to the direct solution at 1e-8 (the method's FP64 target).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import amg as oamg  # noqa: E402
+from oracle import coarse as ocoarse  # noqa: E402
+from oracle import pce as opce  # noqa: E402
+from oracle import ras as oras  # noqa: E402
+from oracle import sg as osg  # noqa: E402
+from oracle import system as osys  # noqa: E402
+from oracle.precond import smoother_radius  # noqa: E402
+from paper_2310_14649_amd import binding as B  # noqa: E402
+from paper_2310_14649_amd.inputs import make_problem  # noqa: E402
+from paper_2310_14649_amd.solver import GpuSG  # noqa: E402
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle(pr):
+    m = pr.mesh
+    return osys.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _to_host(t, shape):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().reshape(shape)
+
+
+def _to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+CASES = {
+    "c0": dict(name="c0"),
+    "c1_64": dict(name="c1", nc=64, sub=(8, 8)),
+    "c3_40": dict(name="c3", nc=40, sub=(4, 4)),       # jittered mesh, M=6, P=84
+    "p1_det": dict(name="c0", M=0, nc=20, sub=(3, 2)),   # P = 1: deterministic FEM
+    "c4_ragged": dict(name="c4", nc=23, sub=(3, 5)),     # tails in every tile
+}
+
+
+def _problem(key):
+    kw = dict(CASES[key])
+    name = kw.pop("name")
+    if name == "c3":
+        kw["sub"] = kw.get("sub")
+        from paper_2310_14649_amd.inputs import structured_partition
+        pr = make_problem("c0", nc=kw["nc"], M=6, p=3, sigma=0.5, ell=0.2, sub=kw["sub"],
+                          overlap=2)
+        from paper_2310_14649_amd.inputs import jittered_mesh, kl_fields
+        mesh = jittered_mesh(kw["nc"], amp=0.3, seed=0)
+        g, _, _ = kl_fields(mesh.centroids(), 6, 0.5, 0.2)
+        pr.mesh = mesh
+        pr.g = g
+        pr.g0 = np.zeros(mesh.n_tri)
+        return pr
+    return make_problem(name, **kw)
+
+
+@pytest.fixture(scope="module")
+def built():
+    _cuda()
+    cache = {}
+
+    def get(key, prec="fp64", coarse="amg"):
+        k = (key, prec, coarse)
+        if k not in cache:
+            pr = _problem(key)
+            print(f"[gpu] building {k}: n={pr.mesh.n} M={pr.M} p={pr.p}", flush=True)
+            cache[k] = (pr, _oracle(pr), GpuSG(pr, prec=prec, coarse=coarse))
+        return cache[k]
+
+    yield get
+    for _, _, g in cache.values():
+        g.close()
+
+
+# ------------------------------------------------------------------ a1
+@pytest.mark.parametrize("M,p_in,p", [(0, 0, 0), (1, 1, 4), (2, 2, 2), (4, 2, 3), (6, 2, 3), (3, 1, 2)])
+def test_triples_bit_exact(M, p_in, p):
+    _cuda()
+    h = B.sg_build_triples(M, p_in, p)
+    try:
+        alpha, ijk, val = B.sg_basis_export(h, M)
+        oa, oijk, oval, L, P = opce.triple_products(M, p_in, p)
+        assert B.sg_basis_info(h)[:2] == (P, L)
+        if M:
+            assert np.array_equal(alpha, oa)
+        got = {tuple(r): v for r, v in zip(ijk.tolist(), val.tolist())}
+        want = {tuple(r): v for r, v in zip(oijk.tolist(), oval.tolist())}
+        assert got == want
+    finally:
+        B.sg_destroy_basis(h)
+
+
+def test_triples_rejects_bad_orders():
+    _cuda()
+    with pytest.raises(B.SgError):
+        B.sg_build_triples(2, 3, 2)
+
+
+# ------------------------------------------------------------------ a2
+@pytest.mark.parametrize("key", ["c0", "c3_40", "c4_ragged", "p1_det"])
+def test_assembly_matches_oracle(built, key):
+    pr, S, g = built(key)
+    rowptr, col, vals = B.sg_op_export(g.op)
+    n = pr.mesh.n
+    for i in range(S.L_in):
+        Kd = S.K[i].toarray()
+        mine = np.zeros((n, n))
+        rows = np.repeat(np.arange(n), np.diff(rowptr))
+        mine[rows, col] = vals[:, i]
+        assert _rel(mine, Kd) < 1e-13, i
+    # entries left out of the pattern are exact zeros of the oracle
+    K0 = S.K[0].tocoo()
+    kept = set(zip(rows.tolist(), col.tolist()))
+    for r, c, v in zip(K0.row, K0.col, K0.data):
+        if (r, c) not in kept:
+            assert v == 0.0
+    B_rhs = _to_host(g.b, (n, S.P))
+    assert _rel(B_rhs, S.B) < 1e-14
+
+
+# ------------------------------------------------------------------ a3
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det"])
+def test_matvec_matches_oracle(built, key):
+    pr, S, g = built(key)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((pr.mesh.n, S.P))
+    Y = g.new_vec()
+    B.sg_matvec(g.op, _to_dev(X), Y)
+    assert _rel(_to_host(Y, X.shape), S.matvec(X)) < 1e-13
+
+
+def test_matvec_rejects_alias(built):
+    pr, S, g = built("c0")
+    X = g.new_vec(1.0)
+    with pytest.raises(B.SgError):
+        B.sg_matvec(g.op, X, X)
+
+
+# ------------------------------------------------------------------ a4
+def _oracle_ras(pr, S, owner=None, n_sub=None, overlap=None):
+    owner = pr.owner if owner is None else owner
+    return oras.ras_setup(S.K[0], owner, pr.n_sub if n_sub is None else n_sub, S.adj,
+                          pr.overlap if overlap is None else overlap)
+
+
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det"])
+def test_ras_fp64_matches_oracle(built, key):
+    pr, S, g = built(key)
+    subs = _oracle_ras(pr, S)
+    nloc, nlev, _ = B.ras_info(g.ras, pr.n_sub)
+    assert nloc.tolist() == [len(sd.nodes) for sd in subs]
+    R = np.random.default_rng(12).standard_normal((pr.mesh.n, S.P))
+    Z = g.new_vec()
+    B.ras_apply(g.ras, _to_dev(R), Z)
+    assert _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact)) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 6e-2)])
+def test_ras_low_precision_close_to_oracle(built, prec, tol):
+    pr, S, g = built("c1_64", prec=prec)
+    subs = _oracle_ras(pr, S)
+    R = np.random.default_rng(13).standard_normal((pr.mesh.n, S.P))
+    Z = g.new_vec()
+    B.ras_apply(g.ras, _to_dev(R), Z)
+    err = _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact))
+    print(f"[gpu] RAS {prec} rel err {err:.3e}")
+    assert err < tol
+
+
+def test_ras_single_subdomain_exact(built):
+    pr, S, _ = built("c4_ragged")
+    owner = np.zeros(pr.mesh.n, dtype=np.int32)
+    g = GpuSG(pr, coarse="none", owner=owner, n_sub=1, overlap=0)
+    try:
+        R = np.random.default_rng(14).standard_normal((pr.mesh.n, S.P))
+        Z = g.new_vec()
+        B.ras_apply(g.ras, _to_dev(R), Z)
+        import scipy.sparse.linalg as spla
+        ref = spla.spsolve(S.K[0].tocsc(), R) / S.alpha_fact[None, :]
+        assert _rel(_to_host(Z, R.shape), ref) < 1e-10
+    finally:
+        g.close()
+
+
+def test_ras_rejects_bad_owner(built):
+    pr, S, g = built("c0")
+    owner = pr.owner.copy()
+    owner[3] = pr.n_sub      # out of range: must fail on the host, before any launch
+    with pytest.raises(B.SgError):
+        B.ras_setup(g.op, owner, pr.n_sub, 1)
+
+
+# ------------------------------------------------------------------ a5
+@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40"])
+def test_coarse_and_vcycle_match_oracle(built, key):
+    pr, S, g = built(key)
+    Z = ocoarse.nicolaides(pr.owner, pr.n_sub)
+    C = ocoarse.coarse_blocks(S.K, Z)
+    h = oamg.setup(ocoarse.coarse_operator(C, S.G), S.P)
+    nl, nodes, agg = B.amg_info(g.amg, pr.n_sub)
+    assert nl == h.n_levels
+    assert nodes.tolist() == [A.shape[0] // S.P for A in h.A]
+    if h.n_levels > 1:
+        assert np.array_equal(agg, h.aggs[0])
+    rng = np.random.default_rng(15)
+    R = rng.standard_normal((pr.mesh.n, S.P))
+    rc = torch.zeros(pr.n_sub * S.P, dtype=torch.float64, device="cuda")
+    B.sg_coarse_restrict(g.amg, _to_dev(R), rc)
+    assert _rel(_to_host(rc, (pr.n_sub, S.P)), ocoarse.restrict(Z, R)) < 1e-13
+    bc = rng.standard_normal((pr.n_sub, S.P))
+    xc = torch.zeros_like(rc)
+    B.amg_vcycle(g.amg, _to_dev(bc), xc)
+    assert _rel(_to_host(xc, bc.shape), oamg.vcycle(h, bc.ravel()).reshape(bc.shape)) < 1e-10
+    Y = _to_dev(R)
+    B.sg_coarse_prolong_add(g.amg, _to_dev(bc), Y)
+    assert _rel(_to_host(Y, R.shape), R + ocoarse.prolong(Z, bc)) < 1e-14
+
+
+def test_mean_exact_coarse_matches_oracle(built):
+    pr, S, g = built("c0", coarse="mean")
+    Z = ocoarse.nicolaides(pr.owner, pr.n_sub)
+    cs = ocoarse.MeanExactCoarse(ocoarse.coarse_blocks(S.K, Z), S.alpha_fact)
+    bc = np.random.default_rng(16).standard_normal((pr.n_sub, S.P))
+    xc = torch.zeros(pr.n_sub * S.P, dtype=torch.float64, device="cuda")
+    B.amg_vcycle(g.amg, _to_dev(bc), xc)
+    assert _rel(_to_host(xc, bc.shape), cs(bc)) < 1e-12
+
+
+# ------------------------------------------------------------------ a6
+@pytest.mark.parametrize("key,coarse", [("c0", "mean"), ("c1_64", "amg"), ("c3_40", "amg")])
+def test_two_level_cycle_matches_oracle(built, key, coarse):
+    pr, S, g = built(key, coarse=coarse)
+    rho, omega = g.damping()
+    B2, subs, C, cs = osys.two_level(S, pr.owner, pr.n_sub, pr.overlap, coarse)
+    assert rho == pytest.approx(
+        smoother_radius(S.matvec, lambda R: oras.ras_apply(subs, R, S.alpha_fact), S.B.shape),
+        rel=1e-9)
+    B2.omega = omega
+    R = np.random.default_rng(17).standard_normal((pr.mesh.n, S.P))
+    Z = g.new_vec()
+    B.sg_precond_apply(g.op, g.ras, g.amg, omega, _to_dev(R), Z, g.precond_workspace())
+    assert _rel(_to_host(Z, R.shape), B2(R)) < 1e-10
+
+
+# ------------------------------------------------------------------ a7
+@pytest.mark.parametrize("key,coarse,restart", [("c0", "mean", 30), ("c1_64", "amg", 50),
+                                                 ("p1_det", "amg", 30), ("c4_ragged", "amg", 50)])
+def test_fgmres_solution_matches_direct(built, key, coarse, restart):
+    pr, S, g = built(key, coarse=coarse)
+    ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    x, info = g.solve(restart, 1e-12)
+    print(f"[gpu] {key}: its={info['iterations']} relres={info['true_relres']:.2e} "
+          f"omega={info['omega']:.3f}", flush=True)
+    assert info["converged"] and info["true_relres"] <= 1e-12
+    U = _to_host(x, ref.shape)
+    assert np.linalg.norm(U - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_fgmres_iterations_track_oracle(built):
+    pr, S, g = built("c0", coarse="mean")
+    B2, *_ = osys.two_level(S, pr.owner, pr.n_sub, pr.overlap, "mean")
+    _, oinfo = osys.solve(S, B2, 30, 1e-8)
+    x, info = g.solve(30, 1e-8)
+    assert abs(info["iterations"] - oinfo.iterations) <= 1
+    h = info["history"]
+    n = min(len(h), len(oinfo.history), 10)
+    assert np.allclose(h[:n], oinfo.history[:n], rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fgmres_mixed_precision_refines_to_fp64(built, prec):
+    pr, S, g = built("c1_64", prec=prec)
+    ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    x, info = g.solve(50, 1e-10)
+    err = np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref)
+    print(f"[gpu] mixed {prec}: its={info['iterations']} err={err:.2e}", flush=True)
+    assert info["converged"] and err < 1e-6
+
+
+def test_fgmres_bitwise_reproducible(built):
+    pr, S, g = built("c4_ragged")
+    x1, i1 = g.solve(50, 1e-10)
+    x2, i2 = g.solve(50, 1e-10)
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+
+
+def test_fgmres_unpreconditioned_matches_library_gmres(built):
+    import scipy.sparse.linalg as spla
+    pr, S, g = built("c0")
+    hist = []
+    spla.gmres(osg.sg_kron(S.K, S.G), S.B.ravel(), restart=20, rtol=1e-9, maxiter=1,
+               callback=lambda r: hist.append(r), callback_type="pr_norm")
+    x, info = g.solve(20, 1e-9, max_it=20, use_precond=False)
+    assert np.allclose(info["history"][1:21], hist[:20], rtol=1e-7)
+
+
+def test_fgmres_zero_rhs_and_cap(built):
+    pr, S, g = built("c0")
+    x, info = g.solve(10, 1e-12, max_it=1)
+    assert info["iterations"] == 1 and not info["converged"]
+    assert info["status"] == B.SG_NOT_CONVERGED
