@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgsolve.so")
 SOURCES = ["triples.hip", "assemble.hip", "matvec.hip", "ras.hip", "coarse.hip", "krylov.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
+FLAGS = ["-O3", "-fPIC", "-std=c++17", "-fconstexpr-steps=100000000", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-Wno-unused-result"]
 

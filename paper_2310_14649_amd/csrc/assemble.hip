@@ -243,6 +243,7 @@ int sg_assemble(const sg_basis* b, int n_vert, const double* xy, int n_tri, cons
                                                     d_cref.p, earea.p, op->F.p);
         HIP_LAUNCH_OK();
         upload_triples(*b, op->tr, s);
+        build_ell(op.get(), s);
         int bad = 0;
         d_bad.download(&bad, 1, s);
         HIP_OK(hipStreamSynchronize(s));

@@ -130,6 +130,11 @@ struct KronCsr {
     const int32_t* rowptr = nullptr;   // device, n+1 (int32: nnz < 2^31)
     const int32_t* col = nullptr;      // device
     const double* vals = nullptr;      // device, nnz*L
+    // optional wave-tiled ELL copy used by the specialised kernels
+    int spec = -1;                     // specialisation id, -1 = generic kernel
+    int ell_S = 0, ell_RW = 0;         // slots per row, rows per tile
+    const int32_t* ecol = nullptr;     // [tiles][S][RW]
+    const double* evals = nullptr;     // [tiles][S][L][RW]
 };
 
 }  // namespace sg
@@ -152,6 +157,9 @@ struct sg_op {
     sg::DevBuf<double> F;            // n
     sg::DevBuf<double> afact;        // P
     sg::TriplesDev tr;
+    int spec = -1, ell_S = 0, ell_RW = 0;
+    sg::DevBuf<int32_t> ecol;
+    sg::DevBuf<double> evals;
     // host copies used by the setup of the preconditioner
     std::vector<int32_t> h_rowptr, h_col;
     std::vector<int64_t> h_graph_ptr;           // mesh graph (overlap growth)
@@ -163,6 +171,7 @@ struct sg_op {
         sg::KronCsr k;
         k.n = n; k.nnz = nnz; k.max_row = max_row;
         k.rowptr = rowptr.p; k.col = col.p; k.vals = vals.p;
+        k.spec = spec; k.ell_S = ell_S; k.ell_RW = ell_RW; k.ecol = ecol.p; k.evals = evals.p;
         return k;
     }
 };
@@ -171,6 +180,9 @@ namespace sg {
 // matvec.hip: Y = alpha * (sum_i A_i X G_i) + beta * C  (C may equal Y).
 void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X, double* Y,
                  double alpha, double beta, const double* C, hipStream_t s);
+// matvec.hip: pick a specialised kernel for this basis/pattern and build its
+// wave-tiled ELL copy of the values (no-op when none applies).
+void build_ell(sg_op* op, hipStream_t s);
 // triples.hip: upload a basis' triple table.
 void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s);
 }  // namespace sg

@@ -12,8 +12,10 @@
 // Only the non-zero triples are touched, so the contraction costs T flops
 // per row instead of the L*P*P of a dense G_i product.
 #include "common.hpp"
+#include "sgtable.hpp"
 
 #include <algorithm>
+#include <utility>
 
 namespace sg {
 namespace {
@@ -93,12 +95,224 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Specialised kernel for a fixed basis (M, PIN, PO), ELL width S and IG lanes
+// per row.  Each lane keeps its row's K_i values for its share of the input
+// terms in registers (read once, coalesced, from the wave-tiled ELL copy),
+// loops over the output columns j with X[b, j] gathered from the S
+// neighbours, forms w_i = sum_s K_i[a, b_s] X[b_s, j] and scatters
+// m_ijk w_i into register-resident y_k with the triple coefficients as
+// immediates.  The IG partial sums of a row are combined by lane shuffles.
+// Value of the partner lane (lane ^ 1): DPP quad permutation [1,0,3,2].
+__device__ __forceinline__ double swap_lane_pair(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class H, int T>
+__device__ __forceinline__ void triple_step(const double* w, double* y) {
+    constexpr int k = H::t.k[T];
+    constexpr int ii = H::t.ii[T];
+    constexpr double m = H::t.m[T];
+    y[k] = fma(m, w[ii], y[k]);
+}
+
+template <class H, int T0, int... Is>
+__device__ __forceinline__ void triple_range(std::integer_sequence<int, Is...>, const double* w,
+                                             double* y) {
+    (triple_step<H, T0 + Is>(w, y), ...);
+}
+
+template <class H, int T>
+__device__ __forceinline__ void pair_step(double sel, const double* w, double* y) {
+    constexpr int k = H::t.k[T];
+    constexpr int ii = H::t.ii[T];
+    constexpr double m0 = H::t.m0[T], d = H::t.m1[T] - H::t.m0[T];
+    // sel is 0 for the first lane of a row and 1 for the second
+    y[k] = fma(fma(sel, d, m0), w[ii], y[k]);
+}
+
+template <class H, int T0, int... Is>
+__device__ __forceinline__ void pair_range(std::integer_sequence<int, Is...>, double sel,
+                                           const double* w, double* y) {
+    (pair_step<H, T0 + Is>(sel, w, y), ...);
+}
+
+template <int M, int PIN, int PO, int IG, int G, int J>
+__device__ __forceinline__ void contract_j(const double* w, double* y) {
+    using H = tab::GroupHolder<M, PIN, PO, IG, G>;
+    constexpr int t0 = H::t.jptr[J], t1 = H::t.jptr[J + 1];
+    triple_range<H, t0>(std::make_integer_sequence<int, t1 - t0>{}, w, y);
+}
+
+template <int M, int PIN, int PO, int S, int IG, int J>
+__device__ __forceinline__ void column_step(int ig, const int* b, const double (*v)[(tab::cbinom(M + PIN, PIN) + IG - 1) / IG],
+                                            const double* __restrict__ X, double* y) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    constexpr int L = tab::cbinom(M + PIN, PIN);
+    constexpr int LI = (L + IG - 1) / IG;
+    double x[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) x[q] = X[(size_t)b[q] * P + J];
+    double w[LI];
+#pragma unroll
+    for (int ii = 0; ii < LI; ++ii) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) a = fma(v[q][ii], x[q], a);
+        w[ii] = a;
+    }
+    if constexpr (IG == 1) {
+        contract_j<M, PIN, PO, IG, 0, J>(w, y);
+    } else {
+        static_assert(IG == 2, "IG must be 1 or 2");
+        using H = tab::PairHolder<M, PIN, PO>;
+        constexpr int t0 = H::t.jptr[J], t1 = H::t.jptr[J + 1];
+        pair_range<H, t0>(std::make_integer_sequence<int, t1 - t0>{}, (double)ig, w, y);
+    }
+}
+
+template <int M, int PIN, int PO, int S, int IG, int... Js>
+__device__ __forceinline__ void all_columns(std::integer_sequence<int, Js...>, int ig, const int* b,
+                                            const double (*v)[(tab::cbinom(M + PIN, PIN) + IG - 1) / IG],
+                                            const double* __restrict__ X, double* y) {
+    (column_step<M, PIN, PO, S, IG, Js>(ig, b, v, X, y), ...);
+}
+
+template <int M, int PIN, int PO, int S, int IG>
+__global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
+    int n, const int32_t* __restrict__ ecol, const double* __restrict__ evals,
+    const double* __restrict__ X, double* Y, double alpha, double beta, const double* C) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    constexpr int L = tab::cbinom(M + PIN, PIN);
+    constexpr int LI = (L + IG - 1) / IG;
+    constexpr int RW = 64 / IG;
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int r = lane / IG;
+    const int ig = lane - r * IG;
+    if (tile * RW >= n) return;               // whole wave past the last row
+    const int row = tile * RW + r;
+    int b[S];
+    double v[S][LI];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        b[q] = ecol[((size_t)tile * S + q) * RW + r];
+#pragma unroll
+        for (int ii = 0; ii < LI; ++ii) {
+            const int i = ig * LI + ii;
+            v[q][ii] = (i < L) ? evals[(((size_t)tile * S + q) * L + i) * RW + r] : 0.0;
+        }
+    }
+    double y[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[k] = 0.0;
+    all_columns<M, PIN, PO, S, IG>(std::make_integer_sequence<int, P>{}, ig, b, v, X, y);
+    if constexpr (IG == 2) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] += swap_lane_pair(y[k]);
+    }
+    if (row >= n || ig != 0) return;     // the first lane of a row writes it
+    double* yr = Y + (size_t)row * P;
+    const double* cr = C ? C + (size_t)row * P : nullptr;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double o = alpha * y[k];
+        if (beta != 0.0) o = fma(beta, cr[k], o);
+        yr[k] = o;
+    }
+}
+
+// ELL copy: entry id of every (tile, slot, lane) position, -1 for padding.
+__global__ void ell_fill_kernel(int64_t npos, int L, int S, int RW, const int64_t* __restrict__ ent,
+                                const double* __restrict__ vals, double* __restrict__ evals) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= npos * L) return;
+    // idx enumerates ((tile*S + s)*L + i)*RW + r
+    const int64_t r = idx % RW;
+    const int64_t i = (idx / RW) % L;
+    const int64_t ts = idx / ((int64_t)RW * L);
+    const int64_t e = ent[ts * RW + r];
+    evals[idx] = e >= 0 ? vals[e * L + i] : 0.0;
+}
+
+struct Spec {
+    int M, PIN, PO, S, IG;
+};
+constexpr Spec kSpecs[] = {{2, 2, 2, 5, 1}, {2, 2, 2, 7, 1}, {4, 2, 3, 5, 2}, {4, 2, 3, 7, 2}};
+
+template <int Id>
+void launch_spec(const KronCsr& A, const double* X, double* Y, double alpha, double beta,
+                 const double* C, hipStream_t s) {
+    constexpr Spec sp = kSpecs[Id];
+    constexpr int RW = 64 / sp.IG;
+    const int tiles = (A.n + RW - 1) / RW;
+    const int blocks = (tiles + kThreads / 64 - 1) / (kThreads / 64);
+    kron_matvec_spec_kernel<sp.M, sp.PIN, sp.PO, sp.S, sp.IG>
+        <<<blocks, kThreads, 0, s>>>(A.n, A.ecol, A.evals, X, Y, alpha, beta, C);
+}
+
 }  // namespace
+
+void build_ell(sg_op* op, hipStream_t s) {
+    op->spec = -1;
+    const sg_basis& b = op->basis;
+    int id = -1;
+    for (int q = 0; q < (int)(sizeof(kSpecs) / sizeof(kSpecs[0])); ++q) {
+        const Spec& sp = kSpecs[q];
+        if (sp.M == b.M && sp.PIN == b.p_in && sp.PO == b.p && op->max_row <= sp.S) {
+            id = q;
+            break;
+        }
+    }
+    if (id < 0) return;
+    const Spec sp = kSpecs[id];
+    const int RW = 64 / sp.IG;
+    const int n = op->n;
+    const int tiles = (n + RW - 1) / RW;
+    std::vector<int32_t> ecol((size_t)tiles * sp.S * RW, 0);
+    std::vector<int64_t> ent((size_t)tiles * sp.S * RW, -1);
+    for (int a = 0; a < n; ++a) {
+        const int t = a / RW, r = a % RW;
+        int q = 0;
+        for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q) {
+            ecol[((size_t)t * sp.S + q) * RW + r] = op->h_col[e];
+            ent[((size_t)t * sp.S + q) * RW + r] = e;
+        }
+        for (; q < sp.S; ++q) ecol[((size_t)t * sp.S + q) * RW + r] = a;   // padding: own row, value 0
+    }
+    op->ecol.upload(ecol, s);
+    DevBuf<int64_t> d_ent;
+    d_ent.upload(ent, s);
+    const int64_t npos = (int64_t)tiles * sp.S * RW;
+    op->evals.alloc((size_t)npos * op->L);
+    ell_fill_kernel<<<(unsigned)((npos * op->L + 255) / 256), 256, 0, s>>>(npos, op->L, sp.S, RW,
+                                                                           d_ent.p, op->vals.p,
+                                                                           op->evals.p);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(s));
+    op->spec = id;
+    op->ell_S = sp.S;
+    op->ell_RW = RW;
+}
 
 void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X, double* Y,
                  double alpha, double beta, const double* C, hipStream_t s) {
     const int P = tr.P, T = tr.T;
     if (A.n == 0) return;
+    if (A.spec >= 0) {
+        switch (A.spec) {
+            case 0: launch_spec<0>(A, X, Y, alpha, beta, C, s); break;
+            case 1: launch_spec<1>(A, X, Y, alpha, beta, C, s); break;
+            case 2: launch_spec<2>(A, X, Y, alpha, beta, C, s); break;
+            case 3: launch_spec<3>(A, X, Y, alpha, beta, C, s); break;
+            default: SG_THROW(SG_ERR_INVALID_ARG, "bad matvec specialisation %d", A.spec);
+        }
+        HIP_LAUNCH_OK();
+        return;
+    }
     // rows per tile: as many as fit the thread count and the LDS budget
     auto lds_for = [&](int R) {
         size_t ent = (size_t)R * A.max_row;

@@ -29,9 +29,9 @@ struct sg_ras {
     std::vector<int32_t> h_nlocal, h_nlev, h_owner;
     std::vector<int32_t> h_own_ptr, h_own_nodes;   // owned nodes per subdomain
     sg::DevBuf<int32_t> sub_node_off, sub_lev_off, lev_start, lev_size, gnode, owned, lrow_ptr,
-        lcol;
+        lcol, prev_idx, next_idx;
     sg::DevBuf<int64_t> sinv_off;
-    sg::DevBuf<double> lval, sinv64, zs, afact;
+    sg::DevBuf<double> lval, sinv64, zs, afact, prev_val, next_val;
     sg::DevBuf<float> sinv32;
     sg::DevBuf<uint16_t> sinv16;
 };
@@ -40,7 +40,9 @@ namespace sg {
 
 constexpr int kRasThreads = 256;
 constexpr int kMaxLevel = 64;
-constexpr int kColChunk = 40;
+constexpr int kColChunk = 16;   // max right-hand-side columns per work-group
+constexpr int kCouple = 6;      // max neighbours of a node in an adjacent level
+constexpr int kPrefetch = (kMaxLevel * kMaxLevel + kRasThreads - 1) / kRasThreads;
 
 namespace {
 
@@ -66,10 +68,11 @@ template <> struct Load<uint16_t> {
     static __device__ float get(const uint16_t* p, int64_t i) { return from_bf16(p[i]); }
 };
 
+// out[q] = K_0 value of global entry ent[q] (0 where ent[q] < 0)
 __global__ void gather_k0_kernel(int64_t m, int L, const int64_t* __restrict__ ent,
                                  const double* __restrict__ vals, double* __restrict__ out) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < m) out[q] = vals[ent[q] * L];
+    if (q < m) out[q] = ent[q] >= 0 ? vals[ent[q] * L] : 0.0;
 }
 
 // Block-tridiagonal factorisation, one work-group per subdomain.
@@ -153,105 +156,158 @@ __global__ __launch_bounds__(kRasThreads) void ras_factor_kernel(
     }
 }
 
-// Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!   per chunk.
+// Apply: one work-group per (subdomain, chunk of KC right-hand-side columns).
+// Per level: phase A gathers r_l and subtracts the coupling to the previous
+// level (fixed-width lists), phase B multiplies by S_l^{-1} held in LDS while
+// the next level's inverse is prefetched into registers and then stored into
+// the other LDS buffer.  Two barriers per level.
+// Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!.
 template <class TS>
 __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
-    int P, int KC, const int32_t* __restrict__ sub_node_off, const int32_t* __restrict__ sub_lev_off,
-    const int32_t* __restrict__ lev_start, const int32_t* __restrict__ lev_size,
-    const int64_t* __restrict__ sinv_off, const TS* __restrict__ sinv,
-    const int32_t* __restrict__ gnode, const int32_t* __restrict__ owned,
-    const int32_t* __restrict__ lrow_ptr, const int32_t* __restrict__ lcol,
-    const double* __restrict__ lval, const double* __restrict__ afact,
+    int P, int KC, int bmax, const int32_t* __restrict__ sub_node_off,
+    const int32_t* __restrict__ sub_lev_off, const int32_t* __restrict__ lev_start,
+    const int32_t* __restrict__ lev_size, const int64_t* __restrict__ sinv_off,
+    const TS* __restrict__ sinv, const int32_t* __restrict__ gnode,
+    const int32_t* __restrict__ owned, const int32_t* __restrict__ prev_idx,
+    const double* __restrict__ prev_val, const int32_t* __restrict__ next_idx,
+    const double* __restrict__ next_val, const double* __restrict__ afact,
     const double* __restrict__ R, double* Z, double* __restrict__ zs, double omega, double beta) {
     using Acc = typename Load<TS>::Acc;
-    extern __shared__ __align__(16) double asm_[];
-    double* buf0 = asm_;
-    double* buf1 = asm_ + kMaxLevel * KC;
-    double* buf2 = asm_ + 2 * kMaxLevel * KC;
+    extern __shared__ __align__(16) unsigned char ras_smem[];
+    double* Y = reinterpret_cast<double*>(ras_smem);
+    double* Zc = Y + bmax * KC;
+    double* Zp = Zc + bmax * KC;
+    TS* Sb0 = reinterpret_cast<TS*>(Zp + bmax * KC);
+    TS* Sb1 = Sb0 + bmax * bmax;
     const int s = blockIdx.x, tid = threadIdx.x;
     const int k0 = blockIdx.y * KC;
     const int kc = min(KC, P - k0);
     const int node0 = sub_node_off[s];
     const int lv0 = sub_lev_off[s], lv1 = sub_lev_off[s + 1];
+    TS pre[kPrefetch];
 
-    double* Y = buf0;      // work
-    double* Zc = buf1;     // current level result
-    double* Zp = buf2;     // previous level result
-    // forward sweep
+    auto load_direct = [&](int lv, TS* dst) {
+        const int b = lev_size[lv];
+        const int64_t off = sinv_off[lv];
+        for (int q = tid; q < b * b; q += kRasThreads) dst[q] = sinv[off + q];
+    };
+    auto prefetch = [&](int lv) {
+        const int b = lev_size[lv];
+        const int64_t off = sinv_off[lv];
+#pragma unroll
+        for (int p = 0; p < kPrefetch; ++p) {
+            const int q = tid + p * kRasThreads;
+            if (q < b * b) pre[p] = sinv[off + q];
+        }
+    };
+    auto commit = [&](int lv, TS* dst) {
+        const int b = lev_size[lv];
+#pragma unroll
+        for (int p = 0; p < kPrefetch; ++p) {
+            const int q = tid + p * kRasThreads;
+            if (q < b * b) dst[q] = pre[p];
+        }
+    };
+    auto write_out = [&](int row, int k, double x) {
+        if (owned[row]) {
+            const size_t o = (size_t)gnode[row] * P + k0 + k;
+            const double v = omega * x / afact[k0 + k];
+            Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
+        }
+    };
+
+    // ---------------- forward sweep
+    load_direct(lv0, Sb0);
+    __syncthreads();
     for (int lv = lv0; lv < lv1; ++lv) {
         const int st = lev_start[lv], b = lev_size[lv];
-        const int stp = lv > lv0 ? lev_start[lv - 1] : 0;
-        const int bp = lv > lv0 ? lev_size[lv - 1] : 0;
+        TS* cur = ((lv - lv0) & 1) ? Sb1 : Sb0;
+        TS* nxt = ((lv - lv0) & 1) ? Sb0 : Sb1;
         for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - (q / kc) * kc;
+            const int r = q / kc, k = q - r * kc;
             const int row = node0 + st + r;
             double y = R[(size_t)gnode[row] * P + k0 + k];
-            if (bp > 0)
-                for (int e = lrow_ptr[row]; e < lrow_ptr[row + 1]; ++e) {
-                    const int c = lcol[e] - stp;
-                    if (c >= 0 && c < bp) y = fma(-lval[e], Zp[c * kc + k], y);
+            if (lv > lv0) {
+#pragma unroll
+                for (int c = 0; c < kCouple; ++c) {
+                    const int pi = prev_idx[(size_t)row * kCouple + c];
+                    if (pi >= 0) y = fma(-prev_val[(size_t)row * kCouple + c], Zp[pi * kc + k], y);
                 }
+            }
             Y[q] = y;
         }
+        if (lv + 1 < lv1) prefetch(lv + 1);
         __syncthreads();
-        const int64_t off = sinv_off[lv];
         for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - (q / kc) * kc;
-            Acc acc = 0;
-            for (int c = 0; c < b; ++c)
-                acc += Load<TS>::get(sinv, off + (int64_t)r * b + c) * (Acc)Y[c * kc + k];
-            Zc[q] = (double)acc;
-            zs[(size_t)(node0 + st + r) * P + k0 + k] = (double)acc;
+            const int r = q / kc, k = q - r * kc;
+            const TS* srow = cur + r * b;
+            Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int c = 0;
+            for (; c + 3 < b; c += 4) {
+                a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
+                a1 += Load<TS>::get(srow, c + 1) * (Acc)Y[(c + 1) * kc + k];
+                a2 += Load<TS>::get(srow, c + 2) * (Acc)Y[(c + 2) * kc + k];
+                a3 += Load<TS>::get(srow, c + 3) * (Acc)Y[(c + 3) * kc + k];
+            }
+            for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
+            const double z = (double)((a0 + a1) + (a2 + a3));
+            Zc[q] = z;
+            zs[(size_t)(node0 + st + r) * P + k0 + k] = z;
         }
+        if (lv + 1 < lv1) commit(lv + 1, nxt);
         __syncthreads();
         double* t = Zp; Zp = Zc; Zc = t;
     }
-    // backward sweep: Zp holds x of the last level
+
+    // ---------------- backward sweep: Zp holds x of the last level
     {
         const int lv = lv1 - 1;
         const int st = lev_start[lv], b = lev_size[lv];
         for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - (q / kc) * kc;
-            const int row = node0 + st + r;
-            if (owned[row]) {
-                const size_t o = (size_t)gnode[row] * P + k0 + k;
-                const double v = omega * Zp[q] / afact[k0 + k];
-                Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
-            }
+            const int r = q / kc, k = q - r * kc;
+            write_out(node0 + st + r, k, Zp[q]);
         }
     }
-    double* Xn = Zp;     // x of level lv+1
-    double* T = Y;
+    if (lv1 - 2 < lv0) return;
+    load_direct(lv1 - 2, Sb0);
+    __syncthreads();
+    double* Xn = Zp;
     double* Xc = Zc;
     for (int lv = lv1 - 2; lv >= lv0; --lv) {
         const int st = lev_start[lv], b = lev_size[lv];
-        const int stn = lev_start[lv + 1], bn = lev_size[lv + 1];
+        TS* cur = ((lv1 - 2 - lv) & 1) ? Sb1 : Sb0;
+        TS* nxt = ((lv1 - 2 - lv) & 1) ? Sb0 : Sb1;
         for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - (q / kc) * kc;
+            const int r = q / kc, k = q - r * kc;
             const int row = node0 + st + r;
             double t = 0.0;
-            for (int e = lrow_ptr[row]; e < lrow_ptr[row + 1]; ++e) {
-                const int c = lcol[e] - stn;
-                if (c >= 0 && c < bn) t = fma(lval[e], Xn[c * kc + k], t);
+#pragma unroll
+            for (int c = 0; c < kCouple; ++c) {
+                const int ni = next_idx[(size_t)row * kCouple + c];
+                if (ni >= 0) t = fma(next_val[(size_t)row * kCouple + c], Xn[ni * kc + k], t);
             }
-            T[q] = t;
+            Y[q] = t;
         }
+        if (lv - 1 >= lv0) prefetch(lv - 1);
         __syncthreads();
-        const int64_t off = sinv_off[lv];
         for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - (q / kc) * kc;
+            const int r = q / kc, k = q - r * kc;
             const int row = node0 + st + r;
-            Acc acc = 0;
-            for (int c = 0; c < b; ++c)
-                acc += Load<TS>::get(sinv, off + (int64_t)r * b + c) * (Acc)T[c * kc + k];
-            const double x = zs[(size_t)row * P + k0 + k] - (double)acc;
-            Xc[q] = x;
-            if (owned[row]) {
-                const size_t o = (size_t)gnode[row] * P + k0 + k;
-                const double v = omega * x / afact[k0 + k];
-                Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
+            const TS* srow = cur + r * b;
+            Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            int c = 0;
+            for (; c + 3 < b; c += 4) {
+                a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
+                a1 += Load<TS>::get(srow, c + 1) * (Acc)Y[(c + 1) * kc + k];
+                a2 += Load<TS>::get(srow, c + 2) * (Acc)Y[(c + 2) * kc + k];
+                a3 += Load<TS>::get(srow, c + 3) * (Acc)Y[(c + 3) * kc + k];
             }
+            for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
+            const double x = zs[(size_t)row * P + k0 + k] - (double)((a0 + a1) + (a2 + a3));
+            Xc[q] = x;
+            write_out(row, k, x);
         }
+        if (lv - 1 >= lv0) commit(lv - 1, nxt);
         __syncthreads();
         double* t2 = Xn; Xn = Xc; Xc = t2;
     }
@@ -261,14 +317,18 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
 
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
-    const int KC = std::min(r->P, kColChunk);
-    dim3 grid(r->n_sub, (r->P + KC - 1) / KC);
-    size_t lds = (size_t)3 * kMaxLevel * KC * sizeof(double);
-#define SG_RAS_ARGS                                                                             \
-    r->P, KC, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p
-#define SG_RAS_TAIL                                                                            \
-    r->gnode.p, r->owned.p, r->lrow_ptr.p, r->lcol.p, r->lval.p, r->afact.p, R, Z, r->zs.p, omega, \
-        beta
+    const int nch = (r->P + kColChunk - 1) / kColChunk;
+    const int KC = (r->P + nch - 1) / nch;
+    dim3 grid(r->n_sub, nch);
+    const int bmax = r->max_b;
+    size_t ts = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
+    size_t lds = (size_t)3 * bmax * KC * sizeof(double) + 2 * (size_t)bmax * bmax * ts;
+#define SG_RAS_ARGS                                                                      \
+    r->P, KC, bmax, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, \
+        r->sinv_off.p
+#define SG_RAS_TAIL                                                                           \
+    r->gnode.p, r->owned.p, r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p,      \
+        r->afact.p, R, Z, r->zs.p, omega, beta
     if (r->prec == SG_FP64)
         ras_apply_kernel<double><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv64.p, SG_RAS_TAIL);
     else if (r->prec == SG_FP32)
@@ -353,8 +413,8 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         }
 
         std::vector<int32_t> sub_node_off(1, 0), sub_lev_off(1, 0), lev_start, lev_size, gnode,
-            owned, lrow_ptr(1, 0), lcol;
-        std::vector<int64_t> lent, sinv_off;
+            owned, lrow_ptr(1, 0), lcol, prev_idx, next_idx;
+        std::vector<int64_t> lent, sinv_off, prev_ent, next_ent;
         int64_t sinv_count = 0;
         std::vector<int32_t> stamp(n, -1), local_id(n, -1);
         r->h_nlocal.resize(n_sub);
@@ -416,8 +476,10 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
             for (int q = 0; q < m; ++q) pos[order[q]] = q;
             // levels
             int q = 0;
+            std::vector<int> lstart(nl + 1, 0);
             for (int l = 0; l < nl; ++l) {
                 int st = q;
+                lstart[l] = st;
                 while (q < m && lvl[order[q]] == l) ++q;
                 int b = q - st;
                 if (b > kMaxLevel)
@@ -429,6 +491,7 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
                 sinv_off.push_back(sinv_count);
                 sinv_count += (int64_t)b * b;
             }
+            lstart[nl] = m;
             // local CSR in level order
             for (int qq = 0; qq < m; ++qq) {
                 int a = nodes[order[qq]];
@@ -440,9 +503,34 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
                     if (stamp[b] == sd) ents.push_back({pos[local_id[b]], (int64_t)e});
                 }
                 std::sort(ents.begin(), ents.end());
+                const int lq = lvl[order[qq]];
+                int np = 0, nn = 0;
+                size_t base = prev_idx.size();
+                prev_idx.resize(base + kCouple, -1);
+                next_idx.resize(base + kCouple, -1);
+                prev_ent.resize(base + kCouple, -1);
+                next_ent.resize(base + kCouple, -1);
                 for (auto& pe : ents) {
                     lcol.push_back(pe.first);
                     lent.push_back(pe.second);
+                    const int lc = lvl[order[pe.first]];
+                    if (lc == lq - 1) {
+                        if (np == kCouple)
+                            SG_THROW(SG_ERR_UNSUPPORTED, "node couples to more than %d nodes of a level",
+                                     kCouple);
+                        prev_idx[base + np] = pe.first - lstart[lc];
+                        prev_ent[base + np] = pe.second;
+                        ++np;
+                    } else if (lc == lq + 1) {
+                        if (nn == kCouple)
+                            SG_THROW(SG_ERR_UNSUPPORTED, "node couples to more than %d nodes of a level",
+                                     kCouple);
+                        next_idx[base + nn] = pe.first - lstart[lc];
+                        next_ent[base + nn] = pe.second;
+                        ++nn;
+                    } else if (lc != lq) {
+                        SG_THROW(SG_ERR_INVALID_ARG, "internal: level structure is not tridiagonal");
+                    }
                 }
                 lrow_ptr.push_back((int32_t)lcol.size());
             }
@@ -475,6 +563,20 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         gather_k0_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(mm, op->L, d_lent.p,
                                                                        op->vals.p, r->lval.p);
         HIP_LAUNCH_OK();
+        r->prev_idx.upload(prev_idx, s);
+        r->next_idx.upload(next_idx, s);
+        DevBuf<int64_t> d_pe, d_ne;
+        d_pe.upload(prev_ent, s);
+        d_ne.upload(next_ent, s);
+        int64_t mc = (int64_t)prev_ent.size();
+        r->prev_val.alloc(mc);
+        r->next_val.alloc(mc);
+        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, d_pe.p, op->vals.p,
+                                                                       r->prev_val.p);
+        HIP_LAUNCH_OK();
+        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, d_ne.p, op->vals.p,
+                                                                       r->next_val.p);
+        HIP_LAUNCH_OK();
         r->sinv64.alloc(sinv_count);
         if (prec == SG_FP32) r->sinv32.alloc(sinv_count);
         if (prec == SG_BF16) r->sinv16.alloc(sinv_count);
@@ -488,6 +590,13 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         if ((size_t)max_lds < lds)
             SG_THROW(SG_ERR_UNSUPPORTED, "device offers %d bytes of LDS per block, need %zu",
                      max_lds, lds);
+        {
+            const int nch = (r->P + kColChunk - 1) / kColChunk;
+            const int KC = (r->P + nch - 1) / nch;
+            size_t need = (size_t)3 * max_b * KC * 8 + 2 * (size_t)max_b * max_b * 8;
+            if ((size_t)max_lds < need)
+                SG_THROW(SG_ERR_UNSUPPORTED, "RAS apply needs %zu bytes of LDS", need);
+        }
         ras_factor_kernel<<<n_sub, kRasThreads, lds, s>>>(
             r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p,
             r->lrow_ptr.p, r->lcol.p, r->lval.p, r->sinv64.p, r->sinv32.p, r->sinv16.p, (int)prec,
