@@ -52,6 +52,9 @@ struct sg_amg {
     sg_prec prec = SG_FP64;
     int n = 0, n_sub = 0, P = 0, L = 0;
     sg::DevBuf<int32_t> own_ptr, own_nodes, owner;
+    int nslices = 0;
+    sg::DevBuf<int32_t> slice_sub, slice_beg, slice_end, sub_slice_ptr;
+    sg::DevBuf<double> slice_part;
     sg::DevBuf<double> afact;
     sg::DevBuf<double> c0inv;                 // mean-exact
     std::vector<sg::AmgLevel> lev;            // AMG levels (last = coarsest)
@@ -78,26 +81,39 @@ __global__ void coarse_entries_kernel(int64_t nce, int L, const int64_t* __restr
     C[idx] = acc;
 }
 
-// r_c[s, k] = sum over owned nodes a of R[a, k]; fixed-order partial sums.
-__global__ __launch_bounds__(256) void restrict_kernel(int P, const int32_t* __restrict__ own_ptr,
-                                                       const int32_t* __restrict__ own_nodes,
-                                                       const double* __restrict__ R,
-                                                       double* __restrict__ rc) {
-    __shared__ double part[256];
-    const int s = blockIdx.x, tid = threadIdx.x;
+// r_c[s, k] = sum over owned nodes a of R[a, k]: stage 1 sums slices of
+// kSlice owned nodes per work-group, stage 2 adds the slices of a subdomain
+// in order (fixed summation order, no atomics).
+constexpr int kSlice = 64;
+__global__ __launch_bounds__(256) void restrict_partial_kernel(
+    int P, int nslices, const int32_t* __restrict__ slice_sub, const int32_t* __restrict__ slice_beg,
+    const int32_t* __restrict__ slice_end, const int32_t* __restrict__ own_nodes,
+    const double* __restrict__ R, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int sl = blockIdx.x, tid = threadIdx.x;
     const int stripes = 256 / P;
     const int k = tid % P, st = tid / P;
     double acc = 0.0;
     if (st < stripes)
-        for (int q = own_ptr[s] + st; q < own_ptr[s + 1]; q += stripes)
+        for (int q = slice_beg[sl] + st; q < slice_end[sl]; q += stripes)
             acc += R[(size_t)own_nodes[q] * P + k];
-    part[tid] = acc;
+    red[tid] = acc;
     __syncthreads();
     if (tid < P) {
         double t = 0.0;
-        for (int w = 0; w < stripes; ++w) t += part[w * P + tid];
-        rc[(size_t)s * P + tid] = t;
+        for (int w = 0; w < stripes; ++w) t += red[w * P + tid];
+        part[(size_t)sl * P + tid] = t;
     }
+}
+
+__global__ void restrict_final_kernel(int ns, int P, const int32_t* __restrict__ sub_slice_ptr,
+                                      const double* __restrict__ part, double* __restrict__ rc) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ns * P) return;
+    int s = idx / P, k = idx - (idx / P) * P;
+    double t = 0.0;
+    for (int q = sub_slice_ptr[s]; q < sub_slice_ptr[s + 1]; ++q) t += part[(size_t)q * P + k];
+    rc[idx] = t;
 }
 
 __global__ void prolong_add_kernel(int64_t total, int P, const int32_t* __restrict__ owner,
@@ -121,23 +137,42 @@ __global__ void mean_exact_kernel(int ns, int P, const double* __restrict__ inv,
     x[idx] = acc / afact[k];
 }
 
-// y = beta * c + alpha * A x   (block-sparse, dense P x P blocks); one
-// work-group per block-row, thread k owns output row k.
-__global__ __launch_bounds__(kBlk) void bsr_mv_kernel(int P, const int32_t* __restrict__ ptr,
-                                                      const int32_t* __restrict__ col,
-                                                      const double* __restrict__ val,
-                                                      const double* __restrict__ x, double* y,
-                                                      double alpha, double beta, const double* c) {
-    const int s = blockIdx.x;
-    for (int k = threadIdx.x; k < P; k += kBlk) {
-        double acc = 0.0;
-        for (int q = ptr[s]; q < ptr[s + 1]; ++q) {
+// y = beta * c + alpha * A x   (block-sparse, dense P x P blocks).  One
+// work-group of kBlkMv threads per block-row: thread (k, part) sums the
+// block-rows' neighbour blocks part, part + nparts, ... for output row k,
+// then the parts are added in a fixed order through LDS.
+constexpr int kBlkMv = 256;
+__global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const double* __restrict__ x, double* y,
+                                                        double alpha, double beta, const double* c) {
+    __shared__ double part[kBlkMv];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nparts = kBlkMv / P;
+    const int k = tid % P, pi = tid / P;
+    double acc = 0.0;
+    if (pi < nparts) {
+        for (int q = ptr[s] + pi; q < ptr[s + 1]; q += nparts) {
             const double* blk = val + (size_t)q * P * P + (size_t)k * P;
             const double* xv = x + (size_t)col[q] * P;
-            for (int j = 0; j < P; ++j) acc = fma(blk[j], xv[j], acc);
+            double a0 = 0.0, a1 = 0.0;
+            int j = 0;
+            for (; j + 1 < P; j += 2) {
+                a0 = fma(blk[j], xv[j], a0);
+                a1 = fma(blk[j + 1], xv[j + 1], a1);
+            }
+            if (j < P) a0 = fma(blk[j], xv[j], a0);
+            acc += a0 + a1;
         }
-        const size_t o = (size_t)s * P + k;
-        double v = alpha * acc;
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < P) {
+        double t = 0.0;
+        for (int w = 0; w < nparts; ++w) t += part[w * P + tid];
+        const size_t o = (size_t)s * P + tid;
+        double v = alpha * t;
         if (beta != 0.0) v = fma(beta, c[o], v);
         y[o] = v;
     }
@@ -384,15 +419,15 @@ void amg_vcycle_level(const sg_amg* a, int l, const double* b, double* x, hipStr
         HIP_LAUNCH_OK();
     };
     jacobi(b, 0.0);
-    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
     HIP_LAUNCH_OK();
-    bsr_mv_kernel<<<C.nn, kBlk, 0, s>>>(P, L.r_ptr.p, L.r_col.p, L.r_val.p, L.r.p, C.b.p, 1.0, 0.0,
+    bsr_mv_kernel<<<C.nn, kBlkMv, 0, s>>>(P, L.r_ptr.p, L.r_col.p, L.r_val.p, L.r.p, C.b.p, 1.0, 0.0,
                                         nullptr);
     HIP_LAUNCH_OK();
     amg_vcycle_level(a, l + 1, C.b.p, C.x.p, s);
-    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, C.x.p, x, 1.0, 1.0, x);
+    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, C.x.p, x, 1.0, 1.0, x);
     HIP_LAUNCH_OK();
-    bsr_mv_kernel<<<L.nn, kBlk, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
     HIP_LAUNCH_OK();
     jacobi(L.r.p, 1.0);
 }
@@ -412,7 +447,13 @@ int amg_nsub(const sg_amg* a) { return a->n_sub; }
 int amg_device(const sg_amg* a) { return a->device; }
 
 void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s) {
-    restrict_kernel<<<a->n_sub, 256, 0, s>>>(a->P, a->own_ptr.p, a->own_nodes.p, R, rc);
+    restrict_partial_kernel<<<a->nslices, 256, 0, s>>>(a->P, a->nslices, a->slice_sub.p,
+                                                        a->slice_beg.p, a->slice_end.p,
+                                                        a->own_nodes.p, R, a->slice_part.p);
+    HIP_LAUNCH_OK();
+    int tot = a->n_sub * a->P;
+    restrict_final_kernel<<<(tot + 255) / 256, 256, 0, s>>>(a->n_sub, a->P, a->sub_slice_ptr.p,
+                                                             a->slice_part.p, rc);
     HIP_LAUNCH_OK();
 }
 
@@ -457,6 +498,23 @@ int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec p
         }
         a->own_ptr.upload(own_ptr, s);
         a->own_nodes.upload(own_nodes, s);
+        {
+            std::vector<int32_t> ssub, sbeg, send, sptr(1, 0);
+            for (int q = 0; q < ns; ++q) {
+                for (int b0 = own_ptr[q]; b0 < own_ptr[q + 1]; b0 += kSlice) {
+                    ssub.push_back(q);
+                    sbeg.push_back(b0);
+                    send.push_back(std::min(b0 + kSlice, own_ptr[q + 1]));
+                }
+                sptr.push_back((int32_t)ssub.size());
+            }
+            a->nslices = (int)ssub.size();
+            a->slice_sub.upload(ssub, s);
+            a->slice_beg.upload(sbeg, s);
+            a->slice_end.upload(send, s);
+            a->sub_slice_ptr.upload(sptr, s);
+            a->slice_part.alloc((size_t)a->nslices * P);
+        }
         a->owner.upload(owner, s);
         a->afact.upload(op->h_afact, s);
 

@@ -23,7 +23,7 @@
 
 struct sg_ras {
     int device = 0;
-    int n = 0, P = 0, L = 0, n_sub = 0, overlap = 0, max_b = 0;
+    int n = 0, P = 0, L = 0, n_sub = 0, overlap = 0, max_b = 0, max_local = 0;
     sg_prec prec = SG_FP64;
     int64_t total_local = 0, n_lev = 0, sinv_count = 0;
     std::vector<int32_t> h_nlocal, h_nlev, h_owner;
@@ -41,8 +41,16 @@ namespace sg {
 constexpr int kRasThreads = 256;
 constexpr int kMaxLevel = 64;
 constexpr int kColChunk = 16;   // max right-hand-side columns per work-group
-constexpr int kCouple = 6;      // max neighbours of a node in an adjacent level
+constexpr int kCouple = 4;      // max neighbours of a node in an adjacent level
 constexpr int kPrefetch = (kMaxLevel * kMaxLevel + kRasThreads - 1) / kRasThreads;
+constexpr int kNQ = (kMaxLevel * kColChunk + kRasThreads - 1) / kRasThreads;
+constexpr int kMaxLocal = 8192;  // max nodes of one overlapping subdomain
+
+inline size_t ras_apply_lds(sg_prec prec, int bmax, int KC, int nmax) {
+    const size_t ts = prec == SG_FP64 ? 8 : (prec == SG_FP32 ? 4 : 2);
+    return (size_t)3 * bmax * KC * sizeof(double) + 2 * (size_t)bmax * bmax * ts + 16 +
+           2 * (size_t)nmax * sizeof(int32_t);
+}
 
 namespace {
 
@@ -157,14 +165,15 @@ __global__ __launch_bounds__(kRasThreads) void ras_factor_kernel(
 }
 
 // Apply: one work-group per (subdomain, chunk of KC right-hand-side columns).
-// Per level: phase A gathers r_l and subtracts the coupling to the previous
-// level (fixed-width lists), phase B multiplies by S_l^{-1} held in LDS while
-// the next level's inverse is prefetched into registers and then stored into
-// the other LDS buffer.  Two barriers per level.
+// The subdomain's global node ids and ownership flags sit in LDS for the
+// whole sweep.  Every global load a level needs (its right-hand-side rows,
+// its couplings, its Schur inverse, and on the way back the stored z) is
+// issued one level ahead, while the previous level's dense product runs, so
+// the dependency chain of the sweeps only waits on LDS and arithmetic.
 // Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!.
 template <class TS>
 __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
-    int P, int KC, int bmax, const int32_t* __restrict__ sub_node_off,
+    int P, int KC, int bmax, int nmax, const int32_t* __restrict__ sub_node_off,
     const int32_t* __restrict__ sub_lev_off, const int32_t* __restrict__ lev_start,
     const int32_t* __restrict__ lev_size, const int64_t* __restrict__ sinv_off,
     const TS* __restrict__ sinv, const int32_t* __restrict__ gnode,
@@ -179,19 +188,27 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     double* Zp = Zc + bmax * KC;
     TS* Sb0 = reinterpret_cast<TS*>(Zp + bmax * KC);
     TS* Sb1 = Sb0 + bmax * bmax;
+    int32_t* lgn = reinterpret_cast<int32_t*>(
+        (reinterpret_cast<uintptr_t>(Sb1 + bmax * bmax) + 15) & ~uintptr_t(15));
+    int32_t* lown = lgn + nmax;
     const int s = blockIdx.x, tid = threadIdx.x;
     const int k0 = blockIdx.y * KC;
     const int kc = min(KC, P - k0);
     const int node0 = sub_node_off[s];
+    const int nloc = sub_node_off[s + 1] - node0;
     const int lv0 = sub_lev_off[s], lv1 = sub_lev_off[s + 1];
-    TS pre[kPrefetch];
 
-    auto load_direct = [&](int lv, TS* dst) {
-        const int b = lev_size[lv];
-        const int64_t off = sinv_off[lv];
-        for (int q = tid; q < b * b; q += kRasThreads) dst[q] = sinv[off + q];
-    };
-    auto prefetch = [&](int lv) {
+    TS pre[kPrefetch];
+    double rv[kNQ];
+    int cidx[kNQ][kCouple];
+    double cval[kNQ][kCouple];
+    double zcur[kNQ];
+
+    for (int q = tid; q < nloc; q += kRasThreads) {
+        lgn[q] = gnode[node0 + q];
+        lown[q] = owned[node0 + q];
+    }
+    auto prefetch_S = [&](int lv) {
         const int b = lev_size[lv];
         const int64_t off = sinv_off[lv];
 #pragma unroll
@@ -200,7 +217,7 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
             if (q < b * b) pre[p] = sinv[off + q];
         }
     };
-    auto commit = [&](int lv, TS* dst) {
+    auto commit_S = [&](int lv, TS* dst) {
         const int b = lev_size[lv];
 #pragma unroll
         for (int p = 0; p < kPrefetch; ++p) {
@@ -208,53 +225,104 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
             if (q < b * b) dst[q] = pre[p];
         }
     };
+    // forward inputs of level lv: right-hand side rows and couplings to lv-1
+    auto prefetch_fwd = [&](int lv) {
+        const int st = lev_start[lv], b = lev_size[lv];
+#pragma unroll
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int r = q / kc, k = q - r * kc;
+                const int row = st + r;
+                rv[o] = R[(size_t)lgn[row] * P + k0 + k];
+#pragma unroll
+                for (int c = 0; c < kCouple; ++c) {
+                    cidx[o][c] = prev_idx[(size_t)(node0 + row) * kCouple + c];
+                    cval[o][c] = prev_val[(size_t)(node0 + row) * kCouple + c];
+                }
+            }
+        }
+    };
+    // backward inputs of level lv: stored z and couplings to lv+1
+    auto prefetch_bwd = [&](int lv) {
+        const int st = lev_start[lv], b = lev_size[lv];
+#pragma unroll
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int r = q / kc, k = q - r * kc;
+                const int row = st + r;
+                rv[o] = zs[(size_t)(node0 + row) * P + k0 + k];
+#pragma unroll
+                for (int c = 0; c < kCouple; ++c) {
+                    cidx[o][c] = next_idx[(size_t)(node0 + row) * kCouple + c];
+                    cval[o][c] = next_val[(size_t)(node0 + row) * kCouple + c];
+                }
+            }
+        }
+    };
     auto write_out = [&](int row, int k, double x) {
-        if (owned[row]) {
-            const size_t o = (size_t)gnode[row] * P + k0 + k;
+        if (lown[row]) {
+            const size_t o = (size_t)lgn[row] * P + k0 + k;
             const double v = omega * x / afact[k0 + k];
             Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
         }
     };
+    auto dense_row = [&](const TS* srow, int b, const double* V, int k) -> double {
+        Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int c = 0;
+        for (; c + 3 < b; c += 4) {
+            a0 += Load<TS>::get(srow, c) * (Acc)V[c * kc + k];
+            a1 += Load<TS>::get(srow, c + 1) * (Acc)V[(c + 1) * kc + k];
+            a2 += Load<TS>::get(srow, c + 2) * (Acc)V[(c + 2) * kc + k];
+            a3 += Load<TS>::get(srow, c + 3) * (Acc)V[(c + 3) * kc + k];
+        }
+        for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)V[c * kc + k];
+        return (double)((a0 + a1) + (a2 + a3));
+    };
 
     // ---------------- forward sweep
-    load_direct(lv0, Sb0);
-    __syncthreads();
+    {
+        const int b = lev_size[lv0];
+        const int64_t off = sinv_off[lv0];
+        for (int q = tid; q < b * b; q += kRasThreads) Sb0[q] = sinv[off + q];
+    }
+    __syncthreads();                      // lgn, Sb0 ready
+    prefetch_fwd(lv0);
     for (int lv = lv0; lv < lv1; ++lv) {
         const int st = lev_start[lv], b = lev_size[lv];
         TS* cur = ((lv - lv0) & 1) ? Sb1 : Sb0;
         TS* nxt = ((lv - lv0) & 1) ? Sb0 : Sb1;
-        for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - r * kc;
-            const int row = node0 + st + r;
-            double y = R[(size_t)gnode[row] * P + k0 + k];
-            if (lv > lv0) {
 #pragma unroll
-                for (int c = 0; c < kCouple; ++c) {
-                    const int pi = prev_idx[(size_t)row * kCouple + c];
-                    if (pi >= 0) y = fma(-prev_val[(size_t)row * kCouple + c], Zp[pi * kc + k], y);
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int k = q - (q / kc) * kc;
+                double y = rv[o];
+                if (lv > lv0) {
+#pragma unroll
+                    for (int c = 0; c < kCouple; ++c)
+                        if (cidx[o][c] >= 0) y = fma(-cval[o][c], Zp[cidx[o][c] * kc + k], y);
                 }
+                Y[q] = y;
             }
-            Y[q] = y;
         }
-        if (lv + 1 < lv1) prefetch(lv + 1);
+        if (lv + 1 < lv1) {
+            prefetch_S(lv + 1);
+            prefetch_fwd(lv + 1);
+        }
         __syncthreads();
-        for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - r * kc;
-            const TS* srow = cur + r * b;
-            Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int c = 0;
-            for (; c + 3 < b; c += 4) {
-                a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
-                a1 += Load<TS>::get(srow, c + 1) * (Acc)Y[(c + 1) * kc + k];
-                a2 += Load<TS>::get(srow, c + 2) * (Acc)Y[(c + 2) * kc + k];
-                a3 += Load<TS>::get(srow, c + 3) * (Acc)Y[(c + 3) * kc + k];
+#pragma unroll
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int r = q / kc, k = q - r * kc;
+                const double z = dense_row(cur + r * b, b, Y, k);
+                Zc[q] = z;
+                zs[(size_t)(node0 + st + r) * P + k0 + k] = z;
             }
-            for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
-            const double z = (double)((a0 + a1) + (a2 + a3));
-            Zc[q] = z;
-            zs[(size_t)(node0 + st + r) * P + k0 + k] = z;
         }
-        if (lv + 1 < lv1) commit(lv + 1, nxt);
+        if (lv + 1 < lv1) commit_S(lv + 1, nxt);
         __syncthreads();
         double* t = Zp; Zp = Zc; Zc = t;
     }
@@ -265,11 +333,16 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
         const int st = lev_start[lv], b = lev_size[lv];
         for (int q = tid; q < b * kc; q += kRasThreads) {
             const int r = q / kc, k = q - r * kc;
-            write_out(node0 + st + r, k, Zp[q]);
+            write_out(st + r, k, Zp[q]);
         }
     }
     if (lv1 - 2 < lv0) return;
-    load_direct(lv1 - 2, Sb0);
+    {
+        const int b = lev_size[lv1 - 2];
+        const int64_t off = sinv_off[lv1 - 2];
+        for (int q = tid; q < b * b; q += kRasThreads) Sb0[q] = sinv[off + q];
+    }
+    prefetch_bwd(lv1 - 2);
     __syncthreads();
     double* Xn = Zp;
     double* Xc = Zc;
@@ -277,37 +350,35 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
         const int st = lev_start[lv], b = lev_size[lv];
         TS* cur = ((lv1 - 2 - lv) & 1) ? Sb1 : Sb0;
         TS* nxt = ((lv1 - 2 - lv) & 1) ? Sb0 : Sb1;
-        for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - r * kc;
-            const int row = node0 + st + r;
-            double t = 0.0;
 #pragma unroll
-            for (int c = 0; c < kCouple; ++c) {
-                const int ni = next_idx[(size_t)row * kCouple + c];
-                if (ni >= 0) t = fma(next_val[(size_t)row * kCouple + c], Xn[ni * kc + k], t);
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int k = q - (q / kc) * kc;
+                double t = 0.0;
+#pragma unroll
+                for (int c = 0; c < kCouple; ++c)
+                    if (cidx[o][c] >= 0) t = fma(cval[o][c], Xn[cidx[o][c] * kc + k], t);
+                Y[q] = t;
+                zcur[o] = rv[o];
             }
-            Y[q] = t;
         }
-        if (lv - 1 >= lv0) prefetch(lv - 1);
+        if (lv - 1 >= lv0) {
+            prefetch_S(lv - 1);
+            prefetch_bwd(lv - 1);
+        }
         __syncthreads();
-        for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - r * kc;
-            const int row = node0 + st + r;
-            const TS* srow = cur + r * b;
-            Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-            int c = 0;
-            for (; c + 3 < b; c += 4) {
-                a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
-                a1 += Load<TS>::get(srow, c + 1) * (Acc)Y[(c + 1) * kc + k];
-                a2 += Load<TS>::get(srow, c + 2) * (Acc)Y[(c + 2) * kc + k];
-                a3 += Load<TS>::get(srow, c + 3) * (Acc)Y[(c + 3) * kc + k];
+#pragma unroll
+        for (int o = 0; o < kNQ; ++o) {
+            const int q = tid + o * kRasThreads;
+            if (q < b * kc) {
+                const int r = q / kc, k = q - r * kc;
+                const double x = zcur[o] - dense_row(cur + r * b, b, Y, k);
+                Xc[q] = x;
+                write_out(st + r, k, x);
             }
-            for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)Y[c * kc + k];
-            const double x = zs[(size_t)row * P + k0 + k] - (double)((a0 + a1) + (a2 + a3));
-            Xc[q] = x;
-            write_out(row, k, x);
         }
-        if (lv - 1 >= lv0) commit(lv - 1, nxt);
+        if (lv - 1 >= lv0) commit_S(lv - 1, nxt);
         __syncthreads();
         double* t2 = Xn; Xn = Xc; Xc = t2;
     }
@@ -320,11 +391,10 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
     const int nch = (r->P + kColChunk - 1) / kColChunk;
     const int KC = (r->P + nch - 1) / nch;
     dim3 grid(r->n_sub, nch);
-    const int bmax = r->max_b;
-    size_t ts = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
-    size_t lds = (size_t)3 * bmax * KC * sizeof(double) + 2 * (size_t)bmax * bmax * ts;
-#define SG_RAS_ARGS                                                                      \
-    r->P, KC, bmax, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, \
+    const int bmax = r->max_b, nmax = r->max_local;
+    size_t lds = ras_apply_lds(r->prec, bmax, KC, nmax);
+#define SG_RAS_ARGS                                                                            \
+    r->P, KC, bmax, nmax, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, \
         r->sinv_off.p
 #define SG_RAS_TAIL                                                                           \
     r->gnode.p, r->owned.p, r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p,      \
@@ -537,6 +607,9 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
             sub_node_off.push_back((int32_t)gnode.size());
             sub_lev_off.push_back((int32_t)lev_start.size());
             r->h_nlocal[sd] = m;
+            if (m > kMaxLocal)
+                SG_THROW(SG_ERR_UNSUPPORTED, "subdomain %d has %d nodes (limit %d)", sd, m, kMaxLocal);
+            r->max_local = std::max(r->max_local, m);
             r->h_nlev[sd] = nl;
             for (int a : nodes) local_id[a] = -1;
         }
@@ -593,7 +666,7 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         {
             const int nch = (r->P + kColChunk - 1) / kColChunk;
             const int KC = (r->P + nch - 1) / nch;
-            size_t need = (size_t)3 * max_b * KC * 8 + 2 * (size_t)max_b * max_b * 8;
+            size_t need = ras_apply_lds(SG_FP64, max_b, KC, r->max_local);
             if ((size_t)max_lds < need)
                 SG_THROW(SG_ERR_UNSUPPORTED, "RAS apply needs %zu bytes of LDS", need);
         }
