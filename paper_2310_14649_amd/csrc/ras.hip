@@ -23,7 +23,8 @@
 
 struct sg_ras {
     int device = 0;
-    int n = 0, P = 0, L = 0, n_sub = 0, overlap = 0, max_b = 0, max_local = 0;
+    int n = 0, P = 0, L = 0, n_sub = 0, overlap = 0, max_b = 0, max_local = 0, max_couple = 0,
+        max_levels = 0;
     sg_prec prec = SG_FP64;
     int64_t total_local = 0, n_lev = 0, sinv_count = 0;
     std::vector<int32_t> h_nlocal, h_nlev, h_owner;
@@ -40,16 +41,18 @@ namespace sg {
 
 constexpr int kRasThreads = 256;
 constexpr int kMaxLevel = 64;
-constexpr int kColChunk = 16;   // max right-hand-side columns per work-group
+constexpr int kColChunk = 16;   // right-hand-side columns per work-group (one MFMA tile)
 constexpr int kCouple = 4;      // max neighbours of a node in an adjacent level
-constexpr int kPrefetch = (kMaxLevel * kMaxLevel + kRasThreads - 1) / kRasThreads;
-constexpr int kNQ = (kMaxLevel * kColChunk + kRasThreads - 1) / kRasThreads;
 constexpr int kMaxLocal = 8192;  // max nodes of one overlapping subdomain
 
-inline size_t ras_apply_lds(sg_prec prec, int bmax, int KC, int nmax) {
+inline size_t ras_apply_lds(sg_prec prec, int bmax, int KC, int nmax, int lmax) {
+    (void)KC;
     const size_t ts = prec == SG_FP64 ? 8 : (prec == SG_FP32 ? 4 : 2);
-    return (size_t)3 * bmax * KC * sizeof(double) + 2 * (size_t)bmax * bmax * ts + 16 +
-           2 * (size_t)nmax * sizeof(int32_t);
+    const int KS = prec == SG_BF16 ? 32 : 4;
+    const size_t rp = ((bmax + 15) / 16) * 16, cp = ((bmax + KS - 1) / KS) * KS;
+    return rp * cp * ts + cp * 16 * ts + 16 + 2 * (size_t)bmax * 16 * sizeof(double) +
+           (size_t)nmax * sizeof(int32_t) + 2 * (size_t)lmax * sizeof(int32_t) + 8 +
+           (size_t)lmax * sizeof(int64_t) + 16 * sizeof(double);
 }
 
 namespace {
@@ -61,6 +64,16 @@ __device__ inline uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Work-group barrier for LDS traffic only: waits for this wave's LDS
+// operations (lgkmcnt) but not for outstanding global loads, so prefetches
+// issued before the barrier stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // vmcnt=max, expcnt=max, lgkmcnt=0
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <class TS> struct Load;
 template <> struct Load<double> {
@@ -164,16 +177,80 @@ __global__ __launch_bounds__(kRasThreads) void ras_factor_kernel(
     }
 }
 
-// Apply: one work-group per (subdomain, chunk of KC right-hand-side columns).
-// The subdomain's global node ids and ownership flags sit in LDS for the
-// whole sweep.  Every global load a level needs (its right-hand-side rows,
-// its couplings, its Schur inverse, and on the way back the stored z) is
-// issued one level ahead, while the previous level's dense product runs, so
-// the dependency chain of the sweeps only waits on LDS and arithmetic.
+// Per-precision matrix-core step of the level product Z_l = S_l^{-1} Y_l on a
+// 16-row tile (wave w owns rows 16w..16w+15, the 16 columns of the chunk):
+//   FP64: v_mfma_f64_16x16x4f64, Y in FP64;
+//   FP32: v_mfma_f32_16x16x4f32, Y rounded to FP32;
+//   BF16: v_mfma_f32_16x16x32_bf16, Y rounded to BF16; FP32 accumulation.
+// A[i][k] sits in lane i + 16*(k / kpl) (kpl consecutive k per lane), B[k][j]
+// in lane j + 16*(k / kpl); the output row of register v is row_of(lane, v)
+// and its column lane % 16.
+typedef double sg_d4 __attribute__((ext_vector_type(4)));
+typedef float sg_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 sg_bf8 __attribute__((ext_vector_type(8)));
+
+template <class TS> struct Mma;
+template <> struct Mma<double> {
+    using YT = double;
+    using Acc = sg_d4;
+    static constexpr int KS = 4;
+    static constexpr bool ytrans = false;
+    static __device__ Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ int row_of(int lane, int v) { return 4 * v + (lane >> 4); }
+    static __device__ Acc step(const double* S, int cp, const double* Y, int c0, int lane, int w,
+                               Acc acc) {
+        const double a = S[(16 * w + (lane & 15)) * cp + c0 + (lane >> 4)];
+        const double b = Y[(c0 + (lane >> 4)) * 16 + (lane & 15)];
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    static __device__ YT conv(double x) { return x; }
+};
+template <> struct Mma<float> {
+    using YT = float;
+    using Acc = sg_f4;
+    static constexpr int KS = 4;
+    static constexpr bool ytrans = false;
+    static __device__ Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ Acc step(const float* S, int cp, const float* Y, int c0, int lane, int w,
+                               Acc acc) {
+        const float a = S[(16 * w + (lane & 15)) * cp + c0 + (lane >> 4)];
+        const float b = Y[(c0 + (lane >> 4)) * 16 + (lane & 15)];
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+    static __device__ YT conv(double x) { return (float)x; }
+};
+template <> struct Mma<uint16_t> {
+    using YT = uint16_t;
+    using Acc = sg_f4;
+    static constexpr int KS = 32;
+    static constexpr bool ytrans = true;      // Y stored [16][cp] so 8 k are contiguous
+    static __device__ Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ Acc step(const uint16_t* S, int cp, const uint16_t* Y, int c0, int lane, int w,
+                               Acc acc) {
+        const uint4 a4 = *reinterpret_cast<const uint4*>(S + (16 * w + (lane & 15)) * cp + c0 + 8 * (lane >> 4));
+        const uint4 b4 = *reinterpret_cast<const uint4*>(Y + (lane & 15) * cp + c0 + 8 * (lane >> 4));
+        sg_bf8 a, b;
+        __builtin_memcpy(&a, &a4, 16);
+        __builtin_memcpy(&b, &b4, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    static __device__ YT conv(double x) { return to_bf16((float)x); }
+};
+
+// Apply: one work-group (4 waves) per (subdomain, chunk of KC <= 16
+// right-hand-side columns).  The subdomain's global node ids and ownership
+// flags sit in LDS for the whole sweep.  Each level: phase A forms the
+// right-hand-side tile (gathered rows minus the coupling to the neighbour
+// level) in the operand precision; phase B multiplies by S_l^{-1} on the
+// matrix cores, one wave per 16-row tile.  Every global load a level needs is
+// issued one level ahead (during the previous level's product), and the
+// barriers wait for LDS traffic only, so those loads stay in flight.
 // Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!.
-template <class TS>
+template <class TS, int KCP, int BM>
 __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
-    int P, int KC, int bmax, int nmax, const int32_t* __restrict__ sub_node_off,
+    int P, int KC, int bmax, int nmax, int lmax, const int32_t* __restrict__ sub_node_off,
     const int32_t* __restrict__ sub_lev_off, const int32_t* __restrict__ lev_start,
     const int32_t* __restrict__ lev_size, const int64_t* __restrict__ sinv_off,
     const TS* __restrict__ sinv, const int32_t* __restrict__ gnode,
@@ -181,205 +258,232 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     const double* __restrict__ prev_val, const int32_t* __restrict__ next_idx,
     const double* __restrict__ next_val, const double* __restrict__ afact,
     const double* __restrict__ R, double* Z, double* __restrict__ zs, double omega, double beta) {
-    using Acc = typename Load<TS>::Acc;
+    using MM = Mma<TS>;
+    using YT = typename MM::YT;
+    constexpr int KS = MM::KS;
+    constexpr int RPM = ((BM + 15) / 16) * 16;
+    constexpr int CPM = ((BM + KS - 1) / KS) * KS;
+    constexpr int NPF = (RPM * CPM + kRasThreads - 1) / kRasThreads;
+    constexpr int NQ = (CPM * 16 + kRasThreads - 1) / kRasThreads;
+    constexpr int NK = CPM / KS;                  // max product steps per level
+    auto rp_of = [](int b) { return ((b + 15) / 16) * 16; };
+    auto cp_of = [](int b) { return ((b + KS - 1) / KS) * KS; };
+    const int rpx = rp_of(bmax), cpx = cp_of(bmax);
     extern __shared__ __align__(16) unsigned char ras_smem[];
-    double* Y = reinterpret_cast<double*>(ras_smem);
-    double* Zc = Y + bmax * KC;
-    double* Zp = Zc + bmax * KC;
-    TS* Sb0 = reinterpret_cast<TS*>(Zp + bmax * KC);
-    TS* Sb1 = Sb0 + bmax * bmax;
-    int32_t* lgn = reinterpret_cast<int32_t*>(
-        (reinterpret_cast<uintptr_t>(Sb1 + bmax * bmax) + 15) & ~uintptr_t(15));
-    int32_t* lown = lgn + nmax;
+    TS* Sb = reinterpret_cast<TS*>(ras_smem);                               // rpx*cpx
+    YT* Y = reinterpret_cast<YT*>(Sb + rpx * cpx);                           // cpx*16
+    double* Zc = reinterpret_cast<double*>(
+        (reinterpret_cast<uintptr_t>(Y + cpx * 16) + 15) & ~uintptr_t(15)); // bmax*16
+    double* Zp = Zc + bmax * 16;
+    int32_t* lgn = reinterpret_cast<int32_t*>(Zp + bmax * 16);               // nmax, bit 31 = owned
+    int32_t* lmeta = lgn + nmax;                                             // 2*lmax: start, size
+    int64_t* loff = reinterpret_cast<int64_t*>(
+        (reinterpret_cast<uintptr_t>(lmeta + 2 * lmax) + 7) & ~uintptr_t(7)); // lmax
+    double* lfac = reinterpret_cast<double*>(loff + lmax);                   // 16
     const int s = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int k0 = blockIdx.y * KC;
     const int kc = min(KC, P - k0);
     const int node0 = sub_node_off[s];
     const int nloc = sub_node_off[s + 1] - node0;
     const int lv0 = sub_lev_off[s], lv1 = sub_lev_off[s + 1];
 
-    TS pre[kPrefetch];
-    double rv[kNQ];
-    int cidx[kNQ][kCouple];
-    double cval[kNQ][kCouple];
-    double zcur[kNQ];
+    TS pre[NPF];
+    double rv[NQ];
+    int cidx[NQ][KCP];
+    double cval[NQ][KCP];
+    double zsv[4], zcur[4];
 
-    for (int q = tid; q < nloc; q += kRasThreads) {
-        lgn[q] = gnode[node0 + q];
-        lown[q] = owned[node0 + q];
+    // phase-A position q -> (row c of the tile, column j)
+    auto pos = [&](int q, int cp, int& c, int& j) {
+        if constexpr (MM::ytrans) { j = q / cp; c = q - j * cp; }
+        else { c = q >> 4; j = q & 15; }
+    };
+    auto yidx = [&](int c, int j, int cp) { return MM::ytrans ? j * cp + c : c * 16 + j; };
+
+    for (int q = tid; q < nloc; q += kRasThreads)
+        lgn[q] = gnode[node0 + q] | (owned[node0 + q] ? int32_t(0x80000000u) : 0);
+    for (int q = tid; q < lv1 - lv0; q += kRasThreads) {
+        lmeta[2 * q] = lev_start[lv0 + q];
+        lmeta[2 * q + 1] = lev_size[lv0 + q];
+        loff[q] = sinv_off[lv0 + q];
     }
+    if (tid < 16) lfac[tid] = tid < kc ? omega / afact[k0 + tid] : 0.0;
+    auto LST = [&](int lv) { return lmeta[2 * (lv - lv0)]; };
+    auto LSZ = [&](int lv) { return lmeta[2 * (lv - lv0) + 1]; };
+    auto LOF = [&](int lv) { return loff[lv - lv0]; };
+    auto gid = [&](int row) { return lgn[row] & 0x7fffffff; };
+
     auto prefetch_S = [&](int lv) {
-        const int b = lev_size[lv];
-        const int64_t off = sinv_off[lv];
+        const int b = LSZ(lv);
+        const int64_t off = LOF(lv);
+        const int rp = rp_of(b), cp = cp_of(b);
 #pragma unroll
-        for (int p = 0; p < kPrefetch; ++p) {
+        for (int p = 0; p < NPF; ++p) {
             const int q = tid + p * kRasThreads;
-            if (q < b * b) pre[p] = sinv[off + q];
-        }
-    };
-    auto commit_S = [&](int lv, TS* dst) {
-        const int b = lev_size[lv];
-#pragma unroll
-        for (int p = 0; p < kPrefetch; ++p) {
-            const int q = tid + p * kRasThreads;
-            if (q < b * b) dst[q] = pre[p];
-        }
-    };
-    // forward inputs of level lv: right-hand side rows and couplings to lv-1
-    auto prefetch_fwd = [&](int lv) {
-        const int st = lev_start[lv], b = lev_size[lv];
-#pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
-            const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int r = q / kc, k = q - r * kc;
-                const int row = st + r;
-                rv[o] = R[(size_t)lgn[row] * P + k0 + k];
-#pragma unroll
-                for (int c = 0; c < kCouple; ++c) {
-                    cidx[o][c] = prev_idx[(size_t)(node0 + row) * kCouple + c];
-                    cval[o][c] = prev_val[(size_t)(node0 + row) * kCouple + c];
-                }
+            if (q < rp * cp) {
+                const int r = q / cp, c = q - r * cp;
+                pre[p] = (r < b && c < b) ? sinv[off + (int64_t)r * b + c] : TS(0);
             }
         }
     };
-    // backward inputs of level lv: stored z and couplings to lv+1
-    auto prefetch_bwd = [&](int lv) {
-        const int st = lev_start[lv], b = lev_size[lv];
+    auto commit_S = [&](int lv) {
+        const int b = LSZ(lv);
+        const int rp = rp_of(b), cp = cp_of(b);
 #pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
+        for (int p = 0; p < NPF; ++p) {
+            const int q = tid + p * kRasThreads;
+            if (q < rp * cp) Sb[q] = pre[p];
+        }
+    };
+    auto prefetch_rows = [&](int lv, bool fwd) {
+        const int st = LST(lv), b = LSZ(lv);
+        const int cp = cp_of(b);
+        const int32_t* ci = fwd ? prev_idx : next_idx;
+        const double* cv = fwd ? prev_val : next_val;
+#pragma unroll
+        for (int o = 0; o < NQ; ++o) {
             const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int r = q / kc, k = q - r * kc;
-                const int row = st + r;
-                rv[o] = zs[(size_t)(node0 + row) * P + k0 + k];
+            int c, j;
+            pos(q, cp, c, j);
+            if (q < cp * 16 && c < b && j < kc) {
+                const int row = st + c;
+                if (fwd) rv[o] = R[(size_t)gid(row) * P + k0 + j];
 #pragma unroll
-                for (int c = 0; c < kCouple; ++c) {
-                    cidx[o][c] = next_idx[(size_t)(node0 + row) * kCouple + c];
-                    cval[o][c] = next_val[(size_t)(node0 + row) * kCouple + c];
+                for (int e = 0; e < KCP; ++e) {
+                    cidx[o][e] = ci[(size_t)(node0 + row) * kCouple + e];
+                    cval[o][e] = cv[(size_t)(node0 + row) * kCouple + e];
                 }
+            }
+        }
+        if (!fwd) {
+            const int rt = rp_of(b) / 16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * wave + MM::row_of(lane, v), j = lane & 15;
+                if (wave < rt && r < b && j < kc) zsv[v] = zs[(size_t)(node0 + st + r) * P + k0 + j];
             }
         }
     };
     auto write_out = [&](int row, int k, double x) {
-        if (lown[row]) {
-            const size_t o = (size_t)lgn[row] * P + k0 + k;
-            const double v = omega * x / afact[k0 + k];
+        const int g = lgn[row];
+        if (g < 0) {
+            const size_t o = (size_t)(g & 0x7fffffff) * P + k0 + k;
+            const double v = x * lfac[k];
             Z[o] = beta != 0.0 ? fma(beta, Z[o], v) : v;
         }
     };
-    auto dense_row = [&](const TS* srow, int b, const double* V, int k) -> double {
-        Acc a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int c = 0;
-        for (; c + 3 < b; c += 4) {
-            a0 += Load<TS>::get(srow, c) * (Acc)V[c * kc + k];
-            a1 += Load<TS>::get(srow, c + 1) * (Acc)V[(c + 1) * kc + k];
-            a2 += Load<TS>::get(srow, c + 2) * (Acc)V[(c + 2) * kc + k];
-            a3 += Load<TS>::get(srow, c + 3) * (Acc)V[(c + 3) * kc + k];
-        }
-        for (; c < b; ++c) a0 += Load<TS>::get(srow, c) * (Acc)V[c * kc + k];
-        return (double)((a0 + a1) + (a2 + a3));
+    // phase B: S_l^{-1} (wave's row tile) * Y on the matrix cores
+    auto product = [&](int b) -> typename MM::Acc {
+        const int nk = cp_of(b) / KS;
+        const int cp = cp_of(b);
+        typename MM::Acc acc = MM::zero();
+#pragma unroll
+        for (int t = 0; t < NK; ++t)
+            if (t < nk) acc = MM::step(Sb, cp, Y, t * KS, lane, wave, acc);
+        return acc;
     };
 
     // ---------------- forward sweep
-    {
-        const int b = lev_size[lv0];
-        const int64_t off = sinv_off[lv0];
-        for (int q = tid; q < b * b; q += kRasThreads) Sb0[q] = sinv[off + q];
-    }
-    __syncthreads();                      // lgn, Sb0 ready
-    prefetch_fwd(lv0);
+    lds_barrier();                               // lgn ready
+    prefetch_S(lv0);
+    prefetch_rows(lv0, true);
     for (int lv = lv0; lv < lv1; ++lv) {
-        const int st = lev_start[lv], b = lev_size[lv];
-        TS* cur = ((lv - lv0) & 1) ? Sb1 : Sb0;
-        TS* nxt = ((lv - lv0) & 1) ? Sb0 : Sb1;
+        const int st = LST(lv), b = LSZ(lv);
+        const int cp = cp_of(b);
+        commit_S(lv);
 #pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
+        for (int o = 0; o < NQ; ++o) {
             const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int k = q - (q / kc) * kc;
-                double y = rv[o];
-                if (lv > lv0) {
+            if (q < cp * 16) {
+                int c, j;
+                pos(q, cp, c, j);
+                double y = 0.0;
+                if (c < b && j < kc) {
+                    y = rv[o];
+                    if (lv > lv0) {
 #pragma unroll
-                    for (int c = 0; c < kCouple; ++c)
-                        if (cidx[o][c] >= 0) y = fma(-cval[o][c], Zp[cidx[o][c] * kc + k], y);
+                        for (int e = 0; e < KCP; ++e)
+                            if (cidx[o][e] >= 0) y = fma(-cval[o][e], Zp[cidx[o][e] * 16 + j], y);
+                    }
                 }
-                Y[q] = y;
+                Y[yidx(c, j, cp)] = MM::conv(y);
             }
         }
+        lds_barrier();
         if (lv + 1 < lv1) {
             prefetch_S(lv + 1);
-            prefetch_fwd(lv + 1);
+            prefetch_rows(lv + 1, true);
         }
-        __syncthreads();
+        if (wave < rp_of(b) / 16) {
+            const auto acc = product(b);
 #pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
-            const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int r = q / kc, k = q - r * kc;
-                const double z = dense_row(cur + r * b, b, Y, k);
-                Zc[q] = z;
-                zs[(size_t)(node0 + st + r) * P + k0 + k] = z;
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * wave + MM::row_of(lane, v), j = lane & 15;
+                if (r < b && j < kc) {
+                    const double z = (double)acc[v];
+                    Zc[r * 16 + j] = z;
+                    zs[(size_t)(node0 + st + r) * P + k0 + j] = z;
+                }
             }
         }
-        if (lv + 1 < lv1) commit_S(lv + 1, nxt);
-        __syncthreads();
+        lds_barrier();
         double* t = Zp; Zp = Zc; Zc = t;
     }
 
     // ---------------- backward sweep: Zp holds x of the last level
     {
         const int lv = lv1 - 1;
-        const int st = lev_start[lv], b = lev_size[lv];
-        for (int q = tid; q < b * kc; q += kRasThreads) {
-            const int r = q / kc, k = q - r * kc;
-            write_out(st + r, k, Zp[q]);
+        const int st = LST(lv), b = LSZ(lv);
+        for (int q = tid; q < b * 16; q += kRasThreads) {
+            const int r = q >> 4, j = q & 15;
+            if (j < kc) write_out(st + r, j, Zp[r * 16 + j]);
         }
     }
     if (lv1 - 2 < lv0) return;
-    {
-        const int b = lev_size[lv1 - 2];
-        const int64_t off = sinv_off[lv1 - 2];
-        for (int q = tid; q < b * b; q += kRasThreads) Sb0[q] = sinv[off + q];
-    }
-    prefetch_bwd(lv1 - 2);
-    __syncthreads();
+    prefetch_S(lv1 - 2);
+    prefetch_rows(lv1 - 2, false);
     double* Xn = Zp;
     double* Xc = Zc;
     for (int lv = lv1 - 2; lv >= lv0; --lv) {
-        const int st = lev_start[lv], b = lev_size[lv];
-        TS* cur = ((lv1 - 2 - lv) & 1) ? Sb1 : Sb0;
-        TS* nxt = ((lv1 - 2 - lv) & 1) ? Sb0 : Sb1;
+        const int st = LST(lv), b = LSZ(lv);
+        const int cp = cp_of(b);
+        commit_S(lv);
 #pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
+        for (int o = 0; o < NQ; ++o) {
             const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int k = q - (q / kc) * kc;
+            if (q < cp * 16) {
+                int c, j;
+                pos(q, cp, c, j);
                 double t = 0.0;
+                if (c < b && j < kc) {
 #pragma unroll
-                for (int c = 0; c < kCouple; ++c)
-                    if (cidx[o][c] >= 0) t = fma(cval[o][c], Xn[cidx[o][c] * kc + k], t);
-                Y[q] = t;
-                zcur[o] = rv[o];
+                    for (int e = 0; e < KCP; ++e)
+                        if (cidx[o][e] >= 0) t = fma(cval[o][e], Xn[cidx[o][e] * 16 + j], t);
+                }
+                Y[yidx(c, j, cp)] = MM::conv(t);
             }
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zcur[v] = zsv[v];
+        lds_barrier();
         if (lv - 1 >= lv0) {
             prefetch_S(lv - 1);
-            prefetch_bwd(lv - 1);
+            prefetch_rows(lv - 1, false);
         }
-        __syncthreads();
+        if (wave < rp_of(b) / 16) {
+            const auto acc = product(b);
 #pragma unroll
-        for (int o = 0; o < kNQ; ++o) {
-            const int q = tid + o * kRasThreads;
-            if (q < b * kc) {
-                const int r = q / kc, k = q - r * kc;
-                const double x = zcur[o] - dense_row(cur + r * b, b, Y, k);
-                Xc[q] = x;
-                write_out(st + r, k, x);
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * wave + MM::row_of(lane, v), j = lane & 15;
+                if (r < b && j < kc) {
+                    const double x = zcur[v] - (double)acc[v];
+                    Xc[r * 16 + j] = x;
+                    write_out(st + r, j, x);
+                }
             }
         }
-        if (lv - 1 >= lv0) commit_S(lv - 1, nxt);
-        __syncthreads();
+        lds_barrier();
         double* t2 = Xn; Xn = Xc; Xc = t2;
     }
 }
@@ -392,19 +496,33 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
     const int KC = (r->P + nch - 1) / nch;
     dim3 grid(r->n_sub, nch);
     const int bmax = r->max_b, nmax = r->max_local;
-    size_t lds = ras_apply_lds(r->prec, bmax, KC, nmax);
+    size_t lds = ras_apply_lds(r->prec, bmax, KC, nmax, r->max_levels);
 #define SG_RAS_ARGS                                                                            \
-    r->P, KC, bmax, nmax, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, \
+    r->P, KC, bmax, nmax, r->max_levels, r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, \
         r->sinv_off.p
 #define SG_RAS_TAIL                                                                           \
     r->gnode.p, r->owned.p, r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p,      \
         r->afact.p, R, Z, r->zs.p, omega, beta
+    const bool small = bmax <= 40;
+    const bool narrow = r->max_couple <= 2;
+#define SG_RAS_GO(TS, PTR)                                                                      \
+    do {                                                                                        \
+        if (narrow && small)                                                                    \
+            ras_apply_kernel<TS, 2, 40><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
+        else if (narrow)                                                                        \
+            ras_apply_kernel<TS, 2, 64><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
+        else if (small)                                                                         \
+            ras_apply_kernel<TS, 4, 40><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
+        else                                                                                    \
+            ras_apply_kernel<TS, 4, 64><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
+    } while (0)
     if (r->prec == SG_FP64)
-        ras_apply_kernel<double><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv64.p, SG_RAS_TAIL);
+        SG_RAS_GO(double, r->sinv64.p);
     else if (r->prec == SG_FP32)
-        ras_apply_kernel<float><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv32.p, SG_RAS_TAIL);
+        SG_RAS_GO(float, r->sinv32.p);
     else
-        ras_apply_kernel<uint16_t><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, r->sinv16.p, SG_RAS_TAIL);
+        SG_RAS_GO(uint16_t, r->sinv16.p);
+#undef SG_RAS_GO
 #undef SG_RAS_ARGS
 #undef SG_RAS_TAIL
     HIP_LAUNCH_OK();
@@ -544,6 +662,19 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
                              [&](int x, int y) { return lvl[x] < lvl[y]; });
             std::vector<int> pos(m);
             for (int q = 0; q < m; ++q) pos[order[q]] = q;
+            // The breadth-first order is a banded ordering: every coupling
+            // joins positions at most `band` apart.  Cutting the order into
+            // consecutive blocks of `band` nodes therefore also gives a block
+            // tridiagonal matrix, with about half as many (wider) blocks as
+            // there are level sets -- half the length of the sequential chain
+            // of the sweeps.  Used whenever the band fits a block.
+            int band = 1;
+            for (int qq = 0; qq < m; ++qq)
+                for (int w : adj[qq]) band = std::max(band, std::abs(pos[qq] - pos[w]));
+            if (band <= kMaxLevel) {
+                for (int qq = 0; qq < m; ++qq) lvl[qq] = pos[qq] / band;
+                nl = (m + band - 1) / band;
+            }
             // levels
             int q = 0;
             std::vector<int> lstart(nl + 1, 0);
@@ -603,6 +734,7 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
                     }
                 }
                 lrow_ptr.push_back((int32_t)lcol.size());
+                r->max_couple = std::max(r->max_couple, std::max(np, nn));
             }
             sub_node_off.push_back((int32_t)gnode.size());
             sub_lev_off.push_back((int32_t)lev_start.size());
@@ -611,6 +743,7 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
                 SG_THROW(SG_ERR_UNSUPPORTED, "subdomain %d has %d nodes (limit %d)", sd, m, kMaxLocal);
             r->max_local = std::max(r->max_local, m);
             r->h_nlev[sd] = nl;
+            r->max_levels = std::max(r->max_levels, nl);
             for (int a : nodes) local_id[a] = -1;
         }
         r->total_local = (int64_t)gnode.size();
@@ -666,7 +799,7 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         {
             const int nch = (r->P + kColChunk - 1) / kColChunk;
             const int KC = (r->P + nch - 1) / nch;
-            size_t need = ras_apply_lds(SG_FP64, max_b, KC, r->max_local);
+            size_t need = ras_apply_lds(SG_FP64, max_b, KC, r->max_local, r->max_levels);
             if ((size_t)max_lds < need)
                 SG_THROW(SG_ERR_UNSUPPORTED, "RAS apply needs %zu bytes of LDS", need);
         }
