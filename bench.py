@@ -112,6 +112,8 @@ def main() -> int:
     ap.add_argument("--mv-launches", type=int, default=50)
     ap.add_argument("--cpu-sample-its", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -147,12 +149,12 @@ def main() -> int:
     ref_x = None
     for prec in precs:
         g = solvers[prec]
-        for _ in range(args.warmup):
-            x, info = g.solve(pr.restart, pr.rtol, omega=omega)
+        for _ in range(max(args.warmup, 1 if args.graph else 0)):
+            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            x, info = g.solve(pr.restart, pr.rtol, omega=omega)
+            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         results[prec] = dict(ms=ms, iterations=info["iterations"], relres=info["true_relres"],
@@ -199,7 +201,8 @@ def main() -> int:
         "config": {"workload": "linear SG Poisson 512x512 P1, M=4 KL vars, order 3 (P=35), "
                                "9,139,235 unknowns, RAS 16x16 overlap 2 + SA-AMG Nicolaides "
                                "coarse, FGMRES(50) to 1e-8, preconditioner " + args.mixed,
-                   "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub},
+                   "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub,
+                   "graph": bool(args.graph)},
         "solves": results,
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / mixed["ms"], 3),
         "matvec": {"us": round(mv_mean_ms * 1e3, 2), "median_us": round(mv_med_ms * 1e3, 2),

@@ -127,10 +127,11 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * Subdomain s grows by `overlap` layers of mesh-graph neighbours.  The local
  * solve is mean-based (K_0 and G_0 = diag(alpha!)), exact up to rounding:
  * each local matrix is factored on the device as a block-tridiagonal matrix
- * over breadth-first level sets, keeping the inverse of every Schur
- * complement in `prec` (FP64, FP32 or BF16; FP32 accumulation for the low
- * precisions).  Level sets wider than 64 nodes give SG_ERR_UNSUPPORTED; a
- * non-positive pivot gives SG_ERR_NUMERIC.
+ * (consecutive blocks of a breadth-first ordering), keeping the inverse of
+ * every Schur complement in `prec` (FP64, FP32 or BF16; the block products
+ * run on the matrix cores, FP32 accumulation for the low precisions).
+ * Blocks wider than 64 nodes give SG_ERR_UNSUPPORTED; a non-positive pivot
+ * gives SG_ERR_NUMERIC.
  * ras_apply: R, Z device [n*P] FP64, must not alias.  Asynchronous.
  * ---------------------------------------------------------------------- */
 int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap,
@@ -193,12 +194,20 @@ int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho
  * workspace of at least fgmres_workspace_bytes(op, amg, restart).
  * Returns SG_OK, SG_NOT_CONVERGED (max_it reached) or an error.
  * Synchronous; the host reads one residual estimate per iteration.
+ * With use_graph, step j (preconditioner cycle, matvec, the j+1 Gram-Schmidt
+ * kernels, normalisation and Givens update) is captured on a library stream
+ * the first time it runs and replayed on `stream` afterwards; the graph only
+ * references the handles' memory and ws, and is dropped when a handle it
+ * references is destroyed (sg_graph_cache_clear drops all).
  * ---------------------------------------------------------------------- */
 typedef struct {
     int restart;        /* m (>= 1)                                   */
     int max_it;         /* total Arnoldi steps allowed                */
     double rtol;        /* relative to ||b||                          */
     double omega;       /* smoother damping (<= 0: estimate it)       */
+    int use_graph;      /* 1: replay each Arnoldi step as a captured  */
+                        /*    HIP graph (captured once per handles,   */
+                        /*    workspace, m, omega and step index)     */
 } sg_krylov_opts;
 
 typedef struct {
@@ -214,6 +223,9 @@ typedef struct {
 } sg_krylov_stats;
 
 size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart);
+/* Drop every cached Arnoldi-step graph (e.g. before freeing a workspace that
+ * was used with use_graph).  Returns the number of graphs released. */
+int sg_graph_cache_clear(void);
 int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
                  const double* b, double* x, const sg_krylov_opts* opts,
                  sg_krylov_stats* stats, void* ws, size_t ws_bytes, void* stream);

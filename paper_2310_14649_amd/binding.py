@@ -34,7 +34,7 @@ class SgError(RuntimeError):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_it", C.c_int), ("rtol", C.c_double),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("use_graph", C.c_int)]
 
 
 class KrylovStats(C.Structure):
@@ -72,6 +72,7 @@ _SIGS = {
     "sg_precond_apply": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]),
     "sg_smoother_damping": (C.c_int, [_vp, _vp, C.c_int, _f64p, _f64p, _vp, C.c_size_t, _vp]),
     "fgmres_workspace_bytes": (C.c_size_t, [_vp, _vp, C.c_int]),
+    "sg_graph_cache_clear": (C.c_int, []),
     "fgmres_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(KrylovOpts),
                                C.POINTER(KrylovStats), _vp, C.c_size_t, _vp]),
 }
@@ -274,9 +275,13 @@ def fgmres_workspace_bytes(op, amg, restart: int) -> int:
     return int(lib().fgmres_workspace_bytes(op, amg, restart))
 
 
+def sg_graph_cache_clear() -> int:
+    return int(lib().sg_graph_cache_clear())
+
+
 def fgmres_solve(op, ras, amg, b, x, restart: int, max_it: int, rtol: float, omega: float,
-                 ws, history_cap: int = 4096, stream=None):
-    opts = KrylovOpts(restart, max_it, rtol, omega)
+                 ws, history_cap: int = 4096, use_graph: bool = False, stream=None):
+    opts = KrylovOpts(restart, max_it, rtol, omega, 1 if use_graph else 0)
     hist = np.zeros(history_cap, dtype=np.float64)
     st = KrylovStats()
     st.history = _ptr(hist, C.c_double)

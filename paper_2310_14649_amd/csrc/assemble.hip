@@ -291,6 +291,9 @@ int sg_op_export(const sg_op* op, int64_t* rowptr, int32_t* col, double* vals) {
     });
 }
 
-void sg_destroy_op(sg_op* op) { delete op; }
+void sg_destroy_op(sg_op* op) {
+    sg::graph_cache_purge(op);
+    delete op;
+}
 
 }  // extern "C"

@@ -737,6 +737,9 @@ int sg_coarse_prolong_add(const sg_amg* a, const double* e_c, double* Y, void* s
     });
 }
 
-void sg_destroy_amg(sg_amg* a) { delete a; }
+void sg_destroy_amg(sg_amg* a) {
+    sg::graph_cache_purge(a);
+    delete a;
+}
 
 }  // extern "C"

@@ -202,5 +202,7 @@ void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s
 void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s);
 void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
 int amg_nsub(const sg_amg* a);
+// krylov.hip: drop cached Arnoldi-step graphs that reference a handle
+void graph_cache_purge(const void* handle);
 int amg_device(const sg_amg* a);
 }  // namespace sg

@@ -14,6 +14,10 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace sg {
 namespace {
@@ -217,7 +221,8 @@ void precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double
                    const double* R, double* Z, char* ws, hipStream_t s) {
     const int64_t N = (int64_t)op->n * op->P;
     if (!ras) {
-        HIP_OK(hipMemcpyAsync(Z, R, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        scale_kernel<<<grid_for(N), 256, 0, s>>>(N, 1.0, R, Z);
+        HIP_LAUNCH_OK();
         return;
     }
     ras_apply_ex(ras, R, Z, omega, 0.0, s);                          // z1 = w M r
@@ -235,7 +240,52 @@ void precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double
     ras_apply_ex(ras, T, Z, omega, 1.0, s);                          // z = z2 + w M t
 }
 
+// ------------------------------------------------------------------ graphs
+struct GraphKey {
+    const void *op, *ras, *amg, *ws;
+    size_t ws_bytes;
+    int m, j;
+    uint64_t omega_bits;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(op, ras, amg, ws, ws_bytes, m, j, omega_bits) <
+               std::tie(o.op, o.ras, o.amg, o.ws, o.ws_bytes, o.m, o.j, o.omega_bits);
+    }
+};
+
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t>& graph_cache() {
+    static std::map<GraphKey, hipGraphExec_t> c;
+    return c;
+}
+std::map<int, hipStream_t>& capture_streams() {
+    static std::map<int, hipStream_t> c;
+    return c;
+}
+
+hipStream_t capture_stream(int dev) {
+    auto& cs = capture_streams();
+    auto it = cs.find(dev);
+    if (it != cs.end()) return it->second;
+    hipStream_t st;
+    HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    cs[dev] = st;
+    return st;
+}
+
 }  // namespace
+
+void graph_cache_purge(const void* handle) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto& c = graph_cache();
+    for (auto it = c.begin(); it != c.end();) {
+        if (it->first.op == handle || it->first.ras == handle || it->first.amg == handle) {
+            (void)hipGraphExecDestroy(it->second);
+            it = c.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
 
 }  // namespace sg
 
@@ -311,6 +361,17 @@ int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho
     });
 }
 
+int sg_graph_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    int n = 0;
+    for (auto& kv : graph_cache()) {
+        (void)hipGraphExecDestroy(kv.second);
+        ++n;
+    }
+    graph_cache().clear();
+    return n;
+}
+
 size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart) {
     if (!op || restart < 1) return 0;
     const size_t N = (size_t)op->n * op->P;
@@ -376,6 +437,30 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
             ++hist;
         };
         double relres = 0.0;
+        // One Arnoldi step: z_j = B v_j, w = A z_j, modified Gram-Schmidt
+        // against v_0..v_j, v_{j+1} = w/||w||, Givens update of column j.
+        auto arnoldi_step = [&](int j, hipStream_t st) {
+            double* vj = V + (size_t)j * (vb / 8);
+            double* zj = Zb + (size_t)j * (vb / 8);
+            precond_apply(op, ras, amg, omega, vj, zj, pws, st);
+            kron_matvec(A, op->L, op->tr, zj, w, 1.0, 0.0, nullptr, st);
+            dot_partial_kernel<<<nb, kVT, 0, st>>>(N, w, V, part[0]);
+            HIP_LAUNCH_OK();
+            double* hcol = H + (size_t)j * (m + 1);
+            for (int i = 0; i <= j; ++i) {
+                const double* vi = V + (size_t)i * (vb / 8);
+                const double* vn = (i < j) ? V + (size_t)(i + 1) * (vb / 8) : nullptr;
+                mgs_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vi, vn, part[i & 1], part[(i + 1) & 1],
+                                               hcol + i);
+                HIP_LAUNCH_OK();
+            }
+            double* vnext = V + (size_t)(j + 1) * (vb / 8);
+            normalize_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vnext, part[(j + 1) & 1], hcol + j + 1,
+                                                 scal + 1);
+            HIP_LAUNCH_OK();
+            givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
+            HIP_LAUNCH_OK();
+        };
         if (bnorm == 0.0) {
             Vec::fill(N, 0.0, x, s);
             converged = true;
@@ -395,26 +480,39 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
                 int jd = 0;
                 double hs[2] = {0.0, 0.0};
                 for (int j = 0; j < m; ++j) {
-                    double* vj = V + (size_t)j * (vb / 8);
-                    double* zj = Zb + (size_t)j * (vb / 8);
-                    precond_apply(op, ras, amg, omega, vj, zj, pws, s);
-                    kron_matvec(A, op->L, op->tr, zj, w, 1.0, 0.0, nullptr, s);
-                    dot_partial_kernel<<<nb, kVT, 0, s>>>(N, w, V, part[0]);
-                    HIP_LAUNCH_OK();
-                    double* hcol = H + (size_t)j * (m + 1);
-                    for (int i = 0; i <= j; ++i) {
-                        const double* vi = V + (size_t)i * (vb / 8);
-                        const double* vn = (i < j) ? V + (size_t)(i + 1) * (vb / 8) : nullptr;
-                        mgs_kernel<<<nb, kVT, 0, s>>>(N, nb, w, vi, vn, part[i & 1],
-                                                      part[(i + 1) & 1], hcol + i);
-                        HIP_LAUNCH_OK();
+                    if (opts->use_graph) {
+                        hipGraphExec_t exec = nullptr;
+                        GraphKey key{op, ras, amg, ws, ws_bytes, m, j, 0};
+                        std::memcpy(&key.omega_bits, &omega, sizeof(double));
+                        {
+                            std::lock_guard<std::mutex> lk(g_graph_mu);
+                            auto it = graph_cache().find(key);
+                            if (it != graph_cache().end()) exec = it->second;
+                        }
+                        if (!exec) {
+                            hipStream_t cst = capture_stream(op->device);
+                            HIP_OK(hipStreamSynchronize(s));
+                            HIP_OK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
+                            try {
+                                arnoldi_step(j, cst);
+                            } catch (...) {
+                                hipGraph_t bad = nullptr;
+                                (void)hipStreamEndCapture(cst, &bad);
+                                if (bad) (void)hipGraphDestroy(bad);
+                                throw;
+                            }
+                            hipGraph_t graph = nullptr;
+                            HIP_OK(hipStreamEndCapture(cst, &graph));
+                            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                            (void)hipGraphDestroy(graph);
+                            HIP_OK(ie);
+                            std::lock_guard<std::mutex> lk(g_graph_mu);
+                            graph_cache()[key] = exec;
+                        }
+                        HIP_OK(hipGraphLaunch(exec, s));
+                    } else {
+                        arnoldi_step(j, s);
                     }
-                    double* vnext = V + (size_t)(j + 1) * (vb / 8);
-                    normalize_kernel<<<nb, kVT, 0, s>>>(N, nb, w, vnext, part[(j + 1) & 1],
-                                                        hcol + j + 1, scal + 1);
-                    HIP_LAUNCH_OK();
-                    givens_kernel<<<1, 1, 0, s>>>(j, m + 1, H, cs, sn, g, scal);
-                    HIP_LAUNCH_OK();
                     HIP_OK(hipMemcpyAsync(hs, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
                     HIP_OK(hipStreamSynchronize(s));
                     ++its;

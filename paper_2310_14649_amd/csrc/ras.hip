@@ -840,7 +840,10 @@ int ras_apply(const sg_ras* r, const double* R, double* Z, void* stream) {
     });
 }
 
-void sg_destroy_ras(sg_ras* r) { delete r; }
+void sg_destroy_ras(sg_ras* r) {
+    sg::graph_cache_purge(r);
+    delete r;
+}
 
 }  // extern "C"
 

@@ -382,3 +382,30 @@ def test_full_size_ras_sampled_subdomains(full_c1):
                             R[nodes]) / S.alpha_fact[None, :]
         mask = pr.owner[nodes] == sd
         assert _rel(Zh[nodes[mask]], loc[mask]) < 1e-10, sd
+
+
+# ------------------------------------------------------------------ a10
+def test_graph_replay_matches_eager(built):
+    """Arnoldi steps replayed from captured graphs give the eager result bit
+    for bit, on every replay, with eager work and synchronisation between."""
+    pr, S, g = built("c4_ragged")
+    x_e, i_e = g.solve(50, 1e-10)
+    for rep in range(3):
+        x_g, i_g = g.solve(50, 1e-10, use_graph=True)
+        assert i_g["iterations"] == i_e["iterations"]
+        assert torch.equal(x_g, x_e), rep
+        # eager work between replays
+        Y = g.new_vec()
+        B.sg_matvec(g.op, x_g, Y)
+        torch.cuda.synchronize()
+    assert B.sg_graph_cache_clear() > 0
+
+
+def test_graph_cache_dropped_with_handles():
+    _cuda()
+    pr = make_problem("c0", nc=12, sub=(2, 2))
+    g = GpuSG(pr, coarse="mean")
+    x, info = g.solve(20, 1e-10, use_graph=True)
+    assert info["converged"]
+    g.close()                       # must release the graphs that reference g's handles
+    assert B.sg_graph_cache_clear() == 0
