@@ -230,6 +230,93 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
                  const double* b, double* x, const sg_krylov_opts* opts,
                  sg_krylov_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Nonlinear problem and Newton's method.
+ *
+ * The paper's nonlinear model -div(c(x,xi) q(u) grad u) = f (Eq.
+ * NLP_StrongPDE, Galerkin system Eqs. stonlp_system / vectorvalPDENL, which
+ * the paper linearises by Picard iterations) with q(u) = kappa(u) =
+ * 1 + a2 u^2, f = 1 and homogeneous Dirichlet data, solved by inexact Newton
+ * with backtracking.  The residual is R(U) = F e_0 - A(U) with
+ *   A(U)[a, m] = sum_T |T| E[c_T kappa(u_T) (grad u_T . grad phi_a) Psi_m],
+ * c_T the input PCE (first L_in terms) at the centroid of T and u_T the
+ * centroid value of u.  All expectations are exact (up to rounding): the
+ * library forms the chaos coefficients of degree <= 2p of c_T kappa(u_T)
+ * and c_T kappa'(u_T) (grad u_T . grad phi_a) by chaos products, so the
+ * Jacobian dA/dU is the Kronecker sum sum_gamma K_gamma (x) T_gamma with
+ * L2 = (M+2p)!/(M! (2p)!) terms on the unpruned P1 pattern.
+ *
+ * sg_nl_setup -- element geometry, input PCE, product tables and both
+ *   operators (the Picard part K1 and the Jacobian K1 + K2) for the basis b
+ *   (its M, p_in, p) on the mesh (same arguments as sg_assemble).
+ *   a2 >= 0.  Synchronous.  Errors: SG_ERR_INVALID_ARG.
+ * sg_nl_eval -- assemble K1 and the Jacobian at U (device, [n x P]) and, if
+ *   R is not NULL, write R(U) (device, [n x P]).  Asynchronous.
+ * sg_nl_jac_apply -- Y = J X with the Jacobian of the last sg_nl_eval.
+ * sg_nl_export -- host copies of the pattern (rowptr [n+1], col [nnz]) and
+ *   of the values of K1 and of the Jacobian ([nnz x L2], entry-major,
+ *   gamma-th value = coefficient of T_gamma); any pointer may be NULL.
+ * sg_nl_mean_op / sg_nl_jac_op -- the K1 and Jacobian operators as sg_op
+ *   handles owned by the sg_nl (for ras_setup: K1's gamma = 0 term is the
+ *   mean-coefficient stiffness used by the RAS local solves; for
+ *   amg_setup / sg_precond_apply / fgmres_solve: the Jacobian).
+ * ---------------------------------------------------------------------- */
+typedef struct sg_nl sg_nl;
+
+int sg_nl_setup(const sg_basis* b, int n_vert, const double* xy, int n_tri,
+                const int32_t* tri, const int32_t* dof, int n, const double* g0,
+                const double* g, double a2, sg_nl** out, void* stream);
+int sg_nl_info(const sg_nl* nl, int* n, int* P, int* L2, int64_t* nnz);
+int sg_nl_eval(sg_nl* nl, const double* U, double* R, void* stream);
+int sg_nl_jac_apply(const sg_nl* nl, const double* X, double* Y, void* stream);
+int sg_nl_export(const sg_nl* nl, int64_t* rowptr, int32_t* col, double* k1, double* jac);
+const sg_op* sg_nl_mean_op(const sg_nl* nl);
+const sg_op* sg_nl_jac_op(const sg_nl* nl);
+void sg_destroy_nl(sg_nl* nl);
+
+/* ------------------------------------------------------------------------
+ * newton_solve -- inexact Newton on R(U) = 0 from the initial guess in U
+ * (device, [n x P], overwritten by the last iterate).  Step k:
+ *   eta_k = max(1e-12, min(eta_max, ||R_k|| / ||F||));
+ *   RAS on K1 (mean-coefficient local solves, subdomains `owner`, overlap)
+ *   and the coarse solver `coarse` on the Jacobian, both rebuilt;
+ *   FGMRES(restart) solves J d = R_k to relative tolerance eta_k from d = 0;
+ *   lambda = 1, halved (at most 9 times) until
+ *   ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R_k||, the last trial taken
+ *   otherwise;  U += lambda d.
+ * Stops when ||R|| / ||F|| <= tol (||F|| = norm of F e_0).  ws: device
+ * workspace of newton_workspace_bytes(nl, n_sub, coarse, restart) bytes.
+ * Returns SG_OK, SG_NOT_CONVERGED (max_steps reached) or an error.
+ * Synchronous.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int max_steps;
+    double tol;          /* on ||R|| / ||F||                             */
+    double eta_max;      /* cap of the inner relative tolerance (0,1)    */
+    int restart;         /* FGMRES restart length                       */
+    int max_it;          /* Arnoldi steps per linear solve              */
+    double omega;        /* smoother damping (<= 0: estimate per step)  */
+    int use_graph;       /* as in sg_krylov_opts                        */
+} sg_newton_opts;
+
+typedef struct {
+    int steps;
+    int krylov_its;          /* total Arnoldi steps                       */
+    int converged;
+    double relres;           /* ||R|| / ||F|| at return                   */
+    double last_lambda;
+    double ms_total, ms_eval, ms_setup, ms_krylov;
+    double* history;         /* host, may be NULL: ||R_k|| / ||F||, k = 0..steps */
+    int* krylov_its_per_step;/* host, may be NULL: entry k-1 for step k   */
+    int history_cap;
+    int history_len;
+} sg_newton_stats;
+
+size_t newton_workspace_bytes(const sg_nl* nl, int n_sub, sg_coarse_kind coarse, int restart);
+int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_prec prec,
+                 sg_coarse_kind coarse, double* U, const sg_newton_opts* opts,
+                 sg_newton_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,9 +24,9 @@ p = 3, so a tensor Gauss-Hermite rule with 8 points per variable evaluates
 the expectations exactly (up to rounding).
 
 Newton: eta_k = max(1e-12, min(1e-2, ||R_k||/||F||)) (||F|| replaced by the
-initial residual when F = 0); backtracking halves
-lambda (at most 10 times) until ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R(U)||;
-stop when ||R||/||F|| <= tol.
+initial residual when F = 0); backtracking tries lambda = 1, 1/2, ...,
+1/512 until ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R(U)|| and takes the
+last trial if none passes; stop when ||R||/||F|| <= tol.
 """
 from __future__ import annotations
 
@@ -121,7 +121,7 @@ class NLProblem:
                 np.add.at(R, d[m, a], -contrib[m, a])
         return R
 
-    def jacobian(self, U: np.ndarray, chunk: int = 64) -> sp.csr_matrix:
+    def jacobian(self, U: np.ndarray, chunk: int = 16) -> sp.csr_matrix:
         """dA/dU in the row-major (a*P + m) numbering."""
         P = self.P
         rows, cols, vals = [], [], []
@@ -134,10 +134,11 @@ class NLProblem:
             g = self.grad[el]
             gu = np.einsum("ebd,ebq->eqd", g, ub)
             w1 = self.wq[None, :] * c * self.kappa(uT)                            # [E,Q]
-            E1 = np.einsum("eq,qm,qn->emn", w1, self.psi, self.psi)               # [E,P,P]
+            # E1[e,m,n] = sum_q w1[e,q] psi[q,m] psi[q,n]  (as a batched matmul)
+            E1 = self.psi.T[None] @ (w1[:, :, None] * self.psi[None])           # [E,P,P]
             w2 = self.wq[None, None, :] * (c * self.dkappa(uT))[:, None, :] * \
                 np.einsum("eqd,ead->eaq", gu, g)                                 # [E,3,Q]
-            E2 = np.einsum("eaq,qm,qn->eamn", w2, self.psi, self.psi)            # [E,3,P,P]
+            E2 = self.psi.T[None, None] @ (w2[..., None] * self.psi[None, None])  # [E,3,P,P]
             gg = np.einsum("ead,ebd->eab", g, g)                                   # [E,3,3]
             d = self.dof[self.tri[el]]
             for a in range(3):
@@ -204,9 +205,9 @@ def newton(pr: NLProblem, U0: Optional[np.ndarray] = None, tol: float = 1e-8,
         else:
             d, its = linear_solve(J, R, eta, U)
         lam = 1.0
-        for _ in range(10):
+        for trial in range(10):
             Rt = pr.residual(U + lam * d)
-            if np.linalg.norm(Rt) <= (1.0 - 1e-4 * lam) * rn:
+            if np.linalg.norm(Rt) <= (1.0 - 1e-4 * lam) * rn or trial == 9:
                 break
             lam *= 0.5
         U = U + lam * d

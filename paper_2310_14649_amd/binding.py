@@ -43,6 +43,20 @@ class KrylovStats(C.Structure):
                 ("history", _f64p), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
+class NewtonOpts(C.Structure):
+    _fields_ = [("max_steps", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
+                ("restart", C.c_int), ("max_it", C.c_int), ("omega", C.c_double),
+                ("use_graph", C.c_int)]
+
+
+class NewtonStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("krylov_its", C.c_int), ("converged", C.c_int),
+                ("relres", C.c_double), ("last_lambda", C.c_double), ("ms_total", C.c_double),
+                ("ms_eval", C.c_double), ("ms_setup", C.c_double), ("ms_krylov", C.c_double),
+                ("history", _f64p), ("krylov_its_per_step", _i32p), ("history_cap", C.c_int),
+                ("history_len", C.c_int)]
+
+
 _SIGS = {
     "sg_last_error": (C.c_char_p, []),
     "sg_version": (C.c_int, []),
@@ -75,6 +89,20 @@ _SIGS = {
     "sg_graph_cache_clear": (C.c_int, []),
     "fgmres_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(KrylovOpts),
                                C.POINTER(KrylovStats), _vp, C.c_size_t, _vp]),
+    "sg_nl_setup": (C.c_int, [_vp, C.c_int, _f64p, C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p,
+                              C.c_double, C.POINTER(_vp), _vp]),
+    "sg_nl_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int64)]),
+    "sg_nl_eval": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_nl_jac_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_nl_export": (C.c_int, [_vp, _i64p, _i32p, _f64p, _f64p]),
+    "sg_nl_mean_op": (_vp, [_vp]),
+    "sg_nl_jac_op": (_vp, [_vp]),
+    "sg_destroy_nl": (None, [_vp]),
+    "newton_workspace_bytes": (C.c_size_t, [_vp, C.c_int, C.c_int, C.c_int]),
+    "newton_solve": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
+                               C.POINTER(NewtonOpts), C.POINTER(NewtonStats), _vp, C.c_size_t,
+                               _vp]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -291,3 +319,83 @@ def fgmres_solve(op, ras, amg, b, x, restart: int, max_it: int, rtol: float, ome
     return dict(status=rc, iterations=st.iterations, restarts=st.restarts,
                 converged=bool(st.converged), true_relres=st.true_relres, omega=st.omega,
                 ms_solve=st.ms_solve, history=hist[:st.history_len].copy())
+
+
+# ---------------------------------------------------------------- Newton
+def sg_nl_setup(basis, xy: np.ndarray, tri: np.ndarray, dof: np.ndarray, n: int,
+                g0: np.ndarray, g: np.ndarray, a2: float = 0.5, stream=None) -> C.c_void_p:
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    dof = np.ascontiguousarray(dof, dtype=np.int32)
+    g0 = np.ascontiguousarray(g0, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    h = C.c_void_p()
+    gp = _ptr(g, C.c_double) if g.size else None
+    _check(lib().sg_nl_setup(basis, xy.shape[0], _ptr(xy, C.c_double), tri.shape[0],
+                             _ptr(tri, C.c_int32), _ptr(dof, C.c_int32), n,
+                             _ptr(g0, C.c_double), gp, a2, C.byref(h), _stream(stream)))
+    return h
+
+
+def sg_nl_info(nl):
+    n, P, L2, nnz = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
+    _check(lib().sg_nl_info(nl, C.byref(n), C.byref(P), C.byref(L2), C.byref(nnz)))
+    return n.value, P.value, L2.value, nnz.value
+
+
+def sg_nl_eval(nl, U, R=None, stream=None):
+    _check(lib().sg_nl_eval(nl, _dev(U), _dev(R), _stream(stream)))
+
+
+def sg_nl_jac_apply(nl, X, Y, stream=None):
+    _check(lib().sg_nl_jac_apply(nl, _dev(X), _dev(Y), _stream(stream)))
+
+
+def sg_nl_export(nl):
+    n, P, L2, nnz = sg_nl_info(nl)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(nnz, dtype=np.int32)
+    k1 = np.zeros(nnz * L2, dtype=np.float64)
+    jac = np.zeros(nnz * L2, dtype=np.float64)
+    _check(lib().sg_nl_export(nl, _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
+                              _ptr(k1, C.c_double), _ptr(jac, C.c_double)))
+    return rowptr, col, k1.reshape(nnz, L2), jac.reshape(nnz, L2)
+
+
+def sg_nl_mean_op(nl) -> C.c_void_p:
+    return C.c_void_p(lib().sg_nl_mean_op(nl))
+
+
+def sg_nl_jac_op(nl) -> C.c_void_p:
+    return C.c_void_p(lib().sg_nl_jac_op(nl))
+
+
+def sg_destroy_nl(nl):
+    lib().sg_destroy_nl(nl)
+
+
+def newton_workspace_bytes(nl, n_sub: int, coarse: int, restart: int) -> int:
+    return int(lib().newton_workspace_bytes(nl, n_sub, coarse, restart))
+
+
+def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coarse: int, U,
+                 ws, max_steps: int = 30, tol: float = 1e-8, eta_max: float = 1e-2,
+                 restart: int = 50, max_it: int = 1000, omega: float = 0.0,
+                 use_graph: bool = False, history_cap: int = 64, stream=None):
+    owner = np.ascontiguousarray(owner, dtype=np.int32)
+    opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0)
+    hist = np.zeros(history_cap, dtype=np.float64)
+    kits = np.zeros(history_cap, dtype=np.int32)
+    st = NewtonStats()
+    st.history = _ptr(hist, C.c_double)
+    st.krylov_its_per_step = _ptr(kits, C.c_int32)
+    st.history_cap = history_cap
+    rc = _check(lib().newton_solve(nl, _ptr(owner, C.c_int32), n_sub, overlap, prec, coarse,
+                                   _dev(U), C.byref(opts), C.byref(st), _dev(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)))
+    h = st.history_len
+    return dict(status=rc, steps=st.steps, krylov_its=st.krylov_its,
+                converged=bool(st.converged), relres=st.relres, last_lambda=st.last_lambda,
+                ms_total=st.ms_total, ms_eval=st.ms_eval, ms_setup=st.ms_setup,
+                ms_krylov=st.ms_krylov, history=hist[:h].copy(),
+                krylov_its_per_step=kits[:max(h - 1, 0)].copy())

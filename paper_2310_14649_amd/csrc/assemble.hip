@@ -113,6 +113,129 @@ __global__ void rhs_kernel(int n, int P, const double* __restrict__ F, double* _
 }  // namespace
 }  // namespace sg
 
+namespace sg {
+
+void validate_mesh(int n_vert, const double* xy, int n_tri, const int32_t* tri,
+                   const int32_t* dof, int n) {
+    SG_REQUIRE(xy && tri && dof, "null mesh argument");
+    SG_REQUIRE(n_vert > 0 && n_tri > 0 && n > 0, "empty mesh");
+    for (int v = 0; v < n_vert; ++v)
+        SG_REQUIRE(dof[v] >= -1 && dof[v] < n, "dof[%d]=%d outside [-1,%d)", v, dof[v], n);
+    std::vector<char> seen(n, 0);
+    for (int v = 0; v < n_vert; ++v)
+        if (dof[v] >= 0) {
+            SG_REQUIRE(!seen[dof[v]], "dof %d used twice", dof[v]);
+            seen[dof[v]] = 1;
+        }
+    for (int a = 0; a < n; ++a) SG_REQUIRE(seen[a], "unknown %d has no vertex", a);
+    for (int64_t t = 0; t < (int64_t)n_tri * 3; ++t)
+        SG_REQUIRE(tri[t] >= 0 && tri[t] < n_vert, "tri entry %lld out of range", (long long)t);
+}
+
+void mesh_pattern(int n_vert, const double* xy, int n_tri, const int32_t* tri, const int32_t* dof,
+                  int n, bool prune, MeshPattern& out) {
+    (void)n_vert;
+    struct Contrib { int64_t key; int32_t ref; bool keep; };
+    std::vector<Contrib> cs;
+    cs.reserve((size_t)n_tri * 9);
+    std::vector<int64_t> gkeys;
+    gkeys.reserve((size_t)n_tri * 6);
+    for (int t = 0; t < n_tri; ++t) {
+        int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        for (int la = 0; la < 3; ++la) {
+            int da = dof[v[la]];
+            if (da < 0) continue;
+            for (int lb = 0; lb < 3; ++lb) {
+                int db = dof[v[lb]];
+                if (db < 0) continue;
+                bool keep = true;
+                if (la != lb) {
+                    if (prune) {
+                        int lc = 3 - la - lb;
+                        double ax = xy[2 * v[la]] - xy[2 * v[lc]], ay = xy[2 * v[la] + 1] - xy[2 * v[lc] + 1];
+                        double bx = xy[2 * v[lb]] - xy[2 * v[lc]], by = xy[2 * v[lb] + 1] - xy[2 * v[lc] + 1];
+                        keep = (ax * bx + ay * by) != 0.0;
+                    }
+                    gkeys.push_back((int64_t)da * n + db);
+                }
+                cs.push_back({(int64_t)da * n + db, t * 9 + la * 3 + lb, keep});
+            }
+        }
+    }
+    std::stable_sort(cs.begin(), cs.end(),
+                     [](const Contrib& x, const Contrib& y) { return x.key < y.key; });
+    out.rowptr.assign(n + 1, 0);
+    out.col.clear();
+    out.cptr.assign(1, 0);
+    out.cref.clear();
+    out.max_row = 0;
+    size_t i0 = 0;
+    while (i0 < cs.size()) {
+        size_t i1 = i0;
+        bool keep = false;
+        while (i1 < cs.size() && cs[i1].key == cs[i0].key) keep |= cs[i1++].keep;
+        int r = (int)(cs[i0].key / n), c = (int)(cs[i0].key % n);
+        if (keep || r == c) {
+            out.col.push_back(c);
+            out.rowptr[r + 1]++;
+            for (size_t q = i0; q < i1; ++q) out.cref.push_back(cs[q].ref);
+            out.cptr.push_back((int64_t)out.cref.size());
+        }
+        i0 = i1;
+    }
+    for (int a = 0; a < n; ++a) {
+        out.max_row = std::max(out.max_row, out.rowptr[a + 1]);
+        out.rowptr[a + 1] += out.rowptr[a];
+    }
+    SG_REQUIRE((int64_t)out.col.size() < (int64_t)INT32_MAX, "too many non-zeros");
+    // mesh graph (all triangle edges between unknowns, pruned or not)
+    std::sort(gkeys.begin(), gkeys.end());
+    gkeys.erase(std::unique(gkeys.begin(), gkeys.end()), gkeys.end());
+    out.graph_ptr.assign(n + 1, 0);
+    out.graph_col.resize(gkeys.size());
+    for (size_t q = 0; q < gkeys.size(); ++q) {
+        out.graph_ptr[gkeys[q] / n + 1]++;
+        out.graph_col[q] = (int32_t)(gkeys[q] % n);
+    }
+    for (int a = 0; a < n; ++a) out.graph_ptr[a + 1] += out.graph_ptr[a];
+}
+
+void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, const int32_t* tri,
+                  const double* g0, const double* g, ElementData& out, hipStream_t s) {
+    SG_REQUIRE(b.L <= kMaxL, "L_in=%d exceeds %d", b.L, kMaxL);
+    SG_REQUIRE(g0 != nullptr, "g0 is NULL");
+    SG_REQUIRE(b.M == 0 || g != nullptr, "g is NULL with M > 0");
+    DevBuf<double> d_xy, d_g0, d_g;
+    DevBuf<int32_t> d_tri, d_alpha;
+    DevBuf<int> d_bad(1);
+    out.ek.alloc((size_t)n_tri * 9);
+    out.ec.alloc((size_t)n_tri * b.L);
+    out.earea.alloc(n_tri);
+    d_xy.upload(xy, (size_t)n_vert * 2, s);
+    d_tri.upload(tri, (size_t)n_tri * 3, s);
+    d_g0.upload(g0, n_tri, s);
+    if (b.M > 0) d_g.upload(g, (size_t)b.M * n_tri, s);
+    std::vector<int32_t> alpha_in(b.alpha.begin(), b.alpha.begin() + (size_t)b.L * b.M);
+    if (b.M > 0) d_alpha.upload(alpha_in, s);
+    HIP_OK(hipMemsetAsync(d_bad.p, 0, sizeof(int), s));
+    element_kernel<<<(n_tri + 255) / 256, 256, 0, s>>>(n_tri, b.M, b.L, d_xy.p, d_tri.p, d_g0.p,
+                                                        d_g.p, d_alpha.p, out.ek.p, out.ec.p,
+                                                        out.earea.p, d_bad.p);
+    HIP_LAUNCH_OK();
+    int bad = 0;
+    d_bad.download(&bad, 1, s);
+    HIP_OK(hipStreamSynchronize(s));
+    SG_REQUIRE(!bad, "degenerate or clockwise triangle");
+}
+
+void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,
+                 const int32_t* cref, const double* earea, double* F, hipStream_t s) {
+    load_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, rowptr, col, cptr, cref, earea, F);
+    HIP_LAUNCH_OK();
+}
+
+}  // namespace sg
+
 using namespace sg;
 
 extern "C" {
@@ -123,131 +246,44 @@ int sg_assemble(const sg_basis* b, int n_vert, const double* xy, int n_tri, cons
     return guarded([&]() -> int {
         SG_REQUIRE(b && xy && tri && dof && g0 && out, "null argument");
         SG_REQUIRE(b->M == 0 || g != nullptr, "g is NULL with M > 0");
-        SG_REQUIRE(n_vert > 0 && n_tri > 0 && n > 0, "empty mesh");
         SG_REQUIRE(b->L <= kMaxL, "L_in=%d exceeds %d", b->L, kMaxL);
         hipStream_t s = as_stream(stream);
-        for (int v = 0; v < n_vert; ++v)
-            SG_REQUIRE(dof[v] >= -1 && dof[v] < n, "dof[%d]=%d outside [-1,%d)", v, dof[v], n);
-        std::vector<char> seen(n, 0);
-        for (int v = 0; v < n_vert; ++v)
-            if (dof[v] >= 0) {
-                SG_REQUIRE(!seen[dof[v]], "dof %d used twice", dof[v]);
-                seen[dof[v]] = 1;
-            }
-        for (int a = 0; a < n; ++a) SG_REQUIRE(seen[a], "unknown %d has no vertex", a);
-        for (int64_t t = 0; t < (int64_t)n_tri * 3; ++t)
-            SG_REQUIRE(tri[t] >= 0 && tri[t] < n_vert, "tri entry %lld out of range", (long long)t);
+        validate_mesh(n_vert, xy, n_tri, tri, dof, n);
+        MeshPattern mp;
+        mesh_pattern(n_vert, xy, n_tri, tri, dof, n, true, mp);
+        const int64_t nnz = (int64_t)mp.col.size();
 
-        // ---- pattern and contribution lists (host, integer) ----
-        struct Contrib { int64_t key; int32_t ref; bool keep; };
-        std::vector<Contrib> cs;
-        cs.reserve((size_t)n_tri * 9);
-        std::vector<int64_t> gkeys;
-        gkeys.reserve((size_t)n_tri * 6);
-        for (int t = 0; t < n_tri; ++t) {
-            int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
-            for (int la = 0; la < 3; ++la) {
-                int da = dof[v[la]];
-                if (da < 0) continue;
-                for (int lb = 0; lb < 3; ++lb) {
-                    int db = dof[v[lb]];
-                    if (db < 0) continue;
-                    bool keep = true;
-                    if (la != lb) {
-                        int lc = 3 - la - lb;
-                        double ax = xy[2 * v[la]] - xy[2 * v[lc]], ay = xy[2 * v[la] + 1] - xy[2 * v[lc] + 1];
-                        double bx = xy[2 * v[lb]] - xy[2 * v[lc]], by = xy[2 * v[lb] + 1] - xy[2 * v[lc] + 1];
-                        keep = (ax * bx + ay * by) != 0.0;
-                        gkeys.push_back((int64_t)da * n + db);
-                    }
-                    cs.push_back({(int64_t)da * n + db, t * 9 + la * 3 + lb, keep});
-                }
-            }
-        }
-        std::stable_sort(cs.begin(), cs.end(),
-                         [](const Contrib& x, const Contrib& y) { return x.key < y.key; });
-        std::vector<int32_t> rowptr(n + 1, 0), col;
-        std::vector<int64_t> cptr(1, 0);
-        std::vector<int32_t> cref;
-        int max_row = 0;
-        size_t i0 = 0;
-        while (i0 < cs.size()) {
-            size_t i1 = i0;
-            bool keep = false;
-            while (i1 < cs.size() && cs[i1].key == cs[i0].key) keep |= cs[i1++].keep;
-            int r = (int)(cs[i0].key / n), c = (int)(cs[i0].key % n);
-            if (keep || r == c) {
-                col.push_back(c);
-                rowptr[r + 1]++;
-                for (size_t q = i0; q < i1; ++q) cref.push_back(cs[q].ref);
-                cptr.push_back((int64_t)cref.size());
-            }
-            i0 = i1;
-        }
-        for (int a = 0; a < n; ++a) {
-            max_row = std::max(max_row, rowptr[a + 1]);
-            rowptr[a + 1] += rowptr[a];
-        }
-        int64_t nnz = (int64_t)col.size();
-        SG_REQUIRE(nnz < (int64_t)INT32_MAX, "too many non-zeros");
-
-        // mesh graph (all triangle edges between unknowns, pruned or not)
-        std::sort(gkeys.begin(), gkeys.end());
-        gkeys.erase(std::unique(gkeys.begin(), gkeys.end()), gkeys.end());
         auto op = std::make_unique<sg_op>();
         op->device = current_device();
-        op->h_graph_ptr.assign(n + 1, 0);
-        op->h_graph_col.resize(gkeys.size());
-        for (size_t q = 0; q < gkeys.size(); ++q) {
-            op->h_graph_ptr[gkeys[q] / n + 1]++;
-            op->h_graph_col[q] = (int32_t)(gkeys[q] % n);
-        }
-        for (int a = 0; a < n; ++a) op->h_graph_ptr[a + 1] += op->h_graph_ptr[a];
-
+        op->h_graph_ptr = std::move(mp.graph_ptr);
+        op->h_graph_col = std::move(mp.graph_col);
         op->n = n; op->P = b->P; op->L = b->L; op->M = b->M;
-        op->nnz = nnz; op->max_row = max_row;
+        op->nnz = nnz; op->max_row = mp.max_row;
         op->basis = *b;
         op->h_afact = b->afact;
-        op->h_rowptr = rowptr;
-        op->h_col = col;
+        op->h_rowptr = mp.rowptr;
+        op->h_col = mp.col;
 
         // ---- device evaluation ----
-        DevBuf<double> d_xy, d_g0, d_g, ek((size_t)n_tri * 9), ec((size_t)n_tri * b->L),
-            earea(n_tri);
-        DevBuf<int32_t> d_tri, d_alpha, d_cref;
+        ElementData ed;
+        element_data(*b, n_vert, xy, n_tri, tri, g0, g, ed, s);
+        DevBuf<int32_t> d_cref;
         DevBuf<int64_t> d_cptr;
-        DevBuf<int> d_bad(1);
-        d_xy.upload(xy, (size_t)n_vert * 2, s);
-        d_tri.upload(tri, (size_t)n_tri * 3, s);
-        d_g0.upload(g0, n_tri, s);
-        if (b->M > 0) d_g.upload(g, (size_t)b->M * n_tri, s);
-        std::vector<int32_t> alpha_in(b->alpha.begin(), b->alpha.begin() + (size_t)b->L * b->M);
-        if (b->M > 0) d_alpha.upload(alpha_in, s);
-        d_cptr.upload(cptr, s);
-        d_cref.upload(cref, s);
-        op->rowptr.upload(rowptr, s);
-        op->col.upload(col, s);
+        d_cptr.upload(mp.cptr, s);
+        d_cref.upload(mp.cref, s);
+        op->rowptr.upload(mp.rowptr, s);
+        op->col.upload(mp.col, s);
         op->vals.alloc((size_t)nnz * b->L);
         op->F.alloc(n);
         op->afact.upload(b->afact, s);
-        HIP_OK(hipMemsetAsync(d_bad.p, 0, sizeof(int), s));
-        element_kernel<<<(n_tri + 255) / 256, 256, 0, s>>>(n_tri, b->M, b->L, d_xy.p, d_tri.p,
-                                                            d_g0.p, d_g.p, d_alpha.p, ek.p, ec.p,
-                                                            earea.p, d_bad.p);
-        HIP_LAUNCH_OK();
         int64_t work = nnz * b->L;
         entry_kernel<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(nnz, b->L, d_cptr.p, d_cref.p,
-                                                                   ek.p, ec.p, op->vals.p);
+                                                                   ed.ek.p, ed.ec.p, op->vals.p);
         HIP_LAUNCH_OK();
-        load_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, op->rowptr.p, op->col.p, d_cptr.p,
-                                                    d_cref.p, earea.p, op->F.p);
-        HIP_LAUNCH_OK();
+        load_vector(n, op->rowptr.p, op->col.p, d_cptr.p, d_cref.p, ed.earea.p, op->F.p, s);
         upload_triples(*b, op->tr, s);
         build_ell(op.get(), s);
-        int bad = 0;
-        d_bad.download(&bad, 1, s);
         HIP_OK(hipStreamSynchronize(s));
-        SG_REQUIRE(!bad, "degenerate or clockwise triangle");
         *out = op.release();
         return SG_OK;
     });

@@ -465,6 +465,168 @@ void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_
 
 }  // namespace sg
 
+namespace sg {
+
+// Owned-node lists (for the restriction), owner map (for the prolongation)
+// and the restriction slices of the Nicolaides space of `owner`.
+void amg_common_setup(sg_amg* a, const std::vector<int32_t>& owner, hipStream_t s) {
+    const int n = a->n, ns = a->n_sub, P = a->P;
+    // owned-node lists and owner map
+    std::vector<int32_t> own_ptr(ns + 1, 0), own_nodes(n);
+    for (int q = 0; q < n; ++q) own_ptr[owner[q] + 1]++;
+    for (int q = 0; q < ns; ++q) own_ptr[q + 1] += own_ptr[q];
+    {
+        std::vector<int32_t> fill(own_ptr.begin(), own_ptr.end() - 1);
+        for (int q = 0; q < n; ++q) own_nodes[fill[owner[q]]++] = q;
+    }
+    a->own_ptr.upload(own_ptr, s);
+    a->own_nodes.upload(own_nodes, s);
+    {
+        std::vector<int32_t> ssub, sbeg, send, sptr(1, 0);
+        for (int q = 0; q < ns; ++q) {
+            for (int b0 = own_ptr[q]; b0 < own_ptr[q + 1]; b0 += kSlice) {
+                ssub.push_back(q);
+                sbeg.push_back(b0);
+                send.push_back(std::min(b0 + kSlice, own_ptr[q + 1]));
+            }
+            sptr.push_back((int32_t)ssub.size());
+        }
+        a->nslices = (int)ssub.size();
+        a->slice_sub.upload(ssub, s);
+        a->slice_beg.upload(sbeg, s);
+        a->slice_end.upload(send, s);
+        a->sub_slice_ptr.upload(sptr, s);
+        a->slice_part.alloc((size_t)a->nslices * P);
+    }
+    a->owner.upload(owner, s);
+}
+
+// The smoothed-aggregation hierarchy of a level-0 block matrix A (host, FP64).
+void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
+    const int P = a->P, ns = a->n_sub;
+    const sg_prec prec = a->prec;
+    std::vector<Bsr> As{A}, Ps;
+    std::vector<std::vector<double>> Dinvs;
+    while ((int)As.size() < amgc::kMaxLevels && As.back().nr > amgc::kMinNodes) {
+        const Bsr& Al = As.back();
+        std::vector<int> agg = aggregate(Al);
+        int na = *std::max_element(agg.begin(), agg.end()) + 1;
+        if (na >= Al.nr) break;
+        if (As.size() == 1) a->h_agg0.assign(agg.begin(), agg.end());
+        // block-diagonal inverse
+        std::vector<double> Dinv((size_t)Al.nr * P * P);
+        for (int r = 0; r < Al.nr; ++r) {
+            bool found = false;
+            for (int q = Al.ptr[r]; q < Al.ptr[r + 1]; ++q)
+                if (Al.col[q] == r) {
+                    std::vector<double> D(Al.blk(q), Al.blk(q) + (size_t)P * P);
+                    invert_dense(D, P);
+                    std::copy(D.begin(), D.end(), Dinv.begin() + (size_t)r * P * P);
+                    found = true;
+                }
+            if (!found) SG_THROW(SG_ERR_NUMERIC, "missing diagonal block");
+        }
+        // spectral radius of D^{-1} A by power iteration from ones
+        std::vector<double> v((size_t)Al.nr * P, 1.0), w, dw((size_t)Al.nr * P);
+        double nv = std::sqrt((double)v.size());
+        for (auto& e : v) e /= nv;
+        double rho = 0.0;
+        for (int it = 0; it < amgc::kPowerIts; ++it) {
+            bsr_apply(Al, v, w);
+            for (int r = 0; r < Al.nr; ++r)
+                for (int i = 0; i < P; ++i) {
+                    double acc = 0.0;
+                    for (int j = 0; j < P; ++j)
+                        acc += Dinv[(size_t)r * P * P + (size_t)i * P + j] * w[(size_t)r * P + j];
+                    dw[(size_t)r * P + i] = acc;
+                }
+            double nw = 0.0;
+            for (double e : dw) nw += e * e;
+            rho = std::sqrt(nw);
+            for (size_t q = 0; q < v.size(); ++q) v[q] = dw[q] / rho;
+        }
+        const double omega = (4.0 / 3.0) / rho;
+        a->h_omegas.push_back(omega);
+        // tentative prolongator and its smoothing P = T - omega D^{-1} A T
+        std::vector<int> sizes(na, 0);
+        for (int r = 0; r < Al.nr; ++r) sizes[agg[r]]++;
+        Bsr Tm;
+        Tm.nr = Al.nr; Tm.nc = na; Tm.P = P;
+        Tm.ptr.resize(Al.nr + 1);
+        Tm.val.assign((size_t)Al.nr * P * P, 0.0);
+        for (int r = 0; r < Al.nr; ++r) {
+            Tm.ptr[r] = r;
+            Tm.col.push_back(agg[r]);
+            double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
+            for (int i = 0; i < P; ++i) Tm.blk(r)[(size_t)i * P + i] = sc;
+        }
+        Tm.ptr[Al.nr] = Al.nr;
+        Bsr AT = bsr_mul(Al, Tm);
+        Bsr Pm = AT;
+        for (int r = 0; r < Al.nr; ++r)
+            for (int q = AT.ptr[r]; q < AT.ptr[r + 1]; ++q) {
+                std::vector<double> prod((size_t)P * P, 0.0);
+                gemm_acc(P, Dinv.data() + (size_t)r * P * P, AT.blk(q), prod.data());
+                double* dst = Pm.blk(q);
+                for (size_t e = 0; e < prod.size(); ++e) dst[e] = -omega * prod[e];
+                if (AT.col[q] == agg[r]) {
+                    double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
+                    for (int i = 0; i < P; ++i) dst[(size_t)i * P + i] += sc;
+                }
+            }
+        Bsr AP = bsr_mul(Al, Pm);
+        Bsr Pt = bsr_transpose(Pm);
+        Bsr Ac = bsr_mul(Pt, AP);
+        Dinvs.push_back(std::move(Dinv));
+        Ps.push_back(std::move(Pm));
+        As.push_back(std::move(Ac));
+    }
+    if (a->h_agg0.empty()) a->h_agg0.assign(ns, -1);
+    const int nl = (int)As.size();
+    a->lev.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+        AmgLevel& Lv = a->lev[l];
+        Lv.nn = As[l].nr;
+        a->h_nodes.push_back(As[l].nr);
+        Lv.x.alloc((size_t)Lv.nn * P);
+        Lv.b.alloc((size_t)Lv.nn * P);
+        Lv.r.alloc((size_t)Lv.nn * P);
+        if (l < nl - 1) {
+            upload_bsr(As[l], Lv.a_ptr, Lv.a_col, Lv.a_val, s);
+            upload_bsr(Ps[l], Lv.p_ptr, Lv.p_col, Lv.p_val, s);
+            upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s);
+            if (prec == SG_FP64) {
+                Lv.dinv64.upload(Dinvs[l], s);
+            } else if (prec == SG_FP32) {
+                std::vector<float> f(Dinvs[l].begin(), Dinvs[l].end());
+                Lv.dinv32.upload(f, s);
+            } else {
+                std::vector<uint16_t> h(Dinvs[l].size());
+                for (size_t q = 0; q < h.size(); ++q) h[q] = host_bf16((float)Dinvs[l][q]);
+                Lv.dinv16.upload(h, s);
+            }
+        }
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    // coarsest: dense FP64 inverse
+    {
+        const Bsr& Ac = As.back();
+        const int N = Ac.nr * P;
+        std::vector<double> D((size_t)N * N, 0.0);
+        for (int r = 0; r < Ac.nr; ++r)
+            for (int q = Ac.ptr[r]; q < Ac.ptr[r + 1]; ++q)
+                for (int i = 0; i < P; ++i)
+                    for (int j = 0; j < P; ++j)
+                        D[(size_t)(r * P + i) * N + Ac.col[q] * P + j] = Ac.blk(q)[(size_t)i * P + j];
+        invert_dense(D, N);
+        a->coarsest_inv.upload(D, s);
+        a->coarsest_n = N;
+    }
+    HIP_OK(hipStreamSynchronize(s));
+}
+
+}  // namespace sg
+
 using namespace sg;
 
 extern "C" {
@@ -488,36 +650,8 @@ int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec p
         a->device = op->device; a->kind = kind; a->prec = prec;
         a->n = n; a->n_sub = ns; a->P = P; a->L = L;
 
-        // owned-node lists and owner map
-        std::vector<int32_t> own_ptr(ns + 1, 0), own_nodes(n);
-        for (int q = 0; q < n; ++q) own_ptr[owner[q] + 1]++;
-        for (int q = 0; q < ns; ++q) own_ptr[q + 1] += own_ptr[q];
-        {
-            std::vector<int32_t> fill(own_ptr.begin(), own_ptr.end() - 1);
-            for (int q = 0; q < n; ++q) own_nodes[fill[owner[q]]++] = q;
-        }
-        a->own_ptr.upload(own_ptr, s);
-        a->own_nodes.upload(own_nodes, s);
-        {
-            std::vector<int32_t> ssub, sbeg, send, sptr(1, 0);
-            for (int q = 0; q < ns; ++q) {
-                for (int b0 = own_ptr[q]; b0 < own_ptr[q + 1]; b0 += kSlice) {
-                    ssub.push_back(q);
-                    sbeg.push_back(b0);
-                    send.push_back(std::min(b0 + kSlice, own_ptr[q + 1]));
-                }
-                sptr.push_back((int32_t)ssub.size());
-            }
-            a->nslices = (int)ssub.size();
-            a->slice_sub.upload(ssub, s);
-            a->slice_beg.upload(sbeg, s);
-            a->slice_end.upload(send, s);
-            a->sub_slice_ptr.upload(sptr, s);
-            a->slice_part.alloc((size_t)a->nslices * P);
-        }
-        a->owner.upload(owner, s);
+        amg_common_setup(a.get(), owner, s);
         a->afact.upload(op->h_afact, s);
-
         // coarse pattern and the fine entries of every coarse entry
         std::vector<std::pair<int64_t, int64_t>> keyed;   // (coarse key, fine entry)
         keyed.reserve(op->nnz);
@@ -575,123 +709,7 @@ int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec p
             for (int t = 0; t < B.T; ++t)
                 blk[(size_t)B.tk[t] * P + B.tj[t]] += C[(size_t)q * L + B.ti[t]] * B.tv[t];
         }
-        std::vector<Bsr> As{A}, Ps;
-        std::vector<std::vector<double>> Dinvs;
-        while ((int)As.size() < amgc::kMaxLevels && As.back().nr > amgc::kMinNodes) {
-            const Bsr& Al = As.back();
-            std::vector<int> agg = aggregate(Al);
-            int na = *std::max_element(agg.begin(), agg.end()) + 1;
-            if (na >= Al.nr) break;
-            if (As.size() == 1) a->h_agg0.assign(agg.begin(), agg.end());
-            // block-diagonal inverse
-            std::vector<double> Dinv((size_t)Al.nr * P * P);
-            for (int r = 0; r < Al.nr; ++r) {
-                bool found = false;
-                for (int q = Al.ptr[r]; q < Al.ptr[r + 1]; ++q)
-                    if (Al.col[q] == r) {
-                        std::vector<double> D(Al.blk(q), Al.blk(q) + (size_t)P * P);
-                        invert_dense(D, P);
-                        std::copy(D.begin(), D.end(), Dinv.begin() + (size_t)r * P * P);
-                        found = true;
-                    }
-                if (!found) SG_THROW(SG_ERR_NUMERIC, "missing diagonal block");
-            }
-            // spectral radius of D^{-1} A by power iteration from ones
-            std::vector<double> v((size_t)Al.nr * P, 1.0), w, dw((size_t)Al.nr * P);
-            double nv = std::sqrt((double)v.size());
-            for (auto& e : v) e /= nv;
-            double rho = 0.0;
-            for (int it = 0; it < amgc::kPowerIts; ++it) {
-                bsr_apply(Al, v, w);
-                for (int r = 0; r < Al.nr; ++r)
-                    for (int i = 0; i < P; ++i) {
-                        double acc = 0.0;
-                        for (int j = 0; j < P; ++j)
-                            acc += Dinv[(size_t)r * P * P + (size_t)i * P + j] * w[(size_t)r * P + j];
-                        dw[(size_t)r * P + i] = acc;
-                    }
-                double nw = 0.0;
-                for (double e : dw) nw += e * e;
-                rho = std::sqrt(nw);
-                for (size_t q = 0; q < v.size(); ++q) v[q] = dw[q] / rho;
-            }
-            const double omega = (4.0 / 3.0) / rho;
-            a->h_omegas.push_back(omega);
-            // tentative prolongator and its smoothing P = T - omega D^{-1} A T
-            std::vector<int> sizes(na, 0);
-            for (int r = 0; r < Al.nr; ++r) sizes[agg[r]]++;
-            Bsr Tm;
-            Tm.nr = Al.nr; Tm.nc = na; Tm.P = P;
-            Tm.ptr.resize(Al.nr + 1);
-            Tm.val.assign((size_t)Al.nr * P * P, 0.0);
-            for (int r = 0; r < Al.nr; ++r) {
-                Tm.ptr[r] = r;
-                Tm.col.push_back(agg[r]);
-                double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
-                for (int i = 0; i < P; ++i) Tm.blk(r)[(size_t)i * P + i] = sc;
-            }
-            Tm.ptr[Al.nr] = Al.nr;
-            Bsr AT = bsr_mul(Al, Tm);
-            Bsr Pm = AT;
-            for (int r = 0; r < Al.nr; ++r)
-                for (int q = AT.ptr[r]; q < AT.ptr[r + 1]; ++q) {
-                    std::vector<double> prod((size_t)P * P, 0.0);
-                    gemm_acc(P, Dinv.data() + (size_t)r * P * P, AT.blk(q), prod.data());
-                    double* dst = Pm.blk(q);
-                    for (size_t e = 0; e < prod.size(); ++e) dst[e] = -omega * prod[e];
-                    if (AT.col[q] == agg[r]) {
-                        double sc = 1.0 / std::sqrt((double)sizes[agg[r]]);
-                        for (int i = 0; i < P; ++i) dst[(size_t)i * P + i] += sc;
-                    }
-                }
-            Bsr AP = bsr_mul(Al, Pm);
-            Bsr Pt = bsr_transpose(Pm);
-            Bsr Ac = bsr_mul(Pt, AP);
-            Dinvs.push_back(std::move(Dinv));
-            Ps.push_back(std::move(Pm));
-            As.push_back(std::move(Ac));
-        }
-        if (a->h_agg0.empty()) a->h_agg0.assign(ns, -1);
-        const int nl = (int)As.size();
-        a->lev.resize(nl);
-        for (int l = 0; l < nl; ++l) {
-            AmgLevel& Lv = a->lev[l];
-            Lv.nn = As[l].nr;
-            a->h_nodes.push_back(As[l].nr);
-            Lv.x.alloc((size_t)Lv.nn * P);
-            Lv.b.alloc((size_t)Lv.nn * P);
-            Lv.r.alloc((size_t)Lv.nn * P);
-            if (l < nl - 1) {
-                upload_bsr(As[l], Lv.a_ptr, Lv.a_col, Lv.a_val, s);
-                upload_bsr(Ps[l], Lv.p_ptr, Lv.p_col, Lv.p_val, s);
-                upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s);
-                if (prec == SG_FP64) {
-                    Lv.dinv64.upload(Dinvs[l], s);
-                } else if (prec == SG_FP32) {
-                    std::vector<float> f(Dinvs[l].begin(), Dinvs[l].end());
-                    Lv.dinv32.upload(f, s);
-                } else {
-                    std::vector<uint16_t> h(Dinvs[l].size());
-                    for (size_t q = 0; q < h.size(); ++q) h[q] = host_bf16((float)Dinvs[l][q]);
-                    Lv.dinv16.upload(h, s);
-                }
-            }
-            HIP_OK(hipStreamSynchronize(s));
-        }
-        // coarsest: dense FP64 inverse
-        {
-            const Bsr& Ac = As.back();
-            const int N = Ac.nr * P;
-            std::vector<double> D((size_t)N * N, 0.0);
-            for (int r = 0; r < Ac.nr; ++r)
-                for (int q = Ac.ptr[r]; q < Ac.ptr[r + 1]; ++q)
-                    for (int i = 0; i < P; ++i)
-                        for (int j = 0; j < P; ++j)
-                            D[(size_t)(r * P + i) * N + Ac.col[q] * P + j] = Ac.blk(q)[(size_t)i * P + j];
-            invert_dense(D, N);
-            a->coarsest_inv.upload(D, s);
-            a->coarsest_n = N;
-        }
+        amg_build_hierarchy(a.get(), std::move(A), s);
         HIP_OK(hipStreamSynchronize(s));
         *out = a.release();
         return SG_OK;

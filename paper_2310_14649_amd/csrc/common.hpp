@@ -118,6 +118,14 @@ struct TriplesDev {
     int P = 0, L = 0, T = 0;
     DevBuf<int32_t> kptr, tij;
     DevBuf<double> tval;
+    // Schedule of the wide-input matvec (L > 32): the k-sorted triples cut
+    // into 64 equal lane chunks; a lane flushes its running sum into a slot at
+    // the end of every run of equal k, and the slots of k are contiguous
+    // ([slot_ptr[k], slot_ptr[k+1])), so y_k sums them in a fixed order.
+    // sched packs i (16 bits) | j << 16 (7 bits) | slot << 23 (8 bits) | flush << 31.
+    int nslot = 0;
+    DevBuf<int32_t> lane_ptr, slot_ptr;
+    DevBuf<uint32_t> sched;
 };
 
 // A "Kronecker-sum" operator Y = sum_i A_i X G_i on a CSR pattern with L
@@ -185,11 +193,59 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
 void build_ell(sg_op* op, hipStream_t s);
 // triples.hip: upload a basis' triple table.
 void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s);
+// triples.hip: graded multi-indices of total degree <= p (count in `count`).
+void enumerate(int M, int p, std::vector<int32_t>& alpha, int& count);
+int binom(int n, int k);
+// triples.hip: non-zero <Psi_a Psi_b Psi_c> for a < na, b < nb, c < nc of
+// the degree-`deg` basis, sorted by (c, a, b).
+struct SparseTriples {
+    std::vector<int32_t> a, b, c;
+    std::vector<double> v;
+};
+void sparse_triples(int M, int deg, int na, int nb, int nc, SparseTriples& out);
+}  // namespace sg
+
+namespace sg {
+// assemble.hip: mesh checks, the P1 pattern with the element contributions
+// of every entry (cref = t*9 + la*3 + lb, in a fixed order), the mesh graph,
+// per-element geometry and input PCE, and the load vector of f = 1.
+struct MeshPattern {
+    std::vector<int32_t> rowptr, col, cref;
+    std::vector<int64_t> cptr;
+    int max_row = 0;
+    std::vector<int64_t> graph_ptr;
+    std::vector<int32_t> graph_col;
+};
+void validate_mesh(int n_vert, const double* xy, int n_tri, const int32_t* tri,
+                   const int32_t* dof, int n);
+// prune: leave out off-diagonal entries whose geometric weight is exactly 0
+// in every element sharing the edge.
+void mesh_pattern(int n_vert, const double* xy, int n_tri, const int32_t* tri, const int32_t* dof,
+                  int n, bool prune, MeshPattern& out);
+struct ElementData {
+    DevBuf<double> ek;      // [n_tri][3][3] |T| grad phi_a . grad phi_b
+    DevBuf<double> ec;      // [n_tri][L] input PCE coefficients at the centroid
+    DevBuf<double> earea;   // [n_tri]
+};
+void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, const int32_t* tri,
+                  const double* g0, const double* g, ElementData& out, hipStream_t s);
+void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,
+                 const int32_t* cref, const double* earea, double* F, hipStream_t s);
 }  // namespace sg
 
 struct sg_ras;
 struct sg_amg;
 namespace sg {
+// The operator FGMRES and the two-grid cycle apply: the Kronecker-sum SG
+// operator of an sg_op (the linear operator, or a Newton Jacobian whose
+// input terms are its degree-2p coefficient fields).
+struct LinOp {
+    const sg_op* kron = nullptr;
+    int n = 0, P = 0;
+};
+// Y = alpha * (A X) + beta * C  (C may equal Y; X must not alias Y)
+void linop_apply(const LinOp& A, const double* X, double* Y, double alpha, double beta,
+                 const double* C, hipStream_t s);
 // ras.hip: Z[owned] = beta * Z[owned] + omega * RAS(R)[owned]
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s);
@@ -205,4 +261,19 @@ int amg_nsub(const sg_amg* a);
 // krylov.hip: drop cached Arnoldi-step graphs that reference a handle
 void graph_cache_purge(const void* handle);
 int amg_device(const sg_amg* a);
+// krylov.hip
+constexpr int kMaxRedBlocks = 1024;
+inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+// synchronous dot product; part: kMaxRedBlocks doubles, scal: 1 double
+double host_dot(int64_t N, const double* x, const double* y, double* part, double* scal,
+                hipStream_t s);
+// workspace of fgmres_core with ns coarse subdomains (ns < 0: no coarse solve)
+size_t fgmres_ws_ns(int n, int P, int ns, int restart);
+size_t fgmres_ws_np(int n, int P, const sg_amg* amg, int restart);
+double smoother_damping_core(const LinOp& A, const sg_ras* ras, int its, char* ws, size_t ws_bytes,
+                             hipStream_t s, double* rho_out);
+// key_op identifies the operator in the graph cache
+int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ras,
+                const sg_amg* amg, const double* b, double* x, const sg_krylov_opts* opts,
+                sg_krylov_stats* stats, void* ws, size_t ws_bytes, hipStream_t s);
 }  // namespace sg

@@ -23,7 +23,6 @@ namespace sg {
 namespace {
 
 constexpr int kVT = 256;      // threads per vector block
-constexpr int kMaxRedBlocks = 1024;
 
 inline int red_blocks(int64_t N) {
     int64_t b = (N + kVT * 4 - 1) / (kVT * 4);
@@ -193,33 +192,22 @@ struct Vec {
     }
 };
 
-// Host-visible dot product (synchronous).
-double host_dot(int64_t N, const double* x, const double* y, double* part, double* scal,
-                hipStream_t s) {
-    const int nb = red_blocks(N);
-    dot_partial_kernel<<<nb, kVT, 0, s>>>(N, x, y, part);
-    HIP_LAUNCH_OK();
-    reduce_kernel<<<1, kVT, 0, s>>>(nb, part, scal);
-    HIP_LAUNCH_OK();
-    double h = 0.0;
-    HIP_OK(hipMemcpyAsync(&h, scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    return h;
-}
-
-size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // workspace needed by the preconditioner: T [N], rc [ns*P], ec [ns*P]
-size_t precond_ws(const sg_op* op, const sg_amg* amg) {
-    size_t N = (size_t)op->n * op->P;
+size_t precond_ws_ns(int n, int P, int ns) {
+    size_t N = (size_t)n * P;
     size_t b = align_up(N * 8);
-    if (amg) b += 2 * align_up((size_t)amg_nsub(amg) * op->P * 8);
+    if (ns >= 0) b += 2 * align_up((size_t)ns * P * 8);
     return b;
 }
+size_t precond_ws_np(int n, int P, const sg_amg* amg) {
+    return precond_ws_ns(n, P, amg ? amg_nsub(amg) : -1);
+}
+size_t precond_ws(const sg_op* op, const sg_amg* amg) { return precond_ws_np(op->n, op->P, amg); }
 
-void precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
+void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double omega,
                    const double* R, double* Z, char* ws, hipStream_t s) {
-    const int64_t N = (int64_t)op->n * op->P;
+    const int64_t N = (int64_t)A.n * A.P;
     if (!ras) {
         scale_kernel<<<grid_for(N), 256, 0, s>>>(N, 1.0, R, Z);
         HIP_LAUNCH_OK();
@@ -230,13 +218,12 @@ void precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double
     double* T = reinterpret_cast<double*>(ws);
     double* rc = reinterpret_cast<double*>(ws + align_up(N * 8));
     double* ec = reinterpret_cast<double*>(ws + align_up(N * 8) +
-                                           align_up((size_t)amg_nsub(amg) * op->P * 8));
-    const KronCsr A = op->csr();
-    kron_matvec(A, op->L, op->tr, Z, T, -1.0, 1.0, R, s);            // t = r - A z1
+                                           align_up((size_t)amg_nsub(amg) * A.P * 8));
+    linop_apply(A, Z, T, -1.0, 1.0, R, s);                           // t = r - A z1
     coarse_restrict(amg, T, rc, s);
     coarse_solve(amg, rc, ec, s);
     coarse_prolong_add(amg, ec, Z, s);                               // z2 = z1 + Q t
-    kron_matvec(A, op->L, op->tr, Z, T, -1.0, 1.0, R, s);            // t = r - A z2
+    linop_apply(A, Z, T, -1.0, 1.0, R, s);                           // t = r - A z2
     ras_apply_ex(ras, T, Z, omega, 1.0, s);                          // z = z2 + w M t
 }
 
@@ -289,95 +276,27 @@ void graph_cache_purge(const void* handle) {
 
 }  // namespace sg
 
-using namespace sg;
+namespace sg {
 
-extern "C" {
-
-size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg) {
-    if (!op) return 0;
-    return precond_ws(op, amg);
+// Host-visible dot product (synchronous).
+double host_dot(int64_t N, const double* x, const double* y, double* part, double* scal,
+                hipStream_t s) {
+    const int nb = red_blocks(N);
+    dot_partial_kernel<<<nb, kVT, 0, s>>>(N, x, y, part);
+    HIP_LAUNCH_OK();
+    reduce_kernel<<<1, kVT, 0, s>>>(nb, part, scal);
+    HIP_LAUNCH_OK();
+    double h = 0.0;
+    HIP_OK(hipMemcpyAsync(&h, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return h;
 }
 
-static void check_set(const sg_op* op, const sg_ras* ras, const sg_amg* amg) {
-    SG_REQUIRE(op != nullptr, "op is NULL");
-    check_device(op->device);
-    if (ras) {
-        SG_REQUIRE(ras_device(ras) == op->device, "ras on another device");
-        SG_REQUIRE(ras_n(ras) == op->n, "ras built for another operator");
-    }
-    if (amg) {
-        SG_REQUIRE(ras != nullptr, "a coarse solver needs the RAS smoother");
-        SG_REQUIRE(amg_device(amg) == op->device, "amg on another device");
-        SG_REQUIRE(amg_nsub(amg) == ras_nsub(ras), "amg and ras disagree on subdomains");
-    }
-}
-
-int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
-                     const double* R, double* Z, void* ws, size_t ws_bytes, void* stream) {
-    return guarded([&]() -> int {
-        check_set(op, ras, amg);
-        SG_REQUIRE(R && Z && R != Z, "R, Z must be distinct non-null");
-        SG_REQUIRE(ras != nullptr, "ras is NULL");
-        if (amg) {
-            if (!ws || ws_bytes < precond_ws(op, amg))
-                SG_THROW(SG_ERR_WORKSPACE, "precond workspace too small (%zu < %zu)", ws_bytes,
-                         precond_ws(op, amg));
-        }
-        precond_apply(op, ras, amg, omega, R, Z, reinterpret_cast<char*>(ws), as_stream(stream));
-        return SG_OK;
-    });
-}
-
-int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho_out,
-                        double* omega_out, void* ws, size_t ws_bytes, void* stream) {
-    return guarded([&]() -> int {
-        check_set(op, ras, nullptr);
-        SG_REQUIRE(ras != nullptr, "ras is NULL");
-        SG_REQUIRE(its >= 1, "its must be >= 1");
-        const int64_t N = (int64_t)op->n * op->P;
-        const size_t need = 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8) + 256;
-        if (!ws || ws_bytes < need)
-            SG_THROW(SG_ERR_WORKSPACE, "damping workspace too small (%zu < %zu)", ws_bytes, need);
-        hipStream_t s = as_stream(stream);
-        char* p = reinterpret_cast<char*>(ws);
-        double* v = reinterpret_cast<double*>(p);
-        double* w = reinterpret_cast<double*>(p + align_up(N * 8));
-        double* part = reinterpret_cast<double*>(p + 2 * align_up(N * 8));
-        double* scal = reinterpret_cast<double*>(p + 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8));
-        Vec::fill(N, 1.0 / std::sqrt((double)N), v, s);
-        double rho = 0.0;
-        const KronCsr A = op->csr();
-        for (int it = 0; it < its; ++it) {
-            kron_matvec(A, op->L, op->tr, v, w, 1.0, 0.0, nullptr, s);
-            ras_apply_ex(ras, w, v, 1.0, 0.0, s);
-            rho = std::sqrt(host_dot(N, v, v, part, scal, s));
-            if (!(rho > 0.0) || !std::isfinite(rho)) SG_THROW(SG_ERR_NUMERIC, "power iteration broke down");
-            Vec::scale(N, 1.0 / rho, v, v, s);
-        }
-        if (rho_out) *rho_out = rho;
-        if (omega_out) *omega_out = std::min(1.0, 1.6 / rho);
-        HIP_OK(hipStreamSynchronize(s));
-        return SG_OK;
-    });
-}
-
-int sg_graph_cache_clear(void) {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    int n = 0;
-    for (auto& kv : graph_cache()) {
-        (void)hipGraphExecDestroy(kv.second);
-        ++n;
-    }
-    graph_cache().clear();
-    return n;
-}
-
-size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart) {
-    if (!op || restart < 1) return 0;
-    const size_t N = (size_t)op->n * op->P;
+size_t fgmres_ws_ns(int n, int P, int ns, int restart) {
+    const size_t N = (size_t)n * P;
     const size_t m = (size_t)restart;
     size_t b = align_up(N * 8) * (2 * m + 2);                 // V (m+1), Z (m), w
-    b += precond_ws(op, amg);
+    b += precond_ws_ns(n, P, ns);
     b += 2 * align_up(kMaxRedBlocks * 8);                     // partial sums
     b += align_up((m + 1) * m * 8) + 4 * align_up((m + 1) * 8) + align_up(64);
     // the damping estimate reuses the front of the workspace
@@ -385,46 +304,73 @@ size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart) {
     return b > damp ? b : damp;
 }
 
-int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const double* b, double* x,
-                 const sg_krylov_opts* opts, sg_krylov_stats* stats, void* ws, size_t ws_bytes,
-                 void* stream) {
-    return guarded([&]() -> int {
-        check_set(op, ras, amg);
-        SG_REQUIRE(b && x && opts, "null argument");
-        SG_REQUIRE(b != x, "b and x must not alias");
-        const int m = opts->restart;
-        SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
-        SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
-        SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
-        const size_t need = fgmres_workspace_bytes(op, amg, m);
-        if (!ws || ws_bytes < need)
-            SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
-        hipStream_t s = as_stream(stream);
-        const int64_t N = (int64_t)op->n * op->P;
-        const size_t vb = align_up(N * 8);
-        char* p = reinterpret_cast<char*>(ws);
-        double* V = reinterpret_cast<double*>(p);                         // (m+1) vectors
-        double* Zb = reinterpret_cast<double*>(p + vb * (m + 1));         // m vectors
-        double* w = reinterpret_cast<double*>(p + vb * (2 * m + 1));
-        char* pws = p + vb * (2 * m + 2);
-        char* q = pws + precond_ws(op, amg);
-        double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
-        double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
-        double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
-        double* cs = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
-        double* sn = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
-        double* g = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
-        double* y = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
-        double* scal = reinterpret_cast<double*>(q);                      // est, flag, dot
-        double* part[2] = {part0, part1};
+size_t fgmres_ws_np(int n, int P, const sg_amg* amg, int restart) {
+    return fgmres_ws_ns(n, P, amg ? amg_nsub(amg) : -1, restart);
+}
+
+// Power estimate of rho(M A) from the all-ones field; returns the smoother
+// damping min(1, 1.6/rho).  ws: >= 2 vectors + partial sums.
+double smoother_damping_core(const LinOp& A, const sg_ras* ras, int its, char* p, size_t ws_bytes,
+                             hipStream_t s, double* rho_out) {
+    const int64_t N = (int64_t)A.n * A.P;
+    const size_t need = 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8) + 256;
+    if (!p || ws_bytes < need)
+        SG_THROW(SG_ERR_WORKSPACE, "damping workspace too small (%zu < %zu)", ws_bytes, need);
+    double* v = reinterpret_cast<double*>(p);
+    double* w = reinterpret_cast<double*>(p + align_up(N * 8));
+    double* part = reinterpret_cast<double*>(p + 2 * align_up(N * 8));
+    double* scal = reinterpret_cast<double*>(p + 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8));
+    Vec::fill(N, 1.0 / std::sqrt((double)N), v, s);
+    double rho = 0.0;
+    for (int it = 0; it < its; ++it) {
+        linop_apply(A, v, w, 1.0, 0.0, nullptr, s);
+        ras_apply_ex(ras, w, v, 1.0, 0.0, s);
+        rho = std::sqrt(host_dot(N, v, v, part, scal, s));
+        if (!(rho > 0.0) || !std::isfinite(rho)) SG_THROW(SG_ERR_NUMERIC, "power iteration broke down");
+        Vec::scale(N, 1.0 / rho, v, v, s);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    if (rho_out) *rho_out = rho;
+    return std::min(1.0, 1.6 / rho);
+}
+
+// Flexible GMRES on any LinOp.  key_op identifies the operator in the graph
+// cache (its handle or matrix storage).
+int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ras,
+                const sg_amg* amg, const double* b, double* x, const sg_krylov_opts* opts,
+                sg_krylov_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+    SG_REQUIRE(b && x && opts, "null argument");
+    SG_REQUIRE(b != x, "b and x must not alias");
+    const int m = opts->restart;
+    SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
+    SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
+    SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
+    const size_t need = fgmres_ws_np(A.n, A.P, amg, m);
+    if (!ws || ws_bytes < need)
+        SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
+    const int64_t N = (int64_t)A.n * A.P;
+    const size_t vb = align_up(N * 8);
+    char* p = reinterpret_cast<char*>(ws);
+    double* V = reinterpret_cast<double*>(p);                         // (m+1) vectors
+    double* Zb = reinterpret_cast<double*>(p + vb * (m + 1));         // m vectors
+    double* w = reinterpret_cast<double*>(p + vb * (2 * m + 1));
+    char* pws = p + vb * (2 * m + 2);
+    char* q = pws + precond_ws_np(A.n, A.P, amg);
+    double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
+    double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
+    double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
+    double* cs = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+    double* sn = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+    double* g = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+    double* y = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+    double* scal = reinterpret_cast<double*>(q);                      // est, flag, dot
+    double* part[2] = {part0, part1};
         const int nb = red_blocks(N);
-        const KronCsr A = op->csr();
 
         double omega = opts->omega;
         if (ras && !(omega > 0.0)) {
             double rho = 0.0;
-            int rc = sg_smoother_damping(op, ras, 15, &rho, &omega, ws, ws_bytes, stream);
-            if (rc != SG_OK) SG_THROW(rc, "%s", sg_last_error());
+            omega = smoother_damping_core(A, ras, 15, reinterpret_cast<char*>(ws), ws_bytes, s, &rho);
         }
         if (!(omega > 0.0)) omega = 1.0;
 
@@ -442,8 +388,8 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
         auto arnoldi_step = [&](int j, hipStream_t st) {
             double* vj = V + (size_t)j * (vb / 8);
             double* zj = Zb + (size_t)j * (vb / 8);
-            precond_apply(op, ras, amg, omega, vj, zj, pws, st);
-            kron_matvec(A, op->L, op->tr, zj, w, 1.0, 0.0, nullptr, st);
+            precond_apply(A, ras, amg, omega, vj, zj, pws, st);
+            linop_apply(A, zj, w, 1.0, 0.0, nullptr, st);
             dot_partial_kernel<<<nb, kVT, 0, st>>>(N, w, V, part[0]);
             HIP_LAUNCH_OK();
             double* hcol = H + (size_t)j * (m + 1);
@@ -467,7 +413,7 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
         } else {
             if (!std::isfinite(bnorm)) SG_THROW(SG_ERR_NUMERIC, "right-hand side is not finite");
             const double target = opts->rtol * bnorm;
-            kron_matvec(A, op->L, op->tr, x, V, -1.0, 1.0, b, s);          // r0 = b - A x0
+            linop_apply(A, x, V, -1.0, 1.0, b, s);                        // r0 = b - A x0
             double beta = std::sqrt(host_dot(N, V, V, part0, scal + 2, s));
             if (!std::isfinite(beta)) SG_THROW(SG_ERR_NUMERIC, "initial residual is not finite");
             relres = beta / bnorm;
@@ -482,7 +428,7 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
                 for (int j = 0; j < m; ++j) {
                     if (opts->use_graph) {
                         hipGraphExec_t exec = nullptr;
-                        GraphKey key{op, ras, amg, ws, ws_bytes, m, j, 0};
+                        GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, 0};
                         std::memcpy(&key.omega_bits, &omega, sizeof(double));
                         {
                             std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -490,7 +436,7 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
                             if (it != graph_cache().end()) exec = it->second;
                         }
                         if (!exec) {
-                            hipStream_t cst = capture_stream(op->device);
+                            hipStream_t cst = capture_stream(device);
                             HIP_OK(hipStreamSynchronize(s));
                             HIP_OK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
                             try {
@@ -527,7 +473,7 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
                 HIP_LAUNCH_OK();
                 multi_axpy_kernel<<<grid_for(N), kVT, 0, s>>>(N, (int64_t)(vb / 8), jd, y, Zb, x);
                 HIP_LAUNCH_OK();
-                kron_matvec(A, op->L, op->tr, x, V, -1.0, 1.0, b, s);      // true residual
+                linop_apply(A, x, V, -1.0, 1.0, b, s);                    // true residual
                 beta = std::sqrt(host_dot(N, V, V, part0, scal + 2, s));
                 relres = beta / bnorm;
                 if (beta <= target) { converged = true; break; }
@@ -547,6 +493,94 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const do
             stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
         }
         return converged ? SG_OK : SG_NOT_CONVERGED;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg) {
+    if (!op) return 0;
+    return precond_ws(op, amg);
+}
+
+static void check_set(const sg_op* op, const sg_ras* ras, const sg_amg* amg) {
+    SG_REQUIRE(op != nullptr, "op is NULL");
+    check_device(op->device);
+    if (ras) {
+        SG_REQUIRE(ras_device(ras) == op->device, "ras on another device");
+        SG_REQUIRE(ras_n(ras) == op->n, "ras built for another operator");
+    }
+    if (amg) {
+        SG_REQUIRE(ras != nullptr, "a coarse solver needs the RAS smoother");
+        SG_REQUIRE(amg_device(amg) == op->device, "amg on another device");
+        SG_REQUIRE(amg_nsub(amg) == ras_nsub(ras), "amg and ras disagree on subdomains");
+    }
+}
+
+static LinOp kron_op(const sg_op* op) {
+    LinOp A;
+    A.kron = op;
+    A.n = op->n;
+    A.P = op->P;
+    return A;
+}
+
+int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
+                     const double* R, double* Z, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, amg);
+        SG_REQUIRE(R && Z && R != Z, "R, Z must be distinct non-null");
+        SG_REQUIRE(ras != nullptr, "ras is NULL");
+        if (amg) {
+            if (!ws || ws_bytes < precond_ws(op, amg))
+                SG_THROW(SG_ERR_WORKSPACE, "precond workspace too small (%zu < %zu)", ws_bytes,
+                         precond_ws(op, amg));
+        }
+        precond_apply(kron_op(op), ras, amg, omega, R, Z, reinterpret_cast<char*>(ws),
+                      as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho_out,
+                        double* omega_out, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, nullptr);
+        SG_REQUIRE(ras != nullptr, "ras is NULL");
+        SG_REQUIRE(its >= 1, "its must be >= 1");
+        double om = smoother_damping_core(kron_op(op), ras, its, reinterpret_cast<char*>(ws),
+                                          ws_bytes, as_stream(stream), rho_out);
+        if (omega_out) *omega_out = om;
+        return SG_OK;
+    });
+}
+
+int sg_graph_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    int n = 0;
+    for (auto& kv : graph_cache()) {
+        (void)hipGraphExecDestroy(kv.second);
+        ++n;
+    }
+    graph_cache().clear();
+    return n;
+}
+
+size_t fgmres_workspace_bytes(const sg_op* op, const sg_amg* amg, int restart) {
+    if (!op || restart < 1) return 0;
+    return fgmres_ws_np(op->n, op->P, amg, restart);
+}
+
+int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg, const double* b, double* x,
+                 const sg_krylov_opts* opts, sg_krylov_stats* stats, void* ws, size_t ws_bytes,
+                 void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, amg);
+        return fgmres_core(kron_op(op), op, op->device, ras, amg, b, x, opts, stats, ws, ws_bytes,
+                           as_stream(stream));
     });
 }
 

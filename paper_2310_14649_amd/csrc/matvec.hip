@@ -96,6 +96,71 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Wide-input kernel (L > 32 input terms, e.g. the degree-2p coefficient
+// fields of a Newton Jacobian).  One wave per row: the row's K_i values
+// (entries x L) and its neighbours' X rows are staged in the wave's own LDS
+// slice (zero-padded to EMAX entries), then every lane walks its chunk of
+// the k-sorted triple table,
+//     acc += m_ijk * sum_e K_i[a, b_e] X[b_e, j],
+// flushing acc into a slot at the end of each run of equal k; lane k then
+// sums the slots of k in order.  Work per row is T*EMAX FMAs, spread evenly
+// over the 64 lanes whatever the number of triples per k.
+__device__ __forceinline__ void wave_lds_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int EMAX>
+__global__ __launch_bounds__(256) void kron_matvec_wide_kernel(
+    int n, int P, int L, int nslot, int wpg, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, const double* __restrict__ vals,
+    const int32_t* __restrict__ lane_ptr, const uint32_t* __restrict__ sched,
+    const double* __restrict__ sval, const int32_t* __restrict__ slot_ptr,
+    const double* __restrict__ X, double* Y, double alpha, double beta, const double* C) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t per_wave = (size_t)EMAX * (L + P) + nslot;
+    double* Kv = reinterpret_cast<double*>(smem_raw) + wave * per_wave;   // [EMAX][L]
+    double* Xv = Kv + (size_t)EMAX * L;                                    // [EMAX][P]
+    double* part = Xv + (size_t)EMAX * P;                                  // [nslot]
+    const int t0 = lane_ptr[lane], t1 = lane_ptr[lane + 1];
+    for (int row = blockIdx.x * wpg + wave; row < n; row += gridDim.x * wpg) {
+        const int e0 = rowptr[row];
+        const int ne = rowptr[row + 1] - e0;
+        for (int q = lane; q < EMAX * L; q += 64)
+            Kv[q] = (q < ne * L) ? vals[(size_t)e0 * L + q] : 0.0;
+        for (int q = lane; q < EMAX * P; q += 64) {
+            const int e = q / P, j = q - (q / P) * P;
+            Xv[q] = (e < ne) ? X[(size_t)col[e0 + e] * P + j] : 0.0;
+        }
+        wave_lds_sync();
+        double acc = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const uint32_t w = sched[t];
+            const int i = (int)(w & 0xffffu), j = (int)((w >> 16) & 0x7fu);
+            double x = 0.0;
+#pragma unroll
+            for (int e = 0; e < EMAX; ++e) x = fma(Kv[e * L + i], Xv[e * P + j], x);
+            acc = fma(sval[t], x, acc);
+            if (w >> 31) {
+                part[(w >> 23) & 0xffu] = acc;
+                acc = 0.0;
+            }
+        }
+        wave_lds_sync();
+        for (int k = lane; k < P; k += 64) {
+            double y = 0.0;
+            for (int q = slot_ptr[k]; q < slot_ptr[k + 1]; ++q) y += part[q];
+            const size_t o = (size_t)row * P + k;
+            double outv = alpha * y;
+            if (beta != 0.0) outv = fma(beta, C[o], outv);
+            Y[o] = outv;
+        }
+        wave_lds_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Specialised kernel for a fixed basis (M, PIN, PO), ELL width S and IG lanes
 // per row.  Each lane keeps its row's K_i values for its share of the input
 // terms in registers (read once, coalesced, from the wave-tiled ELL copy),
@@ -313,6 +378,32 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
         HIP_LAUNCH_OK();
         return;
     }
+    if (L > 32) {
+        SG_REQUIRE(tr.nslot > 0, "wide matvec schedule missing");
+        int emax = A.max_row <= 7 ? 7 : A.max_row <= 10 ? 10 : A.max_row <= 16 ? 16 : 0;
+        if (!emax) SG_THROW(SG_ERR_UNSUPPORTED, "wide matvec: %d entries in a row exceed 16", A.max_row);
+        const size_t per_wave = ((size_t)emax * (L + P) + tr.nslot) * 8;
+        const size_t cap = 64 * 1024;
+        int wpg = (int)std::min<size_t>(4, cap / per_wave);
+        if (wpg < 1)
+            SG_THROW(SG_ERR_UNSUPPORTED, "wide matvec row needs %zu bytes of LDS (L=%d P=%d)", per_wave,
+                     L, P);
+        const size_t lds = per_wave * wpg;
+        const int blocks = (int)std::min<int64_t>((A.n + wpg - 1) / wpg, 8192);
+#define SG_LAUNCH_WIDE(EM)                                                                   \
+    kron_matvec_wide_kernel<EM><<<blocks, 64 * wpg, lds, s>>>(                               \
+        A.n, P, L, tr.nslot, wpg, A.rowptr, A.col, A.vals, tr.lane_ptr.p, tr.sched.p, tr.tval.p, \
+        tr.slot_ptr.p, X, Y, alpha, beta, C)
+        if (emax == 7)
+            SG_LAUNCH_WIDE(7);
+        else if (emax == 10)
+            SG_LAUNCH_WIDE(10);
+        else
+            SG_LAUNCH_WIDE(16);
+#undef SG_LAUNCH_WIDE
+        HIP_LAUNCH_OK();
+        return;
+    }
     // rows per tile: as many as fit the thread count and the LDS budget
     auto lds_for = [&](int R) {
         size_t ent = (size_t)R * A.max_row;
@@ -343,6 +434,13 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
     HIP_LAUNCH_OK();
 }
 
+}  // namespace sg
+
+namespace sg {
+void linop_apply(const LinOp& A, const double* X, double* Y, double alpha, double beta,
+                 const double* C, hipStream_t s) {
+    kron_matvec(A.kron->csr(), A.kron->L, A.kron->tr, X, Y, alpha, beta, C, s);
+}
 }  // namespace sg
 
 using namespace sg;

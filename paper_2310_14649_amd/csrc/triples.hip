@@ -37,20 +37,23 @@ __device__ double hermite_triple(int a, int b, int c) {
            (dev_fact(s - a) * dev_fact(s - b) * dev_fact(s - c));
 }
 
-// One thread per (i, j, k); dense output [L][P][P].
-__global__ void triple_dense_kernel(int M, int L, int P, const int32_t* __restrict__ alpha,
+// One thread per (i, j, k), i < na, j < nb, k < nc (all three index the
+// same graded enumeration); dense output [na][nb][nc].
+__global__ void triple_dense_kernel(int M, int na, int nb, int nc, const int32_t* __restrict__ alpha,
                                     double* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)L * P * P;
+    int64_t total = (int64_t)na * nb * nc;
     if (idx >= total) return;
-    int k = (int)(idx % P);
-    int j = (int)((idx / P) % P);
-    int i = (int)(idx / ((int64_t)P * P));
+    int k = (int)(idx % nc);
+    int j = (int)((idx / nc) % nb);
+    int i = (int)(idx / ((int64_t)nb * nc));
     double m = 1.0;
     for (int d = 0; d < M && m != 0.0; ++d)
         m *= hermite_triple(alpha[i * M + d], alpha[j * M + d], alpha[k * M + d]);
     out[idx] = m;
 }
+
+}  // namespace
 
 // Multi-indices of total degree <= p: by degree, then descending lexicographic.
 void enumerate(int M, int p, std::vector<int32_t>& alpha, int& count) {
@@ -86,7 +89,36 @@ int binom(int n, int k) {
     return (int)r;
 }
 
-}  // namespace
+void sparse_triples(int M, int deg, int na, int nb, int nc, SparseTriples& out) {
+    std::vector<int32_t> alpha;
+    int cnt = 0;
+    enumerate(M, deg, alpha, cnt);
+    SG_REQUIRE(na <= cnt && nb <= cnt && nc <= cnt, "triple ranges exceed the degree-%d basis", deg);
+    out.a.clear(); out.b.clear(); out.c.clear(); out.v.clear();
+    const size_t total = (size_t)na * nb * nc;
+    std::vector<double> dense(total, 0.0);
+    if (M == 0) {
+        dense[0] = 1.0;
+    } else {
+        DevBuf<int32_t> d_alpha;
+        DevBuf<double> d_out(total);
+        d_alpha.upload(alpha, nullptr);
+        const int threads = 256;
+        const int blocks = (int)((total + threads - 1) / threads);
+        triple_dense_kernel<<<blocks, threads>>>(M, na, nb, nc, d_alpha.p, d_out.p);
+        HIP_LAUNCH_OK();
+        d_out.download(dense.data(), total, nullptr);
+        HIP_OK(hipDeviceSynchronize());
+    }
+    for (int k = 0; k < nc; ++k)
+        for (int i = 0; i < na; ++i)
+            for (int j = 0; j < nb; ++j) {
+                const double v = dense[((size_t)i * nb + j) * nc + k];
+                if (v != 0.0) {
+                    out.a.push_back(i); out.b.push_back(j); out.c.push_back(k); out.v.push_back(v);
+                }
+            }
+}
 
 void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s) {
     tr.P = b.P;
@@ -101,6 +133,35 @@ void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s) {
     tr.kptr.upload(kptr, s);
     tr.tij.upload(tij, s);
     tr.tval.upload(b.tv, s);
+    if (b.L > 32) {
+        SG_REQUIRE(b.L <= 65536 && b.P <= 128, "wide matvec schedule limits exceeded");
+        constexpr int kLanes = 64;
+        std::vector<int32_t> lane_ptr(kLanes + 1), slot_ptr(b.P + 1, 0);
+        std::vector<uint32_t> sched(b.T);
+        int slot = 0;
+        for (int c = 0; c < kLanes; ++c) {
+            const int t0 = (int)((int64_t)b.T * c / kLanes), t1 = (int)((int64_t)b.T * (c + 1) / kLanes);
+            lane_ptr[c] = t0;
+            for (int t = t0; t < t1; ++t) {
+                const bool flush = (t + 1 == t1) || (b.tk[t + 1] != b.tk[t]);
+                sched[t] = (uint32_t)b.ti[t] | ((uint32_t)b.tj[t] << 16) | ((uint32_t)slot << 23) |
+                           (flush ? 0x80000000u : 0u);
+                if (flush) {
+                    slot_ptr[b.tk[t] + 1] = slot + 1;
+                    ++slot;
+                }
+            }
+        }
+        lane_ptr[kLanes] = b.T;
+        SG_REQUIRE(slot <= 256, "wide matvec schedule needs %d slots", slot);
+        // every k has at least one triple (i = 0, j = k), so slot_ptr is increasing
+        for (int k = 0; k < b.P; ++k)
+            SG_REQUIRE(slot_ptr[k + 1] > slot_ptr[k], "output mode %d has no triple", k);
+        tr.nslot = slot;
+        tr.lane_ptr.upload(lane_ptr, s);
+        tr.slot_ptr.upload(slot_ptr, s);
+        tr.sched.upload(sched, s);
+    }
     HIP_OK(hipStreamSynchronize(s));
 }
 
@@ -138,31 +199,10 @@ int sg_build_triples(int M, int p_in, int p_out, sg_basis** out) {
             for (int d = 0; d < M; ++d)
                 for (int v = 2; v <= b->alpha[k * M + d]; ++v) b->afact[k] *= v;
 
-        // device evaluation of the dense tensor, host compaction
-        size_t total = (size_t)L * P * P;
-        std::vector<double> dense(total, 0.0);
-        if (M == 0) {
-            dense[0] = 1.0;
-        } else {
-            DevBuf<int32_t> d_alpha;
-            DevBuf<double> d_out(total);
-            d_alpha.upload(b->alpha, nullptr);
-            int threads = 256;
-            int blocks = (int)((total + threads - 1) / threads);
-            triple_dense_kernel<<<blocks, threads>>>(M, L, P, d_alpha.p, d_out.p);
-            HIP_LAUNCH_OK();
-            d_out.download(dense.data(), total, nullptr);
-            HIP_OK(hipDeviceSynchronize());
-        }
-        for (int k = 0; k < P; ++k)
-            for (int i = 0; i < L; ++i)
-                for (int j = 0; j < P; ++j) {
-                    double v = dense[((size_t)i * P + j) * P + k];
-                    if (v != 0.0) {
-                        b->ti.push_back(i); b->tj.push_back(j); b->tk.push_back(k);
-                        b->tv.push_back(v);
-                    }
-                }
+        SparseTriples st;
+        sparse_triples(M, p_out, L, P, P, st);
+        b->ti = std::move(st.a); b->tj = std::move(st.b); b->tk = std::move(st.c);
+        b->tv = std::move(st.v);
         b->T = (int)b->tv.size();
         *out = guard.release();
         return SG_OK;

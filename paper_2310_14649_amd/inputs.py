@@ -307,6 +307,9 @@ CONFIGS = {
     "c3": dict(nc=384, M=6, p=3, sigma=0.5, ell=0.2, sub="graph", overlap=2, restart=50,
                jitter=0.3, graph=(16, 12, 300, 1200)),
     "c4": dict(nc=128, M=4, p=3, sigma=0.5, ell=0.2, sub=(8, 8), overlap=2, restart=50),
+    # jittered mesh with lattice subdomains (reduced test instances)
+    "jit": dict(nc=26, M=4, p=3, sigma=0.5, ell=0.2, sub=(3, 3), overlap=2, restart=50,
+                jitter=0.3),
 }
 
 

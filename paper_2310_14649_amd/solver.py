@@ -100,3 +100,81 @@ class GpuSG:
             self.close()
         except Exception:
             pass
+
+
+class GpuNewton:
+    """Nonlinear SG problem (kappa(u) = 1 + a2 u^2) on the GPU: sequences
+    ``sg_nl_setup`` / ``sg_nl_eval`` / ``newton_solve`` and owns the buffers."""
+
+    def __init__(self, pr: Problem, a2: float = 0.5, prec: str = "fp64", coarse: str = "amg",
+                 overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
+                 n_sub: Optional[int] = None, stream=None):
+        import torch
+        self.torch = torch
+        self.pr = pr
+        self.stream = stream
+        self.basis = self.nl = None
+        m = pr.mesh
+        self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
+        self.nl = B.sg_nl_setup(self.basis, m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, a2,
+                                stream=stream)
+        self.n, self.P, self.L2, self.nnz = B.sg_nl_info(self.nl)
+        self.owner = pr.owner if owner is None else owner
+        self.n_sub = pr.n_sub if n_sub is None else n_sub
+        self.overlap = pr.overlap if overlap is None else overlap
+        self.prec = prec
+        self.coarse = coarse
+        self._ws = None
+        self._ws_restart = None
+
+    def new_vec(self, fill: float = 0.0):
+        return self.torch.full((self.n * self.P,), fill, dtype=self.torch.float64, device="cuda")
+
+    def residual(self, U):
+        """R(U) = F e_0 - A(U); also leaves K1 and the Jacobian assembled at U."""
+        R = self.new_vec()
+        B.sg_nl_eval(self.nl, U, R, stream=self.stream)
+        return R
+
+    def jac_apply(self, X):
+        Y = self.new_vec()
+        B.sg_nl_jac_apply(self.nl, X, Y, stream=self.stream)
+        return Y
+
+    def workspace(self, restart: int):
+        if self._ws is None or self._ws_restart != restart:
+            nbytes = B.newton_workspace_bytes(self.nl, self.n_sub, COARSE[self.coarse], restart)
+            self._ws = self.torch.empty((nbytes + 7) // 8, dtype=self.torch.float64, device="cuda")
+            self._ws_restart = restart
+        return self._ws
+
+    def solve(self, U0=None, tol: float = 1e-8, max_steps: int = 30, restart: Optional[int] = None,
+              max_it: int = 1000, eta_max: float = 1e-2, omega: float = 0.0,
+              use_graph: bool = False):
+        restart = self.pr.restart if restart is None else restart
+        U = self.new_vec() if U0 is None else U0.clone()
+        info = B.newton_solve(self.nl, self.owner, self.n_sub, self.overlap, B.PREC[self.prec],
+                              COARSE[self.coarse], U, self.workspace(restart), max_steps=max_steps,
+                              tol=tol, eta_max=eta_max, restart=restart, max_it=max_it,
+                              omega=omega, use_graph=use_graph, stream=self.stream)
+        return U, info
+
+    def close(self):
+        if self.nl is not None:
+            B.sg_destroy_nl(self.nl)
+            self.nl = None
+        if self.basis is not None:
+            B.sg_destroy_basis(self.basis)
+            self.basis = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,200 @@
+"""Parity of the GPU nonlinear SG path (residual, Jacobian, Newton) with the
+CPU oracle.
+
+The oracle evaluates every expectation by a tensor Gauss-Hermite rule that
+is exact for the degree-14 integrands; the library forms the same
+expectations from chaos products.  Both are exact up to rounding, so the
+residual and the Jacobian agree to 1e-12 relative to their largest entry
+(sums of a few thousand O(1) products).  Newton solutions are compared at
+the converged tolerance: both sides drive ||R||/||F|| below 1e-12, and the
+Jacobian's condition number (< 1e4 at these sizes) bounds the difference
+of the iterates by ~1e-8 relative.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import newton as onl  # noqa: E402
+from paper_2310_14649_amd import binding as B  # noqa: E402
+from paper_2310_14649_amd.inputs import make_problem  # noqa: E402
+from paper_2310_14649_amd.solver import GpuNewton, GpuSG  # noqa: E402
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _host(t, shape):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().reshape(shape)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def _oracle(pr, a2=0.5):
+    m = pr.mesh
+    return onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2)
+
+
+CASES = {
+    "m2p2": dict(name="c0", nc=8, M=2, p=2, sigma=0.4, sub=(2, 2)),
+    "m4p3": dict(name="c4", nc=9, sub=(2, 2)),                  # P = 35, L2 = 210
+    "jit_m2p3": dict(name="jit", nc=10, M=2, p=3, sub=(2, 2)),  # jittered, P = 10, L2 = 28
+    "det": dict(name="c0", nc=10, M=0, p=0, sub=(2, 2)),        # P = 1
+}
+
+
+def _problem(case):
+    kw = dict(CASES[case])
+    return make_problem(kw.pop("name"), **kw)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_residual_and_jacobian_match_oracle(case):
+    _cuda()
+    pr = _problem(case)
+    onl_pr = _oracle(pr)
+    rng = np.random.default_rng(7)
+    U = 0.4 * rng.standard_normal((onl_pr.n, onl_pr.P))
+    V = rng.standard_normal((onl_pr.n, onl_pr.P))
+    with GpuNewton(pr) as g:
+        R = _host(g.residual(_dev(U)), U.shape)
+        JV = _host(g.jac_apply(_dev(V)), V.shape)
+        rowptr, col, k1, jac = B.sg_nl_export(g.nl)
+    R_ref = onl_pr.residual(U)
+    assert _rel(R, R_ref) < 1e-12
+    J = onl_pr.jacobian(U)
+    assert _rel(JV, (J @ V.ravel()).reshape(V.shape)) < 1e-12
+    # K1's gamma = 0 term is the mean-coefficient stiffness
+    Km = onl_pr.mean_stiffness(U).toarray()
+    K0 = np.zeros_like(Km)
+    for a in range(pr.mesh.n):
+        K0[a, col[rowptr[a]:rowptr[a + 1]]] = k1[rowptr[a]:rowptr[a + 1], 0]
+    assert _rel(K0, Km) < 1e-12
+
+
+def test_jacobian_at_zero_is_the_linear_operator():
+    """kappa(0) = 1, kappa'(0) = 0: J(0) = sum_i K_i (x) G_i of the linear problem."""
+    _cuda()
+    pr = make_problem("c4", nc=23, sub=(3, 5))
+    X = torch.randn(pr.mesh.n * 35, dtype=torch.float64, device="cuda")
+    with GpuNewton(pr) as g, GpuSG(pr, coarse="none") as lin:
+        g.residual(g.new_vec())
+        Y = g.jac_apply(X)
+        Y_lin = lin.new_vec()
+        B.sg_matvec(lin.op, X, Y_lin)
+        torch.cuda.synchronize()
+        assert float((Y - Y_lin).abs().max() / Y_lin.abs().max()) < 1e-13
+
+
+def test_full_size_residual_and_jacobian_properties():
+    """Config-4 size (N_c = 128, P = 35): the residual on sampled rows against
+    the oracle restricted to the elements touching them, and J V against a
+    central difference of the GPU residual."""
+    _cuda()
+    pr = make_problem("c4")
+    m = pr.mesh
+    rng = np.random.default_rng(3)
+    U = 0.3 * rng.standard_normal((m.n, 35))
+    V = rng.standard_normal((m.n, 35))
+    eps = 1e-5
+    with GpuNewton(pr) as g:
+        Ud, Vd = _dev(U), _dev(V)
+        Rp = g.residual(Ud + eps * Vd)
+        Rm = g.residual(Ud - eps * Vd)
+        R = g.residual(Ud)
+        JV = _host(g.jac_apply(Vd), V.shape)
+        R = _host(R, U.shape)
+        fd = _host(-(Rp - Rm) / (2 * eps), V.shape)
+    assert _rel(JV, fd) < 1e-7
+    # sampled rows: the oracle on the sub-mesh of the elements at those nodes
+    rows = rng.choice(m.n, 24, replace=False)
+    vert = np.flatnonzero(np.isin(m.dof, rows))
+    els = np.flatnonzero(np.isin(m.tri, vert).any(axis=1))
+    full = _oracle(pr)
+    sub = onl.NLProblem(xy=m.xy, tri=m.tri[els], dof=m.dof, n=m.n, coef=full.coef[:, els],
+                        alpha=full.alpha, L=full.L, P=full.P, a2=0.5)
+    R_ref = sub.residual(U)
+    assert _rel(R[rows], R_ref[rows]) < 1e-12
+
+
+@pytest.mark.parametrize("case,coarse", [("m2p2", "amg"), ("m4p3", "amg"), ("jit_m2p3", "mean"),
+                                         ("det", "amg")])
+def test_newton_matches_oracle(case, coarse):
+    _cuda()
+    pr = _problem(case)
+    onl_pr = _oracle(pr)
+    U_ref, info_ref = onl.newton(onl_pr, tol=1e-12)
+    assert info_ref.converged
+    with GpuNewton(pr, coarse=coarse) as g:
+        U, info = g.solve(tol=1e-12, restart=30)
+        U = _host(U, U_ref.shape)
+    assert info["converged"], info
+    assert info["relres"] <= 1e-12
+    assert abs(info["steps"] - info_ref.steps) <= 1
+    assert _rel(U, U_ref) < 1e-8
+    # the GPU iterate's residual, by the oracle
+    r = np.linalg.norm(onl_pr.residual(U)) / np.linalg.norm(onl_pr.F)
+    assert r < 1e-11
+    h = info["history"]
+    assert len(h) == info["steps"] + 1 and np.all(np.diff(h) < 0)
+
+
+def test_newton_config4_converges_and_is_reproducible():
+    """The benchmark workload: N_c = 128, M = 4, P = 35, 8 x 8 subdomains,
+    FGMRES(50) with RAS + SA-AMG, to ||R||/||F|| <= 1e-8."""
+    _cuda()
+    pr = make_problem("c4")
+    with GpuNewton(pr) as g:
+        U1, info = g.solve(tol=1e-8)
+        U2, info2 = g.solve(tol=1e-8)
+        assert info["converged"] and info["relres"] <= 1e-8
+        assert info["steps"] <= 10 and info["last_lambda"] == 1.0
+        assert torch.equal(U1, U2)
+        # quadratic tail: the last step at least squares the relative residual (up to 1e2)
+        h = info["history"]
+        assert h[-1] < max(1e2 * h[-2] ** 2, 1e-2 * h[-2])
+        R = g.residual(U1)
+        rel = float(torch.linalg.norm(R)) / float(np.linalg.norm(_oracle(pr).F))
+        assert rel <= 1e-8
+
+
+def test_backtracking_from_a_poor_guess():
+    """From a rough random guess the full Newton step overshoots (the oracle
+    cuts lambda to 1/4 at its first step): the iteration still converges to
+    the same solution."""
+    _cuda()
+    pr = _problem("m2p2")
+    onl_pr = _oracle(pr)
+    U0 = np.random.default_rng(0).standard_normal((onl_pr.n, onl_pr.P))
+    U_ref, info_ref = onl.newton(onl_pr, U0=U0, tol=1e-12)
+    assert info_ref.converged and min(info_ref.lambdas) < 1.0
+    with GpuNewton(pr) as g:
+        U, info = g.solve(U0=_dev(U0), tol=1e-12, restart=30)
+        U = _host(U, U_ref.shape)
+    assert info["converged"]
+    assert _rel(U, U_ref) < 1e-8
+
+
+def test_newton_rejects_bad_arguments():
+    _cuda()
+    pr = _problem("m2p2")
+    with GpuNewton(pr) as g:
+        with pytest.raises(B.SgError):
+            g.solve(tol=-1.0)
+        with pytest.raises(B.SgError):
+            g.solve(eta_max=1.5)
+        small = torch.empty(16, dtype=torch.float64, device="cuda")
+        with pytest.raises(B.SgError):
+            B.newton_solve(g.nl, g.owner, g.n_sub, g.overlap, B.SG_FP64, B.SG_COARSE_AMG,
+                           g.new_vec(), small)

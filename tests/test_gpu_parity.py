@@ -64,26 +64,8 @@ CASES = {
 def _problem(key):
     kw = dict(CASES[key])
     name = kw.pop("name")
-    if name == "c3":
-        kw["sub"] = kw.get("sub")
-        from paper_2310_14649_amd.inputs import structured_partition
-        pr = make_problem("c0", nc=kw["nc"], M=6, p=3, sigma=0.5, ell=0.2, sub=kw["sub"],
-                          overlap=2)
-        from paper_2310_14649_amd.inputs import jittered_mesh, kl_fields
-        mesh = jittered_mesh(kw["nc"], amp=0.3, seed=0)
-        g, _, _ = kl_fields(mesh.centroids(), 6, 0.5, 0.2)
-        pr.mesh = mesh
-        pr.g = g
-        pr.g0 = np.zeros(mesh.n_tri)
-        return pr
     if name == "jit":
-        from paper_2310_14649_amd.inputs import jittered_mesh, kl_fields
-        pr = make_problem("c1", nc=kw["nc"], M=kw["M"], p=kw["p"], sub=kw["sub"])
-        mesh = jittered_mesh(kw["nc"], amp=0.3, seed=3)
-        pr.g, _, _ = kl_fields(mesh.centroids(), kw["M"], 0.5, 0.2)
-        pr.mesh = mesh
-        pr.g0 = np.zeros(mesh.n_tri)
-        return pr
+        kw["seed"] = 3
     return make_problem(name, **kw)
 
 
