@@ -136,6 +136,11 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * ---------------------------------------------------------------------- */
 int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap,
               sg_prec prec, sg_ras** out, void* stream);
+/* Refactor with the current values of op, which must have the pattern the
+ * ras was built for (e.g. the same op after its values changed, as in each
+ * Newton step).  Synchronous.  Errors: SG_ERR_INVALID_ARG on a pattern
+ * mismatch, SG_ERR_NUMERIC on a non-positive pivot. */
+int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
 /* host outputs (any may be NULL): number of local nodes per subdomain
  * [n_sub], number of level sets per subdomain [n_sub], and the total bytes
  * of stored Schur-complement inverses. */

@@ -73,6 +73,7 @@ _SIGS = {
     "sg_destroy_op": (None, [_vp]),
     "sg_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
     "ras_setup": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
+    "ras_refactor": (C.c_int, [_vp, _vp, _vp]),
     "ras_info": (C.c_int, [_vp, _i32p, _i32p, _i64p]),
     "ras_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_destroy_ras": (None, [_vp]),
@@ -232,6 +233,10 @@ def ras_setup(op, owner: np.ndarray, n_sub: int, overlap: int, prec: int = SG_FP
     _check(lib().ras_setup(op, _ptr(owner, C.c_int32), n_sub, overlap, prec, C.byref(h),
                            _stream(stream)))
     return h
+
+
+def ras_refactor(r, op, stream=None):
+    _check(lib().ras_refactor(r, op, _stream(stream)))
 
 
 def ras_info(r, n_sub: int):

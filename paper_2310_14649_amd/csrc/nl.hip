@@ -444,11 +444,14 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             // preconditioner of the current Jacobian
             t0 = clock::now();
             amg.reset();
-            ras.reset();
-            sg_ras* r = nullptr;
-            check_status(ras_setup(nl->j1.get(), owner, n_sub, overlap, prec, &r, stream),
-                         "ras_setup");
-            ras.reset(r);
+            if (!ras) {
+                sg_ras* r = nullptr;
+                check_status(ras_setup(nl->j1.get(), owner, n_sub, overlap, prec, &r, stream),
+                             "ras_setup");
+                ras.reset(r);
+            } else {
+                check_status(ras_refactor(ras.get(), nl->j1.get(), stream), "ras_refactor");
+            }
             if (coarse != SG_COARSE_NONE) {
                 sg_amg* a = nullptr;
                 check_status(amg_setup(nl->jac.get(), ras.get(), coarse, prec, &a, stream),

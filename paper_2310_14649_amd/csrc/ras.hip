@@ -35,6 +35,10 @@ struct sg_ras {
     sg::DevBuf<double> lval, sinv64, zs, afact, prev_val, next_val;
     sg::DevBuf<float> sinv32;
     sg::DevBuf<uint16_t> sinv16;
+    // operator entries behind the local values (for refactorisation)
+    int64_t op_nnz = 0;
+    int op_L = 0;
+    sg::DevBuf<int64_t> lent, prev_ent, next_ent;
 };
 
 namespace sg {
@@ -567,6 +571,44 @@ int bfs_levels(const std::vector<std::vector<int>>& adj, int start,
 }  // namespace
 }  // namespace sg
 
+namespace sg {
+namespace {
+
+// Gather the gamma = 0 values of the subdomain matrices from op and factor
+// them (block-tridiagonal Schur complements, explicit inverses).
+void ras_factor_values(sg_ras* r, const sg_op* op, hipStream_t s) {
+    r->op_L = op->L;
+    const int64_t mm = (int64_t)r->lent.n;
+    if (mm)
+        gather_k0_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(mm, op->L, r->lent.p,
+                                                                       op->vals.p, r->lval.p);
+    HIP_LAUNCH_OK();
+    const int64_t mc = (int64_t)r->prev_ent.n;
+    if (mc) {
+        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, r->prev_ent.p,
+                                                                       op->vals.p, r->prev_val.p);
+        HIP_LAUNCH_OK();
+        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, r->next_ent.p,
+                                                                       op->vals.p, r->next_val.p);
+        HIP_LAUNCH_OK();
+    }
+    DevBuf<int> d_status(1);
+    HIP_OK(hipMemsetAsync(d_status.p, 0, sizeof(int), s));
+    const size_t lds = (size_t)2 * kMaxLevel * kMaxLevel * sizeof(double);
+    ras_factor_kernel<<<r->n_sub, kRasThreads, lds, s>>>(
+        r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p,
+        r->lrow_ptr.p, r->lcol.p, r->lval.p, r->sinv64.p, r->sinv32.p, r->sinv16.p, (int)r->prec,
+        d_status.p);
+    HIP_LAUNCH_OK();
+    int status = 0;
+    d_status.download(&status, 1, s);
+    HIP_OK(hipStreamSynchronize(s));
+    if (status) SG_THROW(SG_ERR_NUMERIC, "non-positive pivot in a subdomain factorisation");
+}
+
+}  // namespace
+}  // namespace sg
+
 using namespace sg;
 
 extern "C" {
@@ -762,37 +804,23 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         r->lrow_ptr.upload(lrow_ptr, s);
         r->lcol.upload(lcol, s);
         r->afact.upload(op->h_afact, s);
-        DevBuf<int64_t> d_lent;
-        d_lent.upload(lent, s);
-        r->lval.alloc(lent.size());
-        int64_t mm = (int64_t)lent.size();
-        gather_k0_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(mm, op->L, d_lent.p,
-                                                                       op->vals.p, r->lval.p);
-        HIP_LAUNCH_OK();
         r->prev_idx.upload(prev_idx, s);
         r->next_idx.upload(next_idx, s);
-        DevBuf<int64_t> d_pe, d_ne;
-        d_pe.upload(prev_ent, s);
-        d_ne.upload(next_ent, s);
-        int64_t mc = (int64_t)prev_ent.size();
-        r->prev_val.alloc(mc);
-        r->next_val.alloc(mc);
-        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, d_pe.p, op->vals.p,
-                                                                       r->prev_val.p);
-        HIP_LAUNCH_OK();
-        gather_k0_kernel<<<(unsigned)((mc + 255) / 256), 256, 0, s>>>(mc, op->L, d_ne.p, op->vals.p,
-                                                                       r->next_val.p);
-        HIP_LAUNCH_OK();
+        r->lent.upload(lent, s);
+        r->prev_ent.upload(prev_ent, s);
+        r->next_ent.upload(next_ent, s);
+        r->op_nnz = op->nnz;
+        r->lval.alloc(lent.size());
+        r->prev_val.alloc(prev_ent.size());
+        r->next_val.alloc(prev_ent.size());
         r->sinv64.alloc(sinv_count);
         if (prec == SG_FP32) r->sinv32.alloc(sinv_count);
         if (prec == SG_BF16) r->sinv16.alloc(sinv_count);
         r->zs.alloc((size_t)r->total_local * r->P);
-        DevBuf<int> d_status(1);
-        HIP_OK(hipMemsetAsync(d_status.p, 0, sizeof(int), s));
-        size_t lds = (size_t)2 * kMaxLevel * kMaxLevel * sizeof(double);
         int max_lds = 0;
         HIP_OK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                      op->device));
+        const size_t lds = (size_t)2 * kMaxLevel * kMaxLevel * sizeof(double);
         if ((size_t)max_lds < lds)
             SG_THROW(SG_ERR_UNSUPPORTED, "device offers %d bytes of LDS per block, need %zu",
                      max_lds, lds);
@@ -803,16 +831,20 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
             if ((size_t)max_lds < need)
                 SG_THROW(SG_ERR_UNSUPPORTED, "RAS apply needs %zu bytes of LDS", need);
         }
-        ras_factor_kernel<<<n_sub, kRasThreads, lds, s>>>(
-            r->sub_node_off.p, r->sub_lev_off.p, r->lev_start.p, r->lev_size.p, r->sinv_off.p,
-            r->lrow_ptr.p, r->lcol.p, r->lval.p, r->sinv64.p, r->sinv32.p, r->sinv16.p, (int)prec,
-            d_status.p);
-        HIP_LAUNCH_OK();
-        int status = 0;
-        d_status.download(&status, 1, s);
-        HIP_OK(hipStreamSynchronize(s));
-        if (status) SG_THROW(SG_ERR_NUMERIC, "non-positive pivot in a subdomain factorisation");
+        ras_factor_values(r.get(), op, s);
         *out = r.release();
+        return SG_OK;
+    });
+}
+
+int ras_refactor(sg_ras* r, const sg_op* op, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r && op, "null argument");
+        check_device(op->device);
+        SG_REQUIRE(op->device == r->device, "ras and op on different devices");
+        SG_REQUIRE(op->n == r->n && op->nnz == r->op_nnz && op->P == r->P,
+                   "op does not have the pattern the ras was built for");
+        ras_factor_values(r, op, as_stream(stream));
         return SG_OK;
     });
 }
