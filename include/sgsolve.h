@@ -277,6 +277,9 @@ int sg_nl_jac_apply(const sg_nl* nl, const double* X, double* Y, void* stream);
 int sg_nl_export(const sg_nl* nl, int64_t* rowptr, int32_t* col, double* k1, double* jac);
 const sg_op* sg_nl_mean_op(const sg_nl* nl);
 const sg_op* sg_nl_jac_op(const sg_nl* nl);
+/* New input coefficient fields (g0 [n_tri], g [M][n_tri], host) on the same
+ * mesh and basis: only the element coefficients are recomputed.  Synchronous. */
+int sg_nl_set_coefficients(sg_nl* nl, const double* g0, const double* g, void* stream);
 void sg_destroy_nl(sg_nl* nl);
 
 /* ------------------------------------------------------------------------
@@ -289,6 +292,8 @@ void sg_destroy_nl(sg_nl* nl);
  *   lambda = 1, halved (at most 9 times) until
  *   ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R_k||, the last trial taken
  *   otherwise;  U += lambda d.
+ * The forcing term is safeguarded against over-solving the last steps:
+ * eta_k = min(eta_max, max(eta_k, 0.5 tol ||F|| / ||R_k||)).
  * Stops when ||R|| / ||F|| <= tol (||F|| = norm of F e_0).  ws: device
  * workspace of newton_workspace_bytes(nl, n_sub, coarse, restart) bytes.
  * Returns SG_OK, SG_NOT_CONVERGED (max_steps reached) or an error.
@@ -321,6 +326,59 @@ size_t newton_workspace_bytes(const sg_nl* nl, int n_sub, sg_coarse_kind coarse,
 int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_prec prec,
                  sg_coarse_kind coarse, double* U, const sg_newton_opts* opts,
                  sg_newton_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * newton_guess -- initial guess for newton_solve from a predicted field
+ * U_pred (device [n x P], e.g. the output of nn_forward).  Three damped
+ * Jacobi sweeps (omega 0.6, the mean-coefficient diagonal K1_0[a,a] k!)
+ * smooth U_pred into U_s; with W_d its part on the chaos modes of total
+ * degree d (d = 0..p), one Gauss-Newton step restricted to span{W_d} gives
+ * U_proj = sum_d (1 + beta_d) W_d, beta minimising
+ * ||R(U_s) - J(U_s) sum_d beta_d W_d||; the better of U_s and U_proj is
+ * the smoothed candidate.  U0 (device) receives the candidate with the
+ * smallest residual among the zero guess, U_pred and the smoothed one, so
+ * Newton never starts from a larger residual than with the zero guess.
+ * relres (host [3], may be NULL): ||R|| / ||F|| of the three candidates;
+ * choice: 0 = zero, 1 = prediction, 2 = smoothed.
+ * ws: newton_guess_workspace_bytes(nl) bytes of device memory.  Synchronous.
+ * ---------------------------------------------------------------------- */
+size_t newton_guess_workspace_bytes(const sg_nl* nl);
+int newton_guess(sg_nl* nl, const double* U_pred, double* U0, double* relres, int* choice,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned predictor: a convolutional network on a W x H vertex grid (the
+ * project's own design; the paper has no learned component).  NHWC layout
+ * (sample, y, x, channel).  n_layers 3x3 convolutions with zero padding,
+ * channels[0] -> channels[1] -> ... -> channels[n_layers] (each <= 64), ReLU
+ * between layers:
+ *   Z_l = conv3x3(A_{l-1}, W_l) + b_l,  A_l = max(Z_l, 0),  O = Z_L,
+ *   U[s, y, x, k] = env[y, x] * oscale[k] * O[s, y, x, k].
+ * Convolutions run on the matrix cores with BF16 operands and FP32
+ * accumulation; weights are FP32 master copies updated by Adam.
+ * Parameters are one FP32 vector: W_1 [3][3][c_0][c_1], b_1 [c_1], W_2, ...
+ * (C order).  The loss of nn_loss_grad is mean (env O - T / oscale)^2 over
+ * all samples, pixels and the c_L output channels.
+ * nn_create: device buffers for up to max_batch samples; parameters zero.
+ * nn_set_params: host FP32 parameters, resets the Adam state.
+ * nn_get_params: host copies of the parameters and of the last gradient
+ *   (either may be NULL).
+ * nn_set_output_map: host env [H*W] and oscale [c_L].
+ * nn_forward: X device FP64 [B,H,W,c_0] -> U device FP64 [B,H,W,c_L].
+ * nn_loss_grad: X and T (device FP64 [B,H,W,c_L]) -> loss (host) and the
+ *   gradient kept for nn_adam_step.  Synchronous.
+ * nn_adam_step: one Adam update (bias-corrected) with the last gradient.
+ * ---------------------------------------------------------------------- */
+typedef struct sg_nn sg_nn;
+int nn_create(int n_layers, const int32_t* channels, int H, int W, int max_batch, sg_nn** out);
+int64_t nn_param_count(const sg_nn* nn);
+int nn_set_params(sg_nn* nn, const float* params);
+int nn_get_params(const sg_nn* nn, float* params, float* grads);
+int nn_set_output_map(sg_nn* nn, const float* env, const float* oscale);
+int nn_forward(sg_nn* nn, const double* X, int B, double* U, void* stream);
+int nn_loss_grad(sg_nn* nn, const double* X, const double* T, int B, double* loss, void* stream);
+int nn_adam_step(sg_nn* nn, float lr, float beta1, float beta2, float eps, void* stream);
+void nn_destroy(sg_nn* nn);
 
 #ifdef __cplusplus
 }

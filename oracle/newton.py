@@ -23,8 +23,10 @@ The integrands are polynomials in xi of degree <= 2 + 2*2p + p + p = 14 for
 p = 3, so a tensor Gauss-Hermite rule with 8 points per variable evaluates
 the expectations exactly (up to rounding).
 
-Newton: eta_k = max(1e-12, min(1e-2, ||R_k||/||F||)) (||F|| replaced by the
-initial residual when F = 0); backtracking tries lambda = 1, 1/2, ...,
+Newton: eta_k = max(1e-12, min(1e-2, ||R_k||/||F||)), raised to at least
+0.5 tol ||F|| / ||R_k|| (capped at 1e-2) so that the last correction is not
+solved beyond the final tolerance (||F|| replaced by the initial residual
+when F = 0); backtracking tries lambda = 1, 1/2, ...,
 1/512 until ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R(U)|| and takes the
 last trial if none passes; stop when ||R||/||F|| <= tol.
 """
@@ -199,6 +201,8 @@ def newton(pr: NLProblem, U0: Optional[np.ndarray] = None, tol: float = 1e-8,
             break
         J = pr.jacobian(U)
         eta = max(1e-12, min(1e-2, rn / Fn))
+        # no more accuracy than the final tolerance needs
+        eta = min(1e-2, max(eta, 0.5 * tol * Fn / rn))
         if linear_solve is None:
             d = spla.spsolve(J.tocsc(), R.ravel()).reshape(R.shape)
             its = 0

@@ -100,6 +100,18 @@ _SIGS = {
     "sg_nl_mean_op": (_vp, [_vp]),
     "sg_nl_jac_op": (_vp, [_vp]),
     "sg_destroy_nl": (None, [_vp]),
+    "sg_nl_set_coefficients": (C.c_int, [_vp, _f64p, _f64p, _vp]),
+    "newton_guess_workspace_bytes": (C.c_size_t, [_vp]),
+    "newton_guess": (C.c_int, [_vp, _vp, _vp, _f64p, C.POINTER(C.c_int), _vp, C.c_size_t, _vp]),
+    "nn_create": (C.c_int, [C.c_int, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)]),
+    "nn_param_count": (C.c_int64, [_vp]),
+    "nn_set_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "nn_get_params": (C.c_int, [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "nn_set_output_map": (C.c_int, [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "nn_forward": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
+    "nn_loss_grad": (C.c_int, [_vp, _vp, _vp, C.c_int, _f64p, _vp]),
+    "nn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "nn_destroy": (None, [_vp]),
     "newton_workspace_bytes": (C.c_size_t, [_vp, C.c_int, C.c_int, C.c_int]),
     "newton_solve": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
                                C.POINTER(NewtonOpts), C.POINTER(NewtonStats), _vp, C.c_size_t,
@@ -404,3 +416,73 @@ def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coa
                 ms_total=st.ms_total, ms_eval=st.ms_eval, ms_setup=st.ms_setup,
                 ms_krylov=st.ms_krylov, history=hist[:h].copy(),
                 krylov_its_per_step=kits[:max(h - 1, 0)].copy())
+
+
+def sg_nl_set_coefficients(nl, g0: np.ndarray, g: np.ndarray, stream=None):
+    g0 = np.ascontiguousarray(g0, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    gp = _ptr(g, C.c_double) if g.size else None
+    _check(lib().sg_nl_set_coefficients(nl, _ptr(g0, C.c_double), gp, _stream(stream)))
+
+
+def newton_guess_workspace_bytes(nl) -> int:
+    return int(lib().newton_guess_workspace_bytes(nl))
+
+
+def newton_guess(nl, U_pred, U0, ws, stream=None):
+    rel = np.zeros(3, dtype=np.float64)
+    ch = C.c_int()
+    _check(lib().newton_guess(nl, _dev(U_pred), _dev(U0), _ptr(rel, C.c_double), C.byref(ch),
+                              _dev(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return ch.value, rel
+
+
+# ---------------------------------------------------------------- learned predictor
+def nn_create(channels, H: int, W: int, max_batch: int):
+    ch = np.ascontiguousarray(channels, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().nn_create(len(ch) - 1, _ptr(ch, C.c_int32), H, W, max_batch, C.byref(h)))
+    return h
+
+
+def nn_param_count(nn) -> int:
+    return int(lib().nn_param_count(nn))
+
+
+def nn_set_params(nn, params: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == nn_param_count(nn)
+    _check(lib().nn_set_params(nn, _ptr(p, C.c_float)))
+
+
+def nn_get_params(nn):
+    n = nn_param_count(nn)
+    p = np.zeros(n, dtype=np.float32)
+    g = np.zeros(n, dtype=np.float32)
+    _check(lib().nn_get_params(nn, _ptr(p, C.c_float), _ptr(g, C.c_float)))
+    return p, g
+
+
+def nn_set_output_map(nn, env: np.ndarray, oscale: np.ndarray):
+    e = np.ascontiguousarray(env, dtype=np.float32).ravel()
+    o = np.ascontiguousarray(oscale, dtype=np.float32).ravel()
+    _check(lib().nn_set_output_map(nn, _ptr(e, C.c_float), _ptr(o, C.c_float)))
+
+
+def nn_forward(nn, X, B: int, U, stream=None):
+    _check(lib().nn_forward(nn, _dev(X), B, _dev(U), _stream(stream)))
+
+
+def nn_loss_grad(nn, X, T, B: int, stream=None) -> float:
+    loss = C.c_double()
+    _check(lib().nn_loss_grad(nn, _dev(X), _dev(T), B, C.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def nn_adam_step(nn, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                 stream=None):
+    _check(lib().nn_adam_step(nn, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def nn_destroy(nn):
+    lib().nn_destroy(nn)

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgsolve.so")
 SOURCES = ["triples.hip", "assemble.hip", "matvec.hip", "ras.hip", "coarse.hip", "krylov.hip",
-           "nl.hip"]
+           "nl.hip", "nn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "-fconstexpr-steps=100000000", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

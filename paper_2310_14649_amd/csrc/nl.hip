@@ -48,12 +48,19 @@ struct sg_nl {
     sg::DevBuf<double> inv_gfact;            // 1 / gamma!
     sg::DevBuf<double> w1, yt;               // [n_tri][L2], [n_tri][3][L2]
     sg::DevBuf<double> B;                    // F e_0, [n][P]
+    sg::DevBuf<int32_t> mode_deg;            // total degree of each chaos mode [P]
+    sg_basis basis;                          // the basis of u and c
+    std::vector<double> h_xy;                // mesh (for new coefficient fields)
+    std::vector<int32_t> h_tri;
+    int n_vert = 0;
 };
 
 namespace sg {
 namespace {
 
 constexpr int kWaves = 4;
+constexpr int kGuessSweeps = 3;       // Jacobi sweeps smoothing a predicted guess
+constexpr double kGuessOmega = 0.6;   // their damping
 
 __device__ __forceinline__ void wave_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -176,6 +183,40 @@ __global__ void nl_fill_kernel(int64_t N, double v, double* __restrict__ Y) {
     if (idx < N) Y[idx] = v;
 }
 
+// Y[a, k] = X[a, k] if mode k has total degree d, else 0.
+__global__ void nl_degree_part_kernel(int64_t N, int P, int d, const int32_t* __restrict__ deg,
+                                      const double* __restrict__ X, double* __restrict__ Y) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const int k = (int)(idx % P);
+    Y[idx] = deg[k] == d ? X[idx] : 0.0;
+}
+
+// One damped Jacobi sweep with the mean-coefficient diagonal:
+// X[a, k] += omega R[a, k] / (K1_0[a, a] k!).
+__global__ void nl_jacobi_kernel(int n, int P, int L2, const int32_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ col, const double* __restrict__ k1,
+                                 const double* __restrict__ afact, double omega,
+                                 const double* __restrict__ R, double* __restrict__ X) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * P) return;
+    const int a = (int)(idx / P), k = (int)(idx - (int64_t)a * P);
+    double d = 0.0;
+    for (int e = rowptr[a]; e < rowptr[a + 1]; ++e)
+        if (col[e] == a) d = k1[(size_t)e * L2];
+    if (d > 0.0) X[idx] += omega * R[idx] / (d * afact[k]);
+}
+
+// Y = X + sum_d beta_d W_d, W_d the degree-d part of X (beta on the device).
+__global__ void nl_degree_scale_kernel(int64_t N, int P, const int32_t* __restrict__ deg,
+                                       const double* __restrict__ beta, const double* __restrict__ X,
+                                       double* __restrict__ Y) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const int k = (int)(idx % P);
+    Y[idx] = X[idx] * (1.0 + beta[deg[k]]);
+}
+
 inline unsigned grid1d(int64_t N) { return (unsigned)((N + 255) / 256); }
 
 // Operators sharing the unpruned P1 pattern: the off-diagonal Jacobian
@@ -229,6 +270,7 @@ inline void check_status(int st, const char* what) {
     if (st < 0) SG_THROW(st, "%s: %s", what, sg_last_error());
 }
 
+// R, D, U_trial, R_trial, partial sums, scalars, then the Krylov workspace.
 size_t newton_ws(int n, int P, int n_sub, sg_coarse_kind coarse, int restart) {
     const size_t N = (size_t)n * P;
     const int ns = coarse == SG_COARSE_NONE ? -1 : n_sub;
@@ -321,8 +363,158 @@ int sg_nl_setup(const sg_basis* b, int n_vert, const double* xy, int n_tri, cons
         HIP_LAUNCH_OK();
         nl->w1.alloc((size_t)n_tri * nl->L2);
         nl->yt.alloc((size_t)n_tri * 3 * nl->L2);
+        std::vector<int32_t> deg(b->P, 0);
+        for (int k = 0; k < b->P; ++k)
+            for (int d = 0; d < b->M; ++d) deg[k] += b->alpha[(size_t)k * b->M + d];
+        nl->mode_deg.upload(deg, s);
+        nl->basis = *b;
+        nl->n_vert = n_vert;
+        nl->h_xy.assign(xy, xy + (size_t)n_vert * 2);
+        nl->h_tri.assign(tri, tri + (size_t)n_tri * 3);
         HIP_OK(hipStreamSynchronize(s));
         *out = nl.release();
+        return SG_OK;
+    });
+}
+
+int sg_nl_set_coefficients(sg_nl* nl, const double* g0, const double* g, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(nl != nullptr, "nl is NULL");
+        check_device(nl->device);
+        hipStream_t s = as_stream(stream);
+        element_data(nl->basis, nl->n_vert, nl->h_xy.data(), nl->n_tri, nl->h_tri.data(), g0, g,
+                     nl->ed, s);
+        HIP_OK(hipStreamSynchronize(s));
+        return SG_OK;
+    });
+}
+
+size_t newton_guess_workspace_bytes(const sg_nl* nl) {
+    if (!nl) return 0;
+    const size_t vb = align_up((size_t)nl->n * nl->P * 8);
+    return (size_t)(2 * (nl->p + 1) + 2) * vb + align_up(kMaxRedBlocks * 8) + 512;
+}
+
+int newton_guess(sg_nl* nl, const double* U_pred, double* U0, double* relres, int* choice,
+                 void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(nl && U_pred && U0, "null argument");
+        SG_REQUIRE(U_pred != U0, "U_pred and U0 must not alias");
+        check_device(nl->device);
+        const size_t need = newton_guess_workspace_bytes(nl);
+        if (!ws || ws_bytes < need)
+            SG_THROW(SG_ERR_WORKSPACE, "guess workspace too small (%zu < %zu)", ws_bytes, need);
+        hipStream_t s = as_stream(stream);
+        const int D = nl->p + 1;
+        const int64_t N = (int64_t)nl->n * nl->P;
+        const size_t vb = align_up((size_t)N * 8);
+        char* p = reinterpret_cast<char*>(ws);
+        double* R = reinterpret_cast<double*>(p);
+        double* T = reinterpret_cast<double*>(p + vb);
+        auto Wd = [&](int d) { return reinterpret_cast<double*>(p + (2 + d) * vb); };
+        auto JWd = [&](int d) { return reinterpret_cast<double*>(p + (2 + D + d) * vb); };
+        double* part = reinterpret_cast<double*>(p + (2 + 2 * D) * vb);
+        double* scal = reinterpret_cast<double*>(p + (2 + 2 * D) * vb + align_up(kMaxRedBlocks * 8));
+        double* beta_d = scal + 8;
+        const double fn = std::sqrt(host_dot(N, nl->B.p, nl->B.p, part, scal, s));
+        SG_REQUIRE(fn > 0.0, "the forcing is zero");
+        // residual at the prediction
+        nl_eval(nl, U_pred, R, s);
+        const double r_pred = std::sqrt(host_dot(N, R, R, part, scal, s));
+        // smoothing: damped Jacobi sweeps remove the rough part of the error,
+        // to which the residual is most sensitive
+        double* S = Wd(0);
+        HIP_OK(hipMemcpyAsync(S, U_pred, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        for (int sweep = 0; sweep < kGuessSweeps; ++sweep) {
+            nl_jacobi_kernel<<<grid1d(N), 256, 0, s>>>(nl->n, nl->P, nl->L2, nl->j1->rowptr.p,
+                                                       nl->j1->col.p, nl->j1->vals.p, nl->j1->afact.p,
+                                                       kGuessOmega, R, S);
+            HIP_LAUNCH_OK();
+            nl_eval(nl, S, R, s);
+        }
+        const double r_smooth = std::sqrt(host_dot(N, R, R, part, scal, s));
+        HIP_OK(hipMemcpyAsync(T, S, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(U0, S, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        // Gauss-Newton step restricted to the degree parts of the smoothed field
+        std::vector<double> G((size_t)D * D, 0.0), h(D, 0.0), beta(D, 0.0);
+        for (int d = 0; d < D; ++d) {
+            nl_degree_part_kernel<<<grid1d(N), 256, 0, s>>>(N, nl->P, d, nl->mode_deg.p, T, Wd(d));
+            HIP_LAUNCH_OK();
+            kron_matvec(nl->jac->csr(), nl->L2, nl->jac->tr, Wd(d), JWd(d), 1.0, 0.0, nullptr, s);
+        }
+        for (int d = 0; d < D; ++d) {
+            h[d] = host_dot(N, JWd(d), R, part, scal, s);
+            for (int e = 0; e <= d; ++e)
+                G[(size_t)d * D + e] = G[(size_t)e * D + d] = host_dot(N, JWd(d), JWd(e), part, scal, s);
+        }
+        // Cholesky of the small Gram matrix; degree parts that vanish are skipped
+        std::vector<int> act;
+        for (int d = 0; d < D; ++d)
+            if (G[(size_t)d * D + d] > 0.0) act.push_back(d);
+        const int na = (int)act.size();
+        std::vector<double> A((size_t)na * na), y(na);
+        for (int i = 0; i < na; ++i) {
+            y[i] = h[act[i]];
+            for (int j = 0; j < na; ++j) A[(size_t)i * na + j] = G[(size_t)act[i] * D + act[j]];
+        }
+        bool ok = true;
+        for (int j = 0; j < na && ok; ++j) {
+            double dj = A[(size_t)j * na + j];
+            for (int k = 0; k < j; ++k) dj -= A[(size_t)j * na + k] * A[(size_t)j * na + k];
+            if (!(dj > 1e-14 * A[(size_t)j * na + j])) { ok = false; break; }
+            dj = std::sqrt(dj);
+            A[(size_t)j * na + j] = dj;
+            for (int i = j + 1; i < na; ++i) {
+                double v = A[(size_t)i * na + j];
+                for (int k = 0; k < j; ++k) v -= A[(size_t)i * na + k] * A[(size_t)j * na + k];
+                A[(size_t)i * na + j] = v / dj;
+            }
+        }
+        if (ok) {
+            for (int i = 0; i < na; ++i) {
+                double v = y[i];
+                for (int k = 0; k < i; ++k) v -= A[(size_t)i * na + k] * y[k];
+                y[i] = v / A[(size_t)i * na + i];
+            }
+            for (int i = na - 1; i >= 0; --i) {
+                double v = y[i];
+                for (int k = i + 1; k < na; ++k) v -= A[(size_t)k * na + i] * y[k];
+                y[i] = v / A[(size_t)i * na + i];
+            }
+            for (int i = 0; i < na; ++i) beta[act[i]] = y[i];
+        }
+        HIP_OK(hipMemcpyAsync(beta_d, beta.data(), D * sizeof(double), hipMemcpyHostToDevice, s));
+        double r_proj = NAN;
+        if (ok) {
+            nl_degree_scale_kernel<<<grid1d(N), 256, 0, s>>>(N, nl->P, nl->mode_deg.p, beta_d, T, T);
+            HIP_LAUNCH_OK();
+            nl_eval(nl, T, R, s);
+            r_proj = std::sqrt(host_dot(N, R, R, part, scal, s));
+        }
+        // U0 holds the smoothed field; the projected one replaces it if better
+        double r_sm = r_smooth;
+        if (ok && std::isfinite(r_proj) && r_proj < r_sm) {
+            HIP_OK(hipMemcpyAsync(U0, T, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+            r_sm = r_proj;
+        }
+        // the candidate with the smallest residual; the zero guess has ||R|| = ||F||
+        int c = 0;
+        double best = fn;
+        if (std::isfinite(r_pred) && r_pred < best) { c = 1; best = r_pred; }
+        if (std::isfinite(r_sm) && r_sm < best) { c = 2; best = r_sm; }
+        if (c == 0) {
+            nl_fill_kernel<<<grid1d(N), 256, 0, s>>>(N, 0.0, U0);
+            HIP_LAUNCH_OK();
+        } else if (c == 1) {
+            HIP_OK(hipMemcpyAsync(U0, U_pred, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        if (relres) {
+            relres[0] = 1.0;
+            relres[1] = r_pred / fn;
+            relres[2] = r_sm / fn;
+        }
+        if (choice) *choice = c;
         return SG_OK;
     });
 }
@@ -440,7 +632,10 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
         J.P = nl->P;
         double last_lambda = 0.0;
         while (!converged && steps < opts->max_steps) {
-            const double eta = std::max(1e-12, std::min(opts->eta_max, rn / Fn));
+            // forcing term, safeguarded against solving the correction more
+            // accurately than the final tolerance needs
+            double eta = std::max(1e-12, std::min(opts->eta_max, rn / Fn));
+            eta = std::min(opts->eta_max, std::max(eta, 0.5 * opts->tol * Fn / rn));
             // preconditioner of the current Jacobian
             t0 = clock::now();
             amg.reset();

@@ -198,3 +198,30 @@ def test_newton_rejects_bad_arguments():
         with pytest.raises(B.SgError):
             B.newton_solve(g.nl, g.owner, g.n_sub, g.overlap, B.SG_FP64, B.SG_COARSE_AMG,
                            g.new_vec(), small)
+
+
+def test_ras_refactor_equals_fresh_setup():
+    """Refactoring the RAS of the Newton operator with new values gives the
+    same preconditioner as building it from scratch on those values."""
+    _cuda()
+    pr = _problem("m4p3")
+    rng = np.random.default_rng(5)
+    with GpuNewton(pr) as g:
+        g.residual(g.new_vec())
+        op = B.sg_nl_mean_op(g.nl)
+        r = B.ras_setup(op, pr.owner, pr.n_sub, pr.overlap, B.SG_FP64)
+        try:
+            g.residual(_dev(0.5 * rng.standard_normal((pr.mesh.n, g.P))))
+            B.ras_refactor(r, op)
+            fresh = B.ras_setup(op, pr.owner, pr.n_sub, pr.overlap, B.SG_FP64)
+            try:
+                Rv = torch.randn(pr.mesh.n * g.P, dtype=torch.float64, device="cuda")
+                Z1, Z2 = g.new_vec(), g.new_vec()
+                B.ras_apply(r, Rv, Z1)
+                B.ras_apply(fresh, Rv, Z2)
+                torch.cuda.synchronize()
+                assert torch.equal(Z1, Z2)
+            finally:
+                B.sg_destroy_ras(fresh)
+        finally:
+            B.sg_destroy_ras(r)
