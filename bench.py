@@ -101,6 +101,62 @@ def cpu_baseline(pr, its_gpu: int, sample_its: int):
                 est_solve_ms=per_it * its_gpu * 1e3)
 
 
+def bench_newton(args, torch):
+    """Config 4: Newton-FGMRES to ||R||/||F|| <= 1e-8 from the zero guess on
+    the base draw, then the learned guess: training data from the solver,
+    training, and held-out draws solved from the zero and from the learned
+    guess."""
+    import numpy as np
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.learned import LearnedGuess, draw_params
+    from paper_2310_14649_amd.solver import GpuNewton
+
+    out = {}
+    pr = make_problem("c4")
+    with GpuNewton(pr) as g:
+        U, info = g.solve(tol=1e-8)                      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            U, info = g.solve(tol=1e-8)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out["zero_guess"] = dict(ms=round(ms, 3), steps=info["steps"], krylov_its=info["krylov_its"],
+                             relres=info["relres"], ms_eval=round(info["ms_eval"], 3),
+                             ms_setup=round(info["ms_setup"], 3),
+                             ms_krylov=round(info["ms_krylov"], 3),
+                             its_per_step=info["krylov_its_per_step"].tolist())
+    log(f"[bench] newton c4: {ms:.1f} ms, {info['steps']} steps, {info['krylov_its']} its")
+    if args.learned_draws <= 0:
+        return out
+    lg = LearnedGuess("c4", max_batch=16, seed=0)
+    try:
+        ds = lg.generate(draw_params(args.learned_draws, seed=0))
+        lg.fit_output_scale(ds)
+        losses, t_train = lg.train(ds, steps=args.learned_steps, batch=16, lr=2e-3, lr_final=2e-5)
+        log(f"[bench] learned: {args.learned_draws} solves in {ds.seconds:.1f} s, "
+            f"{args.learned_steps} Adam steps in {t_train:.1f} s, loss {np.mean(losses[-20:]):.3e}")
+        rows = {"zero": [], "nn": []}
+        choices = []
+        for s_, e_ in draw_params(args.learned_heldout, seed=1):
+            for key, use in (("zero", False), ("nn", True)):
+                _, inf = lg.solve(s_, e_, use_nn=use)
+                rows[key].append((inf["steps"], inf["krylov_its"], inf["seconds"] * 1e3))
+                if use:
+                    choices.append(inf["guess_choice"])
+        summary = {k: dict(steps=float(np.mean([r[0] for r in v])),
+                           krylov_its=float(np.mean([r[1] for r in v])),
+                           ms=round(float(np.mean([r[2] for r in v])), 3)) for k, v in rows.items()}
+        out["learned"] = dict(train_draws=args.learned_draws, adam_steps=args.learned_steps,
+                              gen_s=round(ds.seconds, 2), train_s=round(t_train, 2),
+                              final_loss=float(np.mean(losses[-20:])),
+                              heldout=args.learned_heldout, guess_choices=choices, **summary)
+        log(f"[bench] learned guess on {args.learned_heldout} held-out draws: {summary}")
+    finally:
+        lg.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +170,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
+    ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
+    ap.add_argument("--learned-draws", type=int, default=256,
+                    help="training solves for the learned Newton guess (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=1500)
+    ap.add_argument("--learned-heldout", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -184,6 +245,8 @@ def main() -> int:
                          f"({mv_bytes / c['matvec_s'] / 1e9:.2f} GB/s, scipy.sparse single-threaded)"}
         log(f"[bench] cpu oracle: {c['per_it_s']:.2f} s/it")
 
+    newton = bench_newton(args, torch) if args.newton else None
+
     mixed = results[args.mixed]
     out = {
         "metric": "FGMRES time to rel-res 1e-8 (mixed vs FP64 GPU); SG matvec GB/s vs HBM peak",
@@ -214,6 +277,7 @@ def main() -> int:
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
         "omega": omega,
         "cpu_baseline": cpu,
+        "newton_c4": newton,
     }
     for g in solvers.values():
         g.close()

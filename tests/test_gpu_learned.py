@@ -9,7 +9,10 @@ FP64 to a few 1e-3 in relative L2 norm (bound 2e-2).  Each layer the
 gradient passes back through adds one BF16 rounding of the propagated
 gradient and of the weights, and ReLU masks that differ where a
 pre-activation lies within rounding of zero; the bound grows by 1e-2 per
-layer traversed (2e-2 + 1e-2 * depth).  A wrong tap flip, channel
+layer traversed (2e-2 + 1e-2 * depth).  Replaying the oracle's layers on
+operands rounded to BF16 at the same points reproduces the kernels'
+gradients up to FP32 summation order (bound 3e-3), which pins the
+remaining FP64 difference on BF16 rounding.  A wrong tap flip, channel
 transpose or missing mask gives errors of order one.  Adam runs in FP32:
 1e-5 relative to the step.
 """
@@ -32,6 +35,36 @@ def _cuda():
 
 def _rl2(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _bf16(x):
+    """Round to the nearest BF16 (ties to even), as the kernels store operands."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_replay(params, X, T, env, osc):
+    """The oracle's layers evaluated on BF16-rounded operands at the points
+    where the kernels round (weights, inputs, activations, propagated
+    gradients); everything else in FP64."""
+    Pb = [(_bf16(Wt), b) for Wt, b in params]
+    acts = [_bf16(X)]
+    A = acts[0]
+    for l, (Wt, b) in enumerate(Pb):
+        Z = onn.conv3x3(A, Wt, b)
+        if l + 1 < len(Pb):
+            A = _bf16(np.maximum(Z, 0.0))
+            acts.append(A)
+    E = env[None, :, :, None] * Z - T / osc[None, None, None, :]
+    dZ = _bf16(2.0 * env[None, :, :, None] * E / E.size)
+    grads = [None] * len(Pb)
+    for l in range(len(Pb) - 1, -1, -1):
+        dA, dW, db = onn.conv3x3_backward(acts[l], Pb[l][0], dZ)
+        grads[l] = (dW, db)
+        if l > 0:
+            dZ = _bf16(dA * (acts[l] > 0.0))
+    return grads
 
 
 def _setup(channels, H, W, Bn, seed=0):
@@ -82,6 +115,15 @@ def test_forward_and_gradients_match_oracle(channels, H, W, Bn):
             q += nw + nb
         print(f"[learned] gradient rel. L2 per layer (W, b): {errs}", flush=True)
         assert q == g_ref.size
+        # the same rounding replayed on the CPU: only FP32 summation order differs
+        g_bf = onn.flatten(_bf16_replay(params, X, T, env, osc))
+        q = 0
+        for (Wr, br), (gWb, gbb) in zip(params, _bf16_replay(params, X, T, env, osc)):
+            nw, nb = Wr.size, br.size
+            assert _rl2(g[q:q + nw], gWb.ravel()) < 3e-3
+            assert _rl2(g[q + nw:q + nw + nb], gbb) < 3e-3
+            q += nw + nb
+        assert q == g_bf.size
         # Adam with the device gradient against the oracle's update
         p0, _ = B.nn_get_params(nn)
         B.nn_adam_step(nn, 1e-3)
