@@ -170,6 +170,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
+    ap.add_argument("--ras-path", default="auto", choices=["auto", "sweep", "dense"],
+                    help="RAS apply path: autotuned per precision, or forced")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
     ap.add_argument("--learned-draws", type=int, default=256,
                     help="training solves for the learned Newton guess (0: skip)")
@@ -194,12 +196,15 @@ def main() -> int:
     precs = ["fp64", args.mixed] + [p for p in args.also.split(",") if p and p not in ("fp64", args.mixed)]
     solvers = {}
     setup_s = {}
+    ras_paths = {}
     for prec in precs:
         t0 = time.perf_counter()
-        solvers[prec] = GpuSG(pr, prec=prec, coarse="amg")
+        solvers[prec] = GpuSG(pr, prec=prec, coarse="amg", ras_path=args.ras_path)
         torch.cuda.synchronize()
         setup_s[prec] = time.perf_counter() - t0
-        log(f"[bench] setup {prec}: {setup_s[prec]:.2f} s")
+        ras_paths[prec] = dict(path="dense" if B.ras_path_info(solvers[prec].ras)[0] else "sweep",
+                               ms=solvers[prec].ras_ms)
+        log(f"[bench] setup {prec}: {setup_s[prec]:.2f} s, RAS {ras_paths[prec]}")
     g64 = solvers["fp64"]
     n, P, L, nnz = g64.n, g64.P, g64.L, g64.nnz
     T = B.sg_basis_info(g64.basis)[2]
@@ -275,6 +280,7 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "traffic": None},
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
+        "ras_path": ras_paths,
         "omega": omega,
         "cpu_baseline": cpu,
         "newton_c4": newton,

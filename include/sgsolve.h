@@ -141,6 +141,23 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap,
  * Newton step).  Synchronous.  Errors: SG_ERR_INVALID_ARG on a pattern
  * mismatch, SG_ERR_NUMERIC on a non-positive pivot. */
 int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
+/* Apply path.  Sweep (default): the block-tridiagonal forward/backward
+ * sweeps with the stored Schur-complement inverses.  Dense: the rows of the
+ * owned nodes of each local inverse, (R_s K_0 R_s^T)^{-1} restricted to
+ * D_s, formed once by the sweeps on identity blocks (FP64) and stored in the
+ * ras precision; an apply is then one matrix-core product per subdomain
+ * (owned rows x local nodes times local nodes x P), whose bytes scale with
+ * the precision.  Both compute the same operator (up to rounding).
+ * ras_select: 0 = sweep, 1 = dense (built on first use; device memory
+ *   sum_s n_own(s) * n_local(s) entries).  Synchronous.
+ * ras_autotune: builds the dense rows if needed, times `reps` applies of
+ *   each path with HIP events on `stream`, keeps the faster; ms (host [2],
+ *   may be NULL): sweep, dense.  Synchronous.
+ * ras_path_info: current path (1 = dense) and the bytes of the dense rows
+ *   (0 if not built).  A refactorisation rebuilds the dense rows. */
+int ras_select(sg_ras* r, int dense, void* stream);
+int ras_autotune(sg_ras* r, int reps, double* ms, void* stream);
+int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes);
 /* host outputs (any may be NULL): number of local nodes per subdomain
  * [n_sub], number of level sets per subdomain [n_sub], and the total bytes
  * of stored Schur-complement inverses. */

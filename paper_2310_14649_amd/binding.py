@@ -74,6 +74,9 @@ _SIGS = {
     "sg_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
     "ras_setup": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "ras_refactor": (C.c_int, [_vp, _vp, _vp]),
+    "ras_select": (C.c_int, [_vp, C.c_int, _vp]),
+    "ras_autotune": (C.c_int, [_vp, C.c_int, _f64p, _vp]),
+    "ras_path_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i64p]),
     "ras_info": (C.c_int, [_vp, _i32p, _i32p, _i64p]),
     "ras_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_destroy_ras": (None, [_vp]),
@@ -249,6 +252,23 @@ def ras_setup(op, owner: np.ndarray, n_sub: int, overlap: int, prec: int = SG_FP
 
 def ras_refactor(r, op, stream=None):
     _check(lib().ras_refactor(r, op, _stream(stream)))
+
+
+def ras_select(r, dense: bool, stream=None):
+    _check(lib().ras_select(r, 1 if dense else 0, _stream(stream)))
+
+
+def ras_autotune(r, reps: int = 5, stream=None):
+    ms = np.zeros(2, dtype=np.float64)
+    _check(lib().ras_autotune(r, reps, _ptr(ms, C.c_double), _stream(stream)))
+    return float(ms[0]), float(ms[1])
+
+
+def ras_path_info(r):
+    d = C.c_int()
+    nb = C.c_int64()
+    _check(lib().ras_path_info(r, C.byref(d), C.byref(nb)))
+    return bool(d.value), nb.value
 
 
 def ras_info(r, n_sub: int):

@@ -29,6 +29,7 @@ struct sg_ras {
     int64_t total_local = 0, n_lev = 0, sinv_count = 0;
     std::vector<int32_t> h_nlocal, h_nlev, h_owner;
     std::vector<int32_t> h_own_ptr, h_own_nodes;   // owned nodes per subdomain
+    std::vector<int32_t> h_sub_node_off, h_gnode, h_owned;   // local nodes in level order
     sg::DevBuf<int32_t> sub_node_off, sub_lev_off, lev_start, lev_size, gnode, owned, lrow_ptr,
         lcol, prev_idx, next_idx;
     sg::DevBuf<int64_t> sinv_off;
@@ -39,6 +40,21 @@ struct sg_ras {
     int64_t op_nnz = 0;
     int op_L = 0;
     sg::DevBuf<int64_t> lent, prev_ent, next_ent;
+    // dense path: explicit inverse rows of the owned nodes, [n_own(s)][ld(s)]
+    // per subdomain (local columns in level order, ld = nloc padded to 32)
+    bool dense_built = false, use_dense = false;
+    int Pp = 0;                                   // P padded to 16
+    std::vector<int32_t> h_ld, h_nown;
+    std::vector<int64_t> h_aoff, h_xoff;
+    sg::DevBuf<int32_t> own_pos;                  // per local node: owned index or -1
+    sg::DevBuf<int32_t> ld_d, nown_d, node_sub, own_gnode, blk_sub, blk_row0;
+    sg::DevBuf<int64_t> aoff_d, xoff_d, own_off_d;
+    sg::DevBuf<double> ainv64;
+    sg::DevBuf<float> ainv32;
+    sg::DevBuf<uint16_t> ainv16;
+    sg::DevBuf<unsigned char> xg;                 // gathered right-hand sides [s][Pp][ld]
+    int nblk = 0;
+    double ms_sweep = -1.0, ms_dense = -1.0;      // autotuner timings
 };
 
 namespace sg {
@@ -252,7 +268,7 @@ template <> struct Mma<uint16_t> {
 // issued one level ahead (during the previous level's product), and the
 // barriers wait for LDS traffic only, so those loads stay in flight.
 // Z[owned] = beta * Z[owned] + omega * (local solution) / alpha!.
-template <class TS, int KCP, int BM>
+template <class TS, int KCP, int BM, bool SETUP = false>
 __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     int P, int KC, int bmax, int nmax, int lmax, const int32_t* __restrict__ sub_node_off,
     const int32_t* __restrict__ sub_lev_off, const int32_t* __restrict__ lev_start,
@@ -261,7 +277,10 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     const int32_t* __restrict__ owned, const int32_t* __restrict__ prev_idx,
     const double* __restrict__ prev_val, const int32_t* __restrict__ next_idx,
     const double* __restrict__ next_val, const double* __restrict__ afact,
-    const double* __restrict__ R, double* Z, double* __restrict__ zs, double omega, double beta) {
+    const double* __restrict__ R, double* Z, double* __restrict__ zs, double omega, double beta,
+    int qbase = 0, const int32_t* __restrict__ own_pos = nullptr,
+    const int32_t* __restrict__ ainv_ld = nullptr, const int64_t* __restrict__ ainv_off = nullptr,
+    double* __restrict__ ainv = nullptr) {
     using MM = Mma<TS>;
     using YT = typename MM::YT;
     constexpr int KS = MM::KS;
@@ -312,7 +331,9 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
         lmeta[2 * q + 1] = lev_size[lv0 + q];
         loff[q] = sinv_off[lv0 + q];
     }
-    if (tid < 16) lfac[tid] = tid < kc ? omega / afact[k0 + tid] : 0.0;
+    if constexpr (!SETUP) {
+        if (tid < 16) lfac[tid] = tid < kc ? omega / afact[k0 + tid] : 0.0;
+    }
     auto LST = [&](int lv) { return lmeta[2 * (lv - lv0)]; };
     auto LSZ = [&](int lv) { return lmeta[2 * (lv - lv0) + 1]; };
     auto LOF = [&](int lv) { return loff[lv - lv0]; };
@@ -352,7 +373,11 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
             pos(q, cp, c, j);
             if (q < cp * 16 && c < b && j < kc) {
                 const int row = st + c;
-                if (fwd) rv[o] = R[(size_t)gid(row) * P + k0 + j];
+                if constexpr (SETUP) {
+                    if (fwd) rv[o] = (row == qbase + k0 + j) ? 1.0 : 0.0;   // identity columns
+                } else {
+                    if (fwd) rv[o] = R[(size_t)gid(row) * P + k0 + j];
+                }
 #pragma unroll
                 for (int e = 0; e < KCP; ++e) {
                     cidx[o][e] = ci[(size_t)(node0 + row) * kCouple + e];
@@ -371,6 +396,12 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     };
     auto write_out = [&](int row, int k, double x) {
         const int g = lgn[row];
+        if constexpr (SETUP) {
+            const int q = qbase + k0 + k;
+            if (g < 0 && q < nloc)
+                ainv[ainv_off[s] + (int64_t)own_pos[node0 + row] * ainv_ld[s] + q] = x;
+            return;
+        }
         if (g < 0) {
             const size_t o = (size_t)(g & 0x7fffffff) * P + k0 + k;
             const double v = x * lfac[k];
@@ -492,10 +523,186 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     }
 }
 
+// ---------------------------------------------------------------- dense path
+// Right-hand sides of all subdomains, transposed and converted:
+// xg[s][n][q] = R[gnode(s, q)][n] (zero for n >= P and q >= nloc).  One
+// work-group per (subdomain, 64 local nodes), staged through LDS so that the
+// reads of R and the writes of xg are both contiguous.
+template <class TS>
+__global__ __launch_bounds__(256) void dense_gather_kernel(
+    int P, int Pp, const int32_t* __restrict__ sub_node_off, const int32_t* __restrict__ gnode,
+    const int32_t* __restrict__ ld, const int64_t* __restrict__ xoff, const double* __restrict__ R,
+    TS* __restrict__ xg) {
+    __shared__ double tile[64][65];
+    const int s = blockIdx.x, q0 = blockIdx.y * 64;
+    const int node0 = sub_node_off[s], nloc = sub_node_off[s + 1] - node0;
+    if (q0 >= nloc) return;
+    const int nq = min(64, nloc - q0);
+    const int tid = threadIdx.x;
+    const int lds_s = ld[s];
+    TS* out = xg + xoff[s];
+    for (int n0 = 0; n0 < P; n0 += 64) {
+        const int nn = min(64, P - n0);
+        for (int e = tid; e < nq * 64; e += 256) {
+            const int qq = e >> 6, nl = e & 63;
+            tile[qq][nl] = nl < nn ? R[(size_t)gnode[node0 + q0 + qq] * P + n0 + nl] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < nn * 64; e += 256) {
+            const int nl = e >> 6, qq = e & 63;
+            if (qq < nq) out[(size_t)(n0 + nl) * lds_s + q0 + qq] = Mma<TS>::conv(tile[qq][nl]);
+        }
+        __syncthreads();
+    }
+    (void)Pp;
+}
+
+// Z[owned] = beta Z[owned] + omega / n! * (Ainv_s X_s)[own rows]: one wave per
+// 64 owned rows (MT = 4 row tiles of 16) and all P columns (NT tiles of 16),
+// K = local nodes; every right-hand-side fragment loaded serves the four
+// row tiles, and two K steps are in flight.
+constexpr int kDenseRows = 64;       // rows per wave
+template <class TS, int NT>
+__global__ __launch_bounds__(256) void dense_apply_kernel(
+    int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
+    const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
+    const int64_t* __restrict__ aoff, const int64_t* __restrict__ xoff,
+    const int64_t* __restrict__ own_off, const int32_t* __restrict__ own_gnode,
+    const TS* __restrict__ ainv, const TS* __restrict__ xg, const double* __restrict__ afact,
+    double* Z, double omega, double beta) {
+    using Acc = typename Mma<TS>::Acc;
+    constexpr int MT = kDenseRows / 16;
+    // K elements per lane-group load (16 bytes) and per MFMA step
+    constexpr int KL = 16 / sizeof(TS);
+    constexpr int KSTEP = 4 * KL;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x;
+    const int s = blk_sub[b];
+    const int r0 = blk_row0[b] + kDenseRows * wave;
+    const int no = nown[s];
+    if (r0 >= no) return;
+    const int L = ld[s];
+    const int i = lane & 15, g = lane >> 4;
+    const TS* A[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        A[m] = ainv + aoff[s] + (int64_t)min(r0 + 16 * m + i, no - 1) * L + KL * g;
+    const TS* X = xg + xoff[s] + (int64_t)i * L + KL * g;
+    Acc acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
+    auto step = [&](int k) {
+        uint4 av[MT], bv[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = *reinterpret_cast<const uint4*>(A[m] + k);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            bv[t] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (sizeof(TS) == 2) {
+                    sg_bf8 a, bb;
+                    __builtin_memcpy(&a, &av[m], 16);
+                    __builtin_memcpy(&bb, &bv[t], 16);
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[m][t], 0, 0, 0);
+                } else if constexpr (sizeof(TS) == 4) {
+                    float a[4], bb[4];
+                    __builtin_memcpy(a, &av[m], 16);
+                    __builtin_memcpy(bb, &bv[t], 16);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc[m][t], 0, 0, 0);
+                } else {
+                    double a[2], bb[2];
+                    __builtin_memcpy(a, &av[m], 16);
+                    __builtin_memcpy(bb, &bv[t], 16);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc[m][t], 0, 0, 0);
+                }
+            }
+    };
+    int k = 0;
+    for (; k + 2 * KSTEP <= L; k += 2 * KSTEP) {
+        step(k);
+        step(k + KSTEP);
+    }
+    for (; k < L; k += KSTEP) step(k);
+    const int64_t ob = own_off[s];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * m + Mma<TS>::row_of(lane, v);
+                const int n = 16 * t + i;
+                if (r < no && n < P) {
+                    const size_t o = (size_t)own_gnode[ob + r] * P + n;
+                    const double val = omega * (double)acc[m][t][v] / afact[n];
+                    Z[o] = beta != 0.0 ? fma(beta, Z[o], val) : val;
+                }
+            }
+}
+
+__global__ void narrow_kernel(int64_t n, const double* __restrict__ x, float* __restrict__ y32,
+                              uint16_t* __restrict__ y16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (y32) y32[i] = (float)x[i];
+    if (y16) y16[i] = to_bf16((float)x[i]);
+}
+
 }  // namespace
+
+void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, double beta,
+                     hipStream_t s) {
+    int maxn = 0;
+    for (size_t q = 0; q + 1 < r->h_sub_node_off.size(); ++q)
+        maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
+    dim3 gg(r->n_sub, (maxn + 63) / 64);
+    const int NT = r->Pp / 16;
+#define SG_DENSE(TS, BUF)                                                                          \
+    do {                                                                                           \
+        dense_gather_kernel<TS><<<gg, 256, 0, s>>>(r->P, r->Pp, r->sub_node_off.p, r->gnode.p,      \
+                                                   r->ld_d.p, r->xoff_d.p, R,                      \
+                                                   reinterpret_cast<TS*>(r->xg.p));                \
+        HIP_LAUNCH_OK();                                                                           \
+        switch (NT) {                                                                              \
+            SG_DENSE_NT(TS, BUF, 1) SG_DENSE_NT(TS, BUF, 2) SG_DENSE_NT(TS, BUF, 3)                \
+            SG_DENSE_NT(TS, BUF, 4) SG_DENSE_NT(TS, BUF, 5) SG_DENSE_NT(TS, BUF, 6)                \
+            SG_DENSE_NT(TS, BUF, 7) SG_DENSE_NT(TS, BUF, 8)                                        \
+            default: SG_THROW(SG_ERR_UNSUPPORTED, "dense RAS with P=%d", r->P);                   \
+        }                                                                                          \
+        HIP_LAUNCH_OK();                                                                           \
+    } while (0)
+#define SG_DENSE_NT(TS, BUF, N)                                                                    \
+    case N:                                                                                        \
+        dense_apply_kernel<TS, N><<<r->nblk, 256, 0, s>>>(                                          \
+            r->P, r->blk_sub.p, r->blk_row0.p, r->nown_d.p, r->ld_d.p, r->aoff_d.p, r->xoff_d.p,   \
+            r->own_off_d.p, r->own_gnode.p, BUF, reinterpret_cast<const TS*>(r->xg.p), r->afact.p, \
+            Z, omega, beta);                                                                       \
+        break;
+    if (r->prec == SG_FP64)
+        SG_DENSE(double, r->ainv64.p);
+    else if (r->prec == SG_FP32)
+        SG_DENSE(float, r->ainv32.p);
+    else
+        SG_DENSE(uint16_t, r->ainv16.p);
+#undef SG_DENSE_NT
+#undef SG_DENSE
+}
 
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
+    if (r->use_dense) {
+        ras_dense_apply(r, R, Z, omega, beta, s);
+        return;
+    }
     const int nch = (r->P + kColChunk - 1) / kColChunk;
     const int KC = (r->P + nch - 1) / nch;
     dim3 grid(r->n_sub, nch);
@@ -606,12 +813,168 @@ void ras_factor_values(sg_ras* r, const sg_op* op, hipStream_t s) {
     if (status) SG_THROW(SG_ERR_NUMERIC, "non-positive pivot in a subdomain factorisation");
 }
 
+// Explicit inverse rows of the owned nodes of every subdomain: the factored
+// sweeps applied to identity blocks of kSetupCols local columns at a time
+// (FP64), then narrowed to the storage precision.
+constexpr int kSetupCols = 64;
+
+void ras_build_dense(sg_ras* r, hipStream_t s) {
+    const int ns = r->n_sub;
+    r->Pp = (r->P + 15) / 16 * 16;
+    SG_REQUIRE(r->Pp / 16 <= 8, "dense RAS supports P <= 128");
+    if (!r->dense_built) {
+        r->h_ld.assign(ns, 0);
+        r->h_nown.assign(ns, 0);
+        r->h_aoff.assign(ns + 1, 0);
+        r->h_xoff.assign(ns + 1, 0);
+        std::vector<int64_t> own_off(ns + 1, 0);
+        std::vector<int32_t> own_pos(r->h_gnode.size(), -1), own_gnode, node_sub, bsub, brow;
+        for (int q = 0; q < ns; ++q) {
+            const int a0 = r->h_sub_node_off[q], a1 = r->h_sub_node_off[q + 1];
+            int no = 0;
+            for (int a = a0; a < a1; ++a) {
+                node_sub.push_back(q);
+                if (r->h_owned[a]) {
+                    own_pos[a] = no++;
+                    own_gnode.push_back(r->h_gnode[a]);
+                }
+            }
+            r->h_ld[q] = (a1 - a0 + 31) / 32 * 32;
+            r->h_nown[q] = no;
+            r->h_aoff[q + 1] = r->h_aoff[q] + (int64_t)no * r->h_ld[q];
+            r->h_xoff[q + 1] = r->h_xoff[q] + (int64_t)r->Pp * r->h_ld[q];
+            own_off[q + 1] = own_off[q] + no;
+            for (int r0 = 0; r0 < no; r0 += 4 * kDenseRows) {
+                bsub.push_back(q);
+                brow.push_back(r0);
+            }
+        }
+        r->nblk = (int)bsub.size();
+        r->own_pos.upload(own_pos, s);
+        r->ld_d.upload(r->h_ld, s);
+        r->nown_d.upload(r->h_nown, s);
+        r->aoff_d.upload(r->h_aoff, s);
+        r->xoff_d.upload(r->h_xoff, s);
+        r->own_off_d.upload(own_off, s);
+        r->own_gnode.upload(own_gnode, s);
+        r->node_sub.upload(node_sub, s);
+        r->blk_sub.upload(bsub, s);
+        r->blk_row0.upload(brow, s);
+        const size_t ts = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
+        r->xg.alloc((size_t)r->h_xoff[ns] * ts);
+        HIP_OK(hipMemsetAsync(r->xg.p, 0, r->xg.bytes(), s));
+    }
+    const int64_t total = r->h_aoff[ns];
+    r->ainv64.alloc((size_t)total);
+    HIP_OK(hipMemsetAsync(r->ainv64.p, 0, (size_t)total * 8, s));
+    DevBuf<double> zs_tmp((size_t)r->total_local * kSetupCols);
+    int maxn = 0;
+    for (int q = 0; q < ns; ++q) maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
+    const int bmax = r->max_b, nmax = r->max_local;
+    const size_t lds = ras_apply_lds(SG_FP64, bmax, kColChunk, nmax, r->max_levels);
+    dim3 grid(ns, kSetupCols / kColChunk);
+    for (int qb = 0; qb < maxn; qb += kSetupCols) {
+#define SG_SETUP_GO(KCP, BM)                                                                       \
+    ras_apply_kernel<double, KCP, BM, true><<<grid, kRasThreads, lds, s>>>(                         \
+        kSetupCols, kColChunk, bmax, nmax, r->max_levels, r->sub_node_off.p, r->sub_lev_off.p,     \
+        r->lev_start.p, r->lev_size.p, r->sinv_off.p, r->sinv64.p, r->gnode.p, r->owned.p,         \
+        r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p, r->afact.p, nullptr, nullptr,  \
+        zs_tmp.p, 1.0, 0.0, qb, r->own_pos.p, r->ld_d.p, r->aoff_d.p, r->ainv64.p)
+        const bool small = bmax <= 40, narrow = r->max_couple <= 2;
+        if (narrow && small)
+            SG_SETUP_GO(2, 40);
+        else if (narrow)
+            SG_SETUP_GO(2, 64);
+        else if (small)
+            SG_SETUP_GO(4, 40);
+        else
+            SG_SETUP_GO(4, 64);
+#undef SG_SETUP_GO
+        HIP_LAUNCH_OK();
+    }
+    if (r->prec != SG_FP64) {
+        if (r->prec == SG_FP32) r->ainv32.alloc((size_t)total);
+        else r->ainv16.alloc((size_t)total);
+        narrow_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+            total, r->ainv64.p, r->prec == SG_FP32 ? r->ainv32.p : nullptr,
+            r->prec == SG_BF16 ? r->ainv16.p : nullptr);
+        HIP_LAUNCH_OK();
+        HIP_OK(hipStreamSynchronize(s));
+        r->ainv64.release();
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    r->dense_built = true;
+}
+
 }  // namespace
 }  // namespace sg
 
 using namespace sg;
 
 extern "C" {
+
+int ras_select(sg_ras* r, int dense, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r != nullptr, "ras is NULL");
+        check_device(r->device);
+        if (dense && !r->dense_built) ras_build_dense(r, as_stream(stream));
+        r->use_dense = dense != 0;
+        return SG_OK;
+    });
+}
+
+int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r != nullptr, "ras is NULL");
+        SG_REQUIRE(reps >= 1, "reps must be >= 1");
+        check_device(r->device);
+        hipStream_t s = as_stream(stream);
+        if (!r->dense_built) ras_build_dense(r, s);
+        const size_t N = (size_t)r->n * r->P;
+        DevBuf<double> R(N), Z(N);
+        HIP_OK(hipMemsetAsync(R.p, 0, N * 8, s));
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        double ms[2] = {0.0, 0.0};
+        try {
+            for (int path = 0; path < 2; ++path) {
+                r->use_dense = path == 1;
+                ras_apply_ex(r, R.p, Z.p, 1.0, 0.0, s);            // warm-up
+                HIP_OK(hipEventRecord(e0, s));
+                for (int q = 0; q < reps; ++q) ras_apply_ex(r, R.p, Z.p, 1.0, 0.0, s);
+                HIP_OK(hipEventRecord(e1, s));
+                HIP_OK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIP_OK(hipEventElapsedTime(&t, e0, e1));
+                ms[path] = t / reps;
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        r->ms_sweep = ms[0];
+        r->ms_dense = ms[1];
+        r->use_dense = ms[1] < ms[0];
+        if (ms_out) { ms_out[0] = ms[0]; ms_out[1] = ms[1]; }
+        return SG_OK;
+    });
+}
+
+int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r != nullptr, "ras is NULL");
+        if (dense) *dense = r->use_dense ? 1 : 0;
+        if (dense_bytes) {
+            const int64_t per = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
+            *dense_bytes = r->dense_built ? r->h_aoff[r->n_sub] * per : 0;
+        }
+        return SG_OK;
+    });
+}
 
 int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_prec prec,
               sg_ras** out, void* stream) {
@@ -794,6 +1157,9 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
         r->max_b = max_b;
         SG_REQUIRE(lcol.size() < (size_t)INT32_MAX, "local pattern too large");
 
+        r->h_sub_node_off = sub_node_off;
+        r->h_gnode = gnode;
+        r->h_owned = owned;
         r->sub_node_off.upload(sub_node_off, s);
         r->sub_lev_off.upload(sub_lev_off, s);
         r->lev_start.upload(lev_start, s);
@@ -845,6 +1211,7 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream) {
         SG_REQUIRE(op->n == r->n && op->nnz == r->op_nnz && op->P == r->P,
                    "op does not have the pattern the ras was built for");
         ras_factor_values(r, op, as_stream(stream));
+        if (r->dense_built) ras_build_dense(r, as_stream(stream));
         return SG_OK;
     });
 }

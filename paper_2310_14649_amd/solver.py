@@ -19,7 +19,7 @@ COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_
 class GpuSG:
     def __init__(self, pr: Problem, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
-                 n_sub: Optional[int] = None, stream=None):
+                 n_sub: Optional[int] = None, stream=None, ras_path: str = "sweep"):
         import torch
         self.torch = torch
         self.pr = pr
@@ -39,6 +39,13 @@ class GpuSG:
         self.coarse = coarse
         self.ras = B.ras_setup(self.op, self.owner, self.n_sub, self.overlap, B.PREC[prec],
                                stream=stream)
+        self.ras_ms = None
+        if ras_path == "dense":
+            B.ras_select(self.ras, True, stream=stream)
+        elif ras_path == "auto":
+            self.ras_ms = B.ras_autotune(self.ras, 5, stream=stream)
+        elif ras_path != "sweep":
+            raise ValueError(f"unknown RAS path {ras_path!r}")
         if coarse != "none":
             self.amg = B.amg_setup(self.op, self.ras, COARSE[coarse], B.PREC[prec], stream=stream)
         self._ws = None

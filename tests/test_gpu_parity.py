@@ -182,6 +182,68 @@ def test_ras_low_precision_close_to_oracle(built, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4"])
+def test_ras_dense_path_matches_oracle(built, key):
+    """The explicit-inverse path computes the same operator as the sweeps."""
+    pr, S, g = built(key)
+    subs = _oracle_ras(pr, S)
+    R = np.random.default_rng(15).standard_normal((pr.mesh.n, S.P))
+    Z = g.new_vec()
+    B.ras_select(g.ras, True)
+    try:
+        dense, nbytes = B.ras_path_info(g.ras)
+        assert dense and nbytes > 0
+        B.ras_apply(g.ras, _to_dev(R), Z)
+        assert _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact)) < 1e-10
+        # the damped form used inside the two-grid cycle, against the sweeps
+        omega = 0.5
+        op = g.new_vec()
+        B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op, None)
+        B.ras_select(g.ras, False)
+        op_sweep = g.new_vec()
+        B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op_sweep, None)
+        torch.cuda.synchronize()
+        assert float((op - op_sweep).abs().max() / op_sweep.abs().max()) < 1e-10
+    finally:
+        B.ras_select(g.ras, False)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 6e-2)])
+def test_ras_dense_low_precision_close_to_oracle(built, prec, tol):
+    pr, S, g = built("c1_64", prec=prec)
+    subs = _oracle_ras(pr, S)
+    R = np.random.default_rng(16).standard_normal((pr.mesh.n, S.P))
+    Z = g.new_vec()
+    B.ras_select(g.ras, True)
+    try:
+        B.ras_apply(g.ras, _to_dev(R), Z)
+    finally:
+        B.ras_select(g.ras, False)
+    err = _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact))
+    print(f"[gpu] dense RAS {prec} rel err {err:.3e}")
+    assert err < tol
+
+
+def test_ras_autotune_and_dense_fgmres(built):
+    """The autotuner times both paths and keeps the faster; FGMRES with the
+    dense BF16 local solves still reaches the FP64 solution (mixed path)."""
+    pr, S, _ = built("c1_64")
+    g = GpuSG(pr, prec="bf16", coarse="amg", ras_path="auto")
+    try:
+        ms_sweep, ms_dense = g.ras_ms
+        dense, _ = B.ras_path_info(g.ras)
+        print(f"[gpu] RAS autotune: sweep {ms_sweep:.3f} ms, dense {ms_dense:.3f} ms -> "
+              f"{'dense' if dense else 'sweep'}")
+        assert ms_sweep > 0 and ms_dense > 0 and dense == (ms_dense < ms_sweep)
+        B.ras_select(g.ras, True)
+        x, info = g.solve(pr.restart, 1e-10)
+        assert info["converged"]
+        ref = osg.sg_solve_direct(S.K, S.G, S.B)
+        assert _rel(_to_host(x, ref.shape), ref) < 1e-8
+    finally:
+        g.close()
+
+
 def test_ras_single_subdomain_exact(built):
     pr, S, _ = built("c4_ragged")
     owner = np.zeros(pr.mesh.n, dtype=np.int32)
