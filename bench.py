@@ -170,6 +170,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
+    ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
+                    help="Arnoldi orthogonalisation")
     ap.add_argument("--ras-path", default="auto", choices=["auto", "sweep", "dense"],
                     help="RAS apply path: autotuned per precision, or forced")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
@@ -216,11 +218,13 @@ def main() -> int:
     for prec in precs:
         g = solvers[prec]
         for _ in range(max(args.warmup, 1 if args.graph else 0)):
-            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph))
+            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph),
+                              ortho=args.ortho)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph))
+            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph),
+                              ortho=args.ortho)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         results[prec] = dict(ms=ms, iterations=info["iterations"], relres=info["true_relres"],
@@ -233,6 +237,7 @@ def main() -> int:
         log(f"[bench] solve {prec}: {ms:.2f} ms, its={info['iterations']}, "
             f"relres={info['true_relres']:.2e}")
 
+    mv_kernel = "kron_matvec_spec_kernel"
     mv_mean_ms, mv_med_ms = time_matvec(g64, args.mv_launches, torch)
     mv_bytes = matvec_bytes(n, nnz, L, P)
     mv_gbs = mv_bytes / (mv_mean_ms * 1e-3) / 1e9
@@ -270,13 +275,13 @@ def main() -> int:
                                "9,139,235 unknowns, RAS 16x16 overlap 2 + SA-AMG Nicolaides "
                                "coarse, FGMRES(50) to 1e-8, preconditioner " + args.mixed,
                    "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "ortho": args.ortho},
         "solves": results,
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / mixed["ms"], 3),
         "matvec": {"us": round(mv_mean_ms * 1e3, 2), "median_us": round(mv_med_ms * 1e3, 2),
                    "GBps": round(mv_gbs, 1), "frac_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4),
                    "bytes": mv_bytes, "flops": matvec_flops(n, nnz, L, P, T)},
-        "roofline": {"bound": "hbm", "kernel": "kron_matvec_kernel", "achieved": round(mv_gbs, 1),
+        "roofline": {"bound": "hbm", "kernel": mv_kernel, "achieved": round(mv_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "traffic": None},
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},

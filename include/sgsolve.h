@@ -208,7 +208,7 @@ int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho
 
 /* ------------------------------------------------------------------------
  * fgmres_solve -- right-preconditioned flexible GMRES(m) (the outer solver
- * of Secs. 3-4) in FP64: modified Gram-Schmidt Arnoldi, Givens rotations,
+ * of Secs. 3-4) in FP64: Gram-Schmidt Arnoldi (opts->ortho), Givens rotations,
  * stopping test |g_{j+1}| <= rtol ||b|| (relative to the right-hand side),
  * confirmed by the true residual ||b - A x||; restart from x otherwise.
  * x holds the initial guess on entry and the solution on return (device).
@@ -222,6 +222,14 @@ int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho
  * references the handles' memory and ws, and is dropped when a handle it
  * references is destroyed (sg_graph_cache_clear drops all).
  * ---------------------------------------------------------------------- */
+typedef enum {
+    SG_ORTHO_MGS = 0,       /* modified Gram-Schmidt                         */
+    SG_ORTHO_CGS_DGKS = 1,  /* classical, second pass when ||w|| drops by    */
+                            /* more than 1 - 1/sqrt(2) (Daniel-Gragg-Kaufman-  */
+                            /* Stewart)                                       */
+    SG_ORTHO_CGS = 2        /* classical, one pass                           */
+} sg_ortho;
+
 typedef struct {
     int restart;        /* m (>= 1)                                   */
     int max_it;         /* total Arnoldi steps allowed                */
@@ -230,6 +238,7 @@ typedef struct {
     int use_graph;      /* 1: replay each Arnoldi step as a captured  */
                         /*    HIP graph (captured once per handles,   */
                         /*    workspace, m, omega and step index)     */
+    int ortho;          /* sg_ortho: Arnoldi orthogonalisation         */
 } sg_krylov_opts;
 
 typedef struct {
@@ -324,6 +333,7 @@ typedef struct {
     int max_it;          /* Arnoldi steps per linear solve              */
     double omega;        /* smoother damping (<= 0: estimate per step)  */
     int use_graph;       /* as in sg_krylov_opts                        */
+    int ortho;           /* as in sg_krylov_opts                        */
 } sg_newton_opts;
 
 typedef struct {

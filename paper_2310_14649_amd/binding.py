@@ -19,6 +19,8 @@ SG_OK, SG_NOT_CONVERGED = 0, 1
 SG_FP64, SG_FP32, SG_BF16 = 0, 1, 2
 SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG = 0, 1, 2
 PREC = {"fp64": SG_FP64, "fp32": SG_FP32, "bf16": SG_BF16}
+SG_ORTHO_MGS, SG_ORTHO_CGS_DGKS, SG_ORTHO_CGS = 0, 1, 2
+ORTHO = {"mgs": SG_ORTHO_MGS, "cgs2": SG_ORTHO_CGS_DGKS, "cgs": SG_ORTHO_CGS}
 
 _vp = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
@@ -34,7 +36,7 @@ class SgError(RuntimeError):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_it", C.c_int), ("rtol", C.c_double),
-                ("omega", C.c_double), ("use_graph", C.c_int)]
+                ("omega", C.c_double), ("use_graph", C.c_int), ("ortho", C.c_int)]
 
 
 class KrylovStats(C.Structure):
@@ -46,7 +48,7 @@ class KrylovStats(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
                 ("restart", C.c_int), ("max_it", C.c_int), ("omega", C.c_double),
-                ("use_graph", C.c_int)]
+                ("use_graph", C.c_int), ("ortho", C.c_int)]
 
 
 class NewtonStats(C.Structure):
@@ -345,8 +347,9 @@ def sg_graph_cache_clear() -> int:
 
 
 def fgmres_solve(op, ras, amg, b, x, restart: int, max_it: int, rtol: float, omega: float,
-                 ws, history_cap: int = 4096, use_graph: bool = False, stream=None):
-    opts = KrylovOpts(restart, max_it, rtol, omega, 1 if use_graph else 0)
+                 ws, history_cap: int = 4096, use_graph: bool = False, ortho: str = "mgs",
+                 stream=None):
+    opts = KrylovOpts(restart, max_it, rtol, omega, 1 if use_graph else 0, ORTHO[ortho])
     hist = np.zeros(history_cap, dtype=np.float64)
     st = KrylovStats()
     st.history = _ptr(hist, C.c_double)
@@ -418,9 +421,10 @@ def newton_workspace_bytes(nl, n_sub: int, coarse: int, restart: int) -> int:
 def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coarse: int, U,
                  ws, max_steps: int = 30, tol: float = 1e-8, eta_max: float = 1e-2,
                  restart: int = 50, max_it: int = 1000, omega: float = 0.0,
-                 use_graph: bool = False, history_cap: int = 64, stream=None):
+                 use_graph: bool = False, history_cap: int = 64, ortho: str = "mgs", stream=None):
     owner = np.ascontiguousarray(owner, dtype=np.int32)
-    opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0)
+    opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0,
+                      ORTHO[ortho])
     hist = np.zeros(history_cap, dtype=np.float64)
     kits = np.zeros(history_cap, dtype=np.int32)
     st = NewtonStats()

@@ -2,14 +2,15 @@
 // describes) and right-preconditioned flexible GMRES(m) in FP64 (the outer
 // solver of Secs. 3-4).
 //
-// Arnoldi uses modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i for
-// i = 0..j in order.  Each step of that loop is one kernel that first reduces
-// the previous dot product's per-block partial sums (every block sums them in
-// the same fixed order, so every block sees the same h_ij and results are
-// bitwise reproducible), then updates its slice of w and forms the partial
-// sums of the next dot product in the same pass.  The Hessenberg column, the
-// Givens rotations and the residual estimate stay on the device; the host
-// reads one scalar per iteration.
+// Arnoldi orthogonalisation, selectable: modified Gram-Schmidt (one kernel
+// per basis vector: it reduces the previous dot product's partials, updates
+// w and forms the next partials in the same pass), classical Gram-Schmidt
+// with one conditional reorthogonalisation pass (when the first removed more
+// than 1 - 1/sqrt(2) of ||w||), or single-pass classical Gram-Schmidt; the
+// classical variants read the basis twice per pass instead of streaming w
+// once per basis vector.  All reductions sum per-block partials in a fixed
+// order, so results are bitwise reproducible.  The Hessenberg column, the Givens rotations and the residual
+// estimate stay on the device; the host reads one scalar per iteration.
 #include "common.hpp"
 
 #include <chrono>
@@ -87,6 +88,108 @@ __global__ __launch_bounds__(kVT) void mgs_kernel(int64_t N, int nb, double* __r
     }
     double s = block_sum(a, sh);
     if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+}
+
+// ---- classical Gram-Schmidt with one conditional reorthogonalisation
+// (Daniel-Gragg-Kaufman-Stewart criterion: a second pass when the first
+// removes more than 1 - 1/sqrt(2) of ||w||).  Per pass: one kernel forms
+// the partial sums of <w, v_i> for all i (and <w, w>), one reduces them in a
+// fixed order, one subtracts sum_i h_i v_i; so w and the basis are read
+// twice per pass instead of once per basis vector.
+constexpr int kCgsIB = 16;      // basis vectors per work-group column of the dot kernel
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// part[i * nb + block] = partial <w, v_{i0+i}> (i < ni, this column's share)
+// and, in column 0, part[ni * nb + block] = partial <w, w>.  Skipped unless
+// *active (a null pointer means always).
+__global__ __launch_bounds__(kVT) void cgs_dot_kernel(int64_t N, int nb, int ni, int64_t ldv,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ V,
+                                                      double* __restrict__ part,
+                                                      const double* __restrict__ active) {
+    if (active && active[0] == 0.0) return;
+    __shared__ double sh[kVT / 64][kCgsIB + 1];
+    const int ib0 = blockIdx.y * kCgsIB;
+    const int cnt = min(kCgsIB, ni - ib0);
+    const bool with_ww = blockIdx.y == 0;
+    double acc[kCgsIB + 1];
+#pragma unroll
+    for (int q = 0; q <= kCgsIB; ++q) acc[q] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        const double we = w[e];
+#pragma unroll
+        for (int q = 0; q < kCgsIB; ++q)
+            if (q < cnt) acc[q] = fma(we, V[(size_t)(ib0 + q) * ldv + e], acc[q]);
+        if (with_ww) acc[kCgsIB] = fma(we, we, acc[kCgsIB]);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q <= kCgsIB; ++q) {
+        const double t = wave_sum(acc[q]);
+        if (lane == 0) sh[wv][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kCgsIB) {
+        const int q = threadIdx.x;
+        double t = 0.0;
+        for (int u = 0; u < kVT / 64; ++u) t += sh[u][q];
+        if (q < cnt) part[(size_t)(ib0 + q) * nb + blockIdx.x] = t;
+        if (q == kCgsIB && with_ww) part[(size_t)ni * nb + blockIdx.x] = t;
+    }
+}
+
+// One work-group per coefficient: out[i] (+)= sum over blocks of part[i],
+// fixed order.  i = ni is <w, w> (written to ww).  Skipped unless *active.
+__global__ __launch_bounds__(kVT) void cgs_reduce_kernel(int nb, int ni, const double* __restrict__ part,
+                                                         double* __restrict__ h, int accumulate,
+                                                         double* __restrict__ ww,
+                                                         const double* __restrict__ active) {
+    if (active && active[0] == 0.0) return;
+    __shared__ double sh[kVT];
+    const int i = blockIdx.x;
+    const double t = reduce_partials(part + (size_t)i * nb, nb, sh);
+    if (threadIdx.x == 0) {
+        if (i < ni) h[i] = accumulate ? h[i] + t : t;
+        else ww[0] = t;
+    }
+}
+
+// w -= sum_{i < ni} c_i v_i with c = h (first pass) or the correction of
+// the second pass; part_out = partial <w, w>.  Skipped unless *active.
+__global__ __launch_bounds__(kVT) void cgs_update_kernel(int64_t N, int ni, int64_t ldv,
+                                                         double* __restrict__ w,
+                                                         const double* __restrict__ V,
+                                                         const double* __restrict__ c,
+                                                         double* __restrict__ part_out,
+                                                         const double* __restrict__ active) {
+    if (active && active[0] == 0.0) return;
+    __shared__ double cs[64];
+    __shared__ double sh[kVT];
+    for (int q = threadIdx.x; q < ni; q += kVT) cs[q] = c[q];
+    __syncthreads();
+    double a = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        double we = w[e];
+        for (int q = 0; q < ni; ++q) we = fma(-cs[q], V[(size_t)q * ldv + e], we);
+        w[e] = we;
+        a = fma(we, we, a);
+    }
+    const double s = block_sum(a, sh);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+}
+
+// Second pass wanted if ||w_after||^2 < ||w_before||^2 / 2.
+__global__ __launch_bounds__(kVT) void dgks_kernel(int nb, const double* __restrict__ part_after,
+                                                   const double* __restrict__ ww_before,
+                                                   double* __restrict__ flag) {
+    __shared__ double sh[kVT];
+    const double after = reduce_partials(part_after, nb, sh);
+    if (threadIdx.x == 0) flag[0] = (after < 0.5 * ww_before[0]) ? 1.0 : 0.0;
 }
 
 // h_{j+1,j} = ||w||, v_{j+1} = w / h  (or 0 and the breakdown flag).
@@ -231,11 +334,11 @@ void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double 
 struct GraphKey {
     const void *op, *ras, *amg, *ws;
     size_t ws_bytes;
-    int m, j;
+    int m, j, ortho;
     uint64_t omega_bits;
     bool operator<(const GraphKey& o) const {
-        return std::tie(op, ras, amg, ws, ws_bytes, m, j, omega_bits) <
-               std::tie(o.op, o.ras, o.amg, o.ws, o.ws_bytes, o.m, o.j, o.omega_bits);
+        return std::tie(op, ras, amg, ws, ws_bytes, m, j, ortho, omega_bits) <
+               std::tie(o.op, o.ras, o.amg, o.ws, o.ws_bytes, o.m, o.j, o.ortho, o.omega_bits);
     }
 };
 
@@ -298,6 +401,8 @@ size_t fgmres_ws_ns(int n, int P, int ns, int restart) {
     size_t b = align_up(N * 8) * (2 * m + 2);                 // V (m+1), Z (m), w
     b += precond_ws_ns(n, P, ns);
     b += 2 * align_up(kMaxRedBlocks * 8);                     // partial sums
+    b += align_up((m + 2) * kMaxRedBlocks * 8);               // Gram-Schmidt partials
+    b += align_up((m + 1) * 8) + align_up(64);                // correction, flags
     b += align_up((m + 1) * m * 8) + 4 * align_up((m + 1) * 8) + align_up(64);
     // the damping estimate reuses the front of the workspace
     const size_t damp = 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8) + 256;
@@ -345,6 +450,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
     SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
     SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
+    SG_REQUIRE(opts->ortho >= SG_ORTHO_MGS && opts->ortho <= SG_ORTHO_CGS, "bad orthogonalisation");
     const size_t need = fgmres_ws_np(A.n, A.P, amg, m);
     if (!ws || ws_bytes < need)
         SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
@@ -358,6 +464,9 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     char* q = pws + precond_ws_np(A.n, A.P, amg);
     double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
     double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
+    double* gsp = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 2) * kMaxRedBlocks * 8);
+    double* corr = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
+    double* gsf = reinterpret_cast<double*>(q); q += align_up(64);   // ww_before, flag
     double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
     double* cs = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
     double* sn = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
@@ -390,18 +499,46 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             double* zj = Zb + (size_t)j * (vb / 8);
             precond_apply(A, ras, amg, omega, vj, zj, pws, st);
             linop_apply(A, zj, w, 1.0, 0.0, nullptr, st);
-            dot_partial_kernel<<<nb, kVT, 0, st>>>(N, w, V, part[0]);
-            HIP_LAUNCH_OK();
             double* hcol = H + (size_t)j * (m + 1);
-            for (int i = 0; i <= j; ++i) {
-                const double* vi = V + (size_t)i * (vb / 8);
-                const double* vn = (i < j) ? V + (size_t)(i + 1) * (vb / 8) : nullptr;
-                mgs_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vi, vn, part[i & 1], part[(i + 1) & 1],
-                                               hcol + i);
+            const int ni = j + 1;
+            const int64_t ldv = (int64_t)(vb / 8);
+            double* part_w = part[0];                   // partial sums of ||w||^2 at the end
+            if (opts->ortho == SG_ORTHO_MGS) {
+                dot_partial_kernel<<<nb, kVT, 0, st>>>(N, w, V, part[0]);
                 HIP_LAUNCH_OK();
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + (size_t)i * (vb / 8);
+                    const double* vn = (i < j) ? V + (size_t)(i + 1) * (vb / 8) : nullptr;
+                    mgs_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vi, vn, part[i & 1], part[(i + 1) & 1],
+                                                   hcol + i);
+                    HIP_LAUNCH_OK();
+                }
+                part_w = part[(j + 1) & 1];
+            } else {
+                const dim3 dgrid(nb, (ni + kCgsIB - 1) / kCgsIB);
+                // first pass: h = V^T w, w -= V h
+                cgs_dot_kernel<<<dgrid, kVT, 0, st>>>(N, nb, ni, ldv, w, V, gsp, nullptr);
+                HIP_LAUNCH_OK();
+                cgs_reduce_kernel<<<ni + 1, kVT, 0, st>>>(nb, ni, gsp, hcol, 0, gsf, nullptr);
+                HIP_LAUNCH_OK();
+                cgs_update_kernel<<<nb, kVT, 0, st>>>(N, ni, ldv, w, V, hcol, part[0], nullptr);
+                HIP_LAUNCH_OK();
+                if (opts->ortho == SG_ORTHO_CGS_DGKS) {
+                    // second pass only where the first lost more than 1 - 1/sqrt(2) of ||w||
+                    dgks_kernel<<<1, kVT, 0, st>>>(nb, part[0], gsf, gsf + 1);
+                    HIP_LAUNCH_OK();
+                    cgs_dot_kernel<<<dgrid, kVT, 0, st>>>(N, nb, ni, ldv, w, V, gsp, gsf + 1);
+                    HIP_LAUNCH_OK();
+                    cgs_reduce_kernel<<<ni, kVT, 0, st>>>(nb, ni, gsp, corr, 0, gsf + 2, gsf + 1);
+                    HIP_LAUNCH_OK();
+                    cgs_update_kernel<<<nb, kVT, 0, st>>>(N, ni, ldv, w, V, corr, part[0], gsf + 1);
+                    HIP_LAUNCH_OK();
+                    cgs_reduce_kernel<<<ni, kVT, 0, st>>>(nb, ni, gsp, hcol, 1, gsf + 2, gsf + 1);
+                    HIP_LAUNCH_OK();
+                }
             }
             double* vnext = V + (size_t)(j + 1) * (vb / 8);
-            normalize_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vnext, part[(j + 1) & 1], hcol + j + 1,
+            normalize_kernel<<<nb, kVT, 0, st>>>(N, nb, w, vnext, part_w, hcol + j + 1,
                                                  scal + 1);
             HIP_LAUNCH_OK();
             givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
@@ -428,7 +565,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                 for (int j = 0; j < m; ++j) {
                     if (opts->use_graph) {
                         hipGraphExec_t exec = nullptr;
-                        GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, 0};
+                        GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, opts->ortho, 0};
                         std::memcpy(&key.omega_bits, &omega, sizeof(double));
                         {
                             std::lock_guard<std::mutex> lk(g_graph_mu);

@@ -664,6 +664,7 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             ko.rtol = eta;
             ko.omega = opts->omega;
             ko.use_graph = opts->use_graph;
+            ko.ortho = opts->ortho;
             sg_krylov_stats ks{};
             const int kst = fgmres_core(J, nl->jac.get(), nl->device, ras.get(), amg.get(), R, D,
                                         &ko, &ks, kws, kws_bytes, s);

@@ -71,7 +71,7 @@ class GpuSG:
         return B.sg_smoother_damping(self.op, self.ras, its, ws, stream=self.stream)
 
     def solve(self, restart: int, rtol: float, max_it: int = 2000, omega: float = 0.0,
-              x0=None, use_precond: bool = True, use_graph: bool = False):
+              x0=None, use_precond: bool = True, use_graph: bool = False, ortho: str = "mgs"):
         x = self.new_vec() if x0 is None else x0.clone()
         ras = self.ras if use_precond else None
         amg = self.amg if use_precond else None
@@ -79,7 +79,7 @@ class GpuSG:
             (B.fgmres_workspace_bytes(self.op, None, restart) + 7) // 8, dtype=self.torch.float64,
             device="cuda")
         info = B.fgmres_solve(self.op, ras, amg, self.b, x, restart, max_it, rtol, omega, ws,
-                              use_graph=use_graph, stream=self.stream)
+                              use_graph=use_graph, ortho=ortho, stream=self.stream)
         return x, info
 
     def close(self):

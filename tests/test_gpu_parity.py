@@ -333,6 +333,30 @@ def test_fgmres_solution_matches_direct(built, key, coarse, restart):
     assert np.linalg.norm(U - ref) / np.linalg.norm(ref) < 1e-8
 
 
+@pytest.mark.parametrize("ortho", ["cgs", "cgs2"])
+@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40"])
+def test_fgmres_classical_gram_schmidt(built, key, ortho):
+    """Classical Gram-Schmidt (one pass, or with the conditional second pass)
+    reaches the solution (the oracle's direct solve on the small cases, the
+    modified Gram-Schmidt solve on the P = 84 case whose Kronecker matrix is
+    too large for a sparse direct solve); its residual history follows
+    modified Gram-Schmidt's to rounding over the first iterations."""
+    pr, S, g = built(key)
+    x, info = g.solve(50, 1e-10, ortho=ortho)
+    assert info["converged"] and info["true_relres"] <= 1e-10
+    x_m, info_m = g.solve(50, 1e-10, ortho="mgs")
+    if key == "c3_40":
+        ref = _to_host(x_m, (pr.mesh.n, S.P))
+    else:
+        ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
+    n = min(len(info["history"]), len(info_m["history"]), 10)
+    assert np.allclose(info["history"][:n], info_m["history"][:n], rtol=1e-8)
+    assert abs(info["iterations"] - info_m["iterations"]) <= 2
+    x2, info2 = g.solve(50, 1e-10, ortho=ortho, use_graph=True)
+    assert torch.equal(x, x2)
+
+
 def test_fgmres_iterations_track_oracle(built):
     pr, S, g = built("c0", coarse="mean")
     B2, *_ = osys.two_level(S, pr.owner, pr.n_sub, pr.overlap, "mean")
