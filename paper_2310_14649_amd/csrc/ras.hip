@@ -41,7 +41,7 @@ struct sg_ras {
     int op_L = 0;
     sg::DevBuf<int64_t> lent, prev_ent, next_ent;
     // dense path: explicit inverse rows of the owned nodes, [n_own(s)][ld(s)]
-    // per subdomain (local columns in level order, ld = nloc padded to 32)
+    // per subdomain (local columns in level order, ld = nloc padded to 64)
     bool dense_built = false, use_dense = false;
     int Pp = 0;                                   // P padded to 16
     std::vector<int32_t> h_ld, h_nown;
@@ -559,9 +559,13 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(
 
 // Z[owned] = beta Z[owned] + omega / n! * (Ainv_s X_s)[own rows]: one wave per
 // 64 owned rows (MT = 4 row tiles of 16) and all P columns (NT tiles of 16),
-// K = local nodes; every right-hand-side fragment loaded serves the four
-// row tiles, and two K steps are in flight.
+// K = local nodes.  The sum over k runs in any order as long as the A and B
+// operands agree, so each super-step of 2 MFMA k-steps lets lane group g
+// read 32 contiguous bytes at offset 32 g of a 128-byte row segment: the four
+// groups read whole cache lines of the inverse rows.  Every right-hand-side
+// fragment loaded serves the four row tiles.
 constexpr int kDenseRows = 64;       // rows per wave
+constexpr int kDenseLd = 64;         // local-node padding of the stored rows
 template <class TS, int NT>
 __global__ __launch_bounds__(256) void dense_apply_kernel(
     int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
@@ -572,9 +576,8 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
     double* Z, double omega, double beta) {
     using Acc = typename Mma<TS>::Acc;
     constexpr int MT = kDenseRows / 16;
-    // K elements per lane-group load (16 bytes) and per MFMA step
-    constexpr int KL = 16 / sizeof(TS);
-    constexpr int KSTEP = 4 * KL;
+    constexpr int KL = 16 / sizeof(TS);          // elements per 16-byte load
+    constexpr int KSUP = 8 * KL;                 // elements per super-step (128 bytes per row)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b = blockIdx.x;
     const int s = blk_sub[b];
@@ -586,52 +589,66 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
     const TS* A[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
-        A[m] = ainv + aoff[s] + (int64_t)min(r0 + 16 * m + i, no - 1) * L + KL * g;
-    const TS* X = xg + xoff[s] + (int64_t)i * L + KL * g;
+        A[m] = ainv + aoff[s] + (int64_t)min(r0 + 16 * m + i, no - 1) * L + 2 * KL * g;
+    const TS* X = xg + xoff[s] + (int64_t)i * L + 2 * KL * g;
     Acc acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
-    auto step = [&](int k) {
-        uint4 av[MT], bv[NT];
+    // two register buffers: the loads of super-step k + 1 are in flight while
+    // the products of super-step k run
+    uint4 av[2][MT][2], bv[2][NT][2];
+    auto load = [&](int buf, int k) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[m] = *reinterpret_cast<const uint4*>(A[m] + k);
+        for (int m = 0; m < MT; ++m) {
+            av[buf][m][0] = *reinterpret_cast<const uint4*>(A[m] + k);
+            av[buf][m][1] = *reinterpret_cast<const uint4*>(A[m] + k + KL);
+        }
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            bv[t] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k);
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                if constexpr (sizeof(TS) == 2) {
-                    sg_bf8 a, bb;
-                    __builtin_memcpy(&a, &av[m], 16);
-                    __builtin_memcpy(&bb, &bv[t], 16);
-                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[m][t], 0, 0, 0);
-                } else if constexpr (sizeof(TS) == 4) {
-                    float a[4], bb[4];
-                    __builtin_memcpy(a, &av[m], 16);
-                    __builtin_memcpy(bb, &bv[t], 16);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc[m][t], 0, 0, 0);
-                } else {
-                    double a[2], bb[2];
-                    __builtin_memcpy(a, &av[m], 16);
-                    __builtin_memcpy(bb, &bv[t], 16);
-#pragma unroll
-                    for (int u = 0; u < 2; ++u)
-                        acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc[m][t], 0, 0, 0);
-                }
-            }
+        for (int t = 0; t < NT; ++t) {
+            bv[buf][t][0] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k);
+            bv[buf][t][1] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k + KL);
+        }
     };
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if constexpr (sizeof(TS) == 2) {
+                        sg_bf8 a, bb;
+                        __builtin_memcpy(&a, &av[buf][m][h], 16);
+                        __builtin_memcpy(&bb, &bv[buf][t][h], 16);
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[m][t], 0, 0, 0);
+                    } else if constexpr (sizeof(TS) == 4) {
+                        float a[4], bb[4];
+                        __builtin_memcpy(a, &av[buf][m][h], 16);
+                        __builtin_memcpy(bb, &bv[buf][t][h], 16);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc[m][t], 0, 0, 0);
+                    } else {
+                        double a[2], bb[2];
+                        __builtin_memcpy(a, &av[buf][m][h], 16);
+                        __builtin_memcpy(bb, &bv[buf][t][h], 16);
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+                            acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc[m][t], 0, 0, 0);
+                    }
+                }
+    };
+    load(0, 0);
     int k = 0;
-    for (; k + 2 * KSTEP <= L; k += 2 * KSTEP) {
-        step(k);
-        step(k + KSTEP);
+    for (; k + 2 * KSUP <= L; k += 2 * KSUP) {
+        load(1, k + KSUP);
+        compute(0);
+        if (k + 2 * KSUP < L) load(0, k + 2 * KSUP);
+        compute(1);
     }
-    for (; k < L; k += KSTEP) step(k);
+    if (k < L) compute(0);          // L / KSUP odd: the last super-step is in buffer 0
     const int64_t ob = own_off[s];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -839,7 +856,7 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
                     own_gnode.push_back(r->h_gnode[a]);
                 }
             }
-            r->h_ld[q] = (a1 - a0 + 31) / 32 * 32;
+            r->h_ld[q] = (a1 - a0 + kDenseLd - 1) / kDenseLd * kDenseLd;
             r->h_nown[q] = no;
             r->h_aoff[q + 1] = r->h_aoff[q] + (int64_t)no * r->h_ld[q];
             r->h_xoff[q + 1] = r->h_xoff[q] + (int64_t)r->Pp * r->h_ld[q];
