@@ -101,6 +101,17 @@ def cpu_baseline(pr, its_gpu: int, sample_its: int):
                 est_solve_ms=per_it * its_gpu * 1e3)
 
 
+def workload(pr, n: int, P: int, mixed: str) -> str:
+    """The workload named by its sizes."""
+    nc = pr.mesh.nc
+    mesh = f"{nc}x{nc} P1" + (" (jittered vertices)" if pr.mesh.jittered else "")
+    sub = (f"{pr.n_sub} graph-partitioned subdomains" if "partition_seed" in pr.extra
+           else f"{pr.n_sub} lattice subdomains")
+    return (f"linear SG Poisson {mesh}, M={pr.M} KL vars, order {pr.p} (P={P}), {n * P:,} "
+            f"unknowns, RAS on {sub} overlap {pr.overlap} + SA-AMG Nicolaides coarse, "
+            f"FGMRES({pr.restart}) to {pr.rtol:g}, preconditioner {mixed}")
+
+
 def bench_newton(args, torch):
     """Config 4: Newton-FGMRES to ||R||/||F|| <= 1e-8 from the zero guess on
     the base draw, then the learned guess: training data from the solver,
@@ -271,9 +282,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "linear SG Poisson 512x512 P1, M=4 KL vars, order 3 (P=35), "
-                               "9,139,235 unknowns, RAS 16x16 overlap 2 + SA-AMG Nicolaides "
-                               "coarse, FGMRES(50) to 1e-8, preconditioner " + args.mixed,
+        "config": {"workload": workload(pr, n, P, args.mixed),
                    "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub,
                    "graph": bool(args.graph), "ortho": args.ortho},
         "solves": results,

@@ -253,15 +253,14 @@ def graph_partition(mesh: Mesh, nx: int, ny: int, seed: int,
         owner[seeds] = np.arange(len(seeds), dtype=np.int32)
         frontier = np.sort(seeds)
         while frontier.size:
-            cand_nodes, cand_owner = [], []
-            for a in frontier:
-                nb = col[ptr[a]:ptr[a + 1]]
-                nb = nb[owner[nb] < 0]
-                cand_nodes.append(nb)
-                cand_owner.append(np.full(nb.size, owner[a], dtype=np.int32))
-            if not cand_nodes:
-                break
-            cn = np.concatenate(cand_nodes); co = np.concatenate(cand_owner)
+            # all edges leaving the frontier, with the owner of their source
+            deg = ptr[frontier + 1] - ptr[frontier]
+            src = np.repeat(frontier, deg)
+            start = np.repeat(ptr[frontier] - np.cumsum(np.concatenate([[0], deg[:-1]])), deg)
+            cn = col[np.arange(src.size) + start]
+            keep = owner[cn] < 0
+            cn = cn[keep]
+            co = owner[src[keep]]
             if cn.size == 0:
                 break
             order = np.lexsort((co, cn))
