@@ -181,6 +181,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="time only the SG matvec (for counter collection) and print its figures")
     ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
                     help="Arnoldi orthogonalisation")
     ap.add_argument("--ras-path", default="auto", choices=["auto", "sweep", "dense"],
@@ -206,6 +208,17 @@ def main() -> int:
     torch.cuda.set_device(0)
     pr = make_problem(args.config)
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
+    if args.matvec_only:
+        g = GpuSG(pr, prec="fp64", coarse="none")
+        n, P, L, nnz = g.n, g.P, g.L, g.nnz
+        mv_mean_ms, mv_med_ms = time_matvec(g, args.mv_launches, torch)
+        b = matvec_bytes(n, nnz, L, P)
+        print(json.dumps({"matvec_only": True, "config": args.config, "us": round(mv_mean_ms * 1e3, 2),
+                          "median_us": round(mv_med_ms * 1e3, 2), "bytes": b,
+                          "GBps": round(b / (mv_mean_ms * 1e-3) / 1e9, 1),
+                          "flush_bytes_per_launch": 2 * 64 * 1024 * 1024 * 8}))
+        g.close()
+        return 0
     precs = ["fp64", args.mixed] + [p for p in args.also.split(",") if p and p not in ("fp64", args.mixed)]
     solvers = {}
     setup_s = {}

@@ -118,7 +118,7 @@ struct TriplesDev {
     int P = 0, L = 0, T = 0;
     DevBuf<int32_t> kptr, tij;
     DevBuf<double> tval;
-    // Schedule of the wide-input matvec (L > 32): the k-sorted triples cut
+    // Schedule of the wide matvec (L > 32 or P > 64): the k-sorted triples cut
     // into 64 equal lane chunks; a lane flushes its running sum into a slot at
     // the end of every run of equal k, and the slots of k are contiguous
     // ([slot_ptr[k], slot_ptr[k+1])), so y_k sums them in a fixed order.

@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Wide-input kernel (L > 32 input terms, e.g. the degree-2p coefficient
-// fields of a Newton Jacobian).  One wave per row: the row's K_i values
+// Wide kernel (L > 32 input terms, e.g. the degree-2p coefficient fields of
+// a Newton Jacobian, or P > 64 output modes).  One wave per row: the row's K_i values
 // (entries x L) and its neighbours' X rows are staged in the wave's own LDS
 // slice (zero-padded to EMAX entries), then every lane walks its chunk of
 // the k-sorted triple table,
@@ -378,7 +378,9 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
         HIP_LAUNCH_OK();
         return;
     }
-    if (L > 32) {
+    // many input terms, or outputs too wide for the tiled kernel's LDS budget:
+    // one wave per row with the balanced triple schedule
+    if (L > 32 || P > 64) {
         SG_REQUIRE(tr.nslot > 0, "wide matvec schedule missing");
         int emax = A.max_row <= 7 ? 7 : A.max_row <= 10 ? 10 : A.max_row <= 16 ? 16 : 0;
         if (!emax) SG_THROW(SG_ERR_UNSUPPORTED, "wide matvec: %d entries in a row exceed 16", A.max_row);

@@ -62,7 +62,7 @@ namespace sg {
 constexpr int kRasThreads = 256;
 constexpr int kMaxLevel = 64;
 constexpr int kColChunk = 16;   // right-hand-side columns per work-group (one MFMA tile)
-constexpr int kCouple = 4;      // max neighbours of a node in an adjacent level
+constexpr int kCouple = 8;      // max neighbours of a node in an adjacent level
 constexpr int kMaxLocal = 8192;  // max nodes of one overlapping subdomain
 
 inline size_t ras_apply_lds(sg_prec prec, int bmax, int KC, int nmax, int lmax) {
@@ -733,12 +733,15 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
         r->afact.p, R, Z, r->zs.p, omega, beta
     const bool small = bmax <= 40;
     const bool narrow = r->max_couple <= 2;
+    const bool wide = r->max_couple > 4;
 #define SG_RAS_GO(TS, PTR)                                                                      \
     do {                                                                                        \
         if (narrow && small)                                                                    \
             ras_apply_kernel<TS, 2, 40><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
         else if (narrow)                                                                        \
             ras_apply_kernel<TS, 2, 64><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
+        else if (wide)                                                                          \
+            ras_apply_kernel<TS, 8, 64><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
         else if (small)                                                                         \
             ras_apply_kernel<TS, 4, 40><<<grid, kRasThreads, lds, s>>>(SG_RAS_ARGS, PTR, SG_RAS_TAIL); \
         else                                                                                    \
@@ -897,11 +900,13 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         r->lev_start.p, r->lev_size.p, r->sinv_off.p, r->sinv64.p, r->gnode.p, r->owned.p,         \
         r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p, r->afact.p, nullptr, nullptr,  \
         zs_tmp.p, 1.0, 0.0, qb, r->own_pos.p, r->ld_d.p, r->aoff_d.p, r->ainv64.p)
-        const bool small = bmax <= 40, narrow = r->max_couple <= 2;
+        const bool small = bmax <= 40, narrow = r->max_couple <= 2, wide = r->max_couple > 4;
         if (narrow && small)
             SG_SETUP_GO(2, 40);
         else if (narrow)
             SG_SETUP_GO(2, 64);
+        else if (wide)
+            SG_SETUP_GO(8, 64);
         else if (small)
             SG_SETUP_GO(4, 40);
         else

@@ -133,7 +133,7 @@ void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s) {
     tr.kptr.upload(kptr, s);
     tr.tij.upload(tij, s);
     tr.tval.upload(b.tv, s);
-    if (b.L > 32) {
+    if (b.L > 32 || b.P > 64) {
         SG_REQUIRE(b.L <= 65536 && b.P <= 128, "wide matvec schedule limits exceeded");
         constexpr int kLanes = 64;
         std::vector<int32_t> lane_ptr(kLanes + 1), slot_ptr(b.P + 1, 0);

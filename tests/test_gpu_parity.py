@@ -58,15 +58,24 @@ CASES = {
     "c4_ragged": dict(name="c4", nc=23, sub=(3, 5)),     # tails in every tile
     "j4": dict(name="jit", nc=26, M=4, p=3, sub=(3, 3)),  # jittered, 7 entries per row
     "j2": dict(name="jit", nc=30, M=2, p=2, sub=(2, 3)),
+    "g6": dict(name="jit", nc=44, M=6, p=2, sub=(1, 1), graph=(4, 3)),  # graph partition, M=6
 }
 
 
 def _problem(key):
     kw = dict(CASES[key])
     name = kw.pop("name")
+    graph = kw.pop("graph", None)
     if name == "jit":
         kw["seed"] = 3
-    return make_problem(name, **kw)
+    pr = make_problem(name, **kw)
+    if graph is not None:
+        # irregular subdomains: multi-source BFS from jittered lattice centres
+        from paper_2310_14649_amd.inputs import graph_partition
+        gx, gy = graph
+        pr.owner, _ = graph_partition(pr.mesh, gx, gy, 0, 1, 10 ** 9)
+        pr.n_sub = gx * gy
+    return pr
 
 
 @pytest.fixture(scope="module")
@@ -158,7 +167,7 @@ def _oracle_ras(pr, S, owner=None, n_sub=None, overlap=None):
                           pr.overlap if overlap is None else overlap)
 
 
-@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4"])
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "g6"])
 def test_ras_fp64_matches_oracle(built, key):
     pr, S, g = built(key)
     subs = _oracle_ras(pr, S)
@@ -182,7 +191,7 @@ def test_ras_low_precision_close_to_oracle(built, prec, tol):
     assert err < tol
 
 
-@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4"])
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "g6"])
 def test_ras_dense_path_matches_oracle(built, key):
     """The explicit-inverse path computes the same operator as the sweeps."""
     pr, S, g = built(key)
@@ -321,7 +330,8 @@ def test_two_level_cycle_matches_oracle(built, key, coarse):
 
 # ------------------------------------------------------------------ a7
 @pytest.mark.parametrize("key,coarse,restart", [("c0", "mean", 30), ("c1_64", "amg", 50),
-                                                 ("p1_det", "amg", 30), ("c4_ragged", "amg", 50)])
+                                                 ("p1_det", "amg", 30), ("c4_ragged", "amg", 50),
+                                                 ("g6", "amg", 50)])
 def test_fgmres_solution_matches_direct(built, key, coarse, restart):
     pr, S, g = built(key, coarse=coarse)
     ref = osg.sg_solve_direct(S.K, S.G, S.B)
