@@ -34,6 +34,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the matvec kernel measured with the FETCH_SIZE and
+# WRITE_SIZE counters, scaled by the counters' reading of a copy of known
+# size (profiles/sg_matvec_512x512_P35_hbm_traffic.txt), keyed by kernel and
+# workload; a workload or kernel without a measurement reports null.
+MEASURED_TRAFFIC = {("kron_matvec_spec_kernel<4, 2, 3, 5, 2>", 261121, 35): 408.1e6}
 
 
 def log(msg: str) -> None:
@@ -261,7 +266,8 @@ def main() -> int:
         log(f"[bench] solve {prec}: {ms:.2f} ms, its={info['iterations']}, "
             f"relres={info['true_relres']:.2e}")
 
-    mv_kernel = "kron_matvec_spec_kernel"
+    mv_kernel = "kron_matvec_spec_kernel<4, 2, 3, 5, 2>" if L == 15 and P == 35 else "kron_matvec"
+    traffic = MEASURED_TRAFFIC.get((mv_kernel, n, P))
     mv_mean_ms, mv_med_ms = time_matvec(g64, args.mv_launches, torch)
     mv_bytes = matvec_bytes(n, nnz, L, P)
     mv_gbs = mv_bytes / (mv_mean_ms * 1e-3) / 1e9
@@ -305,7 +311,8 @@ def main() -> int:
                    "bytes": mv_bytes, "flops": matvec_flops(n, nnz, L, P, T)},
         "roofline": {"bound": "hbm", "kernel": mv_kernel, "achieved": round(mv_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "traffic_unit": "bytes per launch"},
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
         "ras_path": ras_paths,
         "omega": omega,
