@@ -119,6 +119,14 @@ void sg_destroy_op(sg_op* op);
  * Ajklinear).  X, Y: device [n*P] FP64, must not alias.  Asynchronous.
  * ---------------------------------------------------------------------- */
 int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
+/* Which kernel family applies the operator (chosen when it is assembled):
+ * SG_MV_GENERIC (tiled, any basis with L_in <= 32 and P <= 64), SG_MV_WIDE
+ * (one wave per row: L_in > 32 or P > 64), SG_MV_PAIR (fixed basis, two
+ * lanes per row), SG_MV_STAGED (fixed basis, input terms split between
+ * waves, neighbour rows staged in LDS; needs rows whose neighbours form a
+ * few runs of consecutive rows per block of 128).  Host call. */
+enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3 };
+int sg_matvec_kernel(const sg_op* op, int* kind);
 
 /* ------------------------------------------------------------------------
  * ras_setup / ras_apply -- one-level restricted additive Schwarz, Eq. RASsto:

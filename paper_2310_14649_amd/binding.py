@@ -74,6 +74,7 @@ _SIGS = {
     "sg_op_export": (C.c_int, [_vp, _i64p, _i32p, _f64p]),
     "sg_destroy_op": (None, [_vp]),
     "sg_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "sg_matvec_kernel": (C.c_int, [_vp, C.POINTER(C.c_int)]),
     "ras_setup": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "ras_refactor": (C.c_int, [_vp, _vp, _vp]),
     "ras_select": (C.c_int, [_vp, C.c_int, _vp]),
@@ -240,6 +241,15 @@ def sg_destroy_op(op):
 
 def sg_matvec(op, X, Y, stream=None):
     _check(lib().sg_matvec(op, _dev(X), _dev(Y), _stream(stream)))
+
+
+MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged"}
+
+
+def sg_matvec_kernel(op) -> str:
+    k = C.c_int()
+    _check(lib().sg_matvec_kernel(op, C.byref(k)))
+    return MV_KERNELS[k.value]
 
 
 # ---------------------------------------------------------------- RAS

@@ -143,6 +143,13 @@ struct KronCsr {
     int ell_S = 0, ell_RW = 0;         // slots per row, rows per tile
     const int32_t* ecol = nullptr;     // [tiles][S][RW]
     const double* evals = nullptr;     // [tiles][S][L][RW]
+    // optional staged copy used by the split kernels (id -1 = none): per
+    // block of rows, the runs of neighbour rows staged in LDS, and each
+    // entry's column as an index into that staging area
+    int split = -1;
+    const int32_t* sruns = nullptr;    // [blocks][2*kRuns+1]
+    const int16_t* sslot = nullptr;    // [tiles][S][64]
+    const double* svals = nullptr;     // [tiles][S][L][64]
 };
 
 }  // namespace sg
@@ -168,6 +175,10 @@ struct sg_op {
     int spec = -1, ell_S = 0, ell_RW = 0;
     sg::DevBuf<int32_t> ecol;
     sg::DevBuf<double> evals;
+    int split = -1;
+    sg::DevBuf<int32_t> sruns;
+    sg::DevBuf<int16_t> sslot;
+    sg::DevBuf<double> svals;
     // host copies used by the setup of the preconditioner
     std::vector<int32_t> h_rowptr, h_col;
     std::vector<int64_t> h_graph_ptr;           // mesh graph (overlap growth)
@@ -180,6 +191,7 @@ struct sg_op {
         k.n = n; k.nnz = nnz; k.max_row = max_row;
         k.rowptr = rowptr.p; k.col = col.p; k.vals = vals.p;
         k.spec = spec; k.ell_S = ell_S; k.ell_RW = ell_RW; k.ecol = ecol.p; k.evals = evals.p;
+        k.split = split; k.sruns = sruns.p; k.sslot = sslot.p; k.svals = svals.p;
         return k;
     }
 };

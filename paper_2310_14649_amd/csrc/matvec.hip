@@ -290,6 +290,207 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split kernel for a fixed basis (M, PIN, PO) and at most S entries per row.
+// A work-group of four waves covers 128 consecutive rows, two tiles of 64.
+// Waves 0 and 2 take the first half of the input terms, waves 1 and 3 the
+// second half, each for the 64 rows of its tile with one row per lane.  With
+// the input terms split between waves instead of between lanes, every triple
+// a wave executes belongs to it and the coefficients stay immediates.  The
+// neighbour rows of the block -- a few runs of consecutive rows, found at
+// setup -- are staged in LDS JC columns at a time (double-buffered through
+// registers) and shared by the two halves; the second half's partial sums
+// reach the first through LDS.
+namespace split {
+constexpr int kRuns = 4, kSlots = 512, JC = 5, RB = 64, kBlockRows = 128, kThreads = 256;
+constexpr int kRunWords = 2 * kRuns + 1;
+
+template <class H, int T>
+__device__ __forceinline__ void tstep(const double* w, double* y) {
+    constexpr int k = H::t.k[T];
+    constexpr int ii = H::t.ii[T];
+    constexpr double m = H::t.m[T];
+    y[k] = fma(m, w[ii], y[k]);
+}
+
+template <class H, int T0, int... Is>
+__device__ __forceinline__ void trange(std::integer_sequence<int, Is...>, const double* w, double* y) {
+    (tstep<H, T0 + Is>(w, y), ...);
+}
+
+template <int S, int J, int J0>
+__device__ __forceinline__ void xload(const int* slot, const double* xs, double* x) {
+#pragma unroll
+    for (int q = 0; q < S; ++q) x[q] = xs[slot[q] * JC + (J - J0)];
+}
+
+template <int M, int PIN, int PO, int S, int G, int LI, int J>
+__device__ __forceinline__ void contract(const double (*v)[8], const double* x, double* y) {
+    double w[LI];
+#pragma unroll
+    for (int ii = 0; ii < LI; ++ii) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) a = fma(v[q][ii], x[q], a);
+        w[ii] = a;
+    }
+    using H = tab::GroupHolder<M, PIN, PO, 2, G>;
+    constexpr int t0 = H::t.jptr[J], t1 = H::t.jptr[J + 1];
+    trange<H, t0>(std::make_integer_sequence<int, t1 - t0>{}, w, y);
+}
+
+// Column J of a chunk: fetch column J+1's neighbour values, then contract J.
+template <int M, int PIN, int PO, int S, int G, int LI, int J, int J0, int JE>
+__device__ __forceinline__ void column(const int* slot, const double (*v)[8], const double* xs,
+                                       double (*xb)[S], double* y) {
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (J + 1 < JE) xload<S, J + 1, J0>(slot, xs, xb[(J + 1 - J0) & 1]);
+    contract<M, PIN, PO, S, G, LI, J>(v, xb[(J - J0) & 1], y);
+}
+
+template <int M, int PIN, int PO, int S, int G, int LI, int J0, int... Js>
+__device__ __forceinline__ void columns(std::integer_sequence<int, Js...>, const int* slot,
+                                        const double (*v)[8], const double* xs, double* y) {
+    constexpr int JE = J0 + (int)sizeof...(Js);
+    double xb[2][S];
+    xload<S, J0, J0>(slot, xs, xb[0]);
+    (column<M, PIN, PO, S, G, LI, J0 + Js, J0, JE>(slot, v, xs, xb, y), ...);
+}
+
+template <int P, int C>
+constexpr int chunk_width() {
+    return (P - C * JC) < JC ? (P - C * JC) : JC;
+}
+
+// Global -> registers for chunk C: each thread owns staging slots tid and
+// tid + 256 (rows clamped to a valid row, so the loads never branch).
+template <int P, int C>
+__device__ __forceinline__ void stage_load(const double* __restrict__ X, const int* srow,
+                                           double (*st)[JC]) {
+    constexpr int W = chunk_width<P, C>();
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double* p = X + (size_t)srow[m] * P + C * JC;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) st[m][jj] = p[jj];
+    }
+}
+
+template <int P, int C>
+__device__ __forceinline__ void stage_store(double* buf, int tid, const double (*st)[JC]) {
+    constexpr int W = chunk_width<P, C>();
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) buf[(tid + kThreads * m) * JC + jj] = st[m][jj];
+}
+
+template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int C>
+__device__ __forceinline__ void chunk(const int* slot, const double (*v)[8], double* lds,
+                                      double (*st)[JC], const double* __restrict__ X,
+                                      const int* srow, int tid, double* y) {
+    if constexpr (C + 1 < NCH) stage_load<P, C + 1>(X, srow, st);
+    columns<M, PIN, PO, S, G, LI, C * JC>(std::make_integer_sequence<int, chunk_width<P, C>()>{},
+                                          slot, v, lds + (C & 1) * kSlots * JC, y);
+    if constexpr (C + 1 < NCH) stage_store<P, C + 1>(lds + ((C + 1) & 1) * kSlots * JC, tid, st);
+    __syncthreads();
+}
+
+template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int... Cs>
+__device__ __forceinline__ void chunks(std::integer_sequence<int, Cs...>, const int* slot,
+                                       const double (*v)[8], double* lds, double (*st)[JC],
+                                       const double* __restrict__ X, const int* srow, int tid,
+                                       double* y) {
+    (chunk<M, PIN, PO, S, G, LI, P, NCH, Cs>(slot, v, lds, st, X, srow, tid, y), ...);
+}
+
+// One half of the input terms over the whole row: G = 0 takes i < ceil(L/2).
+template <int M, int PIN, int PO, int S, int G>
+__device__ __forceinline__ void half(int tile, int r, const int* slot,
+                                     const double* __restrict__ svals, double* lds,
+                                     double (*st)[JC], const double* __restrict__ X,
+                                     const int* srow, int tid, double* y) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    constexpr int L = tab::cbinom(M + PIN, PIN);
+    constexpr int LH = (L + 1) / 2;
+    constexpr int LI = G == 0 ? LH : L - LH;
+    constexpr int NCH = (P + JC - 1) / JC;
+    static_assert(LH <= 8, "half of the input terms must fit 8 registers per entry");
+    double v[S][8];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int ii = 0; ii < LI; ++ii)
+            v[q][ii] = svals[(((size_t)tile * S + q) * L + G * LH + ii) * RB + r];
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[k] = 0.0;
+    __syncthreads();   // chunk 0 staged
+    chunks<M, PIN, PO, S, G, LI, P, NCH>(std::make_integer_sequence<int, NCH>{}, slot, v, lds, st,
+                                         X, srow, tid, y);
+}
+
+template <int M, int PIN, int PO, int S>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ runs,
+                              const int16_t* __restrict__ sslot, const double* __restrict__ svals,
+                              const double* __restrict__ X, double* Y, double alpha, double beta,
+                              const double* C) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    static_assert(2 * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
+    __shared__ double lds[2 * kSlots * JC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t* rw = runs + (size_t)blockIdx.x * kRunWords;
+    int rrow[kRuns], rslot[kRuns];
+#pragma unroll
+    for (int q = 0; q < kRuns; ++q) {
+        rrow[q] = rw[q];
+        rslot[q] = rw[kRuns + q];
+    }
+    const int nslot = rw[2 * kRuns];
+    int srow[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int sl = tid + kThreads * m;
+        int row = rrow[0] + (sl - rslot[0]);
+#pragma unroll
+        for (int q = 1; q < kRuns; ++q) row = (sl >= rslot[q]) ? rrow[q] + (sl - rslot[q]) : row;
+        srow[m] = (sl < nslot) ? row : rrow[0];
+    }
+    double st[2][JC];
+    stage_load<P, 0>(X, srow, st);
+    stage_store<P, 0>(lds, tid, st);
+
+    const int g = wave & 1, rb = wave >> 1;
+    const int tile = blockIdx.x * 2 + rb;
+    const bool live = tile < ntiles;
+    const int tt = live ? tile : 0;
+    int slot[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) slot[q] = sslot[((size_t)tt * S + q) * RB + lane];
+    double y[P];
+    if (g == 0)
+        half<M, PIN, PO, S, 0>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+    else
+        half<M, PIN, PO, S, 1>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+    // the staging area is free after the last chunk's barrier
+    if (g == 1) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) lds[(rb * P + k) * RB + lane] = y[k];
+    }
+    __syncthreads();
+    const int row = tile * RB + lane;
+    if (g == 1 || !live || row >= n) return;
+    double* yr = Y + (size_t)row * P;
+    const double* cr = C ? C + (size_t)row * P : nullptr;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double o = alpha * (y[k] + lds[(rb * P + k) * RB + lane]);
+        if (beta != 0.0) o = fma(beta, cr[k], o);
+        yr[k] = o;
+    }
+}
+}  // namespace split
+
 // ELL copy: entry id of every (tile, slot, lane) position, -1 for padding.
 __global__ void ell_fill_kernel(int64_t npos, int L, int S, int RW, const int64_t* __restrict__ ent,
                                 const double* __restrict__ vals, double* __restrict__ evals) {
@@ -319,10 +520,117 @@ void launch_spec(const KronCsr& A, const double* X, double* Y, double alpha, dou
         <<<blocks, kThreads, 0, s>>>(A.n, A.ecol, A.evals, X, Y, alpha, beta, C);
 }
 
+struct SplitSpec {
+    int M, PIN, PO, S;
+};
+constexpr SplitSpec kSplits[] = {{2, 2, 2, 5}, {2, 2, 2, 7}, {4, 2, 3, 5}};
+
+template <int Id>
+void launch_split(const KronCsr& A, const double* X, double* Y, double alpha, double beta,
+                  const double* C, hipStream_t s) {
+    constexpr SplitSpec sp = kSplits[Id];
+    const int tiles = (A.n + split::RB - 1) / split::RB;
+    const int blocks = (A.n + split::kBlockRows - 1) / split::kBlockRows;
+    split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S>
+        <<<blocks, split::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha,
+                                            beta, C);
+}
+
+// Neighbour rows of one block of rows as at most kRuns runs of consecutive
+// rows (the smallest gaps merged first), laid out one after the other in the
+// staging area.  False when they need more than kSlots staged rows.
+bool block_runs(std::vector<int32_t>& cols, int32_t* words) {
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    std::vector<int32_t> start, end;   // [start, end)
+    for (size_t u = 0; u < cols.size();) {
+        size_t w = u + 1;
+        while (w < cols.size() && cols[w] == cols[w - 1] + 1) ++w;
+        start.push_back(cols[u]);
+        end.push_back(cols[w - 1] + 1);
+        u = w;
+    }
+    while ((int)start.size() > split::kRuns) {
+        size_t best = 1;
+        for (size_t q = 2; q < start.size(); ++q)
+            if (start[q] - end[q - 1] < start[best] - end[best - 1]) best = q;
+        end[best - 1] = end[best];
+        start.erase(start.begin() + best);
+        end.erase(end.begin() + best);
+    }
+    int base = 0;
+    for (int q = 0; q < split::kRuns; ++q) {
+        const bool used = q < (int)start.size();
+        words[q] = used ? start[q] : start[0];
+        words[split::kRuns + q] = used ? base : (1 << 30);
+        if (used) base += end[q] - start[q];
+    }
+    words[2 * split::kRuns] = base;
+    return base <= split::kSlots;
+}
+
+// Staged copy for the split kernel: per block the runs, per (tile, entry,
+// lane) the staging index of the entry's column and its L values.
+bool build_split(sg_op* op, hipStream_t s) {
+    const sg_basis& b = op->basis;
+    int id = -1;
+    for (int q = 0; q < (int)(sizeof(kSplits) / sizeof(kSplits[0])); ++q) {
+        const SplitSpec& sp = kSplits[q];
+        if (sp.M == b.M && sp.PIN == b.p_in && sp.PO == b.p && op->max_row <= sp.S) {
+            id = q;
+            break;
+        }
+    }
+    if (id < 0 || op->n == 0) return false;
+    const int S = kSplits[id].S, RB = split::RB;
+    const int n = op->n;
+    const int tiles = (n + RB - 1) / RB;
+    const int blocks = (n + split::kBlockRows - 1) / split::kBlockRows;
+    std::vector<int32_t> runs((size_t)blocks * split::kRunWords);
+    std::vector<int16_t> slot((size_t)tiles * S * RB, 0);
+    std::vector<int64_t> ent((size_t)tiles * S * RB, -1);
+    std::vector<int32_t> cols;
+    for (int blk = 0; blk < blocks; ++blk) {
+        const int a0 = blk * split::kBlockRows, a1 = std::min(n, a0 + split::kBlockRows);
+        cols.assign(op->h_col.begin() + op->h_rowptr[a0], op->h_col.begin() + op->h_rowptr[a1]);
+        for (int a = a0; a < a1; ++a) cols.push_back(a);   // padding entries read the own row
+        int32_t* w = runs.data() + (size_t)blk * split::kRunWords;
+        if (!block_runs(cols, w)) return false;
+        auto staged = [&](int32_t c) {
+            int q = split::kRuns - 1;
+            while (w[split::kRuns + q] == (1 << 30) || c < w[q]) --q;
+            return (int16_t)(w[split::kRuns + q] + (c - w[q]));
+        };
+        for (int a = a0; a < a1; ++a) {
+            const int t = a / RB, r = a % RB;
+            int q = 0;
+            for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q) {
+                slot[((size_t)t * S + q) * RB + r] = staged(op->h_col[e]);
+                ent[((size_t)t * S + q) * RB + r] = e;
+            }
+            for (; q < S; ++q) slot[((size_t)t * S + q) * RB + r] = staged(a);
+        }
+    }
+    op->sruns.upload(runs, s);
+    op->sslot.upload(slot, s);
+    DevBuf<int64_t> d_ent;
+    d_ent.upload(ent, s);
+    const int64_t npos = (int64_t)tiles * S * RB;
+    op->svals.alloc((size_t)npos * op->L);
+    ell_fill_kernel<<<(unsigned)((npos * op->L + 255) / 256), 256, 0, s>>>(npos, op->L, S, RB, d_ent.p,
+                                                                           op->vals.p, op->svals.p);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(s));
+    op->split = id;
+    return true;
+}
+
 }  // namespace
 
 void build_ell(sg_op* op, hipStream_t s) {
     op->spec = -1;
+    op->split = -1;
+    if (build_split(op, s)) return;
     const sg_basis& b = op->basis;
     int id = -1;
     for (int q = 0; q < (int)(sizeof(kSpecs) / sizeof(kSpecs[0])); ++q) {
@@ -367,6 +675,16 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
                  double alpha, double beta, const double* C, hipStream_t s) {
     const int P = tr.P, T = tr.T;
     if (A.n == 0) return;
+    if (A.split >= 0) {
+        switch (A.split) {
+            case 0: launch_split<0>(A, X, Y, alpha, beta, C, s); break;
+            case 1: launch_split<1>(A, X, Y, alpha, beta, C, s); break;
+            case 2: launch_split<2>(A, X, Y, alpha, beta, C, s); break;
+            default: SG_THROW(SG_ERR_INVALID_ARG, "bad matvec split variant %d", A.split);
+        }
+        HIP_LAUNCH_OK();
+        return;
+    }
     if (A.spec >= 0) {
         switch (A.spec) {
             case 0: launch_spec<0>(A, X, Y, alpha, beta, C, s); break;
@@ -453,6 +771,21 @@ extern "C" int sg_matvec(const sg_op* op, const double* X, double* Y, void* stre
         SG_REQUIRE(X != Y, "X and Y must not alias");
         check_device(op->device);
         kron_matvec(op->csr(), op->L, op->tr, X, Y, 1.0, 0.0, nullptr, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+extern "C" int sg_matvec_kernel(const sg_op* op, int* kind) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && kind, "null argument");
+        if (op->split >= 0)
+            *kind = SG_MV_STAGED;
+        else if (op->spec >= 0)
+            *kind = SG_MV_PAIR;
+        else if (op->L > 32 || op->P > 64)
+            *kind = SG_MV_WIDE;
+        else
+            *kind = SG_MV_GENERIC;
         return SG_OK;
     });
 }

@@ -59,16 +59,31 @@ CASES = {
     "j4": dict(name="jit", nc=26, M=4, p=3, sub=(3, 3)),  # jittered, 7 entries per row
     "j2": dict(name="jit", nc=30, M=2, p=2, sub=(2, 3)),
     "g6": dict(name="jit", nc=44, M=6, p=2, sub=(1, 1), graph=(4, 3)),  # graph partition, M=6
+    # unknowns renumbered at random: no block of rows has neighbours in a few
+    # runs of consecutive rows, so the operator takes the lane-pair kernel
+    "perm": dict(name="c1", nc=40, sub=(4, 4), perm=5),
 }
+
+# matvec kernel family each case's operator is expected to select
+MV_KIND = {"c0": "staged", "c1_64": "staged", "c3_40": "wide", "p1_det": "generic",
+           "c4_ragged": "staged", "j4": "pair", "j2": "staged", "perm": "pair"}
 
 
 def _problem(key):
     kw = dict(CASES[key])
     name = kw.pop("name")
     graph = kw.pop("graph", None)
+    perm = kw.pop("perm", None)
     if name == "jit":
         kw["seed"] = 3
     pr = make_problem(name, **kw)
+    if perm is not None:
+        new = np.random.default_rng(perm).permutation(pr.mesh.n).astype(np.int32)
+        inner = pr.mesh.dof >= 0
+        pr.mesh.dof[inner] = new[pr.mesh.dof[inner]]
+        owner = np.empty_like(pr.owner)
+        owner[new] = pr.owner
+        pr.owner = owner
     if graph is not None:
         # irregular subdomains: multi-source BFS from jittered lattice centres
         from paper_2310_14649_amd.inputs import graph_partition
@@ -143,9 +158,10 @@ def test_assembly_matches_oracle(built, key):
 
 
 # ------------------------------------------------------------------ a3
-@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "j2"])
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "j2", "perm"])
 def test_matvec_matches_oracle(built, key):
     pr, S, g = built(key)
+    assert B.sg_matvec_kernel(g.op) == MV_KIND[key]
     rng = np.random.default_rng(11)
     X = rng.standard_normal((pr.mesh.n, S.P))
     Y = g.new_vec()
