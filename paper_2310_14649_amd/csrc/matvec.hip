@@ -292,7 +292,9 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
 
 // ---------------------------------------------------------------------------
 // Split kernel for a fixed basis (M, PIN, PO) and at most S entries per row.
-// A work-group of four waves covers 128 consecutive rows, two tiles of 64.
+// A work-group of four waves covers 128 consecutive rows, two tiles of 64
+// (two work-groups per CU measured fastest: one tile per group is slower, and
+// so are four, which leave one group per CU).
 // Waves 0 and 2 take the first half of the input terms, waves 1 and 3 the
 // second half, each for the 64 rows of its tile with one row per lane.  With
 // the input terms split between waves instead of between lanes, every triple
@@ -302,8 +304,20 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
 // registers) and shared by the two halves; the second half's partial sums
 // reach the first through LDS.
 namespace split {
-constexpr int kRuns = 4, kSlots = 512, JC = 5, RB = 64, kBlockRows = 128, kThreads = 256;
+constexpr int kRuns = 4, JC = 7, RB = 64;
+constexpr int kTiles = 2;                    // tiles of RB rows per work-group
+constexpr int kBlockRows = kTiles * RB;
+constexpr int kThreads = 2 * 64 * kTiles;    // one wave per (tile, half)
+constexpr int kSlots = 2 * kThreads;         // staged rows: two per thread
 constexpr int kRunWords = 2 * kRuns + 1;
+
+// Block b is dispatched to XCD b % 8; return the block id that makes XCD x
+// take the x-th contiguous share of [0, nb) in order.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = (nb + 7) / 8, full = (nb % 8 == 0) ? 8 : nb % 8;
+    const int x = b & 7, q = b >> 3;
+    return x < full ? x * per + q : full * per + (x - full) * (per - 1) + q;
+}
 
 template <class H, int T>
 __device__ __forceinline__ void tstep(const double* w, double* y) {
@@ -436,10 +450,14 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
                               const double* __restrict__ X, double* Y, double alpha, double beta,
                               const double* C) {
     constexpr int P = tab::cbinom(M + PO, PO);
-    static_assert(2 * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
+    static_assert(kTiles * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
     __shared__ double lds[2 * kSlots * JC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int32_t* rw = runs + (size_t)blockIdx.x * kRunWords;
+    // Work-groups are dealt to the 8 XCDs in turn; renumber them so that each
+    // XCD walks one contiguous range of row blocks, and the neighbour rows a
+    // block stages were mostly fetched into the same L2 by its predecessors.
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int32_t* rw = runs + (size_t)blk * kRunWords;
     int rrow[kRuns], rslot[kRuns];
 #pragma unroll
     for (int q = 0; q < kRuns; ++q) {
@@ -461,7 +479,7 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
     stage_store<P, 0>(lds, tid, st);
 
     const int g = wave & 1, rb = wave >> 1;
-    const int tile = blockIdx.x * 2 + rb;
+    const int tile = blk * kTiles + rb;
     const bool live = tile < ntiles;
     const int tt = live ? tile : 0;
     int slot[S];
