@@ -40,7 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counters, scaled by the counters' reading of a copy of known
 # size (profiles/sg_matvec_512x512_P35_hbm_traffic.txt), keyed by kernel and
 # workload; a workload or kernel without a measurement reports null.
-MEASURED_TRAFFIC = {("kron_matvec_spec_kernel<4, 2, 3, 5, 2>", 261121, 35): 408.1e6}
+MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5>", 261121, 35): 341.3e6}
+MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
+                   "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel"}
 
 
 def log(msg: str) -> None:
@@ -192,6 +194,8 @@ def main() -> int:
                     help="time only the SG matvec (for counter collection) and print its figures")
     ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
                     help="Arnoldi orthogonalisation")
+    ap.add_argument("--ortho-compare", default="mgs",
+                    help="other orthogonalisations timed on the mixed solve (comma list)")
     ap.add_argument("--ras-path", default="auto", choices=["auto", "sweep", "dense"],
                     help="RAS apply path: autotuned per precision, or forced")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
@@ -202,8 +206,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding by subdomains is described in "
-                                   "DESIGN.md but not built)"}))
+                                   "(sharding the subdomains over several GPUs is not built)"}))
         return 2
 
     import torch
@@ -268,7 +271,25 @@ def main() -> int:
         log(f"[bench] solve {prec}: {ms:.2f} ms, its={info['iterations']}, "
             f"relres={info['true_relres']:.2e}")
 
-    mv_kernel = "kron_matvec_spec_kernel<4, 2, 3, 5, 2>" if L == 15 and P == 35 else "kron_matvec"
+    # the same mixed solve with the other orthogonalisations, for comparison
+    ortho_cmp = {}
+    for o in [v for v in args.ortho_compare.split(",") if v and v != args.ortho]:
+        g = solvers[args.mixed]
+        g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph), ortho=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph), ortho=o)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ortho_cmp[o] = dict(ms=round(ms, 3), iterations=info["iterations"],
+                            relres=info["true_relres"])
+        log(f"[bench] solve {args.mixed} with {o}: {ms:.2f} ms, its={info['iterations']}")
+
+    mv_family = B.sg_matvec_kernel(g64.op)
+    mv_kernel = MV_KERNEL_NAMES[mv_family]
+    if mv_family == "staged" and L == 15 and P == 35:
+        mv_kernel += "<4, 2, 3, 5>"
     traffic = MEASURED_TRAFFIC.get((mv_kernel, n, P))
     mv_mean_ms, mv_med_ms = time_matvec(g64, args.mv_launches, torch)
     mv_bytes = matvec_bytes(n, nnz, L, P)
@@ -308,6 +329,7 @@ def main() -> int:
                    "graph": bool(args.graph), "ortho": args.ortho},
         "solves": results,
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / mixed["ms"], 3),
+        "mixed_other_ortho": ortho_cmp,
         "matvec": {"us": round(mv_mean_ms * 1e3, 2), "median_us": round(mv_med_ms * 1e3, 2),
                    "GBps": round(mv_gbs, 1), "frac_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4),
                    "bytes": mv_bytes, "flops": matvec_flops(n, nnz, L, P, T)},

@@ -207,13 +207,25 @@ __global__ __launch_bounds__(kBlk) void jacobi_kernel(int P, const TS* __restric
     }
 }
 
-__global__ void dense_mv_kernel(int N, const double* __restrict__ A, const double* __restrict__ b,
-                                double* __restrict__ x) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+// x = A b for the dense column-major coarsest inverse: a work-group of 256
+// threads per 32 rows, thread (r, part) summing columns part, part + 8, ...;
+// the 8 partial sums of a row are added in a fixed order.
+constexpr int kDenseRows = 32, kDenseParts = 8;
+__global__ __launch_bounds__(kDenseRows * kDenseParts) void dense_mv_kernel(
+    int N, const double* __restrict__ A, const double* __restrict__ b, double* __restrict__ x) {
+    __shared__ double part[kDenseParts][kDenseRows];
+    const int r = threadIdx.x % kDenseRows, pt = threadIdx.x / kDenseRows;
+    const int i = blockIdx.x * kDenseRows + r;
     double acc = 0.0;
-    for (int j = 0; j < N; ++j) acc = fma(A[(size_t)i * N + j], b[j], acc);
-    x[i] = acc;
+    if (i < N)
+        for (int j = pt; j < N; j += kDenseParts) acc = fma(A[(size_t)j * N + i], b[j], acc);
+    part[pt][r] = acc;
+    __syncthreads();
+    if (pt == 0 && i < N) {
+        double t = 0.0;
+        for (int q = 0; q < kDenseParts; ++q) t += part[q][r];
+        x[i] = t;
+    }
 }
 
 uint16_t host_bf16(float f) {
@@ -390,6 +402,18 @@ std::vector<int> aggregate(const Bsr& A) {
     return agg;
 }
 
+// Column-major copy of dense P x P blocks (the coarsest inverse is read by
+// columns, so that consecutive threads read consecutive words).
+template <class T>
+std::vector<T> transpose_blocks(const std::vector<T>& v, int P) {
+    std::vector<T> t(v.size());
+    const size_t bs = (size_t)P * P;
+    for (size_t b0 = 0; b0 < v.size(); b0 += bs)
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j) t[b0 + (size_t)j * P + i] = v[b0 + (size_t)i * P + j];
+    return t;
+}
+
 void upload_bsr(const Bsr& A, DevBuf<int32_t>& ptr, DevBuf<int32_t>& col, DevBuf<double>& val,
                 hipStream_t s) {
     ptr.upload(A.ptr, s);
@@ -404,7 +428,8 @@ void amg_vcycle_level(const sg_amg* a, int l, const double* b, double* x, hipStr
     const AmgLevel& L = a->lev[l];
     if (l == (int)a->lev.size() - 1) {
         int N = a->coarsest_n;
-        dense_mv_kernel<<<(N + 127) / 128, 128, 0, s>>>(N, a->coarsest_inv.p, b, x);
+        dense_mv_kernel<<<(N + kDenseRows - 1) / kDenseRows, kDenseRows * kDenseParts, 0, s>>>(
+            N, a->coarsest_inv.p, b, x);
         HIP_LAUNCH_OK();
         return;
     }
@@ -619,7 +644,7 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
                     for (int j = 0; j < P; ++j)
                         D[(size_t)(r * P + i) * N + Ac.col[q] * P + j] = Ac.blk(q)[(size_t)i * P + j];
         invert_dense(D, N);
-        a->coarsest_inv.upload(D, s);
+        a->coarsest_inv.upload(transpose_blocks(D, N), s);   // column-major
         a->coarsest_n = N;
     }
     HIP_OK(hipStreamSynchronize(s));
