@@ -141,7 +141,7 @@ __global__ void mean_exact_kernel(int ns, int P, const double* __restrict__ inv,
 // work-group of kBlkMv threads per block-row: thread (k, part) sums the
 // block-rows' neighbour blocks part, part + nparts, ... for output row k,
 // then the parts are added in a fixed order through LDS.
-constexpr int kBlkMv = 256;
+constexpr int kBlkMv = 1024;
 __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val,

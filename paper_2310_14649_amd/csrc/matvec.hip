@@ -281,13 +281,20 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
     }
     if (row >= n || ig != 0) return;     // the first lane of a row writes it
     double* yr = Y + (size_t)row * P;
-    const double* cr = C ? C + (size_t)row * P : nullptr;
+    // C may alias Y: the whole row of C is read before any of Y is written,
+    // so the loads are not serialised behind the stores
+    if (beta != 0.0) {
+        double c[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        double o = alpha * y[k];
-        if (beta != 0.0) o = fma(beta, cr[k], o);
-        yr[k] = o;
+        for (int k = 0; k < P; ++k) c[k] = C[(size_t)row * P + k];
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] = fma(beta, c[k], alpha * y[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] *= alpha;
     }
+#pragma unroll
+    for (int k = 0; k < P; ++k) yr[k] = y[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -499,13 +506,19 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
     const int row = tile * RB + lane;
     if (g == 1 || !live || row >= n) return;
     double* yr = Y + (size_t)row * P;
-    const double* cr = C ? C + (size_t)row * P : nullptr;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        double o = alpha * (y[k] + lds[(rb * P + k) * RB + lane]);
-        if (beta != 0.0) o = fma(beta, cr[k], o);
-        yr[k] = o;
+    for (int k = 0; k < P; ++k) y[k] = alpha * (y[k] + lds[(rb * P + k) * RB + lane]);
+    // C may alias Y: the whole row of C is read before any of Y is written,
+    // so the loads are not serialised behind the stores
+    if (beta != 0.0) {
+        double c[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) c[k] = C[(size_t)row * P + k];
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] = fma(beta, c[k], y[k]);
     }
+#pragma unroll
+    for (int k = 0; k < P; ++k) yr[k] = y[k];
 }
 }  // namespace split
 

@@ -394,6 +394,15 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
             }
         }
     };
+    // offset of local row `row`, column k0 + k in Z if the row is owned, else -1
+    auto out_index = [&](int row, int k) -> int64_t {
+        const int g = lgn[row];
+        return g < 0 ? (int64_t)(g & 0x7fffffff) * P + k0 + k : -1;
+    };
+    auto store_out = [&](int64_t o, int k, double x, double zold) {
+        const double v = x * lfac[k];
+        Z[o] = beta != 0.0 ? fma(beta, zold, v) : v;
+    };
     auto write_out = [&](int row, int k, double x) {
         const int g = lgn[row];
         if constexpr (SETUP) {
@@ -470,9 +479,28 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
     {
         const int lv = lv1 - 1;
         const int st = LST(lv), b = LSZ(lv);
-        for (int q = tid; q < b * 16; q += kRasThreads) {
-            const int r = q >> 4, j = q & 15;
-            if (j < kc) write_out(st + r, j, Zp[r * 16 + j]);
+        if constexpr (SETUP) {
+            for (int q = tid; q < b * 16; q += kRasThreads) {
+                const int r = q >> 4, j = q & 15;
+                if (j < kc) write_out(st + r, j, Zp[r * 16 + j]);
+            }
+        } else {
+            // Z may be accumulated into: every old value is read before the
+            // first store, so the loads do not wait behind the stores
+            constexpr int NO = (BM * 16 + kRasThreads - 1) / kRasThreads;
+            int64_t zo[NO];
+            double zold[NO];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const int q = tid + o * kRasThreads, r = q >> 4, j = q & 15;
+                zo[o] = (r < b && j < kc) ? out_index(st + r, j) : -1;
+                zold[o] = (beta != 0.0 && zo[o] >= 0) ? Z[zo[o]] : 0.0;
+            }
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const int q = tid + o * kRasThreads, r = q >> 4, j = q & 15;
+                if (zo[o] >= 0) store_out(zo[o], j, Zp[r * 16 + j], zold[o]);
+            }
         }
     }
     if (lv1 - 2 < lv0) return;
@@ -507,6 +535,17 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
             prefetch_rows(lv - 1, false);
         }
         if (wave < rp_of(b) / 16) {
+            // old values of the owned outputs are fetched before the product
+            int64_t zo[4];
+            double zold[4];
+            if constexpr (!SETUP) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * wave + MM::row_of(lane, v), j = lane & 15;
+                    zo[v] = (r < b && j < kc) ? out_index(st + r, j) : -1;
+                    zold[v] = (beta != 0.0 && zo[v] >= 0) ? Z[zo[v]] : 0.0;
+                }
+            }
             const auto acc = product(b);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -514,7 +553,10 @@ __global__ __launch_bounds__(kRasThreads) void ras_apply_kernel(
                 if (r < b && j < kc) {
                     const double x = zcur[v] - (double)acc[v];
                     Xc[r * 16 + j] = x;
-                    write_out(st + r, j, x);
+                    if constexpr (SETUP)
+                        write_out(st + r, j, x);
+                    else if (zo[v] >= 0)
+                        store_out(zo[v], j, x, zold[v]);
                 }
             }
         }
@@ -649,22 +691,38 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
         compute(1);
     }
     if (k < L) compute(0);          // L / KSUP odd: the last super-step is in buffer 0
+    // Z may be accumulated into: per row tile, the old values are all read
+    // before the first store, so the loads do not wait behind each store
     const int64_t ob = own_off[s];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m) {
+        int64_t zo[4];
+        double zold[NT][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * m + Mma<TS>::row_of(lane, v);
+            zo[v] = r < no ? (int64_t)own_gnode[ob + r] * P : -1;
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = r0 + 16 * m + Mma<TS>::row_of(lane, v);
                 const int n = 16 * t + i;
-                if (r < no && n < P) {
-                    const size_t o = (size_t)own_gnode[ob + r] * P + n;
+                zold[t][v] = (beta != 0.0 && zo[v] >= 0 && n < P) ? Z[zo[v] + n] : 0.0;
+            }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = 16 * t + i;
+                if (zo[v] >= 0 && n < P) {
                     const double val = omega * (double)acc[m][t][v] / afact[n];
-                    Z[o] = beta != 0.0 ? fma(beta, Z[o], val) : val;
+                    Z[zo[v] + n] = beta != 0.0 ? fma(beta, zold[t][v], val) : val;
                 }
             }
+    }
 }
+
 
 __global__ void narrow_kernel(int64_t n, const double* __restrict__ x, float* __restrict__ y32,
                               uint16_t* __restrict__ y16) {
