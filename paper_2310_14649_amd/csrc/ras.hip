@@ -585,9 +585,12 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(
     TS* out = xg + xoff[s];
     for (int n0 = 0; n0 < P; n0 += 64) {
         const int nn = min(64, P - n0);
-        for (int e = tid; e < nq * 64; e += 256) {
-            const int qq = e >> 6, nl = e & 63;
-            tile[qq][nl] = nl < nn ? R[(size_t)gnode[node0 + q0 + qq] * P + n0 + nl] : 0.0;
+        // consecutive threads read consecutive columns of a node, then the next
+        // node: every lane carries a value, and nodes with consecutive global
+        // numbers give contiguous reads
+        for (int e = tid; e < nq * nn; e += 256) {
+            const int qq = e / nn, nl = e - qq * nn;
+            tile[qq][nl] = R[(size_t)gnode[node0 + q0 + qq] * P + n0 + nl];
         }
         __syncthreads();
         for (int e = tid; e < nn * 64; e += 256) {
