@@ -321,7 +321,9 @@ void sg_destroy_nl(sg_nl* nl);
  * (device, [n x P], overwritten by the last iterate).  Step k:
  *   eta_k = max(1e-12, min(eta_max, ||R_k|| / ||F||));
  *   RAS on K1 (mean-coefficient local solves, subdomains `owner`, overlap)
- *   and the coarse solver `coarse` on the Jacobian, both rebuilt;
+ *   refactored, and the coarse solver `coarse` on the Jacobian built at the
+ *   first step and rebuilt every amg_rebuild steps after it (0: never: the
+ *   coarse problem of the first Jacobian is kept, a lagged preconditioner);
  *   FGMRES(restart) solves J d = R_k to relative tolerance eta_k from d = 0;
  *   lambda = 1, halved (at most 9 times) until
  *   ||R(U + lambda d)|| <= (1 - 1e-4 lambda) ||R_k||, the last trial taken
@@ -342,6 +344,7 @@ typedef struct {
     double omega;        /* smoother damping (<= 0: estimate per step)  */
     int use_graph;       /* as in sg_krylov_opts                        */
     int ortho;           /* as in sg_krylov_opts                        */
+    int amg_rebuild;     /* coarse-solver rebuild interval in steps (>= 0) */
 } sg_newton_opts;
 
 typedef struct {

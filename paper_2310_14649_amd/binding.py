@@ -48,7 +48,7 @@ class KrylovStats(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
                 ("restart", C.c_int), ("max_it", C.c_int), ("omega", C.c_double),
-                ("use_graph", C.c_int), ("ortho", C.c_int)]
+                ("use_graph", C.c_int), ("ortho", C.c_int), ("amg_rebuild", C.c_int)]
 
 
 class NewtonStats(C.Structure):
@@ -431,10 +431,11 @@ def newton_workspace_bytes(nl, n_sub: int, coarse: int, restart: int) -> int:
 def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coarse: int, U,
                  ws, max_steps: int = 30, tol: float = 1e-8, eta_max: float = 1e-2,
                  restart: int = 50, max_it: int = 1000, omega: float = 0.0,
-                 use_graph: bool = False, history_cap: int = 64, ortho: str = "mgs", stream=None):
+                 use_graph: bool = False, history_cap: int = 64, ortho: str = "mgs",
+                 amg_rebuild: int = 0, stream=None):
     owner = np.ascontiguousarray(owner, dtype=np.int32)
     opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0,
-                      ORTHO[ortho])
+                      ORTHO[ortho], amg_rebuild)
     hist = np.zeros(history_cap, dtype=np.float64)
     kits = np.zeros(history_cap, dtype=np.int32)
     st = NewtonStats()

@@ -585,6 +585,7 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
         SG_REQUIRE(opts->restart >= 1 && opts->restart <= 64, "restart outside [1,64]");
         SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
         SG_REQUIRE(opts->eta_max > 0.0 && opts->eta_max < 1.0, "eta_max outside (0,1)");
+        SG_REQUIRE(opts->amg_rebuild >= 0, "amg_rebuild must be >= 0");
         const size_t need = newton_ws(nl->n, nl->P, n_sub, coarse, opts->restart);
         if (!ws || ws_bytes < need)
             SG_THROW(SG_ERR_WORKSPACE, "newton workspace too small (%zu < %zu)", ws_bytes, need);
@@ -638,7 +639,6 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             eta = std::min(opts->eta_max, std::max(eta, 0.5 * opts->tol * Fn / rn));
             // preconditioner of the current Jacobian
             t0 = clock::now();
-            amg.reset();
             if (!ras) {
                 sg_ras* r = nullptr;
                 check_status(ras_setup(nl->j1.get(), owner, n_sub, overlap, prec, &r, stream),
@@ -647,7 +647,9 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             } else {
                 check_status(ras_refactor(ras.get(), nl->j1.get(), stream), "ras_refactor");
             }
-            if (coarse != SG_COARSE_NONE) {
+            const bool rebuild = !amg || (opts->amg_rebuild > 0 && steps % opts->amg_rebuild == 0);
+            if (coarse != SG_COARSE_NONE && rebuild) {
+                amg.reset();
                 sg_amg* a = nullptr;
                 check_status(amg_setup(nl->jac.get(), ras.get(), coarse, prec, &a, stream),
                              "amg_setup");

@@ -157,13 +157,14 @@ class GpuNewton:
 
     def solve(self, U0=None, tol: float = 1e-8, max_steps: int = 30, restart: Optional[int] = None,
               max_it: int = 1000, eta_max: float = 1e-2, omega: float = 0.0,
-              use_graph: bool = False):
+              use_graph: bool = False, amg_rebuild: int = 0):
         restart = self.pr.restart if restart is None else restart
         U = self.new_vec() if U0 is None else U0.clone()
         info = B.newton_solve(self.nl, self.owner, self.n_sub, self.overlap, B.PREC[self.prec],
                               COARSE[self.coarse], U, self.workspace(restart), max_steps=max_steps,
                               tol=tol, eta_max=eta_max, restart=restart, max_it=max_it,
-                              omega=omega, use_graph=use_graph, stream=self.stream)
+                              omega=omega, use_graph=use_graph, amg_rebuild=amg_rebuild,
+                              stream=self.stream)
         return U, info
 
     def close(self):

@@ -169,6 +169,23 @@ def test_newton_config4_converges_and_is_reproducible():
         assert rel <= 1e-8
 
 
+def test_lagged_coarse_solver_matches_rebuilt():
+    """The coarse hierarchy built once at the first Newton step (the default)
+    and rebuilt at every step give the same solution; the lagged one does
+    not need more Krylov iterations on this weakly nonlinear problem."""
+    _cuda()
+    pr = _problem("m4p3")
+    with GpuNewton(pr) as g:
+        U0, i0 = g.solve(tol=1e-12, restart=30, amg_rebuild=0)
+        U1, i1 = g.solve(tol=1e-12, restart=30, amg_rebuild=1)
+        U2, i2 = g.solve(tol=1e-12, restart=30, amg_rebuild=2)
+    for info in (i0, i1, i2):
+        assert info["converged"] and info["relres"] <= 1e-12
+    assert float(torch.linalg.norm(U0 - U1) / torch.linalg.norm(U1)) < 1e-9
+    assert float(torch.linalg.norm(U2 - U1) / torch.linalg.norm(U1)) < 1e-9
+    assert i0["krylov_its"] <= i1["krylov_its"] + 3
+
+
 def test_backtracking_from_a_poor_guess():
     """From a rough random guess the full Newton step overshoots (the oracle
     cuts lambda to 1/4 at its first step): the iteration still converges to
@@ -194,6 +211,8 @@ def test_newton_rejects_bad_arguments():
             g.solve(tol=-1.0)
         with pytest.raises(B.SgError):
             g.solve(eta_max=1.5)
+        with pytest.raises(B.SgError):
+            g.solve(amg_rebuild=-1)
         small = torch.empty(16, dtype=torch.float64, device="cuda")
         with pytest.raises(B.SgError):
             B.newton_solve(g.nl, g.owner, g.n_sub, g.overlap, B.SG_FP64, B.SG_COARSE_AMG,
