@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counters, scaled by the counters' reading of a copy of known
 # size (profiles/sg_matvec_512x512_P35_hbm_traffic.txt), keyed by kernel and
 # workload; a workload or kernel without a measurement reports null.
-MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5>", 261121, 35): 341.3e6}
+MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5>", 261121, 35): 336.1e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
                    "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel"}
 
