@@ -221,7 +221,8 @@ int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho
  * confirmed by the true residual ||b - A x||; restart from x otherwise.
  * x holds the initial guess on entry and the solution on return (device).
  * ras/amg may be NULL (no preconditioner / one-level).  ws: device
- * workspace of at least fgmres_workspace_bytes(op, amg, restart).
+ * workspace of at least fgmres_workspace_bytes(op, amg, restart), 256-byte
+ * aligned (SG_ERR_INVALID_ARG otherwise).
  * Returns SG_OK, SG_NOT_CONVERGED (max_it reached) or an error.
  * Synchronous; the host reads one residual estimate per iteration.
  * With use_graph, step j (preconditioner cycle, matvec, the j+1 Gram-Schmidt
@@ -331,7 +332,8 @@ void sg_destroy_nl(sg_nl* nl);
  * The forcing term is safeguarded against over-solving the last steps:
  * eta_k = min(eta_max, max(eta_k, 0.5 tol ||F|| / ||R_k||)).
  * Stops when ||R|| / ||F|| <= tol (||F|| = norm of F e_0).  ws: device
- * workspace of newton_workspace_bytes(nl, n_sub, coarse, restart) bytes.
+ * workspace of newton_workspace_bytes(nl, n_sub, coarse, restart) bytes,
+ * 256-byte aligned.
  * Returns SG_OK, SG_NOT_CONVERGED (max_steps reached) or an error.
  * Synchronous.
  * ---------------------------------------------------------------------- */

@@ -120,11 +120,25 @@ __global__ __launch_bounds__(kVT) void cgs_dot_kernel(int64_t N, int nb, int ni,
     double acc[kCgsIB + 1];
 #pragma unroll
     for (int q = 0; q <= kCgsIB; ++q) acc[q] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
-        const double we = w[e];
+    // pairs of elements through 16-byte loads (V's columns start 256-byte
+    // aligned), an odd last element by the first thread
+    const int64_t N2 = N >> 1;
+    const double2* w2 = reinterpret_cast<const double2*>(w);
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N2; e += (int64_t)gridDim.x * kVT) {
+        const double2 we = w2[e];
 #pragma unroll
         for (int q = 0; q < kCgsIB; ++q)
-            if (q < cnt) acc[q] = fma(we, V[(size_t)(ib0 + q) * ldv + e], acc[q]);
+            if (q < cnt) {
+                const double2 v = reinterpret_cast<const double2*>(V + (size_t)(ib0 + q) * ldv)[e];
+                acc[q] = fma(we.y, v.y, fma(we.x, v.x, acc[q]));
+            }
+        if (with_ww) acc[kCgsIB] = fma(we.y, we.y, fma(we.x, we.x, acc[kCgsIB]));
+    }
+    if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double we = w[N - 1];
+#pragma unroll
+        for (int q = 0; q < kCgsIB; ++q)
+            if (q < cnt) acc[q] = fma(we, V[(size_t)(ib0 + q) * ldv + N - 1], acc[q]);
         if (with_ww) acc[kCgsIB] = fma(we, we, acc[kCgsIB]);
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -454,6 +468,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     const size_t need = fgmres_ws_np(A.n, A.P, amg, m);
     if (!ws || ws_bytes < need)
         SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
+    SG_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, "workspace must be 256-byte aligned");
     const int64_t N = (int64_t)A.n * A.P;
     const size_t vb = align_up(N * 8);
     char* p = reinterpret_cast<char*>(ws);
