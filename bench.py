@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counters, scaled by the counters' reading of a copy of known
 # size (profiles/sg_matvec_512x512_P35_hbm_traffic.txt), keyed by kernel and
 # workload; a workload or kernel without a measurement reports null.
-MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5>", 261121, 35): 336.1e6}
+MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 2>", 261121, 35): 336.1e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
                    "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel"}
 
@@ -248,8 +248,8 @@ def main() -> int:
         solvers[prec] = GpuSG(pr, prec=prec, coarse="amg", ras_path=args.ras_path)
         torch.cuda.synchronize()
         setup_s[prec] = time.perf_counter() - t0
-        ras_paths[prec] = dict(path="dense" if B.ras_path_info(solvers[prec].ras)[0] else "sweep",
-                               ms=solvers[prec].ras_ms)
+        ras_paths[prec] = dict(path=B.ras_path_info(solvers[prec].ras)[2],
+                               ms_sweep_dense_dense32=solvers[prec].ras_ms)
         log(f"[bench] setup {prec}: {setup_s[prec]:.2f} s, RAS {ras_paths[prec]}")
     g64 = solvers["fp64"]
     n, P, L, nnz = g64.n, g64.P, g64.L, g64.nnz
@@ -298,8 +298,9 @@ def main() -> int:
 
     mv_family = B.sg_matvec_kernel(g64.op)
     mv_kernel = MV_KERNEL_NAMES[mv_family]
+    mv_tiles = B.sg_matvec_tiles(g64.op)
     if mv_family == "staged" and L == 15 and P == 35:
-        mv_kernel += "<4, 2, 3, 5>"
+        mv_kernel += f"<4, 2, 3, 5, {mv_tiles}>"
     traffic = MEASURED_TRAFFIC.get((mv_kernel, n, P))
     mv_mean_ms, mv_med_ms = time_matvec(g64, args.mv_launches, torch)
     mv_bytes = matvec_bytes(n, nnz, L, P)
@@ -341,6 +342,7 @@ def main() -> int:
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / mixed["ms"], 3),
         "mixed_other_ortho": ortho_cmp,
         "matvec": {"us": round(mv_mean_ms * 1e3, 2), "median_us": round(mv_med_ms * 1e3, 2),
+                   "tiles_per_group": mv_tiles, "autotune_ms_1_2_4_tiles": g64.mv_ms,
                    "GBps": round(mv_gbs, 1), "frac_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4),
                    "bytes": mv_bytes, "flops": matvec_flops(n, nnz, L, P, T)},
         "roofline": {"bound": "hbm", "kernel": mv_kernel, "achieved": round(mv_gbs, 1),

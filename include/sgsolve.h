@@ -127,6 +127,19 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * few runs of consecutive rows per block of 128).  Host call. */
 enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3 };
 int sg_matvec_kernel(const sg_op* op, int* kind);
+/* Work-group shape of the staged kernel: 1, 2 or 4 tiles of 64 rows per
+ * work-group (2 after assembly when it fits).  sg_matvec_autotune times
+ * `reps` launches of every shape that fits (HIP events on `stream`, on an
+ * internal zero input), keeps the fastest and writes ms_out[3] (ms per
+ * launch for 1, 2, 4 tiles; -1 where a shape does not fit); synchronous.
+ * sg_matvec_select sets a shape directly (e.g. a cached tuning result);
+ * sg_matvec_tiles reads it (0 for the other kernel families).  Both return
+ * SG_ERR_UNSUPPORTED for operators without the staged kernel or a shape
+ * that does not fit.  A new shape drops the captured Arnoldi-step graphs of
+ * the operator.  Not to be called while the operator is in use. */
+int sg_matvec_autotune(sg_op* op, int reps, double* ms_out, void* stream);
+int sg_matvec_select(sg_op* op, int tiles);
+int sg_matvec_tiles(const sg_op* op, int* tiles);
 
 /* ------------------------------------------------------------------------
  * ras_setup / ras_apply -- one-level restricted additive Schwarz, Eq. RASsto:
@@ -156,13 +169,16 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
  * ras precision; an apply is then one matrix-core product per subdomain
  * (owned rows x local nodes times local nodes x P), whose bytes scale with
  * the precision.  Both compute the same operator (up to rounding).
- * ras_select: 0 = sweep, 1 = dense (built on first use; device memory
+ * ras_select: 0 = sweep, 1 = dense with 64 owned rows per wave, 2 = dense
+ *   with 32 (the dense rows are built on first use; device memory
  *   sum_s n_own(s) * n_local(s) entries).  Synchronous.
  * ras_autotune: builds the dense rows if needed, times `reps` applies of
- *   each path with HIP events on `stream`, keeps the faster; ms (host [2],
- *   may be NULL): sweep, dense.  Synchronous.
- * ras_path_info: current path (1 = dense) and the bytes of the dense rows
- *   (0 if not built).  A refactorisation rebuilds the dense rows. */
+ *   each of the three with HIP events on `stream` (internal zero input),
+ *   keeps the fastest; ms (host [3], may be NULL): in the order above.
+ *   Synchronous.
+ * ras_path_info: current path (as for ras_select) and the bytes of the
+ *   dense rows (0 if not built).  A refactorisation rebuilds the dense rows.
+ * A new path drops the captured Arnoldi-step graphs that use the handle. */
 int ras_select(sg_ras* r, int dense, void* stream);
 int ras_autotune(sg_ras* r, int reps, double* ms, void* stream);
 int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes);

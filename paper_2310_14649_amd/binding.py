@@ -75,6 +75,9 @@ _SIGS = {
     "sg_destroy_op": (None, [_vp]),
     "sg_matvec": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_matvec_kernel": (C.c_int, [_vp, C.POINTER(C.c_int)]),
+    "sg_matvec_autotune": (C.c_int, [_vp, C.c_int, _f64p, _vp]),
+    "sg_matvec_select": (C.c_int, [_vp, C.c_int]),
+    "sg_matvec_tiles": (C.c_int, [_vp, C.POINTER(C.c_int)]),
     "ras_setup": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "ras_refactor": (C.c_int, [_vp, _vp, _vp]),
     "ras_select": (C.c_int, [_vp, C.c_int, _vp]),
@@ -252,6 +255,24 @@ def sg_matvec_kernel(op) -> str:
     return MV_KERNELS[k.value]
 
 
+def sg_matvec_autotune(op, reps: int = 10, stream=None):
+    """ms per launch for 1, 2 and 4 tiles per work-group (None: does not fit);
+    the fastest is kept."""
+    ms = np.zeros(3, dtype=np.float64)
+    _check(lib().sg_matvec_autotune(op, reps, _ptr(ms, C.c_double), _stream(stream)))
+    return [float(v) if v >= 0 else None for v in ms]
+
+
+def sg_matvec_select(op, tiles: int):
+    _check(lib().sg_matvec_select(op, tiles))
+
+
+def sg_matvec_tiles(op) -> int:
+    t = C.c_int()
+    _check(lib().sg_matvec_tiles(op, C.byref(t)))
+    return t.value
+
+
 # ---------------------------------------------------------------- RAS
 def ras_setup(op, owner: np.ndarray, n_sub: int, overlap: int, prec: int = SG_FP64,
               stream=None):
@@ -266,21 +287,31 @@ def ras_refactor(r, op, stream=None):
     _check(lib().ras_refactor(r, op, _stream(stream)))
 
 
-def ras_select(r, dense: bool, stream=None):
-    _check(lib().ras_select(r, 1 if dense else 0, _stream(stream)))
+RAS_PATHS = {"sweep": 0, "dense": 1, "dense32": 2}
+
+
+def ras_select(r, dense, stream=None):
+    """dense: False/True (sweep / dense with 64 rows per wave) or a path name
+    of RAS_PATHS."""
+    path = RAS_PATHS[dense] if isinstance(dense, str) else (1 if dense else 0)
+    _check(lib().ras_select(r, path, _stream(stream)))
 
 
 def ras_autotune(r, reps: int = 5, stream=None):
-    ms = np.zeros(2, dtype=np.float64)
+    """ms per apply of the sweep, dense (64 rows per wave) and dense32 paths;
+    the fastest is kept."""
+    ms = np.zeros(3, dtype=np.float64)
     _check(lib().ras_autotune(r, reps, _ptr(ms, C.c_double), _stream(stream)))
-    return float(ms[0]), float(ms[1])
+    return float(ms[0]), float(ms[1]), float(ms[2])
 
 
 def ras_path_info(r):
+    """(dense in use, bytes of the dense rows, path name)."""
     d = C.c_int()
     nb = C.c_int64()
     _check(lib().ras_path_info(r, C.byref(d), C.byref(nb)))
-    return bool(d.value), nb.value
+    name = {v: k for k, v in RAS_PATHS.items()}[d.value]
+    return d.value > 0, nb.value, name
 
 
 def ras_info(r, n_sub: int):

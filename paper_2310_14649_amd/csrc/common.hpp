@@ -146,7 +146,7 @@ struct KronCsr {
     // optional staged copy used by the split kernels (id -1 = none): per
     // block of rows, the runs of neighbour rows staged in LDS, and each
     // entry's column as an index into that staging area
-    int split = -1;
+    int split = -1, split_kt = 0;      // split_kt: tiles of 64 rows per work-group
     const int32_t* sruns = nullptr;    // [blocks][2*kRuns+1]
     const int16_t* sslot = nullptr;    // [tiles][S][64]
     const double* svals = nullptr;     // [tiles][S][L][64]
@@ -176,8 +176,10 @@ struct sg_op {
     sg::DevBuf<int32_t> ecol;
     sg::DevBuf<double> evals;
     int split = -1;
-    sg::DevBuf<int32_t> sruns;
-    sg::DevBuf<int16_t> sslot;
+    int split_var = 0;                 // selected tile count: 1, 2, 4 tiles for 0, 1, 2
+    bool split_fits[3] = {false, false, false};
+    sg::DevBuf<int32_t> sruns[3];
+    sg::DevBuf<int16_t> sslot[3];
     sg::DevBuf<double> svals;
     // host copies used by the setup of the preconditioner
     std::vector<int32_t> h_rowptr, h_col;
@@ -191,7 +193,8 @@ struct sg_op {
         k.n = n; k.nnz = nnz; k.max_row = max_row;
         k.rowptr = rowptr.p; k.col = col.p; k.vals = vals.p;
         k.spec = spec; k.ell_S = ell_S; k.ell_RW = ell_RW; k.ecol = ecol.p; k.evals = evals.p;
-        k.split = split; k.sruns = sruns.p; k.sslot = sslot.p; k.svals = svals.p;
+        k.split = split; k.split_kt = 1 << split_var;
+        k.sruns = sruns[split_var].p; k.sslot = sslot[split_var].p; k.svals = svals.p;
         return k;
     }
 };

@@ -299,11 +299,10 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
 
 // ---------------------------------------------------------------------------
 // Split kernel for a fixed basis (M, PIN, PO) and at most S entries per row.
-// A work-group of four waves covers 128 consecutive rows, two tiles of 64
-// (two work-groups per CU measured fastest: one tile per group is slower, and
-// so are four, which leave one group per CU).
-// Waves 0 and 2 take the first half of the input terms, waves 1 and 3 the
-// second half, each for the 64 rows of its tile with one row per lane.  With
+// A work-group of 2 KT waves covers KT tiles of 64 consecutive rows (KT = 1,
+// 2 or 4, chosen per operator by timing).  Even waves take the first half of
+// the input terms, odd waves the second half, each for the 64 rows of its
+// tile with one row per lane.  With
 // the input terms split between waves instead of between lanes, every triple
 // a wave executes belongs to it and the coefficients stay immediates.  The
 // neighbour rows of the block -- a few runs of consecutive rows, found at
@@ -312,11 +311,17 @@ __global__ __launch_bounds__(kThreads) void kron_matvec_spec_kernel(
 // reach the first through LDS.
 namespace split {
 constexpr int kRuns = 4, JC = 7, RB = 64;
-constexpr int kTiles = 2;                    // tiles of RB rows per work-group
-constexpr int kBlockRows = kTiles * RB;
-constexpr int kThreads = 2 * 64 * kTiles;    // one wave per (tile, half)
-constexpr int kSlots = 2 * kThreads;         // staged rows: two per thread
 constexpr int kRunWords = 2 * kRuns + 1;
+constexpr int kTileChoices[] = {1, 2, 4};    // tiles of RB rows per work-group
+constexpr int kNumTileChoices = 3;
+// work-group shape for KT tiles: one wave per (tile, half), two staged rows
+// per thread
+template <int KT>
+struct Shape {
+    static constexpr int kBlockRows = KT * RB;
+    static constexpr int kThreads = 2 * 64 * KT;
+    static constexpr int kSlots = 2 * kThreads;
+};
 
 // Block b is dispatched to XCD b % 8; return the block id that makes XCD x
 // take the x-th contiguous share of [0, nb) in order.
@@ -397,36 +402,38 @@ __device__ __forceinline__ void stage_load(const double* __restrict__ X, const i
     }
 }
 
-template <int P, int C>
+template <int P, int C, int KT>
 __device__ __forceinline__ void stage_store(double* buf, int tid, const double (*st)[JC]) {
     constexpr int W = chunk_width<P, C>();
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int jj = 0; jj < W; ++jj) buf[(tid + kThreads * m) * JC + jj] = st[m][jj];
+        for (int jj = 0; jj < W; ++jj)
+            buf[(tid + Shape<KT>::kThreads * m) * JC + jj] = st[m][jj];
 }
 
-template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int C>
+template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int KT, int C>
 __device__ __forceinline__ void chunk(const int* slot, const double (*v)[8], double* lds,
                                       double (*st)[JC], const double* __restrict__ X,
                                       const int* srow, int tid, double* y) {
+    constexpr int NS = Shape<KT>::kSlots;
     if constexpr (C + 1 < NCH) stage_load<P, C + 1>(X, srow, st);
     columns<M, PIN, PO, S, G, LI, C * JC>(std::make_integer_sequence<int, chunk_width<P, C>()>{},
-                                          slot, v, lds + (C & 1) * kSlots * JC, y);
-    if constexpr (C + 1 < NCH) stage_store<P, C + 1>(lds + ((C + 1) & 1) * kSlots * JC, tid, st);
+                                          slot, v, lds + (C & 1) * NS * JC, y);
+    if constexpr (C + 1 < NCH) stage_store<P, C + 1, KT>(lds + ((C + 1) & 1) * NS * JC, tid, st);
     __syncthreads();
 }
 
-template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int... Cs>
+template <int M, int PIN, int PO, int S, int G, int LI, int P, int NCH, int KT, int... Cs>
 __device__ __forceinline__ void chunks(std::integer_sequence<int, Cs...>, const int* slot,
                                        const double (*v)[8], double* lds, double (*st)[JC],
                                        const double* __restrict__ X, const int* srow, int tid,
                                        double* y) {
-    (chunk<M, PIN, PO, S, G, LI, P, NCH, Cs>(slot, v, lds, st, X, srow, tid, y), ...);
+    (chunk<M, PIN, PO, S, G, LI, P, NCH, KT, Cs>(slot, v, lds, st, X, srow, tid, y), ...);
 }
 
 // One half of the input terms over the whole row: G = 0 takes i < ceil(L/2).
-template <int M, int PIN, int PO, int S, int G>
+template <int M, int PIN, int PO, int S, int G, int KT>
 __device__ __forceinline__ void half(int tile, int r, const int* slot,
                                      const double* __restrict__ svals, double* lds,
                                      double (*st)[JC], const double* __restrict__ X,
@@ -446,18 +453,19 @@ __device__ __forceinline__ void half(int tile, int r, const int* slot,
 #pragma unroll
     for (int k = 0; k < P; ++k) y[k] = 0.0;
     __syncthreads();   // chunk 0 staged
-    chunks<M, PIN, PO, S, G, LI, P, NCH>(std::make_integer_sequence<int, NCH>{}, slot, v, lds, st,
-                                         X, srow, tid, y);
+    chunks<M, PIN, PO, S, G, LI, P, NCH, KT>(std::make_integer_sequence<int, NCH>{}, slot, v, lds,
+                                             st, X, srow, tid, y);
 }
 
-template <int M, int PIN, int PO, int S>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+template <int M, int PIN, int PO, int S, int KT>
+__global__ __launch_bounds__(Shape<KT>::kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ runs,
                               const int16_t* __restrict__ sslot, const double* __restrict__ svals,
                               const double* __restrict__ X, double* Y, double alpha, double beta,
                               const double* C) {
     constexpr int P = tab::cbinom(M + PO, PO);
-    static_assert(kTiles * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
+    constexpr int kThreads = Shape<KT>::kThreads, kSlots = Shape<KT>::kSlots;
+    static_assert(KT * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
     __shared__ double lds[2 * kSlots * JC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // Work-groups are dealt to the 8 XCDs in turn; renumber them so that each
@@ -483,10 +491,10 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
     }
     double st[2][JC];
     stage_load<P, 0>(X, srow, st);
-    stage_store<P, 0>(lds, tid, st);
+    stage_store<P, 0, KT>(lds, tid, st);
 
     const int g = wave & 1, rb = wave >> 1;
-    const int tile = blk * kTiles + rb;
+    const int tile = blk * KT + rb;
     const bool live = tile < ntiles;
     const int tt = live ? tile : 0;
     int slot[S];
@@ -494,9 +502,9 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
     for (int q = 0; q < S; ++q) slot[q] = sslot[((size_t)tt * S + q) * RB + lane];
     double y[P];
     if (g == 0)
-        half<M, PIN, PO, S, 0>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+        half<M, PIN, PO, S, 0, KT>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
     else
-        half<M, PIN, PO, S, 1>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+        half<M, PIN, PO, S, 1, KT>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
     // the staging area is free after the last chunk's barrier
     if (g == 1) {
 #pragma unroll
@@ -556,21 +564,33 @@ struct SplitSpec {
 };
 constexpr SplitSpec kSplits[] = {{2, 2, 2, 5}, {2, 2, 2, 7}, {4, 2, 3, 5}};
 
+template <int Id, int KT>
+void launch_split_kt(const KronCsr& A, const double* X, double* Y, double alpha, double beta,
+                     const double* C, hipStream_t s) {
+    constexpr SplitSpec sp = kSplits[Id];
+    using Sh = split::Shape<KT>;
+    const int tiles = (A.n + split::RB - 1) / split::RB;
+    const int blocks = (A.n + Sh::kBlockRows - 1) / Sh::kBlockRows;
+    split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S, KT>
+        <<<blocks, Sh::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha, beta,
+                                         C);
+}
+
 template <int Id>
 void launch_split(const KronCsr& A, const double* X, double* Y, double alpha, double beta,
                   const double* C, hipStream_t s) {
-    constexpr SplitSpec sp = kSplits[Id];
-    const int tiles = (A.n + split::RB - 1) / split::RB;
-    const int blocks = (A.n + split::kBlockRows - 1) / split::kBlockRows;
-    split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S>
-        <<<blocks, split::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha,
-                                            beta, C);
+    switch (A.split_kt) {
+        case 1: launch_split_kt<Id, 1>(A, X, Y, alpha, beta, C, s); break;
+        case 2: launch_split_kt<Id, 2>(A, X, Y, alpha, beta, C, s); break;
+        case 4: launch_split_kt<Id, 4>(A, X, Y, alpha, beta, C, s); break;
+        default: SG_THROW(SG_ERR_INVALID_ARG, "bad tiles per work-group %d", A.split_kt);
+    }
 }
 
 // Neighbour rows of one block of rows as at most kRuns runs of consecutive
 // rows (the smallest gaps merged first), laid out one after the other in the
-// staging area.  False when they need more than kSlots staged rows.
-bool block_runs(std::vector<int32_t>& cols, int32_t* words) {
+// staging area.  False when they need more than `slots` staged rows.
+bool block_runs(std::vector<int32_t>& cols, int slots, int32_t* words) {
     std::sort(cols.begin(), cols.end());
     cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
     std::vector<int32_t> start, end;   // [start, end)
@@ -597,11 +617,45 @@ bool block_runs(std::vector<int32_t>& cols, int32_t* words) {
         if (used) base += end[q] - start[q];
     }
     words[2 * split::kRuns] = base;
-    return base <= split::kSlots;
+    return base <= slots;
 }
 
-// Staged copy for the split kernel: per block the runs, per (tile, entry,
-// lane) the staging index of the entry's column and its L values.
+// Per block of KT tiles: the runs, and per (tile, entry, lane) the staging
+// index of the entry's column.  False when a block does not fit.
+bool split_staging(const sg_op* op, int S, int KT, std::vector<int32_t>& runs,
+                   std::vector<int16_t>& slot) {
+    const int RB = split::RB, n = op->n;
+    const int rows = KT * RB, slots = 2 * 2 * 64 * KT;
+    const int tiles = (n + RB - 1) / RB;
+    const int blocks = (n + rows - 1) / rows;
+    runs.assign((size_t)blocks * split::kRunWords, 0);
+    slot.assign((size_t)tiles * S * RB, 0);
+    std::vector<int32_t> cols;
+    for (int blk = 0; blk < blocks; ++blk) {
+        const int a0 = blk * rows, a1 = std::min(n, a0 + rows);
+        cols.assign(op->h_col.begin() + op->h_rowptr[a0], op->h_col.begin() + op->h_rowptr[a1]);
+        for (int a = a0; a < a1; ++a) cols.push_back(a);   // padding entries read the own row
+        int32_t* w = runs.data() + (size_t)blk * split::kRunWords;
+        if (!block_runs(cols, slots, w)) return false;
+        auto staged = [&](int32_t c) {
+            int q = split::kRuns - 1;
+            while (w[split::kRuns + q] == (1 << 30) || c < w[q]) --q;
+            return (int16_t)(w[split::kRuns + q] + (c - w[q]));
+        };
+        for (int a = a0; a < a1; ++a) {
+            const int t = a / RB, r = a % RB;
+            int q = 0;
+            for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q)
+                slot[((size_t)t * S + q) * RB + r] = staged(op->h_col[e]);
+            for (; q < S; ++q) slot[((size_t)t * S + q) * RB + r] = staged(a);
+        }
+    }
+    return true;
+}
+
+// Staged copy for the split kernel: the L values per (tile, entry, lane),
+// and the staging of every tile count that fits (two tiles per group when
+// that fits, the default until sg_matvec_autotune or sg_matvec_select).
 bool build_split(sg_op* op, hipStream_t s) {
     const sg_basis& b = op->basis;
     int id = -1;
@@ -616,34 +670,24 @@ bool build_split(sg_op* op, hipStream_t s) {
     const int S = kSplits[id].S, RB = split::RB;
     const int n = op->n;
     const int tiles = (n + RB - 1) / RB;
-    const int blocks = (n + split::kBlockRows - 1) / split::kBlockRows;
-    std::vector<int32_t> runs((size_t)blocks * split::kRunWords);
-    std::vector<int16_t> slot((size_t)tiles * S * RB, 0);
-    std::vector<int64_t> ent((size_t)tiles * S * RB, -1);
-    std::vector<int32_t> cols;
-    for (int blk = 0; blk < blocks; ++blk) {
-        const int a0 = blk * split::kBlockRows, a1 = std::min(n, a0 + split::kBlockRows);
-        cols.assign(op->h_col.begin() + op->h_rowptr[a0], op->h_col.begin() + op->h_rowptr[a1]);
-        for (int a = a0; a < a1; ++a) cols.push_back(a);   // padding entries read the own row
-        int32_t* w = runs.data() + (size_t)blk * split::kRunWords;
-        if (!block_runs(cols, w)) return false;
-        auto staged = [&](int32_t c) {
-            int q = split::kRuns - 1;
-            while (w[split::kRuns + q] == (1 << 30) || c < w[q]) --q;
-            return (int16_t)(w[split::kRuns + q] + (c - w[q]));
-        };
-        for (int a = a0; a < a1; ++a) {
-            const int t = a / RB, r = a % RB;
-            int q = 0;
-            for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q) {
-                slot[((size_t)t * S + q) * RB + r] = staged(op->h_col[e]);
-                ent[((size_t)t * S + q) * RB + r] = e;
-            }
-            for (; q < S; ++q) slot[((size_t)t * S + q) * RB + r] = staged(a);
-        }
+    bool any = false;
+    std::vector<int32_t> runs;
+    std::vector<int16_t> slot;
+    for (int v = 0; v < split::kNumTileChoices; ++v) {
+        op->split_fits[v] = split_staging(op, S, split::kTileChoices[v], runs, slot);
+        if (!op->split_fits[v]) continue;
+        op->sruns[v].upload(runs, s);
+        op->sslot[v].upload(slot, s);
+        any = true;
     }
-    op->sruns.upload(runs, s);
-    op->sslot.upload(slot, s);
+    if (!any) return false;
+    std::vector<int64_t> ent((size_t)tiles * S * RB, -1);
+    for (int a = 0; a < n; ++a) {
+        const int t = a / RB, r = a % RB;
+        int q = 0;
+        for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q)
+            ent[((size_t)t * S + q) * RB + r] = e;
+    }
     DevBuf<int64_t> d_ent;
     d_ent.upload(ent, s);
     const int64_t npos = (int64_t)tiles * S * RB;
@@ -653,6 +697,7 @@ bool build_split(sg_op* op, hipStream_t s) {
     HIP_LAUNCH_OK();
     HIP_OK(hipStreamSynchronize(s));
     op->split = id;
+    op->split_var = op->split_fits[1] ? 1 : (op->split_fits[0] ? 0 : 2);
     return true;
 }
 
@@ -817,6 +862,71 @@ extern "C" int sg_matvec_kernel(const sg_op* op, int* kind) {
             *kind = SG_MV_WIDE;
         else
             *kind = SG_MV_GENERIC;
+        return SG_OK;
+    });
+}
+
+extern "C" int sg_matvec_select(sg_op* op, int tiles) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op, "null argument");
+        if (op->split < 0) SG_THROW(SG_ERR_UNSUPPORTED, "the operator has no staged matvec");
+        int v = -1;
+        for (int q = 0; q < split::kNumTileChoices; ++q)
+            if (split::kTileChoices[q] == tiles) v = q;
+        SG_REQUIRE(v >= 0, "tiles per work-group must be 1, 2 or 4 (got %d)", tiles);
+        if (!op->split_fits[v])
+            SG_THROW(SG_ERR_UNSUPPORTED, "%d tiles per work-group do not fit this operator", tiles);
+        if (v != op->split_var) graph_cache_purge(op);   // captured steps hold the old launch
+        op->split_var = v;
+        return SG_OK;
+    });
+}
+
+extern "C" int sg_matvec_tiles(const sg_op* op, int* tiles) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && tiles, "null argument");
+        *tiles = op->split >= 0 ? split::kTileChoices[op->split_var] : 0;
+        return SG_OK;
+    });
+}
+
+extern "C" int sg_matvec_autotune(sg_op* op, int reps, double* ms_out, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && ms_out, "null argument");
+        SG_REQUIRE(reps >= 1, "reps must be >= 1");
+        check_device(op->device);
+        if (op->split < 0) SG_THROW(SG_ERR_UNSUPPORTED, "the operator has no staged matvec");
+        hipStream_t s = as_stream(stream);
+        const size_t N = (size_t)op->n * op->P;
+        DevBuf<double> X(N), Y(N);
+        HIP_OK(hipMemsetAsync(X.p, 0, N * 8, s));
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        double best = -1.0;
+        int best_v = op->split_var;
+        for (int v = 0; v < split::kNumTileChoices; ++v) {
+            ms_out[v] = -1.0;
+            if (!op->split_fits[v]) continue;
+            op->split_var = v;
+            const KronCsr A = op->csr();
+            kron_matvec(A, op->L, op->tr, X.p, Y.p, 1.0, 0.0, nullptr, s);   // warm-up
+            HIP_OK(hipEventRecord(e0, s));
+            for (int q = 0; q < reps; ++q) kron_matvec(A, op->L, op->tr, X.p, Y.p, 1.0, 0.0, nullptr, s);
+            HIP_OK(hipEventRecord(e1, s));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            ms_out[v] = ms / reps;
+            if (best < 0.0 || ms_out[v] < best) {
+                best = ms_out[v];
+                best_v = v;
+            }
+        }
+        HIP_OK(hipEventDestroy(e0));
+        HIP_OK(hipEventDestroy(e1));
+        op->split_var = best_v;
+        graph_cache_purge(op);   // captured steps hold the launch they were recorded with
         return SG_OK;
     });
 }

@@ -47,13 +47,15 @@ struct sg_ras {
     std::vector<int32_t> h_ld, h_nown;
     std::vector<int64_t> h_aoff, h_xoff;
     sg::DevBuf<int32_t> own_pos;                  // per local node: owned index or -1
-    sg::DevBuf<int32_t> ld_d, nown_d, node_sub, own_gnode, blk_sub, blk_row0;
+    sg::DevBuf<int32_t> ld_d, nown_d, node_sub, own_gnode;
+    sg::DevBuf<int32_t> blk_sub[2], blk_row0[2];   // per rows-per-wave variant
     sg::DevBuf<int64_t> aoff_d, xoff_d, own_off_d;
     sg::DevBuf<double> ainv64;
     sg::DevBuf<float> ainv32;
     sg::DevBuf<uint16_t> ainv16;
     sg::DevBuf<unsigned char> xg;                 // gathered right-hand sides [s][Pp][ld]
-    int nblk = 0;
+    int nblk[2] = {0, 0};
+    int dense_var = 0;                            // 0: 64 rows per wave, 1: 32
     double ms_sweep = -1.0, ms_dense = -1.0;      // autotuner timings
 };
 
@@ -609,9 +611,9 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(
 // read 32 contiguous bytes at offset 32 g of a 128-byte row segment: the four
 // groups read whole cache lines of the inverse rows.  Every right-hand-side
 // fragment loaded serves the four row tiles.
-constexpr int kDenseRows = 64;       // rows per wave
+constexpr int kDenseRowChoices[] = {64, 32};   // rows per wave
 constexpr int kDenseLd = 64;         // local-node padding of the stored rows
-template <class TS, int NT>
+template <class TS, int NT, int kDenseRows>
 __global__ __launch_bounds__(256) void dense_apply_kernel(
     int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
     const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
@@ -744,6 +746,7 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
         maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
     dim3 gg(r->n_sub, (maxn + 63) / 64);
     const int NT = r->Pp / 16;
+    const int v = r->dense_var;
 #define SG_DENSE(TS, BUF)                                                                          \
     do {                                                                                           \
         dense_gather_kernel<TS><<<gg, 256, 0, s>>>(r->P, r->Pp, r->sub_node_off.p, r->gnode.p,      \
@@ -760,10 +763,16 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
     } while (0)
 #define SG_DENSE_NT(TS, BUF, N)                                                                    \
     case N:                                                                                        \
-        dense_apply_kernel<TS, N><<<r->nblk, 256, 0, s>>>(                                          \
-            r->P, r->blk_sub.p, r->blk_row0.p, r->nown_d.p, r->ld_d.p, r->aoff_d.p, r->xoff_d.p,   \
-            r->own_off_d.p, r->own_gnode.p, BUF, reinterpret_cast<const TS*>(r->xg.p), r->afact.p, \
-            Z, omega, beta);                                                                       \
+        if (v == 0)                                                                                \
+            dense_apply_kernel<TS, N, 64><<<r->nblk[v], 256, 0, s>>>(                               \
+                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->aoff_d.p,      \
+                r->xoff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,                                  \
+                reinterpret_cast<const TS*>(r->xg.p), r->afact.p, Z, omega, beta);                 \
+        else                                                                                       \
+            dense_apply_kernel<TS, N, 32><<<r->nblk[v], 256, 0, s>>>(                               \
+                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->aoff_d.p,      \
+                r->xoff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,                                  \
+                reinterpret_cast<const TS*>(r->xg.p), r->afact.p, Z, omega, beta);                 \
         break;
     if (r->prec == SG_FP64)
         SG_DENSE(double, r->ainv64.p);
@@ -909,7 +918,8 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         r->h_aoff.assign(ns + 1, 0);
         r->h_xoff.assign(ns + 1, 0);
         std::vector<int64_t> own_off(ns + 1, 0);
-        std::vector<int32_t> own_pos(r->h_gnode.size(), -1), own_gnode, node_sub, bsub, brow;
+        std::vector<int32_t> own_pos(r->h_gnode.size(), -1), own_gnode, node_sub;
+        std::vector<int32_t> bsub[2], brow[2];
         for (int q = 0; q < ns; ++q) {
             const int a0 = r->h_sub_node_off[q], a1 = r->h_sub_node_off[q + 1];
             int no = 0;
@@ -925,12 +935,13 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
             r->h_aoff[q + 1] = r->h_aoff[q] + (int64_t)no * r->h_ld[q];
             r->h_xoff[q + 1] = r->h_xoff[q] + (int64_t)r->Pp * r->h_ld[q];
             own_off[q + 1] = own_off[q] + no;
-            for (int r0 = 0; r0 < no; r0 += 4 * kDenseRows) {
-                bsub.push_back(q);
-                brow.push_back(r0);
-            }
+            for (int v = 0; v < 2; ++v)
+                for (int r0 = 0; r0 < no; r0 += 4 * kDenseRowChoices[v]) {
+                    bsub[v].push_back(q);
+                    brow[v].push_back(r0);
+                }
         }
-        r->nblk = (int)bsub.size();
+        for (int v = 0; v < 2; ++v) r->nblk[v] = (int)bsub[v].size();
         r->own_pos.upload(own_pos, s);
         r->ld_d.upload(r->h_ld, s);
         r->nown_d.upload(r->h_nown, s);
@@ -939,8 +950,10 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         r->own_off_d.upload(own_off, s);
         r->own_gnode.upload(own_gnode, s);
         r->node_sub.upload(node_sub, s);
-        r->blk_sub.upload(bsub, s);
-        r->blk_row0.upload(brow, s);
+        for (int v = 0; v < 2; ++v) {
+            r->blk_sub[v].upload(bsub[v], s);
+            r->blk_row0[v].upload(brow[v], s);
+        }
         const size_t ts = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
         r->xg.alloc((size_t)r->h_xoff[ns] * ts);
         HIP_OK(hipMemsetAsync(r->xg.p, 0, r->xg.bytes(), s));
@@ -999,9 +1012,13 @@ extern "C" {
 int ras_select(sg_ras* r, int dense, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(r != nullptr, "ras is NULL");
+        SG_REQUIRE(dense >= 0 && dense <= 2, "path must be 0 (sweep), 1 or 2 (dense)");
         check_device(r->device);
         if (dense && !r->dense_built) ras_build_dense(r, as_stream(stream));
+        const bool changed = r->use_dense != (dense != 0) || (dense && r->dense_var != dense - 1);
         r->use_dense = dense != 0;
+        if (dense) r->dense_var = dense - 1;
+        if (changed) graph_cache_purge(r);   // captured steps hold the old path
         return SG_OK;
     });
 }
@@ -1019,10 +1036,12 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        double ms[2] = {0.0, 0.0};
+        // candidates: sweep, dense with 64 and with 32 rows per wave
+        double ms[3] = {0.0, 0.0, 0.0};
         try {
-            for (int path = 0; path < 2; ++path) {
-                r->use_dense = path == 1;
+            for (int c = 0; c < 3; ++c) {
+                r->use_dense = c > 0;
+                r->dense_var = c > 0 ? c - 1 : 0;
                 ras_apply_ex(r, R.p, Z.p, 1.0, 0.0, s);            // warm-up
                 HIP_OK(hipEventRecord(e0, s));
                 for (int q = 0; q < reps; ++q) ras_apply_ex(r, R.p, Z.p, 1.0, 0.0, s);
@@ -1030,7 +1049,7 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
                 HIP_OK(hipEventSynchronize(e1));
                 float t = 0.f;
                 HIP_OK(hipEventElapsedTime(&t, e0, e1));
-                ms[path] = t / reps;
+                ms[c] = t / reps;
             }
         } catch (...) {
             (void)hipEventDestroy(e0);
@@ -1039,10 +1058,15 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        int best = 0;
+        for (int c = 1; c < 3; ++c)
+            if (ms[c] < ms[best]) best = c;
         r->ms_sweep = ms[0];
-        r->ms_dense = ms[1];
-        r->use_dense = ms[1] < ms[0];
-        if (ms_out) { ms_out[0] = ms[0]; ms_out[1] = ms[1]; }
+        r->ms_dense = std::min(ms[1], ms[2]);
+        r->use_dense = best > 0;
+        r->dense_var = best > 0 ? best - 1 : 0;
+        if (ms_out) for (int c = 0; c < 3; ++c) ms_out[c] = ms[c];
+        graph_cache_purge(r);   // captured steps hold the path they were recorded with
         return SG_OK;
     });
 }
@@ -1050,7 +1074,7 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
 int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes) {
     return guarded([&]() -> int {
         SG_REQUIRE(r != nullptr, "ras is NULL");
-        if (dense) *dense = r->use_dense ? 1 : 0;
+        if (dense) *dense = r->use_dense ? 1 + r->dense_var : 0;
         if (dense_bytes) {
             const int64_t per = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
             *dense_bytes = r->dense_built ? r->h_aoff[r->n_sub] * per : 0;

@@ -17,9 +17,15 @@ COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_
 
 
 class GpuSG:
+    """ras_path: "sweep", "dense", "dense32", or "auto" (timed by the library,
+    also choosing the staged matvec's work-group shape).  tune_cache: with
+    "auto", a ``TuneCache`` (or its file path) that supplies choices already
+    made for this shape and records new ones."""
+
     def __init__(self, pr: Problem, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
-                 n_sub: Optional[int] = None, stream=None, ras_path: str = "sweep"):
+                 n_sub: Optional[int] = None, stream=None, ras_path: str = "sweep",
+                 tune_cache=None):
         import torch
         self.torch = torch
         self.pr = pr
@@ -40,10 +46,12 @@ class GpuSG:
         self.ras = B.ras_setup(self.op, self.owner, self.n_sub, self.overlap, B.PREC[prec],
                                stream=stream)
         self.ras_ms = None
-        if ras_path == "dense":
-            B.ras_select(self.ras, True, stream=stream)
+        self.mv_ms = None
+        self.tuned_from_cache = False
+        if ras_path in ("dense", "dense32"):
+            B.ras_select(self.ras, ras_path, stream=stream)
         elif ras_path == "auto":
-            self.ras_ms = B.ras_autotune(self.ras, 5, stream=stream)
+            self._autotune(tune_cache, stream)
         elif ras_path != "sweep":
             raise ValueError(f"unknown RAS path {ras_path!r}")
         if coarse != "none":
@@ -69,6 +77,33 @@ class GpuSG:
         N = self.n * self.P
         ws = self.torch.empty(2 * N + 4096, dtype=self.torch.float64, device="cuda")
         return B.sg_smoother_damping(self.op, self.ras, its, ws, stream=self.stream)
+
+    def _autotune(self, tune_cache, stream):
+        from .autotune import TuneCache, make_key
+        cache = TuneCache(tune_cache) if isinstance(tune_cache, str) else tune_cache
+        arch = self.torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        pr = self.pr
+        shape = dict(n=self.n, P=self.P, L=self.L, nnz=self.nnz, M=pr.M, p=pr.p)
+        staged = B.sg_matvec_kernel(self.op) == "staged"
+        kmv = make_key("sg_matvec", arch, **shape)
+        kras = make_key("ras_apply", arch, prec=self.prec, n_sub=self.n_sub,
+                        overlap=self.overlap, **shape)
+        hit_mv = cache.get(kmv) if cache is not None else None
+        hit_ras = cache.get(kras) if cache is not None else None
+        if staged:
+            if hit_mv is not None:
+                B.sg_matvec_select(self.op, int(hit_mv["tiles"]))
+            else:
+                self.mv_ms = B.sg_matvec_autotune(self.op, 10, stream=stream)
+                if cache is not None:
+                    cache.put(kmv, dict(tiles=B.sg_matvec_tiles(self.op), ms=self.mv_ms))
+        if hit_ras is not None:
+            B.ras_select(self.ras, hit_ras["path"], stream=stream)
+        else:
+            self.ras_ms = B.ras_autotune(self.ras, 5, stream=stream)
+            if cache is not None:
+                cache.put(kras, dict(path=B.ras_path_info(self.ras)[2], ms=list(self.ras_ms)))
+        self.tuned_from_cache = hit_ras is not None and (hit_mv is not None or not staged)
 
     def solve(self, restart: int, rtol: float, max_it: int = 2000, omega: float = 0.0,
               x0=None, use_precond: bool = True, use_graph: bool = False, ortho: str = "mgs"):

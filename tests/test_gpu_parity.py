@@ -169,6 +169,34 @@ def test_matvec_matches_oracle(built, key):
     assert _rel(_to_host(Y, X.shape), S.matvec(X)) < 1e-13
 
 
+def test_matvec_tile_shapes_autotune_and_select(built):
+    """Every work-group shape of the staged kernel gives the oracle's product;
+    the autotuner keeps the fastest shape; shapes are rejected where they do
+    not apply."""
+    pr, S, g = built("c1_64")
+    X = np.random.default_rng(12).standard_normal((pr.mesh.n, S.P))
+    ref = S.matvec(X)
+    try:
+        for tiles in (1, 2, 4):
+            B.sg_matvec_select(g.op, tiles)
+            assert B.sg_matvec_tiles(g.op) == tiles
+            Y = g.new_vec()
+            B.sg_matvec(g.op, _to_dev(X), Y)
+            assert _rel(_to_host(Y, X.shape), ref) < 1e-13
+        ms = B.sg_matvec_autotune(g.op, 3)
+        print(f"[gpu] matvec shapes 1/2/4 tiles: {ms} ms")
+        assert all(v is not None and v > 0 for v in ms)
+        assert B.sg_matvec_tiles(g.op) == (1, 2, 4)[int(np.argmin(ms))]
+        with pytest.raises(B.SgError):
+            B.sg_matvec_select(g.op, 3)
+    finally:
+        B.sg_matvec_select(g.op, 2)
+    _, _, gw = built("c3_40")                     # one-wave-per-row kernel: no shapes
+    assert B.sg_matvec_tiles(gw.op) == 0
+    with pytest.raises(B.SgError):
+        B.sg_matvec_autotune(gw.op, 1)
+
+
 def test_matvec_rejects_alias(built):
     pr, S, g = built("c0")
     X = g.new_vec(1.0)
@@ -214,21 +242,22 @@ def test_ras_dense_path_matches_oracle(built, key):
     subs = _oracle_ras(pr, S)
     R = np.random.default_rng(15).standard_normal((pr.mesh.n, S.P))
     Z = g.new_vec()
-    B.ras_select(g.ras, True)
     try:
-        dense, nbytes = B.ras_path_info(g.ras)
-        assert dense and nbytes > 0
-        B.ras_apply(g.ras, _to_dev(R), Z)
-        assert _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact)) < 1e-10
-        # the damped form used inside the two-grid cycle, against the sweeps
-        omega = 0.5
-        op = g.new_vec()
-        B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op, None)
-        B.ras_select(g.ras, False)
-        op_sweep = g.new_vec()
-        B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op_sweep, None)
-        torch.cuda.synchronize()
-        assert float((op - op_sweep).abs().max() / op_sweep.abs().max()) < 1e-10
+        for path in ("dense", "dense32"):          # 64 and 32 owned rows per wave
+            B.ras_select(g.ras, path)
+            dense, nbytes, name = B.ras_path_info(g.ras)
+            assert dense and nbytes > 0 and name == path
+            B.ras_apply(g.ras, _to_dev(R), Z)
+            assert _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact)) < 1e-10
+            # the damped form used inside the two-grid cycle, against the sweeps
+            omega = 0.5
+            op = g.new_vec()
+            B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op, None)
+            B.ras_select(g.ras, False)
+            op_sweep = g.new_vec()
+            B.sg_precond_apply(g.op, g.ras, None, omega, _to_dev(R), op_sweep, None)
+            torch.cuda.synchronize()
+            assert float((op - op_sweep).abs().max() / op_sweep.abs().max()) < 1e-10
     finally:
         B.ras_select(g.ras, False)
 
@@ -239,27 +268,27 @@ def test_ras_dense_low_precision_close_to_oracle(built, prec, tol):
     subs = _oracle_ras(pr, S)
     R = np.random.default_rng(16).standard_normal((pr.mesh.n, S.P))
     Z = g.new_vec()
-    B.ras_select(g.ras, True)
     try:
-        B.ras_apply(g.ras, _to_dev(R), Z)
+        for path in ("dense", "dense32"):
+            B.ras_select(g.ras, path)
+            B.ras_apply(g.ras, _to_dev(R), Z)
+            err = _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact))
+            print(f"[gpu] dense RAS {prec} {path} rel err {err:.3e}")
+            assert err < tol
     finally:
         B.ras_select(g.ras, False)
-    err = _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact))
-    print(f"[gpu] dense RAS {prec} rel err {err:.3e}")
-    assert err < tol
 
 
 def test_ras_autotune_and_dense_fgmres(built):
-    """The autotuner times both paths and keeps the faster; FGMRES with the
-    dense BF16 local solves still reaches the FP64 solution (mixed path)."""
+    """The autotuner times the three paths and keeps the fastest; FGMRES with
+    the dense BF16 local solves still reaches the FP64 solution (mixed path)."""
     pr, S, _ = built("c1_64")
     g = GpuSG(pr, prec="bf16", coarse="amg", ras_path="auto")
     try:
-        ms_sweep, ms_dense = g.ras_ms
-        dense, _ = B.ras_path_info(g.ras)
-        print(f"[gpu] RAS autotune: sweep {ms_sweep:.3f} ms, dense {ms_dense:.3f} ms -> "
-              f"{'dense' if dense else 'sweep'}")
-        assert ms_sweep > 0 and ms_dense > 0 and dense == (ms_dense < ms_sweep)
+        ms = g.ras_ms
+        _, _, name = B.ras_path_info(g.ras)
+        print(f"[gpu] RAS autotune: sweep / dense / dense32 {ms} ms -> {name}")
+        assert min(ms) > 0 and name == ("sweep", "dense", "dense32")[int(np.argmin(ms))]
         B.ras_select(g.ras, True)
         x, info = g.solve(pr.restart, 1e-10)
         assert info["converged"]
@@ -267,6 +296,25 @@ def test_ras_autotune_and_dense_fgmres(built):
         assert _rel(_to_host(x, ref.shape), ref) < 1e-8
     finally:
         g.close()
+
+
+def test_autotune_cache_reuses_choices(built, tmp_path):
+    """A second set-up of the same shape takes the matvec shape and the RAS
+    path from the cache instead of timing them."""
+    pr, _, _ = built("c1_64")
+    path = str(tmp_path / "tune.json")
+    g1 = GpuSG(pr, prec="bf16", coarse="none", ras_path="auto", tune_cache=path)
+    try:
+        assert not g1.tuned_from_cache and g1.ras_ms is not None and g1.mv_ms is not None
+        choice = (B.sg_matvec_tiles(g1.op), B.ras_path_info(g1.ras)[2])
+    finally:
+        g1.close()
+    g2 = GpuSG(pr, prec="bf16", coarse="none", ras_path="auto", tune_cache=path)
+    try:
+        assert g2.tuned_from_cache and g2.ras_ms is None and g2.mv_ms is None
+        assert (B.sg_matvec_tiles(g2.op), B.ras_path_info(g2.ras)[2]) == choice
+    finally:
+        g2.close()
 
 
 def test_ras_single_subdomain_exact(built):
