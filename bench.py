@@ -40,7 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counters, scaled by the counters' reading of a copy of known
 # size (profiles/sg_matvec_512x512_P35_hbm_traffic.txt), keyed by kernel and
 # workload; a workload or kernel without a measurement reports null.
-MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 2>", 261121, 35): 336.1e6}
+MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 1>", 261121, 35): 331.9e6,
+                    ("kron_matvec_split_kernel<4, 2, 3, 5, 2>", 261121, 35): 335.9e6,
+                    ("kron_matvec_split_kernel<4, 2, 3, 5, 4>", 261121, 35): 351.7e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
                    "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel"}
 
@@ -200,6 +202,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay Arnoldi steps from captured HIP graphs (1) or launch eagerly (0)")
+    ap.add_argument("--mv-tiles", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="with --matvec-only: 64-row tiles per work-group of the staged "
+                         "matvec (0 keeps the library default)")
     ap.add_argument("--matvec-only", action="store_true",
                     help="time only the SG matvec (for counter collection) and print its figures")
     ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
@@ -230,10 +235,14 @@ def main() -> int:
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
     if args.matvec_only:
         g = GpuSG(pr, prec="fp64", coarse="none")
+        if args.mv_tiles:
+            B.sg_matvec_select(g.op, args.mv_tiles)
         n, P, L, nnz = g.n, g.P, g.L, g.nnz
         mv_mean_ms, mv_med_ms = time_matvec(g, args.mv_launches, torch)
         b = matvec_bytes(n, nnz, L, P)
-        print(json.dumps({"matvec_only": True, "config": args.config, "us": round(mv_mean_ms * 1e3, 2),
+        print(json.dumps({"matvec_only": True, "config": args.config,
+                          "kernel": B.sg_matvec_kernel(g.op), "tiles": B.sg_matvec_tiles(g.op),
+                          "us": round(mv_mean_ms * 1e3, 2),
                           "median_us": round(mv_med_ms * 1e3, 2), "bytes": b,
                           "GBps": round(b / (mv_mean_ms * 1e-3) / 1e9, 1),
                           "flush_bytes_per_launch": 2 * 64 * 1024 * 1024 * 8}))
