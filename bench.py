@@ -258,7 +258,7 @@ def main() -> int:
         torch.cuda.synchronize()
         setup_s[prec] = time.perf_counter() - t0
         ras_paths[prec] = dict(path=B.ras_path_info(solvers[prec].ras)[2],
-                               ms_sweep_dense_dense32=solvers[prec].ras_ms)
+                               ms_sweep_dense_dense32_fused=solvers[prec].ras_ms)
         log(f"[bench] setup {prec}: {setup_s[prec]:.2f} s, RAS {ras_paths[prec]}")
     g64 = solvers["fp64"]
     n, P, L, nnz = g64.n, g64.P, g64.L, g64.nnz

@@ -170,12 +170,16 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
  * (owned rows x local nodes times local nodes x P), whose bytes scale with
  * the precision.  Both compute the same operator (up to rounding).
  * ras_select: 0 = sweep, 1 = dense with 64 owned rows per wave, 2 = dense
- *   with 32 (the dense rows are built on first use; device memory
- *   sum_s n_own(s) * n_local(s) entries).  Synchronous.
+ *   with 32, 3 = fused dense: one work-group per subdomain gathers its
+ *   right-hand sides into on-chip memory itself and streams the rows once
+ *   (available where P_pad x n_local entries plus n_local node ids fit one
+ *   work-group's LDS and P <= 48, FP64: P <= 32; else SG_ERR_UNSUPPORTED).
+ *   The dense rows are built on first use; device memory
+ *   sum_s ceil16(n_own(s)) * ceil64(n_local(s)) entries.  Synchronous.
  * ras_autotune: builds the dense rows if needed, times `reps` applies of
- *   each of the three with HIP events on `stream` (internal zero input),
- *   keeps the fastest; ms (host [3], may be NULL): in the order above.
- *   Synchronous.
+ *   each of the four with HIP events on `stream` (internal zero input),
+ *   keeps the fastest; ms (host [4], may be NULL): in the order above,
+ *   -1 for a path that is not available.  Synchronous.
  * ras_path_info: current path (as for ras_select) and the bytes of the
  *   dense rows (0 if not built).  A refactorisation rebuilds the dense rows.
  * A new path drops the captured Arnoldi-step graphs that use the handle. */

@@ -287,7 +287,7 @@ def ras_refactor(r, op, stream=None):
     _check(lib().ras_refactor(r, op, _stream(stream)))
 
 
-RAS_PATHS = {"sweep": 0, "dense": 1, "dense32": 2}
+RAS_PATHS = {"sweep": 0, "dense": 1, "dense32": 2, "fused": 3}
 
 
 def ras_select(r, dense, stream=None):
@@ -298,11 +298,11 @@ def ras_select(r, dense, stream=None):
 
 
 def ras_autotune(r, reps: int = 5, stream=None):
-    """ms per apply of the sweep, dense (64 rows per wave) and dense32 paths;
-    the fastest is kept."""
-    ms = np.zeros(3, dtype=np.float64)
+    """ms per apply of the sweep, dense (64 rows per wave), dense32 and fused
+    paths (-1 where the fused path does not fit); the fastest is kept."""
+    ms = np.zeros(4, dtype=np.float64)
     _check(lib().ras_autotune(r, reps, _ptr(ms, C.c_double), _stream(stream)))
-    return float(ms[0]), float(ms[1]), float(ms[2])
+    return tuple(float(v) for v in ms)
 
 
 def ras_path_info(r):

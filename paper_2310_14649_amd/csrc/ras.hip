@@ -40,22 +40,26 @@ struct sg_ras {
     int64_t op_nnz = 0;
     int op_L = 0;
     sg::DevBuf<int64_t> lent, prev_ent, next_ent;
-    // dense path: explicit inverse rows of the owned nodes, [n_own(s)][ld(s)]
-    // per subdomain (local columns in level order, ld = nloc padded to 64)
+    // dense path: explicit inverse rows of the owned nodes of each subdomain
+    // (local columns in level order, ld = nloc padded to 64), stored in
+    // tiles of 16 rows in the order the apply kernel's lanes load them
+    // (n_own padded to 16 rows; offsets h_toff)
     bool dense_built = false, use_dense = false;
     int Pp = 0;                                   // P padded to 16
     std::vector<int32_t> h_ld, h_nown;
-    std::vector<int64_t> h_aoff, h_xoff;
+    std::vector<int64_t> h_aoff, h_toff, h_xoff;  // row-major (set-up), tiled, gathered
     sg::DevBuf<int32_t> own_pos;                  // per local node: owned index or -1
     sg::DevBuf<int32_t> ld_d, nown_d, node_sub, own_gnode;
-    sg::DevBuf<int32_t> blk_sub[2], blk_row0[2];   // per rows-per-wave variant
-    sg::DevBuf<int64_t> aoff_d, xoff_d, own_off_d;
+    sg::DevBuf<int32_t> blk_sub[3], blk_row0[3];   // per variant: 64 / 32 rows per wave, fused
+    sg::DevBuf<int64_t> aoff_d, toff_d, xoff_d, own_off_d;
     sg::DevBuf<double> ainv64;
     sg::DevBuf<float> ainv32;
     sg::DevBuf<uint16_t> ainv16;
     sg::DevBuf<unsigned char> xg;                 // gathered right-hand sides [s][Pp][ld]
-    int nblk[2] = {0, 0};
-    int dense_var = 0;                            // 0: 64 rows per wave, 1: 32
+    int nblk[3] = {0, 0, 0};
+    int dense_var = 0;                            // 0: 64 rows per wave, 1: 32, 2: fused
+    bool fused_ok = false;                        // fused variant fits (LDS, columns)
+    size_t fused_lds = 0;                         // its LDS bytes per work-group
     double ms_sweep = -1.0, ms_dense = -1.0;      // autotuner timings
 };
 
@@ -607,98 +611,75 @@ __global__ __launch_bounds__(256) void dense_gather_kernel(
 // Z[owned] = beta Z[owned] + omega / n! * (Ainv_s X_s)[own rows]: one wave per
 // 64 owned rows (MT = 4 row tiles of 16) and all P columns (NT tiles of 16),
 // K = local nodes.  The sum over k runs in any order as long as the A and B
-// operands agree, so each super-step of 2 MFMA k-steps lets lane group g
-// read 32 contiguous bytes at offset 32 g of a 128-byte row segment: the four
-// groups read whole cache lines of the inverse rows.  Every right-hand-side
-// fragment loaded serves the four row tiles.
+// operands agree, so in each super-step of 2 MFMA k-steps lane group g takes
+// the 32 bytes at offset 32 g of the 128-byte row segment (whole lines of X).
+// The inverse is stored tile by tile in exactly that load order (below), so
+// each load instruction of a wave reads 1 KB of consecutive bytes and a wave
+// streams each of its row tiles from one contiguous range.  Every
+// right-hand-side fragment loaded serves the MT row tiles.
 constexpr int kDenseRowChoices[] = {64, 32};   // rows per wave
 constexpr int kDenseLd = 64;         // local-node padding of the stored rows
-template <class TS, int NT, int kDenseRows>
-__global__ __launch_bounds__(256) void dense_apply_kernel(
-    int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
+
+// Tiled storage of one subdomain's inverse rows, for entries of TS (KL =
+// 16 / sizeof(TS) per 16-byte load, KSUP = 8 KL per super-step): row tile
+// rt (rows 16 rt .. 16 rt + 15), super-step ks, half h and lane
+// l = i + 16 g hold the KL entries of row 16 rt + i at columns
+// ks KSUP + 2 KL g + h KL + (0 .. KL-1), at element offset
+// rt 16 ld + ((2 ks + h) 64 + l) KL.  Rows past n_own are zero.
+template <class TS>
+__global__ __launch_bounds__(256) void tile_dense_kernel(
     const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
-    const int64_t* __restrict__ aoff, const int64_t* __restrict__ xoff,
-    const int64_t* __restrict__ own_off, const int32_t* __restrict__ own_gnode,
-    const TS* __restrict__ ainv, const TS* __restrict__ xg, const double* __restrict__ afact,
-    double* Z, double omega, double beta) {
-    using Acc = typename Mma<TS>::Acc;
-    constexpr int MT = kDenseRows / 16;
-    constexpr int KL = 16 / sizeof(TS);          // elements per 16-byte load
-    constexpr int KSUP = 8 * KL;                 // elements per super-step (128 bytes per row)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = blockIdx.x;
-    const int s = blk_sub[b];
-    const int r0 = blk_row0[b] + kDenseRows * wave;
+    const int64_t* __restrict__ aoff, const int64_t* __restrict__ toff,
+    const double* __restrict__ rows, TS* __restrict__ out) {
+    constexpr int KL = 16 / sizeof(TS);
+    const int s = blockIdx.x, rt = blockIdx.y;
     const int no = nown[s];
-    if (r0 >= no) return;
+    if (16 * rt >= no) return;
     const int L = ld[s];
-    const int i = lane & 15, g = lane >> 4;
-    const TS* A[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-        A[m] = ainv + aoff[s] + (int64_t)min(r0 + 16 * m + i, no - 1) * L + 2 * KL * g;
-    const TS* X = xg + xoff[s] + (int64_t)i * L + 2 * KL * g;
-    Acc acc[MT][NT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
-    // two register buffers: the loads of super-step k + 1 are in flight while
-    // the products of super-step k run
-    uint4 av[2][MT][2], bv[2][NT][2];
-    auto load = [&](int buf, int k) {
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            av[buf][m][0] = *reinterpret_cast<const uint4*>(A[m] + k);
-            av[buf][m][1] = *reinterpret_cast<const uint4*>(A[m] + k + KL);
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            bv[buf][t][0] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k);
-            bv[buf][t][1] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k + KL);
-        }
-    };
-    auto compute = [&](int buf) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    if constexpr (sizeof(TS) == 2) {
-                        sg_bf8 a, bb;
-                        __builtin_memcpy(&a, &av[buf][m][h], 16);
-                        __builtin_memcpy(&bb, &bv[buf][t][h], 16);
-                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[m][t], 0, 0, 0);
-                    } else if constexpr (sizeof(TS) == 4) {
-                        float a[4], bb[4];
-                        __builtin_memcpy(a, &av[buf][m][h], 16);
-                        __builtin_memcpy(bb, &bv[buf][t][h], 16);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc[m][t], 0, 0, 0);
-                    } else {
-                        double a[2], bb[2];
-                        __builtin_memcpy(a, &av[buf][m][h], 16);
-                        __builtin_memcpy(bb, &bv[buf][t][h], 16);
-#pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc[m][t], 0, 0, 0);
-                    }
-                }
-    };
-    load(0, 0);
-    int k = 0;
-    for (; k + 2 * KSUP <= L; k += 2 * KSUP) {
-        load(1, k + KSUP);
-        compute(0);
-        if (k + 2 * KSUP < L) load(0, k + 2 * KSUP);
-        compute(1);
+    const double* src = rows + aoff[s];
+    TS* dst = out + toff[s] + (int64_t)rt * 16 * L;
+    for (int o = threadIdx.x; o < 16 * L; o += 256) {
+        const int e = o % KL, l = (o / KL) & 63, h = (o / (64 * KL)) & 1, ks = o / (128 * KL);
+        const int row = 16 * rt + (l & 15);
+        const int col = ks * 8 * KL + 2 * KL * (l >> 4) + h * KL + e;
+        dst[o] = Mma<TS>::conv(row < no ? src[(int64_t)row * L + col] : 0.0);
     }
-    if (k < L) compute(0);          // L / KSUP odd: the last super-step is in buffer 0
-    // Z may be accumulated into: per row tile, the old values are all read
-    // before the first store, so the loads do not wait behind each store
-    const int64_t ob = own_off[s];
+}
+
+// One 16-byte A fragment times one 16-byte B fragment on the matrix cores
+// (one MFMA k-step of 32 BF16, four of 4 FP32 or two of 4 FP64 entries).
+template <class TS>
+__device__ inline void dense_mma(typename Mma<TS>::Acc& acc, const uint4& av, const uint4& bv) {
+    if constexpr (sizeof(TS) == 2) {
+        sg_bf8 a, bb;
+        __builtin_memcpy(&a, &av, 16);
+        __builtin_memcpy(&bb, &bv, 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    } else if constexpr (sizeof(TS) == 4) {
+        float a[4], bb[4];
+        __builtin_memcpy(a, &av, 16);
+        __builtin_memcpy(bb, &bv, 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc, 0, 0, 0);
+    } else {
+        double a[2], bb[2];
+        __builtin_memcpy(a, &av, 16);
+        __builtin_memcpy(bb, &bv, 16);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+    }
+}
+
+// Z[own_gnode[r]][n] = beta Z[..] + omega acc / n! for the wave's rows
+// r0 .. r0 + 16 MT - 1 (those below no) and n < P.  Z may be accumulated
+// into: per row tile, the old values are all read before the first store, so
+// the loads do not wait behind each store.
+template <class TS, int NT, int MT>
+__device__ inline void dense_epilogue(const typename Mma<TS>::Acc (&acc)[MT][NT], int P, int r0, int no,
+                                      int lane, const int32_t* __restrict__ own_gnode,
+                                      const double* __restrict__ afact, double* Z, double omega,
+                                      double beta) {
+    const int i = lane & 15;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         int64_t zo[4];
@@ -706,7 +687,7 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + 16 * m + Mma<TS>::row_of(lane, v);
-            zo[v] = r < no ? (int64_t)own_gnode[ob + r] * P : -1;
+            zo[v] = r < no ? (int64_t)own_gnode[r] * P : -1;
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -728,13 +709,208 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
     }
 }
 
+template <class TS, int NT, int kDenseRows>
+__global__ __launch_bounds__(256) void dense_apply_kernel(
+    int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
+    const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
+    const int64_t* __restrict__ toff, const int64_t* __restrict__ xoff,
+    const int64_t* __restrict__ own_off, const int32_t* __restrict__ own_gnode,
+    const TS* __restrict__ ainv, const TS* __restrict__ xg, const double* __restrict__ afact,
+    double* Z, double omega, double beta) {
+    using Acc = typename Mma<TS>::Acc;
+    constexpr int MT = kDenseRows / 16;
+    constexpr int KL = 16 / sizeof(TS);          // elements per 16-byte load
+    constexpr int KSUP = 8 * KL;                 // elements per super-step (128 bytes per row)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x;
+    const int s = blk_sub[b];
+    const int r0 = blk_row0[b] + kDenseRows * wave;
+    const int no = nown[s];
+    if (r0 >= no) return;
+    const int L = ld[s];
+    const int i = lane & 15, g = lane >> 4;
+    // row tiles past the last one (their rows are not stored) read the last
+    const int nrt = (no + 15) >> 4;
+    const TS* A[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        A[m] = ainv + toff[s] + (int64_t)min((r0 >> 4) + m, nrt - 1) * 16 * L + lane * KL;
+    const TS* X = xg + xoff[s] + (int64_t)i * L + 2 * KL * g;
+    Acc acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
+    // two register buffers: the loads of super-step k + 1 are in flight while
+    // the products of super-step k run
+    uint4 av[2][MT][2], bv[2][NT][2];
+    auto load = [&](int buf, int k) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            av[buf][m][0] = *reinterpret_cast<const uint4*>(A[m] + 16 * k);
+            av[buf][m][1] = *reinterpret_cast<const uint4*>(A[m] + 16 * k + 64 * KL);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bv[buf][t][0] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k);
+            bv[buf][t][1] = *reinterpret_cast<const uint4*>(X + (int64_t)16 * t * L + k + KL);
+        }
+    };
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) dense_mma<TS>(acc[m][t], av[buf][m][h], bv[buf][t][h]);
+    };
+    load(0, 0);
+    int k = 0;
+    for (; k + 2 * KSUP <= L; k += 2 * KSUP) {
+        load(1, k + KSUP);
+        compute(0);
+        if (k + 2 * KSUP < L) load(0, k + 2 * KSUP);
+        compute(1);
+    }
+    if (k < L) compute(0);          // L / KSUP odd: the last super-step is in buffer 0
+    dense_epilogue<TS, NT, MT>(acc, P, r0, no, lane, own_gnode + own_off[s], afact, Z, omega, beta);
+}
 
-__global__ void narrow_kernel(int64_t n, const double* __restrict__ x, float* __restrict__ y32,
-                              uint16_t* __restrict__ y16) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (y32) y32[i] = (float)x[i];
-    if (y16) y16[i] = to_bf16((float)x[i]);
+// Fused dense apply: one work-group of kFusedWaves waves per (subdomain,
+// kFusedRows owned rows).  The work-group gathers the subdomain's right-hand
+// sides from R into LDS itself, converted and already in the order in which
+// the lanes take their B fragments ([super-step][column tile][half][lane],
+// 16 bytes each), so the separate gather pass and the re-reads of the
+// gathered copy through L2 disappear.  After one barrier each wave streams
+// its 64 rows of the tiled inverse with B read from LDS and no further
+// barrier.
+// LDS: Pp x ld entries of TS plus ld node ids.
+constexpr int kFusedWaves = 16;
+constexpr int kFusedRows = 64 * kFusedWaves;
+// column tiles whose accumulators fit the 128 registers of a 16-wave group
+inline int fused_max_nt(sg_prec prec) { return prec == SG_FP64 ? 2 : 3; }
+template <class TS, int NT>
+__global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
+    int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
+    const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
+    const int32_t* __restrict__ sub_node_off, const int32_t* __restrict__ gnode,
+    const int64_t* __restrict__ toff, const int64_t* __restrict__ own_off,
+    const int32_t* __restrict__ own_gnode, const TS* __restrict__ ainv,
+    const double* __restrict__ R, const double* __restrict__ afact, double* Z, double omega,
+    double beta) {
+    using Acc = typename Mma<TS>::Acc;
+    constexpr int MT = 4;
+    constexpr int KL = 16 / sizeof(TS);
+    constexpr int KSUP = 8 * KL;
+    constexpr int Pp = 16 * NT;
+    constexpr int kThreads = 64 * kFusedWaves;
+    extern __shared__ uint4 lds_b[];
+    // the wave index is uniform: the row tiles and their base addresses stay
+    // in scalar registers, each lane adds one offset
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s = blk_sub[blockIdx.x];
+    const int r0 = blk_row0[blockIdx.x] + 64 * wave;
+    const int no = nown[s];
+    const int L = ld[s];
+    const int nks = L / KSUP;
+    const int node0 = sub_node_off[s], nloc = sub_node_off[s + 1] - node0;
+    const bool active = r0 < no;
+    const int nrt = (no + 15) >> 4;
+    // scalar base per row tile plus one 32-bit byte offset per lane (a row
+    // tile holds 16 ld entries, well below 4 GB)
+    const char* A[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+        A[m] = reinterpret_cast<const char*>(ainv + toff[s] +
+                                             (int64_t)min((r0 >> 4) + m, nrt - 1) * 16 * L);
+    // the stream runs in half super-steps (one MFMA k-step pair for BF16):
+    // half j of a row tile is the 1 KB at byte 1024 j, and its B fragments
+    // are piece (2 (j / 2) NT + 2 t + j % 2) 64 + lane
+    uint4 av[3][MT];
+    auto aload = [&](int slot, int j) {
+        const uint32_t off = (uint32_t)lane * 16u + (uint32_t)j * 1024u;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[slot][m] = *reinterpret_cast<const uint4*>(A[m] + off);
+    };
+    const int nh = 2 * nks;   // >= 2
+    if (active) {             // the first three half-steps load during the gather
+        aload(0, 0);
+        aload(1, 1);
+        if (nh > 2) aload(2, 2);
+    }
+    // node ids after the B pieces, then the gather: e = q Pp + n, consecutive
+    // threads read consecutive entries of a node's row of R
+    int32_t* ids = reinterpret_cast<int32_t*>(lds_b + (size_t)nks * NT * 128);
+    for (int q = tid; q < nloc; q += kThreads) ids[q] = gnode[node0 + q];
+    __syncthreads();
+    TS* bsh = reinterpret_cast<TS*>(lds_b);
+    // LDS slot of entry (local node q, column n)
+    auto slot = [&](int q, int n) {
+        const int ks = q / KSUP, w = q - ks * KSUP;
+        const int g = w / (2 * KL), h = (w / KL) & 1, el = w % KL;
+        return (((ks * NT + (n >> 4)) * 2 + h) * 64 + (n & 15) + 16 * g) * KL + el;
+    };
+    // the P real columns (zero for the padded nodes q >= nloc), U loads in flight
+    const int total = L * P;
+    constexpr int U = 8;
+    for (int base = tid; base < total; base += U * kThreads) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kThreads;
+            const int q = e / P, n = e - q * P;
+            v[u] = (e < total && q < nloc) ? R[(int64_t)ids[q] * P + n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kThreads;
+            if (e < total) {
+                const int q = e / P, n = e - q * P;
+                bsh[slot(q, n)] = Mma<TS>::conv(v[u]);
+            }
+        }
+    }
+    // zeros in the padded columns P .. Pp - 1
+    const int npad = Pp - P;
+    for (int e = tid; e < L * npad; e += kThreads) {
+        const int q = e / npad;
+        bsh[slot(q, P + e - q * npad)] = Mma<TS>::conv(0.0);
+    }
+    __syncthreads();
+    if (!active) return;
+    Acc acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
+    auto compute = [&](int slot, int j) {
+        const int pb = (2 * (j >> 1) * NT + (j & 1)) * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const uint4 b = lds_b[pb + 128 * t];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) dense_mma<TS>(acc[m][t], av[slot][m], b);
+        }
+    };
+    // a ring of three half-steps: slot j % 3 is refilled three halves ahead
+    // once its products are issued, so a whole super-step stays in flight
+    int j = 0;
+    for (; j + 3 <= nh; j += 3) {
+        compute(0, j);
+        if (j + 3 < nh) aload(0, j + 3);
+        compute(1, j + 1);
+        if (j + 4 < nh) aload(1, j + 4);
+        compute(2, j + 2);
+        if (j + 5 < nh) aload(2, j + 5);
+    }
+    if (j < nh) compute(0, j);
+    if (j + 1 < nh) compute(1, j + 1);
+    dense_epilogue<TS, NT, MT>(acc, P, r0, no, lane, own_gnode + own_off[s], afact, Z, omega, beta);
+}
+
+inline size_t dense_fused_lds(size_t entry_bytes, int Pp, int ld_max) {
+    return (size_t)Pp * ld_max * entry_bytes + (size_t)ld_max * 4;
 }
 
 }  // namespace
@@ -747,6 +923,37 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
     dim3 gg(r->n_sub, (maxn + 63) / 64);
     const int NT = r->Pp / 16;
     const int v = r->dense_var;
+    if (v == 2) {
+        SG_REQUIRE(r->fused_ok, "the fused dense RAS variant does not fit this problem");
+#define SG_FUSED_NT(TS, BUF, N)                                                                    \
+    case N:                                                                                        \
+        dense_fused_kernel<TS, N><<<r->nblk[2], 64 * kFusedWaves, r->fused_lds, s>>>(              \
+            r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p, r->sub_node_off.p,    \
+            r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF, R, r->afact.p, Z, omega, \
+            beta);                                                                                 \
+        break;
+        if (r->prec == SG_FP64) {
+            switch (NT) {
+                SG_FUSED_NT(double, r->ainv64.p, 1) SG_FUSED_NT(double, r->ainv64.p, 2)
+                default: SG_THROW(SG_ERR_UNSUPPORTED, "fused dense RAS with P=%d", r->P);
+            }
+        } else if (r->prec == SG_FP32) {
+            switch (NT) {
+                SG_FUSED_NT(float, r->ainv32.p, 1) SG_FUSED_NT(float, r->ainv32.p, 2)
+                SG_FUSED_NT(float, r->ainv32.p, 3)
+                default: SG_THROW(SG_ERR_UNSUPPORTED, "fused dense RAS with P=%d", r->P);
+            }
+        } else {
+            switch (NT) {
+                SG_FUSED_NT(uint16_t, r->ainv16.p, 1) SG_FUSED_NT(uint16_t, r->ainv16.p, 2)
+                SG_FUSED_NT(uint16_t, r->ainv16.p, 3)
+                default: SG_THROW(SG_ERR_UNSUPPORTED, "fused dense RAS with P=%d", r->P);
+            }
+        }
+#undef SG_FUSED_NT
+        HIP_LAUNCH_OK();
+        return;
+    }
 #define SG_DENSE(TS, BUF)                                                                          \
     do {                                                                                           \
         dense_gather_kernel<TS><<<gg, 256, 0, s>>>(r->P, r->Pp, r->sub_node_off.p, r->gnode.p,      \
@@ -765,12 +972,12 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
     case N:                                                                                        \
         if (v == 0)                                                                                \
             dense_apply_kernel<TS, N, 64><<<r->nblk[v], 256, 0, s>>>(                               \
-                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->aoff_d.p,      \
+                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->toff_d.p,      \
                 r->xoff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,                                  \
                 reinterpret_cast<const TS*>(r->xg.p), r->afact.p, Z, omega, beta);                 \
         else                                                                                       \
             dense_apply_kernel<TS, N, 32><<<r->nblk[v], 256, 0, s>>>(                               \
-                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->aoff_d.p,      \
+                r->P, r->blk_sub[v].p, r->blk_row0[v].p, r->nown_d.p, r->ld_d.p, r->toff_d.p,      \
                 r->xoff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,                                  \
                 reinterpret_cast<const TS*>(r->xg.p), r->afact.p, Z, omega, beta);                 \
         break;
@@ -916,10 +1123,11 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         r->h_ld.assign(ns, 0);
         r->h_nown.assign(ns, 0);
         r->h_aoff.assign(ns + 1, 0);
+        r->h_toff.assign(ns + 1, 0);
         r->h_xoff.assign(ns + 1, 0);
         std::vector<int64_t> own_off(ns + 1, 0);
         std::vector<int32_t> own_pos(r->h_gnode.size(), -1), own_gnode, node_sub;
-        std::vector<int32_t> bsub[2], brow[2];
+        std::vector<int32_t> bsub[3], brow[3];
         for (int q = 0; q < ns; ++q) {
             const int a0 = r->h_sub_node_off[q], a1 = r->h_sub_node_off[q + 1];
             int no = 0;
@@ -933,34 +1141,42 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
             r->h_ld[q] = (a1 - a0 + kDenseLd - 1) / kDenseLd * kDenseLd;
             r->h_nown[q] = no;
             r->h_aoff[q + 1] = r->h_aoff[q] + (int64_t)no * r->h_ld[q];
+            r->h_toff[q + 1] = r->h_toff[q] + (int64_t)(no + 15) / 16 * 16 * r->h_ld[q];
             r->h_xoff[q + 1] = r->h_xoff[q] + (int64_t)r->Pp * r->h_ld[q];
             own_off[q + 1] = own_off[q] + no;
-            for (int v = 0; v < 2; ++v)
-                for (int r0 = 0; r0 < no; r0 += 4 * kDenseRowChoices[v]) {
+            for (int v = 0; v < 3; ++v)
+                for (int r0 = 0; r0 < no; r0 += v < 2 ? 4 * kDenseRowChoices[v] : kFusedRows) {
                     bsub[v].push_back(q);
                     brow[v].push_back(r0);
                 }
         }
-        for (int v = 0; v < 2; ++v) r->nblk[v] = (int)bsub[v].size();
+        for (int v = 0; v < 3; ++v) r->nblk[v] = (int)bsub[v].size();
         r->own_pos.upload(own_pos, s);
         r->ld_d.upload(r->h_ld, s);
         r->nown_d.upload(r->h_nown, s);
         r->aoff_d.upload(r->h_aoff, s);
+        r->toff_d.upload(r->h_toff, s);
         r->xoff_d.upload(r->h_xoff, s);
         r->own_off_d.upload(own_off, s);
         r->own_gnode.upload(own_gnode, s);
         r->node_sub.upload(node_sub, s);
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < 3; ++v) {
             r->blk_sub[v].upload(bsub[v], s);
             r->blk_row0[v].upload(brow[v], s);
         }
         const size_t ts = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
+        int ld_max = 0;
+        for (int q = 0; q < ns; ++q) ld_max = std::max(ld_max, r->h_ld[q]);
+        int lds_max = 0;
+        HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, r->device));
+        r->fused_lds = dense_fused_lds(ts, r->Pp, ld_max);
+        r->fused_ok = r->Pp / 16 <= fused_max_nt(r->prec) && r->fused_lds <= (size_t)lds_max;
         r->xg.alloc((size_t)r->h_xoff[ns] * ts);
         HIP_OK(hipMemsetAsync(r->xg.p, 0, r->xg.bytes(), s));
     }
     const int64_t total = r->h_aoff[ns];
-    r->ainv64.alloc((size_t)total);
-    HIP_OK(hipMemsetAsync(r->ainv64.p, 0, (size_t)total * 8, s));
+    DevBuf<double> rows((size_t)total);
+    HIP_OK(hipMemsetAsync(rows.p, 0, (size_t)total * 8, s));
     DevBuf<double> zs_tmp((size_t)r->total_local * kSetupCols);
     int maxn = 0;
     for (int q = 0; q < ns; ++q) maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
@@ -973,7 +1189,7 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         kSetupCols, kColChunk, bmax, nmax, r->max_levels, r->sub_node_off.p, r->sub_lev_off.p,     \
         r->lev_start.p, r->lev_size.p, r->sinv_off.p, r->sinv64.p, r->gnode.p, r->owned.p,         \
         r->prev_idx.p, r->prev_val.p, r->next_idx.p, r->next_val.p, r->afact.p, nullptr, nullptr,  \
-        zs_tmp.p, 1.0, 0.0, qb, r->own_pos.p, r->ld_d.p, r->aoff_d.p, r->ainv64.p)
+        zs_tmp.p, 1.0, 0.0, qb, r->own_pos.p, r->ld_d.p, r->aoff_d.p, rows.p)
         const bool small = bmax <= 40, narrow = r->max_couple <= 2, wide = r->max_couple > 4;
         if (narrow && small)
             SG_SETUP_GO(2, 40);
@@ -988,16 +1204,25 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
 #undef SG_SETUP_GO
         HIP_LAUNCH_OK();
     }
-    if (r->prec != SG_FP64) {
-        if (r->prec == SG_FP32) r->ainv32.alloc((size_t)total);
-        else r->ainv16.alloc((size_t)total);
-        narrow_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-            total, r->ainv64.p, r->prec == SG_FP32 ? r->ainv32.p : nullptr,
-            r->prec == SG_BF16 ? r->ainv16.p : nullptr);
-        HIP_LAUNCH_OK();
-        HIP_OK(hipStreamSynchronize(s));
-        r->ainv64.release();
-    }
+    // narrow to the storage precision and rearrange into the tiled order
+    const int64_t tiled = r->h_toff[ns];
+    int maxo = 0;
+    for (int q = 0; q < ns; ++q) maxo = std::max(maxo, r->h_nown[q]);
+    const dim3 tg(ns, std::max(1, (maxo + 15) / 16));
+#define SG_TILE(TS, BUF)                                                                           \
+    do {                                                                                           \
+        BUF.alloc((size_t)tiled);                                                                  \
+        tile_dense_kernel<TS><<<tg, 256, 0, s>>>(r->nown_d.p, r->ld_d.p, r->aoff_d.p, r->toff_d.p, \
+                                                 rows.p, BUF.p);                                   \
+        HIP_LAUNCH_OK();                                                                           \
+    } while (0)
+    if (r->prec == SG_FP64)
+        SG_TILE(double, r->ainv64);
+    else if (r->prec == SG_FP32)
+        SG_TILE(float, r->ainv32);
+    else
+        SG_TILE(uint16_t, r->ainv16);
+#undef SG_TILE
     HIP_OK(hipStreamSynchronize(s));
     r->dense_built = true;
 }
@@ -1012,9 +1237,12 @@ extern "C" {
 int ras_select(sg_ras* r, int dense, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(r != nullptr, "ras is NULL");
-        SG_REQUIRE(dense >= 0 && dense <= 2, "path must be 0 (sweep), 1 or 2 (dense)");
+        SG_REQUIRE(dense >= 0 && dense <= 3, "path must be 0 (sweep), 1, 2 or 3 (dense)");
         check_device(r->device);
         if (dense && !r->dense_built) ras_build_dense(r, as_stream(stream));
+        if (dense == 3 && !r->fused_ok)
+            SG_THROW(SG_ERR_UNSUPPORTED, "fused dense RAS needs %zu bytes of LDS and P <= %d",
+                     r->fused_lds, 16 * fused_max_nt(r->prec));
         const bool changed = r->use_dense != (dense != 0) || (dense && r->dense_var != dense - 1);
         r->use_dense = dense != 0;
         if (dense) r->dense_var = dense - 1;
@@ -1036,10 +1264,12 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        // candidates: sweep, dense with 64 and with 32 rows per wave
-        double ms[3] = {0.0, 0.0, 0.0};
+        // candidates: sweep, dense with 64 and with 32 rows per wave, fused
+        // dense (where it fits; -1 otherwise)
+        double ms[4] = {0.0, 0.0, 0.0, -1.0};
         try {
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < 4; ++c) {
+                if (c == 3 && !r->fused_ok) break;
                 r->use_dense = c > 0;
                 r->dense_var = c > 0 ? c - 1 : 0;
                 ras_apply_ex(r, R.p, Z.p, 1.0, 0.0, s);            // warm-up
@@ -1059,13 +1289,14 @@ int ras_autotune(sg_ras* r, int reps, double* ms_out, void* stream) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         int best = 0;
-        for (int c = 1; c < 3; ++c)
-            if (ms[c] < ms[best]) best = c;
+        for (int c = 1; c < 4; ++c)
+            if (ms[c] >= 0.0 && ms[c] < ms[best]) best = c;
         r->ms_sweep = ms[0];
         r->ms_dense = std::min(ms[1], ms[2]);
+        if (ms[3] >= 0.0) r->ms_dense = std::min(r->ms_dense, ms[3]);
         r->use_dense = best > 0;
         r->dense_var = best > 0 ? best - 1 : 0;
-        if (ms_out) for (int c = 0; c < 3; ++c) ms_out[c] = ms[c];
+        if (ms_out) for (int c = 0; c < 4; ++c) ms_out[c] = ms[c];
         graph_cache_purge(r);   // captured steps hold the path they were recorded with
         return SG_OK;
     });
@@ -1077,7 +1308,7 @@ int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes) {
         if (dense) *dense = r->use_dense ? 1 + r->dense_var : 0;
         if (dense_bytes) {
             const int64_t per = r->prec == SG_FP64 ? 8 : (r->prec == SG_FP32 ? 4 : 2);
-            *dense_bytes = r->dense_built ? r->h_aoff[r->n_sub] * per : 0;
+            *dense_bytes = r->dense_built ? r->h_toff[r->n_sub] * per : 0;
         }
         return SG_OK;
     });

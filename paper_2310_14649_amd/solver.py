@@ -17,7 +17,7 @@ COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_
 
 
 class GpuSG:
-    """ras_path: "sweep", "dense", "dense32", or "auto" (timed by the library,
+    """ras_path: "sweep", "dense", "dense32", "fused", or "auto" (timed by the library,
     also choosing the staged matvec's work-group shape).  tune_cache: with
     "auto", a ``TuneCache`` (or its file path) that supplies choices already
     made for this shape and records new ones."""
@@ -48,7 +48,7 @@ class GpuSG:
         self.ras_ms = None
         self.mv_ms = None
         self.tuned_from_cache = False
-        if ras_path in ("dense", "dense32"):
+        if ras_path in ("dense", "dense32", "fused"):
             B.ras_select(self.ras, ras_path, stream=stream)
         elif ras_path == "auto":
             self._autotune(tune_cache, stream)

@@ -59,6 +59,9 @@ CASES = {
     "j4": dict(name="jit", nc=26, M=4, p=3, sub=(3, 3)),  # jittered, 7 entries per row
     "j2": dict(name="jit", nc=30, M=2, p=2, sub=(2, 3)),
     "g6": dict(name="jit", nc=44, M=6, p=2, sub=(1, 1), graph=(4, 3)),  # graph partition, M=6
+    # two subdomains of ~1100 owned nodes: the fused dense RAS takes two
+    # work-groups per subdomain (its LDS holds 16 x 1152 FP64 entries)
+    "big_sub": dict(name="c0", nc=48, sub=(1, 2)),
     # unknowns renumbered at random: no block of rows has neighbours in a few
     # runs of consecutive rows, so the operator takes the lane-pair kernel
     "perm": dict(name="c1", nc=40, sub=(4, 4), perm=5),
@@ -235,15 +238,25 @@ def test_ras_low_precision_close_to_oracle(built, prec, tol):
     assert err < tol
 
 
-@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "g6"])
+# keys whose FP64 fused dense path fits (P <= 32, right-hand sides in LDS)
+FUSED_FP64 = {"c0", "p1_det", "g6", "big_sub"}
+
+
+@pytest.mark.parametrize("key", ["c0", "c1_64", "c3_40", "c4_ragged", "p1_det", "j4", "g6", "big_sub"])
 def test_ras_dense_path_matches_oracle(built, key):
-    """The explicit-inverse path computes the same operator as the sweeps."""
+    """The explicit-inverse paths compute the same operator as the sweeps."""
     pr, S, g = built(key)
     subs = _oracle_ras(pr, S)
     R = np.random.default_rng(15).standard_normal((pr.mesh.n, S.P))
     Z = g.new_vec()
     try:
-        for path in ("dense", "dense32"):          # 64 and 32 owned rows per wave
+        # 64 and 32 owned rows per wave, and the fused gather + product
+        for path in ("dense", "dense32", "fused"):
+            if path == "fused" and key not in FUSED_FP64:
+                with pytest.raises(B.SgError) as ei:
+                    B.ras_select(g.ras, path)
+                assert ei.value.code == -4          # SG_ERR_UNSUPPORTED
+                continue
             B.ras_select(g.ras, path)
             dense, nbytes, name = B.ras_path_info(g.ras)
             assert dense and nbytes > 0 and name == path
@@ -269,7 +282,7 @@ def test_ras_dense_low_precision_close_to_oracle(built, prec, tol):
     R = np.random.default_rng(16).standard_normal((pr.mesh.n, S.P))
     Z = g.new_vec()
     try:
-        for path in ("dense", "dense32"):
+        for path in ("dense", "dense32", "fused"):
             B.ras_select(g.ras, path)
             B.ras_apply(g.ras, _to_dev(R), Z)
             err = _rel(_to_host(Z, R.shape), oras.ras_apply(subs, R, S.alpha_fact))
@@ -280,20 +293,23 @@ def test_ras_dense_low_precision_close_to_oracle(built, prec, tol):
 
 
 def test_ras_autotune_and_dense_fgmres(built):
-    """The autotuner times the three paths and keeps the fastest; FGMRES with
-    the dense BF16 local solves still reaches the FP64 solution (mixed path)."""
+    """The autotuner times the four paths and keeps the fastest; FGMRES with
+    the dense and the fused dense BF16 local solves still reaches the FP64
+    solution (mixed path)."""
     pr, S, _ = built("c1_64")
     g = GpuSG(pr, prec="bf16", coarse="amg", ras_path="auto")
     try:
         ms = g.ras_ms
         _, _, name = B.ras_path_info(g.ras)
-        print(f"[gpu] RAS autotune: sweep / dense / dense32 {ms} ms -> {name}")
-        assert min(ms) > 0 and name == ("sweep", "dense", "dense32")[int(np.argmin(ms))]
-        B.ras_select(g.ras, True)
-        x, info = g.solve(pr.restart, 1e-10)
-        assert info["converged"]
+        print(f"[gpu] RAS autotune: sweep / dense / dense32 / fused {ms} ms -> {name}")
+        assert len(ms) == 4 and min(ms) > 0
+        assert name == ("sweep", "dense", "dense32", "fused")[int(np.argmin(ms))]
         ref = osg.sg_solve_direct(S.K, S.G, S.B)
-        assert _rel(_to_host(x, ref.shape), ref) < 1e-8
+        for path in ("dense", "fused"):
+            B.ras_select(g.ras, path)
+            x, info = g.solve(pr.restart, 1e-10)
+            assert info["converged"]
+            assert _rel(_to_host(x, ref.shape), ref) < 1e-8
     finally:
         g.close()
 
