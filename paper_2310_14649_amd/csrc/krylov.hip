@@ -345,6 +345,38 @@ void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double 
 }
 
 // ------------------------------------------------------------------ graphs
+// Pinned host slots for the per-step residual estimates, two alternating,
+// each behind its own event: the copy of one step's estimate does not hold up
+// the launch of the next step.  The destructor waits for the stream, so no
+// copy still targets the slots when they are freed.
+struct PinnedEstimates {
+    double* p = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t s;
+    explicit PinnedEstimates(hipStream_t st) : s(st) {
+        try {
+            HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p), 4 * sizeof(double),
+                                 hipHostMallocDefault));
+            for (auto& e : ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        } catch (...) {
+            release();
+            throw;
+        }
+    }
+    ~PinnedEstimates() { release(); }
+    PinnedEstimates(const PinnedEstimates&) = delete;
+    PinnedEstimates& operator=(const PinnedEstimates&) = delete;
+
+  private:
+    void release() {
+        (void)hipStreamSynchronize(s);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
+};
+
 struct GraphKey {
     const void *op, *ras, *amg, *ws;
     size_t ws_bytes;
@@ -571,48 +603,72 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             relres = beta / bnorm;
             push_hist(relres);
             if (beta <= target) converged = true;
+            // one Arnoldi step, from its captured graph (captured on first use)
+            auto launch_step = [&](int j) {
+                if (!opts->use_graph) {
+                    arnoldi_step(j, s);
+                    return;
+                }
+                hipGraphExec_t exec = nullptr;
+                GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, opts->ortho, 0};
+                std::memcpy(&key.omega_bits, &omega, sizeof(double));
+                {
+                    std::lock_guard<std::mutex> lk(g_graph_mu);
+                    auto it = graph_cache().find(key);
+                    if (it != graph_cache().end()) exec = it->second;
+                }
+                if (!exec) {
+                    hipStream_t cst = capture_stream(device);
+                    HIP_OK(hipStreamSynchronize(s));
+                    HIP_OK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
+                    try {
+                        arnoldi_step(j, cst);
+                    } catch (...) {
+                        hipGraph_t bad = nullptr;
+                        (void)hipStreamEndCapture(cst, &bad);
+                        if (bad) (void)hipGraphDestroy(bad);
+                        throw;
+                    }
+                    hipGraph_t graph = nullptr;
+                    HIP_OK(hipStreamEndCapture(cst, &graph));
+                    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    HIP_OK(ie);
+                    std::lock_guard<std::mutex> lk(g_graph_mu);
+                    graph_cache()[key] = exec;
+                }
+                HIP_OK(hipGraphLaunch(exec, s));
+            };
+            PinnedEstimates pin(s);
             while (!converged && its < opts->max_it) {
                 init_cycle_kernel<<<1, 128, 0, s>>>(m + 1, beta, g);
                 HIP_LAUNCH_OK();
                 Vec::scale(N, 1.0 / beta, V, V, s);
                 int jd = 0;
-                double hs[2] = {0.0, 0.0};
+                int launched = -1;
+                double est_prev[2] = {0.0, 0.0};   // estimates of the last two steps
                 for (int j = 0; j < m; ++j) {
-                    if (opts->use_graph) {
-                        hipGraphExec_t exec = nullptr;
-                        GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, opts->ortho, 0};
-                        std::memcpy(&key.omega_bits, &omega, sizeof(double));
-                        {
-                            std::lock_guard<std::mutex> lk(g_graph_mu);
-                            auto it = graph_cache().find(key);
-                            if (it != graph_cache().end()) exec = it->second;
-                        }
-                        if (!exec) {
-                            hipStream_t cst = capture_stream(device);
-                            HIP_OK(hipStreamSynchronize(s));
-                            HIP_OK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
-                            try {
-                                arnoldi_step(j, cst);
-                            } catch (...) {
-                                hipGraph_t bad = nullptr;
-                                (void)hipStreamEndCapture(cst, &bad);
-                                if (bad) (void)hipGraphDestroy(bad);
-                                throw;
-                            }
-                            hipGraph_t graph = nullptr;
-                            HIP_OK(hipStreamEndCapture(cst, &graph));
-                            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                            (void)hipGraphDestroy(graph);
-                            HIP_OK(ie);
-                            std::lock_guard<std::mutex> lk(g_graph_mu);
-                            graph_cache()[key] = exec;
-                        }
-                        HIP_OK(hipGraphLaunch(exec, s));
-                    } else {
-                        arnoldi_step(j, s);
+                    if (launched < j) {
+                        launch_step(j);
+                        launched = j;
                     }
-                    HIP_OK(hipMemcpyAsync(hs, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-                    HIP_OK(hipStreamSynchronize(s));
+                    double* hb = pin.p + 2 * (j & 1);
+                    HIP_OK(hipMemcpyAsync(hb, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                    HIP_OK(hipEventRecord(pin.ev[j & 1], s));
+                    // The next step runs while the host reads this one's
+                    // estimate.  A step past convergence writes only column
+                    // j + 1 of H, g[j + 1], g[j + 2], V_{j+2} and Z_{j+1},
+                    // none of which the update with j + 1 columns reads; it
+                    // is not started where the last two estimates extrapolate
+                    // to within 4 x the target (it would be wasted work).
+                    const bool near = j >= 2 && est_prev[1] > 0.0 &&
+                                      est_prev[0] * est_prev[0] / est_prev[1] <= 4.0 * target;
+                    if (j + 1 < m && its + 1 < opts->max_it && !near) {
+                        launch_step(j + 1);
+                        launched = j + 1;
+                    }
+                    HIP_OK(hipEventSynchronize(pin.ev[j & 1]));
+                    const double hs[2] = {hb[0], hb[1]};
                     ++its;
                     jd = j + 1;
                     if (!std::isfinite(hs[0]))
@@ -620,6 +676,8 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                     relres = hs[0] / bnorm;
                     push_hist(relres);
                     if (hs[0] <= target || hs[1] != 0.0 || its >= opts->max_it) break;
+                    est_prev[1] = est_prev[0];
+                    est_prev[0] = hs[0];
                 }
                 trisolve_kernel<<<1, 1, 0, s>>>(jd, m + 1, H, g, y);
                 HIP_LAUNCH_OK();
