@@ -62,29 +62,120 @@ def matvec_flops(n: int, nnz: int, L: int, P: int, T: int) -> int:
     return 2 * nnz * L * P + 2 * n * T
 
 
-def time_matvec(g, launches: int, torch):
-    """Average duration of the matvec kernel, HIP events around each launch
-    on the launching stream, 512 MB written between launches to flush the
-    256 MB Infinity Cache."""
-    from paper_2310_14649_amd import binding as B
-    X = g.new_vec()
-    X.normal_()
-    Y = g.new_vec()
+def time_launches(fn, launches: int, torch):
+    """Mean and median duration (ms) of fn() on the current stream (where
+    the library launches when given no stream), HIP events around each call,
+    512 MB written between calls to flush the 256 MB Infinity Cache."""
     flush = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     for _ in range(5):
-        B.sg_matvec(g.op, X, Y)
+        fn()
     times = []
     for _ in range(launches):
         flush.add_(1.0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        B.sg_matvec(g.op, X, Y)
+        fn()
         e1.record(stream)
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
     return float(np.mean(times)), float(np.median(times))
+
+
+def time_matvec(g, launches: int, torch):
+    """Average duration of the matvec kernel (see time_launches)."""
+    from paper_2310_14649_amd import binding as B
+    X = g.new_vec()
+    X.normal_()
+    Y = g.new_vec()
+    return time_launches(lambda: B.sg_matvec(g.op, X, Y), launches, torch)
+
+
+ENTRY_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense, MI355X
+
+
+def ras_only(pr, prec: str, path: str, launches: int, torch, g=None) -> dict:
+    """One RAS apply (Z = sum_s R_s^T D_s A_s^{-1} R_s R) timed alone.
+    Algorithmic bytes: the stored inverse data read once (dense rows, or the
+    sweep's Schur-complement inverses), R read once, Z written once; flops
+    of the dense paths: 2 n_own n_local P per subdomain.  g: an existing
+    GpuSG of that precision to reuse (kept open), else one is set up."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.solver import GpuSG
+    own = g is None
+    if own:
+        g = GpuSG(pr, prec=prec, coarse="none", ras_path=path)
+    try:
+        name = B.ras_path_info(g.ras)[2]
+        nloc, _, factor_bytes = B.ras_info(g.ras, pr.n_sub)
+        nown = np.bincount(np.asarray(pr.owner), minlength=pr.n_sub).astype(np.int64)
+        vec = g.n * g.P * 8
+        dense_entries = int((nown * nloc.astype(np.int64)).sum())
+        if name == "sweep":
+            stored = int(factor_bytes)
+            flops = None
+        else:
+            stored = dense_entries * ENTRY_BYTES[prec]
+            flops = 2 * dense_entries * g.P
+        R = g.new_vec()
+        R.normal_()
+        Z = g.new_vec()
+        mean_ms, med_ms = time_launches(lambda: B.ras_apply(g.ras, R, Z), launches, torch)
+        nbytes = stored + 2 * vec
+        out = {"ras_only": True, "prec": prec, "path": name, "us": round(mean_ms * 1e3, 2),
+               "median_us": round(med_ms * 1e3, 2), "bytes": nbytes, "stored_bytes": stored,
+               "GBps": round(nbytes / (mean_ms * 1e-3) / 1e9, 1),
+               "frac_hbm_peak": round(nbytes / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "ras_ms_sweep_dense_dense32_fused": g.ras_ms}
+        if flops is not None:
+            tf = flops / (mean_ms * 1e-3) / 1e12
+            out.update(flops=flops, TFLOPs=round(tf, 2),
+                       frac_mfma_peak=round(tf / MFMA_PEAK_TFLOPS[prec], 4))
+        return out
+    finally:
+        if own:
+            g.close()
+
+
+def amg_only(pr, prec: str, launches: int, torch, g=None) -> dict:
+    """One SA-AMG V(1,1)-cycle on the coarse problem timed alone.
+    Algorithmic bytes per cycle: on every level but the coarsest, the
+    operator's blocks twice (the residuals after pre- and post-smoothing),
+    the prolongator and restriction once each and the block-Jacobi inverses
+    twice; the coarsest dense FP64 inverse once (vectors are negligible).
+    g: an existing GpuSG with an AMG coarse solver to reuse (kept open)."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.solver import GpuSG
+    own = g is None
+    if own:
+        g = GpuSG(pr, prec=prec, coarse="amg", ras_path="sweep")
+    try:
+        P = g.P
+        nl, nodes, _ = B.amg_info(g.amg, pr.n_sub)
+        blk = P * P * 8
+        levels = []
+        nbytes = 0
+        for lv in range(nl):
+            a_b, p_b, r_b = B.amg_level_blocks(g.amg, lv)
+            if lv < nl - 1:
+                lb = (2 * a_b + p_b + r_b) * blk + 2 * int(nodes[lv]) * P * P * ENTRY_BYTES[prec]
+            else:
+                lb = a_b * blk
+            levels.append(dict(nodes=int(nodes[lv]), a_blocks=a_b, p_blocks=p_b, r_blocks=r_b,
+                               bytes=lb))
+            nbytes += lb
+        b_c = torch.randn(pr.n_sub * P, dtype=torch.float64, device="cuda")
+        x_c = torch.empty_like(b_c)
+        mean_ms, med_ms = time_launches(lambda: B.amg_vcycle(g.amg, b_c, x_c), launches, torch)
+        return {"amg_only": True, "prec": prec, "levels": levels, "us": round(mean_ms * 1e3, 2),
+                "median_us": round(med_ms * 1e3, 2), "bytes": nbytes,
+                "GBps": round(nbytes / (mean_ms * 1e-3) / 1e9, 1),
+                "frac_hbm_peak": round(nbytes / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    finally:
+        if own:
+            g.close()
 
 
 def cpu_baseline(pr, its_gpu: int, sample_its: int):
@@ -211,8 +302,16 @@ def main() -> int:
                     help="Arnoldi orthogonalisation")
     ap.add_argument("--ortho-compare", default="mgs",
                     help="other orthogonalisations timed on the mixed solve (comma list)")
-    ap.add_argument("--ras-path", default="auto", choices=["auto", "sweep", "dense"],
+    ap.add_argument("--ras-path", default="auto",
+                    choices=["auto", "sweep", "dense", "dense32", "fused"],
                     help="RAS apply path: autotuned per precision, or forced")
+    ap.add_argument("--ras-only", action="store_true",
+                    help="time only one RAS apply (precision --part-prec) and print its figures")
+    ap.add_argument("--amg-only", action="store_true",
+                    help="time only one AMG V-cycle (precision --part-prec) and print its figures")
+    ap.add_argument("--part-prec", default="bf16", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--parts", type=int, default=1,
+                    help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
     ap.add_argument("--learned-draws", type=int, default=256,
                     help="training solves for the learned Newton guess (0: skip)")
@@ -233,6 +332,12 @@ def main() -> int:
     torch.cuda.set_device(0)
     pr = make_problem(args.config)
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
+    if args.ras_only:
+        print(json.dumps(ras_only(pr, args.part_prec, args.ras_path, args.mv_launches, torch)))
+        return 0
+    if args.amg_only:
+        print(json.dumps(amg_only(pr, args.part_prec, args.mv_launches, torch)))
+        return 0
     if args.matvec_only:
         g = GpuSG(pr, prec="fp64", coarse="none")
         if args.mv_tiles:
@@ -315,6 +420,13 @@ def main() -> int:
     mv_bytes = matvec_bytes(n, nnz, L, P)
     mv_gbs = mv_bytes / (mv_mean_ms * 1e-3) / 1e9
     log(f"[bench] matvec: {mv_mean_ms * 1e3:.1f} us avg, {mv_gbs:.0f} GB/s algorithmic")
+    # the two preconditioner parts alone, on the mixed-precision solver
+    parts = {}
+    if args.parts:
+        parts["ras"] = ras_only(pr, args.mixed, args.ras_path, 20, torch, g=solvers[args.mixed])
+        parts["amg_vcycle"] = amg_only(pr, args.mixed, 50, torch, g=solvers[args.mixed])
+        log(f"[bench] RAS {parts['ras']['path']}: {parts['ras']['us']:.1f} us, "
+            f"{parts['ras']['GBps']:.0f} GB/s; AMG V-cycle {parts['amg_vcycle']['us']:.1f} us")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -358,6 +470,7 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch"},
+        "parts": parts,
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
         "ras_path": ras_paths,
         "omega": omega,

@@ -212,6 +212,13 @@ int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec p
  * not NULL, receives the first-level aggregate of every subdomain [n_sub]
  * (-1 when there is a single level). */
 int amg_info(const sg_amg* a, int* n_levels, int32_t* nodes_per_level, int32_t* agg);
+/* host outputs (any may be NULL): the P x P FP64 blocks stored for level
+ * `level` (0 .. n_levels-1) of an SG_COARSE_AMG hierarchy: its operator,
+ * prolongator and restriction; on the coarsest level the operator is the
+ * dense inverse (n_l^2 blocks) and the other two are 0.  For sizing the
+ * bytes a V-cycle moves.  SG_ERR_INVALID_ARG for a level out of range. */
+int amg_level_blocks(const sg_amg* a, int level, int64_t* a_blocks, int64_t* p_blocks,
+                     int64_t* r_blocks);
 int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream);
 /* r_c = Z^T R (sum over owned nodes) and Y += Z e_c.  Asynchronous. */
 int sg_coarse_restrict(const sg_amg* a, const double* R, double* r_c, void* stream);

@@ -89,6 +89,7 @@ _SIGS = {
     "amg_setup": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "amg_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i32p, _i32p]),
     "amg_vcycle": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "amg_level_blocks": (C.c_int, [_vp, C.c_int, _i64p, _i64p, _i64p]),
     "sg_coarse_restrict": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_coarse_prolong_add": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_destroy_amg": (None, [_vp]),
@@ -343,6 +344,13 @@ def amg_info(a, n_sub: int):
     agg = np.zeros(n_sub, dtype=np.int32)
     _check(lib().amg_info(a, C.byref(nl), _ptr(nodes, C.c_int32), _ptr(agg, C.c_int32)))
     return nl.value, nodes[:nl.value], agg
+
+
+def amg_level_blocks(a, level: int):
+    """(operator, prolongator, restriction) P x P blocks stored on `level`."""
+    ab, pb, rb = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().amg_level_blocks(a, level, C.byref(ab), C.byref(pb), C.byref(rb)))
+    return ab.value, pb.value, rb.value
 
 
 def amg_vcycle(a, b_c, x_c, stream=None):

@@ -752,6 +752,21 @@ int amg_info(const sg_amg* a, int* n_levels, int32_t* nodes_per_level, int32_t* 
     });
 }
 
+int amg_level_blocks(const sg_amg* a, int level, int64_t* a_blocks, int64_t* p_blocks,
+                     int64_t* r_blocks) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a != nullptr, "amg is NULL");
+        SG_REQUIRE(level >= 0 && level < (int)a->lev.size(), "level %d out of range (%zu levels)",
+                   level, a->lev.size());
+        const AmgLevel& L = a->lev[level];
+        const bool coarsest = level == (int)a->lev.size() - 1;
+        if (a_blocks) *a_blocks = coarsest ? (int64_t)L.nn * L.nn : (int64_t)L.a_col.n;
+        if (p_blocks) *p_blocks = coarsest ? 0 : (int64_t)L.p_col.n;
+        if (r_blocks) *r_blocks = coarsest ? 0 : (int64_t)L.r_col.n;
+        return SG_OK;
+    });
+}
+
 int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(a && b_c && x_c, "null argument");

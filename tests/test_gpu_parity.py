@@ -368,6 +368,16 @@ def test_coarse_and_vcycle_match_oracle(built, key):
     assert nodes.tolist() == [A.shape[0] // S.P for A in h.A]
     if h.n_levels > 1:
         assert np.array_equal(agg, h.aggs[0])
+    # stored blocks per level: R = P^T holds as many blocks as P, every node
+    # has its diagonal block and a prolongator block; the coarsest level is dense
+    for lv in range(nl):
+        a_b, p_b, r_b = B.amg_level_blocks(g.amg, lv)
+        if lv < nl - 1:
+            assert a_b >= nodes[lv] and p_b >= nodes[lv] and r_b == p_b
+        else:
+            assert (a_b, p_b, r_b) == (int(nodes[lv]) ** 2, 0, 0)
+    with pytest.raises(B.SgError):
+        B.amg_level_blocks(g.amg, nl)
     rng = np.random.default_rng(15)
     R = rng.standard_normal((pr.mesh.n, S.P))
     rc = torch.zeros(pr.n_sub * S.P, dtype=torch.float64, device="cuda")
