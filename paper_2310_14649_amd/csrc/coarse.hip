@@ -140,8 +140,13 @@ __global__ void mean_exact_kernel(int ns, int P, const double* __restrict__ inv,
 // y = beta * c + alpha * A x   (block-sparse, dense P x P blocks).  One
 // work-group of kBlkMv threads per block-row: thread (k, part) sums the
 // block-rows' neighbour blocks part, part + nparts, ... for output row k,
-// then the parts are added in a fixed order through LDS.
+// then the parts are added in a fixed order through LDS.  Blocks stored by
+// rows (kColMajor false: each lane walks its own row, which suits block rows
+// with few blocks) or by columns (a load instruction reads consecutive
+// entries, which suits block rows with many blocks, where the lanes' rows
+// would overflow L1: the restriction).
 constexpr int kBlkMv = 1024;
+template <bool kColMajor>
 __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val,
@@ -154,15 +159,17 @@ __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __
     double acc = 0.0;
     if (pi < nparts) {
         for (int q = ptr[s] + pi; q < ptr[s + 1]; q += nparts) {
-            const double* blk = val + (size_t)q * P * P + (size_t)k * P;
+            // entry (k, j) of block q at blk[j * js]
+            const double* blk = val + (size_t)q * P * P + (kColMajor ? (size_t)k : (size_t)k * P);
+            const size_t js = kColMajor ? (size_t)P : 1;
             const double* xv = x + (size_t)col[q] * P;
             double a0 = 0.0, a1 = 0.0;
             int j = 0;
             for (; j + 1 < P; j += 2) {
-                a0 = fma(blk[j], xv[j], a0);
-                a1 = fma(blk[j + 1], xv[j + 1], a1);
+                a0 = fma(blk[j * js], xv[j], a0);
+                a1 = fma(blk[(j + 1) * js], xv[j + 1], a1);
             }
-            if (j < P) a0 = fma(blk[j], xv[j], a0);
+            if (j < P) a0 = fma(blk[j * js], xv[j], a0);
             acc += a0 + a1;
         }
     }
@@ -414,11 +421,25 @@ std::vector<T> transpose_blocks(const std::vector<T>& v, int P) {
     return t;
 }
 
+// col_major: store every P x P block by columns (the layout bsr_mv_kernel
+// reads with kColMajor).
 void upload_bsr(const Bsr& A, DevBuf<int32_t>& ptr, DevBuf<int32_t>& col, DevBuf<double>& val,
-                hipStream_t s) {
+                hipStream_t s, bool col_major = false) {
     ptr.upload(A.ptr, s);
     col.upload(A.col, s);
-    val.upload(A.val, s);
+    if (!col_major) {
+        val.upload(A.val, s);
+        return;
+    }
+    const size_t nb = A.col.size();
+    const int P = A.P;
+    std::vector<double> t(A.val.size());
+    for (size_t q = 0; q < nb; ++q)
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j)
+                t[q * P * P + (size_t)j * P + i] = A.val[q * P * P + (size_t)i * P + j];
+    val.upload(t, s);
+    HIP_OK(hipStreamSynchronize(s));   // t is freed on return
 }
 
 }  // namespace
@@ -444,15 +465,18 @@ void amg_vcycle_level(const sg_amg* a, int l, const double* b, double* x, hipStr
         HIP_LAUNCH_OK();
     };
     jacobi(b, 0.0);
-    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    bsr_mv_kernel<false><<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0,
+                                               1.0, b);
     HIP_LAUNCH_OK();
-    bsr_mv_kernel<<<C.nn, kBlkMv, 0, s>>>(P, L.r_ptr.p, L.r_col.p, L.r_val.p, L.r.p, C.b.p, 1.0, 0.0,
-                                        nullptr);
+    bsr_mv_kernel<true><<<C.nn, kBlkMv, 0, s>>>(P, L.r_ptr.p, L.r_col.p, L.r_val.p, L.r.p, C.b.p, 1.0,
+                                              0.0, nullptr);
     HIP_LAUNCH_OK();
     amg_vcycle_level(a, l + 1, C.b.p, C.x.p, s);
-    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, C.x.p, x, 1.0, 1.0, x);
+    bsr_mv_kernel<false><<<L.nn, kBlkMv, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, C.x.p, x, 1.0, 1.0,
+                                               x);
     HIP_LAUNCH_OK();
-    bsr_mv_kernel<<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0, 1.0, b);
+    bsr_mv_kernel<false><<<L.nn, kBlkMv, 0, s>>>(P, L.a_ptr.p, L.a_col.p, L.a_val.p, x, L.r.p, -1.0,
+                                               1.0, b);
     HIP_LAUNCH_OK();
     jacobi(L.r.p, 1.0);
 }
@@ -619,7 +643,7 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
         if (l < nl - 1) {
             upload_bsr(As[l], Lv.a_ptr, Lv.a_col, Lv.a_val, s);
             upload_bsr(Ps[l], Lv.p_ptr, Lv.p_col, Lv.p_val, s);
-            upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s);
+            upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s, true);
             if (prec == SG_FP64) {
                 Lv.dinv64.upload(Dinvs[l], s);
             } else if (prec == SG_FP32) {
