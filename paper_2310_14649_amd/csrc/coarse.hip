@@ -94,9 +94,22 @@ __global__ __launch_bounds__(256) void restrict_partial_kernel(
     const int stripes = 256 / P;
     const int k = tid % P, st = tid / P;
     double acc = 0.0;
-    if (st < stripes)
-        for (int q = slice_beg[sl] + st; q < slice_end[sl]; q += stripes)
-            acc += R[(size_t)own_nodes[q] * P + k];
+    if (st < stripes) {
+        // the nodes q = beg + st, beg + st + stripes, ... added in order; the
+        // loads of four of them are issued before their additions
+        const int end = slice_end[sl];
+        for (int q = slice_beg[sl] + st; q < end; q += 4 * stripes) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int qq = q + u * stripes;
+                v[u] = qq < end ? R[(size_t)own_nodes[qq] * P + k] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q + u * stripes < end) acc += v[u];
+        }
+    }
     red[tid] = acc;
     __syncthreads();
     if (tid < P) {
@@ -116,12 +129,14 @@ __global__ void restrict_final_kernel(int ns, int P, const int32_t* __restrict__
     rc[idx] = t;
 }
 
-__global__ void prolong_add_kernel(int64_t total, int P, const int32_t* __restrict__ owner,
+// Y[a, k] += e_c[owner(a), k]; total = n P < 2^31 (checked by the caller),
+// so the node index comes from a 32-bit division.
+__global__ void prolong_add_kernel(int total, int P, const int32_t* __restrict__ owner,
                                    const double* __restrict__ ec, double* __restrict__ Y) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    int64_t a = idx / P;
-    int k = (int)(idx - a * P);
+    const int a = (int)((unsigned)idx / (unsigned)P);
+    const int k = idx - a * P;
     Y[idx] += ec[(size_t)owner[a] * P + k];
 }
 
@@ -507,8 +522,11 @@ void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s
 }
 
 void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s) {
-    int64_t tot = (int64_t)a->n * a->P;
-    prolong_add_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(tot, a->P, a->owner.p, ec, Y);
+    const int64_t tot = (int64_t)a->n * a->P;
+    SG_REQUIRE(tot < (int64_t)INT32_MAX, "n*P = %lld exceeds the 32-bit prolongation index",
+               (long long)tot);
+    prolong_add_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((int)tot, a->P, a->owner.p,
+                                                                       ec, Y);
     HIP_LAUNCH_OK();
 }
 

@@ -220,8 +220,16 @@ __global__ __launch_bounds__(kVT) void normalize_kernel(int64_t N, int nb,
         flag[0] = (nrm == 0.0) ? 1.0 : 0.0;
     }
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N; i += (int64_t)gridDim.x * kVT)
-        vnext[i] = w[i] * inv;
+    // pairs through 16-byte accesses (both vectors start 256-byte aligned),
+    // an odd last element by the first thread
+    const int64_t N2 = N >> 1;
+    const double2* w2 = reinterpret_cast<const double2*>(w);
+    double2* v2 = reinterpret_cast<double2*>(vnext);
+    for (int64_t i = (int64_t)blockIdx.x * kVT + threadIdx.x; i < N2; i += (int64_t)gridDim.x * kVT) {
+        const double2 x = w2[i];
+        v2[i] = make_double2(x.x * inv, x.y * inv);
+    }
+    if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) vnext[N - 1] = w[N - 1] * inv;
 }
 
 // Apply the previous rotations to column j, form rotation j, update g.
