@@ -552,6 +552,57 @@ def test_full_size_ras_sampled_subdomains(full_c1):
         assert _rel(Zh[nodes[mask]], loc[mask]) < 1e-10, sd
 
 
+def _sampled_local_solves(pr, S, R, subs):
+    """The oracle's dense local solves of a few subdomains: (owned node ids,
+    their rows of the RAS output)."""
+    import scipy.linalg as sla
+    out = []
+    for sd in subs:
+        own = np.nonzero(pr.owner == sd)[0]
+        nodes = oras.grow_overlap(own, S.adj, pr.overlap)
+        loc = sla.cho_solve(sla.cho_factor(S.K[0][nodes][:, nodes].toarray(), lower=True),
+                            R[nodes]) / S.alpha_fact[None, :]
+        mask = pr.owner[nodes] == sd
+        out.append((nodes[mask], loc[mask]))
+    return out
+
+
+def test_full_size_ras_dense_and_fused_paths(full_c1):
+    """The explicit-inverse paths at full size: FP64 dense (64 and 32 rows per
+    wave) against the oracle's local solves to 1e-10, and the BF16 fused path
+    the benchmark times against them to the BF16 bound and bit for bit
+    against the BF16 two-kernel path."""
+    pr, S, g = full_c1
+    rng = np.random.default_rng(23)
+    R = rng.standard_normal((pr.mesh.n, S.P))
+    ref = _sampled_local_solves(pr, S, R, (0, 31, 128, 255))
+    Z = g.new_vec()
+    try:
+        for path in ("dense", "dense32"):
+            B.ras_select(g.ras, path)
+            B.ras_apply(g.ras, _to_dev(R), Z)
+            Zh = _to_host(Z, R.shape)
+            for rows, loc in ref:
+                assert _rel(Zh[rows], loc) < 1e-10, path
+    finally:
+        B.ras_select(g.ras, "sweep")
+    g16 = GpuSG(pr, prec="bf16", coarse="none")
+    try:
+        out = {}
+        for path in ("dense", "fused"):
+            B.ras_select(g16.ras, path)
+            Z16 = g16.new_vec()
+            B.ras_apply(g16.ras, _to_dev(R), Z16)
+            out[path] = Z16
+            Zh = _to_host(Z16, R.shape)
+            for rows, loc in ref:
+                err = _rel(Zh[rows], loc)
+                assert err < 6e-2, (path, err)
+        assert torch.equal(out["dense"], out["fused"])
+    finally:
+        g16.close()
+
+
 # ------------------------------------------------------------------ a10
 def test_graph_replay_matches_eager(built):
     """Arnoldi steps replayed from captured graphs give the eager result bit
