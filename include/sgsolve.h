@@ -173,7 +173,7 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
  *   with 32, 3 = fused dense: one work-group per subdomain gathers its
  *   right-hand sides into on-chip memory itself and streams the rows once
  *   (available where P_pad x n_local entries plus n_local node ids fit one
- *   work-group's LDS and P <= 48, FP64: P <= 32; else SG_ERR_UNSUPPORTED).
+ *   work-group's LDS and P <= 48, FP64: P <= 16; else SG_ERR_UNSUPPORTED).
  *   The dense rows are built on first use; device memory
  *   sum_s ceil16(n_own(s)) * ceil64(n_local(s)) entries.  Synchronous.
  * ras_autotune: builds the dense rows if needed, times `reps` applies of

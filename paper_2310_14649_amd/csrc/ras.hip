@@ -787,8 +787,9 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
 // LDS: Pp x ld entries of TS plus ld node ids.
 constexpr int kFusedWaves = 16;
 constexpr int kFusedRows = 64 * kFusedWaves;
+constexpr int kFusedChunks = 7;   // right-hand-side chunks gathered under the stream
 // column tiles whose accumulators fit the 128 registers of a 16-wave group
-inline int fused_max_nt(sg_prec prec) { return prec == SG_FP64 ? 2 : 3; }
+inline int fused_max_nt(sg_prec prec) { return prec == SG_FP64 ? 1 : 3; }
 template <class TS, int NT>
 __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
@@ -839,11 +840,9 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
         aload(1, 1);
         if (nh > 2) aload(2, 2);
     }
-    // node ids after the B pieces, then the gather: e = q Pp + n, consecutive
-    // threads read consecutive entries of a node's row of R
+    // node ids after the B pieces
     int32_t* ids = reinterpret_cast<int32_t*>(lds_b + (size_t)nks * NT * 128);
     for (int q = tid; q < nloc; q += kThreads) ids[q] = gnode[node0 + q];
-    __syncthreads();
     TS* bsh = reinterpret_cast<TS*>(lds_b);
     // LDS slot of entry (local node q, column n)
     auto slot = [&](int q, int n) {
@@ -851,61 +850,103 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
         const int g = w / (2 * KL), h = (w / KL) & 1, el = w % KL;
         return (((ks * NT + (n >> 4)) * 2 + h) * 64 + (n & 15) + 16 * g) * KL + el;
     };
-    // the P real columns (zero for the padded nodes q >= nloc), U loads in flight
-    const int total = L * P;
-    constexpr int U = 8;
-    for (int base = tid; base < total; base += U * kThreads) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * kThreads;
-            const int q = e / P, n = e - q * P;
-            v[u] = (e < total && q < nloc) ? R[(int64_t)ids[q] * P + n] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * kThreads;
-            if (e < total) {
-                const int q = e / P, n = e - q * P;
-                bsh[slot(q, n)] = Mma<TS>::conv(v[u]);
-            }
-        }
-    }
-    // zeros in the padded columns P .. Pp - 1
+    // zeros in the padded columns P .. Pp - 1 (no chunk's gather writes them)
     const int npad = Pp - P;
     for (int e = tid; e < L * npad; e += kThreads) {
         const int q = e / npad;
         bsh[slot(q, P + e - q * npad)] = Mma<TS>::conv(0.0);
     }
     __syncthreads();
-    if (!active) return;
+    // The right-hand sides arrive in chunks of CS super-steps (a multiple of
+    // three, so that chunk borders fall on the three-slot ring below).  Entry
+    // e of a chunk is local node q0 + e / P, column e % P: consecutive threads
+    // read consecutive entries of a node's row of R; padded nodes are zero.
+    const int CS = 3 * ((nks + 3 * kFusedChunks - 1) / (3 * kFusedChunks));
+    const int nchunks = (nks + CS - 1) / CS;
+    auto chunk_count = [&](int c) { return (min((c + 1) * CS * KSUP, L) - c * CS * KSUP) * P; };
+    auto fetch = [&](int c, int e) {
+        const int q = c * CS * KSUP + e / P;
+        return q < nloc ? R[(int64_t)ids[q] * P + (e - (e / P) * P)] : 0.0;
+    };
+    auto put = [&](int c, int e, double v) {
+        const int q = c * CS * KSUP + e / P;
+        bsh[slot(q, e - (e / P) * P)] = Mma<TS>::conv(v);
+    };
+    {   // chunk 0 in full, U loads in flight per thread
+        constexpr int U = 8;
+        const int cnt = chunk_count(0);
+        for (int base = tid; base < cnt; base += U * kThreads) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * kThreads;
+                v[u] = e < cnt ? fetch(0, e) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (base + u * kThreads < cnt) put(0, base + u * kThreads, v[u]);
+        }
+    }
+    __syncthreads();
     Acc acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
-    auto compute = [&](int slot, int j) {
+    auto compute = [&](int slot_, int j) {
         const int pb = (2 * (j >> 1) * NT + (j & 1)) * 64 + lane;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const uint4 b = lds_b[pb + 128 * t];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) dense_mma<TS>(acc[m][t], av[slot][m], b);
+            for (int m = 0; m < MT; ++m) dense_mma<TS>(acc[m][t], av[slot_][m], b);
         }
     };
-    // a ring of three half-steps: slot j % 3 is refilled three halves ahead
-    // once its products are issued, so a whole super-step stays in flight
-    int j = 0;
-    for (; j + 3 <= nh; j += 3) {
-        compute(0, j);
-        if (j + 3 < nh) aload(0, j + 3);
-        compute(1, j + 1);
-        if (j + 4 < nh) aload(1, j + 4);
-        compute(2, j + 2);
-        if (j + 5 < nh) aload(2, j + 5);
+    // While chunk c streams, every thread (active wave or not) fetches two
+    // entries of chunk c + 1 per half-step and stores the two it fetched one
+    // half-step earlier; what is left of chunk c + 1 is fetched at the end of
+    // chunk c, then a barrier publishes it.  A wave's A stream is the ring of
+    // three half-steps: slot j % 3 is refilled three halves ahead once its
+    // products are issued.
+    for (int c = 0; c < nchunks; ++c) {
+        const int j0 = 2 * c * CS, j1 = min(2 * (c + 1) * CS, nh);
+        const int cn = c + 1 < nchunks ? chunk_count(c + 1) : 0;
+        int ge = tid;                      // next entry of chunk c + 1 for this thread
+        double gv[2] = {0.0, 0.0};
+        int ga[2] = {-1, -1};              // entries fetched one half-step ago
+        auto gather_step = [&]() {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                ga[u] = ge < cn ? ge : -1;
+                if (ga[u] >= 0) gv[u] = fetch(c + 1, ge);
+                ge += kThreads;
+            }
+        };
+        for (int j = j0; j < j1; j += 3) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int jj = j + r;
+                if (jj < j1) {
+                    if (active) {
+                        compute(r, jj);
+                        if (jj + 3 < nh) aload(r, jj + 3);
+                    }
+                    if (cn > 0) gather_step();
+                }
+            }
+        }
+        if (cn > 0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
+            for (; ge < cn; ge += kThreads) put(c + 1, ge, fetch(c + 1, ge));
+            __syncthreads();
+        }
     }
-    if (j < nh) compute(0, j);
-    if (j + 1 < nh) compute(1, j + 1);
+    if (!active) return;
     dense_epilogue<TS, NT, MT>(acc, P, r0, no, lane, own_gnode + own_off[s], afact, Z, omega, beta);
 }
 
@@ -934,7 +975,7 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
         break;
         if (r->prec == SG_FP64) {
             switch (NT) {
-                SG_FUSED_NT(double, r->ainv64.p, 1) SG_FUSED_NT(double, r->ainv64.p, 2)
+                SG_FUSED_NT(double, r->ainv64.p, 1)
                 default: SG_THROW(SG_ERR_UNSUPPORTED, "fused dense RAS with P=%d", r->P);
             }
         } else if (r->prec == SG_FP32) {
