@@ -620,6 +620,27 @@ def test_graph_replay_matches_eager(built):
     assert B.sg_graph_cache_clear() > 0
 
 
+def test_graph_replay_fused_ras_matches_eager(built):
+    """The BF16 solve with the fused dense RAS (its per-chunk barriers and
+    run-ahead steps inside captured graphs) gives the eager result bit for
+    bit on every replay."""
+    pr, S, _ = built("c1_64")
+    g = GpuSG(pr, prec="bf16", coarse="amg", ras_path="fused")
+    try:
+        assert B.ras_path_info(g.ras)[2] == "fused"
+        x_e, i_e = g.solve(pr.restart, 1e-10)
+        assert i_e["converged"]
+        for rep in range(3):
+            x_g, i_g = g.solve(pr.restart, 1e-10, use_graph=True)
+            assert i_g["iterations"] == i_e["iterations"]
+            assert torch.equal(x_g, x_e), rep
+            Y = g.new_vec()
+            B.sg_matvec(g.op, x_g, Y)
+            torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
 def test_graph_cache_dropped_with_handles():
     _cuda()
     pr = make_problem("c0", nc=12, sub=(2, 2))
