@@ -303,8 +303,9 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
  * The paper's nonlinear model -div(c(x,xi) q(u) grad u) = f (Eq.
  * NLP_StrongPDE, Galerkin system Eqs. stonlp_system / vectorvalPDENL, which
  * the paper linearises by Picard iterations) with q(u) = kappa(u) =
- * 1 + a2 u^2, f = 1 and homogeneous Dirichlet data, solved by inexact Newton
- * with backtracking.  The residual is R(U) = F e_0 - A(U) with
+ * 1 + a1 u + a2 u^2 (the paper's 1 + alpha u: a1 = alpha, a2 = 0), f = 1 and
+ * homogeneous Dirichlet data, solved by inexact Newton with backtracking or
+ * by Picard iterations (newton_solve).  The residual is R(U) = F e_0 - A(U) with
  *   A(U)[a, m] = sum_T |T| E[c_T kappa(u_T) (grad u_T . grad phi_a) Psi_m],
  * c_T the input PCE (first L_in terms) at the centroid of T and u_T the
  * centroid value of u.  All expectations are exact (up to rounding): the
@@ -316,7 +317,7 @@ int fgmres_solve(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
  * sg_nl_setup -- element geometry, input PCE, product tables and both
  *   operators (the Picard part K1 and the Jacobian K1 + K2) for the basis b
  *   (its M, p_in, p) on the mesh (same arguments as sg_assemble).
- *   a2 >= 0.  Synchronous.  Errors: SG_ERR_INVALID_ARG.
+ *   a1 finite, a2 >= 0.  Synchronous.  Errors: SG_ERR_INVALID_ARG.
  * sg_nl_eval -- assemble K1 and the Jacobian at U (device, [n x P]) and, if
  *   R is not NULL, write R(U) (device, [n x P]).  Asynchronous.
  * sg_nl_jac_apply -- Y = J X with the Jacobian of the last sg_nl_eval.
@@ -332,7 +333,7 @@ typedef struct sg_nl sg_nl;
 
 int sg_nl_setup(const sg_basis* b, int n_vert, const double* xy, int n_tri,
                 const int32_t* tri, const int32_t* dof, int n, const double* g0,
-                const double* g, double a2, sg_nl** out, void* stream);
+                const double* g, double a1, double a2, sg_nl** out, void* stream);
 int sg_nl_info(const sg_nl* nl, int* n, int* P, int* L2, int64_t* nnz);
 int sg_nl_eval(sg_nl* nl, const double* U, double* R, void* stream);
 int sg_nl_jac_apply(const sg_nl* nl, const double* X, double* Y, void* stream);
@@ -345,7 +346,8 @@ int sg_nl_set_coefficients(sg_nl* nl, const double* g0, const double* g, void* s
 void sg_destroy_nl(sg_nl* nl);
 
 /* ------------------------------------------------------------------------
- * newton_solve -- inexact Newton on R(U) = 0 from the initial guess in U
+ * newton_solve -- inexact Newton (method SG_NEWTON) or Picard iterations
+ * (SG_PICARD) on R(U) = 0 from the initial guess in U
  * (device, [n x P], overwritten by the last iterate).  Step k:
  *   eta_k = max(1e-12, min(eta_max, ||R_k|| / ||F||));
  *   RAS on K1 (mean-coefficient local solves, subdomains `owner`, overlap)
@@ -358,7 +360,11 @@ void sg_destroy_nl(sg_nl* nl);
  *   otherwise;  U += lambda d.
  * The forcing term is safeguarded against over-solving the last steps:
  * eta_k = min(eta_max, max(eta_k, 0.5 tol ||F|| / ||R_k||)).
- * Stops when ||R|| / ||F|| <= tol (||F|| = norm of F e_0).  ws: device
+ * SG_PICARD: the same with the secant operator K1(U) (A(U) = K1(U) U) in place
+ * of the Jacobian, for FGMRES and the coarse solver, and the full step
+ * lambda = 1 (U_{k+1} = K1(U_k)^{-1} F e_0 up to the inner tolerance).
+ * Stops when ||R|| / ||F|| <= tol (||F|| = norm of F e_0) or, if du_tol > 0,
+ * when ||lambda d|| <= du_tol ||U|| (the paper's Picard criterion).  ws: device
  * workspace of newton_workspace_bytes(nl, n_sub, coarse, restart) bytes,
  * 256-byte aligned.
  * Returns SG_OK, SG_NOT_CONVERGED (max_steps reached) or an error.
@@ -374,7 +380,11 @@ typedef struct {
     int use_graph;       /* as in sg_krylov_opts                        */
     int ortho;           /* as in sg_krylov_opts                        */
     int amg_rebuild;     /* coarse-solver rebuild interval in steps (>= 0) */
+    int method;          /* SG_NEWTON or SG_PICARD                       */
+    double du_tol;       /* stop on ||lambda d|| <= du_tol ||U|| (0: off) */
 } sg_newton_opts;
+
+enum { SG_NEWTON = 0, SG_PICARD = 1 };
 
 typedef struct {
     int steps;
@@ -382,6 +392,7 @@ typedef struct {
     int converged;
     double relres;           /* ||R|| / ||F|| at return                   */
     double last_lambda;
+    double last_du;          /* ||lambda d|| / ||U|| of the last step (if du_tol > 0) */
     double ms_total, ms_eval, ms_setup, ms_krylov;
     double* history;         /* host, may be NULL: ||R_k|| / ||F||, k = 0..steps */
     int* krylov_its_per_step;/* host, may be NULL: entry k-1 for step k   */

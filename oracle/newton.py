@@ -3,9 +3,11 @@ Test infrastructure only.
 
 The paper's nonlinear model is -div(c(x,theta)(1 + alpha u) grad u) = f
 (Eq. NLP_StrongPDE), linearised by Picard iterations (Eq. stonlp_system,
-Eq. vectorvalPDENL).  The configuration studied here keeps that structure
-with kappa(u) = 1 + a2 u^2 (a2 = 0.5) and solves the Galerkin system with
-Newton's method instead of Picard.
+Eq. vectorvalPDENL).  Here kappa(u) = 1 + a1 u + a2 u^2: the paper's model is
+a1 = alpha, a2 = 0; the Newton configuration uses a1 = 0, a2 = 0.5.  The
+Galerkin system is solved by Newton's method or by the paper's Picard
+iteration (``picard``: U <- K1(U)^{-1} F e_0 with the secant operator K1,
+A(U) = K1(U) U, until ||U_{k+1} - U_k|| <= du_tol ||U_{k+1}||).
 
 Exact-Galerkin residual, with u_b(xi) = sum_j U[b, j] Psi_j(xi):
 
@@ -68,6 +70,7 @@ class NLProblem:
     L: int
     P: int
     a2: float = 0.5
+    a1: float = 0.0
     uD: Optional[np.ndarray] = None      # Dirichlet value per vertex (deterministic)
     fvals: Optional[np.ndarray] = None   # forcing per vertex (default 1)
     # derived
@@ -88,10 +91,10 @@ class NLProblem:
             self.F = fem.load_vector_nodal(self.xy, self.tri, self.dof, self.n, self.fvals)
 
     def kappa(self, u):
-        return 1.0 + self.a2 * u * u
+        return 1.0 + self.a1 * u + self.a2 * u * u
 
     def dkappa(self, u):
-        return 2.0 * self.a2 * u
+        return self.a1 + 2.0 * self.a2 * u
 
     def _vertex_fields(self, U: np.ndarray, el: np.ndarray) -> np.ndarray:
         """u_b(xi_q) for the 3 vertices of elements el: [E, 3, Q]."""
@@ -123,8 +126,14 @@ class NLProblem:
                 np.add.at(R, d[m, a], -contrib[m, a])
         return R
 
-    def jacobian(self, U: np.ndarray, chunk: int = 16) -> sp.csr_matrix:
-        """dA/dU in the row-major (a*P + m) numbering."""
+    def secant(self, U: np.ndarray) -> sp.csr_matrix:
+        """K1(U) with A(U) = K1(U) U: the first term of the Jacobian,
+        sum_T |T| E[c kappa(u_T) Psi_m Psi_n] grad phi_b . grad phi_a."""
+        return self.jacobian(U, with_dkappa=False)
+
+    def jacobian(self, U: np.ndarray, chunk: int = 16, with_dkappa: bool = True) -> sp.csr_matrix:
+        """dA/dU in the row-major (a*P + m) numbering (without the kappa'
+        term: the secant operator K1(U))."""
         P = self.P
         rows, cols, vals = [], [], []
         idx = np.arange(P)
@@ -149,7 +158,8 @@ class NLProblem:
                     if not m.any():
                         continue
                     blk = self.area[el[m], None, None] * (
-                        E1[m] * gg[m, a, b][:, None, None] + E2[m, a] / 3.0)       # [E,P(m),P(n)]
+                        E1[m] * gg[m, a, b][:, None, None] +
+                        (E2[m, a] / 3.0 if with_dkappa else 0.0))                   # [E,P(m),P(n)]
                     ra = d[m, a][:, None, None] * P + idx[None, :, None]
                     cb = d[m, b][:, None, None] * P + idx[None, None, :]
                     rows.append(np.broadcast_to(ra, blk.shape).ravel())
@@ -226,9 +236,49 @@ def newton(pr: NLProblem, U0: Optional[np.ndarray] = None, tol: float = 1e-8,
     return U, info
 
 
-def build(xy, tri, dof, n, g0, g, M, p_in, p, a2=0.5, **kw) -> NLProblem:
+@dataclass
+class PicardInfo:
+    steps: int = 0
+    du: List[float] = field(default_factory=list)          # ||U_{k+1} - U_k|| / ||U_{k+1}||
+    residuals: List[float] = field(default_factory=list)   # ||R(U_k)|| / ||F||
+    krylov_its: List[int] = field(default_factory=list)
+    converged: bool = False
+
+
+def picard(pr: NLProblem, U0: Optional[np.ndarray] = None, du_tol: float = 1e-6,
+           max_steps: int = 100, linear_solve: Optional[Callable] = None) -> tuple:
+    """The paper's Picard iteration on the Galerkin system: solve
+    K1(U_k) U_{k+1} = F e_0, written as the correction K1(U_k) d = R(U_k),
+    U_{k+1} = U_k + d (full step), until ||d|| <= du_tol ||U_{k+1}||.
+    ``linear_solve(K1, R, U)`` returns (d, its); by default a direct solve."""
+    U = np.zeros((pr.n, pr.P)) if U0 is None else U0.copy()
+    info = PicardInfo()
+    R = pr.residual(U)
+    Fn = np.linalg.norm(pr.F) if np.linalg.norm(pr.F) > 0 else np.linalg.norm(R)
+    info.residuals.append(np.linalg.norm(R) / Fn)
+    while info.steps < max_steps:
+        K1 = pr.secant(U)
+        if linear_solve is None:
+            d = spla.spsolve(K1.tocsc(), R.ravel()).reshape(R.shape)
+            its = 0
+        else:
+            d, its = linear_solve(K1, R, U)
+        U = U + d
+        R = pr.residual(U)
+        info.steps += 1
+        info.krylov_its.append(its)
+        info.residuals.append(np.linalg.norm(R) / Fn)
+        un = np.linalg.norm(U)
+        info.du.append(np.linalg.norm(d) / un if un > 0 else np.linalg.norm(d))
+        if info.du[-1] <= du_tol:
+            info.converged = True
+            break
+    return U, info
+
+
+def build(xy, tri, dof, n, g0, g, M, p_in, p, a2=0.5, a1=0.0, **kw) -> NLProblem:
     alpha = pce.multi_indices(M, p)
     L = pce.n_terms(M, p_in)
     coef = pce.lognormal_coefficients(g0, g, alpha[:L])
     return NLProblem(xy=xy, tri=tri, dof=dof, n=n, coef=coef, alpha=alpha, L=L,
-                     P=alpha.shape[0], a2=a2, **kw)
+                     P=alpha.shape[0], a2=a2, a1=a1, **kw)

@@ -48,12 +48,18 @@ class KrylovStats(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
                 ("restart", C.c_int), ("max_it", C.c_int), ("omega", C.c_double),
-                ("use_graph", C.c_int), ("ortho", C.c_int), ("amg_rebuild", C.c_int)]
+                ("use_graph", C.c_int), ("ortho", C.c_int), ("amg_rebuild", C.c_int),
+                ("method", C.c_int), ("du_tol", C.c_double)]
+
+
+SG_NEWTON, SG_PICARD = 0, 1
+NL_METHODS = {"newton": SG_NEWTON, "picard": SG_PICARD}
 
 
 class NewtonStats(C.Structure):
     _fields_ = [("steps", C.c_int), ("krylov_its", C.c_int), ("converged", C.c_int),
-                ("relres", C.c_double), ("last_lambda", C.c_double), ("ms_total", C.c_double),
+                ("relres", C.c_double), ("last_lambda", C.c_double), ("last_du", C.c_double),
+                ("ms_total", C.c_double),
                 ("ms_eval", C.c_double), ("ms_setup", C.c_double), ("ms_krylov", C.c_double),
                 ("history", _f64p), ("krylov_its_per_step", _i32p), ("history_cap", C.c_int),
                 ("history_len", C.c_int)]
@@ -101,7 +107,7 @@ _SIGS = {
     "fgmres_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(KrylovOpts),
                                C.POINTER(KrylovStats), _vp, C.c_size_t, _vp]),
     "sg_nl_setup": (C.c_int, [_vp, C.c_int, _f64p, C.c_int, _i32p, _i32p, C.c_int, _f64p, _f64p,
-                              C.c_double, C.POINTER(_vp), _vp]),
+                              C.c_double, C.c_double, C.POINTER(_vp), _vp]),
     "sg_nl_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int64)]),
     "sg_nl_eval": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -412,7 +418,9 @@ def fgmres_solve(op, ras, amg, b, x, restart: int, max_it: int, rtol: float, ome
 
 # ---------------------------------------------------------------- Newton
 def sg_nl_setup(basis, xy: np.ndarray, tri: np.ndarray, dof: np.ndarray, n: int,
-                g0: np.ndarray, g: np.ndarray, a2: float = 0.5, stream=None) -> C.c_void_p:
+                g0: np.ndarray, g: np.ndarray, a2: float = 0.5, a1: float = 0.0,
+                stream=None) -> C.c_void_p:
+    """kappa(u) = 1 + a1 u + a2 u^2."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     dof = np.ascontiguousarray(dof, dtype=np.int32)
@@ -422,7 +430,7 @@ def sg_nl_setup(basis, xy: np.ndarray, tri: np.ndarray, dof: np.ndarray, n: int,
     gp = _ptr(g, C.c_double) if g.size else None
     _check(lib().sg_nl_setup(basis, xy.shape[0], _ptr(xy, C.c_double), tri.shape[0],
                              _ptr(tri, C.c_int32), _ptr(dof, C.c_int32), n,
-                             _ptr(g0, C.c_double), gp, a2, C.byref(h), _stream(stream)))
+                             _ptr(g0, C.c_double), gp, a1, a2, C.byref(h), _stream(stream)))
     return h
 
 
@@ -471,10 +479,12 @@ def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coa
                  ws, max_steps: int = 30, tol: float = 1e-8, eta_max: float = 1e-2,
                  restart: int = 50, max_it: int = 1000, omega: float = 0.0,
                  use_graph: bool = False, history_cap: int = 64, ortho: str = "mgs",
-                 amg_rebuild: int = 0, stream=None):
+                 amg_rebuild: int = 0, method: str = "newton", du_tol: float = 0.0,
+                 stream=None):
+    """method "newton" or "picard"; du_tol > 0 also stops on ||lambda d|| <= du_tol ||U||."""
     owner = np.ascontiguousarray(owner, dtype=np.int32)
     opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0,
-                      ORTHO[ortho], amg_rebuild)
+                      ORTHO[ortho], amg_rebuild, NL_METHODS[method], du_tol)
     hist = np.zeros(history_cap, dtype=np.float64)
     kits = np.zeros(history_cap, dtype=np.int32)
     st = NewtonStats()
@@ -487,6 +497,7 @@ def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coa
     h = st.history_len
     return dict(status=rc, steps=st.steps, krylov_its=st.krylov_its,
                 converged=bool(st.converged), relres=st.relres, last_lambda=st.last_lambda,
+                last_du=st.last_du,
                 ms_total=st.ms_total, ms_eval=st.ms_eval, ms_setup=st.ms_setup,
                 ms_krylov=st.ms_krylov, history=hist[:h].copy(),
                 krylov_its_per_step=kits[:max(h - 1, 0)].copy())

@@ -3,9 +3,11 @@
 // The paper's nonlinear model (Eq. NLP_StrongPDE) is -div(c(x,xi) q(u)
 // grad u) = f with a polynomial q, Galerkin-projected and linearised by
 // Picard iterations (Eqs. stonlp_system, vectorvalPDENL).  Here
-// q(u) = kappa(u) = 1 + a2 u^2, f = 1, homogeneous Dirichlet data, and the
-// Galerkin system R(U) = F e_0 - A(U) = 0 is solved by inexact Newton with
-// backtracking, each correction by FGMRES with the two-grid RAS cycle.
+// q(u) = kappa(u) = 1 + a1 u + a2 u^2 (the paper's 1 + alpha u is a1 = alpha,
+// a2 = 0), f = 1, homogeneous Dirichlet data, and the Galerkin system
+// R(U) = F e_0 - A(U) = 0 is solved by inexact Newton with backtracking or by
+// the paper's Picard iteration U <- U + K1(U)^{-1} R(U) = K1(U)^{-1} F e_0,
+// each linear system by FGMRES with the two-grid RAS cycle.
 //
 // Exact Galerkin integrals without quadrature.  With P1 elements and the
 // centroid value u_T = (u_1 + u_2 + u_3)/3 in kappa,
@@ -34,7 +36,7 @@
 struct sg_nl {
     int device = 0;
     int n = 0, P = 0, M = 0, p = 0, L_in = 0, L2 = 0, n_tri = 0;
-    double a2 = 0.5;
+    double a1 = 0.0, a2 = 0.5;
     std::unique_ptr<sg_op> j1, jac;          // K1 (residual, RAS) and K1 + K2 (Jacobian)
     sg::DevBuf<int32_t> edof;                // [n_tri][3]
     sg::ElementData ed;
@@ -70,7 +72,7 @@ __device__ __forceinline__ void wave_sync() {
 // One wave per element: chaos coefficients (degree <= 2p) of w_T and of
 // y_{T,a} |T| / 3 (the factor 1/3 of d u_T / d u_b folded in).
 __global__ __launch_bounds__(64 * kWaves) void nl_element_kernel(
-    int n_tri, int P, int L_in, int L2, double a2, const int32_t* __restrict__ edof,
+    int n_tri, int P, int L_in, int L2, double a1, double a2, const int32_t* __restrict__ edof,
     const double* __restrict__ ek, const double* __restrict__ ec, const double* __restrict__ U,
     const int32_t* __restrict__ sq_ptr, const int32_t* __restrict__ sq_ij,
     const double* __restrict__ sq_v, const int32_t* __restrict__ cm_ptr,
@@ -102,7 +104,9 @@ __global__ __launch_bounds__(64 * kWaves) void nl_element_kernel(
                 fl[a * P + j] = e9[3 * a] * u0 + e9[3 * a + 1] * u1 + e9[3 * a + 2] * u2;
         }
         wave_sync();
-        // kappa(u_T) = 1 + a2 u_T^2 and u_T * flux_a, both of degree 2p
+        // kappa(u_T) = 1 + a1 u_T + a2 u_T^2 and kappa'(u_T) flux_a =
+        // a1 flux_a + 2 a2 u_T flux_a, of degree <= 2p (the first P terms of the
+        // degree-2p basis are the degree-p basis in the same order)
         for (int g = lane; g < L2; g += 64) {
             double s = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
             for (int q = sq_ptr[g]; q < sq_ptr[g + 1]; ++q) {
@@ -115,14 +119,15 @@ __global__ __launch_bounds__(64 * kWaves) void nl_element_kernel(
                 v2 = fma(mu, fl[2 * P + j], v2);
             }
             const double ig = inv_gfact[g];
-            kap[g] = (g == 0 ? 1.0 : 0.0) + a2 * s * ig;
-            v[g] = v0 * ig;
-            v[L2 + g] = v1 * ig;
-            v[2 * L2 + g] = v2 * ig;
+            const bool lin = g < P;
+            kap[g] = (g == 0 ? 1.0 : 0.0) + (lin ? a1 * uT[g] : 0.0) + a2 * s * ig;
+            v[g] = (lin ? a1 * fl[g] : 0.0) + 2.0 * a2 * v0 * ig;
+            v[L2 + g] = (lin ? a1 * fl[P + g] : 0.0) + 2.0 * a2 * v1 * ig;
+            v[2 * L2 + g] = (lin ? a1 * fl[2 * P + g] : 0.0) + 2.0 * a2 * v2 * ig;
         }
         wave_sync();
         // products with c_T, projected onto degree <= 2p
-        const double yscale = 2.0 * a2 / 3.0;
+        const double yscale = 1.0 / 3.0;
         for (int g = lane; g < L2; g += 64) {
             double w = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0;
             for (int q = cm_ptr[g]; q < cm_ptr[g + 1]; ++q) {
@@ -247,7 +252,7 @@ void nl_eval(sg_nl* nl, const double* U, double* R, hipStream_t s) {
     const size_t per_wave = ((size_t)7 * nl->P + nl->L_in + 4 * (size_t)nl->L2) * 8;
     const unsigned blocks = (unsigned)std::min<int64_t>((nl->n_tri + kWaves - 1) / kWaves, 16384);
     nl_element_kernel<<<blocks, 64 * kWaves, per_wave * kWaves, s>>>(
-        nl->n_tri, nl->P, nl->L_in, nl->L2, nl->a2, nl->edof.p, nl->ed.ek.p, nl->ed.ec.p, U,
+        nl->n_tri, nl->P, nl->L_in, nl->L2, nl->a1, nl->a2, nl->edof.p, nl->ed.ek.p, nl->ed.ec.p, U,
         nl->sq_ptr.p, nl->sq_ij.p, nl->sq_v.p, nl->cm_ptr.p, nl->cm_kd.p, nl->cm_v.p,
         nl->inv_gfact.p, nl->w1.p, nl->yt.p);
     HIP_LAUNCH_OK();
@@ -285,16 +290,18 @@ using namespace sg;
 extern "C" {
 
 int sg_nl_setup(const sg_basis* b, int n_vert, const double* xy, int n_tri, const int32_t* tri,
-                const int32_t* dof, int n, const double* g0, const double* g, double a2,
+                const int32_t* dof, int n, const double* g0, const double* g, double a1, double a2,
                 sg_nl** out, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(b && out, "null argument");
+        SG_REQUIRE(std::isfinite(a1), "a1 must be finite");
         SG_REQUIRE(std::isfinite(a2) && a2 >= 0.0, "a2 must be finite and >= 0");
         hipStream_t s = as_stream(stream);
         validate_mesh(n_vert, xy, n_tri, tri, dof, n);
         auto nl = std::make_unique<sg_nl>();
         nl->device = current_device();
         nl->n = n; nl->P = b->P; nl->M = b->M; nl->p = b->p; nl->L_in = b->L; nl->n_tri = n_tri;
+        nl->a1 = a1;
         nl->a2 = a2;
         const int deg2 = 2 * b->p;
         nl->L2 = b->M == 0 ? 1 : binom(b->M + deg2, deg2);
@@ -586,6 +593,10 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
         SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
         SG_REQUIRE(opts->eta_max > 0.0 && opts->eta_max < 1.0, "eta_max outside (0,1)");
         SG_REQUIRE(opts->amg_rebuild >= 0, "amg_rebuild must be >= 0");
+        SG_REQUIRE(opts->method == SG_NEWTON || opts->method == SG_PICARD,
+                   "method must be SG_NEWTON or SG_PICARD");
+        SG_REQUIRE(opts->du_tol >= 0.0, "du_tol must be >= 0");
+        const bool picard = opts->method == SG_PICARD;
         const size_t need = newton_ws(nl->n, nl->P, n_sub, coarse, opts->restart);
         if (!ws || ws_bytes < need)
             SG_THROW(SG_ERR_WORKSPACE, "newton workspace too small (%zu < %zu)", ws_bytes, need);
@@ -627,11 +638,14 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
         push(Fn > 0.0 ? rn / Fn : 0.0, 0);
         std::unique_ptr<sg_ras, RasDel> ras;
         std::unique_ptr<sg_amg, AmgDel> amg;
+        // the linear operator of a step: the Jacobian (Newton) or the secant
+        // operator K1(U) with A(U) = K1(U) U (Picard)
+        sg_op* Jop = picard ? nl->j1.get() : nl->jac.get();
         LinOp J;
-        J.kron = nl->jac.get();
+        J.kron = Jop;
         J.n = nl->n;
         J.P = nl->P;
-        double last_lambda = 0.0;
+        double last_lambda = 0.0, last_du = 0.0;
         while (!converged && steps < opts->max_steps) {
             // forcing term, safeguarded against solving the correction more
             // accurately than the final tolerance needs
@@ -651,8 +665,7 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             if (coarse != SG_COARSE_NONE && rebuild) {
                 amg.reset();
                 sg_amg* a = nullptr;
-                check_status(amg_setup(nl->jac.get(), ras.get(), coarse, prec, &a, stream),
-                             "amg_setup");
+                check_status(amg_setup(Jop, ras.get(), coarse, prec, &a, stream), "amg_setup");
                 amg.reset(a);
             }
             ms_setup += ms_since(t0);
@@ -668,20 +681,20 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             ko.use_graph = opts->use_graph;
             ko.ortho = opts->ortho;
             sg_krylov_stats ks{};
-            const int kst = fgmres_core(J, nl->jac.get(), nl->device, ras.get(), amg.get(), R, D,
-                                        &ko, &ks, kws, kws_bytes, s);
+            const int kst = fgmres_core(J, Jop, nl->device, ras.get(), amg.get(), R, D, &ko, &ks,
+                                        kws, kws_bytes, s);
             if (kst < 0) return kst;
             kits += ks.iterations;
             ms_krylov += ms_since(t0);
-            // backtracking on ||R||
+            // backtracking on ||R|| (Newton); the full step (Picard)
             t0 = clock::now();
             double lam = 1.0, rt = 0.0;
-            for (int ls = 0; ls < 10; ++ls) {
+            for (int ls = 0; ls < (picard ? 1 : 10); ++ls) {
                 nl_axpy_kernel<<<grid1d(N), 256, 0, s>>>(N, lam, U, D, Ut);
                 HIP_LAUNCH_OK();
                 nl_eval(nl, Ut, Rt, s);
                 rt = std::sqrt(host_dot(N, Rt, Rt, part, scal, s));
-                if ((std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn) || ls == 9) break;
+                if (picard || (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * rn) || ls == 9) break;
                 lam *= 0.5;
             }
             if (!std::isfinite(rt)) SG_THROW(SG_ERR_NUMERIC, "residual is not finite");
@@ -693,6 +706,13 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             last_lambda = lam;
             push(rn / Fn, ks.iterations);
             converged = rn / Fn <= opts->tol;
+            if (opts->du_tol > 0.0) {
+                // relative size of the update, ||lambda D|| / ||U||
+                const double dn = lam * std::sqrt(host_dot(N, D, D, part, scal, s));
+                const double un = std::sqrt(host_dot(N, U, U, part, scal, s));
+                last_du = un > 0.0 ? dn / un : dn;
+                converged = converged || last_du <= opts->du_tol;
+            }
         }
         HIP_OK(hipStreamSynchronize(s));
         if (stats) {
@@ -701,6 +721,7 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
             stats->converged = converged ? 1 : 0;
             stats->relres = Fn > 0.0 ? rn / Fn : 0.0;
             stats->last_lambda = last_lambda;
+            stats->last_du = last_du;
             stats->ms_total = ms_since(t_all);
             stats->ms_eval = ms_eval;
             stats->ms_setup = ms_setup;

@@ -145,12 +145,12 @@ class GpuSG:
 
 
 class GpuNewton:
-    """Nonlinear SG problem (kappa(u) = 1 + a2 u^2) on the GPU: sequences
+    """Nonlinear SG problem (kappa(u) = 1 + a1 u + a2 u^2) on the GPU: sequences
     ``sg_nl_setup`` / ``sg_nl_eval`` / ``newton_solve`` and owns the buffers."""
 
     def __init__(self, pr: Problem, a2: float = 0.5, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
-                 n_sub: Optional[int] = None, stream=None):
+                 n_sub: Optional[int] = None, stream=None, a1: float = 0.0):
         import torch
         self.torch = torch
         self.pr = pr
@@ -158,7 +158,7 @@ class GpuNewton:
         self.basis = self.nl = None
         m = pr.mesh
         self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
-        self.nl = B.sg_nl_setup(self.basis, m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, a2,
+        self.nl = B.sg_nl_setup(self.basis, m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, a2, a1=a1,
                                 stream=stream)
         self.n, self.P, self.L2, self.nnz = B.sg_nl_info(self.nl)
         self.owner = pr.owner if owner is None else owner
@@ -192,14 +192,15 @@ class GpuNewton:
 
     def solve(self, U0=None, tol: float = 1e-8, max_steps: int = 30, restart: Optional[int] = None,
               max_it: int = 1000, eta_max: float = 1e-2, omega: float = 0.0,
-              use_graph: bool = False, amg_rebuild: int = 0):
+              use_graph: bool = False, amg_rebuild: int = 0, method: str = "newton",
+              du_tol: float = 0.0):
         restart = self.pr.restart if restart is None else restart
         U = self.new_vec() if U0 is None else U0.clone()
         info = B.newton_solve(self.nl, self.owner, self.n_sub, self.overlap, B.PREC[self.prec],
                               COARSE[self.coarse], U, self.workspace(restart), max_steps=max_steps,
                               tol=tol, eta_max=eta_max, restart=restart, max_it=max_it,
                               omega=omega, use_graph=use_graph, amg_rebuild=amg_rebuild,
-                              stream=self.stream)
+                              method=method, du_tol=du_tol, stream=self.stream)
         return U, info
 
     def close(self):

@@ -41,9 +41,9 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
 
 
-def _oracle(pr, a2=0.5):
+def _oracle(pr, a2=0.5, a1=0.0):
     m = pr.mesh
-    return onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2)
+    return onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2, a1=a1)
 
 
 CASES = {
@@ -81,6 +81,50 @@ def test_residual_and_jacobian_match_oracle(case):
     for a in range(pr.mesh.n):
         K0[a, col[rowptr[a]:rowptr[a + 1]]] = k1[rowptr[a]:rowptr[a + 1], 0]
     assert _rel(K0, Km) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["m2p2", "m4p3", "det"])
+def test_paper_model_residual_jacobian_and_secant(case):
+    """The paper's kappa(u) = 1 + u (a1 = 1, a2 = 0): residual, J V and the
+    secant operator K1(U) V (the Picard operator, through its sg_op handle)
+    against the oracle."""
+    _cuda()
+    pr = _problem(case)
+    onl_pr = _oracle(pr, a2=0.0, a1=1.0)
+    rng = np.random.default_rng(8)
+    U = 0.4 * rng.standard_normal((onl_pr.n, onl_pr.P))
+    V = rng.standard_normal((onl_pr.n, onl_pr.P))
+    with GpuNewton(pr, a1=1.0, a2=0.0) as g:
+        R = _host(g.residual(_dev(U)), U.shape)
+        JV = _host(g.jac_apply(_dev(V)), V.shape)
+        KV = torch.empty(onl_pr.n * onl_pr.P, dtype=torch.float64, device="cuda")
+        B.sg_matvec(B.sg_nl_mean_op(g.nl), _dev(V), KV)
+        KV = _host(KV, V.shape)
+    assert _rel(R, onl_pr.residual(U)) < 1e-12
+    assert _rel(JV, (onl_pr.jacobian(U) @ V.ravel()).reshape(V.shape)) < 1e-12
+    assert _rel(KV, (onl_pr.secant(U) @ V.ravel()).reshape(V.shape)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["m2p2", "m4p3"])
+def test_picard_matches_oracle(case):
+    """Picard iterations (the paper's linearisation) on the GPU against the
+    oracle's Picard with direct solves, stopped at ||d|| <= 1e-10 ||U||: the
+    same fixed point as Newton, and the same step count within the inner
+    tolerance's effect."""
+    _cuda()
+    pr = _problem(case)
+    onl_pr = _oracle(pr, a2=0.0, a1=1.0)
+    U_ref, info_ref = onl.picard(onl_pr, du_tol=1e-10)
+    U_newton, _ = onl.newton(onl_pr, tol=1e-13)
+    assert info_ref.converged
+    with GpuNewton(pr, a1=1.0, a2=0.0) as g:
+        U, info = g.solve(tol=1e-14, du_tol=1e-10, method="picard", restart=30, max_steps=60)
+        U = _host(U, U_ref.shape)
+    assert info["converged"], info
+    assert info["last_lambda"] == 1.0 and info["last_du"] <= 1e-10
+    assert abs(info["steps"] - info_ref.steps) <= 2, (info["steps"], info_ref.steps)
+    assert _rel(U, U_ref) < 1e-8
+    assert _rel(U, U_newton) < 1e-8
 
 
 def test_jacobian_at_zero_is_the_linear_operator():
@@ -213,6 +257,10 @@ def test_newton_rejects_bad_arguments():
             g.solve(eta_max=1.5)
         with pytest.raises(B.SgError):
             g.solve(amg_rebuild=-1)
+        with pytest.raises(B.SgError):
+            g.solve(du_tol=-1.0)
+        with pytest.raises(KeyError):
+            g.solve(method="secant")
         small = torch.empty(16, dtype=torch.float64, device="cuda")
         with pytest.raises(B.SgError):
             B.newton_solve(g.nl, g.owner, g.n_sub, g.overlap, B.SG_FP64, B.SG_COARSE_AMG,

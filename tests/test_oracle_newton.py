@@ -12,10 +12,11 @@ from oracle import system as osys
 from paper_2310_14649_amd.inputs import make_problem, structured_mesh
 
 
-def _nl(nc=5, M=2, p=2, sigma=0.4, a2=0.5):
+def _nl(nc=5, M=2, p=2, sigma=0.4, a2=0.5, a1=0.0):
     pr = make_problem("c0", nc=nc, M=M, p=p, sigma=sigma, sub=(1, 1))
     m = pr.mesh
-    return pr, onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2)
+    return pr, onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2,
+                         a1=a1)
 
 
 def test_quadrature_rule_exact_to_degree_15():
@@ -26,8 +27,13 @@ def test_quadrature_rule_exact_to_degree_15():
     assert (w * pts[:, 0] ** 4 * pts[:, 1] ** 10).sum() == pytest.approx(3 * 945.0, rel=1e-10)
 
 
-def test_jacobian_matches_finite_differences():
-    pr, nl = _nl()
+# kappa(u) = 1 + a1 u + a2 u^2: the Newton configuration, the paper's 1 + u, a mix
+KAPPAS = [(0.0, 0.5), (1.0, 0.0), (0.7, 0.3)]
+
+
+@pytest.mark.parametrize("a1,a2", KAPPAS)
+def test_jacobian_matches_finite_differences(a1, a2):
+    pr, nl = _nl(a1=a1, a2=a2)
     rng = np.random.default_rng(0)
     U = 0.3 * rng.standard_normal((nl.n, nl.P))
     V = rng.standard_normal((nl.n, nl.P))
@@ -117,3 +123,61 @@ def test_sg_mean_against_collocation_of_nonlinear_problem():
             Ud, _ = onl.newton(det, tol=1e-13)
             mean_col += w[i] * w[j] * Ud[:, 0]
     assert np.abs(mean_sg - mean_col).max() / np.abs(mean_col).max() < 2e-4
+
+
+@pytest.mark.parametrize("a1,a2", KAPPAS)
+def test_secant_operator_reproduces_residual(a1, a2):
+    """A(U) = K1(U) U: the secant operator (assembled like the Jacobian's
+    first term) and the residual (assembled from the flux) agree."""
+    pr, nl = _nl(nc=6, M=2, p=2, a1=a1, a2=a2)
+    U = 0.3 * np.random.default_rng(4).standard_normal((nl.n, nl.P))
+    K1 = nl.secant(U)
+    F = np.zeros((nl.n, nl.P))
+    F[:, 0] = nl.F
+    R = F - (K1 @ U.ravel()).reshape(U.shape)
+    assert np.abs(R - nl.residual(U)).max() / np.abs(nl.residual(U)).max() < 1e-12
+
+
+def _strip(nc, a1, a2):
+    m = structured_mesh(nc)
+    x = m.xy[:, 0]
+    dof = np.full(m.n_vert, -1, dtype=np.int32)
+    free = (x > 0) & (x < 1)
+    dof[free] = np.arange(free.sum())
+    uD = np.where(np.isclose(x, 1.0), 1.0, 0.0)
+    nl = onl.NLProblem(xy=m.xy, tri=m.tri, dof=dof, n=int(free.sum()),
+                       coef=np.ones((1, m.n_tri)), alpha=np.zeros((1, 0), dtype=np.int64),
+                       L=1, P=1, a2=a2, a1=a1, uD=uD, fvals=np.zeros(m.n_vert))
+    return m, x, dof, free, uD, nl
+
+
+def test_paper_model_strip_kirchhoff_picard_and_newton():
+    """The paper's kappa = 1 + u on the strip -(kappa(u) u')' = 0, u(0)=0,
+    u(1)=1: the Kirchhoff transform gives u + u^2/2 = 3x/2, i.e.
+    u = sqrt(1 + 3x) - 1.  Picard and Newton reach the same discrete solution,
+    Picard with a contracting (linear) update sequence, and the P1 error is
+    O(h^2)."""
+    errs = []
+    for nc in (8, 16, 32):
+        m, x, dof, free, uD, nl = _strip(nc, 1.0, 0.0)
+        Un, info_n = onl.newton(nl, tol=1e-13)
+        Up, info_p = onl.picard(nl, du_tol=1e-12, max_steps=200)
+        assert info_n.converged and info_p.converged
+        assert np.abs(Up - Un).max() < 1e-10
+        du = np.array(info_p.du)
+        assert info_p.steps > info_n.steps
+        assert np.all(du[2:] / du[1:-1] < 0.9)                # linear contraction
+        u = np.zeros(m.n_vert)
+        u[free] = Un[dof[free], 0]
+        u += uD
+        errs.append(np.abs(u - (np.sqrt(1.0 + 3.0 * x) - 1.0)).max())
+    assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs
+
+
+def test_picard_and_newton_same_sg_solution():
+    pr, nl = _nl(nc=6, M=2, p=2, sigma=0.4, a1=1.0, a2=0.0)
+    Un, info_n = onl.newton(nl, tol=1e-13)
+    Up, info_p = onl.picard(nl, du_tol=1e-12)
+    assert info_n.converged and info_p.converged
+    assert np.abs(Up - Un).max() / np.abs(Un).max() < 1e-10
+    assert info_p.residuals[-1] < 1e-10
