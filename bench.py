@@ -250,6 +250,32 @@ def bench_newton(args, torch):
                              ms_krylov=round(info["ms_krylov"], 3),
                              its_per_step=info["krylov_its_per_step"].tolist())
     log(f"[bench] newton c4: {ms:.1f} ms, {info['steps']} steps, {info['krylov_its']} its")
+    # the paper's model kappa(u) = 1 + u: its Picard linearisation (stopped at
+    # ||dU|| <= 1e-6 ||U||, the paper's criterion) against Newton (to
+    # ||R|| / ||F|| <= 1e-8), both from the zero guess
+    with GpuNewton(pr, a1=1.0, a2=0.0) as gp:
+        res, sol = {}, {}
+        for meth, kw in (("newton", dict(tol=1e-8)),
+                         ("picard", dict(tol=1e-14, du_tol=1e-6, method="picard",
+                                         max_steps=100))):
+            gp.solve(**kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                Us, inf = gp.solve(**kw)
+            torch.cuda.synchronize()
+            res[meth] = dict(ms=round((time.perf_counter() - t0) * 1e3 / args.steps, 3),
+                             steps=inf["steps"], krylov_its=inf["krylov_its"],
+                             relres=inf["relres"], last_du=inf["last_du"],
+                             its_per_step=inf["krylov_its_per_step"].tolist())
+            sol[meth] = Us
+        res["picard_vs_newton_rel_diff"] = float(torch.linalg.norm(sol["picard"] - sol["newton"]) /
+                                                 torch.linalg.norm(sol["newton"]))
+    out["paper_model_1_plus_u"] = res
+    log(f"[bench] kappa = 1 + u, c4: Newton {res['newton']['ms']:.1f} ms, "
+        f"{res['newton']['steps']} steps, {res['newton']['krylov_its']} its; Picard "
+        f"{res['picard']['ms']:.1f} ms, {res['picard']['steps']} steps, "
+        f"{res['picard']['krylov_its']} its; difference {res['picard_vs_newton_rel_diff']:.2e}")
     if args.learned_draws <= 0:
         return out
     lg = LearnedGuess("c4", max_batch=16, seed=0)
