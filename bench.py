@@ -178,6 +178,54 @@ def amg_only(pr, prec: str, launches: int, torch, g=None) -> dict:
             g.close()
 
 
+def stochastic_sweep(args, torch) -> dict:
+    """Iterations and time against the number of random variables M and the
+    output order p on one mesh (the paper's weak scaling in the stochastic
+    dimensions): config 1's field (sigma 0.5, l 0.2), input order
+    min(2, p), N_c = args.sweep_nc, 8 x 8 subdomains with overlap 2, the
+    two-level preconditioner in FP64 and BF16, FGMRES(50) to 1e-8, for every
+    (M, p) with M in 2..6, p in 1..4 and P <= 128."""
+    from math import comb
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.solver import GpuSG
+    rows = []
+    for M in range(2, 7):
+        for p in range(1, 5):
+            P = comb(M + p, p)
+            if P > 128:
+                continue
+            pr = make_problem("c1", nc=args.sweep_nc, M=M, p=p, sub=(8, 8))
+            row = dict(M=M, p=p, P=P, L_in=comb(M + min(2, p), min(2, p)),
+                       unknowns=pr.mesh.n * P)
+            for prec in ("fp64", "bf16"):
+                try:
+                    g = GpuSG(pr, prec=prec, coarse="amg", ras_path="auto")
+                except B.SgError as e:          # a shape outside a compiled limit
+                    row[prec] = dict(error=str(e))
+                    continue
+                with g:
+                    rho, omega = g.damping()
+                    g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True,
+                                      ortho="cgs")
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3
+                    row[prec] = dict(its=info["iterations"], ms=round(ms, 3),
+                                     us_per_it=round(ms * 1e3 / max(info["iterations"], 1), 1),
+                                     relres=info["true_relres"],
+                                     ras_path=B.ras_path_info(g.ras)[2])
+                    row["matvec_kernel"] = B.sg_matvec_kernel(g.op)
+            log(f"[bench] sweep M={M} p={p} P={P}: " + ", ".join(
+                f"{k} " + (f"{row[k]['its']} its {row[k]['ms']:.1f} ms" if "its" in row[k]
+                           else row[k]["error"]) for k in ("fp64", "bf16"))
+                + f" ({row.get('matvec_kernel', '?')} matvec)")
+            rows.append(row)
+    return {"sweep": True, "nc": args.sweep_nc, "rows": rows}
+
+
 def cpu_baseline(pr, its_gpu: int, sample_its: int):
     """The oracle (plain NumPy/SciPy FP64) on the host: setup, then
     ``sample_its`` FGMRES iterations with the same preconditioner definition,
@@ -336,6 +384,9 @@ def main() -> int:
     ap.add_argument("--amg-only", action="store_true",
                     help="time only one AMG V-cycle (precision --part-prec) and print its figures")
     ap.add_argument("--part-prec", default="bf16", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--sweep", action="store_true",
+                    help="iterations and time against M (2..6) and p (1..4) on one mesh")
+    ap.add_argument("--sweep-nc", type=int, default=256)
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
@@ -358,6 +409,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     pr = make_problem(args.config)
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
+    if args.sweep:
+        print(json.dumps(stochastic_sweep(args, torch)))
+        return 0
     if args.ras_only:
         print(json.dumps(ras_only(pr, args.part_prec, args.ras_path, args.mv_launches, torch)))
         return 0
