@@ -226,6 +226,75 @@ def stochastic_sweep(args, torch) -> dict:
     return {"sweep": True, "nc": args.sweep_nc, "rows": rows}
 
 
+def _timed_solve(g, pr, omega, torch, graph=True):
+    """One warm solve, then one timed: (milliseconds, info)."""
+    g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho="cgs")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho="cgs")
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, info
+
+
+def coarse_study(args, torch) -> dict:
+    """The paper's coarse-solve variants and coarse-grid ratio (Sec. 3 and the
+    coarse-ratio tables).  variants: on the configuration's problem, the
+    coarse problem solved by one V-cycle, by GMRES + V-cycle to 1e-5 (2GV3)
+    and by GMRES + block Jacobi to 1e-2, <= 100 steps (2GV2), with the FP64
+    and BF16 preconditioners.  ratio: config 1's field on an N_c = args.ratio_nc
+    mesh, subdomain grids 4 x 4 .. 32 x 32 (fine nodes per coarse node from
+    N_c^2/16 down to N_c^2/1024), V-cycle and 2GV3, BF16 preconditioner."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.solver import GpuSG
+    variants = []
+    pr = make_problem(args.config)
+    for prec in ("fp64", "bf16"):
+        with GpuSG(pr, prec=prec, coarse="amg", ras_path="auto") as g:
+            rho, omega = g.damping()
+            for inner, rtol in (("none", 0.0), ("gmres_amg", 1e-5), ("gmres_bj", 1e-2)):
+                if inner != "none":
+                    g.set_inner(inner, rtol, 100)
+                c0, i0, _ = B.amg_inner_stats(g.amg)
+                ms, info = _timed_solve(g, pr, omega, torch)
+                c1, i1, _ = B.amg_inner_stats(g.amg)
+                row = dict(prec=prec, coarse=inner, inner_rtol=rtol, its=info["iterations"],
+                           ms=round(ms, 3), relres=info["true_relres"])
+                if inner != "none":
+                    # the warm-up solve counted too: the timed solve's share
+                    row["inner_steps_per_solve"] = round((i1 - i0) / max(c1 - c0, 1), 2)
+                g.set_inner("none")
+                log(f"[bench] coarse {prec} {inner}: {row['its']} its {ms:.1f} ms"
+                    + (f", {row['inner_steps_per_solve']} inner steps per coarse solve"
+                       if inner != "none" else ""))
+                variants.append(row)
+    ratio = []
+    for gx in (4, 8, 16, 32):
+        prr = make_problem("c1", nc=args.ratio_nc, sub=(gx, gx))
+        path = "sweep" if prr.mesh.n / (gx * gx) > 2500 else "auto"
+        for inner in ("none", "gmres_amg"):
+            try:
+                g = GpuSG(prr, prec="bf16", coarse="amg", ras_path=path)
+            except B.SgError as e:
+                ratio.append(dict(sub=gx * gx, coarse=inner, error=str(e)))
+                log(f"[bench] ratio {gx}x{gx}: {e}")
+                continue
+            with g:
+                rho, omega = g.damping()
+                if inner != "none":
+                    g.set_inner(inner, 1e-5, 100)
+                ms, info = _timed_solve(g, prr, omega, torch)
+                row = dict(sub=gx * gx, nodes_per_coarse_node=round(prr.mesh.n / (gx * gx), 1),
+                           coarse_unknowns=gx * gx * g.P, coarse=inner, its=info["iterations"],
+                           ms=round(ms, 3), ras_path=B.ras_path_info(g.ras)[2],
+                           amg_levels=B.amg_info(g.amg, gx * gx)[0])
+            log(f"[bench] ratio {gx}x{gx} ({row['nodes_per_coarse_node']} nodes per coarse node) "
+                f"{inner}: {row['its']} its {row['ms']:.1f} ms")
+            ratio.append(row)
+    return {"coarse_study": True, "config": args.config, "variants": variants,
+            "ratio_nc": args.ratio_nc, "ratio": ratio}
+
+
 def cpu_baseline(pr, its_gpu: int, sample_its: int):
     """The oracle (plain NumPy/SciPy FP64) on the host: setup, then
     ``sample_its`` FGMRES iterations with the same preconditioner definition,
@@ -387,6 +456,9 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true",
                     help="iterations and time against M (2..6) and p (1..4) on one mesh")
     ap.add_argument("--sweep-nc", type=int, default=256)
+    ap.add_argument("--coarse-study", action="store_true",
+                    help="coarse-solve variants (V-cycle, 2GV3, 2GV2) and the coarse-ratio sweep")
+    ap.add_argument("--ratio-nc", type=int, default=512)
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
@@ -411,6 +483,9 @@ def main() -> int:
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
     if args.sweep:
         print(json.dumps(stochastic_sweep(args, torch)))
+        return 0
+    if args.coarse_study:
+        print(json.dumps(coarse_study(args, torch)))
         return 0
     if args.ras_only:
         print(json.dumps(ras_only(pr, args.part_prec, args.ras_path, args.mv_launches, torch)))

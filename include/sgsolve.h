@@ -56,6 +56,14 @@ typedef enum {
     SG_COARSE_AMG = 2          /* one smoothed-aggregation V(1,1) cycle on A_c    */
 } sg_coarse_kind;
 
+/* The coarse problem of the two-grid cycle solved by an inner Krylov method
+ * (Sec. 3: the variants that solve the coarse problem inexactly by GMRES). */
+typedef enum {
+    SG_INNER_NONE = 0,       /* the coarse kind's own solve (one V-cycle)           */
+    SG_INNER_GMRES_AMG = 1,  /* 2GV3: GMRES on A_c preconditioned by one V-cycle    */
+    SG_INNER_GMRES_BJ = 2    /* 2GV2: GMRES on A_c preconditioned by block Jacobi   */
+} sg_inner_kind;
+
 typedef struct sg_basis sg_basis;
 typedef struct sg_op sg_op;
 typedef struct sg_ras sg_ras;
@@ -219,7 +227,31 @@ int amg_info(const sg_amg* a, int* n_levels, int32_t* nodes_per_level, int32_t* 
  * bytes a V-cycle moves.  SG_ERR_INVALID_ARG for a level out of range. */
 int amg_level_blocks(const sg_amg* a, int level, int64_t* a_blocks, int64_t* p_blocks,
                      int64_t* r_blocks);
+/* The kind's own coarse solve: one V-cycle (SG_COARSE_AMG) or the exact
+ * mean-based solve, whatever amg_set_inner chose. */
 int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream);
+/* amg_set_inner -- the coarse solve of the two-grid cycle becomes GMRES on
+ * A_c (Sec. 3, the 2GV2 / 2GV3 variants), flexible, no restart, classical
+ * Gram-Schmidt with a second pass, stopped at ||b_c - A_c x_c|| <= rtol ||b_c||
+ * (the Givens estimate) or after max_its steps (1..200), from x_c = 0.
+ * SG_INNER_GMRES_AMG preconditions each step with one V-cycle (the paper
+ * uses BoomerAMG, rtol 1e-5); SG_INNER_GMRES_BJ with the block Jacobi of
+ * A_c's diagonal P x P blocks held in the hierarchy's precision, i.e. a
+ * one-level Schwarz method without overlap whose subdomains are single
+ * coarse nodes (the paper uses one-level RAS, rtol 1e-2, <= 100 steps).
+ * SG_INNER_NONE restores the V-cycle.  Needs kind SG_COARSE_AMG; a
+ * hierarchy of one level is already an exact solve and keeps it.  Allocates
+ * the inner basis ((2 max_its + 2) n_sub P doubles) and a pinned host slot.
+ * The inner solve reads its residual estimate on the host after every step,
+ * so it synchronises the stream: fgmres_solve does not capture graphs of
+ * Arnoldi steps while it is active, and a caller must not capture it. */
+int amg_set_inner(sg_amg* a, sg_inner_kind inner, double rtol, int max_its);
+/* host outputs (any may be NULL): inner solves so far, their total steps,
+ * and the steps of the last one. */
+int amg_inner_stats(const sg_amg* a, int64_t* calls, int64_t* its, int* last_its);
+/* The coarse solve the two-grid cycle uses: amg_vcycle, or the inner GMRES
+ * of amg_set_inner (then synchronous).  b_c, x_c device [n_sub*P], no alias. */
+int amg_coarse_solve(const sg_amg* a, const double* b_c, double* x_c, void* stream);
 /* r_c = Z^T R (sum over owned nodes) and Y += Z e_c.  Asynchronous. */
 int sg_coarse_restrict(const sg_amg* a, const double* R, double* r_c, void* stream);
 int sg_coarse_prolong_add(const sg_amg* a, const double* e_c, double* Y, void* stream);
@@ -237,7 +269,9 @@ size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg);
 int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
                      const double* R, double* Z, void* ws, size_t ws_bytes, void* stream);
 /* Damping of the smoother: rho = power estimate of rho(M A) (`its`
- * iterations from the all-ones field); omega = min(1, 1.6/rho).  Synchronous. */
+ * iterations from a SplitMix64 field: entry i of the flattened [n*P] start
+ * is output i + 1 from state 0, top 53 bits mapped to [-1/2, 1/2));
+ * omega = min(1, 1.8/rho).  Synchronous. */
 int sg_smoother_damping(const sg_op* op, const sg_ras* ras, int its, double* rho,
                         double* omega, void* ws, size_t ws_bytes, void* stream);
 

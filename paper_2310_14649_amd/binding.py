@@ -95,6 +95,9 @@ _SIGS = {
     "amg_setup": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "amg_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i32p, _i32p]),
     "amg_vcycle": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "amg_set_inner": (C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
+    "amg_inner_stats": (C.c_int, [_vp, _i64p, _i64p, C.POINTER(C.c_int)]),
+    "amg_coarse_solve": (C.c_int, [_vp, _vp, _vp, _vp]),
     "amg_level_blocks": (C.c_int, [_vp, C.c_int, _i64p, _i64p, _i64p]),
     "sg_coarse_restrict": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_coarse_prolong_add": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -361,6 +364,27 @@ def amg_level_blocks(a, level: int):
 
 def amg_vcycle(a, b_c, x_c, stream=None):
     _check(lib().amg_vcycle(a, _dev(b_c), _dev(x_c), _stream(stream)))
+
+
+SG_INNER_NONE, SG_INNER_GMRES_AMG, SG_INNER_GMRES_BJ = 0, 1, 2
+INNER = {"none": SG_INNER_NONE, "gmres_amg": SG_INNER_GMRES_AMG, "gmres_bj": SG_INNER_GMRES_BJ}
+
+
+def amg_set_inner(a, inner="none", rtol: float = 1e-5, max_its: int = 100):
+    """inner: "none" (one V-cycle), "gmres_amg" (2GV3) or "gmres_bj" (2GV2)."""
+    kind = INNER[inner] if isinstance(inner, str) else int(inner)
+    _check(lib().amg_set_inner(a, kind, rtol, max_its))
+
+
+def amg_inner_stats(a):
+    """(inner solves, their total steps, steps of the last one)."""
+    calls, its, last = C.c_int64(), C.c_int64(), C.c_int()
+    _check(lib().amg_inner_stats(a, C.byref(calls), C.byref(its), C.byref(last)))
+    return calls.value, its.value, last.value
+
+
+def amg_coarse_solve(a, b_c, x_c, stream=None):
+    _check(lib().amg_coarse_solve(a, _dev(b_c), _dev(x_c), _stream(stream)))
 
 
 def sg_coarse_restrict(a, R, r_c, stream=None):

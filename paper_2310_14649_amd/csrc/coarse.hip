@@ -27,6 +27,7 @@ constexpr int kMaxLevels = 4;
 constexpr int kMinNodes = 8;
 constexpr int kPowerIts = 15;
 }  // namespace amgc
+constexpr int kMaxInnerIts = 200;
 
 // Host block-sparse matrix with dense P x P row-major blocks.
 struct Bsr {
@@ -64,6 +65,19 @@ struct sg_amg {
     int coarsest_n = 0;
     std::vector<int32_t> h_nodes, h_agg0;
     std::vector<double> h_omegas;
+    // inner Krylov coarse solve (amg_set_inner): basis V [(m+1) ld], flexible
+    // directions Z [m ld], w [ld], and Hessenberg / rotations / scalars
+    sg_inner_kind inner = SG_INNER_NONE;
+    double inner_rtol = 0.0;
+    int inner_max = 0;
+    int64_t inner_ld = 0;
+    sg::DevBuf<double> iV, iZ, iw, ismall;
+    double* ipin = nullptr;                   // pinned host slot for one estimate
+    mutable int64_t inner_calls = 0, inner_its = 0;
+    mutable int inner_last = 0;
+    ~sg_amg() {
+        if (ipin) (void)hipHostFree(ipin);
+    }
 };
 
 namespace sg {
@@ -573,7 +587,204 @@ const double* amg_vcycle_level(const sg_amg* a, int l, const double* b, double* 
     return L.xs.p;
 }
 
-void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
+// ------------------------------------------------------------------ inner GMRES
+// The coarse problem solved by GMRES on A_c (Sec. 3, the variants with an
+// inner Krylov solve): right-preconditioned by one V-cycle (2GV3) or by the
+// block Jacobi of the level-0 blocks, i.e. a non-overlapping one-level
+// Schwarz method with one coarse node per subdomain (2GV2), flexible form
+// (the directions z_j are kept), classical Gram-Schmidt with a second pass,
+// Givens rotations.  The host reads the residual estimate after every step
+// to stop at rtol ||b_c|| or after max_its steps (no restart).
+constexpr int kIT = 256;
+
+// c[i] = <V_i, w>, one work-group per basis vector (ldv = 0 and one
+// work-group give <w, w> with V = w).
+__global__ __launch_bounds__(kIT) void inner_dots_kernel(int N, int64_t ldv,
+                                                         const double* __restrict__ V,
+                                                         const double* __restrict__ w,
+                                                         double* __restrict__ c) {
+    __shared__ double sh[kIT / 64];
+    const double* v = V + (int64_t)blockIdx.x * ldv;
+    double a = 0.0;
+    for (int t = threadIdx.x; t < N; t += kIT) a = fma(v[t], w[t], a);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int q = 0; q < kIT / 64; ++q) r += sh[q];
+        c[blockIdx.x] = r;
+    }
+}
+
+// w -= sum_{i<k} c_i V_i
+__global__ __launch_bounds__(kIT) void inner_update_kernel(int N, int k, int64_t ldv,
+                                                           const double* __restrict__ V,
+                                                           const double* __restrict__ c,
+                                                           double* __restrict__ w) {
+    const int t = blockIdx.x * kIT + threadIdx.x;
+    if (t >= N) return;
+    double v = w[t];
+    for (int i = 0; i < k; ++i) v = fma(-c[i], V[(int64_t)i * ldv + t], v);
+    w[t] = v;
+}
+
+// Column j of the Hessenberg matrix (the two Gram-Schmidt passes c0 + c1,
+// and ||w|| below the diagonal), the earlier rotations applied to it, a new
+// rotation, and the residual estimate |g_{j+1}|: sc[0] = estimate,
+// sc[1] = 1/||w|| (0 at a breakdown).
+__global__ void inner_givens_kernel(int j, int m, const double* __restrict__ c0,
+                                    const double* __restrict__ c1, const double* __restrict__ ww,
+                                    double* H, double* cs, double* sn, double* g, double* sc) {
+    if (threadIdx.x != 0) return;
+    double* h = H + (size_t)j * (m + 1);
+    for (int i = 0; i <= j; ++i) h[i] = c0[i] + c1[i];
+    const double hn = sqrt(fmax(*ww, 0.0));
+    sc[1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    h[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double r = hypot(h[j], hn);
+    const double c = r > 0.0 ? h[j] / r : 1.0, sj = r > 0.0 ? hn / r : 0.0;
+    cs[j] = c;
+    sn[j] = sj;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = c * g[j];
+    sc[0] = fabs(g[j + 1]);
+}
+
+// y = H_k^{-1} g (upper triangular k x k), then the caller forms x = Z y
+__global__ void inner_backsolve_kernel(int k, int m, const double* __restrict__ H,
+                                       const double* __restrict__ g, double* __restrict__ y) {
+    if (threadIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int l = i + 1; l < k; ++l) v -= H[(size_t)l * (m + 1) + i] * y[l];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? v / d : 0.0;
+    }
+}
+
+// x = sum_{i<k} y_i Z_i
+__global__ __launch_bounds__(kIT) void inner_combine_kernel(int N, int k, int64_t ldz,
+                                                            const double* __restrict__ Z,
+                                                            const double* __restrict__ y,
+                                                            double* __restrict__ x) {
+    const int t = blockIdx.x * kIT + threadIdx.x;
+    if (t >= N) return;
+    double v = 0.0;
+    for (int i = 0; i < k; ++i) v = fma(y[i], Z[(int64_t)i * ldz + t], v);
+    x[t] = v;
+}
+
+// v = a w, a = *ad when ad is not null, else ah
+__global__ __launch_bounds__(kIT) void inner_scale_kernel(int N, const double* ad, double ah,
+                                                          const double* __restrict__ w,
+                                                          double* __restrict__ v) {
+    const int t = blockIdx.x * kIT + threadIdx.x;
+    if (t >= N) return;
+    v[t] = (ad ? *ad : ah) * w[t];
+}
+
+__global__ void inner_init_kernel(int m, double beta, double* g) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = i == 0 ? beta : 0.0;
+}
+
+bool inner_active(const sg_amg* a) {
+    return a->inner != SG_INNER_NONE && a->kind == SG_COARSE_AMG && a->lev.size() > 1;
+}
+
+void coarse_gmres(const sg_amg* a, const double* b, double* x, hipStream_t s) {
+    const int P = a->P, N = a->n_sub * P, m = a->inner_max;
+    const int64_t ld = a->inner_ld;
+    const AmgLevel& L0 = a->lev[0];
+    SG_REQUIRE(L0.nn == a->n_sub && a->iV.n >= (size_t)(m + 1) * ld && ld >= N,
+               "inner GMRES workspace does not match the hierarchy");
+    double* V = a->iV.p;
+    double* Zd = a->iZ.p;
+    double* w = a->iw.p;
+    double* H = a->ismall.p;
+    double* cs = H + (size_t)(m + 1) * m;
+    double* sn = cs + (m + 1);
+    double* g = sn + (m + 1);
+    double* y = g + (m + 1);
+    double* c0 = y + (m + 1);
+    double* c1 = c0 + (m + 1);
+    double* sc = c1 + (m + 1);                // estimate, 1/||w||, <w, w>
+    const unsigned gN = (unsigned)((N + kIT - 1) / kIT);
+    auto read_scalar = [&](const double* d) {
+        HIP_OK(hipMemcpyAsync(a->ipin, d, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        return a->ipin[0];
+    };
+    inner_dots_kernel<<<1, kIT, 0, s>>>(N, 0, b, b, sc + 2);
+    HIP_LAUNCH_OK();
+    const double beta = std::sqrt(read_scalar(sc + 2));
+    if (!std::isfinite(beta)) SG_THROW(SG_ERR_NUMERIC, "coarse right-hand side is not finite");
+    ++a->inner_calls;
+    a->inner_last = 0;
+    if (beta == 0.0) {
+        inner_scale_kernel<<<gN, kIT, 0, s>>>(N, nullptr, 0.0, b, x);
+        HIP_LAUNCH_OK();
+        return;
+    }
+    inner_init_kernel<<<1, 64, 0, s>>>(m, beta, g);
+    HIP_LAUNCH_OK();
+    inner_scale_kernel<<<gN, kIT, 0, s>>>(N, nullptr, 1.0 / beta, b, V);
+    HIP_LAUNCH_OK();
+    const double target = a->inner_rtol * beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+        const double* vj = V + (int64_t)j * ld;
+        double* zj = Zd + (int64_t)j * ld;
+        if (a->inner == SG_INNER_GMRES_AMG) {
+            amg_vcycle_level(a, 0, vj, zj, s, false);
+        } else if (a->prec == SG_FP64) {
+            jacobi_kernel<double><<<L0.nn, kBlk, 0, s>>>(P, L0.dinv64.p, vj, zj, 1.0, 0.0);
+        } else if (a->prec == SG_FP32) {
+            jacobi_kernel<float><<<L0.nn, kBlk, 0, s>>>(P, L0.dinv32.p, vj, zj, 1.0, 0.0);
+        } else {
+            jacobi_kernel<uint16_t><<<L0.nn, kBlk, 0, s>>>(P, L0.dinv16.p, vj, zj, 1.0, 0.0);
+        }
+        HIP_LAUNCH_OK();
+        bsr_mv_kernel<false, void><<<L0.nn, kBlkMv, 0, s>>>(
+            P, L0.a_ptr.p, L0.a_col.p, L0.a_val.p, zj, w, 1.0, 0.0, nullptr, nullptr, nullptr,
+            nullptr, 0.0, 0.0);
+        HIP_LAUNCH_OK();
+        inner_dots_kernel<<<j + 1, kIT, 0, s>>>(N, ld, V, w, c0);
+        HIP_LAUNCH_OK();
+        inner_update_kernel<<<gN, kIT, 0, s>>>(N, j + 1, ld, V, c0, w);
+        HIP_LAUNCH_OK();
+        inner_dots_kernel<<<j + 1, kIT, 0, s>>>(N, ld, V, w, c1);
+        HIP_LAUNCH_OK();
+        inner_update_kernel<<<gN, kIT, 0, s>>>(N, j + 1, ld, V, c1, w);
+        HIP_LAUNCH_OK();
+        inner_dots_kernel<<<1, kIT, 0, s>>>(N, 0, w, w, sc + 2);
+        HIP_LAUNCH_OK();
+        inner_givens_kernel<<<1, 64, 0, s>>>(j, m, c0, c1, sc + 2, H, cs, sn, g, sc);
+        HIP_LAUNCH_OK();
+        inner_scale_kernel<<<gN, kIT, 0, s>>>(N, sc + 1, 0.0, w, V + (int64_t)(j + 1) * ld);
+        HIP_LAUNCH_OK();
+        k = j + 1;
+        const double est = read_scalar(sc);
+        if (!(est > target)) break;           // converged, breakdown (0) or not finite
+    }
+    inner_backsolve_kernel<<<1, 64, 0, s>>>(k, m, H, g, y);
+    HIP_LAUNCH_OK();
+    inner_combine_kernel<<<gN, kIT, 0, s>>>(N, k, ld, Zd, y, x);
+    HIP_LAUNCH_OK();
+    a->inner_last = k;
+    a->inner_its += k;
+}
+
+// The coarse solve of the kind alone: one V-cycle, or the exact mean-based solve.
+void coarse_solve_base(const sg_amg* a, const double* b, double* x, hipStream_t s) {
     if (a->kind == SG_COARSE_MEAN_EXACT) {
         int tot = a->n_sub * a->P;
         mean_exact_kernel<<<(tot + 127) / 128, 128, 0, s>>>(a->n_sub, a->P, a->c0inv.p, a->afact.p,
@@ -582,6 +793,11 @@ void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
     } else {
         amg_vcycle_level(a, 0, b, x, s, false);
     }
+}
+
+void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
+    if (inner_active(a)) coarse_gmres(a, b, x, s);
+    else coarse_solve_base(a, b, x, s);
 }
 
 int amg_nsub(const sg_amg* a) { return a->n_sub; }
@@ -888,6 +1104,57 @@ int amg_level_blocks(const sg_amg* a, int level, int64_t* a_blocks, int64_t* p_b
 }
 
 int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a && b_c && x_c, "null argument");
+        SG_REQUIRE(b_c != x_c, "b_c and x_c must not alias");
+        check_device(a->device);
+        coarse_solve_base(a, b_c, x_c, as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int amg_set_inner(sg_amg* a, sg_inner_kind inner, double rtol, int max_its) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a != nullptr, "amg is NULL");
+        SG_REQUIRE(inner == SG_INNER_NONE || inner == SG_INNER_GMRES_AMG ||
+                       inner == SG_INNER_GMRES_BJ, "bad inner kind %d", (int)inner);
+        if (inner == SG_INNER_NONE) {
+            a->inner = SG_INNER_NONE;
+            return SG_OK;
+        }
+        SG_REQUIRE(a->kind == SG_COARSE_AMG, "an inner Krylov solve needs an SG_COARSE_AMG hierarchy");
+        SG_REQUIRE(rtol > 0.0 && rtol < 1.0, "inner rtol must be in (0, 1)");
+        SG_REQUIRE(max_its >= 1 && max_its <= kMaxInnerIts, "inner max_its=%d outside [1, %d]",
+                   max_its, kMaxInnerIts);
+        check_device(a->device);
+        const int64_t N = (int64_t)a->n_sub * a->P;
+        const int64_t ld = (N + 31) / 32 * 32;
+        if (a->inner_max != max_its || a->inner_ld != ld) {
+            a->iV.alloc((size_t)(max_its + 1) * ld);
+            a->iZ.alloc((size_t)max_its * ld);
+            a->iw.alloc((size_t)ld);
+            a->ismall.alloc((size_t)(max_its + 1) * max_its + 6 * (size_t)(max_its + 1) + 4);
+        }
+        if (!a->ipin) HIP_OK(hipHostMalloc(&a->ipin, 2 * sizeof(double), hipHostMallocDefault));
+        a->inner = inner;
+        a->inner_rtol = rtol;
+        a->inner_max = max_its;
+        a->inner_ld = ld;
+        return SG_OK;
+    });
+}
+
+int amg_inner_stats(const sg_amg* a, int64_t* calls, int64_t* its, int* last_its) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a != nullptr, "amg is NULL");
+        if (calls) *calls = a->inner_calls;
+        if (its) *its = a->inner_its;
+        if (last_its) *last_its = a->inner_last;
+        return SG_OK;
+    });
+}
+
+int amg_coarse_solve(const sg_amg* a, const double* b_c, double* x_c, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(a && b_c && x_c, "null argument");
         SG_REQUIRE(b_c != x_c, "b_c and x_c must not alias");

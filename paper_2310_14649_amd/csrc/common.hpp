@@ -272,6 +272,9 @@ int ras_n(const sg_ras* r);
 void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s);
 void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s);
 void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
+// true when the coarse solve is an inner Krylov iteration (host-synchronous,
+// so the Arnoldi step that contains it is not captured into a graph)
+bool inner_active(const sg_amg* a);
 int amg_nsub(const sg_amg* a);
 // krylov.hip: drop cached Arnoldi-step graphs that reference a handle
 void graph_cache_purge(const void* handle);

@@ -467,8 +467,23 @@ size_t fgmres_ws_np(int n, int P, const sg_amg* amg, int restart) {
     return fgmres_ws_ns(n, P, amg ? amg_nsub(amg) : -1, restart);
 }
 
-// Power estimate of rho(M A) from the all-ones field; returns the smoother
-// damping min(1, 1.6/rho).  ws: >= 2 vectors + partial sums.
+// Entry i of the power iteration's start: output i + 1 of the SplitMix64
+// generator (Steele, Lea and Flood, OOPSLA 2014) from state 0, its top 53 bits
+// as a uniform in [-1/2, 1/2).  A smooth start (all ones) holds too little of
+// the oscillating top modes for 15 steps to find them.
+__global__ __launch_bounds__(256) void power_start_kernel(int64_t N, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * 256) {
+        uint64_t z = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        y[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    }
+}
+
+// Power estimate of rho(M A) from the pseudo-random start; returns the
+// smoother damping min(1, 1.8/rho).  ws: >= 2 vectors + partial sums.
 double smoother_damping_core(const LinOp& A, const sg_ras* ras, int its, char* p, size_t ws_bytes,
                              hipStream_t s, double* rho_out) {
     const int64_t N = (int64_t)A.n * A.P;
@@ -479,7 +494,12 @@ double smoother_damping_core(const LinOp& A, const sg_ras* ras, int its, char* p
     double* w = reinterpret_cast<double*>(p + align_up(N * 8));
     double* part = reinterpret_cast<double*>(p + 2 * align_up(N * 8));
     double* scal = reinterpret_cast<double*>(p + 2 * align_up(N * 8) + align_up(kMaxRedBlocks * 8));
-    Vec::fill(N, 1.0 / std::sqrt((double)N), v, s);
+    power_start_kernel<<<grid_for(N), 256, 0, s>>>(N, v);
+    HIP_LAUNCH_OK();
+    {
+        const double n0 = std::sqrt(host_dot(N, v, v, part, scal, s));
+        Vec::scale(N, 1.0 / n0, v, v, s);
+    }
     double rho = 0.0;
     for (int it = 0; it < its; ++it) {
         linop_apply(A, v, w, 1.0, 0.0, nullptr, s);
@@ -490,7 +510,7 @@ double smoother_damping_core(const LinOp& A, const sg_ras* ras, int its, char* p
     }
     HIP_OK(hipStreamSynchronize(s));
     if (rho_out) *rho_out = rho;
-    return std::min(1.0, 1.6 / rho);
+    return std::min(1.0, 1.8 / rho);
 }
 
 // Flexible GMRES on any LinOp.  key_op identifies the operator in the graph
@@ -613,7 +633,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             if (beta <= target) converged = true;
             // one Arnoldi step, from its captured graph (captured on first use)
             auto launch_step = [&](int j) {
-                if (!opts->use_graph) {
+                if (!opts->use_graph || (amg && inner_active(amg))) {
                     arnoldi_step(j, s);
                     return;
                 }

@@ -105,6 +105,12 @@ class GpuSG:
                 cache.put(kras, dict(path=B.ras_path_info(self.ras)[2], ms=list(self.ras_ms)))
         self.tuned_from_cache = hit_ras is not None and (hit_mv is not None or not staged)
 
+    def set_inner(self, inner: str = "none", rtol: float = 1e-5, max_its: int = 100):
+        """The coarse solve of the two-grid cycle: one V-cycle ("none"), or an
+        inner GMRES preconditioned by a V-cycle ("gmres_amg", the paper's 2GV3)
+        or by block Jacobi ("gmres_bj", 2GV2)."""
+        B.amg_set_inner(self.amg, inner, rtol, max_its)
+
     def solve(self, restart: int, rtol: float, max_it: int = 2000, omega: float = 0.0,
               x0=None, use_precond: bool = True, use_graph: bool = False, ortho: str = "mgs"):
         x = self.new_vec() if x0 is None else x0.clone()
