@@ -242,8 +242,8 @@ def coarse_study(args, torch) -> dict:
     coarse problem solved by one V-cycle, by GMRES + V-cycle to 1e-5 (2GV3)
     and by GMRES + block Jacobi to 1e-2, <= 100 steps (2GV2), with the FP64
     and BF16 preconditioners.  ratio: config 1's field on an N_c = args.ratio_nc
-    mesh, subdomain grids 4 x 4 .. 32 x 32 (fine nodes per coarse node from
-    N_c^2/16 down to N_c^2/1024), V-cycle and 2GV3, BF16 preconditioner."""
+    mesh, subdomain grids 8 x 8 .. 64 x 64 (fine nodes per coarse node from
+    about N_c^2/64 down to N_c^2/4096), V-cycle and 2GV3, BF16 preconditioner."""
     from paper_2310_14649_amd import binding as B
     from paper_2310_14649_amd.inputs import make_problem
     from paper_2310_14649_amd.solver import GpuSG
@@ -269,12 +269,11 @@ def coarse_study(args, torch) -> dict:
                        if inner != "none" else ""))
                 variants.append(row)
     ratio = []
-    for gx in (4, 8, 16, 32):
+    for gx in (8, 16, 32, 64):
         prr = make_problem("c1", nc=args.ratio_nc, sub=(gx, gx))
-        path = "sweep" if prr.mesh.n / (gx * gx) > 2500 else "auto"
         for inner in ("none", "gmres_amg"):
             try:
-                g = GpuSG(prr, prec="bf16", coarse="amg", ras_path=path)
+                g = GpuSG(prr, prec="bf16", coarse="amg", ras_path="auto")
             except B.SgError as e:
                 ratio.append(dict(sub=gx * gx, coarse=inner, error=str(e)))
                 log(f"[bench] ratio {gx}x{gx}: {e}")
@@ -458,7 +457,7 @@ def main() -> int:
     ap.add_argument("--sweep-nc", type=int, default=256)
     ap.add_argument("--coarse-study", action="store_true",
                     help="coarse-solve variants (V-cycle, 2GV3, 2GV2) and the coarse-ratio sweep")
-    ap.add_argument("--ratio-nc", type=int, default=512)
+    ap.add_argument("--ratio-nc", type=int, default=256)
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
