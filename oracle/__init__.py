@@ -19,6 +19,7 @@ amg      smoothed-aggregation AMG hierarchy and its V-cycle
 precond  the multiplicative two-level composition
 krylov   flexible GMRES(m)
 stats    mean / variance of a PCE field, Monte Carlo and collocation checks
+cond     condition number of the SG operator against the deterministic one
 
 Every function is in FP64 and cites the passage of the paper it restates.
 Readings of passages that are silent, ambiguous or garbled are stated in
