@@ -455,6 +455,8 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true",
                     help="iterations and time against M (2..6) and p (1..4) on one mesh")
     ap.add_argument("--sweep-nc", type=int, default=256)
+    ap.add_argument("--local", default="mean", choices=["mean", "kron"],
+                    help="RAS local solves: mean-based K_0 (x) G_0 or Kronecker K_0 (x) Gt")
     ap.add_argument("--coarse-study", action="store_true",
                     help="coarse-solve variants (V-cycle, 2GV3, 2GV2) and the coarse-ratio sweep")
     ap.add_argument("--ratio-nc", type=int, default=256)
@@ -513,7 +515,8 @@ def main() -> int:
     ras_paths = {}
     for prec in precs:
         t0 = time.perf_counter()
-        solvers[prec] = GpuSG(pr, prec=prec, coarse="amg", ras_path=args.ras_path)
+        solvers[prec] = GpuSG(pr, prec=prec, coarse="amg", ras_path=args.ras_path,
+                              local=args.local)
         torch.cuda.synchronize()
         setup_s[prec] = time.perf_counter() - t0
         ras_paths[prec] = dict(path=B.ras_path_info(solvers[prec].ras)[2],
@@ -627,6 +630,7 @@ def main() -> int:
         "parts": parts,
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
         "ras_path": ras_paths,
+        "local_solves": args.local,
         "omega": omega,
         "cpu_baseline": cpu,
         "newton_c4": newton,

@@ -56,6 +56,12 @@ typedef enum {
     SG_COARSE_AMG = 2          /* one smoothed-aggregation V(1,1) cycle on A_c    */
 } sg_coarse_kind;
 
+/* Local solves of the RAS subdomains (ras_set_local). */
+typedef enum {
+    SG_LOCAL_MEAN = 0,   /* mean-based: (R_s A_0 R_s^T)^{-1} (x) G_0^{-1}                  */
+    SG_LOCAL_KRON = 1    /* Kronecker (Ullmann): (R_s K_0 R_s^T)^{-1} (x) Gt^{-1}           */
+} sg_local_kind;
+
 /* The coarse problem of the two-grid cycle solved by an inner Krylov method
  * (Sec. 3: the variants that solve the coarse problem inexactly by GMRES). */
 typedef enum {
@@ -198,6 +204,22 @@ int ras_path_info(const sg_ras* r, int* dense, int64_t* dense_bytes);
  * [n_sub], number of level sets per subdomain [n_sub], and the total bytes
  * of stored Schur-complement inverses. */
 int ras_info(const sg_ras* r, int32_t* n_local, int32_t* n_levels, int64_t* factor_bytes);
+/* ras_set_local -- the local solve of every subdomain (Sec. 3 uses the full
+ * local SG block; the Kronecker-product preconditioners it cites for SG
+ * systems motivate the second kind).  SG_LOCAL_MEAN (the default) solves with
+ * K_0 (x) G_0.  SG_LOCAL_KRON solves with K_0 (x) Gt, Ullmann's Kronecker
+ * factor Gt = sum_i (<K_i, K_0>_F / <K_0, K_0>_F) G_i, the G that minimises
+ * ||sum_i K_i (x) G_i - K_0 (x) G||_F, computed from `op`'s values (the
+ * global stiffness matrices, stored pattern).  Applied as a per-node mixing of
+ * the right-hand side by Gt^{-1} G_0 (a [n*P] FP64 buffer the handle
+ * allocates) before the unchanged mean-based kernels, since the mixing
+ * commutes with restriction, local K_0 solve and partition of unity; every
+ * path and precision takes it, and ras_refactor recomputes Gt.  Synchronous;
+ * captured Arnoldi-step graphs that use the handle are dropped.
+ * SG_ERR_NUMERIC if Gt is singular. */
+int ras_set_local(sg_ras* r, const sg_op* op, sg_local_kind mode, void* stream);
+/* host output: Gt [P*P] row-major, for SG_LOCAL_KRON handles. */
+int ras_local_factor(const sg_ras* r, double* gt);
 int ras_apply(const sg_ras* r, const double* R, double* Z, void* stream);
 void sg_destroy_ras(sg_ras* r);
 

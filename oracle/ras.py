@@ -78,3 +78,23 @@ def ras_apply(subs: List[Subdomain], R: np.ndarray, alpha_fact: np.ndarray) -> n
         loc = sla.cho_solve(sd.chol, R[sd.nodes]) / alpha_fact[None, :]
         Z[sd.nodes[sd.owned]] = loc[sd.owned]
     return Z
+
+
+def kron_factor(K: List[sp.csr_matrix], G: np.ndarray) -> np.ndarray:
+    """Ullmann's Kronecker factor for SG operators (the Kronecker-product
+    preconditioners the paper cites, Sec. 1): the P x P matrix Gt that makes
+    K_0 (x) Gt closest to sum_i K_i (x) G_i in the Frobenius norm,
+    Gt = sum_i (<K_i, K_0>_F / <K_0, K_0>_F) G_i."""
+    t0 = K[0].multiply(K[0]).sum()
+    return sum((Ki.multiply(K[0]).sum() / t0) * G[i] for i, Ki in enumerate(K))
+
+
+def ras_apply_kron(subs: List[Subdomain], R: np.ndarray, Gt: np.ndarray) -> np.ndarray:
+    """RAS with Kronecker local solves:
+    Z = sum_s R_s^T D_s [(R_s K0 R_s^T)^{-1} (R_s R) Gt^{-1}]."""
+    Gi = np.linalg.inv(Gt)
+    Z = np.zeros_like(R)
+    for sd in subs:
+        loc = sla.cho_solve(sd.chol, R[sd.nodes]) @ Gi
+        Z[sd.nodes[sd.owned]] = loc[sd.owned]
+    return Z

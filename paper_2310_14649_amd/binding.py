@@ -90,6 +90,8 @@ _SIGS = {
     "ras_autotune": (C.c_int, [_vp, C.c_int, _f64p, _vp]),
     "ras_path_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i64p]),
     "ras_info": (C.c_int, [_vp, _i32p, _i32p, _i64p]),
+    "ras_set_local": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "ras_local_factor": (C.c_int, [_vp, _f64p]),
     "ras_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "sg_destroy_ras": (None, [_vp]),
     "amg_setup": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
@@ -330,6 +332,22 @@ def ras_info(r, n_sub: int):
     fb = C.c_int64()
     _check(lib().ras_info(r, _ptr(nloc, C.c_int32), _ptr(nlev, C.c_int32), C.byref(fb)))
     return nloc, nlev, fb.value
+
+
+SG_LOCAL_MEAN, SG_LOCAL_KRON = 0, 1
+LOCAL = {"mean": SG_LOCAL_MEAN, "kron": SG_LOCAL_KRON}
+
+
+def ras_set_local(r, op, mode="mean", stream=None):
+    """Local solves: "mean" (K_0 (x) G_0) or "kron" (K_0 (x) Gt, Ullmann)."""
+    kind = LOCAL[mode] if isinstance(mode, str) else int(mode)
+    _check(lib().ras_set_local(r, op, kind, _stream(stream)))
+
+
+def ras_local_factor(r, P: int):
+    gt = np.zeros(P * P, dtype=np.float64)
+    _check(lib().ras_local_factor(r, _ptr(gt, C.c_double)))
+    return gt.reshape(P, P)
 
 
 def ras_apply(r, R, Z, stream=None):

@@ -58,6 +58,11 @@ struct sg_ras {
     sg::DevBuf<unsigned char> xg;                 // gathered right-hand sides [s][Pp][ld]
     int nblk[3] = {0, 0, 0};
     int dense_var = 0;                            // 0: 64 rows per wave, 1: 32, 2: fused
+    // Kronecker local solves (ras_set_local): the right-hand side is first
+    // mixed per node by W = Gt^{-1} G_0 [P x Pw, row k col j, zero-padded] into kron_t
+    sg_local_kind local_mode = SG_LOCAL_MEAN;
+    sg::DevBuf<double> kron_w, kron_t;
+    std::vector<double> h_gt;                     // Gt, for ras_local_factor
     bool fused_ok = false;                        // fused variant fits (LDS, columns)
     size_t fused_lds = 0;                         // its LDS bytes per work-group
     double ms_sweep = -1.0, ms_dense = -1.0;      // autotuner timings
@@ -1032,8 +1037,55 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
 #undef SG_DENSE
 }
 
+// T[a, j] = sum_k R[a, k] W[k, j]: the mode mixing of the Kronecker local
+// solve K_0 (x) Gt, applied ahead of the mean-based RAS (it acts per node, so
+// it commutes with the restriction, the local K_0 solves and the partition of
+// unity).  One wave per 64 nodes, one lane per node: the tile of R is staged
+// in LDS with coalesced loads, and each lane forms its outputs in groups of
+// kMixJ, reading W (padded to a multiple of kMixJ columns) at wave-uniform
+// addresses, so W comes through the scalar cache and each FMA needs one LDS
+// read per kMixJ outputs.  HBM sees one read of R and one write of T, the
+// latter in 64-byte runs.
+constexpr int kMixJ = 8;
+inline int kron_wcols(int P) { return (P + kMixJ - 1) / kMixJ * kMixJ; }
+__global__ __launch_bounds__(64) void kron_mix_kernel(int n, int P, const double* __restrict__ W,
+                                                      const double* __restrict__ R,
+                                                      double* __restrict__ T) {
+    extern __shared__ double Rs[];            // [64][P]
+    const int a0 = blockIdx.x * 64, lane = threadIdx.x;
+    const int cnt = min(64, n - a0) * P;
+    const double* rg = R + (int64_t)a0 * P;
+    for (int q = lane; q < cnt; q += 64) Rs[q] = rg[q];
+    __syncthreads();
+    if (a0 + lane >= n) return;
+    const int Pw = (P + kMixJ - 1) / kMixJ * kMixJ;
+    const double* rr = Rs + lane * P;
+    double* tg = T + (int64_t)(a0 + lane) * P;
+    for (int j0 = 0; j0 < P; j0 += kMixJ) {
+        double acc[kMixJ];
+#pragma unroll
+        for (int u = 0; u < kMixJ; ++u) acc[u] = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < P; ++k) {
+            const double rk = rr[k];
+            const double* wk = W + (size_t)k * Pw + j0;
+#pragma unroll
+            for (int u = 0; u < kMixJ; ++u) acc[u] = fma(rk, wk[u], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kMixJ; ++u)
+            if (j0 + u < P) tg[j0 + u] = acc[u];
+    }
+}
+
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
+    if (r->local_mode == SG_LOCAL_KRON) {
+        kron_mix_kernel<<<(unsigned)((r->n + 63) / 64), 64, (size_t)64 * r->P * 8, s>>>(
+            r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+        HIP_LAUNCH_OK();
+        R = r->kron_t.p;
+    }
     if (r->use_dense) {
         ras_dense_apply(r, R, Z, omega, beta, s);
         return;
@@ -1582,6 +1634,91 @@ int ras_setup(const sg_op* op, const int32_t* owner, int n_sub, int overlap, sg_
     });
 }
 
+// The Kronecker local factor of Ullmann's preconditioner: Gt = sum_i
+// (<K_i, K_0>_F / <K_0, K_0>_F) G_i, the G that minimises the Frobenius
+// distance of K_0 (x) G to sum_i K_i (x) G_i, and the mixing W = Gt^{-1} G_0
+// that turns the mean-based RAS (which divides mode j by <Psi_j^2>) into
+// RAS with the local operator K_0 (x) Gt.
+void ras_kron_weights(sg_ras* r, const sg_op* op, hipStream_t s) {
+    const int L = op->L, P = op->P;
+    std::vector<double> v((size_t)op->nnz * L);
+    op->vals.download(v.data(), v.size(), s);
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<double> t(L, 0.0);
+    for (int64_t e = 0; e < op->nnz; ++e) {
+        const double k0 = v[(size_t)e * L];
+        for (int i = 0; i < L; ++i) t[i] += v[(size_t)e * L + i] * k0;
+    }
+    if (!(t[0] > 0.0)) SG_THROW(SG_ERR_NUMERIC, "mean stiffness matrix is zero");
+    const sg_basis& B = op->basis;
+    std::vector<double> G((size_t)P * P, 0.0);
+    for (int q = 0; q < B.T; ++q)
+        G[(size_t)B.tk[q] * P + B.tj[q]] += (t[B.ti[q]] / t[0]) * B.tv[q];
+    r->h_gt = G;
+    // Gauss-Jordan with partial pivoting: Ginv = Gt^{-1}
+    std::vector<double> A = G, I((size_t)P * P, 0.0);
+    for (int k = 0; k < P; ++k) I[(size_t)k * P + k] = 1.0;
+    for (int c = 0; c < P; ++c) {
+        int piv = c;
+        for (int q = c + 1; q < P; ++q)
+            if (std::fabs(A[(size_t)q * P + c]) > std::fabs(A[(size_t)piv * P + c])) piv = q;
+        if (!(std::fabs(A[(size_t)piv * P + c]) > 0.0))
+            SG_THROW(SG_ERR_NUMERIC, "Kronecker factor Gt is singular");
+        if (piv != c)
+            for (int q = 0; q < P; ++q) {
+                std::swap(A[(size_t)piv * P + q], A[(size_t)c * P + q]);
+                std::swap(I[(size_t)piv * P + q], I[(size_t)c * P + q]);
+            }
+        const double d = 1.0 / A[(size_t)c * P + c];
+        for (int q = 0; q < P; ++q) {
+            A[(size_t)c * P + q] *= d;
+            I[(size_t)c * P + q] *= d;
+        }
+        for (int q2 = 0; q2 < P; ++q2) {
+            if (q2 == c) continue;
+            const double f = A[(size_t)q2 * P + c];
+            if (f == 0.0) continue;
+            for (int q = 0; q < P; ++q) {
+                A[(size_t)q2 * P + q] -= f * A[(size_t)c * P + q];
+                I[(size_t)q2 * P + q] -= f * I[(size_t)c * P + q];
+            }
+        }
+    }
+    const int Pw = kron_wcols(P);                // columns padded with zeros
+    std::vector<double> W((size_t)P * Pw, 0.0);
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j) W[(size_t)k * Pw + j] = I[(size_t)k * P + j] * op->h_afact[j];
+    r->kron_w.upload(W, s);
+    const size_t N = (size_t)r->n * P;
+    if (r->kron_t.n < N) r->kron_t.alloc(N);
+    HIP_OK(hipStreamSynchronize(s));
+}
+
+int ras_set_local(sg_ras* r, const sg_op* op, sg_local_kind mode, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r && op, "null argument");
+        SG_REQUIRE(mode == SG_LOCAL_MEAN || mode == SG_LOCAL_KRON, "bad local-solve kind %d",
+                   (int)mode);
+        check_device(op->device);
+        SG_REQUIRE(op->device == r->device, "ras and op on different devices");
+        SG_REQUIRE(op->n == r->n && op->nnz == r->op_nnz && op->P == r->P,
+                   "op does not have the pattern the ras was built for");
+        if (mode == SG_LOCAL_KRON) ras_kron_weights(r, op, as_stream(stream));
+        if (r->local_mode != mode) sg::graph_cache_purge(r);   // captured steps hold the old mode
+        r->local_mode = mode;
+        return SG_OK;
+    });
+}
+
+int ras_local_factor(const sg_ras* r, double* gt) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(r && gt, "null argument");
+        SG_REQUIRE(r->local_mode == SG_LOCAL_KRON, "local solves are not Kronecker");
+        std::copy(r->h_gt.begin(), r->h_gt.end(), gt);
+        return SG_OK;
+    });
+}
+
 int ras_refactor(sg_ras* r, const sg_op* op, void* stream) {
     return guarded([&]() -> int {
         SG_REQUIRE(r && op, "null argument");
@@ -1591,6 +1728,7 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream) {
                    "op does not have the pattern the ras was built for");
         ras_factor_values(r, op, as_stream(stream));
         if (r->dense_built) ras_build_dense(r, as_stream(stream));
+        if (r->local_mode == SG_LOCAL_KRON) ras_kron_weights(r, op, as_stream(stream));
         return SG_OK;
     });
 }

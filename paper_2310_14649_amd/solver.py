@@ -17,7 +17,8 @@ COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_
 
 
 class GpuSG:
-    """ras_path: "sweep", "dense", "dense32", "fused", or "auto" (timed by the library,
+    """local: the subdomain solves, "mean" (K_0 (x) G_0) or "kron" (K_0 (x) Gt).
+    ras_path: "sweep", "dense", "dense32", "fused", or "auto" (timed by the library,
     also choosing the staged matvec's work-group shape).  tune_cache: with
     "auto", a ``TuneCache`` (or its file path) that supplies choices already
     made for this shape and records new ones."""
@@ -25,7 +26,7 @@ class GpuSG:
     def __init__(self, pr: Problem, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
                  n_sub: Optional[int] = None, stream=None, ras_path: str = "sweep",
-                 tune_cache=None):
+                 tune_cache=None, local: str = "mean"):
         import torch
         self.torch = torch
         self.pr = pr
@@ -45,6 +46,8 @@ class GpuSG:
         self.coarse = coarse
         self.ras = B.ras_setup(self.op, self.owner, self.n_sub, self.overlap, B.PREC[prec],
                                stream=stream)
+        if local != "mean":
+            B.ras_set_local(self.ras, self.op, local, stream=stream)
         self.ras_ms = None
         self.mv_ms = None
         self.tuned_from_cache = False
