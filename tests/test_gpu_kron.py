@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "c1_64": dict(name="c1", nc=64, sub=(8, 8)),
     "c4_ragged": dict(name="c4", nc=23, sub=(3, 5)),
-    "c3_40": dict(name="c3", nc=40, sub=(4, 4)),
+    "c3_40": dict(name="c3", nc=40, sub=(4, 4)),          # P = 84
+    "m5p3": dict(name="c1", nc=24, M=5, p=3, sub=(3, 3)),  # P = 56
 }
 
 
@@ -36,7 +37,7 @@ def _host(t, shape):
     return t.cpu().numpy().reshape(shape)
 
 
-@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40"])
+@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40", "m5p3"])
 def test_kron_factor_and_ras_match_oracle(key):
     pr, S = _setup(key)
     subs = oras.ras_setup(S.K[0], pr.owner, pr.n_sub, S.adj, pr.overlap)
