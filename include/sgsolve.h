@@ -263,7 +263,8 @@ int amg_vcycle(const sg_amg* a, const double* b_c, double* x_c, void* stream);
  * coarse nodes (the paper uses one-level RAS, rtol 1e-2, <= 100 steps).
  * SG_INNER_NONE restores the V-cycle.  Needs kind SG_COARSE_AMG; a
  * hierarchy of one level is already an exact solve and keeps it.  Allocates
- * the inner basis ((2 max_its + 2) n_sub P doubles) and a pinned host slot.
+ * the inner basis ((2 max_its + 2) n_sub P doubles) and a pinned host slot;
+ * a call that changes max_its first waits for the device.
  * The inner solve reads its residual estimate on the host after every step,
  * so it synchronises the stream: fgmres_solve does not capture graphs of
  * Arnoldi steps while it is active, and a caller must not capture it. */

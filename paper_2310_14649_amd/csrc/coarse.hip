@@ -1130,6 +1130,8 @@ int amg_set_inner(sg_amg* a, sg_inner_kind inner, double rtol, int max_its) {
         const int64_t N = (int64_t)a->n_sub * a->P;
         const int64_t ld = (N + 31) / 32 * 32;
         if (a->inner_max != max_its || a->inner_ld != ld) {
+            // the last inner solve's combination may still be reading the basis
+            HIP_OK(hipDeviceSynchronize());
             a->iV.alloc((size_t)(max_its + 1) * ld);
             a->iZ.alloc((size_t)max_its * ld);
             a->iw.alloc((size_t)ld);
