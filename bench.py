@@ -294,17 +294,22 @@ def coarse_study(args, torch) -> dict:
             "ratio_nc": args.ratio_nc, "ratio": ratio}
 
 
-def cpu_baseline(pr, its_gpu: int, sample_its: int):
+def cpu_baseline(pr, its_gpu: int, sample_its: int, local: str = "mean"):
     """The oracle (plain NumPy/SciPy FP64) on the host: setup, then
-    ``sample_its`` FGMRES iterations with the same preconditioner definition,
-    scaled to the iteration count of the GPU FP64 solve."""
+    ``sample_its`` FGMRES iterations with the same preconditioner definition
+    (mean-based or Kronecker local solves), scaled to the iteration count of
+    the GPU FP64 solve."""
     from threadpoolctl import threadpool_info
 
     from oracle import krylov, system
+    from oracle import ras as oras
     m = pr.mesh
     t0 = time.perf_counter()
     S = system.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p)
-    B2, *_ = system.two_level(S, pr.owner, pr.n_sub, pr.overlap, "amg", omega=0.5)
+    B2, subs, *_ = system.two_level(S, pr.owner, pr.n_sub, pr.overlap, "amg", omega=0.5)
+    if local == "kron":
+        Gt = oras.kron_factor(S.K, S.G)
+        B2.M = lambda R: oras.ras_apply_kron(subs, R, Gt)  # noqa: E731
     t_setup = time.perf_counter() - t0
     X = np.random.default_rng(0).standard_normal((m.n, S.P))
     t0 = time.perf_counter()
@@ -455,7 +460,7 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true",
                     help="iterations and time against M (2..6) and p (1..4) on one mesh")
     ap.add_argument("--sweep-nc", type=int, default=256)
-    ap.add_argument("--local", default="mean", choices=["mean", "kron"],
+    ap.add_argument("--local", default="kron", choices=["mean", "kron"],
                     help="RAS local solves: mean-based K_0 (x) G_0 or Kronecker K_0 (x) Gt")
     ap.add_argument("--coarse-study", action="store_true",
                     help="coarse-solve variants (V-cycle, 2GV3, 2GV2) and the coarse-ratio sweep")
@@ -587,7 +592,7 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        c = cpu_baseline(pr, results["fp64"]["iterations"], args.cpu_sample_its)
+        c = cpu_baseline(pr, results["fp64"]["iterations"], args.cpu_sample_its, args.local)
         cpu = {"value": c["est_solve_ms"], "unit": "ms", "cores": c["threads"], "kind": "oracle",
                "sample": f"{args.cpu_sample_its} oracle FGMRES(50) iterations of this workload "
                          f"(FP64, same two-grid preconditioner, setup {c['setup_s']:.1f} s "

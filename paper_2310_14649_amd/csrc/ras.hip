@@ -1037,51 +1037,67 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
 #undef SG_DENSE
 }
 
+// W's rows are padded with zero columns to a multiple of kMixJ.
+constexpr int kMixJ = 8;
+inline int kron_wcols(int P) { return (P + kMixJ - 1) / kMixJ * kMixJ; }
+
 // T[a, j] = sum_k R[a, k] W[k, j]: the mode mixing of the Kronecker local
 // solve K_0 (x) Gt, applied ahead of the mean-based RAS (it acts per node, so
 // it commutes with the restriction, the local K_0 solves and the partition of
-// unity).  One wave per 64 nodes, one lane per node: the tile of R is staged
-// in LDS with coalesced loads, and each lane forms its outputs in groups of
-// kMixJ, reading W (padded to a multiple of kMixJ columns) at wave-uniform
-// addresses, so W comes through the scalar cache and each FMA needs one LDS
-// read per kMixJ outputs.  HBM sees one read of R and one write of T, the
-// latter in 64-byte runs.
-constexpr int kMixJ = 8;
-inline int kron_wcols(int P) { return (P + kMixJ - 1) / kMixJ * kMixJ; }
-__global__ __launch_bounds__(64) void kron_mix_kernel(int n, int P, const double* __restrict__ W,
-                                                      const double* __restrict__ R,
-                                                      double* __restrict__ T) {
+// unity), on the FP64 matrix cores: per wave a tile of 64 nodes,
+// T_tile (64 x P) = R_tile (64 x P) W (P x P) as 16 x 16 x 4 FP64 MFMA steps
+// (four 16-row blocks per 16-column block, K in steps of 4).  Lane l feeds
+// A[l % 16][l / 16] (the node row from LDS), B[l / 16][l % 16] (W from the
+// cache) and holds D[l / 16 + 4 r][l % 16], r = 0..3 (checked with a probe
+// of one non-zero B entry against lane-numbered A).  Rows of the tile
+// past n and the K and column tails are zero-filled or not stored; a row of D
+// depends only on its own row of A.
+typedef double kmix_d4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(64) void kron_mix_mfma_kernel(int n, int P,
+                                                           const double* __restrict__ W,
+                                                           const double* __restrict__ R,
+                                                           double* __restrict__ T) {
     extern __shared__ double Rs[];            // [64][P]
     const int a0 = blockIdx.x * 64, lane = threadIdx.x;
-    const int cnt = min(64, n - a0) * P;
+    const int na = min(64, n - a0), cnt = na * P;
     const double* rg = R + (int64_t)a0 * P;
     for (int q = lane; q < cnt; q += 64) Rs[q] = rg[q];
+    for (int q = cnt + lane; q < 64 * P; q += 64) Rs[q] = 0.0;
     __syncthreads();
-    if (a0 + lane >= n) return;
     const int Pw = (P + kMixJ - 1) / kMixJ * kMixJ;
-    const double* rr = Rs + lane * P;
-    double* tg = T + (int64_t)(a0 + lane) * P;
-    for (int j0 = 0; j0 < P; j0 += kMixJ) {
-        double acc[kMixJ];
+    const int li = lane & 15, lk = lane >> 4;
+    const int nk = (P + 3) / 4, ncb = (P + 15) / 16;
+    double* tg = T + (int64_t)a0 * P;
+    for (int cb = 0; cb < ncb; ++cb) {
+        const int j = cb * 16 + li;
+        kmix_d4 acc[4];
 #pragma unroll
-        for (int u = 0; u < kMixJ; ++u) acc[u] = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < P; ++k) {
-            const double rk = rr[k];
-            const double* wk = W + (size_t)k * Pw + j0;
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = kmix_d4{0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < nk; ++ks) {
+            const int k = ks * 4 + lk;
+            const double b = (k < P && j < P) ? W[(size_t)k * Pw + j] : 0.0;
 #pragma unroll
-            for (int u = 0; u < kMixJ; ++u) acc[u] = fma(rk, wk[u], acc[u]);
+            for (int rb = 0; rb < 4; ++rb) {
+                const double av = k < P ? Rs[(rb * 16 + li) * P + k] : 0.0;
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[rb], 0, 0, 0);
+            }
         }
+        if (j < P) {
 #pragma unroll
-        for (int u = 0; u < kMixJ; ++u)
-            if (j0 + u < P) tg[j0 + u] = acc[u];
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int node = rb * 16 + lk + 4 * q;
+                    if (node < na) tg[(size_t)node * P + j] = acc[rb][q];
+                }
+        }
     }
 }
 
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
     if (r->local_mode == SG_LOCAL_KRON) {
-        kron_mix_kernel<<<(unsigned)((r->n + 63) / 64), 64, (size_t)64 * r->P * 8, s>>>(
+        kron_mix_mfma_kernel<<<(unsigned)((r->n + 63) / 64), 64, (size_t)64 * r->P * 8, s>>>(
             r->n, r->P, r->kron_w.p, R, r->kron_t.p);
         HIP_LAUNCH_OK();
         R = r->kron_t.p;
