@@ -1094,11 +1094,70 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_kernel(int n, int P,
     }
 }
 
+// The same MFMA mixing for P <= 4 NK with the A fragments of the whole tile
+// loaded straight into registers (lane l: rows rb*16 + l % 16, columns
+// 4 ks + l / 16), all issued before the first MFMA; no LDS, so occupancy is
+// set by registers alone.
+template <int NK>
+__global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
+                                                               const double* __restrict__ W,
+                                                               const double* __restrict__ R,
+                                                               double* __restrict__ T) {
+    const int a0 = blockIdx.x * 64, lane = threadIdx.x;
+    const int na = min(64, n - a0);
+    const int li = lane & 15, lk = lane >> 4;
+    const int Pw = (P + kMixJ - 1) / kMixJ * kMixJ;
+    double av[4][NK];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int m = rb * 16 + li;
+        const double* rr = R + (int64_t)(a0 + m) * P;
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+            const int k = ks * 4 + lk;
+            av[rb][ks] = (m < na && k < P) ? rr[k] : 0.0;
+        }
+    }
+    const int ncb = (P + 15) / 16;
+    double* tg = T + (int64_t)a0 * P;
+    for (int cb = 0; cb < ncb; ++cb) {
+        const int j = cb * 16 + li;
+        kmix_d4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = kmix_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+            if (ks * 4 < P) {
+                const int k = ks * 4 + lk;
+                const double b = (k < P && j < P) ? W[(size_t)k * Pw + j] : 0.0;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb][ks], b, acc[rb], 0, 0, 0);
+            }
+        }
+        if (j < P) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int node = rb * 16 + lk + 4 * q;
+                    if (node < na) tg[(size_t)node * P + j] = acc[rb][q];
+                }
+        }
+    }
+}
+
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
     if (r->local_mode == SG_LOCAL_KRON) {
-        kron_mix_mfma_kernel<<<(unsigned)((r->n + 63) / 64), 64, (size_t)64 * r->P * 8, s>>>(
-            r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+        const unsigned g = (unsigned)((r->n + 63) / 64);
+        if (r->P <= 40)
+            kron_mix_mfma_reg_kernel<10><<<g, 64, 0, s>>>(r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+        else if (r->P <= 64)
+            kron_mix_mfma_reg_kernel<16><<<g, 64, 0, s>>>(r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+        else
+            kron_mix_mfma_kernel<<<g, 64, (size_t)64 * r->P * 8, s>>>(r->n, r->P, r->kron_w.p, R,
+                                                                     r->kron_t.p);
         HIP_LAUNCH_OK();
         R = r->kron_t.p;
     }
