@@ -200,7 +200,7 @@ def stochastic_sweep(args, torch) -> dict:
                        unknowns=pr.mesh.n * P)
             for prec in ("fp64", "bf16"):
                 try:
-                    g = GpuSG(pr, prec=prec, coarse="amg", ras_path="auto")
+                    g = GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local=args.local)
                 except B.SgError as e:          # a shape outside a compiled limit
                     row[prec] = dict(error=str(e))
                     continue
@@ -223,7 +223,7 @@ def stochastic_sweep(args, torch) -> dict:
                            else row[k]["error"]) for k in ("fp64", "bf16"))
                 + f" ({row.get('matvec_kernel', '?')} matvec)")
             rows.append(row)
-    return {"sweep": True, "nc": args.sweep_nc, "rows": rows}
+    return {"sweep": True, "nc": args.sweep_nc, "local_solves": args.local, "rows": rows}
 
 
 def _timed_solve(g, pr, omega, torch, graph=True):
@@ -250,7 +250,7 @@ def coarse_study(args, torch) -> dict:
     variants = []
     pr = make_problem(args.config)
     for prec in ("fp64", "bf16"):
-        with GpuSG(pr, prec=prec, coarse="amg", ras_path="auto") as g:
+        with GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local=args.local) as g:
             rho, omega = g.damping()
             for inner, rtol in (("none", 0.0), ("gmres_amg", 1e-5), ("gmres_bj", 1e-2)):
                 if inner != "none":
@@ -273,7 +273,7 @@ def coarse_study(args, torch) -> dict:
         prr = make_problem("c1", nc=args.ratio_nc, sub=(gx, gx))
         for inner in ("none", "gmres_amg"):
             try:
-                g = GpuSG(prr, prec="bf16", coarse="amg", ras_path="auto")
+                g = GpuSG(prr, prec="bf16", coarse="amg", ras_path="auto", local=args.local)
             except B.SgError as e:
                 ratio.append(dict(sub=gx * gx, coarse=inner, error=str(e)))
                 log(f"[bench] ratio {gx}x{gx}: {e}")
@@ -290,7 +290,8 @@ def coarse_study(args, torch) -> dict:
             log(f"[bench] ratio {gx}x{gx} ({row['nodes_per_coarse_node']} nodes per coarse node) "
                 f"{inner}: {row['its']} its {row['ms']:.1f} ms")
             ratio.append(row)
-    return {"coarse_study": True, "config": args.config, "variants": variants,
+    return {"coarse_study": True, "config": args.config, "local_solves": args.local,
+            "variants": variants,
             "ratio_nc": args.ratio_nc, "ratio": ratio}
 
 
