@@ -325,14 +325,16 @@ def cpu_baseline(pr, its_gpu: int, sample_its: int, local: str = "mean"):
                 est_solve_ms=per_it * its_gpu * 1e3)
 
 
-def workload(pr, n: int, P: int, mixed: str) -> str:
+def workload(pr, n: int, P: int, mixed: str, local: str = "mean") -> str:
     """The workload named by its sizes."""
     nc = pr.mesh.nc
     mesh = f"{nc}x{nc} P1" + (" (jittered vertices)" if pr.mesh.jittered else "")
     sub = (f"{pr.n_sub} graph-partitioned subdomains" if "partition_seed" in pr.extra
            else f"{pr.n_sub} lattice subdomains")
     return (f"linear SG Poisson {mesh}, M={pr.M} KL vars, order {pr.p} (P={P}), {n * P:,} "
-            f"unknowns, RAS on {sub} overlap {pr.overlap} + SA-AMG Nicolaides coarse, "
+            f"unknowns, RAS on {sub} overlap {pr.overlap} with "
+            f"{'Kronecker K0 x Gt' if local == 'kron' else 'mean-based K0 x G0'} local solves "
+            f"+ SA-AMG Nicolaides coarse, "
             f"FGMRES({pr.restart}) to {pr.rtol:g}, preconditioner {mixed}")
 
 
@@ -619,7 +621,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload(pr, n, P, args.mixed),
+        "config": {"workload": workload(pr, n, P, args.mixed, args.local),
                    "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub,
                    "graph": bool(args.graph), "ortho": args.ortho},
         "solves": results,
