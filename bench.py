@@ -96,7 +96,7 @@ ENTRY_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense, MI355X
 
 
-def ras_only(pr, prec: str, path: str, launches: int, torch, g=None) -> dict:
+def ras_only(pr, prec: str, path: str, launches: int, torch, g=None, local: str = "mean") -> dict:
     """One RAS apply (Z = sum_s R_s^T D_s A_s^{-1} R_s R) timed alone.
     Algorithmic bytes: the stored inverse data read once (dense rows, or the
     sweep's Schur-complement inverses), R read once, Z written once; flops
@@ -106,7 +106,7 @@ def ras_only(pr, prec: str, path: str, launches: int, torch, g=None) -> dict:
     from paper_2310_14649_amd.solver import GpuSG
     own = g is None
     if own:
-        g = GpuSG(pr, prec=prec, coarse="none", ras_path=path)
+        g = GpuSG(pr, prec=prec, coarse="none", ras_path=path, local=local)
     try:
         name = B.ras_path_info(g.ras)[2]
         nloc, _, factor_bytes = B.ras_info(g.ras, pr.n_sub)
@@ -497,7 +497,8 @@ def main() -> int:
         print(json.dumps(coarse_study(args, torch)))
         return 0
     if args.ras_only:
-        print(json.dumps(ras_only(pr, args.part_prec, args.ras_path, args.mv_launches, torch)))
+        print(json.dumps(ras_only(pr, args.part_prec, args.ras_path, args.mv_launches, torch,
+                                  local=args.local)))
         return 0
     if args.amg_only:
         print(json.dumps(amg_only(pr, args.part_prec, args.mv_launches, torch)))
