@@ -1096,8 +1096,8 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_kernel(int n, int P,
 
 // The same MFMA mixing for P <= 4 NK with the A fragments of the whole tile
 // loaded straight into registers (lane l: rows rb*16 + l % 16, columns
-// 4 ks + l / 16), all issued before the first MFMA; no LDS, so occupancy is
-// set by registers alone.
+// 4 ks + l / 16), all issued before the first MFMA; D goes through an LDS
+// tile so that each node row is stored contiguously.
 template <int NK>
 __global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
                                                                const double* __restrict__ W,
@@ -1119,7 +1119,7 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
         }
     }
     const int ncb = (P + 15) / 16;
-    double* tg = T + (int64_t)a0 * P;
+    extern __shared__ double Ts[];            // [64][P]: the tile's D, stored row-contiguous
     for (int cb = 0; cb < ncb; ++cb) {
         const int j = cb * 16 + li;
         kmix_d4 acc[4];
@@ -1139,12 +1139,12 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int node = rb * 16 + lk + 4 * q;
-                    if (node < na) tg[(size_t)node * P + j] = acc[rb][q];
-                }
+                for (int q = 0; q < 4; ++q) Ts[(rb * 16 + lk + 4 * q) * P + j] = acc[rb][q];
         }
     }
+    __syncthreads();
+    double* tg = T + (int64_t)a0 * P;
+    for (int q = lane; q < na * P; q += 64) tg[q] = Ts[q];
 }
 
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
@@ -1152,9 +1152,11 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
     if (r->local_mode == SG_LOCAL_KRON) {
         const unsigned g = (unsigned)((r->n + 63) / 64);
         if (r->P <= 40)
-            kron_mix_mfma_reg_kernel<10><<<g, 64, 0, s>>>(r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+            kron_mix_mfma_reg_kernel<10><<<g, 64, (size_t)64 * r->P * 8, s>>>(r->n, r->P, r->kron_w.p,
+                                                                           R, r->kron_t.p);
         else if (r->P <= 64)
-            kron_mix_mfma_reg_kernel<16><<<g, 64, 0, s>>>(r->n, r->P, r->kron_w.p, R, r->kron_t.p);
+            kron_mix_mfma_reg_kernel<16><<<g, 64, (size_t)64 * r->P * 8, s>>>(r->n, r->P, r->kron_w.p,
+                                                                           R, r->kron_t.p);
         else
             kron_mix_mfma_kernel<<<g, 64, (size_t)64 * r->P * 8, s>>>(r->n, r->P, r->kron_w.p, R,
                                                                      r->kron_t.p);
