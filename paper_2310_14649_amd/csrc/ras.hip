@@ -1379,9 +1379,11 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
     int maxo = 0;
     for (int q = 0; q < ns; ++q) maxo = std::max(maxo, r->h_nown[q]);
     const dim3 tg(ns, std::max(1, (maxo + 15) / 16));
+    // A rebuild (ras_refactor) keeps the buffer when its size is unchanged, so
+    // captured Arnoldi-step graphs that read it stay valid.
 #define SG_TILE(TS, BUF)                                                                           \
     do {                                                                                           \
-        BUF.alloc((size_t)tiled);                                                                  \
+        if (BUF.n != (size_t)tiled || !BUF.p) BUF.alloc((size_t)tiled);                            \
         tile_dense_kernel<TS><<<tg, 256, 0, s>>>(r->nown_d.p, r->ld_d.p, r->aoff_d.p, r->toff_d.p, \
                                                  rows.p, BUF.p);                                   \
         HIP_LAUNCH_OK();                                                                           \
@@ -1803,9 +1805,13 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream) {
         SG_REQUIRE(op->device == r->device, "ras and op on different devices");
         SG_REQUIRE(op->n == r->n && op->nnz == r->op_nnz && op->P == r->P,
                    "op does not have the pattern the ras was built for");
+        const void* before[3] = {r->ainv64.p, r->ainv32.p, r->ainv16.p};
         ras_factor_values(r, op, as_stream(stream));
         if (r->dense_built) ras_build_dense(r, as_stream(stream));
         if (r->local_mode == SG_LOCAL_KRON) ras_kron_weights(r, op, as_stream(stream));
+        // graphs captured earlier hold the dense rows' address: drop them if it moved
+        if (before[0] != r->ainv64.p || before[1] != r->ainv32.p || before[2] != r->ainv16.p)
+            sg::graph_cache_purge(r);
         return SG_OK;
     });
 }

@@ -124,13 +124,22 @@ def test_forward_and_gradients_match_oracle(channels, H, W, Bn):
             assert _rl2(g[q + nw:q + nw + nb], gbb) < 3e-3
             q += nw + nb
         assert q == g_bf.size
-        # Adam with the device gradient against the oracle's update
+        # Adam with the device gradient against the oracle's update, over
+        # three steps with a new gradient each time (other targets), the
+        # oracle carrying its moments and step count as the device does
         p0, _ = B.nn_get_params(nn)
-        B.nn_adam_step(nn, 1e-3)
-        p1, _ = B.nn_get_params(nn)
-        ref = onn.adam_step(onn.unflatten(p0.astype(np.float64), channels),
-                            onn.unflatten(g.astype(np.float64), channels), {}, 1e-3)
-        assert np.abs(p1 - onn.flatten(ref)).max() <= 1e-5 * 1e-3 + 1e-6 * np.abs(p0).max()
+        state, ref = {}, onn.unflatten(p0.astype(np.float64), channels)
+        rng = np.random.default_rng(9)
+        for step in range(3):
+            if step:
+                B.nn_loss_grad(nn, Xd, torch.from_numpy(rng.standard_normal(T.shape)).cuda(), Bn)
+                _, g = B.nn_get_params(nn)
+            B.nn_adam_step(nn, 1e-3)
+            p1, _ = B.nn_get_params(nn)
+            ref = onn.adam_step(ref, onn.unflatten(g.astype(np.float64), channels), state, 1e-3)
+            # FP32 master weights: an update of size <= lr per step, rounded to FP32
+            assert np.abs(p1 - onn.flatten(ref)).max() <= 1e-5 * 1e-3 + 1e-6 * np.abs(p0).max(), step
+        assert state["t"] == 3
     finally:
         B.nn_destroy(nn)
 
@@ -187,14 +196,15 @@ def test_guess_falls_back_to_zero_for_a_bad_prediction(small_model):
     assert choice in (1, 2) and min(rel[1], rel[2]) < 1e-9
 
 
-def test_learned_guess_against_zero_guess(small_model):
-    """What the trained network gains on held-out draws: Newton steps and
-    Krylov iterations from the learned guess against the zero guess (both to
-    ||R||/||F|| <= 1e-8, same solution).  The guess never starts from a larger
-    residual than zero; on this mildly nonlinear problem, whose zero-guess
-    Newton already converges in three steps, a prediction with a few per cent
-    of error saves only a few iterations, so the test bounds the loss (at most
-    one Krylov iteration per solve on average) and reports the gain."""
+def test_learned_guess_lowers_the_starting_residual(small_model):
+    """What the trained network gains on held-out draws: the starting
+    residual ||R(U_0)||/||F|| of the learned guess against the zero guess's 1
+    (strictly below 1 on every draw, and on average by at least 10 %), with
+    the same converged solution.  Newton steps and Krylov iterations are
+    reported beside it; on this mildly nonlinear problem, whose zero-guess
+    Newton converges in three steps, the lower start saves at most a few
+    Krylov iterations, so those are only bounded (no Newton step more, at
+    most one Krylov iteration more on average)."""
     lg, train, _ = small_model
     held = draw_params(8, seed=1)
     its_nn, its_zero, steps_nn, steps_zero, rel = [], [], [], [], []
@@ -204,7 +214,7 @@ def test_learned_guess_against_zero_guess(small_model):
         assert i0["converged"] and i1["converged"]
         assert i1["guess_choice"] in (0, 1, 2)
         chosen = [1.0, *i1["guess_relres"][1:]][i1["guess_choice"]]
-        assert chosen <= 1.0
+        assert chosen < 1.0
         rel.append(chosen)
         # both meet ||R||/||F|| <= 1e-8; the iterates agree to the solve tolerance
         assert float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0)) < 1e-6
@@ -218,6 +228,6 @@ def test_learned_guess_against_zero_guess(small_model):
     print(f"[learned] mean: zero {np.mean(steps_zero):.2f} steps / {np.mean(its_zero):.2f} its, "
           f"nn {np.mean(steps_nn):.2f} steps / {np.mean(its_nn):.2f} its, "
           f"start residual {np.mean(rel):.3f}", flush=True)
-    assert np.mean(rel) < 1.0
+    assert np.mean(rel) < 0.9
     assert np.mean(its_nn) <= np.mean(its_zero) + 1.0
     assert np.mean(steps_nn) <= np.mean(steps_zero)
