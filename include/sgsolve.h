@@ -138,8 +138,11 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * (one wave per row: L_in > 32 or P > 64), SG_MV_PAIR (fixed basis, two
  * lanes per row), SG_MV_STAGED (fixed basis, input terms split between
  * waves, neighbour rows staged in LDS; needs rows whose neighbours form a
- * few runs of consecutive rows per block of 128).  Host call. */
-enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3 };
+ * few runs of consecutive rows per block of 128), SG_MV_GROUPED (a wide
+ * fixed basis, M = 6, p_in = 2, p = 3: input terms and output modes split
+ * between the waves of a 64-row tile, neighbour rows staged in LDS).
+ * Host call. */
+enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3, SG_MV_GROUPED = 4 };
 int sg_matvec_kernel(const sg_op* op, int* kind);
 /* Work-group shape of the staged kernel: 1, 2 or 4 tiles of 64 rows per
  * work-group (2 after assembly when it fits).  sg_matvec_autotune times

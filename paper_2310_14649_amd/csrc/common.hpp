@@ -147,6 +147,7 @@ struct KronCsr {
     // block of rows, the runs of neighbour rows staged in LDS, and each
     // entry's column as an index into that staging area
     int split = -1, split_kt = 0;      // split_kt: tiles of 64 rows per work-group
+    int group = -1;                    // grouped kernel id (one tile per work-group), -1 = none
     const int32_t* sruns = nullptr;    // [blocks][2*kRuns+1]
     const int16_t* sslot = nullptr;    // [tiles][S][64]
     const double* svals = nullptr;     // [tiles][S][L][64]
@@ -176,6 +177,7 @@ struct sg_op {
     sg::DevBuf<int32_t> ecol;
     sg::DevBuf<double> evals;
     int split = -1;
+    int group = -1;                    // grouped kernel (staging in sruns[0], sslot[0], svals)
     int split_var = 0;                 // selected tile count: 1, 2, 4 tiles for 0, 1, 2
     bool split_fits[3] = {false, false, false};
     sg::DevBuf<int32_t> sruns[3];
@@ -193,7 +195,7 @@ struct sg_op {
         k.n = n; k.nnz = nnz; k.max_row = max_row;
         k.rowptr = rowptr.p; k.col = col.p; k.vals = vals.p;
         k.spec = spec; k.ell_S = ell_S; k.ell_RW = ell_RW; k.ecol = ecol.p; k.evals = evals.p;
-        k.split = split; k.split_kt = 1 << split_var;
+        k.split = split; k.split_kt = 1 << split_var; k.group = group;
         k.sruns = sruns[split_var].p; k.sslot = sslot[split_var].p; k.svals = svals.p;
         return k;
     }

@@ -530,6 +530,255 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
 }
 }  // namespace split
 
+// ---------------------------------------------------------------------------
+// Grouped kernel for wide fixed bases (many input terms and output modes,
+// e.g. M = 6, p = 3: L_in = 28, P = 84, on the 7-point pattern of a jittered
+// mesh).  One work-group takes one tile of 64 rows with IGN x KGN waves.
+// Wave (ig, kg) holds, one row per lane, the K values of the input terms
+// [ig*LI, ig*LI + LI) of its row's entries and accumulates the output modes
+// [kg*KL, kg*KL + KL), so both the values and the accumulators fit the
+// registers of two waves per SIMD; the coefficients m_ijk of each wave's
+// share stay immediates.  The tile's neighbour rows (a few runs of
+// consecutive rows, as for the split kernel) are staged in LDS JC columns at
+// a time, double-buffered through registers, and shared by all waves; JC is
+// odd, so the 8-byte reads of consecutive rows hit distinct banks.  The
+// waves of one input-term group add their partial sums through LDS at the
+// end, in a fixed order.
+namespace grp {
+constexpr int RB = 64, JC = 13, kSlots = 256;
+using split::kRuns;
+using split::kRunWords;
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(1))) const uint32_t glb_u32;
+
+template <int P, int C>
+constexpr int width() {
+    return (P - C * JC) < JC ? (P - C * JC) : JC;
+}
+
+constexpr int kBufDoubles = kSlots * JC;          // one staged chunk: [slot][JC]
+constexpr int kDmaBlocks = kBufDoubles * 2 / 64;  // 64 dwords per wave-wide DMA
+static_assert(kBufDoubles * 2 % 64 == 0, "a chunk must be whole DMA blocks");
+
+// LDS: two chunk buffers, or the partial sums of the input-term groups
+// (after the last chunk); then the source row of each staging slot and the
+// staging offset of each entry of the tile's rows.
+template <int S>
+constexpr size_t kTableDoubles = (kSlots + S * RB + 1) / 2;
+
+template <int P, int S>
+constexpr size_t lds_doubles(int IGN, int KGN) {
+    const size_t stage = 2 * (size_t)kBufDoubles;
+    const size_t red = (size_t)(IGN - 1) * KGN * ((P + KGN - 1) / KGN) * RB;
+    return (stage > red ? stage : red) + kTableDoubles<S>;
+}
+
+// Stage chunk C of the tile's neighbour rows into buf by LDS DMA: dword d of
+// the chunk is half (d & 1) of X[row(slot)][C*JC + jj], slot*JC + jj = d / 2.
+// Wave w issues the 64-dword blocks w, w + NW, ...; no registers hold the
+// values, and the loads stay in flight until the wave's vmcnt wait.
+template <int P, int C, int NW>
+__device__ __forceinline__ void stage_dma(const double* __restrict__ X, const int* srows,
+                                          double* buf, int wave, int lane) {
+    constexpr int W = width<P, C>();
+    for (int blk = wave; blk < kDmaBlocks; blk += NW) {
+        const int d = blk * 64 + lane;
+        const int e = d >> 1;
+        const int slot = e / JC, jj = e - slot * JC;
+        const int col = C * JC + (jj < W ? jj : 0);     // positions past the chunk read column 0
+        const uint32_t* src =
+            reinterpret_cast<const uint32_t*>(X + (size_t)srows[slot] * P + col) + (d & 1);
+        __builtin_amdgcn_global_load_lds((glb_u32*)src, (lds_u32*)((char*)buf + blk * 256), 4, 0,
+                                         0);
+    }
+}
+
+__device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// slot: staging offsets in doubles (staging slot * JC).  The reads are
+// volatile: every wave group reads the same addresses, and merging those
+// reads across the groups' branches would hoist them and keep many columns'
+// values live at once.
+template <int S, int JJ>
+__device__ __forceinline__ void xload(const int* slot, const double* xs, double* x) {
+    typedef const volatile __attribute__((address_space(3))) double lds_cvd;
+    lds_cvd* vx = (lds_cvd*)xs;
+#pragma unroll
+    for (int q = 0; q < S; ++q) x[q] = vx[slot[q] + JJ];
+}
+
+// The triples of one column (sorted by input term) form each
+// w = sum_q K_i[a, b_q] X[b_q, j] just before the triples that use it, so only
+// one w is live.
+template <class H, int J>
+constexpr bool has_triples() {
+    return H::t.jptr[J + 1] > H::t.jptr[J];
+}
+
+template <class H, int S, int LI, int T0, int T>
+__device__ __forceinline__ void wstep(const double (*v)[LI], const double* x, double& w,
+                                      double* y) {
+    constexpr int ii = H::t.ii[T];
+    if constexpr (T == T0 || H::t.ii[T > T0 ? T - 1 : T0] != ii) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) a = fma(v[q][ii], x[q], a);
+        w = a;
+    }
+    constexpr int k = H::t.k[T];
+    constexpr double m = H::t.m[T];
+    y[k] = fma(m, w, y[k]);
+}
+
+template <class H, int S, int LI, int T0, int... Is>
+__device__ __forceinline__ void wrange(std::integer_sequence<int, Is...>, const double (*v)[LI],
+                                       const double* x, double* y) {
+    double w = 0.0;
+    (wstep<H, S, LI, T0, T0 + Is>(v, x, w, y), ...);
+}
+
+// Column J0 + JJ for the wave group of H: load the neighbour values, then
+// walk the column's triples.
+template <class H, int S, int LI, int J0, int JJ>
+__device__ __forceinline__ void column(const int* slot, const double (*v)[LI], const double* xs,
+                                       double* y) {
+    if constexpr (has_triples<H, J0 + JJ>()) {
+        constexpr int t0 = H::t.jptr[J0 + JJ], t1 = H::t.jptr[J0 + JJ + 1];
+        // columns are not interleaved by the scheduler: that would keep more
+        // products live than the registers hold
+        __builtin_amdgcn_sched_barrier(0);
+        double x[S];
+        xload<S, JJ>(slot, xs, x);
+        wrange<H, S, LI, t0>(std::make_integer_sequence<int, t1 - t0>{}, v, x, y);
+    }
+}
+
+template <class H, int S, int LI, int J0, int... JJs>
+__device__ __forceinline__ void columns(std::integer_sequence<int, JJs...>, const int* slot,
+                                        const double (*v)[LI], const double* xs, double* y) {
+    (column<H, S, LI, J0, JJs>(slot, v, xs, y), ...);
+}
+
+// The columns of chunk C for the wave's group (one branch per group and
+// chunk).  The staging offsets of the rows' entries are read from LDS at the
+// start of the chunk, so they are not kept in registers across chunks.
+template <int M, int PIN, int PO, int S, int IGN, int KGN, int LI, int C, int... Gs>
+__device__ __forceinline__ void chunk_groups(std::integer_sequence<int, Gs...>, int wave, int lane,
+                                             const int* soff, const double (*v)[LI],
+                                             const double* xs, double* y) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    constexpr int W = width<P, C>();
+    int slot[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) slot[q] = soff[q * RB + lane];
+    ((wave == Gs ? (columns<tab::WaveGroupHolder<M, PIN, PO, IGN, KGN, Gs>, S, LI, C * JC>(
+                        std::make_integer_sequence<int, W>{}, slot, v, xs, y),
+                    0)
+                 : 0),
+     ...);
+}
+
+template <int M, int PIN, int PO, int S, int IGN, int KGN, int LI, int NCH, int... Cs>
+__device__ __forceinline__ void chunks(std::integer_sequence<int, Cs...>, int wave, int lane,
+                                       const int* srows, const int* soff, const double (*v)[LI],
+                                       double* lds, const double* __restrict__ X, double* y) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    (([&] {
+         // chunk Cs + 1 streams into the other buffer (last read in chunk Cs - 1,
+         // before the barrier that ended it) while chunk Cs is computed
+         if constexpr (Cs + 1 < NCH)
+             stage_dma<P, Cs + 1, IGN * KGN>(X, srows, lds + ((Cs + 1) & 1) * kBufDoubles, wave,
+                                             lane);
+         chunk_groups<M, PIN, PO, S, IGN, KGN, LI, Cs>(
+             std::make_integer_sequence<int, IGN * KGN>{}, wave, lane, soff, v,
+             lds + (Cs & 1) * kBufDoubles, y);
+         dma_wait();
+         __syncthreads();
+     }()),
+     ...);
+}
+
+template <int M, int PIN, int PO, int S, int IGN, int KGN>
+__global__ __launch_bounds__(64 * IGN * KGN) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void kron_matvec_group_kernel(int n, int ntiles, const int32_t* __restrict__ runs,
+                              const int16_t* __restrict__ sslot, const double* __restrict__ svals,
+                              const double* __restrict__ X, double* Y, double alpha, double beta,
+                              const double* C) {
+    constexpr int P = tab::cbinom(M + PO, PO);
+    constexpr int L = tab::cbinom(M + PIN, PIN);
+    constexpr int LI = (L + IGN - 1) / IGN, KL = (P + KGN - 1) / KGN;
+    constexpr int NCH = (P + JC - 1) / JC;
+    constexpr int kThreads = 64 * IGN * KGN;
+    static_assert(kThreads >= kSlots && kThreads >= S * RB, "threads for the LDS tables");
+    extern __shared__ __align__(16) double glds[];
+    int* srows = reinterpret_cast<int*>(glds + (lds_doubles<P, S>(IGN, KGN) - kTableDoubles<S>));
+    int* soff = srows + kSlots;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ig = wave % IGN, kg = wave / IGN;
+    const int tile = split::xcd_block(blockIdx.x, gridDim.x);
+    // source row of every staging slot (slots past the runs read a valid row),
+    // and the staging offset (in doubles) of every entry of the tile's rows
+    if (tid < kSlots) {
+        const int32_t* rw = runs + (size_t)tile * kRunWords;
+        int r = rw[0] + (tid - rw[kRuns]);
+#pragma unroll
+        for (int q = 1; q < kRuns; ++q) r = (tid >= rw[kRuns + q]) ? rw[q] + (tid - rw[kRuns + q]) : r;
+        srows[tid] = tid < rw[2 * kRuns] ? r : rw[0];
+    }
+    if (tid < S * RB) soff[tid] = (int)sslot[(size_t)tile * S * RB + tid] * JC;
+    double v[S][LI];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int ii = 0; ii < LI; ++ii) {
+            const int i = ig * LI + ii;
+            v[q][ii] = i < L ? svals[(((size_t)tile * S + q) * L + i) * RB + lane] : 0.0;
+        }
+    __syncthreads();                                  // tables ready
+    stage_dma<P, 0, IGN * KGN>(X, srows, glds, wave, lane);
+    double y[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) y[k] = 0.0;
+    dma_wait();
+    __syncthreads();                                  // chunk 0 staged
+    chunks<M, PIN, PO, S, IGN, KGN, LI, NCH>(std::make_integer_sequence<int, NCH>{}, wave, lane,
+                                             srows, soff, v, glds, X, y);
+    // partial sums of input-term groups 1.. through LDS (the staging area is free)
+    double* red = glds;
+    if (ig > 0) {
+#pragma unroll
+        for (int k = 0; k < KL; ++k) red[(((size_t)(ig - 1) * KGN + kg) * KL + k) * RB + lane] = y[k];
+    }
+    __syncthreads();
+    if (ig > 0) return;
+    for (int g2 = 1; g2 < IGN; ++g2) {
+#pragma unroll
+        for (int k = 0; k < KL; ++k) y[k] += red[(((size_t)(g2 - 1) * KGN + kg) * KL + k) * RB + lane];
+    }
+    const int row = tile * RB + lane;
+    if (row >= n) return;
+    const int k0 = kg * KL;
+    double* yr = Y + (size_t)row * P + k0;
+    if (beta != 0.0) {
+        // C may alias Y: this wave's part of the row of C is read before any
+        // of Y is written
+        double c[KL];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) c[k] = (k0 + k < P) ? C[(size_t)row * P + k0 + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < KL; ++k) y[k] = fma(beta, c[k], alpha * y[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KL; ++k) y[k] *= alpha;
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k)
+        if (k0 + k < P) yr[k] = y[k];
+}
+}  // namespace grp
+
 // ELL copy: entry id of every (tile, slot, lane) position, -1 for padding.
 __global__ void ell_fill_kernel(int64_t npos, int L, int S, int RW, const int64_t* __restrict__ ent,
                                 const double* __restrict__ vals, double* __restrict__ evals) {
@@ -585,6 +834,23 @@ void launch_split(const KronCsr& A, const double* X, double* Y, double alpha, do
         case 4: launch_split_kt<Id, 4>(A, X, Y, alpha, beta, C, s); break;
         default: SG_THROW(SG_ERR_INVALID_ARG, "bad tiles per work-group %d", A.split_kt);
     }
+}
+
+struct GroupSpec {
+    int M, PIN, PO, S, IGN, KGN;
+};
+constexpr GroupSpec kGroups[] = {{6, 2, 3, 7, 4, 2}};
+
+template <int Id>
+void launch_group(const KronCsr& A, const double* X, double* Y, double alpha, double beta,
+                  const double* C, hipStream_t s) {
+    constexpr GroupSpec g = kGroups[Id];
+    constexpr int P = tab::cbinom(g.M + g.PO, g.PO);
+    const int tiles = (A.n + grp::RB - 1) / grp::RB;
+    const size_t lds = grp::lds_doubles<P, g.S>(g.IGN, g.KGN) * sizeof(double);
+    grp::kron_matvec_group_kernel<g.M, g.PIN, g.PO, g.S, g.IGN, g.KGN>
+        <<<tiles, 64 * g.IGN * g.KGN, lds, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha,
+                                                beta, C);
 }
 
 // Neighbour rows of one block of rows as at most kRuns runs of consecutive
@@ -701,12 +967,64 @@ bool build_split(sg_op* op, hipStream_t s) {
     return true;
 }
 
+// Staged copy for the grouped kernel: one tile of 64 rows per work-group, the
+// values per (tile, entry, lane) and the staging of each tile's neighbour rows.
+bool build_group(sg_op* op, hipStream_t s) {
+    const sg_basis& b = op->basis;
+    int id = -1;
+    for (int q = 0; q < (int)(sizeof(kGroups) / sizeof(kGroups[0])); ++q) {
+        const GroupSpec& g = kGroups[q];
+        if (g.M == b.M && g.PIN == b.p_in && g.PO == b.p && op->max_row <= g.S) {
+            id = q;
+            break;
+        }
+    }
+    if (id < 0 || op->n == 0) return false;
+    const int S = kGroups[id].S, RB = grp::RB;
+    static_assert(grp::RB == split::RB && grp::kSlots == 2 * 2 * split::RB,
+                  "the grouped kernel reuses the one-tile staging of the split kernel");
+    std::vector<int32_t> runs;
+    std::vector<int16_t> slot;
+    if (!split_staging(op, S, 1, runs, slot)) return false;
+    int lds_max = 0;
+    HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device));
+    const GroupSpec g = kGroups[id];
+    const int P = op->P;
+    const size_t need = (std::max(2 * (size_t)grp::kBufDoubles,
+                                  (size_t)(g.IGN - 1) * g.KGN * ((P + g.KGN - 1) / g.KGN) * RB) +
+                         (grp::kSlots + (size_t)S * RB + 1) / 2) * 8;
+    if (need > (size_t)lds_max) return false;
+    op->sruns[0].upload(runs, s);
+    op->sslot[0].upload(slot, s);
+    const int n = op->n, tiles = (n + RB - 1) / RB;
+    std::vector<int64_t> ent((size_t)tiles * S * RB, -1);
+    for (int a = 0; a < n; ++a) {
+        const int t = a / RB, r = a % RB;
+        int q = 0;
+        for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q)
+            ent[((size_t)t * S + q) * RB + r] = e;
+    }
+    DevBuf<int64_t> d_ent;
+    d_ent.upload(ent, s);
+    const int64_t npos = (int64_t)tiles * S * RB;
+    op->svals.alloc((size_t)npos * op->L);
+    ell_fill_kernel<<<(unsigned)((npos * op->L + 255) / 256), 256, 0, s>>>(npos, op->L, S, RB, d_ent.p,
+                                                                           op->vals.p, op->svals.p);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(s));
+    op->group = id;
+    op->split_var = 0;
+    return true;
+}
+
 }  // namespace
 
 void build_ell(sg_op* op, hipStream_t s) {
     op->spec = -1;
     op->split = -1;
+    op->group = -1;
     if (build_split(op, s)) return;
+    if (build_group(op, s)) return;
     const sg_basis& b = op->basis;
     int id = -1;
     for (int q = 0; q < (int)(sizeof(kSpecs) / sizeof(kSpecs[0])); ++q) {
@@ -751,6 +1069,14 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
                  double alpha, double beta, const double* C, hipStream_t s) {
     const int P = tr.P, T = tr.T;
     if (A.n == 0) return;
+    if (A.group >= 0) {
+        switch (A.group) {
+            case 0: launch_group<0>(A, X, Y, alpha, beta, C, s); break;
+            default: SG_THROW(SG_ERR_INVALID_ARG, "bad grouped matvec variant %d", A.group);
+        }
+        HIP_LAUNCH_OK();
+        return;
+    }
     if (A.split >= 0) {
         switch (A.split) {
             case 0: launch_split<0>(A, X, Y, alpha, beta, C, s); break;
@@ -854,7 +1180,9 @@ extern "C" int sg_matvec(const sg_op* op, const double* X, double* Y, void* stre
 extern "C" int sg_matvec_kernel(const sg_op* op, int* kind) {
     return guarded([&]() -> int {
         SG_REQUIRE(op && kind, "null argument");
-        if (op->split >= 0)
+        if (op->group >= 0)
+            *kind = SG_MV_GROUPED;
+        else if (op->split >= 0)
             *kind = SG_MV_STAGED;
         else if (op->spec >= 0)
             *kind = SG_MV_PAIR;

@@ -176,6 +176,59 @@ struct GroupHolder {
     static constexpr GroupTable<M, PIN, PO, IG, G> t = make_group<M, PIN, PO, IG, G>();
 };
 
+// Triples of one wave group of the grouped kernel: input terms i in
+// [IG*LI, IG*LI + LI) and output modes k in [KG*KL, KG*KL + KL), G = IG +
+// IGN*KG, sorted by j, with local indices ii = i - IG*LI and k - KG*KL (field
+// k), and per-j ranges jptr.
+template <int M, int PIN, int PO, int IGN, int KGN, int G>
+struct WaveGroupTable {
+    static constexpr int P = cbinom(M + PO, PO);
+    static constexpr int L = cbinom(M + PIN, PIN);
+    static constexpr int LI = (L + IGN - 1) / IGN;
+    static constexpr int KL = (P + KGN - 1) / KGN;
+    static constexpr int IG = G % IGN, KG = G / IGN;
+    static constexpr bool mine(int i, int k) {
+        return i >= IG * LI && i < IG * LI + LI && k >= KG * KL && k < KG * KL + KL;
+    }
+    static constexpr int count() {
+        constexpr const auto& t = TableHolder<M, PIN, PO>::t;
+        int c = 0;
+        for (int q = 0; q < Table<M, PIN, PO>::T; ++q)
+            if (mine(t.ti[q], t.tk[q])) ++c;
+        return c;
+    }
+    static constexpr int T = count();
+    int jptr[P + 1] = {};
+    int ii[T > 0 ? T : 1] = {}, k[T > 0 ? T : 1] = {};
+    double m[T > 0 ? T : 1] = {};
+};
+
+template <int M, int PIN, int PO, int IGN, int KGN, int G>
+constexpr WaveGroupTable<M, PIN, PO, IGN, KGN, G> make_wave_group() {
+    using GT = WaveGroupTable<M, PIN, PO, IGN, KGN, G>;
+    GT g{};
+    constexpr const auto& t = TableHolder<M, PIN, PO>::t;
+    int q = 0;
+    for (int j = 0; j < GT::P; ++j) {
+        g.jptr[j] = q;
+        for (int r = 0; r < Table<M, PIN, PO>::T; ++r)
+            if (t.tj[r] == j && GT::mine(t.ti[r], t.tk[r])) {
+                g.ii[q] = t.ti[r] - GT::IG * GT::LI;
+                g.k[q] = t.tk[r] - GT::KG * GT::KL;
+                g.m[q] = t.tv[r];
+                ++q;
+            }
+    }
+    g.jptr[GT::P] = q;
+    return g;
+}
+
+template <int M, int PIN, int PO, int IGN, int KGN, int G>
+struct WaveGroupHolder {
+    static constexpr WaveGroupTable<M, PIN, PO, IGN, KGN, G> t =
+        make_wave_group<M, PIN, PO, IGN, KGN, G>();
+};
+
 // Union over the IG = 2 lane groups: entries (j, ii, k) with the triple of
 // group 0 (i = ii) and of group 1 (i = LI + ii), either possibly zero, so one
 // uniform instruction stream serves both lanes of a row.
