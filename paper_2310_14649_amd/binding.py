@@ -258,7 +258,7 @@ def sg_matvec(op, X, Y, stream=None):
     _check(lib().sg_matvec(op, _dev(X), _dev(Y), _stream(stream)))
 
 
-MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged"}
+MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged", 4: "grouped"}
 
 
 def sg_matvec_kernel(op) -> str:
