@@ -294,6 +294,22 @@ void sg_destroy_amg(sg_amg* a);
 size_t sg_precond_workspace_bytes(const sg_op* op, const sg_amg* amg);
 int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, double omega,
                      const double* R, double* Z, void* ws, size_t ws_bytes, void* stream);
+/* sg_precond_apply_noalloc -- the two-grid cycle of sg_precond_apply for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the workspace comes from a
+ * static device array of SG_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends, instead of a `ws` argument.  Same arguments and result as
+ * sg_precond_apply; the call makes no device allocation.  All calls on one
+ * GPU share that GPU's scratch, so calls that overlap on one GPU (other
+ * streams, other threads) race; order them on one stream.  The scratch keeps
+ * the last call's contents; the cycle writes every entry before reading it.
+ * Errors: SG_ERR_WORKSPACE when sg_precond_workspace_bytes(op, amg) exceeds
+ * SG_NOALLOC_SCRATCH_BYTES (amg == NULL needs none); as sg_precond_apply
+ * otherwise.  With an inner coarse GMRES (amg_set_inner) the call
+ * synchronises the stream, as the apply with a workspace does. */
+#define SG_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int sg_precond_apply_noalloc(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
+                             double omega, const double* R, double* Z, void* stream);
 /* Damping of the smoother: rho = power estimate of rho(M A) (`its`
  * iterations from a SplitMix64 field: entry i of the flattened [n*P] start
  * is output i + 1 from state 0, top 53 bits mapped to [-1/2, 1/2));

@@ -133,6 +133,7 @@ _SIGS = {
     "nn_loss_grad": (C.c_int, [_vp, _vp, _vp, C.c_int, _f64p, _vp]),
     "nn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     "nn_destroy": (None, [_vp]),
+    "sg_precond_apply_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp]),
     "newton_workspace_bytes": (C.c_size_t, [_vp, C.c_int, C.c_int, C.c_int]),
     "newton_solve": (C.c_int, [_vp, _i32p, C.c_int, C.c_int, C.c_int, C.c_int, _vp,
                                C.POINTER(NewtonOpts), C.POINTER(NewtonStats), _vp, C.c_size_t,
@@ -426,6 +427,14 @@ def sg_precond_apply(op, ras, amg, omega: float, R, Z, ws, stream=None):
     nbytes = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().sg_precond_apply(op, ras, amg, omega, _dev(R), _dev(Z), _dev(ws), nbytes,
                                   _stream(stream)))
+
+
+SG_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
+
+
+def sg_precond_apply_noalloc(op, ras, amg, omega: float, R, Z, stream=None):
+    _check(lib().sg_precond_apply_noalloc(op, ras, amg, omega, _dev(R), _dev(Z),
+                                          _stream(stream)))
 
 
 def sg_smoother_damping(op, ras, its, ws, stream=None):

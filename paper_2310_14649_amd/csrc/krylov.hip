@@ -733,6 +733,32 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
         return converged ? SG_OK : SG_NOT_CONVERGED;
 }
 
+// ------------------------------------------------- the no-allocation apply
+// Scratch of sg_precond_apply_noalloc: the workspace of sg_precond_apply
+// (T [n*P], then r_c and e_c [n_sub*P], each 256-byte aligned) in a
+// file-scope device array.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is not a device
+// address: kernels receive the address hipGetSymbolAddress returns for the
+// current device, looked up once per device and cached here.
+static __device__ __align__(256) char scratch[SG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+char* scratch_ptr() {
+    const int dev = current_device();
+    SG_REQUIRE(dev >= 0 && dev < kMaxScratchDevices, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SG_REQUIRE(p != nullptr, "no device address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
 }  // namespace sg
 
 using namespace sg;
@@ -779,6 +805,30 @@ int sg_precond_apply(const sg_op* op, const sg_ras* ras, const sg_amg* amg, doub
         }
         precond_apply(kron_op(op), ras, amg, omega, R, Z, reinterpret_cast<char*>(ws),
                       as_stream(stream));
+        return SG_OK;
+    });
+}
+
+int sg_precond_apply_noalloc(const sg_op* op, const sg_ras* ras, const sg_amg* amg,
+                             double omega, const double* R, double* Z, void* stream) {
+    return guarded([&]() -> int {
+        check_set(op, ras, amg);
+        SG_REQUIRE(R && Z && R != Z, "R, Z must be distinct non-null");
+        SG_REQUIRE(ras != nullptr, "ras is NULL");
+        char* ws = nullptr;
+        if (amg) {
+            const size_t need = precond_ws(op, amg);
+            if (need > (size_t)SG_NOALLOC_SCRATCH_BYTES)
+                SG_THROW(SG_ERR_WORKSPACE,
+                         "sg_precond_apply_noalloc needs %zu bytes of scratch, the static "
+                         "scratch holds %zu (use sg_precond_apply with a workspace)",
+                         need, (size_t)SG_NOALLOC_SCRATCH_BYTES);
+            ws = scratch_ptr();
+        }
+        // every scratch entry the cycle reads is written earlier in the same
+        // call (t = r - A z1, r_c = Z^T t, e_c = coarse solve), so nothing left
+        // by an earlier call is read and nothing needs clearing
+        precond_apply(kron_op(op), ras, amg, omega, R, Z, ws, as_stream(stream));
         return SG_OK;
     });
 }
