@@ -44,7 +44,8 @@ MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 1>", 261121, 35): 331
                     ("kron_matvec_split_kernel<4, 2, 3, 5, 2>", 261121, 35): 335.9e6,
                     ("kron_matvec_split_kernel<4, 2, 3, 5, 4>", 261121, 35): 351.7e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
-                   "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel"}
+                   "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel",
+                   "grouped": "kron_matvec_group_kernel"}
 
 
 def log(msg: str) -> None:
@@ -56,6 +57,14 @@ def matvec_bytes(n: int, nnz: int, L: int, P: int) -> int:
     index and row pointer of every stored non-zero, X read once, Y written
     once."""
     return L * nnz * 8 + nnz * 4 + (n + 1) * 4 + 2 * n * P * 8
+
+
+def matvec_mf_bytes(n: int, P: int, M: int, n_tri: int, uniform: bool, S: int) -> int:
+    """Algorithmic bytes of the matrix-free apply: X read and Y written once,
+    each element's fields (c0, g_1..g_M) read once, its six local stiffness
+    entries unless the lattice is uniform, and a 16-bit staging index per
+    stencil direction of every row."""
+    return 2 * n * P * 8 + n_tri * (M + 1) * 8 + (0 if uniform else n_tri * 6 * 8) + n * S * 2
 
 
 def matvec_flops(n: int, nnz: int, L: int, P: int, T: int) -> int:
@@ -178,52 +187,53 @@ def amg_only(pr, prec: str, launches: int, torch, g=None) -> dict:
             g.close()
 
 
-def stochastic_sweep(args, torch) -> dict:
+def stochastic_sweep(args, torch, shapes=None, nc=None) -> dict:
     """Iterations and time against the number of random variables M and the
     output order p on one mesh (the paper's weak scaling in the stochastic
     dimensions): config 1's field (sigma 0.5, l 0.2), input order
-    min(2, p), N_c = args.sweep_nc, 8 x 8 subdomains with overlap 2, the
-    two-level preconditioner in FP64 and BF16, FGMRES(50) to 1e-8, for every
-    (M, p) with M in 2..6, p in 1..4 and P <= 128."""
+    min(2, p), N_c = nc (default args.sweep_nc), 8 x 8 subdomains with
+    overlap 2, the two-level preconditioner in FP64 and BF16, FGMRES(50) to
+    1e-8, for every (M, p) of `shapes` (default: M in 2..6, p in 1..4 with
+    P <= 128)."""
     from math import comb
     from paper_2310_14649_amd import binding as B
     from paper_2310_14649_amd.inputs import make_problem
     from paper_2310_14649_amd.solver import GpuSG
+    nc = args.sweep_nc if nc is None else nc
+    if shapes is None:
+        shapes = [(M, p) for M in range(2, 7) for p in range(1, 5) if comb(M + p, p) <= 128]
     rows = []
-    for M in range(2, 7):
-        for p in range(1, 5):
-            P = comb(M + p, p)
-            if P > 128:
+    for M, p in shapes:
+        P = comb(M + p, p)
+        pr = make_problem("c1", nc=nc, M=M, p=p, sub=(8, 8))
+        row = dict(M=M, p=p, P=P, L_in=comb(M + min(2, p), min(2, p)),
+                   unknowns=pr.mesh.n * P)
+        for prec in ("fp64", "bf16"):
+            try:
+                g = GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local=args.local)
+            except B.SgError as e:          # a shape outside a compiled limit
+                row[prec] = dict(error=str(e))
                 continue
-            pr = make_problem("c1", nc=args.sweep_nc, M=M, p=p, sub=(8, 8))
-            row = dict(M=M, p=p, P=P, L_in=comb(M + min(2, p), min(2, p)),
-                       unknowns=pr.mesh.n * P)
-            for prec in ("fp64", "bf16"):
-                try:
-                    g = GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local=args.local)
-                except B.SgError as e:          # a shape outside a compiled limit
-                    row[prec] = dict(error=str(e))
-                    continue
-                with g:
-                    rho, omega = g.damping()
-                    g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True,
-                                      ortho="cgs")
-                    torch.cuda.synchronize()
-                    ms = (time.perf_counter() - t0) * 1e3
-                    row[prec] = dict(its=info["iterations"], ms=round(ms, 3),
-                                     us_per_it=round(ms * 1e3 / max(info["iterations"], 1), 1),
-                                     relres=info["true_relres"],
-                                     ras_path=B.ras_path_info(g.ras)[2])
-                    row["matvec_kernel"] = B.sg_matvec_kernel(g.op)
-            log(f"[bench] sweep M={M} p={p} P={P}: " + ", ".join(
-                f"{k} " + (f"{row[k]['its']} its {row[k]['ms']:.1f} ms" if "its" in row[k]
-                           else row[k]["error"]) for k in ("fp64", "bf16"))
-                + f" ({row.get('matvec_kernel', '?')} matvec)")
-            rows.append(row)
-    return {"sweep": True, "nc": args.sweep_nc, "local_solves": args.local, "rows": rows}
+            with g:
+                rho, omega = g.damping()
+                g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True,
+                                  ortho="cgs")
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                row[prec] = dict(its=info["iterations"], ms=round(ms, 3),
+                                 us_per_it=round(ms * 1e3 / max(info["iterations"], 1), 1),
+                                 relres=info["true_relres"],
+                                 ras_path=B.ras_path_info(g.ras)[2])
+                row["matvec_kernel"] = B.sg_matvec_kernel(g.op)
+        log(f"[bench] sweep M={M} p={p} P={P}: " + ", ".join(
+            f"{k} " + (f"{row[k]['its']} its {row[k]['ms']:.1f} ms" if "its" in row[k]
+                       else row[k]["error"]) for k in ("fp64", "bf16"))
+            + f" ({row.get('matvec_kernel', '?')} matvec)")
+        rows.append(row)
+    return {"sweep": True, "nc": nc, "local_solves": args.local, "rows": rows}
 
 
 def _timed_solve(g, pr, omega, torch, graph=True):
@@ -295,11 +305,23 @@ def coarse_study(args, torch) -> dict:
             "ratio_nc": args.ratio_nc, "ratio": ratio}
 
 
-def cpu_baseline(pr, its_gpu: int, sample_its: int, local: str = "mean"):
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, its_gpu: int, sample_its: int, local: str = "mean", omega: float = 0.5):
     """The oracle (plain NumPy/SciPy FP64) on the host: setup, then
     ``sample_its`` FGMRES iterations with the same preconditioner definition
-    (mean-based or Kronecker local solves), scaled to the iteration count of
-    the GPU FP64 solve."""
+    (mean-based or Kronecker local solves, the GPU solve's damping omega),
+    scaled to the iteration count of the GPU FP64 solve."""
     from threadpoolctl import threadpool_info
 
     from oracle import krylov, system
@@ -307,7 +329,7 @@ def cpu_baseline(pr, its_gpu: int, sample_its: int, local: str = "mean"):
     m = pr.mesh
     t0 = time.perf_counter()
     S = system.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p)
-    B2, subs, *_ = system.two_level(S, pr.owner, pr.n_sub, pr.overlap, "amg", omega=0.5)
+    B2, subs, *_ = system.two_level(S, pr.owner, pr.n_sub, pr.overlap, "amg", omega=omega)
     if local == "kron":
         Gt = oras.kron_factor(S.K, S.G)
         B2.M = lambda R: oras.ras_apply_kron(subs, R, Gt)  # noqa: E731
@@ -336,6 +358,79 @@ def workload(pr, n: int, P: int, mixed: str, local: str = "mean") -> str:
             f"{'Kronecker K0 x Gt' if local == 'kron' else 'mean-based K0 x G0'} local solves "
             f"+ SA-AMG Nicolaides coarse, "
             f"FGMRES({pr.restart}) to {pr.rtol:g}, preconditioner {mixed}")
+
+
+def config_faithful(pr, args, torch) -> dict:
+    """Configs 1 and 2 as they are stated: mean-based local solves
+    K_0 (x) G_0 and modified Gram-Schmidt, the FP64 preconditioner against
+    the BF16 one (FP32 too), each RAS path autotuned."""
+    from paper_2310_14649_amd.solver import GpuSG
+    out = {"local_solves": "mean", "ortho": "mgs"}
+    ref = None
+    for prec in ("fp64", "bf16", "fp32"):
+        with GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local="mean") as g:
+            rho, omega = g.damping()
+            g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="mgs")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="mgs")
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row = dict(ms=round(ms, 3), iterations=info["iterations"],
+                       relres=info["true_relres"], omega=round(omega, 4))
+            if ref is None:
+                ref = x.clone()
+            else:
+                row["rel_diff_vs_fp64"] = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+            out[prec] = row
+            log(f"[bench] config-faithful (mean local, MGS) {prec}: {ms:.1f} ms, "
+                f"{info['iterations']} its")
+    out["speedup_bf16_vs_fp64"] = round(out["fp64"]["ms"] / out["bf16"]["ms"], 3)
+    return out
+
+
+def bench_config3(args, torch) -> dict:
+    """Config 3: the jittered 384 x 384 mesh, M = 6, p = 3 (P = 84, 12.3M
+    unknowns), 192 graph-partitioned subdomains of uneven size, FGMRES(50)
+    to 1e-8 with graph-captured Arnoldi steps and autotuned RAS paths, in
+    FP64 and with the BF16 preconditioner; and its SG matvec (grouped
+    kernel) after a cache flush against its algorithmic bytes."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.solver import GpuSG
+    t0 = time.perf_counter()
+    pr = make_problem("c3")
+    out = {"workload": workload(pr, pr.mesh.n, 84, "bf16", args.local),
+           "generate_s": round(time.perf_counter() - t0, 2)}
+    ref = None
+    for prec in ("fp64", "bf16"):
+        t0 = time.perf_counter()
+        with GpuSG(pr, prec=prec, coarse="amg", ras_path="auto", local=args.local) as g:
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            rho, omega = g.damping()
+            ms, info = _timed_solve(g, pr, omega, torch)
+            row = dict(ms=round(ms, 3), iterations=info["iterations"],
+                       relres=info["true_relres"], setup_s=round(setup, 2),
+                       ras_path=B.ras_path_info(g.ras)[2], omega=round(omega, 4))
+            x = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")[0]
+            if ref is None:
+                ref = x.clone()
+                n, P, L, nnz = g.n, g.P, g.L, g.nnz
+                mv_ms, mv_med = time_matvec(g, 20, torch)
+                b = matvec_bytes(n, nnz, L, P)
+                out["matvec"] = dict(kernel=B.sg_matvec_kernel(g.op), us=round(mv_ms * 1e3, 2),
+                                     bytes=b, GBps=round(b / (mv_ms * 1e-3) / 1e9, 1),
+                                     frac_hbm_peak=round(b / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+            else:
+                row["rel_diff_vs_fp64"] = float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+            out[prec] = row
+            log(f"[bench] config 3 {prec}: {ms:.1f} ms, {info['iterations']} its")
+    return out
+
+
+SWEEP_SHAPES = [(2, 1), (4, 1), (2, 2), (4, 2), (6, 2), (3, 3), (4, 3), (2, 4), (4, 4)]
 
 
 def bench_newton(args, torch):
@@ -446,6 +541,8 @@ def main() -> int:
     ap.add_argument("--mv-tiles", type=int, default=0, choices=[0, 1, 2, 4],
                     help="with --matvec-only: 64-row tiles per work-group of the staged "
                          "matvec (0 keeps the library default)")
+    ap.add_argument("--matrix-free", action="store_true",
+                    help="with --matvec-only: time the matrix-free apply")
     ap.add_argument("--matvec-only", action="store_true",
                     help="time only the SG matvec (for counter collection) and print its figures")
     ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
@@ -471,10 +568,16 @@ def main() -> int:
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
-    ap.add_argument("--learned-draws", type=int, default=256,
+    ap.add_argument("--faithful", type=int, default=1,
+                    help="also time configs 1/2 as stated (mean-based local solves, MGS)")
+    ap.add_argument("--c3", type=int, default=1, help="also time config 3 (P = 84, jittered)")
+    ap.add_argument("--small-sweep", type=int, default=1,
+                    help="also run a few (M, p) shapes of the stochastic sweep")
+    ap.add_argument("--small-sweep-nc", type=int, default=128)
+    ap.add_argument("--learned-draws", type=int, default=512,
                     help="training solves for the learned Newton guess (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=1500)
-    ap.add_argument("--learned-heldout", type=int, default=8)
+    ap.add_argument("--learned-heldout", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -505,11 +608,14 @@ def main() -> int:
         return 0
     if args.matvec_only:
         g = GpuSG(pr, prec="fp64", coarse="none")
+        if args.matrix_free:
+            B.sg_matvec_matrix_free(g.op, True)
         if args.mv_tiles:
             B.sg_matvec_select(g.op, args.mv_tiles)
         n, P, L, nnz = g.n, g.P, g.L, g.nnz
         mv_mean_ms, mv_med_ms = time_matvec(g, args.mv_launches, torch)
-        b = matvec_bytes(n, nnz, L, P)
+        b = (matvec_mf_bytes(n, P, pr.M, pr.mesh.n_tri, not pr.mesh.jittered, 5)
+             if args.matrix_free else matvec_bytes(n, nnz, L, P))
         print(json.dumps({"matvec_only": True, "config": args.config,
                           "kernel": B.sg_matvec_kernel(g.op), "tiles": B.sg_matvec_tiles(g.op),
                           "us": round(mv_mean_ms * 1e3, 2),
@@ -586,6 +692,36 @@ def main() -> int:
     mv_bytes = matvec_bytes(n, nnz, L, P)
     mv_gbs = mv_bytes / (mv_mean_ms * 1e-3) / 1e9
     log(f"[bench] matvec: {mv_mean_ms * 1e3:.1f} us avg, {mv_gbs:.0f} GB/s algorithmic")
+    # the matrix-free apply of the same operator (K values formed per row from
+    # the element fields), timed the same way against its own bytes
+    mv_mf = None
+    try:
+        B.sg_matvec_matrix_free(g64.op, True)
+        mf_tiles = {}
+        for tiles in (1, 2, 4):
+            try:
+                B.sg_matvec_select(g64.op, tiles)
+            except B.SgError:
+                continue
+            mf_tiles[tiles] = time_matvec(g64, 20, torch)[0]
+        best = min(mf_tiles, key=mf_tiles.get)
+        B.sg_matvec_select(g64.op, best)
+        mf_ms, mf_med = time_matvec(g64, args.mv_launches, torch)
+        mf_b = matvec_mf_bytes(n, P, pr.M, pr.mesh.n_tri, not pr.mesh.jittered, 5)
+        mv_mf = {"us": round(mf_ms * 1e3, 2), "median_us": round(mf_med * 1e3, 2),
+                 "tiles_per_group": best,
+                 "us_by_tiles": {k: round(v * 1e3, 2) for k, v in mf_tiles.items()},
+                 "bytes": mf_b, "GBps": round(mf_b / (mf_ms * 1e-3) / 1e9, 1),
+                 "frac_hbm_peak": round(mf_b / (mf_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 }
+        mv_mf["speedup_vs_stored"] = round(mv_mean_ms / mf_ms, 3)
+        log(f"[bench] matrix-free matvec: {mf_ms * 1e3:.1f} us ({best} tiles), "
+            f"{mv_mf['GBps']:.0f} GB/s of its {mf_b / 1e6:.0f} MB")
+    except B.SgError as e:
+        mv_mf = {"error": str(e)}
+    finally:
+        B.sg_matvec_matrix_free(g64.op, False)
+        B.sg_matvec_select(g64.op, mv_tiles)
     # the two preconditioner parts alone, on the mixed-precision solver
     parts = {}
     if args.parts:
@@ -596,9 +732,12 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        c = cpu_baseline(pr, results["fp64"]["iterations"], args.cpu_sample_its, args.local)
+        c = cpu_baseline(pr, results["fp64"]["iterations"], args.cpu_sample_its, args.local,
+                         omega)
         cpu = {"value": c["est_solve_ms"], "unit": "ms", "cores": c["threads"], "kind": "oracle",
+               "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
                "sample": f"{args.cpu_sample_its} oracle FGMRES(50) iterations of this workload "
+                         f"(omega {omega:.4f} as on the GPU) "
                          f"(FP64, same two-grid preconditioner, setup {c['setup_s']:.1f} s "
                          f"excluded) at {c['per_it_s']:.2f} s/iteration, scaled to the "
                          f"{results['fp64']['iterations']} iterations of the GPU FP64 solve; "
@@ -606,6 +745,10 @@ def main() -> int:
                          f"({mv_bytes / c['matvec_s'] / 1e9:.2f} GB/s, scipy.sparse single-threaded)"}
         log(f"[bench] cpu oracle: {c['per_it_s']:.2f} s/it")
 
+    faithful = config_faithful(pr, args, torch) if args.faithful else None
+    c3 = bench_config3(args, torch) if args.c3 else None
+    sweep = (stochastic_sweep(args, torch, SWEEP_SHAPES, nc=args.small_sweep_nc)
+             if args.small_sweep else None)
     newton = bench_newton(args, torch) if args.newton else None
 
     mixed = results[args.mixed]
@@ -620,7 +763,7 @@ def main() -> int:
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": f"f64 outer / {args.mixed} preconditioner",
         "data": "synthetic",
         "config": {"workload": workload(pr, n, P, args.mixed, args.local),
                    "n": n, "P": P, "L_in": L, "nnz": nnz, "triples": T, "subdomains": pr.n_sub,
@@ -632,6 +775,7 @@ def main() -> int:
                    "tiles_per_group": mv_tiles, "autotune_ms_1_2_4_tiles": g64.mv_ms,
                    "GBps": round(mv_gbs, 1), "frac_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4),
                    "bytes": mv_bytes, "flops": matvec_flops(n, nnz, L, P, T)},
+        "matvec_matrix_free": mv_mf,
         "roofline": {"bound": "hbm", "kernel": mv_kernel, "achieved": round(mv_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
@@ -642,6 +786,9 @@ def main() -> int:
         "local_solves": args.local,
         "omega": omega,
         "cpu_baseline": cpu,
+        "config_faithful_mean_mgs": faithful,
+        "config3": c3,
+        "stochastic_sweep": sweep,
         "newton_c4": newton,
     }
     for g in solvers.values():

@@ -142,8 +142,24 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * fixed basis, M = 6, p_in = 2, p = 3: input terms and output modes split
  * between the waves of a 64-row tile, neighbour rows staged in LDS).
  * Host call. */
-enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3, SG_MV_GROUPED = 4 };
+enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3, SG_MV_GROUPED = 4,
+       SG_MV_MATRIX_FREE = 5 };
 int sg_matvec_kernel(const sg_op* op, int* kind);
+/* sg_matvec_matrix_free -- apply the operator without reading its stored
+ * values (the matrix-free approach the paper names as future work, Sec. 5):
+ * each row forms its K_i[a, b] from the six elements around it, with the
+ * input coefficients c_i(T) = c0(T) prod_m g_m(T)^alpha_m / alpha_m!
+ * regenerated from the element's fields (Eq. inputlogn) and the element's
+ * local stiffness |T| grad phi_a . grad phi_b (two matrices for a uniform
+ * lattice, else one per element), then contracts as the staged kernel does.
+ * Needs a mesh that is the structured N x N lattice of "/"-cut squares
+ * (vertices may be moved) in the lattice numbering (element 2(jN+i) =
+ * (v(i,j), v(i+1,j), v(i+1,j+1)), 2(jN+i)+1 = (v(i,j), v(i+1,j+1), v(i,j+1)),
+ * v(i,j) = j(N+1)+i, unknowns numbered x-fastest), a basis with the staged
+ * kernel (SG_MV_STAGED) and input order <= 2; else SG_ERR_UNSUPPORTED.
+ * enable = 0 returns to the stored values.  Results equal the stored-value
+ * apply up to rounding.  Synchronous; drops captured graphs that use the op. */
+int sg_matvec_matrix_free(sg_op* op, int enable, void* stream);
 /* Work-group shape of the staged kernel: 1, 2 or 4 tiles of 64 rows per
  * work-group (2 after assembly when it fits).  sg_matvec_autotune times
  * `reps` launches of every shape that fits (HIP events on `stream`, on an
@@ -529,6 +545,17 @@ int64_t nn_param_count(const sg_nn* nn);
 int nn_set_params(sg_nn* nn, const float* params);
 int nn_get_params(const sg_nn* nn, float* params, float* grads);
 int nn_set_output_map(sg_nn* nn, const float* env, const float* oscale);
+/* nn_fit_output_map: the output map from data, on the device: env = shape /
+ * max(shape) (shape: device FP64 [H*W], e.g. the solution of the problem with
+ * unit coefficient, which vanishes where every chaos mode does) and
+ * oscale[k] = max(RMS over the B samples and all pixels of T[.., k], 1e-30) /
+ * RMS(env) (T: device FP64 [B,H,W,c_L], training targets).  Synchronous. */
+int nn_fit_output_map(sg_nn* nn, const double* shape, const double* T, int B, void* stream);
+/* nn_input_fields: the network's input channels at npts points (device FP64):
+ * X[p] = [c0, g_1 .. g_M] with c0 = exp(g0 + |g|^2 / 2), the mean of the
+ * log-normal coefficient (Eq. inputlogn); g0 [npts], g [M][npts] (row m
+ * contiguous), X [npts][M+1].  M <= 16.  Asynchronous. */
+int nn_input_fields(int npts, int M, const double* g0, const double* g, double* X, void* stream);
 int nn_forward(sg_nn* nn, const double* X, int B, double* U, void* stream);
 int nn_loss_grad(sg_nn* nn, const double* X, const double* T, int B, double* loss, void* stream);
 int nn_adam_step(sg_nn* nn, float lr, float beta1, float beta2, float eps, void* stream);

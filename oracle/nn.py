@@ -135,3 +135,22 @@ def unflatten(vec: np.ndarray, sizes: List[int]):
     if q != vec.size:
         raise ValueError("parameter vector size mismatch")
     return out
+
+
+def input_channels(g0: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """The network's input channels at npts points: [c0, g_1 .. g_M] with c0
+    the mean of the log-normal coefficient (Eq. inputlogn), taken from the
+    input chaos expansion (its zero-order coefficient).  g0 [npts],
+    g [M, npts] -> [npts, M + 1]."""
+    from . import pce
+    M = g.shape[0]
+    c0 = pce.lognormal_coefficients(g0, g, np.zeros((1, M), dtype=np.int64))[0]
+    return np.concatenate([c0[:, None], g.T], axis=1)
+
+
+def output_map(shape: np.ndarray, T: np.ndarray):
+    """env = shape / max(shape); oscale[k] = max(RMS of T[..., k] over samples
+    and pixels, 1e-30) / RMS(env).  shape [H*W], T [B, H*W, c_L]."""
+    env = shape / shape.max()
+    rms_t = np.sqrt((T.reshape(-1, T.shape[-1]) ** 2).mean(axis=0))
+    return env, np.maximum(rms_t, 1e-30) / np.sqrt((env ** 2).mean())

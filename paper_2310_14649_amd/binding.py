@@ -130,6 +130,9 @@ _SIGS = {
     "nn_get_params": (C.c_int, [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "nn_set_output_map": (C.c_int, [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "nn_forward": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
+    "sg_matvec_matrix_free": (C.c_int, [_vp, C.c_int, _vp]),
+    "nn_fit_output_map": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "nn_input_fields": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "nn_loss_grad": (C.c_int, [_vp, _vp, _vp, C.c_int, _f64p, _vp]),
     "nn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     "nn_destroy": (None, [_vp]),
@@ -259,7 +262,11 @@ def sg_matvec(op, X, Y, stream=None):
     _check(lib().sg_matvec(op, _dev(X), _dev(Y), _stream(stream)))
 
 
-MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged", 4: "grouped"}
+MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged", 4: "grouped", 5: "matrix_free"}
+
+
+def sg_matvec_matrix_free(op, enable: bool = True, stream=None):
+    _check(lib().sg_matvec_matrix_free(op, 1 if enable else 0, _stream(stream)))
 
 
 def sg_matvec_kernel(op) -> str:
@@ -603,6 +610,15 @@ def nn_set_output_map(nn, env: np.ndarray, oscale: np.ndarray):
     e = np.ascontiguousarray(env, dtype=np.float32).ravel()
     o = np.ascontiguousarray(oscale, dtype=np.float32).ravel()
     _check(lib().nn_set_output_map(nn, _ptr(e, C.c_float), _ptr(o, C.c_float)))
+
+
+def nn_fit_output_map(nn, shape, T, B: int, stream=None):
+    _check(lib().nn_fit_output_map(nn, _dev(shape), _dev(T), B, _stream(stream)))
+
+
+def nn_input_fields(npts: int, M: int, g0, g, X, stream=None):
+    _check(lib().nn_input_fields(npts, M, _dev(g0), _dev(g) if M else None, _dev(X),
+                                 _stream(stream)))
 
 
 def nn_forward(nn, X, B: int, U, stream=None):

@@ -27,7 +27,8 @@ __global__ void element_kernel(int n_tri, int M, int L, const double* __restrict
                                const int32_t* __restrict__ tri, const double* __restrict__ g0,
                                const double* __restrict__ g, const int32_t* __restrict__ alpha,
                                double* __restrict__ ek, double* __restrict__ ec,
-                               double* __restrict__ earea, int* __restrict__ bad) {
+                               double* __restrict__ earea, double* __restrict__ ef,
+                               int* __restrict__ bad) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tri) return;
     int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
@@ -59,6 +60,8 @@ __global__ void element_kernel(int n_tri, int M, int L, const double* __restrict
         s2 += gm[m] * gm[m];
     }
     double c0 = exp(g0[t] + 0.5 * s2);
+    ef[(int64_t)t * (M + 1)] = c0;
+    for (int m = 0; m < M; ++m) ef[(int64_t)t * (M + 1) + 1 + m] = gm[m];
     for (int i = 0; i < L; ++i) {
         double term = c0;
         for (int m = 0; m < M; ++m) {
@@ -211,6 +214,7 @@ void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, co
     out.ek.alloc((size_t)n_tri * 9);
     out.ec.alloc((size_t)n_tri * b.L);
     out.earea.alloc(n_tri);
+    out.ef.alloc((size_t)n_tri * (b.M + 1));
     d_xy.upload(xy, (size_t)n_vert * 2, s);
     d_tri.upload(tri, (size_t)n_tri * 3, s);
     d_g0.upload(g0, n_tri, s);
@@ -220,12 +224,33 @@ void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, co
     HIP_OK(hipMemsetAsync(d_bad.p, 0, sizeof(int), s));
     element_kernel<<<(n_tri + 255) / 256, 256, 0, s>>>(n_tri, b.M, b.L, d_xy.p, d_tri.p, d_g0.p,
                                                         d_g.p, d_alpha.p, out.ek.p, out.ec.p,
-                                                        out.earea.p, d_bad.p);
+                                                        out.earea.p, out.ef.p, d_bad.p);
     HIP_LAUNCH_OK();
     int bad = 0;
     d_bad.download(&bad, 1, s);
     HIP_OK(hipStreamSynchronize(s));
     SG_REQUIRE(!bad, "degenerate or clockwise triangle");
+}
+
+int lattice_cells(int n_vert, int n_tri, const int32_t* tri, const int32_t* dof, int n) {
+    int N = 0;
+    while ((int64_t)(N + 2) * (N + 2) <= n_vert) ++N;
+    if ((int64_t)(N + 1) * (N + 1) != n_vert || N < 2) return 0;
+    if ((int64_t)n_tri != 2LL * N * N || (int64_t)n != (int64_t)(N - 1) * (N - 1)) return 0;
+    auto v = [N](int i, int j) { return j * (N + 1) + i; };
+    for (int cj = 0; cj < N; ++cj)
+        for (int ci = 0; ci < N; ++ci) {
+            const int32_t* a = tri + 6 * ((int64_t)cj * N + ci);
+            if (a[0] != v(ci, cj) || a[1] != v(ci + 1, cj) || a[2] != v(ci + 1, cj + 1) ||
+                a[3] != v(ci, cj) || a[4] != v(ci + 1, cj + 1) || a[5] != v(ci, cj + 1))
+                return 0;
+        }
+    for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i) {
+            const bool in = i > 0 && i < N && j > 0 && j < N;
+            if (dof[v(i, j)] != (in ? (j - 1) * (N - 1) + (i - 1) : -1)) return 0;
+        }
+    return N;
 }
 
 void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,
@@ -283,6 +308,33 @@ int sg_assemble(const sg_basis* b, int n_vert, const double* xy, int n_tri, cons
         load_vector(n, op->rowptr.p, op->col.p, d_cptr.p, d_cref.p, ed.earea.p, op->F.p, s);
         upload_triples(*b, op->tr, s);
         build_ell(op.get(), s);
+        // lattice meshes keep the element fields and local matrices for the
+        // matrix-free apply (sg_matvec_matrix_free)
+        op->lattice_N = lattice_cells(n_vert, n_tri, tri, dof, n);
+        if (op->lattice_N > 0) {
+            std::vector<double> ek((size_t)n_tri * 9);
+            ed.ek.download(ek.data(), ek.size(), s);
+            HIP_OK(hipStreamSynchronize(s));
+            static const int kPair[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
+            std::vector<double> ek6((size_t)n_tri * 6);
+            for (int t = 0; t < n_tri; ++t)
+                for (int q = 0; q < 6; ++q)
+                    ek6[(size_t)t * 6 + q] = ek[(size_t)t * 9 + 3 * kPair[q][0] + kPair[q][1]];
+            bool uniform = true;
+            for (int t = 2; t < n_tri && uniform; ++t)
+                for (int q = 0; q < 6; ++q)
+                    if (ek6[(size_t)t * 6 + q] != ek6[(size_t)(t & 1) * 6 + q]) {
+                        uniform = false;
+                        break;
+                    }
+            op->mf_uniform = uniform;
+            for (int q = 0; q < 6; ++q) {
+                op->mf_ekL[q] = ek6[q];
+                op->mf_ekU[q] = ek6[6 + q];
+            }
+            if (!uniform) op->mf_ek6.upload(ek6, s);
+            op->mf_ef = std::move(ed.ef);
+        }
         HIP_OK(hipStreamSynchronize(s));
         *out = op.release();
         return SG_OK;

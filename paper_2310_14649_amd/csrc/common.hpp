@@ -151,6 +151,14 @@ struct KronCsr {
     const int32_t* sruns = nullptr;    // [blocks][2*kRuns+1]
     const int16_t* sslot = nullptr;    // [tiles][S][64]
     const double* svals = nullptr;     // [tiles][S][L][64]
+    // matrix-free apply of the split kernel (lattice meshes): the K values of
+    // a row are formed from the fields of its six elements
+    bool mf = false;
+    int mf_N = 0;                      // cells per side of the lattice
+    const int16_t* sdir = nullptr;     // [tiles][S][64] staging index per stencil direction
+    const double* ef = nullptr;        // [n_tri][M+1]: c0, g_1..g_M at the centroid
+    const double* ek6 = nullptr;       // [n_tri][6] local stiffness (00,11,22,01,12,02) or null
+    double ekL[6] = {}, ekU[6] = {};   // the two element matrices of a uniform lattice
 };
 
 }  // namespace sg
@@ -183,6 +191,14 @@ struct sg_op {
     sg::DevBuf<int32_t> sruns[3];
     sg::DevBuf<int16_t> sslot[3];
     sg::DevBuf<double> svals;
+    // matrix-free apply (sg_matvec_matrix_free), for meshes that are the
+    // structured N x N lattice of "/"-cut squares (jittered or not)
+    int lattice_N = 0;                 // 0: not a lattice
+    bool mf_on = false, mf_uniform = false;
+    bool mf_fits[3] = {false, false, false};
+    sg::DevBuf<double> mf_ef, mf_ek6;
+    sg::DevBuf<int16_t> mf_sdir[3];
+    double mf_ekL[6] = {}, mf_ekU[6] = {};
     // host copies used by the setup of the preconditioner
     std::vector<int32_t> h_rowptr, h_col;
     std::vector<int64_t> h_graph_ptr;           // mesh graph (overlap growth)
@@ -197,6 +213,12 @@ struct sg_op {
         k.spec = spec; k.ell_S = ell_S; k.ell_RW = ell_RW; k.ecol = ecol.p; k.evals = evals.p;
         k.split = split; k.split_kt = 1 << split_var; k.group = group;
         k.sruns = sruns[split_var].p; k.sslot = sslot[split_var].p; k.svals = svals.p;
+        k.mf = mf_on && split >= 0;
+        if (k.mf) {
+            k.mf_N = lattice_N; k.sdir = mf_sdir[split_var].p; k.ef = mf_ef.p;
+            k.ek6 = mf_uniform ? nullptr : mf_ek6.p;
+            for (int q = 0; q < 6; ++q) { k.ekL[q] = mf_ekL[q]; k.ekU[q] = mf_ekU[q]; }
+        }
         return k;
     }
 };
@@ -243,7 +265,13 @@ struct ElementData {
     DevBuf<double> ek;      // [n_tri][3][3] |T| grad phi_a . grad phi_b
     DevBuf<double> ec;      // [n_tri][L] input PCE coefficients at the centroid
     DevBuf<double> earea;   // [n_tri]
+    DevBuf<double> ef;      // [n_tri][M+1]: c0 = exp(g0 + |g|^2/2), g_1..g_M
 };
+// Cells per side N when the mesh is the structured lattice: (N+1)^2
+// vertices v(i,j) = j(N+1) + i, element 2(jN + i) = (v(i,j), v(i+1,j),
+// v(i+1,j+1)) and 2(jN + i) + 1 = (v(i,j), v(i+1,j+1), v(i,j+1)), unknown
+// (j-1)(N-1) + (i-1) at interior vertices; 0 otherwise.
+int lattice_cells(int n_vert, int n_tri, const int32_t* tri, const int32_t* dof, int n);
 void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, const int32_t* tri,
                   const double* g0, const double* g, ElementData& out, hipStream_t s);
 void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,

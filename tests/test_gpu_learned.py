@@ -144,6 +144,37 @@ def test_forward_and_gradients_match_oracle(channels, H, W, Bn):
         B.nn_destroy(nn)
 
 
+def test_input_fields_and_output_map_match_oracle():
+    """nn_input_fields against the oracle's channels; nn_fit_output_map read
+    back through a network whose output is one everywhere (last weights
+    zero, last bias one), so that U = env (x) oscale in FP32."""
+    _cuda()
+    rng = np.random.default_rng(5)
+    H, W, M, P, Bn = 9, 7, 4, 6, 3
+    g0 = 0.1 * rng.standard_normal(H * W)
+    g = 0.5 * rng.standard_normal((M, H * W))
+    X = torch.empty((H * W, M + 1), dtype=torch.float64, device="cuda")
+    B.nn_input_fields(H * W, M, torch.from_numpy(g0).cuda(), torch.from_numpy(g).cuda(), X)
+    assert _rl2(X.cpu().numpy(), onn.input_channels(g0, g)) < 1e-15
+    channels = [M + 1, 8, P]
+    nn = B.nn_create(channels, H, W, Bn)
+    try:
+        params = onn.unflatten(np.zeros(int(B.nn_param_count(nn))), channels)
+        params[-1] = (params[-1][0], np.ones(P))
+        B.nn_set_params(nn, onn.flatten(params).astype(np.float32))
+        shape = rng.uniform(0.1, 2.0, H * W)
+        T = rng.standard_normal((Bn, H * W, P)) * np.arange(1, P + 1)
+        B.nn_fit_output_map(nn, torch.from_numpy(shape).cuda(), torch.from_numpy(T).cuda(), Bn)
+        U = torch.empty(H * W * P, dtype=torch.float64, device="cuda")
+        B.nn_forward(nn, X.view(1, H, W, M + 1), 1, U)
+        env, osc = onn.output_map(shape, T)
+        ref = env.astype(np.float32).astype(np.float64)[:, None] * \
+            osc.astype(np.float32).astype(np.float64)[None, :]
+        assert np.allclose(U.cpu().numpy().reshape(H * W, P), ref, rtol=1e-6, atol=0)
+    finally:
+        B.nn_destroy(nn)
+
+
 def test_nn_rejects_bad_arguments():
     _cuda()
     with pytest.raises(B.SgError):

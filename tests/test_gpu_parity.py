@@ -183,6 +183,66 @@ def test_matvec_matches_oracle(built, key):
     assert _rel(_to_host(Y, X.shape), S.matvec(X)) < 1e-13
 
 
+# matrix-free apply: lattice meshes whose basis has the staged kernel
+MF_KEYS = ["c0", "c1_64", "c4_ragged", "j2"]
+
+
+@pytest.mark.parametrize("key", MF_KEYS)
+def test_matrix_free_matvec_matches_oracle_and_stored(built, key):
+    """K values formed per row from the element fields (c0, g_m) and local
+    stiffness: against the oracle's stiffness matrices at 1e-13, against the
+    stored-value apply at 1e-14, for every tile shape of the staged kernel."""
+    pr, S, g = built(key)
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((pr.mesh.n, S.P))
+    ref = S.matvec(X)
+    Ys = g.new_vec()
+    B.sg_matvec(g.op, _to_dev(X), Ys)
+    stored = _to_host(Ys, X.shape)
+    tiles0 = B.sg_matvec_tiles(g.op)
+    try:
+        B.sg_matvec_matrix_free(g.op, True)
+        assert B.sg_matvec_kernel(g.op) == "matrix_free"
+        for tiles in (1, 2, 4):
+            try:
+                B.sg_matvec_select(g.op, tiles)
+            except B.SgError:
+                continue
+            Y = g.new_vec()
+            B.sg_matvec(g.op, _to_dev(X), Y)
+            Yh = _to_host(Y, X.shape)
+            assert _rel(Yh, ref) < 1e-13, tiles
+            assert _rel(Yh, stored) < 1e-14, tiles
+    finally:
+        B.sg_matvec_matrix_free(g.op, False)
+        B.sg_matvec_select(g.op, tiles0)
+    assert B.sg_matvec_kernel(g.op) == MV_KIND[key]
+
+
+@pytest.mark.parametrize("key", ["c3_40", "perm", "p1_det"])
+def test_matrix_free_unsupported(built, key):
+    """No staged kernel (P = 84, P = 1) or not the lattice numbering."""
+    pr, S, g = built(key)
+    with pytest.raises(B.SgError) as e:
+        B.sg_matvec_matrix_free(g.op, True)
+    assert e.value.code == -4
+    assert B.sg_matvec_kernel(g.op) == MV_KIND[key]
+
+
+def test_matrix_free_solve_matches_direct(built):
+    """FGMRES (graph-captured steps) with the matrix-free operator."""
+    pr, S, g = built("c4_ragged")
+    ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    try:
+        B.sg_matvec_matrix_free(g.op, True)
+        x, info = g.solve(50, 1e-12, use_graph=True)
+        assert info["converged"]
+        assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
+    finally:
+        B.sg_matvec_matrix_free(g.op, False)
+        B.sg_graph_cache_clear()
+
+
 def test_matvec_tile_shapes_autotune_and_select(built):
     """Every work-group shape of the staged kernel gives the oracle's product;
     the autotuner keeps the fastest shape; shapes are rejected where they do
@@ -627,6 +687,32 @@ def test_full_size_matvec_sampled_rows(full_c1):
     for i, Ki in enumerate(S.K):
         ref += (Ki[rows] @ X) @ S.G[i].T
     assert _rel(Yh[rows], ref) < 1e-13
+
+
+def test_full_size_matrix_free_matvec_sampled_rows(full_c1):
+    """The matrix-free apply on the 9.14M-unknown workload: sampled rows
+    against the oracle, all rows against the stored-value apply."""
+    pr, S, g = full_c1
+    rng = np.random.default_rng(25)
+    X = rng.standard_normal((pr.mesh.n, S.P))
+    Xd = _to_dev(X)
+    Ys = g.new_vec()
+    B.sg_matvec(g.op, Xd, Ys)
+    try:
+        B.sg_matvec_matrix_free(g.op, True)
+        Y = g.new_vec()
+        B.sg_matvec(g.op, Xd, Y)
+        torch.cuda.synchronize()
+        assert float((Y - Ys).abs().max() / Ys.abs().max()) < 1e-14
+        Yh = _to_host(Y, X.shape)
+        rows = np.unique(np.concatenate([rng.choice(pr.mesh.n, 2000, replace=False),
+                                         np.arange(0, 600), np.arange(pr.mesh.n - 600, pr.mesh.n)]))
+        ref = np.zeros((rows.size, S.P))
+        for i, Ki in enumerate(S.K):
+            ref += (Ki[rows] @ X) @ S.G[i].T
+        assert _rel(Yh[rows], ref) < 1e-13
+    finally:
+        B.sg_matvec_matrix_free(g.op, False)
 
 
 def test_full_size_c3_matvec_sampled_rows():

@@ -88,3 +88,31 @@ def test_flatten_roundtrip():
     back = nn.unflatten(nn.flatten(params), sizes)
     for (W, b), (W2, b2) in zip(params, back):
         assert np.array_equal(W, W2) and np.array_equal(b, b2)
+
+
+def test_input_channels_mean_is_lognormal_mean_by_quadrature():
+    """c0 = E[exp(g0 + g . xi)] for standard Gaussian xi: Gauss-Hermite."""
+    from numpy.polynomial.hermite_e import hermegauss
+    rng = np.random.default_rng(4)
+    g0 = 0.2 * rng.standard_normal(5)
+    g = 0.4 * rng.standard_normal((2, 5))
+    X = nn.input_channels(g0, g)
+    x, w = hermegauss(30)
+    w = w / w.sum()
+    for p in range(5):
+        q = sum(wa * wb * np.exp(g0[p] + g[0, p] * xa + g[1, p] * xb)
+                for xa, wa in zip(x, w) for xb, wb in zip(x, w))
+        assert X[p, 0] == pytest.approx(q, rel=1e-13)
+    assert np.array_equal(X[:, 1:], g.T)
+
+
+def test_output_map_closed_forms():
+    """Constant targets c_k give oscale_k = |c_k| / RMS(env); env peaks at 1."""
+    shape = np.array([1.0, 3.0, 2.0, 4.0])
+    T = np.empty((3, 4, 2))
+    T[..., 0] = -2.0
+    T[..., 1] = 0.5
+    env, osc = nn.output_map(shape, T)
+    assert np.allclose(env, [0.25, 0.75, 0.5, 1.0]) and env.max() == 1.0
+    rms_env = np.sqrt((0.25 ** 2 + 0.75 ** 2 + 0.5 ** 2 + 1.0) / 4)
+    assert np.allclose(osc, [2.0 / rms_env, 0.5 / rms_env], rtol=1e-15)
