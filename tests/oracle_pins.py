@@ -209,3 +209,29 @@ def newton_fixture(a1=0.3, a2=0.5):
     nl = onl.build(m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, pr.M, pr.p_in, pr.p, a2=a2, a1=a1)
     _, ijk, val, _, _ = pce.triple_products(pr.M, pr.p_in, pr.p)
     return nl, ijk, val
+
+
+# --------------------------------------------------------- geometric coarse
+def pin_prolongation(prolongation) -> bool:
+    """P e_J is the coarse hat of node J at the fine nodes: 1 - max(|X|,|Y|)
+    where X Y >= 0 (the "/" diagonal is an edge there), else 1 - |X| - |Y|,
+    clipped at 0, X, Y the offsets from the node in coarse cells."""
+    from paper_2310_14649_amd.inputs import structured_mesh
+    try:
+        for N, r in ((8, 2), (12, 4), (9, 3)):
+            P = prolongation(N, r)
+            xf = structured_mesh(N).interior_xy()
+            Nc = N // r
+            nc = (Nc - 1) ** 2
+            for J in range(nc):
+                e = np.zeros(nc)
+                e[J] = 1.0
+                ci, cj = J % (Nc - 1) + 1, J // (Nc - 1) + 1
+                X, Y = xf[:, 0] * Nc - ci, xf[:, 1] * Nc - cj
+                hat = np.where(X * Y >= 0, 1 - np.maximum(np.abs(X), np.abs(Y)),
+                               1 - np.abs(X) - np.abs(Y))
+                if not np.allclose(P @ e, np.maximum(hat, 0.0), atol=1e-14):
+                    return False
+        return True
+    except Exception:
+        return False

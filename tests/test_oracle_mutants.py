@@ -7,7 +7,7 @@ import textwrap
 
 import pytest
 
-from oracle import amg, coarse, fem, nn
+from oracle import amg, coarse, fem, geometric, nn
 from oracle import newton as onl
 
 import oracle_pins as pins
@@ -86,3 +86,17 @@ ADAM_MUTANTS = [
 def test_adam_pin_rejects(name, old, new):
     assert pins.pin_adam(nn.adam_step)
     assert not pins.pin_adam(_mutant(nn.adam_step, old, new)), name
+
+
+PROLONG_MUTANTS = [
+    ("triangles swapped", "if a >= b:", "if a <= b:"),
+    ("lower-triangle weight", "add(row, ci + 1, cj, a - b)", "add(row, ci + 1, cj, b - a)"),
+    ("upper-triangle corner", "add(row, ci, cj + 1, b - a)", "add(row, ci + 1, cj, b - a)"),
+    ("local coordinate", "a, b = (i % r) / r, (j % r) / r", "a, b = (j % r) / r, (i % r) / r"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", PROLONG_MUTANTS, ids=[m[0] for m in PROLONG_MUTANTS])
+def test_prolongation_pin_rejects(name, old, new):
+    assert pins.pin_prolongation(geometric.prolongation)
+    assert not pins.pin_prolongation(_mutant(geometric.prolongation, old, new)), name
