@@ -300,9 +300,56 @@ def coarse_study(args, torch) -> dict:
             log(f"[bench] ratio {gx}x{gx} ({row['nodes_per_coarse_node']} nodes per coarse node) "
                 f"{inner}: {row['its']} its {row['ms']:.1f} ms")
             ratio.append(row)
+    geometric = geometric_ratio_study(args, torch)
     return {"coarse_study": True, "config": args.config, "local_solves": args.local,
             "variants": variants,
-            "ratio_nc": args.ratio_nc, "ratio": ratio}
+            "ratio_nc": args.ratio_nc, "ratio": ratio, "geometric": geometric}
+
+
+def geometric_ratio_study(args, torch) -> list:
+    """The coarse-ratio study with the coarse space of a coarser lattice
+    (Eq. coarse; the ratio tables of Sec. 5): config 1's field on an
+    N = args.ratio_nc lattice, 16 x 16 fine subdomains, cell ratios r = 2, 4,
+    8, 16 (fine:coarse unknowns about 4, 16, 66, 290), the coarse problem
+    solved by FGMRES to 1e-5 (<= 100 steps) preconditioned by its own RAS
+    (8 x 8 subdomains) with its mean-based Nicolaides correction (a third
+    level), and by FGMRES to 1e-2 with its one-level RAS (the 2GV2 reading);
+    FP64 and BF16 fine-level preconditioners."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.solver import Geometric, GpuSG
+    rows = []
+    prr = make_problem("c1", nc=args.ratio_nc, sub=(16, 16))
+    for prec in ("fp64", "bf16"):
+        for r in (2, 4, 8, 16):
+            for level, rtol in (("mean", 1e-5), ("none", 1e-2)):
+                geo = Geometric(r, sub=(8, 8), overlap=1, level_coarse=level, rtol=rtol,
+                                max_its=100)
+                try:
+                    t0 = time.perf_counter()
+                    g = GpuSG(prr, prec=prec, coarse=geo, ras_path="auto", local=args.local)
+                    setup_ms = (time.perf_counter() - t0) * 1e3
+                except B.SgError as e:
+                    rows.append(dict(prec=prec, ratio=r, level_coarse=level, error=str(e)))
+                    log(f"[bench] geometric r={r}: {e}")
+                    continue
+                with g:
+                    rho, omega = g.damping()
+                    nc, nnz_c, om_c = B.amg_geometric_info(g.amg)
+                    c0, i0, _ = B.amg_inner_stats(g.amg)
+                    ms, info = _timed_solve(g, prr, omega, torch)
+                    c1, i1, _ = B.amg_inner_stats(g.amg)
+                    row = dict(prec=prec, ratio=r, unknown_ratio=round(g.n / nc, 2),
+                               coarse_nodes=nc, coarse_unknowns=nc * g.P, level_coarse=level,
+                               inner_rtol=rtol, its=info["iterations"], ms=round(ms, 3),
+                               relres=info["true_relres"], setup_ms=round(setup_ms, 1),
+                               coarse_steps_per_solve=round((i1 - i0) / max(c1 - c0, 1), 2),
+                               coarse_omega=round(om_c, 4))
+                log(f"[bench] geometric {prec} r={r} ({row['unknown_ratio']}:1) {level}: "
+                    f"{row['its']} its, {row['coarse_steps_per_solve']} coarse steps, "
+                    f"{ms:.1f} ms")
+                rows.append(row)
+    return rows
 
 
 def cpu_model() -> str:
@@ -565,6 +612,8 @@ def main() -> int:
     ap.add_argument("--coarse-study", action="store_true",
                     help="coarse-solve variants (V-cycle, 2GV3, 2GV2) and the coarse-ratio sweep")
     ap.add_argument("--ratio-nc", type=int, default=256)
+    ap.add_argument("--geometric-study", action="store_true",
+                    help="only the coarse-ratio sweep with the geometric coarse space")
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
@@ -595,6 +644,11 @@ def main() -> int:
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
     if args.sweep:
         print(json.dumps(stochastic_sweep(args, torch)))
+        return 0
+    if args.geometric_study:
+        print(json.dumps({"geometric_study": True, "ratio_nc": args.ratio_nc,
+                          "local_solves": args.local,
+                          "geometric": geometric_ratio_study(args, torch)}))
         return 0
     if args.coarse_study:
         print(json.dumps(coarse_study(args, torch)))
@@ -666,6 +720,33 @@ def main() -> int:
                                                       torch.linalg.norm(ref_x))
         log(f"[bench] solve {prec}: {ms:.2f} ms, its={info['iterations']}, "
             f"relres={info['true_relres']:.2e}")
+
+    # the solves with the matrix-free operator apply (same preconditioner)
+    mf_solves = {}
+    for prec in ("fp64", args.mixed):
+        g = solvers[prec]
+        try:
+            B.sg_matvec_matrix_free(g.op, True)
+        except B.SgError as e:
+            mf_solves = {"error": str(e)}
+            break
+        try:
+            g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph), ortho=args.ortho)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=bool(args.graph),
+                                  ortho=args.ortho)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            mf_solves[prec] = dict(ms=round(ms, 3), iterations=info["iterations"],
+                                   relres=info["true_relres"],
+                                   rel_diff_vs_fp64=float(torch.linalg.norm(x - ref_x) /
+                                                          torch.linalg.norm(ref_x)))
+            log(f"[bench] solve {prec} with the matrix-free apply: {ms:.2f} ms, "
+                f"its={info['iterations']}")
+        finally:
+            B.sg_matvec_matrix_free(g.op, False)
 
     # the same mixed solve with the other orthogonalisations, for comparison
     ortho_cmp = {}
@@ -771,6 +852,7 @@ def main() -> int:
         "solves": results,
         "speedup_mixed_vs_fp64": round(results["fp64"]["ms"] / mixed["ms"], 3),
         "mixed_other_ortho": ortho_cmp,
+        "solves_matrix_free_apply": mf_solves,
         "matvec": {"us": round(mv_mean_ms * 1e3, 2), "median_us": round(mv_med_ms * 1e3, 2),
                    "tiles_per_group": mv_tiles, "autotune_ms_1_2_4_tiles": g64.mv_ms,
                    "GBps": round(mv_gbs, 1), "frac_hbm_peak": round(mv_gbs / HBM_PEAK_GBS, 4),

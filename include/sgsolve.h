@@ -53,7 +53,9 @@ typedef enum { SG_FP64 = 0, SG_FP32 = 1, SG_BF16 = 2 } sg_prec;
 typedef enum {
     SG_COARSE_NONE = 0,        /* one-level RAS only                             */
     SG_COARSE_MEAN_EXACT = 1,  /* (C_0 (x) G_0)^{-1}: exact mean-based coarse     */
-    SG_COARSE_AMG = 2          /* one smoothed-aggregation V(1,1) cycle on A_c    */
+    SG_COARSE_AMG = 2,         /* one smoothed-aggregation V(1,1) cycle on A_c    */
+    SG_COARSE_GEOMETRIC = 3    /* coarser lattice, A_c = P_0^T A P_0, inner FGMRES */
+                               /* (amg_setup_geometric only)                     */
 } sg_coarse_kind;
 
 /* Local solves of the RAS subdomains (ras_set_local). */
@@ -294,6 +296,50 @@ int amg_inner_stats(const sg_amg* a, int64_t* calls, int64_t* its, int* last_its
 /* The coarse solve the two-grid cycle uses: amg_vcycle, or the inner GMRES
  * of amg_set_inner (then synchronous).  b_c, x_c device [n_sub*P], no alias. */
 int amg_coarse_solve(const sg_amg* a, const double* b_c, double* x_c, void* stream);
+/* ------------------------------------------------------------------------
+ * amg_setup_geometric -- the coarse space of Eq. coarse (Sec. 3) taken from
+ * a coarser triangulation, as in the fine:coarse ratio study of Sec. 5 (the
+ * ratio_deter / ratio_stoc tables): R_0^T = P_0 interpolates the P1 functions
+ * of the N/ratio x N/ratio lattice (the same "/"-cut squares) at the fine
+ * nodes, and
+ *   A_c = P_0^T A P_0 = sum_i (P_0^T K_i P_0) (x) G_i   ((N/ratio - 1)^2 * P).
+ * op must come from sg_assemble on the structured N x N lattice (jittered
+ * vertices allowed: P_0 is defined on the lattice topology), ratio >= 1
+ * dividing N with N/ratio >= 2.  Fine node (i, j) lies in coarse cell
+ * (i / r, j / r) at (a, b) = ((i mod r)/r, (j mod r)/r); its weights are
+ * (1-a, a-b, b) on the corners (0,0), (1,0), (1,1) when a >= b, else
+ * (1-b, a, b-a) on (0,0), (1,1), (0,1); boundary coarse nodes are dropped.
+ * A_c is formed on the host from op's values (exact cancellations, such as
+ * the hypotenuse pairs of a right-angled lattice, are left out of its
+ * pattern).  The coarse solve is FGMRES on A_c (Sec. 3: GMRES for the coarse
+ * grid) from x_c = 0, classical Gram-Schmidt with the conditional second
+ * pass, restart min(max_its, 64), stopped at ||b_c - A_c x_c|| <= rtol ||b_c||
+ * or after max_its steps (rtol in (0, 1), max_its 1..1000), right-
+ * preconditioned by the two-grid cycle of the coarse problem itself: RAS on
+ * owner_c [(N/ratio - 1)^2] (host; n_sub_c subdomains, `overlap` layers of
+ * coarse-lattice neighbours, local solves in `prec`) with its own damping
+ * (estimated here) and, unless level_coarse is SG_COARSE_NONE (one-level, the
+ * 2GV2 reading), the Nicolaides coarse correction of kind level_coarse
+ * (SG_COARSE_MEAN_EXACT or SG_COARSE_AMG).  The handle serves wherever an
+ * sg_amg does (sg_precond_apply, fgmres_solve, amg_coarse_solve,
+ * sg_coarse_restrict / sg_coarse_prolong_add on [(N/ratio - 1)^2 * P]
+ * coarse vectors) with any RAS of op; its coarse solve synchronises the
+ * stream (no Arnoldi-step graphs are captured with it), and
+ * amg_inner_stats counts its steps.  Synchronous.  Errors:
+ * SG_ERR_INVALID_ARG (not a lattice operator, bad ratio or arguments),
+ * and those of ras_setup / amg_setup on the coarse problem.
+ * ---------------------------------------------------------------------- */
+int amg_setup_geometric(const sg_op* op, int ratio, const int32_t* owner_c, int n_sub_c,
+                        int overlap, sg_coarse_kind level_coarse, sg_prec prec, double rtol,
+                        int max_its, sg_amg** out, void* stream);
+/* host outputs (any may be NULL): coarse unknowns (N/ratio - 1)^2, entries of
+ * the coarse pattern, and the coarse smoother's damping.  SG_ERR_INVALID_ARG
+ * for other kinds. */
+int amg_geometric_info(const sg_amg* a, int* n_c, int64_t* nnz_c, double* omega_c);
+/* The coarse operator A_c of a geometric handle (owned by it, valid until
+ * sg_destroy_amg), e.g. for sg_op_export; NULL for other kinds. */
+const sg_op* amg_geometric_op(const sg_amg* a);
+
 /* r_c = Z^T R (sum over owned nodes) and Y += Z e_c.  Asynchronous. */
 int sg_coarse_restrict(const sg_amg* a, const double* R, double* r_c, void* stream);
 int sg_coarse_prolong_add(const sg_amg* a, const double* e_c, double* Y, void* stream);

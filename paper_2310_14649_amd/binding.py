@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsgsolve.so")
 
 SG_OK, SG_NOT_CONVERGED = 0, 1
 SG_FP64, SG_FP32, SG_BF16 = 0, 1, 2
-SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG = 0, 1, 2
+SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG, SG_COARSE_GEOMETRIC = 0, 1, 2, 3
 PREC = {"fp64": SG_FP64, "fp32": SG_FP32, "bf16": SG_BF16}
 SG_ORTHO_MGS, SG_ORTHO_CGS_DGKS, SG_ORTHO_CGS = 0, 1, 2
 ORTHO = {"mgs": SG_ORTHO_MGS, "cgs2": SG_ORTHO_CGS_DGKS, "cgs": SG_ORTHO_CGS}
@@ -96,6 +96,11 @@ _SIGS = {
     "sg_destroy_ras": (None, [_vp]),
     "amg_setup": (C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(_vp), _vp]),
     "amg_info": (C.c_int, [_vp, C.POINTER(C.c_int), _i32p, _i32p]),
+    "amg_setup_geometric": (C.c_int, [_vp, C.c_int, _i32p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                      C.c_double, C.c_int, C.POINTER(_vp), _vp]),
+    "amg_geometric_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_double)]),
+    "amg_geometric_op": (_vp, [_vp]),
     "amg_vcycle": (C.c_int, [_vp, _vp, _vp, _vp]),
     "amg_set_inner": (C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
     "amg_inner_stats": (C.c_int, [_vp, _i64p, _i64p, C.POINTER(C.c_int)]),
@@ -371,6 +376,34 @@ def amg_setup(op, ras, kind: int = SG_COARSE_AMG, prec: int = SG_FP64, stream=No
     h = C.c_void_p()
     _check(lib().amg_setup(op, ras, kind, prec, C.byref(h), _stream(stream)))
     return h
+
+
+def amg_setup_geometric(op, ratio: int, owner_c, n_sub_c: int, overlap: int,
+                        level_coarse: int = SG_COARSE_MEAN_EXACT, prec: int = SG_FP64,
+                        rtol: float = 1e-5, max_its: int = 100, stream=None):
+    """Geometric coarse space of the N x N lattice operator `op` with
+    fine:coarse cell ratio `ratio`; owner_c partitions the coarse unknowns."""
+    owner_c = np.ascontiguousarray(owner_c, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().amg_setup_geometric(op, int(ratio), _ptr(owner_c, C.c_int32), int(n_sub_c),
+                                     int(overlap), int(level_coarse), int(prec), float(rtol),
+                                     int(max_its), C.byref(h), _stream(stream)))
+    return h
+
+
+def amg_geometric_info(a):
+    """(coarse unknowns, coarse pattern entries, coarse smoother damping)."""
+    n, nnz, om = C.c_int(), C.c_int64(), C.c_double()
+    _check(lib().amg_geometric_info(a, C.byref(n), C.byref(nnz), C.byref(om)))
+    return n.value, nnz.value, om.value
+
+
+def amg_geometric_op(a):
+    """The coarse operator of a geometric handle (owned by it)."""
+    h = lib().amg_geometric_op(a)
+    if not h:
+        raise SgError(-1, "not a geometric coarse space")
+    return C.c_void_p(h)
 
 
 def amg_info(a, n_sub: int):

@@ -253,6 +253,36 @@ int lattice_cells(int n_vert, int n_tri, const int32_t* tri, const int32_t* dof,
     return N;
 }
 
+sg_op* make_csr_op(const sg_basis& b, int n, const std::vector<int32_t>& rowptr,
+                   const std::vector<int32_t>& col, const std::vector<double>& vals,
+                   const std::vector<int64_t>& graph_ptr, const std::vector<int32_t>& graph_col,
+                   hipStream_t s) {
+    SG_REQUIRE((int)rowptr.size() == n + 1 && (size_t)rowptr[n] == col.size() &&
+                   vals.size() == col.size() * (size_t)b.L, "inconsistent CSR operator");
+    auto op = std::make_unique<sg_op>();
+    op->device = current_device();
+    op->n = n; op->P = b.P; op->L = b.L; op->M = b.M;
+    op->nnz = (int64_t)col.size();
+    op->max_row = 0;
+    for (int a = 0; a < n; ++a) op->max_row = std::max(op->max_row, rowptr[a + 1] - rowptr[a]);
+    op->basis = b;
+    op->h_afact = b.afact;
+    op->h_rowptr = rowptr;
+    op->h_col = col;
+    op->h_graph_ptr = graph_ptr;
+    op->h_graph_col = graph_col;
+    op->rowptr.upload(rowptr, s);
+    op->col.upload(col, s);
+    op->vals.upload(vals, s);
+    op->F.alloc(n);
+    HIP_OK(hipMemsetAsync(op->F.p, 0, (size_t)n * 8, s));
+    op->afact.upload(b.afact, s);
+    upload_triples(b, op->tr, s);
+    build_ell(op.get(), s);
+    HIP_OK(hipStreamSynchronize(s));
+    return op.release();
+}
+
 void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,
                  const int32_t* cref, const double* earea, double* F, hipStream_t s) {
     load_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, rowptr, col, cptr, cref, earea, F);

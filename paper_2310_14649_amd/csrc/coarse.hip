@@ -75,8 +75,23 @@ struct sg_amg {
     double* ipin = nullptr;                   // pinned host slot for one estimate
     mutable int64_t inner_calls = 0, inner_its = 0;
     mutable int inner_last = 0;
+    // geometric coarse space (SG_COARSE_GEOMETRIC): P_0 by fine rows (three
+    // (coarse node, weight) slots per fine node, weight 0 in unused slots),
+    // P_0^T by coarse rows, and the coarse problem's own operator, RAS,
+    // coarse correction and FGMRES workspace
+    int ratio = 0, g_restart = 0, g_max = 0;
+    double g_omega = 1.0;
+    sg::DevBuf<int32_t> gp_col, gr_ptr, gr_col;
+    sg::DevBuf<double> gp_val, gr_val;
+    sg_op* gop = nullptr;
+    sg_ras* gras = nullptr;
+    sg_amg* gamg = nullptr;
+    sg::DevBuf<char> gws;
     ~sg_amg() {
         if (ipin) (void)hipHostFree(ipin);
+        if (gamg) sg_destroy_amg(gamg);
+        if (gras) sg_destroy_ras(gras);
+        if (gop) sg_destroy_op(gop);
     }
 };
 
@@ -154,6 +169,46 @@ __global__ void prolong_add_kernel(int total, int P, const int32_t* __restrict__
     const int a = (int)((unsigned)idx / (unsigned)P);
     const int k = idx - a * P;
     Y[idx] += ec[(size_t)owner[a] * P + k];
+}
+
+// Geometric coarse space.  r_c[I, k] = sum_q w_q R[a_q, k] over the fine
+// nodes a_q of coarse row I of P_0^T (one work-group per coarse node, the
+// entries q = beg + st, beg + st + stripes, ... per stripe, stripes added in
+// order), and Y[a, k] += sum_{slots} w e_c[I, k] over the (at most three)
+// coarse nodes interpolated at fine node a.
+__global__ __launch_bounds__(256) void geo_restrict_kernel(
+    int P, const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+    const double* __restrict__ rval, const double* __restrict__ R, double* __restrict__ rc) {
+    __shared__ double red[256];
+    const int I = blockIdx.x, tid = threadIdx.x;
+    const int stripes = 256 / P;
+    const int k = tid % P, st = tid / P;
+    double acc = 0.0;
+    if (st < stripes) {
+        const int end = rptr[I + 1];
+        for (int q = rptr[I] + st; q < end; q += stripes)
+            acc = fma(rval[q], R[(size_t)rcol[q] * P + k], acc);
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < P) {
+        double t = 0.0;
+        for (int w = 0; w < stripes; ++w) t += red[w * P + tid];
+        rc[(size_t)I * P + tid] = t;
+    }
+}
+
+__global__ void geo_prolong_add_kernel(int total, int P, const int32_t* __restrict__ pcol,
+                                       const double* __restrict__ pval,
+                                       const double* __restrict__ ec, double* __restrict__ Y) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int a = (int)((unsigned)idx / (unsigned)P);
+    const int k = idx - a * P;
+    double t = Y[idx];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) t = fma(pval[3 * a + q], ec[(size_t)pcol[3 * a + q] * P + k], t);
+    Y[idx] = t;
 }
 
 // x[s, k] = sum_t C0inv[s, t] b[t, k] / alpha_k!
@@ -697,7 +752,8 @@ __global__ void inner_init_kernel(int m, double beta, double* g) {
 }
 
 bool inner_active(const sg_amg* a) {
-    return a->inner != SG_INNER_NONE && a->kind == SG_COARSE_AMG && a->lev.size() > 1;
+    return (a->inner != SG_INNER_NONE && a->kind == SG_COARSE_AMG && a->lev.size() > 1) ||
+           a->kind == SG_COARSE_GEOMETRIC;
 }
 
 void coarse_gmres(const sg_amg* a, const double* b, double* x, hipStream_t s) {
@@ -783,9 +839,34 @@ void coarse_gmres(const sg_amg* a, const double* b, double* x, hipStream_t s) {
     a->inner_its += k;
 }
 
-// The coarse solve of the kind alone: one V-cycle, or the exact mean-based solve.
+// Geometric coarse solve: FGMRES on A_c = P_0^T A P_0 from x = 0, stopped at
+// ||b - A_c x|| <= rtol ||b|| or after g_max steps, preconditioned by the
+// coarse problem's own RAS and (if any) its coarse correction.
+void geometric_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
+    HIP_OK(hipMemsetAsync(x, 0, (size_t)a->n_sub * a->P * sizeof(double), s));
+    sg_krylov_opts o{};
+    o.restart = a->g_restart;
+    o.max_it = a->g_max;
+    o.rtol = a->inner_rtol;
+    o.omega = a->g_omega;
+    o.use_graph = 0;
+    o.ortho = SG_ORTHO_CGS_DGKS;
+    sg_krylov_stats st{};
+    LinOp A;
+    A.kron = a->gop; A.n = a->n_sub; A.P = a->P;
+    (void)fgmres_core(A, a->gop, a->device, a->gras, a->gamg, b, x, &o, &st, a->gws.p, a->gws.n,
+                      s);
+    ++a->inner_calls;
+    a->inner_last = st.iterations;
+    a->inner_its += st.iterations;
+}
+
+// The coarse solve of the kind alone: one V-cycle, the exact mean-based
+// solve, or the geometric coarse problem's FGMRES.
 void coarse_solve_base(const sg_amg* a, const double* b, double* x, hipStream_t s) {
-    if (a->kind == SG_COARSE_MEAN_EXACT) {
+    if (a->kind == SG_COARSE_GEOMETRIC) {
+        geometric_solve(a, b, x, s);
+    } else if (a->kind == SG_COARSE_MEAN_EXACT) {
         int tot = a->n_sub * a->P;
         mean_exact_kernel<<<(tot + 127) / 128, 128, 0, s>>>(a->n_sub, a->P, a->c0inv.p, a->afact.p,
                                                              b, x);
@@ -796,7 +877,7 @@ void coarse_solve_base(const sg_amg* a, const double* b, double* x, hipStream_t 
 }
 
 void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
-    if (inner_active(a)) coarse_gmres(a, b, x, s);
+    if (a->kind != SG_COARSE_GEOMETRIC && inner_active(a)) coarse_gmres(a, b, x, s);
     else coarse_solve_base(a, b, x, s);
 }
 
@@ -804,6 +885,12 @@ int amg_nsub(const sg_amg* a) { return a->n_sub; }
 int amg_device(const sg_amg* a) { return a->device; }
 
 void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s) {
+    if (a->kind == SG_COARSE_GEOMETRIC) {
+        geo_restrict_kernel<<<a->n_sub, 256, 0, s>>>(a->P, a->gr_ptr.p, a->gr_col.p, a->gr_val.p,
+                                                      R, rc);
+        HIP_LAUNCH_OK();
+        return;
+    }
     restrict_partial_kernel<<<a->nslices, 256, 0, s>>>(a->P, a->nslices, a->slice_sub.p,
                                                         a->slice_beg.p, a->slice_end.p,
                                                         a->own_nodes.p, R, a->slice_part.p);
@@ -818,6 +905,12 @@ void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_
     const int64_t tot = (int64_t)a->n * a->P;
     SG_REQUIRE(tot < (int64_t)INT32_MAX, "n*P = %lld exceeds the 32-bit prolongation index",
                (long long)tot);
+    if (a->kind == SG_COARSE_GEOMETRIC) {
+        geo_prolong_add_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            (int)tot, a->P, a->gp_col.p, a->gp_val.p, ec, Y);
+        HIP_LAUNCH_OK();
+        return;
+    }
     prolong_add_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((int)tot, a->P, a->owner.p,
                                                                        ec, Y);
     HIP_LAUNCH_OK();
@@ -990,7 +1083,214 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
 
 using namespace sg;
 
+namespace sg {
+
+bool amg_is_geometric(const sg_amg* a) { return a->kind == SG_COARSE_GEOMETRIC; }
+int amg_fine_n(const sg_amg* a) { return a->n; }
+
+// Host part of the geometric coarse space on the N x N lattice with ratio r:
+// P_0 (nested P1 interpolation, boundary coarse nodes dropped), P_0^T by
+// coarse rows, and the Galerkin values C_i = P_0^T K_i P_0 with the mesh
+// graph of the coarse lattice.  Every fine element lies in one coarse
+// triangle, so the pattern of C_i is the coarse 7-point stencil; an
+// off-diagonal entry whose every term cancels to rounding residue (|C| <=
+// 1e-12 sum |contributions|, e.g. the hypotenuse pairs of a right-angled
+// lattice, exactly zero in exact arithmetic) is left out, as the assembly
+// leaves out zero-weight entries.
+struct GeoHost {
+    int Nc = 0, nc = 0;
+    std::vector<int32_t> pcol, rptr, rcol, cptr, ccol;
+    std::vector<double> pval, rval, cval;
+    std::vector<int64_t> gptr;
+    std::vector<int32_t> gcol;
+};
+
+void geometric_host(const sg_op* op, const std::vector<double>& vals, int r, GeoHost& g) {
+    const int N = op->lattice_N, L = op->L;
+    const int Nc = N / r, nf = op->n, nc = (Nc - 1) * (Nc - 1);
+    SG_REQUIRE(nf == (N - 1) * (N - 1), "operator is not the lattice's");
+    g.Nc = Nc; g.nc = nc;
+    g.pcol.assign((size_t)3 * nf, 0);
+    g.pval.assign((size_t)3 * nf, 0.0);
+    for (int j = 1; j < N; ++j)
+        for (int i = 1; i < N; ++i) {
+            const int row = (j - 1) * (N - 1) + (i - 1);
+            const int ci = i / r, cj = j / r;
+            const double a = (double)(i % r) / r, b = (double)(j % r) / r;
+            int cx[3], cy[3];
+            double w[3];
+            if (a >= b) {
+                cx[0] = ci; cy[0] = cj; w[0] = 1.0 - a;
+                cx[1] = ci + 1; cy[1] = cj; w[1] = a - b;
+                cx[2] = ci + 1; cy[2] = cj + 1; w[2] = b;
+            } else {
+                cx[0] = ci; cy[0] = cj; w[0] = 1.0 - b;
+                cx[1] = ci + 1; cy[1] = cj + 1; w[1] = a;
+                cx[2] = ci; cy[2] = cj + 1; w[2] = b - a;
+            }
+            for (int q = 0; q < 3; ++q)
+                if (w[q] != 0.0 && cx[q] > 0 && cx[q] < Nc && cy[q] > 0 && cy[q] < Nc) {
+                    g.pcol[(size_t)3 * row + q] = (cy[q] - 1) * (Nc - 1) + (cx[q] - 1);
+                    g.pval[(size_t)3 * row + q] = w[q];
+                }
+        }
+    // P_0^T by coarse rows, fine rows ascending within a row
+    g.rptr.assign(nc + 1, 0);
+    for (size_t q = 0; q < g.pval.size(); ++q)
+        if (g.pval[q] != 0.0) g.rptr[g.pcol[q] + 1]++;
+    for (int I = 0; I < nc; ++I) g.rptr[I + 1] += g.rptr[I];
+    g.rcol.resize(g.rptr[nc]);
+    g.rval.resize(g.rptr[nc]);
+    {
+        std::vector<int32_t> fill(g.rptr.begin(), g.rptr.end() - 1);
+        for (int a = 0; a < nf; ++a)
+            for (int q = 0; q < 3; ++q) {
+                const double w = g.pval[(size_t)3 * a + q];
+                if (w == 0.0) continue;
+                const int32_t at = fill[g.pcol[(size_t)3 * a + q]]++;
+                g.rcol[at] = a;
+                g.rval[at] = w;
+            }
+    }
+    // Galerkin triple product into the 7 stencil slots of every coarse row:
+    // (dx, dy) = (-1,-1), (0,-1), (-1,0), (0,0), (1,0), (0,1), (1,1), which is
+    // also increasing column order
+    static const int kDx[7] = {-1, 0, -1, 0, 1, 0, 1}, kDy[7] = {-1, -1, 0, 0, 0, 1, 1};
+    static const int kSlot[3][3] = {{0, 1, -1}, {2, 3, 4}, {-1, 5, 6}};
+    const int W = Nc - 1;
+    std::vector<double> acc((size_t)nc * 7 * L, 0.0), sab((size_t)nc * 7 * L, 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int p = 0; p < 3; ++p) {
+            const double wp = g.pval[(size_t)3 * a + p];
+            if (wp == 0.0) continue;
+            const int I = g.pcol[(size_t)3 * a + p];
+            const int Ix = I % W, Iy = I / W;
+            for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e) {
+                const int b = op->h_col[e];
+                const double* v = vals.data() + (size_t)e * L;
+                for (int q = 0; q < 3; ++q) {
+                    const double wq = g.pval[(size_t)3 * b + q];
+                    if (wq == 0.0) continue;
+                    const int J = g.pcol[(size_t)3 * b + q];
+                    const int dx = J % W - Ix, dy = J / W - Iy;
+                    SG_REQUIRE(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 &&
+                                   kSlot[dy + 1][dx + 1] >= 0,
+                               "operator couples nodes outside one coarse triangle");
+                    const size_t base = ((size_t)I * 7 + kSlot[dy + 1][dx + 1]) * L;
+                    const double w = wp * wq;
+                    for (int l = 0; l < L; ++l) {
+                        const double t = w * v[l];
+                        acc[base + l] += t;
+                        sab[base + l] += std::fabs(t);
+                    }
+                }
+            }
+        }
+    g.cptr.assign(nc + 1, 0);
+    g.gptr.assign(nc + 1, 0);
+    for (int I = 0; I < nc; ++I) {
+        const int Ix = I % W, Iy = I / W;
+        for (int sl = 0; sl < 7; ++sl) {
+            const int x = Ix + kDx[sl], y = Iy + kDy[sl];
+            if (x < 0 || x >= W || y < 0 || y >= W) continue;
+            const int J = y * W + x;
+            if (sl != 3) g.gcol.push_back(J);
+            const size_t base = ((size_t)I * 7 + sl) * L;
+            bool keep = sl == 3;
+            for (int l = 0; l < L && !keep; ++l)
+                keep = std::fabs(acc[base + l]) > 1e-12 * sab[base + l];
+            if (!keep) continue;
+            g.ccol.push_back(J);
+            g.cval.insert(g.cval.end(), acc.begin() + base, acc.begin() + base + L);
+        }
+        g.cptr[I + 1] = (int32_t)g.ccol.size();
+        g.gptr[I + 1] = (int64_t)g.gcol.size();
+    }
+}
+
+}  // namespace sg
+
 extern "C" {
+
+int amg_setup_geometric(const sg_op* op, int ratio, const int32_t* owner_c, int n_sub_c,
+                        int overlap, sg_coarse_kind level_coarse, sg_prec prec, double rtol,
+                        int max_its, sg_amg** out, void* stream) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op && owner_c && out, "null argument");
+        SG_REQUIRE(op->lattice_N > 0,
+                   "the geometric coarse space needs an operator assembled on the N x N lattice");
+        const int N = op->lattice_N;
+        SG_REQUIRE(ratio >= 1 && N % ratio == 0 && N / ratio >= 2,
+                   "ratio %d must divide N = %d and leave at least 2 coarse cells", ratio, N);
+        SG_REQUIRE(level_coarse == SG_COARSE_NONE || level_coarse == SG_COARSE_MEAN_EXACT ||
+                       level_coarse == SG_COARSE_AMG, "bad coarse kind for the coarse level");
+        SG_REQUIRE(prec == SG_FP64 || prec == SG_FP32 || prec == SG_BF16, "bad precision");
+        SG_REQUIRE(rtol > 0.0 && rtol < 1.0, "coarse rtol must be in (0, 1)");
+        SG_REQUIRE(max_its >= 1 && max_its <= 1000, "coarse max_its=%d outside [1, 1000]",
+                   max_its);
+        SG_REQUIRE(op->P <= 256, "P=%d exceeds 256 in the restriction kernel", op->P);
+        check_device(op->device);
+        hipStream_t s = as_stream(stream);
+        std::vector<double> vals((size_t)op->nnz * op->L);
+        op->vals.download(vals.data(), vals.size(), s);
+        HIP_OK(hipStreamSynchronize(s));
+        GeoHost g;
+        geometric_host(op, vals, ratio, g);
+        vals.clear();
+        vals.shrink_to_fit();
+
+        auto a = std::make_unique<sg_amg>();
+        a->device = op->device;
+        a->kind = SG_COARSE_GEOMETRIC;
+        a->prec = prec;
+        a->n = op->n; a->n_sub = g.nc; a->P = op->P; a->L = op->L;
+        a->ratio = ratio;
+        a->h_nodes = {g.nc};
+        a->h_agg0.assign(g.nc, -1);
+        a->inner_rtol = rtol;
+        a->g_max = max_its;
+        a->g_restart = std::min(max_its, 64);
+        a->gp_col.upload(g.pcol, s);
+        a->gp_val.upload(g.pval, s);
+        a->gr_ptr.upload(g.rptr, s);
+        a->gr_col.upload(g.rcol, s);
+        a->gr_val.upload(g.rval, s);
+        a->gop = make_csr_op(op->basis, g.nc, g.cptr, g.ccol, g.cval, g.gptr, g.gcol, s);
+        int rc = ras_setup(a->gop, owner_c, n_sub_c, overlap, prec, &a->gras, stream);
+        if (rc != SG_OK) SG_THROW(rc, "coarse-level RAS: %s", sg_last_error());
+        if (level_coarse != SG_COARSE_NONE) {
+            rc = amg_setup(a->gop, a->gras, level_coarse, prec, &a->gamg, stream);
+            if (rc != SG_OK) SG_THROW(rc, "coarse-level coarse solver: %s", sg_last_error());
+        }
+        a->gws.alloc(fgmres_ws_np(g.nc, op->P, a->gamg, a->g_restart));
+        LinOp A;
+        A.kron = a->gop; A.n = g.nc; A.P = op->P;
+        double rho = 0.0;
+        a->g_omega = smoother_damping_core(A, a->gras, 15, a->gws.p, a->gws.n, s, &rho);
+        HIP_OK(hipStreamSynchronize(s));
+        *out = a.release();
+        return SG_OK;
+    });
+}
+
+/* host outputs (any may be NULL): the coarse problem of a geometric coarse
+ * space: its unknowns, the entries of its pattern, its smoother damping. */
+int amg_geometric_info(const sg_amg* a, int* n_c, int64_t* nnz_c, double* omega_c) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(a != nullptr, "amg is NULL");
+        SG_REQUIRE(a->kind == SG_COARSE_GEOMETRIC, "not a geometric coarse space");
+        if (n_c) *n_c = a->n_sub;
+        if (nnz_c) *nnz_c = a->gop->nnz;
+        if (omega_c) *omega_c = a->g_omega;
+        return SG_OK;
+    });
+}
+
+/* The coarse operator of a geometric coarse space (owned by `a`; valid until
+ * sg_destroy_amg(a)), e.g. for sg_op_export. */
+const sg_op* amg_geometric_op(const sg_amg* a) {
+    return (a && a->kind == SG_COARSE_GEOMETRIC) ? a->gop : nullptr;
+}
 
 int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec prec,
               sg_amg** out, void* stream) {

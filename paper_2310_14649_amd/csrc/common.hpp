@@ -272,6 +272,13 @@ struct ElementData {
 // v(i+1,j+1)) and 2(jN + i) + 1 = (v(i,j), v(i+1,j+1), v(i,j+1)), unknown
 // (j-1)(N-1) + (i-1) at interior vertices; 0 otherwise.
 int lattice_cells(int n_vert, int n_tri, const int32_t* tri, const int32_t* dof, int n);
+// An SG operator sum_i K_i (x) G_i from a CSR pattern with L values per entry
+// (entry-major, host) and its mesh graph (for overlap growth), e.g. a
+// Galerkin coarse operator; no load vector.
+sg_op* make_csr_op(const sg_basis& b, int n, const std::vector<int32_t>& rowptr,
+                   const std::vector<int32_t>& col, const std::vector<double>& vals,
+                   const std::vector<int64_t>& graph_ptr, const std::vector<int32_t>& graph_col,
+                   hipStream_t s);
 void element_data(const sg_basis& b, int n_vert, const double* xy, int n_tri, const int32_t* tri,
                   const double* g0, const double* g, ElementData& out, hipStream_t s);
 void load_vector(int n, const int32_t* rowptr, const int32_t* col, const int64_t* cptr,
@@ -306,6 +313,8 @@ void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
 // so the Arnoldi step that contains it is not captured into a graph)
 bool inner_active(const sg_amg* a);
 int amg_nsub(const sg_amg* a);
+bool amg_is_geometric(const sg_amg* a);
+int amg_fine_n(const sg_amg* a);
 // krylov.hip: drop cached Arnoldi-step graphs that reference a handle
 void graph_cache_purge(const void* handle);
 int amg_device(const sg_amg* a);

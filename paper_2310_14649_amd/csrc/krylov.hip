@@ -780,7 +780,10 @@ static void check_set(const sg_op* op, const sg_ras* ras, const sg_amg* amg) {
     if (amg) {
         SG_REQUIRE(ras != nullptr, "a coarse solver needs the RAS smoother");
         SG_REQUIRE(amg_device(amg) == op->device, "amg on another device");
-        SG_REQUIRE(amg_nsub(amg) == ras_nsub(ras), "amg and ras disagree on subdomains");
+        if (amg_is_geometric(amg))
+            SG_REQUIRE(amg_fine_n(amg) == op->n, "amg built for another operator");
+        else
+            SG_REQUIRE(amg_nsub(amg) == ras_nsub(ras), "amg and ras disagree on subdomains");
     }
 }
 

@@ -11,22 +11,41 @@ from typing import Optional
 import numpy as np
 
 from . import binding as B
-from .inputs import Problem
+from .inputs import Problem, structured_partition
 
 COARSE = {"none": B.SG_COARSE_NONE, "mean": B.SG_COARSE_MEAN_EXACT, "amg": B.SG_COARSE_AMG}
 
 
+class Geometric:
+    """Parameters of the geometric coarse space (amg_setup_geometric): the
+    fine:coarse cell ratio, the coarse lattice's subdomains (sx, sy) and
+    overlap, the coarse level's own coarse correction ("none", "mean" or
+    "amg"), and the inner FGMRES tolerance and step limit."""
+
+    def __init__(self, ratio: int, sub=(4, 4), overlap: int = 1, level_coarse: str = "mean",
+                 rtol: float = 1e-5, max_its: int = 100):
+        self.ratio, self.sub, self.overlap = ratio, tuple(sub), overlap
+        self.level_coarse, self.rtol, self.max_its = level_coarse, rtol, max_its
+
+    def owner(self, nc: int):
+        Nc = nc // self.ratio
+        sx, sy = (min(self.sub[0], Nc - 1), min(self.sub[1], Nc - 1))
+        return structured_partition(Nc, sx, sy), sx * sy
+
+
 class GpuSG:
     """local: the subdomain solves, "mean" (K_0 (x) G_0) or "kron" (K_0 (x) Gt).
+    matrix_free: apply the operator with sg_matvec_matrix_free (lattice meshes).
     ras_path: "sweep", "dense", "dense32", "fused", or "auto" (timed by the library,
     also choosing the staged matvec's work-group shape).  tune_cache: with
     "auto", a ``TuneCache`` (or its file path) that supplies choices already
-    made for this shape and records new ones."""
+    made for this shape and records new ones.  coarse: "none", "mean", "amg"
+    (Nicolaides coarse space) or a ``Geometric`` (coarser lattice)."""
 
     def __init__(self, pr: Problem, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
                  n_sub: Optional[int] = None, stream=None, ras_path: str = "sweep",
-                 tune_cache=None, local: str = "mean"):
+                 tune_cache=None, local: str = "mean", matrix_free: bool = False):
         import torch
         self.torch = torch
         self.pr = pr
@@ -36,6 +55,8 @@ class GpuSG:
         self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
         self.op = B.sg_assemble(self.basis, m.xy, m.tri, m.dof, m.n, pr.g0, pr.g, stream=stream)
         self.n, self.P, self.L, self.nnz = B.sg_op_info(self.op)
+        if matrix_free:
+            B.sg_matvec_matrix_free(self.op, True, stream=stream)
         dev = torch.device("cuda")
         self.b = torch.empty(self.n * self.P, dtype=torch.float64, device=dev)
         B.sg_op_rhs(self.op, self.b, stream=stream)
@@ -57,7 +78,13 @@ class GpuSG:
             self._autotune(tune_cache, stream)
         elif ras_path != "sweep":
             raise ValueError(f"unknown RAS path {ras_path!r}")
-        if coarse != "none":
+        if isinstance(coarse, Geometric):
+            owner_c, nsub_c = coarse.owner(m.nc)
+            self.amg = B.amg_setup_geometric(self.op, coarse.ratio, owner_c, nsub_c,
+                                             coarse.overlap, COARSE[coarse.level_coarse],
+                                             B.PREC[prec], coarse.rtol, coarse.max_its,
+                                             stream=stream)
+        elif coarse != "none":
             self.amg = B.amg_setup(self.op, self.ras, COARSE[coarse], B.PREC[prec], stream=stream)
         self._ws = None
         self._ws_restart = None
