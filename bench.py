@@ -312,9 +312,9 @@ def geometric_ratio_study(args, torch) -> list:
     N = args.ratio_nc lattice, 16 x 16 fine subdomains, cell ratios r = 2, 4,
     8, 16 (fine:coarse unknowns about 4, 16, 66, 290), the coarse problem
     solved by FGMRES to 1e-5 (<= 100 steps) preconditioned by its own RAS
-    (8 x 8 subdomains) with its mean-based Nicolaides correction (a third
-    level), and by FGMRES to 1e-2 with its one-level RAS (the 2GV2 reading);
-    FP64 and BF16 fine-level preconditioners."""
+    (subdomains of about 16 x 16 coarse nodes) with its mean-based Nicolaides
+    correction (a third level), and by FGMRES to 1e-2 with its one-level RAS
+    (the 2GV2 reading); FP64 and BF16 fine-level preconditioners."""
     from paper_2310_14649_amd import binding as B
     from paper_2310_14649_amd.inputs import make_problem
     from paper_2310_14649_amd.solver import Geometric, GpuSG
@@ -323,7 +323,7 @@ def geometric_ratio_study(args, torch) -> list:
     for prec in ("fp64", "bf16"):
         for r in (2, 4, 8, 16):
             for level, rtol in (("mean", 1e-5), ("none", 1e-2)):
-                geo = Geometric(r, sub=(8, 8), overlap=1, level_coarse=level, rtol=rtol,
+                geo = Geometric(r, overlap=1, level_coarse=level, rtol=rtol,
                                 max_its=100)
                 try:
                     t0 = time.perf_counter()
@@ -434,6 +434,45 @@ def config_faithful(pr, args, torch) -> dict:
             log(f"[bench] config-faithful (mean local, MGS) {prec}: {ms:.1f} ms, "
                 f"{info['iterations']} its")
     out["speedup_bf16_vs_fp64"] = round(out["fp64"]["ms"] / out["bf16"]["ms"], 3)
+    return out
+
+
+def config1_geometric(pr, args, torch) -> dict:
+    """Config 1's problem with the paper's own coarse space instead of the
+    Nicolaides one: a coarser lattice (Eq. coarse) with cell ratio 16 or 32
+    (coarse lattices of 31^2 and 15^2 nodes), the coarse problem solved by
+    FGMRES to 1e-2 (<= 100 steps) with its one-level RAS (subdomains of about
+    16 x 16 coarse nodes), the fine level as in the headline solve."""
+    from paper_2310_14649_amd import binding as B
+    from paper_2310_14649_amd.solver import Geometric, GpuSG
+    out = {"coarse": "geometric", "local_solves": args.local, "ortho": args.ortho,
+           "coarse_rtol": 1e-2, "rows": []}
+    for prec in ("fp64", args.mixed):
+        for r in (16, 32):
+            geo = Geometric(r, overlap=1, level_coarse="none", rtol=1e-2, max_its=100)
+            t0 = time.perf_counter()
+            with GpuSG(pr, prec=prec, coarse=geo, ras_path="auto", local=args.local) as g:
+                setup_ms = (time.perf_counter() - t0) * 1e3
+                rho, omega = g.damping()
+                g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho=args.ortho)
+                c0, i0, _ = B.amg_inner_stats(g.amg)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True,
+                                      ortho=args.ortho)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / args.steps
+                c1, i1, _ = B.amg_inner_stats(g.amg)
+                nc = B.amg_geometric_info(g.amg)[0]
+                row = dict(prec=prec, ratio=r, coarse_unknowns=nc * g.P,
+                           unknown_ratio=round(g.n / nc, 1), ms=round(ms, 3),
+                           iterations=info["iterations"], relres=info["true_relres"],
+                           coarse_steps_per_solve=round((i1 - i0) / max(c1 - c0, 1), 2),
+                           setup_ms=round(setup_ms, 1))
+            out["rows"].append(row)
+            log(f"[bench] config 1, geometric coarse r={r} {prec}: {ms:.1f} ms, "
+                f"{info['iterations']} its, {row['coarse_steps_per_solve']} coarse steps")
     return out
 
 
@@ -617,6 +656,8 @@ def main() -> int:
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
+    ap.add_argument("--geometric", type=int, default=1,
+                    help="also time config 1 with the geometric coarse space (ratios 16, 32)")
     ap.add_argument("--faithful", type=int, default=1,
                     help="also time configs 1/2 as stated (mean-based local solves, MGS)")
     ap.add_argument("--c3", type=int, default=1, help="also time config 3 (P = 84, jittered)")
@@ -827,6 +868,7 @@ def main() -> int:
         log(f"[bench] cpu oracle: {c['per_it_s']:.2f} s/it")
 
     faithful = config_faithful(pr, args, torch) if args.faithful else None
+    geometric = config1_geometric(pr, args, torch) if args.geometric else None
     c3 = bench_config3(args, torch) if args.c3 else None
     sweep = (stochastic_sweep(args, torch, SWEEP_SHAPES, nc=args.small_sweep_nc)
              if args.small_sweep else None)
@@ -869,6 +911,7 @@ def main() -> int:
         "omega": omega,
         "cpu_baseline": cpu,
         "config_faithful_mean_mgs": faithful,
+        "config1_geometric_coarse": geometric,
         "config3": c3,
         "stochastic_sweep": sweep,
         "newton_c4": newton,

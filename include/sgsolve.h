@@ -324,8 +324,10 @@ int amg_coarse_solve(const sg_amg* a, const double* b_c, double* x_c, void* stre
  * sg_amg does (sg_precond_apply, fgmres_solve, amg_coarse_solve,
  * sg_coarse_restrict / sg_coarse_prolong_add on [(N/ratio - 1)^2 * P]
  * coarse vectors) with any RAS of op; its coarse solve synchronises the
- * stream (no Arnoldi-step graphs are captured with it), and
- * amg_inner_stats counts its steps.  Synchronous.  Errors:
+ * stream, so the Arnoldi steps of a solve that uses the handle are not
+ * captured into graphs, while the coarse FGMRES replays its own steps as
+ * graphs captured on first use; amg_inner_stats counts its steps.
+ * Synchronous.  Errors:
  * SG_ERR_INVALID_ARG (not a lattice operator, bad ratio or arguments),
  * and those of ras_setup / amg_setup on the coarse problem.
  * ---------------------------------------------------------------------- */

@@ -79,7 +79,7 @@ struct sg_amg {
     // (coarse node, weight) slots per fine node, weight 0 in unused slots),
     // P_0^T by coarse rows, and the coarse problem's own operator, RAS,
     // coarse correction and FGMRES workspace
-    int ratio = 0, g_restart = 0, g_max = 0;
+    int ratio = 0, g_restart = 0, g_max = 0, g_graph = 1;
     double g_omega = 1.0;
     sg::DevBuf<int32_t> gp_col, gr_ptr, gr_col;
     sg::DevBuf<double> gp_val, gr_val;
@@ -849,7 +849,7 @@ void geometric_solve(const sg_amg* a, const double* b, double* x, hipStream_t s)
     o.max_it = a->g_max;
     o.rtol = a->inner_rtol;
     o.omega = a->g_omega;
-    o.use_graph = 0;
+    o.use_graph = a->g_graph;
     o.ortho = SG_ORTHO_CGS_DGKS;
     sg_krylov_stats st{};
     LinOp A;
@@ -1258,6 +1258,15 @@ int amg_setup_geometric(const sg_op* op, int ratio, const int32_t* owner_c, int 
         a->gop = make_csr_op(op->basis, g.nc, g.cptr, g.ccol, g.cval, g.gptr, g.gcol, s);
         int rc = ras_setup(a->gop, owner_c, n_sub_c, overlap, prec, &a->gras, stream);
         if (rc != SG_OK) SG_THROW(rc, "coarse-level RAS: %s", sg_last_error());
+        // the coarse problem is small and its kernels latency-bound: time the
+        // RAS apply paths and the staged matvec's shapes once and keep the
+        // fastest (every path computes the same operator up to rounding)
+        rc = ras_autotune(a->gras, 5, nullptr, stream);
+        if (rc != SG_OK) SG_THROW(rc, "coarse-level RAS autotune: %s", sg_last_error());
+        double mv_ms[3];
+        rc = sg_matvec_autotune(a->gop, 10, mv_ms, stream);
+        if (rc != SG_OK && rc != SG_ERR_UNSUPPORTED)
+            SG_THROW(rc, "coarse-level matvec autotune: %s", sg_last_error());
         if (level_coarse != SG_COARSE_NONE) {
             rc = amg_setup(a->gop, a->gras, level_coarse, prec, &a->gamg, stream);
             if (rc != SG_OK) SG_THROW(rc, "coarse-level coarse solver: %s", sg_last_error());

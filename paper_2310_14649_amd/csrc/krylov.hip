@@ -355,34 +355,58 @@ void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double 
 // ------------------------------------------------------------------ graphs
 // Pinned host slots for the per-step residual estimates, two alternating,
 // each behind its own event: the copy of one step's estimate does not hold up
-// the launch of the next step.  The destructor waits for the stream, so no
-// copy still targets the slots when they are freed.
+// the launch of the next step.  The slots and events come from a per-device
+// pool and go back to it (not freed) when the solve ends, after the stream
+// has drained, so a solve nested in a preconditioner (the geometric coarse
+// solve) does not allocate pinned memory on every call.
+struct PinnedSlot {
+    double* p = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+constexpr int kMaxPoolDevices = 64;
+std::mutex g_pin_mu;
+std::vector<PinnedSlot> g_pin_pool[kMaxPoolDevices];
+
 struct PinnedEstimates {
     double* p = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipStream_t s;
-    explicit PinnedEstimates(hipStream_t st) : s(st) {
+    int dev;
+    explicit PinnedEstimates(hipStream_t st) : s(st), dev(current_device()) {
+        SG_REQUIRE(dev >= 0 && dev < kMaxPoolDevices, "device %d beyond the pinned pool", dev);
+        {
+            std::lock_guard<std::mutex> lk(g_pin_mu);
+            if (!g_pin_pool[dev].empty()) {
+                PinnedSlot sl = g_pin_pool[dev].back();
+                g_pin_pool[dev].pop_back();
+                p = sl.p;
+                ev[0] = sl.ev[0];
+                ev[1] = sl.ev[1];
+                return;
+            }
+        }
         try {
             HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&p), 4 * sizeof(double),
                                  hipHostMallocDefault));
             for (auto& e : ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         } catch (...) {
-            release();
+            for (auto& e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (p) (void)hipHostFree(p);
             throw;
         }
     }
-    ~PinnedEstimates() { release(); }
+    ~PinnedEstimates() {
+        (void)hipStreamSynchronize(s);
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        PinnedSlot sl;
+        sl.p = p;
+        sl.ev[0] = ev[0];
+        sl.ev[1] = ev[1];
+        g_pin_pool[dev].push_back(sl);
+    }
     PinnedEstimates(const PinnedEstimates&) = delete;
     PinnedEstimates& operator=(const PinnedEstimates&) = delete;
-
-  private:
-    void release() {
-        (void)hipStreamSynchronize(s);
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (p) (void)hipHostFree(p);
-        p = nullptr;
-    }
 };
 
 struct GraphKey {

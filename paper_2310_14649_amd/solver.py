@@ -22,14 +22,23 @@ class Geometric:
     overlap, the coarse level's own coarse correction ("none", "mean" or
     "amg"), and the inner FGMRES tolerance and step limit."""
 
-    def __init__(self, ratio: int, sub=(4, 4), overlap: int = 1, level_coarse: str = "mean",
-                 rtol: float = 1e-5, max_its: int = 100):
-        self.ratio, self.sub, self.overlap = ratio, tuple(sub), overlap
+    def __init__(self, ratio: int, sub=None, overlap: int = 1, level_coarse: str = "mean",
+                 rtol: float = 1e-5, max_its: int = 100, nodes_per_side: int = 16):
+        self.ratio, self.overlap = ratio, overlap
+        self.sub = None if sub is None else tuple(sub)
+        self.nodes_per_side = nodes_per_side
         self.level_coarse, self.rtol, self.max_its = level_coarse, rtol, max_its
 
     def owner(self, nc: int):
+        """Lattice partition of the coarse unknowns: `sub`, or (default)
+        subdomains of about nodes_per_side x nodes_per_side coarse nodes."""
         Nc = nc // self.ratio
-        sx, sy = (min(self.sub[0], Nc - 1), min(self.sub[1], Nc - 1))
+        if self.sub is None:
+            k = max(1, round((Nc - 1) / self.nodes_per_side))
+            sx = sy = k
+        else:
+            sx, sy = self.sub
+        sx, sy = min(sx, Nc - 1), min(sy, Nc - 1)
         return structured_partition(Nc, sx, sy), sx * sy
 
 
