@@ -81,6 +81,41 @@ const char* sg_last_error(void);
 int sg_version(void);
 
 /* ------------------------------------------------------------------------
+ * Device memory.  Every device buffer a handle holds (operators, factors,
+ * hierarchies, internal workspaces of setup, networks), and every temporary
+ * buffer of a setup call, is taken from one source, chosen process-wide:
+ *   - hipMalloc / hipFree (the default);
+ *   - the caller's functions (sg_set_allocator): alloc(bytes, device, ctx)
+ *     returns a 256-byte aligned device pointer on `device` or NULL (the
+ *     call then fails with SG_ERR_WORKSPACE); release(ptr, bytes, device,
+ *     ctx) takes it back when the handle is destroyed or the temporary
+ *     dropped.  A stream-ordered allocator (e.g. a framework's caching
+ *     allocator) must order the release after the library's work: destroy
+ *     handles only after their work has finished;
+ *   - a caller-owned arena (sg_set_arena): base (256-byte aligned device
+ *     memory of the current device) and bytes; buffers are cut from it in
+ *     order and never reused until sg_arena_reset (which needs every buffer
+ *     cut from it released, i.e. the handles destroyed).  An allocation
+ *     beyond the arena fails with SG_ERR_WORKSPACE and the setup call
+ *     releases what it had taken.
+ * The bytes a sequence of setup calls needs are found by running it once
+ * and reading the peak (sg_memory_stats: live bytes held by the library,
+ * their peak since sg_memory_reset_peak, and the bytes cut from the arena).
+ * A buffer goes back to the source it came from even if the source changed
+ * meanwhile.  sg_set_allocator(NULL, NULL, NULL) restores hipMalloc and
+ * sg_set_arena(NULL, 0) leaves arena mode.  Not to be called while another
+ * thread is inside the library.  Pinned host memory (a few residual
+ * estimates) still comes from hipHostMalloc.
+ * ---------------------------------------------------------------------- */
+typedef void* (*sg_device_alloc_fn)(size_t bytes, int device, void* ctx);
+typedef void (*sg_device_free_fn)(void* ptr, size_t bytes, int device, void* ctx);
+int sg_set_allocator(sg_device_alloc_fn alloc, sg_device_free_fn release, void* ctx);
+int sg_set_arena(void* base, size_t bytes);
+int sg_arena_reset(void);
+int sg_memory_stats(int64_t* live_bytes, int64_t* peak_bytes, int64_t* arena_used);
+int sg_memory_reset_peak(void);
+
+/* ------------------------------------------------------------------------
  * sg_build_triples -- Hermite chaos basis and the triple-product tensor
  * m_ijk = <Psi_i Psi_j Psi_k> of Eq. Galerkin_L_exp, keeping only non-zero
  * entries (Sec. 2.1: only the non-zero multiplication-tensor entries are

@@ -68,6 +68,12 @@ class NewtonStats(C.Structure):
 _SIGS = {
     "sg_last_error": (C.c_char_p, []),
     "sg_version": (C.c_int, []),
+    "sg_set_allocator": (C.c_int, [_vp, _vp, _vp]),
+    "sg_set_arena": (C.c_int, [_vp, C.c_size_t]),
+    "sg_arena_reset": (C.c_int, []),
+    "sg_memory_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]),
+    "sg_memory_reset_peak": (C.c_int, []),
     "sg_build_triples": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(_vp)]),
     "sg_basis_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "sg_basis_export": (C.c_int, [_vp, _i32p, _i32p, _f64p]),
@@ -168,6 +174,72 @@ def lib() -> C.CDLL:
 
 def exported_symbols():
     return list(_SIGS)
+
+
+# ----------------------------------------------------------------- memory
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+_hooks = None          # the installed callbacks (kept alive while installed)
+
+
+def memory_stats():
+    """(live bytes the library holds, their peak, bytes cut from the arena)."""
+    live, peak, used = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().sg_memory_stats(C.byref(live), C.byref(peak), C.byref(used)))
+    return live.value, peak.value, used.value
+
+
+def memory_reset_peak():
+    _check(lib().sg_memory_reset_peak())
+
+
+def use_torch_allocator(enable: bool = True):
+    """Take the library's device memory from torch's caching allocator
+    (torch.cuda.caching_allocator_alloc / _delete on the current stream), or
+    go back to hipMalloc."""
+    global _hooks
+    if not enable:
+        _check(lib().sg_set_allocator(None, None, None))
+        _hooks = None
+        return
+    import torch
+
+    def _alloc(nbytes, device, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, nbytes, device, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().sg_set_allocator(C.cast(hooks[0], _vp), C.cast(hooks[1], _vp), None))
+    _hooks = hooks
+
+
+class Arena:
+    """Context manager: the library cuts its device memory from `buf` (a
+    device tensor, caller-owned) while active; on exit arena mode ends (the
+    handles made inside keep their memory, which stays valid as long as buf
+    lives)."""
+
+    def __init__(self, buf):
+        self.buf = buf
+
+    def __enter__(self):
+        nbytes = self.buf.numel() * self.buf.element_size()
+        _check(lib().sg_set_arena(C.c_void_p(self.buf.data_ptr()), nbytes))
+        return self
+
+    def used(self) -> int:
+        return memory_stats()[2]
+
+    def reset(self):
+        _check(lib().sg_arena_reset())
+
+    def __exit__(self, *exc):
+        lib().sg_set_arena(None, 0)
 
 
 def _check(rc: int) -> int:

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgsolve.so")
-SOURCES = ["triples.hip", "assemble.hip", "matvec.hip", "ras.hip", "coarse.hip", "krylov.hip",
+SOURCES = ["memory.hip", "triples.hip", "assemble.hip", "matvec.hip", "ras.hip", "coarse.hip", "krylov.hip",
            "nl.hip", "nn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "-fconstexpr-steps=100000000", "--offload-arch=gfx950",

@@ -62,6 +62,11 @@ int guarded(F&& body) {
     }
 }
 
+// memory.hip: every device buffer of the library (hipMalloc, the caller's
+// allocator or the caller's arena; see sg_set_allocator / sg_set_arena)
+void* device_alloc(size_t bytes);
+void device_free(void* p);
+
 // Owning device allocation.
 template <class T>
 struct DevBuf {
@@ -80,10 +85,10 @@ struct DevBuf {
     void alloc(size_t count) {
         release();
         n = count;
-        if (count) HIP_OK(hipMalloc(&p, count * sizeof(T)));
+        if (count) p = static_cast<T*>(device_alloc(count * sizeof(T)));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) device_free(p);
         p = nullptr;
         n = 0;
     }

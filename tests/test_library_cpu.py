@@ -14,8 +14,9 @@ HEADER = os.path.join(ROOT, "include", "sgsolve.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
-                       text, flags=re.M)
+    # function declarations (typedefs of function pointers are not entry points)
+    names = re.findall(r"^(?!\s*typedef)\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*"
+                       r"([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
