@@ -216,11 +216,11 @@ def stochastic_sweep(args, torch, shapes=None, nc=None) -> dict:
                 continue
             with g:
                 rho, omega = g.damping()
-                g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")
+                g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho=args.ortho)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True,
-                                  ortho="cgs")
+                                  ortho=args.ortho)
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t0) * 1e3
                 row[prec] = dict(its=info["iterations"], ms=round(ms, 3),
@@ -236,12 +236,12 @@ def stochastic_sweep(args, torch, shapes=None, nc=None) -> dict:
     return {"sweep": True, "nc": nc, "local_solves": args.local, "rows": rows}
 
 
-def _timed_solve(g, pr, omega, torch, graph=True):
+def _timed_solve(g, pr, omega, torch, graph=True, ortho="block2"):
     """One warm solve, then one timed: (milliseconds, info)."""
-    g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho="cgs")
+    g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho=ortho)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho="cgs")
+    x, info = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho=ortho)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3, info
 
@@ -266,7 +266,7 @@ def coarse_study(args, torch) -> dict:
                 if inner != "none":
                     g.set_inner(inner, rtol, 100)
                 c0, i0, _ = B.amg_inner_stats(g.amg)
-                ms, info = _timed_solve(g, pr, omega, torch)
+                ms, info = _timed_solve(g, pr, omega, torch, ortho=args.ortho)
                 c1, i1, _ = B.amg_inner_stats(g.amg)
                 row = dict(prec=prec, coarse=inner, inner_rtol=rtol, its=info["iterations"],
                            ms=round(ms, 3), relres=info["true_relres"])
@@ -292,7 +292,7 @@ def coarse_study(args, torch) -> dict:
                 rho, omega = g.damping()
                 if inner != "none":
                     g.set_inner(inner, 1e-5, 100)
-                ms, info = _timed_solve(g, prr, omega, torch)
+                ms, info = _timed_solve(g, prr, omega, torch, ortho=args.ortho)
                 row = dict(sub=gx * gx, nodes_per_coarse_node=round(prr.mesh.n / (gx * gx), 1),
                            coarse_unknowns=gx * gx * g.P, coarse=inner, its=info["iterations"],
                            ms=round(ms, 3), ras_path=B.ras_path_info(g.ras)[2],
@@ -337,7 +337,7 @@ def geometric_ratio_study(args, torch) -> list:
                     rho, omega = g.damping()
                     nc, nnz_c, om_c = B.amg_geometric_info(g.amg)
                     c0, i0, _ = B.amg_inner_stats(g.amg)
-                    ms, info = _timed_solve(g, prr, omega, torch)
+                    ms, info = _timed_solve(g, prr, omega, torch, ortho=args.ortho)
                     c1, i1, _ = B.amg_inner_stats(g.amg)
                     row = dict(prec=prec, ratio=r, unknown_ratio=round(g.n / nc, 2),
                                coarse_nodes=nc, coarse_unknowns=nc * g.P, level_coarse=level,
@@ -496,11 +496,11 @@ def bench_config3(args, torch) -> dict:
             torch.cuda.synchronize()
             setup = time.perf_counter() - t0
             rho, omega = g.damping()
-            ms, info = _timed_solve(g, pr, omega, torch)
+            ms, info = _timed_solve(g, pr, omega, torch, ortho=args.ortho)
             row = dict(ms=round(ms, 3), iterations=info["iterations"],
                        relres=info["true_relres"], setup_s=round(setup, 2),
                        ras_path=B.ras_path_info(g.ras)[2], omega=round(omega, 4))
-            x = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho="cgs")[0]
+            x = g.solve(pr.restart, pr.rtol, omega=omega, use_graph=True, ortho=args.ortho)[0]
             if ref is None:
                 ref = x.clone()
                 n, P, L, nnz = g.n, g.P, g.L, g.nnz
@@ -531,7 +531,7 @@ def bench_newton(args, torch):
 
     out = {}
     pr = make_problem("c4")
-    with GpuNewton(pr) as g:
+    with GpuNewton(pr, ortho=args.ortho) as g:
         U, info = g.solve(tol=1e-8)                      # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -558,7 +558,7 @@ def bench_newton(args, torch):
     # the paper's model kappa(u) = 1 + u: its Picard linearisation (stopped at
     # ||dU|| <= 1e-6 ||U||, the paper's criterion) against Newton (to
     # ||R|| / ||F|| <= 1e-8), both from the zero guess
-    with GpuNewton(pr, a1=1.0, a2=0.0) as gp:
+    with GpuNewton(pr, a1=1.0, a2=0.0, ortho=args.ortho) as gp:
         res, sol = {}, {}
         for meth, kw in (("newton", dict(tol=1e-8)),
                          ("picard", dict(tol=1e-14, du_tol=1e-6, method="picard",
@@ -583,7 +583,7 @@ def bench_newton(args, torch):
         f"{res['picard']['krylov_its']} its; difference {res['picard_vs_newton_rel_diff']:.2e}")
     if args.learned_draws <= 0:
         return out
-    lg = LearnedGuess("c4", max_batch=16, seed=0)
+    lg = LearnedGuess("c4", max_batch=16, seed=0, ortho=args.ortho)
     try:
         ds = lg.generate(draw_params(args.learned_draws, seed=0))
         lg.fit_output_scale(ds)
@@ -631,9 +631,9 @@ def main() -> int:
                     help="with --matvec-only: time the matrix-free apply")
     ap.add_argument("--matvec-only", action="store_true",
                     help="time only the SG matvec (for counter collection) and print its figures")
-    ap.add_argument("--ortho", default="cgs", choices=["mgs", "cgs2", "cgs"],
+    ap.add_argument("--ortho", default="block2", choices=["mgs", "cgs2", "cgs", "block2"],
                     help="Arnoldi orthogonalisation")
-    ap.add_argument("--ortho-compare", default="mgs",
+    ap.add_argument("--ortho-compare", default="cgs,mgs",
                     help="other orthogonalisations timed on the mixed solve (comma list)")
     ap.add_argument("--ras-path", default="auto",
                     choices=["auto", "sweep", "dense", "dense32", "fused"],

@@ -438,7 +438,20 @@ typedef enum {
     SG_ORTHO_CGS_DGKS = 1,  /* classical, second pass when ||w|| drops by    */
                             /* more than 1 - 1/sqrt(2) (Daniel-Gragg-Kaufman-  */
                             /* Stewart)                                       */
-    SG_ORTHO_CGS = 2        /* classical, one pass                           */
+    SG_ORTHO_CGS = 2,       /* classical, one pass                           */
+    SG_ORTHO_CGS_BLOCK2 = 3 /* classical, one pass over the basis for two    */
+                            /* directions: step pair (j, j+1) takes          */
+                            /* u1 = A M v_j and u2 = A M u1 (flexible        */
+                            /* direction of column j+1: M u1), projects both */
+                            /* against v_0..v_j together, then u2 against    */
+                            /* u1 (norms from the projected Gram matrix, the */
+                            /* norm of v_{j+2} recomputed where the 2 x 2    */
+                            /* step cancels more than 1 - 1e-4 of ||u2||^2). */
+                            /* Same Krylov space as one step at a time for a */
+                            /* fixed linear preconditioner; the basis is     */
+                            /* read about half as often.  Convergence is     */
+                            /* checked after every pair; an odd restart      */
+                            /* length ends with a single step.               */
 } sg_ortho;
 
 typedef struct {

@@ -19,8 +19,9 @@ SG_OK, SG_NOT_CONVERGED = 0, 1
 SG_FP64, SG_FP32, SG_BF16 = 0, 1, 2
 SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG, SG_COARSE_GEOMETRIC = 0, 1, 2, 3
 PREC = {"fp64": SG_FP64, "fp32": SG_FP32, "bf16": SG_BF16}
-SG_ORTHO_MGS, SG_ORTHO_CGS_DGKS, SG_ORTHO_CGS = 0, 1, 2
-ORTHO = {"mgs": SG_ORTHO_MGS, "cgs2": SG_ORTHO_CGS_DGKS, "cgs": SG_ORTHO_CGS}
+SG_ORTHO_MGS, SG_ORTHO_CGS_DGKS, SG_ORTHO_CGS, SG_ORTHO_CGS_BLOCK2 = 0, 1, 2, 3
+ORTHO = {"mgs": SG_ORTHO_MGS, "cgs2": SG_ORTHO_CGS_DGKS, "cgs": SG_ORTHO_CGS,
+         "block2": SG_ORTHO_CGS_BLOCK2}
 
 _vp = C.c_void_p
 _i32p = C.POINTER(C.c_int32)

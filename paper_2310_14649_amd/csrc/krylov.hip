@@ -197,6 +197,180 @@ __global__ __launch_bounds__(kVT) void cgs_update_kernel(int64_t N, int ni, int6
     if (threadIdx.x == 0) part_out[blockIdx.x] = s;
 }
 
+// ---- two Krylov directions per Gram-Schmidt pass (SG_ORTHO_CGS_BLOCK2).
+// Step pair (j, j+1): u1 = A M v_j and u2 = A M u1 (the flexible direction
+// of column j+1 is M u1), both projected against v_0..v_j in one pass over
+// the basis, then against each other.  part[(2q + t) nb + block] = partial
+// <u_{t+1}, v_{i0+q}>.
+constexpr int kB2 = 16;         // basis vectors per work-group column
+
+__global__ __launch_bounds__(kVT) void cgs2_dot_kernel(int64_t N, int nb, int ni, int64_t ldv,
+                                                       const double* __restrict__ u1,
+                                                       const double* __restrict__ u2,
+                                                       const double* __restrict__ V,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[kVT / 64][2 * kB2];
+    const int ib0 = blockIdx.y * kB2;
+    const int cnt = min(kB2, ni - ib0);
+    double a1[kB2], a2[kB2];
+#pragma unroll
+    for (int q = 0; q < kB2; ++q) a1[q] = a2[q] = 0.0;
+    const int64_t N2 = N >> 1;
+    const double2* x2 = reinterpret_cast<const double2*>(u1);
+    const double2* y2 = reinterpret_cast<const double2*>(u2);
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N2; e += (int64_t)gridDim.x * kVT) {
+        const double2 x = x2[e], y = y2[e];
+#pragma unroll
+        for (int q = 0; q < kB2; ++q)
+            if (q < cnt) {
+                const double2 v = reinterpret_cast<const double2*>(V + (size_t)(ib0 + q) * ldv)[e];
+                a1[q] = fma(x.y, v.y, fma(x.x, v.x, a1[q]));
+                a2[q] = fma(y.y, v.y, fma(y.x, v.x, a2[q]));
+            }
+    }
+    if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double x = u1[N - 1], y = u2[N - 1];
+#pragma unroll
+        for (int q = 0; q < kB2; ++q)
+            if (q < cnt) {
+                const double v = V[(size_t)(ib0 + q) * ldv + N - 1];
+                a1[q] = fma(x, v, a1[q]);
+                a2[q] = fma(y, v, a2[q]);
+            }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kB2; ++q) {
+        const double t1 = wave_sum(a1[q]), t2 = wave_sum(a2[q]);
+        if (lane == 0) {
+            sh[wv][2 * q] = t1;
+            sh[wv][2 * q + 1] = t2;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * cnt) {
+        const int r = threadIdx.x;
+        double t = 0.0;
+        for (int u = 0; u < kVT / 64; ++u) t += sh[u][r];
+        part[(size_t)(2 * ib0 + r) * nb + blockIdx.x] = t;
+    }
+}
+
+// Block r < 2 ni reduces coefficient r: c_t[q] with q = r / 2, t = r % 2,
+// into column j (t = 0) or j + 1 (t = 1) of the Hessenberg.
+__global__ __launch_bounds__(kVT) void cgs2_reduce_kernel(int nb, const double* __restrict__ part,
+                                                          double* __restrict__ hj,
+                                                          double* __restrict__ hj1) {
+    __shared__ double sh[kVT];
+    const int r = blockIdx.x;
+    const double t = reduce_partials(part + (size_t)r * nb, nb, sh);
+    if (threadIdx.x == 0) ((r & 1) ? hj1 : hj)[r >> 1] = t;
+}
+
+// u1 -= sum_q c1_q v_q, u2 -= sum_q c2_q v_q (one pass over the basis);
+// part_out[t nb + block] = partial <u1,u1>, <u1,u2>, <u2,u2> (t = 0, 1, 2)
+// of the projected vectors.
+__global__ __launch_bounds__(kVT) void cgs2_update_kernel(int64_t N, int nb, int ni, int64_t ldv,
+                                                          double* __restrict__ u1,
+                                                          double* __restrict__ u2,
+                                                          const double* __restrict__ V,
+                                                          const double* __restrict__ c1,
+                                                          const double* __restrict__ c2,
+                                                          double* __restrict__ part_out) {
+    __shared__ double cs1[64], cs2[64];
+    __shared__ double sh[kVT];
+    for (int q = threadIdx.x; q < ni; q += kVT) {
+        cs1[q] = c1[q];
+        cs2[q] = c2[q];
+    }
+    __syncthreads();
+    double g11 = 0.0, g12 = 0.0, g22 = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        double x = u1[e], y = u2[e];
+        for (int q = 0; q < ni; ++q) {
+            const double v = V[(size_t)q * ldv + e];
+            x = fma(-cs1[q], v, x);
+            y = fma(-cs2[q], v, y);
+        }
+        u1[e] = x;
+        u2[e] = y;
+        g11 = fma(x, x, g11);
+        g12 = fma(x, y, g12);
+        g22 = fma(y, y, g22);
+    }
+    const double s11 = block_sum(g11, sh), s12 = block_sum(g12, sh), s22 = block_sum(g22, sh);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x] = s11;
+        part_out[nb + blockIdx.x] = s12;
+        part_out[2 * nb + blockIdx.x] = s22;
+    }
+}
+
+// The 2 x 2 step: r11 = ||u1||, r12 = <u1,u2>/r11, r22 = sqrt(||u2||^2 - r12^2);
+// v_{j+1} = u1/r11, v_{j+2} = (u2 - r12 v_{j+1})/r22 in place.  H(j+1, j) =
+// r11, H(j+1, j+1) = r12, H(j+2, j+1) = r22.  flag = 1: breakdown at column j
+// (u1 = 0), 2: at column j + 1; gate = 1 when r22^2 kept less than 1e-4 of
+// ||u2||^2, so the Pythagorean r22 is recomputed from the vector.
+__global__ __launch_bounds__(kVT) void pair_normalize_kernel(int64_t N, int nb,
+                                                             double* __restrict__ u1,
+                                                             double* __restrict__ u2,
+                                                             const double* __restrict__ part,
+                                                             double* __restrict__ hj,
+                                                             double* __restrict__ hj1, int j,
+                                                             double* __restrict__ flag,
+                                                             double* __restrict__ gate) {
+    __shared__ double sh[kVT];
+    const double g11 = reduce_partials(part, nb, sh);
+    const double g12 = reduce_partials(part + nb, nb, sh);
+    const double g22 = reduce_partials(part + 2 * nb, nb, sh);
+    const double r11 = sqrt(g11);
+    const double r12 = r11 > 0.0 ? g12 / r11 : 0.0;
+    const double r22sq = g22 - r12 * r12;
+    const double r22 = (r11 > 0.0 && r22sq > 0.0) ? sqrt(r22sq) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hj[j + 1] = r11;
+        hj1[j + 1] = r12;
+        hj1[j + 2] = r22;
+        flag[0] = r11 == 0.0 ? 1.0 : (r22 == 0.0 ? 2.0 : 0.0);
+        gate[0] = (r22 > 0.0 && r22sq < 1e-4 * g22) ? 1.0 : 0.0;
+    }
+    const double i11 = r11 > 0.0 ? 1.0 / r11 : 0.0;
+    const double i22 = r22 > 0.0 ? 1.0 / r22 : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        const double v1 = u1[e] * i11;
+        u1[e] = v1;
+        u2[e] = (u2[e] - r12 * v1) * i22;
+    }
+}
+
+// Where the gate is set: part = partial <v, v> of v_{j+2}; then v_{j+2} and
+// H(j+2, j+1) rescaled by the exact norm (pair_rescale_kernel).
+__global__ __launch_bounds__(kVT) void gated_norm_kernel(int64_t N, const double* __restrict__ v,
+                                                         double* __restrict__ part,
+                                                         const double* __restrict__ gate) {
+    if (gate[0] == 0.0) return;
+    __shared__ double sh[kVT];
+    double a = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT)
+        a = fma(v[e], v[e], a);
+    const double s = block_sum(a, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kVT) void pair_rescale_kernel(int64_t N, int nb, double* __restrict__ v,
+                                                           const double* __restrict__ part,
+                                                           double* __restrict__ hj1, int j,
+                                                           const double* __restrict__ gate) {
+    if (gate[0] == 0.0) return;
+    __shared__ double sh[kVT];
+    const double nrm = sqrt(reduce_partials(part, nb, sh));
+    if (!(nrm > 0.0)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) hj1[j + 2] *= nrm;
+    const double inv = 1.0 / nrm;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT)
+        v[e] *= inv;
+}
+
 // Second pass wanted if ||w_after||^2 < ||w_before||^2 / 2.
 __global__ __launch_bounds__(kVT) void dgks_kernel(int nb, const double* __restrict__ part_after,
                                                    const double* __restrict__ ww_before,
@@ -479,7 +653,7 @@ size_t fgmres_ws_ns(int n, int P, int ns, int restart) {
     size_t b = align_up(N * 8) * (2 * m + 2);                 // V (m+1), Z (m), w
     b += precond_ws_ns(n, P, ns);
     b += 2 * align_up(kMaxRedBlocks * 8);                     // partial sums
-    b += align_up((m + 2) * kMaxRedBlocks * 8);               // Gram-Schmidt partials
+    b += align_up((2 * m + 4) * kMaxRedBlocks * 8);           // Gram-Schmidt partials
     b += align_up((m + 1) * 8) + align_up(64);                // correction, flags
     b += align_up((m + 1) * m * 8) + 4 * align_up((m + 1) * 8) + align_up(64);
     // the damping estimate reuses the front of the workspace
@@ -548,7 +722,8 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
     SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
     SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
-    SG_REQUIRE(opts->ortho >= SG_ORTHO_MGS && opts->ortho <= SG_ORTHO_CGS, "bad orthogonalisation");
+    SG_REQUIRE(opts->ortho >= SG_ORTHO_MGS && opts->ortho <= SG_ORTHO_CGS_BLOCK2,
+               "bad orthogonalisation");
     const size_t need = fgmres_ws_np(A.n, A.P, amg, m);
     if (!ws || ws_bytes < need)
         SG_THROW(SG_ERR_WORKSPACE, "fgmres workspace too small (%zu < %zu)", ws_bytes, need);
@@ -563,7 +738,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     char* q = pws + precond_ws_np(A.n, A.P, amg);
     double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
     double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
-    double* gsp = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 2) * kMaxRedBlocks * 8);
+    double* gsp = reinterpret_cast<double*>(q); q += align_up((size_t)(2 * m + 4) * kMaxRedBlocks * 8);
     double* corr = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
     double* gsf = reinterpret_cast<double*>(q); q += align_up(64);   // ww_before, flag
     double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
@@ -643,6 +818,50 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
             HIP_LAUNCH_OK();
         };
+        // Step pair (j, j + 1) of SG_ORTHO_CGS_BLOCK2: z_j = M v_j, u1 = A z_j,
+        // z_{j+1} = M u1, u2 = A z_{j+1}; u1 and u2 projected against
+        // v_0..v_j in one pass (coefficients into columns j and j + 1 of H),
+        // then orthonormalised against each other into v_{j+1}, v_{j+2}, so
+        // that A z_i = V H(:, i) holds for both columns.
+        const bool block = opts->ortho == SG_ORTHO_CGS_BLOCK2;
+        auto pair_step = [&](int j, hipStream_t st) {
+            const int64_t ldv = (int64_t)(vb / 8);
+            double* vj = V + (size_t)j * ldv;
+            double* u1 = V + (size_t)(j + 1) * ldv;
+            double* u2 = V + (size_t)(j + 2) * ldv;
+            double* zj = Zb + (size_t)j * ldv;
+            double* zj1 = Zb + (size_t)(j + 1) * ldv;
+            precond_apply(A, ras, amg, omega, vj, zj, pws, st);
+            linop_apply(A, zj, u1, 1.0, 0.0, nullptr, st);
+            precond_apply(A, ras, amg, omega, u1, zj1, pws, st);
+            linop_apply(A, zj1, u2, 1.0, 0.0, nullptr, st);
+            const int ni = j + 1;
+            double* hj = H + (size_t)j * (m + 1);
+            double* hj1 = H + (size_t)(j + 1) * (m + 1);
+            const dim3 dgrid(nb, (ni + kB2 - 1) / kB2);
+            cgs2_dot_kernel<<<dgrid, kVT, 0, st>>>(N, nb, ni, ldv, u1, u2, V, gsp);
+            HIP_LAUNCH_OK();
+            cgs2_reduce_kernel<<<2 * ni, kVT, 0, st>>>(nb, gsp, hj, hj1);
+            HIP_LAUNCH_OK();
+            cgs2_update_kernel<<<nb, kVT, 0, st>>>(N, nb, ni, ldv, u1, u2, V, hj, hj1, gsp);
+            HIP_LAUNCH_OK();
+            pair_normalize_kernel<<<nb, kVT, 0, st>>>(N, nb, u1, u2, gsp, hj, hj1, j, scal + 1,
+                                                      gsf + 3);
+            HIP_LAUNCH_OK();
+            gated_norm_kernel<<<nb, kVT, 0, st>>>(N, u2, part[0], gsf + 3);
+            HIP_LAUNCH_OK();
+            pair_rescale_kernel<<<nb, kVT, 0, st>>>(N, nb, u2, part[0], hj1, j, gsf + 3);
+            HIP_LAUNCH_OK();
+            givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
+            HIP_LAUNCH_OK();
+            givens_kernel<<<1, 1, 0, st>>>(j + 1, m + 1, H, cs, sn, g, scal);
+            HIP_LAUNCH_OK();
+        };
+        // columns of the unit that starts at column j: a pair in block mode
+        // while both columns fit the cycle and the step budget
+        auto width = [&](int j, int its_now) {
+            return (block && j + 1 < m && its_now + 2 <= opts->max_it) ? 2 : 1;
+        };
         if (bnorm == 0.0) {
             Vec::fill(N, 0.0, x, s);
             converged = true;
@@ -655,14 +874,22 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             relres = beta / bnorm;
             push_hist(relres);
             if (beta <= target) converged = true;
-            // one Arnoldi step, from its captured graph (captured on first use)
-            auto launch_step = [&](int j) {
+            // one Arnoldi step (w = 1) or step pair (w = 2), from its captured
+            // graph (captured on first use)
+            auto launch_unit = [&](int j, int w) {
+                auto run = [&](hipStream_t st) {
+                    if (w == 2) pair_step(j, st);
+                    else arnoldi_step(j, st);
+                };
                 if (!opts->use_graph || (amg && inner_active(amg))) {
-                    arnoldi_step(j, s);
+                    run(s);
                     return;
                 }
                 hipGraphExec_t exec = nullptr;
-                GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, opts->ortho, 0};
+                const int kortho = w == 2 ? (int)SG_ORTHO_CGS_BLOCK2
+                                          : (opts->ortho == SG_ORTHO_CGS_BLOCK2 ? (int)SG_ORTHO_CGS
+                                                                                : opts->ortho);
+                GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, kortho, 0};
                 std::memcpy(&key.omega_bits, &omega, sizeof(double));
                 {
                     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -674,7 +901,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                     HIP_OK(hipStreamSynchronize(s));
                     HIP_OK(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
                     try {
-                        arnoldi_step(j, cst);
+                        run(cst);
                     } catch (...) {
                         hipGraph_t bad = nullptr;
                         (void)hipStreamEndCapture(cst, &bad);
@@ -697,32 +924,35 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                 HIP_LAUNCH_OK();
                 Vec::scale(N, 1.0 / beta, V, V, s);
                 int jd = 0;
-                int launched = -1;
-                double est_prev[2] = {0.0, 0.0};   // estimates of the last two steps
-                for (int j = 0; j < m; ++j) {
-                    if (launched < j) {
-                        launch_step(j);
-                        launched = j;
-                    }
-                    double* hb = pin.p + 2 * (j & 1);
+                int launched = -1;                  // first column of the unit in flight
+                double est_prev[2] = {0.0, 0.0};   // estimates of the last two units
+                int unit = 0;
+                for (int j = 0; j < m;) {
+                    const int w = width(j, its);
+                    if (launched != j) launch_unit(j, w);
+                    double* hb = pin.p + 2 * (unit & 1);
                     HIP_OK(hipMemcpyAsync(hb, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-                    HIP_OK(hipEventRecord(pin.ev[j & 1], s));
-                    // The next step runs while the host reads this one's
-                    // estimate.  A step past convergence writes only column
-                    // j + 1 of H, g[j + 1], g[j + 2], V_{j+2} and Z_{j+1},
-                    // none of which the update with j + 1 columns reads; it
-                    // is not started where the last two estimates extrapolate
-                    // to within 4 x the target (it would be wasted work).
-                    const bool near = j >= 2 && est_prev[1] > 0.0 &&
+                    HIP_OK(hipEventRecord(pin.ev[unit & 1], s));
+                    // The next unit (one step, or a step pair) runs while the
+                    // host reads this one's estimate.  A unit past convergence
+                    // writes only columns from j + w on of H, g[j + w ..], and
+                    // V, Z beyond the columns the update with j + w columns
+                    // reads; it is not started where the last two estimates
+                    // extrapolate to within 4 x the target (wasted work).
+                    const int jn = j + w;
+                    const bool near = unit >= 2 && est_prev[1] > 0.0 &&
                                       est_prev[0] * est_prev[0] / est_prev[1] <= 4.0 * target;
-                    if (j + 1 < m && its + 1 < opts->max_it && !near) {
-                        launch_step(j + 1);
-                        launched = j + 1;
+                    launched = -1;
+                    if (jn < m && its + w < opts->max_it && !near) {
+                        launch_unit(jn, width(jn, its + w));
+                        launched = jn;
                     }
-                    HIP_OK(hipEventSynchronize(pin.ev[j & 1]));
+                    HIP_OK(hipEventSynchronize(pin.ev[unit & 1]));
                     const double hs[2] = {hb[0], hb[1]};
-                    ++its;
-                    jd = j + 1;
+                    // a pair whose first direction broke down keeps one column
+                    const bool first_only = w == 2 && hs[1] == 1.0;
+                    its += first_only ? 1 : w;
+                    jd = first_only ? j + 1 : jn;
                     if (!std::isfinite(hs[0]))
                         SG_THROW(SG_ERR_NUMERIC, "Arnoldi produced a non-finite value");
                     relres = hs[0] / bnorm;
@@ -730,6 +960,8 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                     if (hs[0] <= target || hs[1] != 0.0 || its >= opts->max_it) break;
                     est_prev[1] = est_prev[0];
                     est_prev[0] = hs[0];
+                    ++unit;
+                    j = jn;
                 }
                 trisolve_kernel<<<1, 1, 0, s>>>(jd, m + 1, H, g, y);
                 HIP_LAUNCH_OK();

@@ -195,11 +195,13 @@ class GpuNewton:
 
     def __init__(self, pr: Problem, a2: float = 0.5, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
-                 n_sub: Optional[int] = None, stream=None, a1: float = 0.0):
+                 n_sub: Optional[int] = None, stream=None, a1: float = 0.0,
+                 ortho: str = "mgs"):
         import torch
         self.torch = torch
         self.pr = pr
         self.stream = stream
+        self.ortho = ortho
         self.basis = self.nl = None
         m = pr.mesh
         self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
@@ -245,7 +247,8 @@ class GpuNewton:
                               COARSE[self.coarse], U, self.workspace(restart), max_steps=max_steps,
                               tol=tol, eta_max=eta_max, restart=restart, max_it=max_it,
                               omega=omega, use_graph=use_graph, amg_rebuild=amg_rebuild,
-                              method=method, du_tol=du_tol, stream=self.stream)
+                              method=method, du_tol=du_tol, ortho=self.ortho,
+                              stream=self.stream)
         return U, info
 
     def close(self):

@@ -71,10 +71,12 @@ def test_indefinite_local_block_is_a_numeric_error():
             B.sg_destroy_ras(ras)
 
 
-def test_lucky_breakdown_returns_exact_solution():
+@pytest.mark.parametrize("ortho", ["mgs", "block2"])
+def test_lucky_breakdown_returns_exact_solution(ortho):
     """One unknown, deterministic (P = 1), no preconditioner: A v = k v
     exactly, so the first Arnoldi step leaves w - h v = 0, the breakdown
-    flag ends the cycle, and x = b / k."""
+    flag ends the cycle, and x = b / k.  With step pairs the pair's first
+    direction breaks down and the cycle keeps one column."""
     _cuda()
     pr = make_problem("c0", nc=2, M=0, p=0, sub=(1, 1))
     m = pr.mesh
@@ -88,7 +90,7 @@ def test_lucky_breakdown_returns_exact_solution():
         x = torch.zeros(1, dtype=torch.float64, device="cuda")
         ws = torch.empty((B.fgmres_workspace_bytes(op, None, 10) + 7) // 8, dtype=torch.float64,
                          device="cuda")
-        info = B.fgmres_solve(op, None, None, b, x, 10, 10, 1e-14, 1.0, ws)
+        info = B.fgmres_solve(op, None, None, b, x, 10, 10, 1e-14, 1.0, ws, ortho=ortho)
         assert info["converged"] and info["iterations"] == 1
         assert float(x[0]) == pytest.approx(3.0 / k, rel=1e-15)
     finally:

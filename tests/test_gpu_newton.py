@@ -172,15 +172,16 @@ def test_full_size_residual_and_jacobian_properties():
     assert _rel(R[rows], R_ref[rows]) < 1e-12
 
 
-@pytest.mark.parametrize("case,coarse", [("m2p2", "amg"), ("m4p3", "amg"), ("jit_m2p3", "mean"),
-                                         ("det", "amg")])
-def test_newton_matches_oracle(case, coarse):
+@pytest.mark.parametrize("case,coarse,ortho", [("m2p2", "amg", "mgs"), ("m4p3", "amg", "mgs"),
+                                               ("jit_m2p3", "mean", "mgs"), ("det", "amg", "mgs"),
+                                               ("m4p3", "amg", "block2")])
+def test_newton_matches_oracle(case, coarse, ortho):
     _cuda()
     pr = _problem(case)
     onl_pr = _oracle(pr)
     U_ref, info_ref = onl.newton(onl_pr, tol=1e-12)
     assert info_ref.converged
-    with GpuNewton(pr, coarse=coarse) as g:
+    with GpuNewton(pr, coarse=coarse, ortho=ortho) as g:
         U, info = g.solve(tol=1e-12, restart=30)
         U = _host(U, U_ref.shape)
     assert info["converged"], info

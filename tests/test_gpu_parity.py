@@ -613,6 +613,62 @@ def test_fgmres_classical_gram_schmidt(built, key, ortho):
     assert torch.equal(x, x2)
 
 
+@pytest.mark.parametrize("key,coarse", [("c0", "mean"), ("c1_64", "amg"), ("c4_ragged", "amg"),
+                                       ("c3_40", "amg"), ("j4", "amg")])
+def test_fgmres_block2_gram_schmidt(built, key, coarse):
+    """Two directions per Gram-Schmidt pass (step pairs u1 = A M v_j,
+    u2 = A M u1): with the fixed FP64 preconditioner the Krylov spaces are
+    those of one step at a time, so after every pair (column 2k - 1) the
+    residual estimate equals modified Gram-Schmidt's after the same column;
+    the solution reaches the direct one (the MGS solve for the P = 84
+    case), and graph replay equals the eager run bit for bit."""
+    pr, S, g = built(key, coarse=coarse)
+    restart = 30 if key == "c0" else 50
+    x, info = g.solve(restart, 1e-10, ortho="block2")
+    assert info["converged"] and info["true_relres"] <= 1e-10
+    x_m, info_m = g.solve(restart, 1e-10, ortho="mgs")
+    if key == "c3_40":
+        ref = _to_host(x_m, (pr.mesh.n, S.P))
+    else:
+        ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
+    hb, hm = info["history"], info_m["history"]
+    npair = min(len(hb) - 1, (len(hm) - 1) // 2, 8)
+    assert npair >= 3
+    for k in range(1, npair + 1):
+        assert hb[k] == pytest.approx(hm[2 * k], rel=1e-6), k
+    print(f"[gpu] block2 {key}: its={info['iterations']} (mgs {info_m['iterations']})", flush=True)
+    assert abs(info["iterations"] - info_m["iterations"]) <= 2
+    x2, info2 = g.solve(restart, 1e-10, ortho="block2", use_graph=True)
+    assert info2["iterations"] == info["iterations"] and torch.equal(x, x2)
+
+
+def test_fgmres_block2_odd_restart_and_cap(built):
+    """An odd restart length ends each cycle with one single step; an odd
+    step budget ends with one single step; both keep the solution exact."""
+    pr, S, g = built("c4_ragged")
+    ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    x, info = g.solve(7, 1e-10, ortho="block2", max_it=2000)
+    assert info["converged"] and info["restarts"] >= 1
+    assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
+    x5, info5 = g.solve(10, 1e-14, ortho="block2", max_it=5)
+    assert info5["iterations"] == 5 and info5["status"] == B.SG_NOT_CONVERGED
+    x5m, info5m = g.solve(10, 1e-14, ortho="mgs", max_it=5)
+    assert info5["true_relres"] == pytest.approx(info5m["true_relres"], rel=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fgmres_block2_mixed_precision_refines_to_fp64(built, prec):
+    """With a low-precision (not exactly linear) preconditioner the pair's
+    second direction M u1 is still a valid flexible direction: the solve
+    reaches the FP64 solution."""
+    pr, S, g = built("c1_64", prec=prec)
+    ref = osg.sg_solve_direct(S.K, S.G, S.B)
+    x, info = g.solve(50, 1e-10, ortho="block2")
+    err = np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref)
+    assert info["converged"] and err < 1e-6
+
+
 def test_fgmres_iterations_track_oracle(built):
     pr, S, g = built("c0", coarse="mean")
     B2, *_ = osys.two_level(S, pr.owner, pr.n_sub, pr.overlap, "mean")
