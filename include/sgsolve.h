@@ -290,7 +290,12 @@ void sg_destroy_ras(sg_ras* r);
  * aggregation, prolongator smoothing with omega = (4/3)/rho(D^{-1}A),
  * <= 4 levels / <= 8 block-nodes, damped block-Jacobi omega_s = 2/3 whose
  * block inverses are stored in `prec`, coarsest level exact in FP64).
- * b_c, x_c: device [n_sub*P] FP64.  Asynchronous.
+ * For an operator from sg_assemble the handle also holds (A Z) on the rows
+ * where it is non-zero (next to a subdomain interface or the boundary), so
+ * that the two-grid cycle forms r - A z2 as (r - A z1) - (A Z) e_c instead
+ * of a matvec; the cycle writes a small buffer of the handle
+ * ([L_in x n_sub x P]), so cycles that share a handle must be ordered on
+ * one stream.  b_c, x_c: device [n_sub*P] FP64.  Asynchronous.
  * ---------------------------------------------------------------------- */
 int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec prec,
               sg_amg** out, void* stream);
@@ -386,7 +391,8 @@ void sg_destroy_amg(sg_amg* a);
  * Two-grid preconditioner, Eq. RAS_2L read as the cycle the text describes
  * (the printed Q P Q^{-1} term equals P^T):
  *   z1 = w M r,  z2 = z1 + Q (r - A z1),  z = z2 + w M (r - A z2),
- * M = ras, Q = Z (coarse solve of `amg`) Z^T, w = the smoother damping.
+ * M = ras, Q = Z (coarse solve of `amg`) Z^T, w = the smoother damping;
+ * r - A z2 is (r - A z1) - (A Z) e_c where `amg` holds A Z for `op`.
  * amg may be NULL (one-level: z = w M r).  ws: device workspace of at
  * least sg_precond_workspace_bytes(op, amg).  R, Z device [n*P], no alias.
  * ---------------------------------------------------------------------- */

@@ -164,6 +164,10 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (loading the library first brings in the system runtime, and torch
+        # then finds no GPU)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

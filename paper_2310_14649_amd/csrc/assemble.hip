@@ -271,6 +271,7 @@ sg_op* make_csr_op(const sg_basis& b, int n, const std::vector<int32_t>& rowptr,
     op->h_col = col;
     op->h_graph_ptr = graph_ptr;
     op->h_graph_col = graph_col;
+    op->fixed_values = true;
     op->rowptr.upload(rowptr, s);
     op->col.upload(col, s);
     op->vals.upload(vals, s);
@@ -318,6 +319,7 @@ int sg_assemble(const sg_basis* b, int n_vert, const double* xy, int n_tri, cons
         op->h_afact = b->afact;
         op->h_rowptr = mp.rowptr;
         op->h_col = mp.col;
+        op->fixed_values = true;
 
         // ---- device evaluation ----
         ElementData ed;

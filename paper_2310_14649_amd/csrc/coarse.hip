@@ -17,6 +17,7 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <tuple>
 #include <type_traits>
 
 namespace sg {
@@ -87,6 +88,14 @@ struct sg_amg {
     sg_ras* gras = nullptr;
     sg_amg* gamg = nullptr;
     sg::DevBuf<char> gws;
+    // (A Z) of the Nicolaides space for the operator it was built from
+    // (values fixed): rows with a non-zero, their entries (subdomain, L_in
+    // values), the triple table by (k, i, j) with per-(k, i) ranges, and E =
+    // e_c G_i [L_in][n_sub][P] of the current coarse correction
+    const sg_op* az_op = nullptr;
+    int az_rows_n = 0;
+    sg::DevBuf<int32_t> az_rows, az_ptr, az_col, az_kptr, az_tj;
+    sg::DevBuf<double> az_val, az_tv, az_E;
     ~sg_amg() {
         if (ipin) (void)hipHostFree(ipin);
         if (gamg) sg_destroy_amg(gamg);
@@ -209,6 +218,52 @@ __global__ void geo_prolong_add_kernel(int total, int P, const int32_t* __restri
 #pragma unroll
     for (int q = 0; q < 3; ++q) t = fma(pval[3 * a + q], ec[(size_t)pcol[3 * a + q] * P + k], t);
     Y[idx] = t;
+}
+
+// E[i][s][k] = sum_j m_ijk e_c[s, j]: one thread per (i, s, k) over the
+// triples of (k, i) (kiptr ranges of the table sorted by k, i, j).
+__global__ void az_mix_kernel(int ns, int P, int L, const int32_t* __restrict__ kiptr,
+                              const int32_t* __restrict__ tj, const double* __restrict__ tv,
+                              const double* __restrict__ ec, double* __restrict__ E) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * ns * P) return;
+    const int i = idx / (ns * P);
+    const int rem = idx - i * ns * P;
+    const int sd = rem / P, k = rem - sd * P;
+    const int t0 = kiptr[k * L + i], t1 = kiptr[k * L + i + 1];
+    double acc = 0.0;
+    for (int t = t0; t < t1; ++t) acc = fma(tv[t], ec[(size_t)sd * P + tj[t]], acc);
+    E[idx] = acc;
+}
+
+// T[a, k] -= sum_{(a, s) entries} sum_i AZ_i[a, s] E[i][s][k] for the rows
+// with entries (one thread per (row, k)); the loads of eight input terms are
+// issued before their products.
+__global__ void az_update_kernel(int nrows, int ns, int P, int L, const int32_t* __restrict__ rows,
+                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, const double* __restrict__ E,
+                                 double* __restrict__ T) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * P) return;
+    const int r = idx / P, k = idx - r * P;
+    const size_t stride = (size_t)ns * P;
+    double acc = 0.0;
+    for (int e = ptr[r]; e < ptr[r + 1]; ++e) {
+        const double* v = val + (size_t)e * L;
+        const double* Ee = E + (size_t)col[e] * P + k;
+        for (int i0 = 0; i0 < L; i0 += 8) {
+            double vv[8], ee[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = i0 + u < L;
+                vv[u] = in ? v[i0 + u] : 0.0;
+                ee[u] = in ? Ee[(size_t)(i0 + u) * stride] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fma(vv[u], ee[u], acc);
+        }
+    }
+    T[(size_t)rows[r] * P + k] -= acc;
 }
 
 // x[s, k] = sum_t C0inv[s, t] b[t, k] / alpha_k!
@@ -881,6 +936,23 @@ void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
     else coarse_solve_base(a, b, x, s);
 }
 
+bool coarse_residual_update(const sg_amg* a, const sg_op* op, const double* ec, double* T,
+                            hipStream_t s) {
+    if (!op || a->az_op != op || !op->fixed_values) return false;
+    const int ns = a->n_sub, P = a->P, L = a->L;
+    az_mix_kernel<<<(L * ns * P + 255) / 256, 256, 0, s>>>(ns, P, L, a->az_kptr.p, a->az_tj.p,
+                                                             a->az_tv.p, ec, a->az_E.p);
+    HIP_LAUNCH_OK();
+    if (a->az_rows_n > 0) {
+        const int64_t tot = (int64_t)a->az_rows_n * P;
+        az_update_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            a->az_rows_n, ns, P, L, a->az_rows.p, a->az_ptr.p, a->az_col.p, a->az_val.p,
+            a->az_E.p, T);
+        HIP_LAUNCH_OK();
+    }
+    return true;
+}
+
 int amg_nsub(const sg_amg* a) { return a->n_sub; }
 int amg_device(const sg_amg* a) { return a->device; }
 
@@ -1084,6 +1156,80 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
 using namespace sg;
 
 namespace sg {
+
+// (A Z) for the Nicolaides space: AZ_i[a, s] = sum of K_i[a, b] over the
+// columns b owned by subdomain s, in column order.  A row whose neighbours
+// all lie in one subdomain has AZ_i[a, s] = 0 in exact arithmetic (the
+// stiffness rows sum to zero away from the boundary); such sums, which
+// cancel to within 64 u of their terms' magnitudes in every input term, are
+// left out, so only rows at an interface or the Dirichlet boundary remain.
+void build_az(sg_amg* a, const sg_op* op, const std::vector<int32_t>& owner, hipStream_t s) {
+    const int n = op->n, L = op->L, P = op->P, ns = a->n_sub;
+    std::vector<double> vals((size_t)op->nnz * L);
+    op->vals.download(vals.data(), vals.size(), s);
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<int32_t> rows, ptr(1, 0), col;
+    std::vector<double> val;
+    std::vector<int32_t> subs;
+    std::vector<double> acc, sab;
+    for (int r = 0; r < n; ++r) {
+        subs.clear();
+        for (int e = op->h_rowptr[r]; e < op->h_rowptr[r + 1]; ++e) {
+            const int sd = owner[op->h_col[e]];
+            if (std::find(subs.begin(), subs.end(), sd) == subs.end()) subs.push_back(sd);
+        }
+        std::sort(subs.begin(), subs.end());
+        const size_t before = col.size();
+        for (int sd : subs) {
+            acc.assign(L, 0.0);
+            sab.assign(L, 0.0);
+            for (int e = op->h_rowptr[r]; e < op->h_rowptr[r + 1]; ++e) {
+                if (owner[op->h_col[e]] != sd) continue;
+                for (int i = 0; i < L; ++i) {
+                    acc[i] += vals[(size_t)e * L + i];
+                    sab[i] += std::fabs(vals[(size_t)e * L + i]);
+                }
+            }
+            bool keep = false;
+            for (int i = 0; i < L && !keep; ++i)
+                keep = std::fabs(acc[i]) > 64.0 * 1.1102230246251565e-16 * sab[i];
+            if (!keep) continue;
+            col.push_back(sd);
+            val.insert(val.end(), acc.begin(), acc.end());
+        }
+        if (col.size() > before) {
+            rows.push_back(r);
+            ptr.push_back((int32_t)col.size());
+        }
+    }
+    const sg_basis& B = op->basis;
+    std::vector<int32_t> order(B.T);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return std::make_tuple(B.tk[x], B.ti[x], B.tj[x]) < std::make_tuple(B.tk[y], B.ti[y], B.tj[y]);
+    });
+    // ranges of the (k, i) pairs: kiptr[k L + i] .. kiptr[k L + i + 1]
+    std::vector<int32_t> kiptr((size_t)P * L + 1, 0), tj(B.T);
+    std::vector<double> tv(B.T);
+    for (int q = 0; q < B.T; ++q) {
+        const int t = order[q];
+        tj[q] = B.tj[t];
+        tv[q] = B.tv[t];
+        kiptr[(size_t)B.tk[t] * L + B.ti[t] + 1]++;
+    }
+    for (size_t q = 0; q < (size_t)P * L; ++q) kiptr[q + 1] += kiptr[q];
+    a->az_rows_n = (int)rows.size();
+    a->az_rows.upload(rows, s);
+    a->az_ptr.upload(ptr, s);
+    a->az_col.upload(col, s);
+    a->az_val.upload(val, s);
+    a->az_kptr.upload(kiptr, s);
+    a->az_tj.upload(tj, s);
+    a->az_tv.upload(tv, s);
+    a->az_E.alloc((size_t)L * ns * P);
+    a->az_op = op;
+    HIP_OK(hipStreamSynchronize(s));
+}
 
 bool amg_is_geometric(const sg_amg* a) { return a->kind == SG_COARSE_GEOMETRIC; }
 int amg_fine_n(const sg_amg* a) { return a->n; }
@@ -1352,6 +1498,7 @@ int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec p
         std::vector<double> C((size_t)nce * L);
         d_C.download(C.data(), C.size(), s);
         HIP_OK(hipStreamSynchronize(s));
+        if (op->fixed_values) build_az(a.get(), op, owner, s);
 
         if (kind == SG_COARSE_MEAN_EXACT) {
             std::vector<double> C0((size_t)ns * ns, 0.0);

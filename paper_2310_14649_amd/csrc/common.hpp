@@ -199,6 +199,9 @@ struct sg_op {
     // matrix-free apply (sg_matvec_matrix_free), for meshes that are the
     // structured N x N lattice of "/"-cut squares (jittered or not)
     int lattice_N = 0;                 // 0: not a lattice
+    // values fixed after construction (sg_assemble, coarse operators); the
+    // operators of a nonlinear problem change at every evaluation
+    bool fixed_values = false;
     bool mf_on = false, mf_uniform = false;
     bool mf_fits[3] = {false, false, false};
     sg::DevBuf<double> mf_ef, mf_ek6;
@@ -314,6 +317,11 @@ int ras_n(const sg_ras* r);
 void coarse_restrict(const sg_amg* a, const double* R, double* rc, hipStream_t s);
 void coarse_prolong_add(const sg_amg* a, const double* ec, double* Y, hipStream_t s);
 void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
+// T -= (A Z) e_c for the operator the coarse space was built from, where the
+// product touches only the rows next to a subdomain interface or the
+// boundary; false (nothing done) when `op` is not that operator.
+bool coarse_residual_update(const sg_amg* a, const sg_op* op, const double* ec, double* T,
+                            hipStream_t s);
 // true when the coarse solve is an inner Krylov iteration (host-synchronous,
 // so the Arnoldi step that contains it is not captured into a graph)
 bool inner_active(const sg_amg* a);

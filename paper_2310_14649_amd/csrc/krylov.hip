@@ -522,7 +522,11 @@ void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double 
     coarse_restrict(amg, T, rc, s);
     coarse_solve(amg, rc, ec, s);
     coarse_prolong_add(amg, ec, Z, s);                               // z2 = z1 + Q t
-    linop_apply(A, Z, T, -1.0, 1.0, R, s);                           // t = r - A z2
+    // t = r - A z2 = (r - A z1) - (A Z) e_c: only interface and boundary rows
+    // of A Z are non-zero for the Nicolaides space, so the update replaces a
+    // matvec where the coarse space holds A Z; else the residual is formed
+    if (!coarse_residual_update(amg, A.kron, ec, T, s))
+        linop_apply(A, Z, T, -1.0, 1.0, R, s);
     ras_apply_ex(ras, T, Z, omega, 1.0, s);                          // z = z2 + w M t
 }
 

@@ -62,6 +62,15 @@ struct sg_ras {
     // mixed per node by W = Gt^{-1} G_0 [P x Pw, row k col j, zero-padded] into kron_t
     sg_local_kind local_mode = SG_LOCAL_MEAN;
     sg::DevBuf<double> kron_w, kron_t;
+    // the fused dense path applies the mixing to its output instead:
+    // Z = N(R) Gt^{-1} with N the node operator, Gt^{-1} [P x Pp] (the
+    // mixing commutes with N, and W diag(1/alpha!) = Gt^{-1}; applied in the
+    // accumulator precision, FP64 for the FP64 path)
+    sg::DevBuf<double> kron_post;
+    bool post_ok = false;
+    int post_pp = 0;                              // its column padding (P padded to 16)
+    size_t post_lds = 0;
+    size_t lds_max = 0;                           // LDS bytes a work-group may use
     std::vector<double> h_gt;                     // Gt, for ras_local_factor
     bool fused_ok = false;                        // fused variant fits (LDS, columns)
     size_t fused_lds = 0;                         // its LDS bytes per work-group
@@ -795,7 +804,21 @@ constexpr int kFusedRows = 64 * kFusedWaves;
 constexpr int kFusedChunks = 7;   // right-hand-side chunks gathered under the stream
 // column tiles whose accumulators fit the 128 registers of a 16-wave group
 inline int fused_max_nt(sg_prec prec) { return prec == SG_FP64 ? 1 : 3; }
-template <class TS, int NT>
+// Output mixing of the Kronecker local solves in the fused path (POST): after
+// the stream Gt^{-1} is staged in LDS, every wave dumps 32 of its 64 rows of
+// accumulators to its own LDS slice (row stride Pp + 1), two lanes per row
+// multiply it by Gt^{-1} (half the columns each) and write it back, and the
+// wave stores the slice to Z with consecutive lanes on consecutive entries
+// of the flattened rows; then the other 32 rows.
+inline size_t dense_post_lds(int P, int Pp, size_t acc_bytes) {
+    return ((size_t)kFusedWaves * 32 * (Pp + 1) + (size_t)P * Pp) * acc_bytes;
+}
+
+// STORE: 0 = stores from the matrix-core layout (dense_epilogue); 1 = the
+// output mixing by Gt^{-1} (Kronecker local solves); 2 = the same row-slice
+// store with the division by alpha! (mean-based local solves), bit-identical
+// to 0.
+template <class TS, int NT, int STORE>
 __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     int P, const int32_t* __restrict__ blk_sub, const int32_t* __restrict__ blk_row0,
     const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
@@ -803,7 +826,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     const int64_t* __restrict__ toff, const int64_t* __restrict__ own_off,
     const int32_t* __restrict__ own_gnode, const TS* __restrict__ ainv,
     const double* __restrict__ R, const double* __restrict__ afact, double* Z, double omega,
-    double beta) {
+    double beta, const double* __restrict__ post) {
     using Acc = typename Mma<TS>::Acc;
     constexpr int MT = 4;
     constexpr int KL = 16 / sizeof(TS);
@@ -951,6 +974,59 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             __syncthreads();
         }
     }
+    if constexpr (STORE != 0) {
+        using AT = typename std::conditional<std::is_same<TS, double>::value, double, float>::type;
+        constexpr int RS = Pp + 1;          // odd row stride: conflict-free row reads
+        constexpr int JH = Pp / 2;          // columns per lane (two lanes per row)
+        __syncthreads();                    // every wave has streamed: the LDS is free
+        // Gt^{-1} after the row slices, in the accumulator precision
+        AT* ps = reinterpret_cast<AT*>(lds_b) + (size_t)kFusedWaves * 32 * RS;
+        if (STORE == 1) {
+            for (int q = tid; q < P * Pp; q += kThreads) ps[q] = (AT)post[q];
+            __syncthreads();
+        }
+        if (!active) return;
+        AT* rb = reinterpret_cast<AT*>(lds_b) + (size_t)wave * 32 * RS;
+        const int32_t* og = own_gnode + own_off[s];
+        const int i = lane & 15;
+        const int row = lane & 31, j0 = (lane >> 5) * JH;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        rb[(16 * m + Mma<TS>::row_of(lane, v)) * RS + 16 * t + i] =
+                            acc[2 * hf + m][t][v];
+            if (STORE == 1) {
+                AT z[JH];
+#pragma unroll
+                for (int j = 0; j < JH; ++j) z[j] = AT(0);
+                for (int k = 0; k < P; ++k) {
+                    const AT xk = rb[row * RS + k];
+                    const AT* pk = ps + k * Pp + j0;
+#pragma unroll
+                    for (int j = 0; j < JH; ++j) z[j] = fma(xk, pk[j], z[j]);
+                }
+                // both lanes of a row have read it (the LDS runs a wave's
+                // instructions in order) before either overwrites its half
+#pragma unroll
+                for (int j = 0; j < JH; ++j) rb[row * RS + j0 + j] = z[j];
+            }
+            const int rbase = r0 + 32 * hf;
+            const int nr = min(32, no - rbase);
+            for (int e = lane; e < nr * P; e += 64) {
+                const int rr = e / P, c = e - rr * P;
+                const int64_t zo = (int64_t)og[rbase + rr] * P + c;
+                const double val = STORE == 1 ? omega * (double)rb[rr * RS + c]
+                                              : omega * (double)rb[rr * RS + c] / afact[c];
+                Z[zo] = beta != 0.0 ? fma(beta, Z[zo], val) : val;
+            }
+        }
+        return;
+    }
     if (!active) return;
     dense_epilogue<TS, NT, MT>(acc, P, r0, no, lane, own_gnode + own_off[s], afact, Z, omega, beta);
 }
@@ -962,7 +1038,7 @@ inline size_t dense_fused_lds(size_t entry_bytes, int Pp, int ld_max) {
 }  // namespace
 
 void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, double beta,
-                     hipStream_t s) {
+                     hipStream_t s, bool post) {
     int maxn = 0;
     for (size_t q = 0; q + 1 < r->h_sub_node_off.size(); ++q)
         maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
@@ -971,12 +1047,28 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
     const int v = r->dense_var;
     if (v == 2) {
         SG_REQUIRE(r->fused_ok, "the fused dense RAS variant does not fit this problem");
+        // the row-slice store (no mixing) where its LDS fits
+        const size_t row_lds = dense_post_lds(0, r->Pp, r->prec == SG_FP64 ? 8 : 4);
+        const bool row_store = !post && row_lds <= r->lds_max;
 #define SG_FUSED_NT(TS, BUF, N)                                                                    \
     case N:                                                                                        \
-        dense_fused_kernel<TS, N><<<r->nblk[2], 64 * kFusedWaves, r->fused_lds, s>>>(              \
-            r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p, r->sub_node_off.p,    \
-            r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF, R, r->afact.p, Z, omega, \
-            beta);                                                                                 \
+        if (post)                                                                                  \
+            dense_fused_kernel<TS, N, 1><<<r->nblk[2], 64 * kFusedWaves,                           \
+                                           std::max(r->fused_lds, r->post_lds), s>>>(              \
+                r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
+                r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
+                R, r->afact.p, Z, omega, beta, r->kron_post.p);                                    \
+        else if (row_store)                                                                        \
+            dense_fused_kernel<TS, N, 2><<<r->nblk[2], 64 * kFusedWaves,                           \
+                                           std::max(r->fused_lds, row_lds), s>>>(                  \
+                r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
+                r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
+                R, r->afact.p, Z, omega, beta, nullptr);                                           \
+        else                                                                                       \
+            dense_fused_kernel<TS, N, 0><<<r->nblk[2], 64 * kFusedWaves, r->fused_lds, s>>>(       \
+                r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
+                r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
+                R, r->afact.p, Z, omega, beta, nullptr);                                           \
         break;
         if (r->prec == SG_FP64) {
             switch (NT) {
@@ -1149,7 +1241,10 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
 
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
                   hipStream_t s) {
-    if (r->local_mode == SG_LOCAL_KRON) {
+    // the fused dense path mixes its output (Kronecker local solves)
+    const bool post = r->local_mode == SG_LOCAL_KRON && r->use_dense && r->dense_var == 2 &&
+                      r->post_ok && r->Pp == r->post_pp;
+    if (r->local_mode == SG_LOCAL_KRON && !post) {
         const unsigned g = (unsigned)((r->n + 63) / 64);
         if (r->P <= 40)
             kron_mix_mfma_reg_kernel<10><<<g, 64, (size_t)64 * r->P * 8, s>>>(r->n, r->P, r->kron_w.p,
@@ -1164,7 +1259,7 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
         R = r->kron_t.p;
     }
     if (r->use_dense) {
-        ras_dense_apply(r, R, Z, omega, beta, s);
+        ras_dense_apply(r, R, Z, omega, beta, s, post);
         return;
     }
     const int nch = (r->P + kColChunk - 1) / kColChunk;
@@ -1340,6 +1435,7 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
         int lds_max = 0;
         HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, r->device));
         r->fused_lds = dense_fused_lds(ts, r->Pp, ld_max);
+        r->lds_max = (size_t)lds_max;
         r->fused_ok = r->Pp / 16 <= fused_max_nt(r->prec) && r->fused_lds <= (size_t)lds_max;
         r->xg.alloc((size_t)r->h_xoff[ns] * ts);
         HIP_OK(hipMemsetAsync(r->xg.p, 0, r->xg.bytes(), s));
@@ -1768,6 +1864,17 @@ void ras_kron_weights(sg_ras* r, const sg_op* op, hipStream_t s) {
     for (int k = 0; k < P; ++k)
         for (int j = 0; j < P; ++j) W[(size_t)k * Pw + j] = I[(size_t)k * P + j] * op->h_afact[j];
     r->kron_w.upload(W, s);
+    // Gt^{-1} [P x Pp] for the output mixing of the fused path
+    const int Pp = 16 * ((P + 15) / 16);
+    std::vector<double> post((size_t)P * Pp, 0.0);
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j) post[(size_t)k * Pp + j] = I[(size_t)k * P + j];
+    r->kron_post.upload(post, s);
+    int lds_max = 0;
+    HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, r->device));
+    r->post_pp = Pp;
+    r->post_lds = dense_post_lds(P, Pp, r->prec == SG_FP64 ? 8 : 4);
+    r->post_ok = r->post_lds <= (size_t)lds_max;
     const size_t N = (size_t)r->n * P;
     if (r->kron_t.n < N) r->kron_t.alloc(N);
     HIP_OK(hipStreamSynchronize(s));

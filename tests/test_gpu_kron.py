@@ -18,6 +18,7 @@ CASES = {
     "c4_ragged": dict(name="c4", nc=23, sub=(3, 5)),
     "c3_40": dict(name="c3", nc=40, sub=(4, 4)),          # P = 84
     "m5p3": dict(name="c1", nc=24, M=5, p=3, sub=(3, 3)),  # P = 56
+    "m2p3": dict(name="c1", nc=24, M=2, p=3, sub=(3, 3)),  # P = 10: the FP64 fused path
 }
 
 
@@ -37,7 +38,7 @@ def _host(t, shape):
     return t.cpu().numpy().reshape(shape)
 
 
-@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40", "m5p3"])
+@pytest.mark.parametrize("key", ["c1_64", "c4_ragged", "c3_40", "m5p3", "m2p3"])
 def test_kron_factor_and_ras_match_oracle(key):
     pr, S = _setup(key)
     subs = oras.ras_setup(S.K[0], pr.owner, pr.n_sub, S.adj, pr.overlap)
@@ -70,6 +71,33 @@ def test_kron_factor_and_ras_match_oracle(key):
             B.ras_local_factor(g.ras, S.P)
         with pytest.raises(B.SgError):
             B.ras_set_local(g.ras, g.op, 5)
+
+
+@pytest.mark.parametrize("key", ["c1_64", "c4_ragged"])
+def test_kron_bf16_fused_output_mixing(key):
+    """The BF16 fused path applies the Kronecker mixing to its output
+    (Z = N(R) Gt^{-1}) instead of its input; the other BF16 dense paths mix
+    the input.  Both equal the oracle up to the BF16 rounding of the
+    operands (a relative 2e-2 covers the 8-bit significand of R and of the
+    stored inverse rows), and each other to the same level."""
+    pr, S = _setup(key)
+    subs = oras.ras_setup(S.K[0], pr.owner, pr.n_sub, S.adj, pr.overlap)
+    Gt = oras.kron_factor(S.K, S.G)
+    R = np.random.default_rng(43).standard_normal((pr.mesh.n, S.P))
+    ref = oras.ras_apply_kron(subs, R, Gt)
+    out = {}
+    with GpuSG(pr, prec="bf16", coarse="none", local="kron") as g:
+        Rd = torch.from_numpy(R.ravel()).cuda()
+        for path in ("dense", "fused"):
+            B.ras_select(g.ras, path)
+            Zd = torch.zeros_like(Rd)
+            B.ras_apply(g.ras, Rd, Zd)
+            out[path] = _host(Zd, R.shape)
+            err = np.linalg.norm(out[path] - ref) / np.linalg.norm(ref)
+            print(f"[gpu] {key} kron bf16 {path}: {err:.2e}", flush=True)
+            assert err < 2e-2
+    d = np.linalg.norm(out["fused"] - out["dense"]) / np.linalg.norm(out["dense"])
+    assert d < 2e-2
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16"])
