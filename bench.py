@@ -236,7 +236,7 @@ def stochastic_sweep(args, torch, shapes=None, nc=None) -> dict:
     return {"sweep": True, "nc": nc, "local_solves": args.local, "rows": rows}
 
 
-def _timed_solve(g, pr, omega, torch, graph=True, ortho="block2"):
+def _timed_solve(g, pr, omega, torch, graph=True, ortho="block3"):
     """One warm solve, then one timed: (milliseconds, info)."""
     g.solve(pr.restart, pr.rtol, omega=omega, use_graph=graph, ortho=ortho)
     torch.cuda.synchronize()
@@ -631,9 +631,10 @@ def main() -> int:
                     help="with --matvec-only: time the matrix-free apply")
     ap.add_argument("--matvec-only", action="store_true",
                     help="time only the SG matvec (for counter collection) and print its figures")
-    ap.add_argument("--ortho", default="block2", choices=["mgs", "cgs2", "cgs", "block2"],
+    ap.add_argument("--ortho", default="block3",
+                    choices=["mgs", "cgs2", "cgs", "block2", "block3", "block4"],
                     help="Arnoldi orthogonalisation")
-    ap.add_argument("--ortho-compare", default="cgs,mgs",
+    ap.add_argument("--ortho-compare", default="block2,block4,cgs,mgs",
                     help="other orthogonalisations timed on the mixed solve (comma list)")
     ap.add_argument("--ras-path", default="auto",
                     choices=["auto", "sweep", "dense", "dense32", "fused"],

@@ -445,19 +445,21 @@ typedef enum {
                             /* more than 1 - 1/sqrt(2) (Daniel-Gragg-Kaufman-  */
                             /* Stewart)                                       */
     SG_ORTHO_CGS = 2,       /* classical, one pass                           */
-    SG_ORTHO_CGS_BLOCK2 = 3 /* classical, one pass over the basis for two    */
-                            /* directions: step pair (j, j+1) takes          */
-                            /* u1 = A M v_j and u2 = A M u1 (flexible        */
-                            /* direction of column j+1: M u1), projects both */
-                            /* against v_0..v_j together, then u2 against    */
-                            /* u1 (norms from the projected Gram matrix, the */
-                            /* norm of v_{j+2} recomputed where the 2 x 2    */
-                            /* step cancels more than 1 - 1e-4 of ||u2||^2). */
-                            /* Same Krylov space as one step at a time for a */
-                            /* fixed linear preconditioner; the basis is     */
-                            /* read about half as often.  Convergence is     */
-                            /* checked after every pair; an odd restart      */
-                            /* length ends with a single step.               */
+    SG_ORTHO_CGS_BLOCK2 = 3,/* classical, one pass over the basis for a      */
+                            /* block of 2 directions: the block at column j  */
+                            /* takes u_1 = A M v_j, u_{t+1} = A M u_t (the   */
+                            /* flexible direction of column j+t is M u_t),   */
+                            /* projects all against v_0..v_j together, then  */
+                            /* orthonormalises them by a Cholesky factor of  */
+                            /* their Gram matrix (repeated once where a      */
+                            /* pivot keeps less than 1e-4 of its column's    */
+                            /* norm).  Same Krylov space as one step at a    */
+                            /* time for a fixed linear preconditioner; the   */
+                            /* basis is read once per block.  Convergence is */
+                            /* checked after every block; the blocks shrink  */
+                            /* to fit the restart length and the step budget.*/
+    SG_ORTHO_CGS_BLOCK3 = 4,/* the same with blocks of 3 directions          */
+    SG_ORTHO_CGS_BLOCK4 = 5 /* the same with blocks of 4 directions          */
 } sg_ortho;
 
 typedef struct {

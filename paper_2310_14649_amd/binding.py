@@ -20,8 +20,10 @@ SG_FP64, SG_FP32, SG_BF16 = 0, 1, 2
 SG_COARSE_NONE, SG_COARSE_MEAN_EXACT, SG_COARSE_AMG, SG_COARSE_GEOMETRIC = 0, 1, 2, 3
 PREC = {"fp64": SG_FP64, "fp32": SG_FP32, "bf16": SG_BF16}
 SG_ORTHO_MGS, SG_ORTHO_CGS_DGKS, SG_ORTHO_CGS, SG_ORTHO_CGS_BLOCK2 = 0, 1, 2, 3
+SG_ORTHO_CGS_BLOCK3, SG_ORTHO_CGS_BLOCK4 = 4, 5
 ORTHO = {"mgs": SG_ORTHO_MGS, "cgs2": SG_ORTHO_CGS_DGKS, "cgs": SG_ORTHO_CGS,
-         "block2": SG_ORTHO_CGS_BLOCK2}
+         "block2": SG_ORTHO_CGS_BLOCK2, "block3": SG_ORTHO_CGS_BLOCK3,
+         "block4": SG_ORTHO_CGS_BLOCK4}
 
 _vp = C.c_void_p
 _i32p = C.POINTER(C.c_int32)

@@ -197,178 +197,289 @@ __global__ __launch_bounds__(kVT) void cgs_update_kernel(int64_t N, int ni, int6
     if (threadIdx.x == 0) part_out[blockIdx.x] = s;
 }
 
-// ---- two Krylov directions per Gram-Schmidt pass (SG_ORTHO_CGS_BLOCK2).
-// Step pair (j, j+1): u1 = A M v_j and u2 = A M u1 (the flexible direction
-// of column j+1 is M u1), both projected against v_0..v_j in one pass over
-// the basis, then against each other.  part[(2q + t) nb + block] = partial
-// <u_{t+1}, v_{i0+q}>.
-constexpr int kB2 = 16;         // basis vectors per work-group column
+// ---- S Krylov directions per Gram-Schmidt pass (SG_ORTHO_CGS_BLOCK2..4).
+// Block (j .. j+S-1): u_1 = A M v_j and u_{t+1} = A M u_t (the flexible
+// direction of column j+t is M u_t), all projected against v_0..v_j in one
+// pass over the basis, then orthonormalised among themselves by a Cholesky
+// factorisation R of their Gram matrix (U = V_new R), repeated once on the
+// new vectors where a diagonal of R keeps less than 1e-4 of its column's
+// squared norm.  The directions are stored consecutively in V (slots j+1 ..
+// j+S), with stride ldv.  part[(S q + t) nb + block] = partial <u_t, v_q>.
+template <int S> struct BlockGS {
+    static constexpr int kB = S == 2 ? 16 : (S == 3 ? 10 : 8);   // basis vectors per column
+    static constexpr int NG = S * (S + 1) / 2;                   // Gram entries (t <= u)
+};
 
-__global__ __launch_bounds__(kVT) void cgs2_dot_kernel(int64_t N, int nb, int ni, int64_t ldv,
-                                                       const double* __restrict__ u1,
-                                                       const double* __restrict__ u2,
+template <int S>
+__global__ __launch_bounds__(kVT) void cgsb_dot_kernel(int64_t N, int nb, int ni, int64_t ldv,
+                                                       const double* __restrict__ U,
                                                        const double* __restrict__ V,
                                                        double* __restrict__ part) {
-    __shared__ double sh[kVT / 64][2 * kB2];
-    const int ib0 = blockIdx.y * kB2;
-    const int cnt = min(kB2, ni - ib0);
-    double a1[kB2], a2[kB2];
+    constexpr int kB = BlockGS<S>::kB;
+    __shared__ double sh[kVT / 64][S * kB];
+    const int ib0 = blockIdx.y * kB;
+    const int cnt = min(kB, ni - ib0);
+    double a[kB][S];
 #pragma unroll
-    for (int q = 0; q < kB2; ++q) a1[q] = a2[q] = 0.0;
+    for (int q = 0; q < kB; ++q)
+#pragma unroll
+        for (int t = 0; t < S; ++t) a[q][t] = 0.0;
     const int64_t N2 = N >> 1;
-    const double2* x2 = reinterpret_cast<const double2*>(u1);
-    const double2* y2 = reinterpret_cast<const double2*>(u2);
     for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N2; e += (int64_t)gridDim.x * kVT) {
-        const double2 x = x2[e], y = y2[e];
+        double2 x[S];
 #pragma unroll
-        for (int q = 0; q < kB2; ++q)
+        for (int t = 0; t < S; ++t) x[t] = reinterpret_cast<const double2*>(U + (size_t)t * ldv)[e];
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
             if (q < cnt) {
                 const double2 v = reinterpret_cast<const double2*>(V + (size_t)(ib0 + q) * ldv)[e];
-                a1[q] = fma(x.y, v.y, fma(x.x, v.x, a1[q]));
-                a2[q] = fma(y.y, v.y, fma(y.x, v.x, a2[q]));
+#pragma unroll
+                for (int t = 0; t < S; ++t) a[q][t] = fma(x[t].y, v.y, fma(x[t].x, v.x, a[q][t]));
             }
     }
     if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        const double x = u1[N - 1], y = u2[N - 1];
 #pragma unroll
-        for (int q = 0; q < kB2; ++q)
+        for (int q = 0; q < kB; ++q)
             if (q < cnt) {
                 const double v = V[(size_t)(ib0 + q) * ldv + N - 1];
-                a1[q] = fma(x, v, a1[q]);
-                a2[q] = fma(y, v, a2[q]);
+#pragma unroll
+                for (int t = 0; t < S; ++t) a[q][t] = fma(U[(size_t)t * ldv + N - 1], v, a[q][t]);
             }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < kB2; ++q) {
-        const double t1 = wave_sum(a1[q]), t2 = wave_sum(a2[q]);
-        if (lane == 0) {
-            sh[wv][2 * q] = t1;
-            sh[wv][2 * q + 1] = t2;
+    for (int q = 0; q < kB; ++q)
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const double r = wave_sum(a[q][t]);
+            if (lane == 0) sh[wv][S * q + t] = r;
         }
-    }
     __syncthreads();
-    if (threadIdx.x < 2 * cnt) {
+    if (threadIdx.x < S * cnt) {
         const int r = threadIdx.x;
         double t = 0.0;
         for (int u = 0; u < kVT / 64; ++u) t += sh[u][r];
-        part[(size_t)(2 * ib0 + r) * nb + blockIdx.x] = t;
+        part[(size_t)(S * ib0 + r) * nb + blockIdx.x] = t;
     }
 }
 
-// Block r < 2 ni reduces coefficient r: c_t[q] with q = r / 2, t = r % 2,
-// into column j (t = 0) or j + 1 (t = 1) of the Hessenberg.
-__global__ __launch_bounds__(kVT) void cgs2_reduce_kernel(int nb, const double* __restrict__ part,
-                                                          double* __restrict__ hj,
-                                                          double* __restrict__ hj1) {
+// Block r < S ni reduces coefficient r: c_t[q], q = r / S, t = r % S, into
+// column j + t of the Hessenberg (column-major, leading dimension ldh).
+template <int S>
+__global__ __launch_bounds__(kVT) void cgsb_reduce_kernel(int nb, const double* __restrict__ part,
+                                                          double* __restrict__ hj, int ldh) {
     __shared__ double sh[kVT];
     const int r = blockIdx.x;
     const double t = reduce_partials(part + (size_t)r * nb, nb, sh);
-    if (threadIdx.x == 0) ((r & 1) ? hj1 : hj)[r >> 1] = t;
+    if (threadIdx.x == 0) hj[(size_t)(r % S) * ldh + r / S] = t;
 }
 
-// u1 -= sum_q c1_q v_q, u2 -= sum_q c2_q v_q (one pass over the basis);
-// part_out[t nb + block] = partial <u1,u1>, <u1,u2>, <u2,u2> (t = 0, 1, 2)
-// of the projected vectors.
-__global__ __launch_bounds__(kVT) void cgs2_update_kernel(int64_t N, int nb, int ni, int64_t ldv,
-                                                          double* __restrict__ u1,
-                                                          double* __restrict__ u2,
+// U_t -= sum_q c_t[q] v_q (one pass over the basis); part_out[g nb + block]
+// = partial Gram entry g of the projected vectors (pairs t <= u in order).
+template <int S>
+__global__ __launch_bounds__(kVT) void cgsb_update_kernel(int64_t N, int nb, int ni, int64_t ldv,
+                                                          double* __restrict__ U,
                                                           const double* __restrict__ V,
-                                                          const double* __restrict__ c1,
-                                                          const double* __restrict__ c2,
+                                                          const double* __restrict__ hj, int ldh,
                                                           double* __restrict__ part_out) {
-    __shared__ double cs1[64], cs2[64];
+    constexpr int NG = BlockGS<S>::NG;
+    __shared__ double cs[S][64];
     __shared__ double sh[kVT];
-    for (int q = threadIdx.x; q < ni; q += kVT) {
-        cs1[q] = c1[q];
-        cs2[q] = c2[q];
-    }
+    for (int q = threadIdx.x; q < ni; q += kVT)
+#pragma unroll
+        for (int t = 0; t < S; ++t) cs[t][q] = hj[(size_t)t * ldh + q];
     __syncthreads();
-    double g11 = 0.0, g12 = 0.0, g22 = 0.0;
+    double g[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) g[q] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
-        double x = u1[e], y = u2[e];
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
         for (int q = 0; q < ni; ++q) {
             const double v = V[(size_t)q * ldv + e];
-            x = fma(-cs1[q], v, x);
-            y = fma(-cs2[q], v, y);
+#pragma unroll
+            for (int t = 0; t < S; ++t) x[t] = fma(-cs[t][q], v, x[t]);
         }
-        u1[e] = x;
-        u2[e] = y;
-        g11 = fma(x, x, g11);
-        g12 = fma(x, y, g12);
-        g22 = fma(y, y, g22);
+        int k = 0;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            U[(size_t)t * ldv + e] = x[t];
+#pragma unroll
+            for (int u = t; u < S; ++u) {
+                g[k] = fma(x[t], x[u], g[k]);
+                ++k;
+            }
+        }
     }
-    const double s11 = block_sum(g11, sh), s12 = block_sum(g12, sh), s22 = block_sum(g22, sh);
-    if (threadIdx.x == 0) {
-        part_out[blockIdx.x] = s11;
-        part_out[nb + blockIdx.x] = s12;
-        part_out[2 * nb + blockIdx.x] = s22;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        const double r = block_sum(g[q], sh);
+        if (threadIdx.x == 0) part_out[(size_t)q * nb + blockIdx.x] = r;
     }
 }
 
-// The 2 x 2 step: r11 = ||u1||, r12 = <u1,u2>/r11, r22 = sqrt(||u2||^2 - r12^2);
-// v_{j+1} = u1/r11, v_{j+2} = (u2 - r12 v_{j+1})/r22 in place.  H(j+1, j) =
-// r11, H(j+1, j+1) = r12, H(j+2, j+1) = r22.  flag = 1: breakdown at column j
-// (u1 = 0), 2: at column j + 1; gate = 1 when r22^2 kept less than 1e-4 of
-// ||u2||^2, so the Pythagorean r22 is recomputed from the vector.
-__global__ __launch_bounds__(kVT) void pair_normalize_kernel(int64_t N, int nb,
-                                                             double* __restrict__ u1,
-                                                             double* __restrict__ u2,
-                                                             const double* __restrict__ part,
-                                                             double* __restrict__ hj,
-                                                             double* __restrict__ hj1, int j,
-                                                             double* __restrict__ flag,
-                                                             double* __restrict__ gate) {
+// Cholesky factor of the S x S Gram matrix reduced from part (entries t <= u
+// in order).  Returns the index of the first direction that broke down (its
+// pivot not positive) or S; R[t][u] for t <= u, zero past a breakdown.
+// *weak: a pivot kept less than 1e-4 of its column's diagonal.
+template <int S>
+__device__ inline int block_chol(const double* part, int nb, double* sh, double (&R)[S][S],
+                                 bool* weak) {
+    double G[S][S];
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+#pragma unroll
+        for (int u = t; u < S; ++u) {
+            G[t][u] = reduce_partials(part + (size_t)(k++) * nb, nb, sh);
+            G[u][t] = G[t][u];
+        }
+    int bad = S;
+    *weak = false;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+#pragma unroll
+        for (int u = 0; u < S; ++u) R[t][u] = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        if (bad < S) break;
+        double d = G[t][t];
+#pragma unroll
+        for (int q = 0; q < t; ++q) d -= R[q][t] * R[q][t];
+        if (!(d > 0.0)) { bad = t; break; }
+        if (d < 1e-4 * G[t][t]) *weak = true;
+        R[t][t] = sqrt(d);
+#pragma unroll
+        for (int u = t + 1; u < S; ++u) {
+            double o = G[t][u];
+#pragma unroll
+            for (int q = 0; q < t; ++q) o -= R[q][t] * R[q][u];
+            R[t][u] = o / R[t][t];
+        }
+    }
+    return bad;
+}
+
+// U = V_new R: V_new = U R^{-1} in place (forward substitution per entry);
+// H(j+1+q, j+t) = R[q][t]; flag = 1 + (first direction that broke down), 0
+// if none; gate = 1 where a pivot was weak (a second factorisation follows).
+template <int S>
+__global__ __launch_bounds__(kVT) void block_qr_kernel(int64_t N, int nb, int64_t ldv,
+                                                       double* __restrict__ U,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ hj, int ldh, int j,
+                                                       double* __restrict__ flag,
+                                                       double* __restrict__ gate) {
     __shared__ double sh[kVT];
-    const double g11 = reduce_partials(part, nb, sh);
-    const double g12 = reduce_partials(part + nb, nb, sh);
-    const double g22 = reduce_partials(part + 2 * nb, nb, sh);
-    const double r11 = sqrt(g11);
-    const double r12 = r11 > 0.0 ? g12 / r11 : 0.0;
-    const double r22sq = g22 - r12 * r12;
-    const double r22 = (r11 > 0.0 && r22sq > 0.0) ? sqrt(r22sq) : 0.0;
+    double R[S][S];
+    bool weak;
+    const int bad = block_chol<S>(part, nb, sh, R, &weak);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        hj[j + 1] = r11;
-        hj1[j + 1] = r12;
-        hj1[j + 2] = r22;
-        flag[0] = r11 == 0.0 ? 1.0 : (r22 == 0.0 ? 2.0 : 0.0);
-        gate[0] = (r22 > 0.0 && r22sq < 1e-4 * g22) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int q = 0; q <= t; ++q) hj[(size_t)t * ldh + j + 1 + q] = R[q][t];
+        flag[0] = bad < S ? (double)(bad + 1) : 0.0;
+        gate[0] = (bad == S && weak) ? 1.0 : 0.0;
     }
-    const double i11 = r11 > 0.0 ? 1.0 / r11 : 0.0;
-    const double i22 = r22 > 0.0 ? 1.0 / r22 : 0.0;
+    double inv[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) inv[t] = R[t][t] > 0.0 ? 1.0 / R[t][t] : 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
-        const double v1 = u1[e] * i11;
-        u1[e] = v1;
-        u2[e] = (u2[e] - r12 * v1) * i22;
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            double y = x[t];
+#pragma unroll
+            for (int q = 0; q < t; ++q) y = fma(-R[q][t], x[q], y);
+            x[t] = y * inv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) U[(size_t)t * ldv + e] = x[t];
     }
 }
 
-// Where the gate is set: part = partial <v, v> of v_{j+2}; then v_{j+2} and
-// H(j+2, j+1) rescaled by the exact norm (pair_rescale_kernel).
-__global__ __launch_bounds__(kVT) void gated_norm_kernel(int64_t N, const double* __restrict__ v,
+// Where the gate is set: the Gram partials of the new vectors ...
+template <int S>
+__global__ __launch_bounds__(kVT) void gated_gram_kernel(int64_t N, int nb, int64_t ldv,
+                                                         const double* __restrict__ U,
                                                          double* __restrict__ part,
                                                          const double* __restrict__ gate) {
     if (gate[0] == 0.0) return;
+    constexpr int NG = BlockGS<S>::NG;
     __shared__ double sh[kVT];
-    double a = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT)
-        a = fma(v[e], v[e], a);
-    const double s = block_sum(a, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    double g[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) g[q] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
+        int k = 0;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int u = t; u < S; ++u) {
+                g[k] = fma(x[t], x[u], g[k]);
+                ++k;
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        const double r = block_sum(g[q], sh);
+        if (threadIdx.x == 0) part[(size_t)q * nb + blockIdx.x] = r;
+    }
 }
 
-__global__ __launch_bounds__(kVT) void pair_rescale_kernel(int64_t N, int nb, double* __restrict__ v,
-                                                           const double* __restrict__ part,
-                                                           double* __restrict__ hj1, int j,
-                                                           const double* __restrict__ gate) {
+// ... and a second factorisation R2: V = V R2^{-1}, H's block R <- R2 R.
+template <int S>
+__global__ __launch_bounds__(kVT) void gated_requr_kernel(int64_t N, int nb, int64_t ldv,
+                                                          double* __restrict__ U,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ hj, int ldh,
+                                                          int j, const double* __restrict__ gate) {
     if (gate[0] == 0.0) return;
     __shared__ double sh[kVT];
-    const double nrm = sqrt(reduce_partials(part, nb, sh));
-    if (!(nrm > 0.0)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) hj1[j + 2] *= nrm;
-    const double inv = 1.0 / nrm;
-    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT)
-        v[e] *= inv;
+    double R2[S][S];
+    bool weak;
+    const int bad = block_chol<S>(part, nb, sh, R2, &weak);
+    if (bad < S) return;     // past the gate the new vectors are independent
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double R[S][S];
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int q = 0; q < S; ++q) R[q][t] = q <= t ? hj[(size_t)t * ldh + j + 1 + q] : 0.0;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int q = 0; q <= t; ++q) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = q; k <= t; ++k) a = fma(R2[q][k], R[k][t], a);
+                hj[(size_t)t * ldh + j + 1 + q] = a;
+            }
+    }
+    double inv[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) inv[t] = 1.0 / R2[t][t];
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            double y = x[t];
+#pragma unroll
+            for (int q = 0; q < t; ++q) y = fma(-R2[q][t], x[q], y);
+            x[t] = y * inv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) U[(size_t)t * ldv + e] = x[t];
+    }
 }
 
 // Second pass wanted if ||w_after||^2 < ||w_before||^2 / 2.
@@ -657,7 +768,7 @@ size_t fgmres_ws_ns(int n, int P, int ns, int restart) {
     size_t b = align_up(N * 8) * (2 * m + 2);                 // V (m+1), Z (m), w
     b += precond_ws_ns(n, P, ns);
     b += 2 * align_up(kMaxRedBlocks * 8);                     // partial sums
-    b += align_up((2 * m + 4) * kMaxRedBlocks * 8);           // Gram-Schmidt partials
+    b += align_up((4 * m + 8) * kMaxRedBlocks * 8);           // Gram-Schmidt partials
     b += align_up((m + 1) * 8) + align_up(64);                // correction, flags
     b += align_up((m + 1) * m * 8) + 4 * align_up((m + 1) * 8) + align_up(64);
     // the damping estimate reuses the front of the workspace
@@ -726,7 +837,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     SG_REQUIRE(m >= 1 && m <= 64, "restart=%d outside [1,64]", m);
     SG_REQUIRE(opts->max_it >= 1, "max_it must be >= 1");
     SG_REQUIRE(opts->rtol > 0.0, "rtol must be > 0");
-    SG_REQUIRE(opts->ortho >= SG_ORTHO_MGS && opts->ortho <= SG_ORTHO_CGS_BLOCK2,
+    SG_REQUIRE(opts->ortho >= SG_ORTHO_MGS && opts->ortho <= SG_ORTHO_CGS_BLOCK4,
                "bad orthogonalisation");
     const size_t need = fgmres_ws_np(A.n, A.P, amg, m);
     if (!ws || ws_bytes < need)
@@ -742,7 +853,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
     char* q = pws + precond_ws_np(A.n, A.P, amg);
     double* part0 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
     double* part1 = reinterpret_cast<double*>(q); q += align_up(kMaxRedBlocks * 8);
-    double* gsp = reinterpret_cast<double*>(q); q += align_up((size_t)(2 * m + 4) * kMaxRedBlocks * 8);
+    double* gsp = reinterpret_cast<double*>(q); q += align_up((size_t)(4 * m + 8) * kMaxRedBlocks * 8);
     double* corr = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * 8);
     double* gsf = reinterpret_cast<double*>(q); q += align_up(64);   // ww_before, flag
     double* H = reinterpret_cast<double*>(q); q += align_up((size_t)(m + 1) * m * 8);
@@ -822,49 +933,56 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
             HIP_LAUNCH_OK();
         };
-        // Step pair (j, j + 1) of SG_ORTHO_CGS_BLOCK2: z_j = M v_j, u1 = A z_j,
-        // z_{j+1} = M u1, u2 = A z_{j+1}; u1 and u2 projected against
-        // v_0..v_j in one pass (coefficients into columns j and j + 1 of H),
-        // then orthonormalised against each other into v_{j+1}, v_{j+2}, so
-        // that A z_i = V H(:, i) holds for both columns.
-        const bool block = opts->ortho == SG_ORTHO_CGS_BLOCK2;
-        auto pair_step = [&](int j, hipStream_t st) {
+        // Block (j .. j+S-1) of SG_ORTHO_CGS_BLOCK2..4: z_j = M v_j, u_1 = A z_j,
+        // z_{j+t} = M u_t, u_{t+1} = A z_{j+t}; the u projected against
+        // v_0..v_j in one pass (coefficients into columns j .. j+S-1 of H),
+        // then orthonormalised among themselves (Cholesky of their Gram
+        // matrix) into v_{j+1} .. v_{j+S}, so that A z_i = V H(:, i) holds
+        // for every column of the block.
+        const int sblock = opts->ortho == SG_ORTHO_CGS_BLOCK2 ? 2
+                         : opts->ortho == SG_ORTHO_CGS_BLOCK3 ? 3
+                         : opts->ortho == SG_ORTHO_CGS_BLOCK4 ? 4 : 1;
+        auto block_step = [&](int j, int S, hipStream_t st) {
             const int64_t ldv = (int64_t)(vb / 8);
-            double* vj = V + (size_t)j * ldv;
-            double* u1 = V + (size_t)(j + 1) * ldv;
-            double* u2 = V + (size_t)(j + 2) * ldv;
-            double* zj = Zb + (size_t)j * ldv;
-            double* zj1 = Zb + (size_t)(j + 1) * ldv;
-            precond_apply(A, ras, amg, omega, vj, zj, pws, st);
-            linop_apply(A, zj, u1, 1.0, 0.0, nullptr, st);
-            precond_apply(A, ras, amg, omega, u1, zj1, pws, st);
-            linop_apply(A, zj1, u2, 1.0, 0.0, nullptr, st);
+            for (int t = 0; t < S; ++t) {
+                const double* src = V + (size_t)(j + t) * ldv;     // v_j, then u_1 .. u_{S-1}
+                double* zt = Zb + (size_t)(j + t) * ldv;
+                precond_apply(A, ras, amg, omega, src, zt, pws, st);
+                linop_apply(A, zt, V + (size_t)(j + t + 1) * ldv, 1.0, 0.0, nullptr, st);
+            }
             const int ni = j + 1;
+            double* U = V + (size_t)(j + 1) * ldv;
             double* hj = H + (size_t)j * (m + 1);
-            double* hj1 = H + (size_t)(j + 1) * (m + 1);
-            const dim3 dgrid(nb, (ni + kB2 - 1) / kB2);
-            cgs2_dot_kernel<<<dgrid, kVT, 0, st>>>(N, nb, ni, ldv, u1, u2, V, gsp);
-            HIP_LAUNCH_OK();
-            cgs2_reduce_kernel<<<2 * ni, kVT, 0, st>>>(nb, gsp, hj, hj1);
-            HIP_LAUNCH_OK();
-            cgs2_update_kernel<<<nb, kVT, 0, st>>>(N, nb, ni, ldv, u1, u2, V, hj, hj1, gsp);
-            HIP_LAUNCH_OK();
-            pair_normalize_kernel<<<nb, kVT, 0, st>>>(N, nb, u1, u2, gsp, hj, hj1, j, scal + 1,
-                                                      gsf + 3);
-            HIP_LAUNCH_OK();
-            gated_norm_kernel<<<nb, kVT, 0, st>>>(N, u2, part[0], gsf + 3);
-            HIP_LAUNCH_OK();
-            pair_rescale_kernel<<<nb, kVT, 0, st>>>(N, nb, u2, part[0], hj1, j, gsf + 3);
-            HIP_LAUNCH_OK();
-            givens_kernel<<<1, 1, 0, st>>>(j, m + 1, H, cs, sn, g, scal);
-            HIP_LAUNCH_OK();
-            givens_kernel<<<1, 1, 0, st>>>(j + 1, m + 1, H, cs, sn, g, scal);
-            HIP_LAUNCH_OK();
+            const int ldh = m + 1;
+            auto go = [&](auto tag) {
+                constexpr int SB = decltype(tag)::value;
+                const dim3 dgrid(nb, (ni + BlockGS<SB>::kB - 1) / BlockGS<SB>::kB);
+                cgsb_dot_kernel<SB><<<dgrid, kVT, 0, st>>>(N, nb, ni, ldv, U, V, gsp);
+                HIP_LAUNCH_OK();
+                cgsb_reduce_kernel<SB><<<SB * ni, kVT, 0, st>>>(nb, gsp, hj, ldh);
+                HIP_LAUNCH_OK();
+                cgsb_update_kernel<SB><<<nb, kVT, 0, st>>>(N, nb, ni, ldv, U, V, hj, ldh, gsp);
+                HIP_LAUNCH_OK();
+                block_qr_kernel<SB><<<nb, kVT, 0, st>>>(N, nb, ldv, U, gsp, hj, ldh, j, scal + 1,
+                                                         gsf + 3);
+                HIP_LAUNCH_OK();
+                gated_gram_kernel<SB><<<nb, kVT, 0, st>>>(N, nb, ldv, U, gsp, gsf + 3);
+                HIP_LAUNCH_OK();
+                gated_requr_kernel<SB><<<nb, kVT, 0, st>>>(N, nb, ldv, U, gsp, hj, ldh, j, gsf + 3);
+                HIP_LAUNCH_OK();
+            };
+            if (S == 2) go(std::integral_constant<int, 2>{});
+            else if (S == 3) go(std::integral_constant<int, 3>{});
+            else go(std::integral_constant<int, 4>{});
+            for (int t = 0; t < S; ++t) {
+                givens_kernel<<<1, 1, 0, st>>>(j + t, m + 1, H, cs, sn, g, scal);
+                HIP_LAUNCH_OK();
+            }
         };
-        // columns of the unit that starts at column j: a pair in block mode
-        // while both columns fit the cycle and the step budget
+        // columns of the unit that starts at column j: a block of up to
+        // sblock directions while they fit the cycle and the step budget
         auto width = [&](int j, int its_now) {
-            return (block && j + 1 < m && its_now + 2 <= opts->max_it) ? 2 : 1;
+            return std::max(1, std::min(sblock, std::min(m - j, opts->max_it - its_now)));
         };
         if (bnorm == 0.0) {
             Vec::fill(N, 0.0, x, s);
@@ -882,7 +1000,7 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
             // graph (captured on first use)
             auto launch_unit = [&](int j, int w) {
                 auto run = [&](hipStream_t st) {
-                    if (w == 2) pair_step(j, st);
+                    if (w >= 2) block_step(j, w, st);
                     else arnoldi_step(j, st);
                 };
                 if (!opts->use_graph || (amg && inner_active(amg))) {
@@ -890,9 +1008,10 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                     return;
                 }
                 hipGraphExec_t exec = nullptr;
-                const int kortho = w == 2 ? (int)SG_ORTHO_CGS_BLOCK2
-                                          : (opts->ortho == SG_ORTHO_CGS_BLOCK2 ? (int)SG_ORTHO_CGS
-                                                                                : opts->ortho);
+                // a block's graph is keyed by its width, a single step by the
+                // orthogonalisation it runs (blocks end with single-pass CGS)
+                const int kortho = w >= 2 ? 100 + w
+                                          : (sblock > 1 ? (int)SG_ORTHO_CGS : opts->ortho);
                 GraphKey key{key_op, ras, amg, ws, ws_bytes, m, j, kortho, 0};
                 std::memcpy(&key.omega_bits, &omega, sizeof(double));
                 {
@@ -953,10 +1072,11 @@ int fgmres_core(const LinOp& A, const void* key_op, int device, const sg_ras* ra
                     }
                     HIP_OK(hipEventSynchronize(pin.ev[unit & 1]));
                     const double hs[2] = {hb[0], hb[1]};
-                    // a pair whose first direction broke down keeps one column
-                    const bool first_only = w == 2 && hs[1] == 1.0;
-                    its += first_only ? 1 : w;
-                    jd = first_only ? j + 1 : jn;
+                    // a block whose direction t broke down keeps t + 1 columns
+                    // (flag = t + 1; a single step's flag 1 keeps its column)
+                    const int keep = (w >= 2 && hs[1] >= 1.0) ? (int)hs[1] : w;
+                    its += keep;
+                    jd = j + keep;
                     if (!std::isfinite(hs[0]))
                         SG_THROW(SG_ERR_NUMERIC, "Arnoldi produced a non-finite value");
                     relres = hs[0] / bnorm;

@@ -71,7 +71,7 @@ def test_indefinite_local_block_is_a_numeric_error():
             B.sg_destroy_ras(ras)
 
 
-@pytest.mark.parametrize("ortho", ["mgs", "block2"])
+@pytest.mark.parametrize("ortho", ["mgs", "block2", "block3", "block4"])
 def test_lucky_breakdown_returns_exact_solution(ortho):
     """One unknown, deterministic (P = 1), no preconditioner: A v = k v
     exactly, so the first Arnoldi step leaves w - h v = 0, the breakdown

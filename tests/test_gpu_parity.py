@@ -613,18 +613,23 @@ def test_fgmres_classical_gram_schmidt(built, key, ortho):
     assert torch.equal(x, x2)
 
 
+BLOCK = {"block2": 2, "block3": 3, "block4": 4}
+
+
+@pytest.mark.parametrize("ortho", list(BLOCK))
 @pytest.mark.parametrize("key,coarse", [("c0", "mean"), ("c1_64", "amg"), ("c4_ragged", "amg"),
                                        ("c3_40", "amg"), ("j4", "amg")])
-def test_fgmres_block2_gram_schmidt(built, key, coarse):
-    """Two directions per Gram-Schmidt pass (step pairs u1 = A M v_j,
-    u2 = A M u1): with the fixed FP64 preconditioner the Krylov spaces are
-    those of one step at a time, so after every pair (column 2k - 1) the
-    residual estimate equals modified Gram-Schmidt's after the same column;
-    the solution reaches the direct one (the MGS solve for the P = 84
-    case), and graph replay equals the eager run bit for bit."""
+def test_fgmres_block_gram_schmidt(built, key, coarse, ortho):
+    """S directions per Gram-Schmidt pass (blocks u_1 = A M v_j,
+    u_{t+1} = A M u_t): with the fixed FP64 preconditioner the Krylov spaces
+    are those of one step at a time, so after every block (column S k - 1)
+    the residual estimate equals modified Gram-Schmidt's after the same
+    column; the solution reaches the direct one (the MGS solve for the
+    P = 84 case), and graph replay equals the eager run bit for bit."""
     pr, S, g = built(key, coarse=coarse)
+    sb = BLOCK[ortho]
     restart = 30 if key == "c0" else 50
-    x, info = g.solve(restart, 1e-10, ortho="block2")
+    x, info = g.solve(restart, 1e-10, ortho=ortho)
     assert info["converged"] and info["true_relres"] <= 1e-10
     x_m, info_m = g.solve(restart, 1e-10, ortho="mgs")
     if key == "c3_40":
@@ -633,38 +638,41 @@ def test_fgmres_block2_gram_schmidt(built, key, coarse):
         ref = osg.sg_solve_direct(S.K, S.G, S.B)
     assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
     hb, hm = info["history"], info_m["history"]
-    npair = min(len(hb) - 1, (len(hm) - 1) // 2, 8)
-    assert npair >= 3
-    for k in range(1, npair + 1):
-        assert hb[k] == pytest.approx(hm[2 * k], rel=1e-6), k
-    print(f"[gpu] block2 {key}: its={info['iterations']} (mgs {info_m['iterations']})", flush=True)
-    assert abs(info["iterations"] - info_m["iterations"]) <= 2
-    x2, info2 = g.solve(restart, 1e-10, ortho="block2", use_graph=True)
+    nblk = min(len(hb) - 1, (len(hm) - 1) // sb, 8, restart // sb)
+    assert nblk >= 2
+    for k in range(1, nblk + 1):
+        assert hb[k] == pytest.approx(hm[sb * k], rel=1e-6), k
+    print(f"[gpu] {ortho} {key}: its={info['iterations']} (mgs {info_m['iterations']})", flush=True)
+    assert abs(info["iterations"] - info_m["iterations"]) <= sb
+    x2, info2 = g.solve(restart, 1e-10, ortho=ortho, use_graph=True)
     assert info2["iterations"] == info["iterations"] and torch.equal(x, x2)
 
 
-def test_fgmres_block2_odd_restart_and_cap(built):
-    """An odd restart length ends each cycle with one single step; an odd
-    step budget ends with one single step; both keep the solution exact."""
+@pytest.mark.parametrize("ortho", list(BLOCK))
+def test_fgmres_block_odd_restart_and_cap(built, ortho):
+    """A restart length that the block does not divide ends each cycle with
+    a shorter block or a single step; so does a step budget; both keep the
+    solution exact and the budget exact."""
     pr, S, g = built("c4_ragged")
     ref = osg.sg_solve_direct(S.K, S.G, S.B)
-    x, info = g.solve(7, 1e-10, ortho="block2", max_it=2000)
+    x, info = g.solve(7, 1e-10, ortho=ortho, max_it=2000)
     assert info["converged"] and info["restarts"] >= 1
     assert np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref) < 1e-8
-    x5, info5 = g.solve(10, 1e-14, ortho="block2", max_it=5)
+    x5, info5 = g.solve(10, 1e-14, ortho=ortho, max_it=5)
     assert info5["iterations"] == 5 and info5["status"] == B.SG_NOT_CONVERGED
     x5m, info5m = g.solve(10, 1e-14, ortho="mgs", max_it=5)
     assert info5["true_relres"] == pytest.approx(info5m["true_relres"], rel=1e-6)
 
 
+@pytest.mark.parametrize("ortho", ["block2", "block4"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_fgmres_block2_mixed_precision_refines_to_fp64(built, prec):
+def test_fgmres_block_mixed_precision_refines_to_fp64(built, prec, ortho):
     """With a low-precision (not exactly linear) preconditioner the pair's
     second direction M u1 is still a valid flexible direction: the solve
     reaches the FP64 solution."""
     pr, S, g = built("c1_64", prec=prec)
     ref = osg.sg_solve_direct(S.K, S.G, S.B)
-    x, info = g.solve(50, 1e-10, ortho="block2")
+    x, info = g.solve(50, 1e-10, ortho=ortho)
     err = np.linalg.norm(_to_host(x, ref.shape) - ref) / np.linalg.norm(ref)
     assert info["converged"] and err < 1e-6
 
