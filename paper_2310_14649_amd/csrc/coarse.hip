@@ -936,9 +936,17 @@ void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s) {
     else coarse_solve_base(a, b, x, s);
 }
 
+bool coarse_has_az(const sg_amg* a, const sg_op* op) {
+    return op && a->az_op == op && op->fixed_values;
+}
+
+const int32_t* coarse_owner_dev(const sg_amg* a) {
+    return (a->kind == SG_COARSE_MEAN_EXACT || a->kind == SG_COARSE_AMG) ? a->owner.p : nullptr;
+}
+
 bool coarse_residual_update(const sg_amg* a, const sg_op* op, const double* ec, double* T,
                             hipStream_t s) {
-    if (!op || a->az_op != op || !op->fixed_values) return false;
+    if (!coarse_has_az(a, op)) return false;
     const int ns = a->n_sub, P = a->P, L = a->L;
     az_mix_kernel<<<(L * ns * P + 255) / 256, 256, 0, s>>>(ns, P, L, a->az_kptr.p, a->az_tj.p,
                                                              a->az_tv.p, ec, a->az_E.p);

@@ -307,8 +307,10 @@ struct LinOp {
 void linop_apply(const LinOp& A, const double* X, double* Y, double alpha, double beta,
                  const double* C, hipStream_t s);
 // ras.hip: Z[owned] = beta * Z[owned] + omega * RAS(R)[owned]
+// cadd, cown (fused path only, beta = 1): also add cadd[cown[a]] to row a
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
-                  hipStream_t s);
+                  hipStream_t s, const double* cadd = nullptr, const int32_t* cown = nullptr);
+bool ras_can_add_coarse(const sg_ras* r);
 const std::vector<int32_t>& ras_owner(const sg_ras* r);
 int ras_nsub(const sg_ras* r);
 int ras_device(const sg_ras* r);
@@ -322,6 +324,10 @@ void coarse_solve(const sg_amg* a, const double* b, double* x, hipStream_t s);
 // boundary; false (nothing done) when `op` is not that operator.
 bool coarse_residual_update(const sg_amg* a, const sg_op* op, const double* ec, double* T,
                             hipStream_t s);
+// the coarse space holds A Z for `op` (coarse_residual_update applies)
+bool coarse_has_az(const sg_amg* a, const sg_op* op);
+// the subdomain of every fine node for a Nicolaides space (device), else NULL
+const int32_t* coarse_owner_dev(const sg_amg* a);
 // true when the coarse solve is an inner Krylov iteration (host-synchronous,
 // so the Arnoldi step that contains it is not captured into a graph)
 bool inner_active(const sg_amg* a);

@@ -632,10 +632,17 @@ void precond_apply(const LinOp& A, const sg_ras* ras, const sg_amg* amg, double 
     linop_apply(A, Z, T, -1.0, 1.0, R, s);                           // t = r - A z1
     coarse_restrict(amg, T, rc, s);
     coarse_solve(amg, rc, ec, s);
-    coarse_prolong_add(amg, ec, Z, s);                               // z2 = z1 + Q t
     // t = r - A z2 = (r - A z1) - (A Z) e_c: only interface and boundary rows
     // of A Z are non-zero for the Nicolaides space, so the update replaces a
-    // matvec where the coarse space holds A Z; else the residual is formed
+    // matvec where the coarse space holds A Z.  Then z2 = z1 + Z e_c is not
+    // needed before the last smoothing, whose fused store adds it where it can.
+    const int32_t* cown = coarse_owner_dev(amg);
+    if (cown && coarse_has_az(amg, A.kron) && ras_can_add_coarse(ras)) {
+        coarse_residual_update(amg, A.kron, ec, T, s);
+        ras_apply_ex(ras, T, Z, omega, 1.0, s, ec, cown);           // z = z1 + Q t + w M t2
+        return;
+    }
+    coarse_prolong_add(amg, ec, Z, s);                               // z2 = z1 + Q t
     if (!coarse_residual_update(amg, A.kron, ec, T, s))
         linop_apply(A, Z, T, -1.0, 1.0, R, s);
     ras_apply_ex(ras, T, Z, omega, 1.0, s);                          // z = z2 + w M t

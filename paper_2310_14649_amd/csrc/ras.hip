@@ -826,7 +826,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     const int64_t* __restrict__ toff, const int64_t* __restrict__ own_off,
     const int32_t* __restrict__ own_gnode, const TS* __restrict__ ainv,
     const double* __restrict__ R, const double* __restrict__ afact, double* Z, double omega,
-    double beta, const double* __restrict__ post) {
+    double beta, const double* __restrict__ post, const double* __restrict__ cadd,
+    const int32_t* __restrict__ cown) {
     using Acc = typename Mma<TS>::Acc;
     constexpr int MT = 4;
     constexpr int KL = 16 / sizeof(TS);
@@ -1022,7 +1023,14 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
                 const int64_t zo = (int64_t)og[rbase + rr] * P + c;
                 const double val = STORE == 1 ? omega * (double)rb[rr * RS + c]
                                               : omega * (double)rb[rr * RS + c] / afact[c];
-                Z[zo] = beta != 0.0 ? fma(beta, Z[zo], val) : val;
+                if (beta != 0.0) {
+                    double zold = Z[zo];
+                    // z2 = z1 + Z e_c formed here, as the prolongation would
+                    if (cadd) zold += cadd[(int64_t)cown[og[rbase + rr]] * P + c];
+                    Z[zo] = fma(beta, zold, val);
+                } else {
+                    Z[zo] = val;
+                }
             }
         }
         return;
@@ -1038,7 +1046,7 @@ inline size_t dense_fused_lds(size_t entry_bytes, int Pp, int ld_max) {
 }  // namespace
 
 void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, double beta,
-                     hipStream_t s, bool post) {
+                     hipStream_t s, bool post, const double* cadd, const int32_t* cown) {
     int maxn = 0;
     for (size_t q = 0; q + 1 < r->h_sub_node_off.size(); ++q)
         maxn = std::max(maxn, r->h_sub_node_off[q + 1] - r->h_sub_node_off[q]);
@@ -1050,6 +1058,7 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
         // the row-slice store (no mixing) where its LDS fits
         const size_t row_lds = dense_post_lds(0, r->Pp, r->prec == SG_FP64 ? 8 : 4);
         const bool row_store = !post && row_lds <= r->lds_max;
+        SG_REQUIRE(!cadd || post || row_store, "the coarse correction needs the row-slice store");
 #define SG_FUSED_NT(TS, BUF, N)                                                                    \
     case N:                                                                                        \
         if (post)                                                                                  \
@@ -1057,18 +1066,18 @@ void ras_dense_apply(const sg_ras* r, const double* R, double* Z, double omega, 
                                            std::max(r->fused_lds, r->post_lds), s>>>(              \
                 r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
                 r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
-                R, r->afact.p, Z, omega, beta, r->kron_post.p);                                    \
+                R, r->afact.p, Z, omega, beta, r->kron_post.p, cadd, cown);                        \
         else if (row_store)                                                                        \
             dense_fused_kernel<TS, N, 2><<<r->nblk[2], 64 * kFusedWaves,                           \
                                            std::max(r->fused_lds, row_lds), s>>>(                  \
                 r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
                 r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
-                R, r->afact.p, Z, omega, beta, nullptr);                                           \
+                R, r->afact.p, Z, omega, beta, nullptr, cadd, cown);                               \
         else                                                                                       \
             dense_fused_kernel<TS, N, 0><<<r->nblk[2], 64 * kFusedWaves, r->fused_lds, s>>>(       \
                 r->P, r->blk_sub[2].p, r->blk_row0[2].p, r->nown_d.p, r->ld_d.p,                   \
                 r->sub_node_off.p, r->gnode.p, r->toff_d.p, r->own_off_d.p, r->own_gnode.p, BUF,   \
-                R, r->afact.p, Z, omega, beta, nullptr);                                           \
+                R, r->afact.p, Z, omega, beta, nullptr, nullptr, nullptr);                         \
         break;
         if (r->prec == SG_FP64) {
             switch (NT) {
@@ -1239,8 +1248,20 @@ __global__ __launch_bounds__(64) void kron_mix_mfma_reg_kernel(int n, int P,
     for (int q = lane; q < na * P; q += 64) tg[q] = Ts[q];
 }
 
+// The fused dense path with its row-slice store: it can also add a
+// Nicolaides coarse correction (Z = Z + e_c[owner] + omega M R, beta = 1).
+bool ras_can_add_coarse(const sg_ras* r) {
+    if (!r->use_dense || r->dense_var != 2 || !r->fused_ok) return false;
+    const bool post = r->local_mode == SG_LOCAL_KRON && r->post_ok && r->Pp == r->post_pp;
+    if (post) return true;
+    if (r->local_mode == SG_LOCAL_KRON) return false;
+    return dense_post_lds(0, r->Pp, r->prec == SG_FP64 ? 8 : 4) <= r->lds_max;
+}
+
 void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, double beta,
-                  hipStream_t s) {
+                  hipStream_t s, const double* cadd, const int32_t* cown) {
+    SG_REQUIRE(!cadd || (beta == 1.0 && ras_can_add_coarse(r)),
+               "coarse correction inside the RAS needs the fused path and beta = 1");
     // the fused dense path mixes its output (Kronecker local solves)
     const bool post = r->local_mode == SG_LOCAL_KRON && r->use_dense && r->dense_var == 2 &&
                       r->post_ok && r->Pp == r->post_pp;
@@ -1259,7 +1280,7 @@ void ras_apply_ex(const sg_ras* r, const double* R, double* Z, double omega, dou
         R = r->kron_t.p;
     }
     if (r->use_dense) {
-        ras_dense_apply(r, R, Z, omega, beta, s, post);
+        ras_dense_apply(r, R, Z, omega, beta, s, post, cadd, cown);
         return;
     }
     const int nch = (r->P + kColChunk - 1) / kColChunk;

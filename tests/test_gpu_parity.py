@@ -908,6 +908,26 @@ def test_graph_replay_matches_eager(built):
     assert B.sg_graph_cache_clear() > 0
 
 
+def test_precond_fused_coarse_add_is_exact(built):
+    """With the fused BF16 RAS the two-grid cycle adds the coarse correction
+    inside the last smoothing's store instead of a separate prolongation;
+    for mean-based local solves the fused and the dense RAS give identical
+    bits, so the cycle must too."""
+    pr, S, _ = built("c1_64")
+    R = torch.from_numpy(np.random.default_rng(19).standard_normal(pr.mesh.n * S.P)).cuda()
+    out = {}
+    for path in ("dense", "fused"):
+        g = GpuSG(pr, prec="bf16", coarse="amg", ras_path=path)
+        try:
+            Z = g.new_vec()
+            B.sg_precond_apply(g.op, g.ras, g.amg, 0.45, R, Z, g.precond_workspace())
+            torch.cuda.synchronize()
+            out[path] = Z
+        finally:
+            g.close()
+    assert torch.equal(out["dense"], out["fused"])
+
+
 def test_graph_replay_fused_ras_matches_eager(built):
     """The BF16 solve with the fused dense RAS (its per-chunk barriers and
     run-ahead steps inside captured graphs) gives the eager result bit for
