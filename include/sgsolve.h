@@ -241,9 +241,12 @@ int ras_refactor(sg_ras* r, const sg_op* op, void* stream);
  * the precision.  Both compute the same operator (up to rounding).
  * ras_select: 0 = sweep, 1 = dense with 64 owned rows per wave, 2 = dense
  *   with 32, 3 = fused dense: one work-group per subdomain gathers its
- *   right-hand sides into on-chip memory itself and streams the rows once
- *   (available where P_pad x n_local entries plus n_local node ids fit one
- *   work-group's LDS and P <= 48, FP64: P <= 16; else SG_ERR_UNSUPPORTED).
+ *   right-hand sides into on-chip memory itself, in chunks of about a
+ *   seventh of its local nodes held in a ring of two, and streams the rows
+ *   once (available where two chunks of P_pad columns plus n_local node ids
+ *   fit one work-group's LDS and P <= 48, FP64: P <= 16; else
+ *   SG_ERR_UNSUPPORTED).  With Kronecker local solves the fused path mixes
+ *   its output by Gt^{-1} instead of the right-hand side by Gt^{-1} G_0.
  *   The dense rows are built on first use; device memory
  *   sum_s ceil16(n_own(s)) * ceil64(n_local(s)) entries.  Synchronous.
  * ras_autotune: builds the dense rows if needed, times `reps` applies of

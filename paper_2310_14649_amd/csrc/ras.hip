@@ -869,29 +869,33 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
         aload(1, 1);
         if (nh > 2) aload(2, 2);
     }
+    // The right-hand sides arrive in chunks of CS super-steps (a multiple of
+    // three, so that chunk borders fall on the three-slot ring below).  Entry
+    // e of a chunk is local node q0 + e / P, column e % P: consecutive threads
+    // read consecutive entries of a node's row of R; padded nodes are zero.
+    // Only chunks c (streamed) and c + 1 (gathered) are live at once, so the
+    // LDS holds a ring of two chunks: super-step ks sits at ks mod 2 CS.
+    const int CS = 3 * ((nks + 3 * kFusedChunks - 1) / (3 * kFusedChunks));
+    const int nchunks = (nks + CS - 1) / CS;
+    const int ring = min(nks, 2 * CS);        // super-steps held
     // node ids after the B pieces
-    int32_t* ids = reinterpret_cast<int32_t*>(lds_b + (size_t)nks * NT * 128);
+    int32_t* ids = reinterpret_cast<int32_t*>(lds_b + (size_t)ring * NT * 128);
     for (int q = tid; q < nloc; q += kThreads) ids[q] = gnode[node0 + q];
     TS* bsh = reinterpret_cast<TS*>(lds_b);
     // LDS slot of entry (local node q, column n)
     auto slot = [&](int q, int n) {
         const int ks = q / KSUP, w = q - ks * KSUP;
         const int g = w / (2 * KL), h = (w / KL) & 1, el = w % KL;
-        return (((ks * NT + (n >> 4)) * 2 + h) * 64 + (n & 15) + 16 * g) * KL + el;
+        return ((((ks % (2 * CS)) * NT + (n >> 4)) * 2 + h) * 64 + (n & 15) + 16 * g) * KL + el;
     };
-    // zeros in the padded columns P .. Pp - 1 (no chunk's gather writes them)
+    // zeros in the padded columns P .. Pp - 1 of the ring (no chunk's gather
+    // writes them)
     const int npad = Pp - P;
-    for (int e = tid; e < L * npad; e += kThreads) {
+    for (int e = tid; e < ring * KSUP * npad; e += kThreads) {
         const int q = e / npad;
         bsh[slot(q, P + e - q * npad)] = Mma<TS>::conv(0.0);
     }
     __syncthreads();
-    // The right-hand sides arrive in chunks of CS super-steps (a multiple of
-    // three, so that chunk borders fall on the three-slot ring below).  Entry
-    // e of a chunk is local node q0 + e / P, column e % P: consecutive threads
-    // read consecutive entries of a node's row of R; padded nodes are zero.
-    const int CS = 3 * ((nks + 3 * kFusedChunks - 1) / (3 * kFusedChunks));
-    const int nchunks = (nks + CS - 1) / CS;
     auto chunk_count = [&](int c) { return (min((c + 1) * CS * KSUP, L) - c * CS * KSUP) * P; };
     auto fetch = [&](int c, int e) {
         const int q = c * CS * KSUP + e / P;
@@ -923,7 +927,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = Mma<TS>::zero();
     auto compute = [&](int slot_, int j) {
-        const int pb = (2 * (j >> 1) * NT + (j & 1)) * 64 + lane;
+        const int pb = (2 * ((j >> 1) % (2 * CS)) * NT + (j & 1)) * 64 + lane;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const uint4 b = lds_b[pb + 128 * t];
@@ -1039,8 +1043,14 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     dense_epilogue<TS, NT, MT>(acc, P, r0, no, lane, own_gnode + own_off[s], afact, Z, omega, beta);
 }
 
+// LDS of the fused path: the ring of two right-hand-side chunks (as the
+// kernel sizes its chunks for the widest subdomain) plus the node ids.
 inline size_t dense_fused_lds(size_t entry_bytes, int Pp, int ld_max) {
-    return (size_t)Pp * ld_max * entry_bytes + (size_t)ld_max * 4;
+    const int ksup = 8 * (int)(16 / entry_bytes);
+    const int nks = ld_max / ksup;
+    const int cs = 3 * ((nks + 3 * kFusedChunks - 1) / (3 * kFusedChunks));
+    const int ring = std::min(nks, 2 * cs);
+    return (size_t)Pp * ring * ksup * entry_bytes + (size_t)ld_max * 4;
 }
 
 }  // namespace
