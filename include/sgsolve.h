@@ -296,9 +296,9 @@ void sg_destroy_ras(sg_ras* r);
  * For an operator from sg_assemble the handle also holds (A Z) on the rows
  * where it is non-zero (next to a subdomain interface or the boundary), so
  * that the two-grid cycle forms r - A z2 as (r - A z1) - (A Z) e_c instead
- * of a matvec; the cycle writes a small buffer of the handle
- * ([L_in x n_sub x P]), so cycles that share a handle must be ordered on
- * one stream.  b_c, x_c: device [n_sub*P] FP64.  Asynchronous.
+ * of a matvec; the cycle writes a buffer of the handle (P doubles per
+ * (row, subdomain) entry of A Z), so cycles that share a handle must be
+ * ordered on one stream.  b_c, x_c: device [n_sub*P] FP64.  Asynchronous.
  * ---------------------------------------------------------------------- */
 int amg_setup(const sg_op* op, const sg_ras* ras, sg_coarse_kind kind, sg_prec prec,
               sg_amg** out, void* stream);

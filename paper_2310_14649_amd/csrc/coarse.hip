@@ -94,8 +94,11 @@ struct sg_amg {
     // e_c G_i [L_in][n_sub][P] of the current coarse correction
     const sg_op* az_op = nullptr;
     int az_rows_n = 0;
-    sg::DevBuf<int32_t> az_rows, az_ptr, az_col, az_kptr, az_tj;
-    sg::DevBuf<double> az_val, az_tv, az_E;
+    // entries grouped by subdomain (az_sptr ranges, values az_sval) so that
+    // one work-group per subdomain forms E_s in LDS and the products of its
+    // entries (into az_W [entry][P]); per row, the entries' positions az_rpos
+    sg::DevBuf<int32_t> az_rows, az_ptr, az_rpos, az_sptr, az_kptr, az_tj;
+    sg::DevBuf<double> az_sval, az_tv, az_W;
     ~sg_amg() {
         if (ipin) (void)hipHostFree(ipin);
         if (gamg) sg_destroy_amg(gamg);
@@ -220,49 +223,60 @@ __global__ void geo_prolong_add_kernel(int total, int P, const int32_t* __restri
     Y[idx] = t;
 }
 
-// E[i][s][k] = sum_j m_ijk e_c[s, j]: one thread per (i, s, k) over the
-// triples of (k, i) (kiptr ranges of the table sorted by k, i, j).
-__global__ void az_mix_kernel(int ns, int P, int L, const int32_t* __restrict__ kiptr,
-                              const int32_t* __restrict__ tj, const double* __restrict__ tv,
-                              const double* __restrict__ ec, double* __restrict__ E) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= L * ns * P) return;
-    const int i = idx / (ns * P);
-    const int rem = idx - i * ns * P;
-    const int sd = rem / P, k = rem - sd * P;
-    const int t0 = kiptr[k * L + i], t1 = kiptr[k * L + i + 1];
-    double acc = 0.0;
-    for (int t = t0; t < t1; ++t) acc = fma(tv[t], ec[(size_t)sd * P + tj[t]], acc);
-    E[idx] = acc;
-}
-
-// T[a, k] -= sum_{(a, s) entries} sum_i AZ_i[a, s] E[i][s][k] for the rows
-// with entries (one thread per (row, k)); the loads of eight input terms are
-// issued before their products.
-__global__ void az_update_kernel(int nrows, int ns, int P, int L, const int32_t* __restrict__ rows,
-                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                 const double* __restrict__ val, const double* __restrict__ E,
-                                 double* __restrict__ T) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nrows * P) return;
-    const int r = idx / P, k = idx - r * P;
-    const size_t stride = (size_t)ns * P;
-    double acc = 0.0;
-    for (int e = ptr[r]; e < ptr[r + 1]; ++e) {
-        const double* v = val + (size_t)e * L;
-        const double* Ee = E + (size_t)col[e] * P + k;
+// One work-group per subdomain s: E_s[i][k] = sum_j m_ijk e_c[s, j] in LDS
+// (one thread per (i, k) over the triples of (k, i), kiptr ranges of the
+// table sorted by k, i, j), then W[q][k] = sum_i AZ_i(q) E_s[i][k] for the
+// entries q of column s.
+__global__ __launch_bounds__(1024) void az_entry_kernel(int P, int L,
+                                                       const int32_t* __restrict__ sptr,
+                                                       const double* __restrict__ sval,
+                                                       const int32_t* __restrict__ kiptr,
+                                                       const int32_t* __restrict__ tj,
+                                                       const double* __restrict__ tv,
+                                                       const double* __restrict__ ec,
+                                                       double* __restrict__ W) {
+    extern __shared__ double Es[];                 // [L][P]
+    const int sd = blockIdx.x;
+    const int q0 = sptr[sd], q1 = sptr[sd + 1];
+    if (q0 == q1) return;
+    for (int x = threadIdx.x; x < L * P; x += blockDim.x) {
+        const int i = x / P, k = x - i * P;
+        double acc = 0.0;
+        for (int t = kiptr[k * L + i]; t < kiptr[k * L + i + 1]; ++t)
+            acc = fma(tv[t], ec[(size_t)sd * P + tj[t]], acc);
+        Es[x] = acc;
+    }
+    __syncthreads();
+    // the loads of eight input terms are issued before their products
+    for (int x = threadIdx.x; x < (q1 - q0) * P; x += blockDim.x) {
+        const int qq = x / P, k = x - qq * P;
+        const double* v = sval + (size_t)(q0 + qq) * L;
+        double acc = 0.0;
         for (int i0 = 0; i0 < L; i0 += 8) {
             double vv[8], ee[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const bool in = i0 + u < L;
                 vv[u] = in ? v[i0 + u] : 0.0;
-                ee[u] = in ? Ee[(size_t)(i0 + u) * stride] : 0.0;
+                ee[u] = in ? Es[(i0 + u) * P + k] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc = fma(vv[u], ee[u], acc);
         }
+        W[(size_t)(q0 + qq) * P + k] = acc;
     }
+}
+
+// T[a, k] -= sum of W[q][k] over the row's entries q (column order), one
+// thread per (row, k).
+__global__ void az_rows_kernel(int nrows, int P, const int32_t* __restrict__ rows,
+                               const int32_t* __restrict__ ptr, const int32_t* __restrict__ rpos,
+                               const double* __restrict__ W, double* __restrict__ T) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * P) return;
+    const int r = idx / P, k = idx - r * P;
+    double acc = 0.0;
+    for (int e = ptr[r]; e < ptr[r + 1]; ++e) acc += W[(size_t)rpos[e] * P + k];
     T[(size_t)rows[r] * P + k] -= acc;
 }
 
@@ -948,14 +962,13 @@ bool coarse_residual_update(const sg_amg* a, const sg_op* op, const double* ec, 
                             hipStream_t s) {
     if (!coarse_has_az(a, op)) return false;
     const int ns = a->n_sub, P = a->P, L = a->L;
-    az_mix_kernel<<<(L * ns * P + 255) / 256, 256, 0, s>>>(ns, P, L, a->az_kptr.p, a->az_tj.p,
-                                                             a->az_tv.p, ec, a->az_E.p);
-    HIP_LAUNCH_OK();
     if (a->az_rows_n > 0) {
+        az_entry_kernel<<<ns, 1024, (size_t)L * P * sizeof(double), s>>>(
+            P, L, a->az_sptr.p, a->az_sval.p, a->az_kptr.p, a->az_tj.p, a->az_tv.p, ec, a->az_W.p);
+        HIP_LAUNCH_OK();
         const int64_t tot = (int64_t)a->az_rows_n * P;
-        az_update_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
-            a->az_rows_n, ns, P, L, a->az_rows.p, a->az_ptr.p, a->az_col.p, a->az_val.p,
-            a->az_E.p, T);
+        az_rows_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            a->az_rows_n, P, a->az_rows.p, a->az_ptr.p, a->az_rpos.p, a->az_W.p, T);
         HIP_LAUNCH_OK();
     }
     return true;
@@ -1173,6 +1186,9 @@ namespace sg {
 // left out, so only rows at an interface or the Dirichlet boundary remain.
 void build_az(sg_amg* a, const sg_op* op, const std::vector<int32_t>& owner, hipStream_t s) {
     const int n = op->n, L = op->L, P = op->P, ns = a->n_sub;
+    // E_s [L_in x P] FP64 must fit the LDS of one work-group; otherwise the
+    // cycle keeps forming the residual with a matvec
+    if ((size_t)L * P * sizeof(double) > 64 * 1024) return;
     std::vector<double> vals((size_t)op->nnz * L);
     op->vals.download(vals.data(), vals.size(), s);
     HIP_OK(hipStreamSynchronize(s));
@@ -1226,15 +1242,31 @@ void build_az(sg_amg* a, const sg_op* op, const std::vector<int32_t>& owner, hip
         kiptr[(size_t)B.tk[t] * L + B.ti[t] + 1]++;
     }
     for (size_t q = 0; q < (size_t)P * L; ++q) kiptr[q + 1] += kiptr[q];
+    // entries grouped by subdomain (stable: row order within a subdomain)
+    const int ne = (int)col.size();
+    std::vector<int32_t> sptr(ns + 1, 0), rpos(ne);
+    for (int e = 0; e < ne; ++e) sptr[col[e] + 1]++;
+    for (int q = 0; q < ns; ++q) sptr[q + 1] += sptr[q];
+    std::vector<double> sval((size_t)ne * L);
+    {
+        std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+        for (int e = 0; e < ne; ++e) {
+            const int q = fill[col[e]]++;
+            rpos[e] = q;
+            std::copy(val.begin() + (size_t)e * L, val.begin() + (size_t)(e + 1) * L,
+                      sval.begin() + (size_t)q * L);
+        }
+    }
     a->az_rows_n = (int)rows.size();
     a->az_rows.upload(rows, s);
     a->az_ptr.upload(ptr, s);
-    a->az_col.upload(col, s);
-    a->az_val.upload(val, s);
+    a->az_rpos.upload(rpos, s);
+    a->az_sptr.upload(sptr, s);
+    a->az_sval.upload(sval, s);
     a->az_kptr.upload(kiptr, s);
     a->az_tj.upload(tj, s);
     a->az_tv.upload(tv, s);
-    a->az_E.alloc((size_t)L * ns * P);
+    a->az_W.alloc((size_t)std::max(ne, 1) * P);
     a->az_op = op;
     HIP_OK(hipStreamSynchronize(s));
 }
