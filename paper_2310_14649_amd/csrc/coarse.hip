@@ -41,6 +41,10 @@ struct Bsr {
 
 struct AmgLevel {
     int nn = 0;
+    // ap: A P (block rows of the level, columns of the next), for the
+    // post-smoothing residual r - (A P) x_c
+    DevBuf<int32_t> ap_ptr, ap_col;
+    DevBuf<double> ap_val;
     DevBuf<int32_t> a_ptr, a_col, p_ptr, p_col, r_ptr, r_col;
     DevBuf<double> a_val, p_val, r_val, dinv64, x, b, r;
     DevBuf<double> xs;   // post-smoothed x of a level below the first
@@ -344,21 +348,17 @@ __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __
     const int s = blockIdx.x, tid = threadIdx.x;
     const int nparts = kBlkMv / P;
     const int k = tid % P, pi = tid / P;
+    // thread (k, pi) takes the (block, column) pairs e = pi, pi + nparts, ...
+    // of the row: independent loads, a few per thread, issued together
     double acc = 0.0;
     if (pi < nparts) {
-        for (int q = ptr[s] + pi; q < ptr[s + 1]; q += nparts) {
-            // entry (k, j) of block q at blk[j * js]
-            const double* blk = val + (size_t)q * P * P + (kColMajor ? (size_t)k : (size_t)k * P);
-            const size_t js = kColMajor ? (size_t)P : 1;
-            const double* xv = x + (size_t)col[q] * P;
-            double a0 = 0.0, a1 = 0.0;
-            int j = 0;
-            for (; j + 1 < P; j += 2) {
-                a0 = fma(blk[j * js], xv[j], a0);
-                a1 = fma(blk[(j + 1) * js], xv[j + 1], a1);
-            }
-            if (j < P) a0 = fma(blk[j * js], xv[j], a0);
-            acc += a0 + a1;
+        const int q0 = ptr[s], tot = (ptr[s + 1] - q0) * P;
+#pragma unroll 4
+        for (int e = pi; e < tot; e += nparts) {
+            const int qq = e / P, j = e - qq * P;
+            const int q = q0 + qq;
+            const double a = val[(size_t)q * P * P + (kColMajor ? (size_t)j * P + k : (size_t)k * P + j)];
+            acc = fma(a, x[(size_t)col[q] * P + j], acc);
         }
     }
     part[tid] = acc;
@@ -379,6 +379,55 @@ __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __
             const size_t o = (size_t)s * P + tid;
             xj[o] = (beta_j != 0.0 ? beta_j * xo[o] : 0.0) + omega_j * acc;
         }
+    }
+}
+
+// The coarse correction and post-smoothing of one level, per block row s:
+// p = (P x_c)_s, q = ((A P) x_c)_s, r1 = r0_s - q (= b - A (x + P x_c)),
+// out_s = x_s + p + omega D_s^{-1} r1; r0 is the residual of the iterate
+// before the correction.  out may equal x (each row reads only its own x).
+template <class TJ>
+__global__ __launch_bounds__(kBlkMv) void bsr_post_kernel(
+    int P, const int32_t* __restrict__ pptr, const int32_t* __restrict__ pcol,
+    const double* __restrict__ pval, const int32_t* __restrict__ aptr,
+    const int32_t* __restrict__ acol, const double* __restrict__ aval,
+    const double* __restrict__ xc, const double* __restrict__ r0, const double* x, double* out,
+    const TJ* __restrict__ dinv, double omega) {
+    __shared__ double part[kBlkMv];
+    __shared__ double ps[kBlk], rs[kBlk];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nparts = kBlkMv / P;
+    const int k = tid % P, pi = tid / P;
+    auto row_product = [&](const int32_t* ptr, const int32_t* col, const double* val) {
+        double acc = 0.0;
+        if (pi < nparts) {
+            const int q0 = ptr[s], tot = (ptr[s + 1] - q0) * P;
+#pragma unroll 4
+            for (int e = pi; e < tot; e += nparts) {
+                const int qq = e / P, j = e - qq * P;
+                const int q = q0 + qq;
+                acc = fma(val[(size_t)q * P * P + (size_t)k * P + j], xc[(size_t)col[q] * P + j], acc);
+            }
+        }
+        part[tid] = acc;
+        __syncthreads();
+        double t = 0.0;
+        if (tid < P)
+            for (int w = 0; w < nparts; ++w) t += part[w * P + tid];
+        __syncthreads();
+        return t;
+    };
+    const double p = row_product(pptr, pcol, pval);
+    const double q = row_product(aptr, acol, aval);
+    if (tid < P) {
+        ps[tid] = p;
+        rs[tid] = r0[(size_t)s * P + tid] - q;
+    }
+    __syncthreads();
+    if (tid < P) {
+        const double acc = jacobi_row<TJ>(P, dinv + (size_t)s * P * P + (size_t)tid * P, rs);
+        const size_t o = (size_t)s * P + tid;
+        out[o] = x[o] + ps[tid] + omega * acc;
     }
 }
 
@@ -699,6 +748,20 @@ const double* amg_vcycle_level(const sg_amg* a, int l, const double* b, double* 
     mv(true, C.nn, L.r_ptr, L.r_col, L.r_val, L.r.p, C.b.p, 1.0, 0.0, nullptr,
        c_smooth ? l + 1 : -1, c_smooth ? C.x.p : nullptr, nullptr, 0.0);
     const double* xc = amg_vcycle_level(a, l + 1, C.b.p, C.x.p, s, c_smooth);
+    // x + P x_c + w D^{-1} (r - (A P) x_c) in one pass (into xs below level
+    // 0), r = b - A x being the residual formed before the restriction
+    if (L.ap_val.p) {
+        double* out = l == 0 ? x : L.xs.p;
+#define SG_POST(TS, DINV)                                                                          \
+    bsr_post_kernel<TS><<<L.nn, kBlkMv, 0, s>>>(P, L.p_ptr.p, L.p_col.p, L.p_val.p, L.ap_ptr.p,    \
+                                                L.ap_col.p, L.ap_val.p, xc, L.r.p, x, out, DINV, w)
+        if (a->prec == SG_FP64) SG_POST(double, L.dinv64.p);
+        else if (a->prec == SG_FP32) SG_POST(float, L.dinv32.p);
+        else SG_POST(uint16_t, L.dinv16.p);
+#undef SG_POST
+        HIP_LAUNCH_OK();
+        return out;
+    }
     // x += P x_c; r = b - A x; then x + w D^{-1} r (into xs below level 0)
     mv(false, L.nn, L.p_ptr, L.p_col, L.p_val, xc, x, 1.0, 1.0, x, -1, nullptr, nullptr, 0.0);
     if (l == 0) {
@@ -1051,7 +1114,7 @@ void amg_common_setup(sg_amg* a, const std::vector<int32_t>& owner, hipStream_t 
 void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
     const int P = a->P, ns = a->n_sub;
     const sg_prec prec = a->prec;
-    std::vector<Bsr> As{A}, Ps;
+    std::vector<Bsr> As{A}, Ps, APs;
     std::vector<std::vector<double>> Dinvs;
     while ((int)As.size() < amgc::kMaxLevels && As.back().nr > amgc::kMinNodes) {
         const Bsr& Al = As.back();
@@ -1125,6 +1188,7 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
         Bsr Ac = bsr_mul(Pt, AP);
         Dinvs.push_back(std::move(Dinv));
         Ps.push_back(std::move(Pm));
+        APs.push_back(std::move(AP));
         As.push_back(std::move(Ac));
     }
     if (a->h_agg0.empty()) a->h_agg0.assign(ns, -1);
@@ -1141,6 +1205,7 @@ void amg_build_hierarchy(sg_amg* a, Bsr A, hipStream_t s) {
         if (l < nl - 1) {
             upload_bsr(As[l], Lv.a_ptr, Lv.a_col, Lv.a_val, s);
             upload_bsr(Ps[l], Lv.p_ptr, Lv.p_col, Lv.p_val, s);
+            upload_bsr(APs[l], Lv.ap_ptr, Lv.ap_col, Lv.ap_val, s);
             upload_bsr(bsr_transpose(Ps[l]), Lv.r_ptr, Lv.r_col, Lv.r_val, s, true);
             if (prec == SG_FP64) {
                 Lv.dinv64.upload(Dinvs[l], s);
