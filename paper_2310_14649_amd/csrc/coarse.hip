@@ -297,35 +297,47 @@ __global__ void mean_exact_kernel(int ns, int P, const double* __restrict__ inv,
 }
 
 // y = beta * c + alpha * A x   (block-sparse, dense P x P blocks).  One
-// work-group of kBlkMv threads per block-row: thread (k, part) sums the
-// block-rows' neighbour blocks part, part + nparts, ... for output row k,
-// then the parts are added in a fixed order through LDS.  Blocks stored by
-// rows (kColMajor false: each lane walks its own row, which suits block rows
-// with few blocks) or by columns (a load instruction reads consecutive
-// entries, which suits block rows with many blocks, where the lanes' rows
-// would overflow L1: the restriction).
+// work-group of kBlkMv threads per block-row: thread (k, part) sums, for
+// output row k, the (block, column) pairs part, part + nparts, ... of the
+// block row (a few independent loads per thread), then the parts are added
+// in a fixed order through LDS.  Blocks stored by rows (kColMajor false) or
+// by columns (the restriction, whose block rows hold many blocks).
 constexpr int kBlkMv = 1024;
 
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// Row k of a block-Jacobi step: sum_j Dinv_s[k][j] r_s[j] with Dinv in TS (a
-// column-ordered FP64 sum, or an FP32 sum for the low precisions).
+// D_s^{-1} r_s (block-Jacobi) spread over a work-group of nthreads:
+// thread (k, pi) sums columns pi, pi + np, ... of row k (np = nthreads / P),
+// then the np partial sums of a row are added in order.  rs and part are in
+// LDS (part: nthreads entries); every thread of the group calls it.  FP32
+// accumulation for FP32 and BF16 blocks.
 template <class TS>
-__device__ inline double jacobi_row(int P, const TS* __restrict__ blk, const double* rv) {
-    if constexpr (sizeof(TS) == 8) {
-        double acc = 0.0;
-        for (int j = 0; j < P; ++j) acc = fma((double)blk[j], rv[j], acc);
-        return acc;
-    } else {
-        float f = 0.0f;
-        for (int j = 0; j < P; ++j) {
-            float d;
-            if constexpr (sizeof(TS) == 4) d = (float)blk[j];
-            else d = bf16_to_f((uint16_t)blk[j]);
-            f = fmaf(d, (float)rv[j], f);
+__device__ inline double jacobi_par(int P, const TS* __restrict__ blk, const double* rs,
+                                    double* part, int nthreads) {
+    const int tid = threadIdx.x, np = nthreads / P;
+    const int k = tid % P, pi = tid / P;
+    double a = 0.0;
+    if (pi < np) {
+        if constexpr (sizeof(TS) == 8) {
+            for (int j = pi; j < P; j += np) a = fma((double)blk[(size_t)k * P + j], rs[j], a);
+        } else {
+            float f = 0.0f;
+            for (int j = pi; j < P; j += np) {
+                float d;
+                if constexpr (sizeof(TS) == 4) d = (float)blk[(size_t)k * P + j];
+                else d = bf16_to_f((uint16_t)blk[(size_t)k * P + j]);
+                f = fmaf(d, (float)rs[j], f);
+            }
+            a = (double)f;
         }
-        return (double)f;
     }
+    part[tid] = a;
+    __syncthreads();
+    double t = 0.0;
+    if (tid < P)
+        for (int w = 0; w < np; ++w) t += part[w * P + tid];
+    __syncthreads();
+    return t;
 }
 
 // TJ (not void): the work-group then also applies the block-Jacobi step
@@ -374,8 +386,8 @@ __global__ __launch_bounds__(kBlkMv) void bsr_mv_kernel(int P, const int32_t* __
     }
     if constexpr (!std::is_void_v<TJ>) {
         __syncthreads();
+        const double acc = jacobi_par<TJ>(P, dinv + (size_t)s * P * P, ys, part, kBlkMv);
         if (tid < P) {
-            const double acc = jacobi_row<TJ>(P, dinv + (size_t)s * P * P + (size_t)tid * P, ys);
             const size_t o = (size_t)s * P + tid;
             xj[o] = (beta_j != 0.0 ? beta_j * xo[o] : 0.0) + omega_j * acc;
         }
@@ -424,8 +436,8 @@ __global__ __launch_bounds__(kBlkMv) void bsr_post_kernel(
         rs[tid] = r0[(size_t)s * P + tid] - q;
     }
     __syncthreads();
+    const double acc = jacobi_par<TJ>(P, dinv + (size_t)s * P * P, rs, part, kBlkMv);
     if (tid < P) {
-        const double acc = jacobi_row<TJ>(P, dinv + (size_t)s * P * P + (size_t)tid * P, rs);
         const size_t o = (size_t)s * P + tid;
         out[o] = x[o] + ps[tid] + omega * acc;
     }
@@ -436,11 +448,13 @@ template <class TS>
 __global__ __launch_bounds__(kBlk) void jacobi_kernel(int P, const TS* __restrict__ dinv,
                                                       const double* __restrict__ r, double* x,
                                                       double omega, double beta) {
-    const int s = blockIdx.x;
-    for (int k = threadIdx.x; k < P; k += kBlk) {
-        const double acc = jacobi_row<TS>(P, dinv + (size_t)s * P * P + (size_t)k * P,
-                                          r + (size_t)s * P);
-        const size_t o = (size_t)s * P + k;
+    __shared__ double rs[kBlk], part[kBlk];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    if (tid < P) rs[tid] = r[(size_t)s * P + tid];
+    __syncthreads();
+    const double acc = jacobi_par<TS>(P, dinv + (size_t)s * P * P, rs, part, kBlk);
+    if (tid < P) {
+        const size_t o = (size_t)s * P + tid;
         x[o] = (beta != 0.0 ? beta * x[o] : 0.0) + omega * acc;
     }
 }
