@@ -43,7 +43,7 @@ struct sg_ras {
     // dense path: explicit inverse rows of the owned nodes of each subdomain
     // (local columns in level order, ld = nloc padded to 64), stored in
     // tiles of 16 rows in the order the apply kernel's lanes load them
-    // (n_own padded to 16 rows; offsets h_toff)
+    // (n_own padded to 64 rows; offsets h_toff)
     bool dense_built = false, use_dense = false;
     int Pp = 0;                                   // P padded to 16
     std::vector<int32_t> h_ld, h_nown;
@@ -635,11 +635,15 @@ constexpr int kDenseRowChoices[] = {64, 32};   // rows per wave
 constexpr int kDenseLd = 64;         // local-node padding of the stored rows
 
 // Tiled storage of one subdomain's inverse rows, for entries of TS (KL =
-// 16 / sizeof(TS) per 16-byte load, KSUP = 8 KL per super-step): row tile
-// rt (rows 16 rt .. 16 rt + 15), super-step ks, half h and lane
+// 16 / sizeof(TS) per 16-byte load, KSUP = 8 KL per super-step).  Rows come
+// in blocks of four row tiles (64 rows, n_own padded to a multiple of 64):
+// row tile rt (rows 16 rt .. 16 rt + 15), super-step ks, half h and lane
 // l = i + 16 g hold the KL entries of row 16 rt + i at columns
 // ks KSUP + 2 KL g + h KL + (0 .. KL-1), at element offset
-// rt 16 ld + ((2 ks + h) 64 + l) KL.  Rows past n_own are zero.
+// (rt / 4) 64 ld + (((2 ks + h) 4 + rt % 4) 64 + l) KL.  A wave that takes
+// the four tiles of a block reads one contiguous 4 KB per half super-step.
+// Rows past n_own are zero.
+constexpr int kTileBlock = 4;                 // row tiles per stored block
 template <class TS>
 __global__ __launch_bounds__(256) void tile_dense_kernel(
     const int32_t* __restrict__ nown, const int32_t* __restrict__ ld,
@@ -648,15 +652,16 @@ __global__ __launch_bounds__(256) void tile_dense_kernel(
     constexpr int KL = 16 / sizeof(TS);
     const int s = blockIdx.x, rt = blockIdx.y;
     const int no = nown[s];
-    if (16 * rt >= no) return;
+    if (16 * rt >= (no + 63) / 64 * 64) return;
     const int L = ld[s];
     const double* src = rows + aoff[s];
-    TS* dst = out + toff[s] + (int64_t)rt * 16 * L;
+    TS* dst = out + toff[s] + (int64_t)(rt / kTileBlock) * 64 * L + (rt % kTileBlock) * 64 * KL;
     for (int o = threadIdx.x; o < 16 * L; o += 256) {
         const int e = o % KL, l = (o / KL) & 63, h = (o / (64 * KL)) & 1, ks = o / (128 * KL);
         const int row = 16 * rt + (l & 15);
         const int col = ks * 8 * KL + 2 * KL * (l >> 4) + h * KL + e;
-        dst[o] = Mma<TS>::conv(row < no ? src[(int64_t)row * L + col] : 0.0);
+        dst[(int64_t)(o / (64 * KL)) * kTileBlock * 64 * KL + o % (64 * KL)] =
+            Mma<TS>::conv(row < no ? src[(int64_t)row * L + col] : 0.0);
     }
 }
 
@@ -743,12 +748,15 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
     if (r0 >= no) return;
     const int L = ld[s];
     const int i = lane & 15, g = lane >> 4;
-    // row tiles past the last one (their rows are not stored) read the last
-    const int nrt = (no + 15) >> 4;
+    // r0 is a multiple of 16 MT: the wave's row tiles lie in one stored block
+    // (tiles past n_own are zero)
     const TS* A[MT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-        A[m] = ainv + toff[s] + (int64_t)min((r0 >> 4) + m, nrt - 1) * 16 * L + lane * KL;
+    for (int m = 0; m < MT; ++m) {
+        const int rt = (r0 >> 4) + m;
+        A[m] = ainv + toff[s] + (int64_t)(rt / kTileBlock) * 64 * L +
+               (rt % kTileBlock) * 64 * KL + lane * KL;
+    }
     const TS* X = xg + xoff[s] + (int64_t)i * L + 2 * KL * g;
     Acc acc[MT][NT];
 #pragma unroll
@@ -761,8 +769,9 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(
     auto load = [&](int buf, int k) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-            av[buf][m][0] = *reinterpret_cast<const uint4*>(A[m] + 16 * k);
-            av[buf][m][1] = *reinterpret_cast<const uint4*>(A[m] + 16 * k + 64 * KL);
+            av[buf][m][0] = *reinterpret_cast<const uint4*>(A[m] + 16 * kTileBlock * k);
+            av[buf][m][1] =
+                *reinterpret_cast<const uint4*>(A[m] + 16 * kTileBlock * k + kTileBlock * 64 * KL);
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -810,8 +819,11 @@ inline int fused_max_nt(sg_prec prec) { return prec == SG_FP64 ? 1 : 3; }
 // multiply it by Gt^{-1} (half the columns each) and write it back, and the
 // wave stores the slice to Z with consecutive lanes on consecutive entries
 // of the flattened rows; then the other 32 rows.
+// After them, per wave, the global node of each of its 64 rows and that
+// node's coarse owner (two int32 each).
 inline size_t dense_post_lds(int P, int Pp, size_t acc_bytes) {
-    return ((size_t)kFusedWaves * 32 * (Pp + 1) + (size_t)P * Pp) * acc_bytes;
+    return ((size_t)kFusedWaves * 32 * (Pp + 1) + (size_t)P * Pp) * acc_bytes +
+           (size_t)kFusedWaves * 128 * sizeof(int32_t);
 }
 
 // STORE: 0 = stores from the matrix-core layout (dense_epilogue); 1 = the
@@ -846,22 +858,20 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     const int nks = L / KSUP;
     const int node0 = sub_node_off[s], nloc = sub_node_off[s + 1] - node0;
     const bool active = r0 < no;
-    const int nrt = (no + 15) >> 4;
-    // scalar base per row tile plus one 32-bit byte offset per lane (a row
-    // tile holds 16 ld entries, well below 4 GB)
-    const char* A[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-        A[m] = reinterpret_cast<const char*>(ainv + toff[s] +
-                                             (int64_t)min((r0 >> 4) + m, nrt - 1) * 16 * L);
+    // the wave's four row tiles are one stored block (r0 is a multiple of
+    // 64): a scalar base plus one 32-bit byte offset per lane (a block holds
+    // 64 ld entries, well below 4 GB)
+    static_assert(MT == kTileBlock, "one wave streams one block of row tiles");
+    const char* A = reinterpret_cast<const char*>(ainv + toff[s] + (int64_t)(r0 >> 6) * 64 * L);
     // the stream runs in half super-steps (one MFMA k-step pair for BF16):
-    // half j of a row tile is the 1 KB at byte 1024 j, and its B fragments
-    // are piece (2 (j / 2) NT + 2 t + j % 2) 64 + lane
+    // half j of row tile m is the 1 KB at byte 1024 (4 j + m), and its B
+    // fragments are piece (2 (j / 2) NT + 2 t + j % 2) 64 + lane
     uint4 av[3][MT];
     auto aload = [&](int slot, int j) {
-        const uint32_t off = (uint32_t)lane * 16u + (uint32_t)j * 1024u;
+        const uint32_t off = (uint32_t)lane * 16u + (uint32_t)j * (1024u * MT);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[slot][m] = *reinterpret_cast<const uint4*>(A[m] + off);
+        for (int m = 0; m < MT; ++m)
+            av[slot][m] = *reinterpret_cast<const uint4*>(A + off + 1024u * m);
     };
     const int nh = 2 * nks;   // >= 2
     if (active) {             // the first three half-steps load during the gather
@@ -963,11 +973,12 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             for (int r = 0; r < 3; ++r) {
                 const int jj = j + r;
                 if (jj < j1) {
-                    if (active) {
-                        compute(r, jj);
-                        if (jj + 3 < nh) aload(r, jj + 3);
-                    }
+                    // the gather's stores wait for its loads of the previous
+                    // half-step and for every load issued before them; the A
+                    // loads issued after those stay in flight
+                    if (active) compute(r, jj);
                     if (cn > 0) gather_step();
+                    if (active && jj + 3 < nh) aload(r, jj + 3);
                 }
             }
         }
@@ -976,23 +987,30 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             for (int u = 0; u < 2; ++u)
                 if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
             for (; ge < cn; ge += kThreads) put(c + 1, ge, fetch(c + 1, ge));
-            __syncthreads();
+            lds_barrier();   // the ring's A loads stay in flight across it
         }
     }
     if constexpr (STORE != 0) {
         using AT = typename std::conditional<std::is_same<TS, double>::value, double, float>::type;
         constexpr int RS = Pp + 1;          // odd row stride: conflict-free row reads
         constexpr int JH = Pp / 2;          // columns per lane (two lanes per row)
+        constexpr int UB = 8;               // stores per batch, their loads issued together
         __syncthreads();                    // every wave has streamed: the LDS is free
         // Gt^{-1} after the row slices, in the accumulator precision
         AT* ps = reinterpret_cast<AT*>(lds_b) + (size_t)kFusedWaves * 32 * RS;
+        int32_t* info = reinterpret_cast<int32_t*>(ps + (STORE == 1 ? P * Pp : 0)) + wave * 128;
+        if (active) {   // this wave's rows: global node, and its coarse owner
+            const int row = r0 + lane;
+            const int gn = row < no ? own_gnode[own_off[s] + row] : 0;
+            info[lane] = gn;
+            info[64 + lane] = (cadd && row < no) ? cown[gn] : 0;
+        }
         if (STORE == 1) {
             for (int q = tid; q < P * Pp; q += kThreads) ps[q] = (AT)post[q];
             __syncthreads();
         }
         if (!active) return;
         AT* rb = reinterpret_cast<AT*>(lds_b) + (size_t)wave * 32 * RS;
-        const int32_t* og = own_gnode + own_off[s];
         const int i = lane & 15;
         const int row = lane & 31, j0 = (lane >> 5) * JH;
 #pragma unroll
@@ -1020,20 +1038,35 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
 #pragma unroll
                 for (int j = 0; j < JH; ++j) rb[row * RS + j0 + j] = z[j];
             }
-            const int rbase = r0 + 32 * hf;
-            const int nr = min(32, no - rbase);
-            for (int e = lane; e < nr * P; e += 64) {
-                const int rr = e / P, c = e - rr * P;
-                const int64_t zo = (int64_t)og[rbase + rr] * P + c;
-                const double val = STORE == 1 ? omega * (double)rb[rr * RS + c]
-                                              : omega * (double)rb[rr * RS + c] / afact[c];
-                if (beta != 0.0) {
-                    double zold = Z[zo];
-                    // z2 = z1 + Z e_c formed here, as the prolongation would
-                    if (cadd) zold += cadd[(int64_t)cown[og[rbase + rr]] * P + c];
-                    Z[zo] = fma(beta, zold, val);
-                } else {
-                    Z[zo] = val;
+            // entry e of the slice is row e / P, column e % P; the old values
+            // of a batch (Z and the coarse correction) are loaded before any
+            // of its stores, so they are in flight together
+            const int rbase = 32 * hf;
+            const int ne = min(32, no - (r0 + rbase)) * P;
+            for (int e0 = lane; e0 < ne; e0 += UB * 64) {
+                double zold[UB], cv[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = e0 + 64 * u;
+                    const int rr = e / P, c = e - rr * P;
+                    zold[u] = 0.0;
+                    cv[u] = 0.0;
+                    if (beta != 0.0 && e < ne) {
+                        zold[u] = Z[(int64_t)info[rbase + rr] * P + c];
+                        // z2 = z1 + Z e_c formed here, as the prolongation would
+                        if (cadd) cv[u] = cadd[(int64_t)info[64 + rbase + rr] * P + c];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = e0 + 64 * u;
+                    if (e < ne) {
+                        const int rr = e / P, c = e - rr * P;
+                        const double val = STORE == 1 ? omega * (double)rb[rr * RS + c]
+                                                      : omega * (double)rb[rr * RS + c] / afact[c];
+                        const double zo = cadd ? zold[u] + cv[u] : zold[u];
+                        Z[(int64_t)info[rbase + rr] * P + c] = beta != 0.0 ? fma(beta, zo, val) : val;
+                    }
                 }
             }
         }
@@ -1437,7 +1470,7 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
             r->h_ld[q] = (a1 - a0 + kDenseLd - 1) / kDenseLd * kDenseLd;
             r->h_nown[q] = no;
             r->h_aoff[q + 1] = r->h_aoff[q] + (int64_t)no * r->h_ld[q];
-            r->h_toff[q + 1] = r->h_toff[q] + (int64_t)(no + 15) / 16 * 16 * r->h_ld[q];
+            r->h_toff[q + 1] = r->h_toff[q] + (int64_t)(no + 63) / 64 * 64 * r->h_ld[q];
             r->h_xoff[q + 1] = r->h_xoff[q] + (int64_t)r->Pp * r->h_ld[q];
             own_off[q + 1] = own_off[q] + no;
             for (int v = 0; v < 3; ++v)
@@ -1505,7 +1538,7 @@ void ras_build_dense(sg_ras* r, hipStream_t s) {
     const int64_t tiled = r->h_toff[ns];
     int maxo = 0;
     for (int q = 0; q < ns; ++q) maxo = std::max(maxo, r->h_nown[q]);
-    const dim3 tg(ns, std::max(1, (maxo + 15) / 16));
+    const dim3 tg(ns, std::max(1, (maxo + 63) / 64 * kTileBlock));
     // A rebuild (ras_refactor) keeps the buffer when its size is unchanged, so
     // captured Arnoldi-step graphs that read it stay valid.
 #define SG_TILE(TS, BUF)                                                                           \
