@@ -677,17 +677,19 @@ constexpr int kBufDoubles = kSlots * JC;          // one staged chunk: [slot][JC
 constexpr int kDmaBlocks = kBufDoubles * 2 / 64;  // 64 dwords per wave-wide DMA
 static_assert(kBufDoubles * 2 % 64 == 0, "a chunk must be whole DMA blocks");
 
-// LDS: two chunk buffers, or the partial sums of the input-term groups
-// (after the last chunk); then the source row of each staging slot and the
-// staging offset of each entry of the tile's rows.
+// LDS: two chunk buffers, each its own array.  A DMA into one array does
+// not make the compiler wait for it before reads of the other (it keeps the
+// two apart; slices of one array it could not), so chunk C + 1 streams in
+// while chunk C is read.  After the last chunk the buffers take the partial
+// sums of the input-term groups, one group at a time, output group kg in
+// buffer kg.  The dynamic LDS holds the source row of each staging slot and
+// the staging offset of each entry of the tile's rows.
 template <int S>
 constexpr size_t kTableDoubles = (kSlots + S * RB + 1) / 2;
 
 template <int P, int S>
 constexpr size_t lds_doubles(int IGN, int KGN) {
-    const size_t stage = 2 * (size_t)kBufDoubles;
-    const size_t red = (size_t)(IGN - 1) * KGN * ((P + KGN - 1) / KGN) * RB;
-    return (stage > red ? stage : red) + kTableDoubles<S>;
+    return kTableDoubles<S>;
 }
 
 // Stage chunk C of the tile's neighbour rows into buf by LDS DMA: dword d of
@@ -798,17 +800,17 @@ __device__ __forceinline__ void chunk_groups(std::integer_sequence<int, Gs...>, 
 template <int M, int PIN, int PO, int S, int IGN, int KGN, int LI, int NCH, int... Cs>
 __device__ __forceinline__ void chunks(std::integer_sequence<int, Cs...>, int wave, int lane,
                                        const int* srows, const int* soff, const double (*v)[LI],
-                                       double* lds, const double* __restrict__ X, double* y) {
+                                       double* buf0, double* buf1, const double* __restrict__ X,
+                                       double* y) {
     constexpr int P = tab::cbinom(M + PO, PO);
     (([&] {
          // chunk Cs + 1 streams into the other buffer (last read in chunk Cs - 1,
          // before the barrier that ended it) while chunk Cs is computed
          if constexpr (Cs + 1 < NCH)
-             stage_dma<P, Cs + 1, IGN * KGN>(X, srows, lds + ((Cs + 1) & 1) * kBufDoubles, wave,
-                                             lane);
+             stage_dma<P, Cs + 1, IGN * KGN>(X, srows, (Cs + 1) & 1 ? buf1 : buf0, wave, lane);
          chunk_groups<M, PIN, PO, S, IGN, KGN, LI, Cs>(
              std::make_integer_sequence<int, IGN * KGN>{}, wave, lane, soff, v,
-             lds + (Cs & 1) * kBufDoubles, y);
+             Cs & 1 ? buf1 : buf0, y);
          dma_wait();
          __syncthreads();
      }()),
@@ -827,8 +829,11 @@ void kron_matvec_group_kernel(int n, int ntiles, const int32_t* __restrict__ run
     constexpr int NCH = (P + JC - 1) / JC;
     constexpr int kThreads = 64 * IGN * KGN;
     static_assert(kThreads >= kSlots && kThreads >= S * RB, "threads for the LDS tables");
+    static_assert(KGN <= 2 && KL * RB <= kBufDoubles, "partial sums of a group fit one buffer");
+    __shared__ __align__(16) double buf0[kBufDoubles];
+    __shared__ __align__(16) double buf1[kBufDoubles];
     extern __shared__ __align__(16) double glds[];
-    int* srows = reinterpret_cast<int*>(glds + (lds_doubles<P, S>(IGN, KGN) - kTableDoubles<S>));
+    int* srows = reinterpret_cast<int*>(glds);
     int* soff = srows + kSlots;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -853,26 +858,30 @@ void kron_matvec_group_kernel(int n, int ntiles, const int32_t* __restrict__ run
             v[q][ii] = i < L ? svals[(((size_t)tile * S + q) * L + i) * RB + lane] : 0.0;
         }
     __syncthreads();                                  // tables ready
-    stage_dma<P, 0, IGN * KGN>(X, srows, glds, wave, lane);
+    stage_dma<P, 0, IGN * KGN>(X, srows, buf0, wave, lane);
     double y[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) y[k] = 0.0;
     dma_wait();
     __syncthreads();                                  // chunk 0 staged
     chunks<M, PIN, PO, S, IGN, KGN, LI, NCH>(std::make_integer_sequence<int, NCH>{}, wave, lane,
-                                             srows, soff, v, glds, X, y);
-    // partial sums of input-term groups 1.. through LDS (the staging area is free)
-    double* red = glds;
-    if (ig > 0) {
-#pragma unroll
-        for (int k = 0; k < KL; ++k) red[(((size_t)(ig - 1) * KGN + kg) * KL + k) * RB + lane] = y[k];
-    }
-    __syncthreads();
-    if (ig > 0) return;
+                                             srows, soff, v, buf0, buf1, X, y);
+    // partial sums of input-term groups 1.. through LDS (the staging buffers
+    // are free), added to group 0's in group order
+    double* red = kg == 0 ? buf0 : buf1;
     for (int g2 = 1; g2 < IGN; ++g2) {
+        if (ig == g2) {
 #pragma unroll
-        for (int k = 0; k < KL; ++k) y[k] += red[(((size_t)(g2 - 1) * KGN + kg) * KL + k) * RB + lane];
+            for (int k = 0; k < KL; ++k) red[(size_t)k * RB + lane] = y[k];
+        }
+        __syncthreads();
+        if (ig == 0) {
+#pragma unroll
+            for (int k = 0; k < KL; ++k) y[k] += red[(size_t)k * RB + lane];
+        }
+        __syncthreads();
     }
+    if (ig > 0) return;
     const int row = tile * RB + lane;
     if (row >= n) return;
     const int k0 = kg * KL;
@@ -1162,9 +1171,7 @@ bool build_group(sg_op* op, hipStream_t s) {
     HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device));
     const GroupSpec g = kGroups[id];
     const int P = op->P;
-    const size_t need = (std::max(2 * (size_t)grp::kBufDoubles,
-                                  (size_t)(g.IGN - 1) * g.KGN * ((P + g.KGN - 1) / g.KGN) * RB) +
-                         (grp::kSlots + (size_t)S * RB + 1) / 2) * 8;
+    const size_t need = (2 * (size_t)grp::kBufDoubles + (grp::kSlots + (size_t)S * RB + 1) / 2) * 8;
     if (need > (size_t)lds_max) return false;
     op->sruns[0].upload(runs, s);
     op->sslot[0].upload(slot, s);
