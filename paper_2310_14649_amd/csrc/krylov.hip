@@ -276,6 +276,9 @@ __global__ __launch_bounds__(kVT) void cgsb_reduce_kernel(int nb, const double* 
 
 // U_t -= sum_q c_t[q] v_q (one pass over the basis); part_out[g nb + block]
 // = partial Gram entry g of the projected vectors (pairs t <= u in order).
+// Each thread takes two consecutive entries per step (16-byte loads and
+// stores; ldv is even and the vectors 16-byte aligned); the last entry of
+// an odd N goes to thread 0 of block 0.
 template <int S>
 __global__ __launch_bounds__(kVT) void cgsb_update_kernel(int64_t N, int nb, int ni, int64_t ldv,
                                                           double* __restrict__ U,
@@ -292,25 +295,52 @@ __global__ __launch_bounds__(kVT) void cgsb_update_kernel(int64_t N, int nb, int
     double g[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) g[q] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
-        double x[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
-        for (int q = 0; q < ni; ++q) {
-            const double v = V[(size_t)q * ldv + e];
-#pragma unroll
-            for (int t = 0; t < S; ++t) x[t] = fma(-cs[t][q], v, x[t]);
-        }
+    auto gram = [&](const double* x) {
         int k = 0;
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-            U[(size_t)t * ldv + e] = x[t];
+        for (int t = 0; t < S; ++t)
 #pragma unroll
             for (int u = t; u < S; ++u) {
                 g[k] = fma(x[t], x[u], g[k]);
                 ++k;
             }
+    };
+    const int64_t N2 = N >> 1;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N2; e += (int64_t)gridDim.x * kVT) {
+        double x0[S], x1[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const double2 u2 = reinterpret_cast<const double2*>(U + (size_t)t * ldv)[e];
+            x0[t] = u2.x;
+            x1[t] = u2.y;
         }
+#pragma unroll 4
+        for (int q = 0; q < ni; ++q) {
+            const double2 v = reinterpret_cast<const double2*>(V + (size_t)q * ldv)[e];
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                x0[t] = fma(-cs[t][q], v.x, x0[t]);
+                x1[t] = fma(-cs[t][q], v.y, x1[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+            reinterpret_cast<double2*>(U + (size_t)t * ldv)[e] = make_double2(x0[t], x1[t]);
+        gram(x0);
+        gram(x1);
+    }
+    if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + N - 1];
+        for (int q = 0; q < ni; ++q) {
+            const double v = V[(size_t)q * ldv + N - 1];
+#pragma unroll
+            for (int t = 0; t < S; ++t) x[t] = fma(-cs[t][q], v, x[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) U[(size_t)t * ldv + N - 1] = x[t];
+        gram(x);
     }
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
@@ -386,10 +416,7 @@ __global__ __launch_bounds__(kVT) void block_qr_kernel(int64_t N, int nb, int64_
     double inv[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) inv[t] = R[t][t] > 0.0 ? 1.0 / R[t][t] : 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N; e += (int64_t)gridDim.x * kVT) {
-        double x[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + e];
+    auto solve = [&](double* x) {
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             double y = x[t];
@@ -397,8 +424,30 @@ __global__ __launch_bounds__(kVT) void block_qr_kernel(int64_t N, int nb, int64_
             for (int q = 0; q < t; ++q) y = fma(-R[q][t], x[q], y);
             x[t] = y * inv[t];
         }
+    };
+    // two consecutive entries per thread and step, as in cgsb_update_kernel
+    const int64_t N2 = N >> 1;
+    for (int64_t e = (int64_t)blockIdx.x * kVT + threadIdx.x; e < N2; e += (int64_t)gridDim.x * kVT) {
+        double x0[S], x1[S];
 #pragma unroll
-        for (int t = 0; t < S; ++t) U[(size_t)t * ldv + e] = x[t];
+        for (int t = 0; t < S; ++t) {
+            const double2 u2 = reinterpret_cast<const double2*>(U + (size_t)t * ldv)[e];
+            x0[t] = u2.x;
+            x1[t] = u2.y;
+        }
+        solve(x0);
+        solve(x1);
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+            reinterpret_cast<double2*>(U + (size_t)t * ldv)[e] = make_double2(x0[t], x1[t]);
+    }
+    if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double x[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) x[t] = U[(size_t)t * ldv + N - 1];
+        solve(x);
+#pragma unroll
+        for (int t = 0; t < S; ++t) U[(size_t)t * ldv + N - 1] = x[t];
     }
 }
 
