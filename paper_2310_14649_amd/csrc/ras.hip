@@ -1023,7 +1023,39 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
                     for (int v = 0; v < 4; ++v)
                         rb[(16 * m + Mma<TS>::row_of(lane, v)) * RS + 16 * t + i] =
                             acc[2 * hf + m][t][v];
-            if (STORE == 1) {
+            if constexpr (STORE == 1 && std::is_same<AT, float>::value) {
+                // the slice times Gt^{-1} on the matrix cores: 32 x Pp by
+                // P x Pp in k-steps of 4 (A from the slice, whose columns
+                // P .. Pp - 1 are zero; B rows past P read as zero), then the
+                // products written over the slice; the LDS runs a wave's
+                // instructions in order, so every read precedes the writes
+                using Acc = typename Mma<float>::Acc;
+                Acc z[2][NT];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) z[m][t] = Mma<float>::zero();
+                for (int k0 = 0; k0 < P; k0 += 4) {
+                    const int kk = k0 + (lane >> 4);
+                    float a[2], b[NT];
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) a[m] = rb[(16 * m + i) * RS + kk];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) b[t] = kk < P ? ps[kk * Pp + 16 * t + i] : 0.f;
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            z[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[t], z[m][t], 0, 0, 0);
+                }
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            rb[(16 * m + Mma<float>::row_of(lane, v)) * RS + 16 * t + i] = z[m][t][v];
+            } else if constexpr (STORE == 1) {
                 AT z[JH];
 #pragma unroll
                 for (int j = 0; j < JH; ++j) z[j] = AT(0);
