@@ -866,7 +866,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
     // the stream runs in half super-steps (one MFMA k-step pair for BF16):
     // half j of row tile m is the 1 KB at byte 1024 (4 j + m), and its B
     // fragments are piece (2 (j / 2) NT + 2 t + j % 2) 64 + lane
-    uint4 av[3][MT];
+    constexpr bool kBurst = std::is_same<TS, float>::value;
+    uint4 av[kBurst ? 2 : 3][MT];
     auto aload = [&](int slot, int j) {
         const uint32_t off = (uint32_t)lane * 16u + (uint32_t)j * (1024u * MT);
 #pragma unroll
@@ -874,10 +875,12 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             av[slot][m] = *reinterpret_cast<const uint4*>(A + off + 1024u * m);
     };
     const int nh = 2 * nks;   // >= 2
-    if (active) {             // the first three half-steps load during the gather
+    if (active) {             // the first half-steps of the ring load during the gather
         aload(0, 0);
         aload(1, 1);
-        if (nh > 2) aload(2, 2);
+        if constexpr (!kBurst) {
+            if (nh > 2) aload(2, 2);
+        }
     }
     // The right-hand sides arrive in chunks of CS super-steps (a multiple of
     // three, so that chunk borders fall on the three-slot ring below).  Entry
@@ -945,49 +948,117 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             for (int m = 0; m < MT; ++m) dense_mma<TS>(acc[m][t], av[slot_][m], b);
         }
     };
-    // While chunk c streams, every thread (active wave or not) fetches two
-    // entries of chunk c + 1 per half-step and stores the two it fetched one
-    // half-step earlier; what is left of chunk c + 1 is fetched at the end of
-    // chunk c, then a barrier publishes it.  A wave's A stream is the ring of
-    // three half-steps: slot j % 3 is refilled three halves ahead once its
-    // products are issued.
-    for (int c = 0; c < nchunks; ++c) {
-        const int j0 = 2 * c * CS, j1 = min(2 * (c + 1) * CS, nh);
-        const int cn = c + 1 < nchunks ? chunk_count(c + 1) : 0;
-        int ge = tid;                      // next entry of chunk c + 1 for this thread
-        double gv[2] = {0.0, 0.0};
-        int ga[2] = {-1, -1};              // entries fetched one half-step ago
-        auto gather_step = [&]() {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                ga[u] = ge < cn ? ge : -1;
-                if (ga[u] >= 0) gv[u] = fetch(c + 1, ge);
-                ge += kThreads;
+    // Two forms of the stream, chosen by measurement on config 1: for FP32
+    // the gather in one burst per chunk (apply 430 -> 393 us after a cache
+    // flush); for BF16 the per-half-step gather (the burst form measured
+    // 186 -> 191 us back to back there), which FP64 keeps as well.
+    if constexpr (kBurst) {
+        // Entry e < chunk_count(c) of chunk c, read whatever the data: the node
+        // index is clamped and padded nodes are zeroed afterwards.
+        auto fetch_clamped = [&](int c, int e) {
+            const int q = c * CS * KSUP + e / P;
+            const double v = R[(int64_t)ids[min(q, nloc - 1)] * P + (e - (e / P) * P)];
+            return q < nloc ? v : 0.0;
+        };
+        // The stream of chunk c.  At its start every thread fetches its first
+        // GB entries of chunk c + 1 (entries tid, tid + 1024, ...) into
+        // registers; it stores them to LDS at the chunk's end, fetches what is
+        // left of the chunk, and a barrier publishes it.  In between, half-step
+        // jj runs the products of jj (A from ring slot jj % 2, B from LDS) and
+        // the A loads of half-step jj + 2 into the slot just used.  Every
+        // half-step issues the same loads whatever the data (addresses clamped,
+        // no load on one path only), so the compiler's count of loads in flight
+        // stays exact: the products of jj wait for the loads of jj (and those
+        // before), and the next half-step's loads stay in flight; the gathered
+        // entries are waited for once, at the chunk's end.  (Where a
+        // load is issued on one path only, the count is lost and every wait
+        // becomes a wait for all loads.)  Waves past the subdomain's rows (ACT
+        // false) only gather.
+        constexpr int GB = 7;
+        auto stream = [&](auto act, auto gather, int c) {
+            constexpr bool ACT = decltype(act)::value, GATHER = decltype(gather)::value;
+            const int j0 = 2 * c * CS, j1 = min(2 * (c + 1) * CS, nh);
+            const int cn = GATHER ? chunk_count(c + 1) : 0;
+            double gv[GB];
+            if constexpr (GATHER) {
+    #pragma unroll
+                for (int u = 0; u < GB; ++u)
+                    gv[u] = fetch_clamped(c + 1, min(tid + u * kThreads, cn - 1));
+            }
+            auto step = [&](int r, int jj) {
+                if constexpr (ACT) {
+                    compute(r, jj);
+                    aload(r, min(jj + 2, nh - 1));
+                }
+            };
+            // j0 and j1 - j0 are even: ring slot jj % 2 is r
+            for (int j = j0; j < j1; j += 2) {
+                step(0, j);
+                step(1, j + 1);
+            }
+            if constexpr (GATHER) {
+                // a thread past the chunk's entries fetched entry cn - 1 and
+                // stores that same value again
+    #pragma unroll
+                for (int u = 0; u < GB; ++u) put(c + 1, min(tid + u * kThreads, cn - 1), gv[u]);
+                for (int e = tid + GB * kThreads; e < cn; e += kThreads) put(c + 1, e, fetch(c + 1, e));
+                lds_barrier();   // the ring's A loads stay in flight across it
             }
         };
-        for (int j = j0; j < j1; j += 3) {
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int jj = j + r;
-                if (jj < j1) {
-                    // the gather's stores wait for its loads of the previous
-                    // half-step and for every load issued before them; the A
-                    // loads issued after those stay in flight
-                    if (active) compute(r, jj);
-                    if (cn > 0) gather_step();
-                    if (active && jj + 3 < nh) aload(r, jj + 3);
+        const std::true_type yes{};
+        const std::false_type no_{};
+        if (active) {
+            for (int c = 0; c + 1 < nchunks; ++c) stream(yes, yes, c);
+            stream(yes, no_, nchunks - 1);
+        } else {
+            for (int c = 0; c + 1 < nchunks; ++c) stream(no_, yes, c);
+            stream(no_, no_, nchunks - 1);
+        }
+    } else {
+        // While chunk c streams, every thread (active wave or not) fetches two
+        // entries of chunk c + 1 per half-step and stores the two it fetched one
+        // half-step earlier; what is left of chunk c + 1 is fetched at the end of
+        // chunk c, then a barrier publishes it.  A wave's A stream is the ring of
+        // three half-steps: slot j % 3 is refilled three halves ahead once its
+        // products are issued.
+        for (int c = 0; c < nchunks; ++c) {
+            const int j0 = 2 * c * CS, j1 = min(2 * (c + 1) * CS, nh);
+            const int cn = c + 1 < nchunks ? chunk_count(c + 1) : 0;
+            int ge = tid;                      // next entry of chunk c + 1 for this thread
+            double gv[2] = {0.0, 0.0};
+            int ga[2] = {-1, -1};              // entries fetched one half-step ago
+            auto gather_step = [&]() {
+    #pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
+    #pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    ga[u] = ge < cn ? ge : -1;
+                    if (ga[u] >= 0) gv[u] = fetch(c + 1, ge);
+                    ge += kThreads;
+                }
+            };
+            for (int j = j0; j < j1; j += 3) {
+    #pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int jj = j + r;
+                    if (jj < j1) {
+                        // the gather's stores wait for its loads of the previous
+                        // half-step and for every load issued before them; the A
+                        // loads issued after those stay in flight
+                        if (active) compute(r, jj);
+                        if (cn > 0) gather_step();
+                        if (active && jj + 3 < nh) aload(r, jj + 3);
+                    }
                 }
             }
-        }
-        if (cn > 0) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
-            for (; ge < cn; ge += kThreads) put(c + 1, ge, fetch(c + 1, ge));
-            lds_barrier();   // the ring's A loads stay in flight across it
+            if (cn > 0) {
+    #pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
+                for (; ge < cn; ge += kThreads) put(c + 1, ge, fetch(c + 1, ge));
+                lds_barrier();   // the ring's A loads stay in flight across it
+            }
         }
     }
     if constexpr (STORE != 0) {
