@@ -981,7 +981,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             const int cn = GATHER ? chunk_count(c + 1) : 0;
             double gv[GB];
             if constexpr (GATHER) {
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < GB; ++u)
                     gv[u] = fetch_clamped(c + 1, min(tid + u * kThreads, cn - 1));
             }
@@ -999,7 +999,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             if constexpr (GATHER) {
                 // a thread past the chunk's entries fetched entry cn - 1 and
                 // stores that same value again
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < GB; ++u) put(c + 1, min(tid + u * kThreads, cn - 1), gv[u]);
                 for (int e = tid + GB * kThreads; e < cn; e += kThreads) put(c + 1, e, fetch(c + 1, e));
                 lds_barrier();   // the ring's A loads stay in flight across it
@@ -1028,10 +1028,10 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
             double gv[2] = {0.0, 0.0};
             int ga[2] = {-1, -1};              // entries fetched one half-step ago
             auto gather_step = [&]() {
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 2; ++u)
                     if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     ga[u] = ge < cn ? ge : -1;
                     if (ga[u] >= 0) gv[u] = fetch(c + 1, ge);
@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
                 }
             };
             for (int j = j0; j < j1; j += 3) {
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int jj = j + r;
                     if (jj < j1) {
@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
                 }
             }
             if (cn > 0) {
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 2; ++u)
                     if (ga[u] >= 0) put(c + 1, ga[u], gv[u]);
                 for (; ge < cn; ge += kThreads) put(c + 1, ge, fetch(c + 1, ge));
