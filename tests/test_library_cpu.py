@@ -20,10 +20,10 @@ def _declared():
     return sorted(set(names))
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_the_method_calls():
     names = _declared()
     for call in ("sg_build_triples", "sg_assemble", "sg_matvec", "ras_apply", "amg_vcycle",
-                 "fgmres_solve"):
+                 "fgmres_solve", "newton_solve"):
         assert call in names
 
 
