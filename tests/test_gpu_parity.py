@@ -891,6 +891,44 @@ def test_full_size_ras_dense_and_fused_paths(full_c1):
         g16.close()
 
 
+@pytest.mark.parametrize("local", ["mean", "kron"])
+def test_fp32_fused_path_with_long_chunks(local):
+    """The FP32 fused dense RAS gathers the next chunk's right-hand sides in
+    bursts of seven entries per thread; subdomains of ~1,900 local nodes
+    (two work-groups of owned rows each) make chunks of 10,080 entries, so
+    the entries past the bursts take the fetch at the chunk's end.  The fused
+    result equals the two-kernel dense path's bit for bit with mean-based
+    local solves (same products in the same order), and to the FP32 level
+    with Kronecker ones (mixing on the output instead of the input); both
+    match the FP64 sweep to the FP32 level."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pr = make_problem("c1", nc=80, sub=(2, 2))
+    R = np.random.default_rng(61).standard_normal(pr.mesh.n * 35)
+    Rd = _to_dev(R)
+    out = {}
+    with GpuSG(pr, prec="fp64", coarse="none", ras_path="sweep", local=local) as g:
+        Z = g.new_vec()
+        B.ras_apply(g.ras, Rd, Z)
+        out["fp64"] = Z.clone()
+    with GpuSG(pr, prec="fp32", coarse="none", local=local) as g:
+        for path in ("dense", "fused"):
+            B.ras_select(g.ras, path)
+            assert B.ras_path_info(g.ras)[2] == path
+            Z = g.new_vec()
+            B.ras_apply(g.ras, Rd, Z)
+            out[path] = Z.clone()
+    for path in ("dense", "fused"):
+        err = float(torch.linalg.norm(out[path] - out["fp64"]) / torch.linalg.norm(out["fp64"]))
+        print(f"[gpu] fp32 {local} {path} vs fp64 sweep: {err:.2e}", flush=True)
+        assert err < 2e-5, path
+    if local == "mean":
+        assert torch.equal(out["dense"], out["fused"])
+    else:
+        d = float(torch.linalg.norm(out["fused"] - out["dense"]) / torch.linalg.norm(out["dense"]))
+        assert d < 2e-5
+
+
 # ------------------------------------------------------------------ a10
 def test_graph_replay_matches_eager(built):
     """Arnoldi steps replayed from captured graphs give the eager result bit
