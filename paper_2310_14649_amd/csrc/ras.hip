@@ -883,7 +883,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void dense_fused_kernel(
         }
     }
     // The right-hand sides arrive in chunks of CS super-steps (a multiple of
-    // three, so that chunk borders fall on the three-slot ring below).  Entry
+    // three, so that chunk borders fall on the three-slot ring below; the
+    // FP32 form's two-slot ring needs only the even count of half-steps).  Entry
     // e of a chunk is local node q0 + e / P, column e % P: consecutive threads
     // read consecutive entries of a node's row of R; padded nodes are zero.
     // Only chunks c (streamed) and c + 1 (gathered) are live at once, so the
