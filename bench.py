@@ -43,9 +43,28 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 1>", 261121, 35): 331.9e6,
                     ("kron_matvec_split_kernel<4, 2, 3, 5, 2>", 261121, 35): 335.9e6,
                     ("kron_matvec_split_kernel<4, 2, 3, 5, 4>", 261121, 35): 351.7e6}
+# The same for the fused dense RAS apply with Kronecker local solves and BF16
+# inverse rows (profiles/ras_512x512_P35_counters.txt), keyed by precision and
+# workload.
+MEASURED_RAS_TRAFFIC = {("bf16", 261121, 35): 872.1e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
                    "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel",
                    "grouped": "kron_matvec_group_kernel"}
+
+
+def ras_roofline(ras, prec: str, n: int, P: int):
+    """The RAS apply beside the matvec's roofline: it takes the larger share
+    of the mixed-precision solve (two applies per iteration against two
+    matvecs), so its HBM figures are reported the same way (algorithmic
+    bytes of one flushed apply over its HIP-event time); None without the
+    RAS part."""
+    if not ras or ras.get("path") not in ("fused", "dense", "dense32"):
+        return None
+    return {"bound": "hbm", "kernel": f"dense RAS ({ras['path']}, {prec})",
+            "achieved": ras["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ras["GBps"] / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_RAS_TRAFFIC.get((prec, n, P)) if ras["path"] == "fused" else None,
+            "traffic_unit": "bytes per launch"}
 
 
 def log(msg: str) -> None:
@@ -905,6 +924,7 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch"},
+        "roofline_ras": ras_roofline(parts.get("ras"), args.mixed, n, P),
         "parts": parts,
         "setup_s": {k: round(v, 2) for k, v in setup_s.items()},
         "ras_path": ras_paths,
