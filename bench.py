@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {("kron_matvec_split_kernel<4, 2, 3, 5, 1>", 261121, 35): 331
 MEASURED_RAS_TRAFFIC = {("bf16", 261121, 35): 872.1e6}
 MV_KERNEL_NAMES = {"staged": "kron_matvec_split_kernel", "pair": "kron_matvec_spec_kernel",
                    "wide": "kron_matvec_wide_kernel", "generic": "kron_matvec_kernel",
-                   "grouped": "kron_matvec_group_kernel"}
+                   "grouped": "kron_matvec_group_kernel", "row_tiled": "kron_matvec_rowtile_kernel"}
 
 
 def ras_roofline(ras, prec: str, n: int, P: int):

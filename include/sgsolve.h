@@ -180,8 +180,19 @@ int sg_matvec(const sg_op* op, const double* X, double* Y, void* stream);
  * between the waves of a 64-row tile, neighbour rows staged in LDS).
  * Host call. */
 enum { SG_MV_GENERIC = 0, SG_MV_WIDE = 1, SG_MV_PAIR = 2, SG_MV_STAGED = 3, SG_MV_GROUPED = 4,
-       SG_MV_MATRIX_FREE = 5 };
+       SG_MV_MATRIX_FREE = 5, SG_MV_ROW_TILED = 6 };
 int sg_matvec_kernel(const sg_op* op, int* kind);
+/* sg_matvec_row_tiled -- switch the row-tiled kernel of a wide operator on
+ * (enable != 0, the default where it is built) or off (the one-wave-per-row
+ * kernel SG_MV_WIDE).  The same operator, Y = sum_i K_i X G_i (Eq.
+ * Galerkin_L_exp), with one lane per row over tiles of 64 rows.  It is
+ * built for input bases with L > 32 terms and P <= 48 output modes, on
+ * patterns of at most 7 entries per row whose neighbour rows form at most 4
+ * runs of at most 256 rows per tile (lattice-ordered P1 meshes), e.g. the
+ * Jacobian and secant operators of sg_nl_setup; SG_ERR_UNSUPPORTED when
+ * enabling an operator without it.  Cached graphs of the operator are
+ * dropped on a change.  Host call. */
+int sg_matvec_row_tiled(sg_op* op, int enable);
 /* sg_matvec_matrix_free -- apply the operator without reading its stored
  * values (the matrix-free approach the paper names as future work, Sec. 5):
  * each row forms its K_i[a, b] from the six elements around it, with the

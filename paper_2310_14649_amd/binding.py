@@ -145,6 +145,7 @@ _SIGS = {
     "nn_set_output_map": (C.c_int, [_vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "nn_forward": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
     "sg_matvec_matrix_free": (C.c_int, [_vp, C.c_int, _vp]),
+    "sg_matvec_row_tiled": (C.c_int, [_vp, C.c_int]),
     "nn_fit_output_map": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "nn_input_fields": (C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "nn_loss_grad": (C.c_int, [_vp, _vp, _vp, C.c_int, _f64p, _vp]),
@@ -346,11 +347,16 @@ def sg_matvec(op, X, Y, stream=None):
     _check(lib().sg_matvec(op, _dev(X), _dev(Y), _stream(stream)))
 
 
-MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged", 4: "grouped", 5: "matrix_free"}
+MV_KERNELS = {0: "generic", 1: "wide", 2: "pair", 3: "staged", 4: "grouped", 5: "matrix_free",
+              6: "row_tiled"}
 
 
 def sg_matvec_matrix_free(op, enable: bool = True, stream=None):
     _check(lib().sg_matvec_matrix_free(op, 1 if enable else 0, _stream(stream)))
+
+
+def sg_matvec_row_tiled(op, enable: bool = True):
+    _check(lib().sg_matvec_row_tiled(op, 1 if enable else 0))
 
 
 def sg_matvec_kernel(op) -> str:

@@ -164,6 +164,16 @@ struct KronCsr {
     const double* ef = nullptr;        // [n_tri][M+1]: c0, g_1..g_M at the centroid
     const double* ek6 = nullptr;       // [n_tri][6] local stiffness (00,11,22,01,12,02) or null
     double ekL[6] = {}, ekU[6] = {};   // the two element matrices of a uniform lattice
+    // row-tiled kernel for wide input bases (one lane per row, tiles of 64
+    // rows; staging in sruns / sslot, values in svals): per (chunk of input
+    // terms, wave) a list of (i - chunk start) | j << 8 | mode slot << 16
+    // with its m_ijk, and the output mode of every (wave, slot) (-1 = none)
+    bool rowt = false;
+    int rt_nch = 0;
+    const int32_t* rt_lptr = nullptr;  // [nch][waves] + 1
+    const uint32_t* rt_lij = nullptr;
+    const double* rt_lm = nullptr;
+    const int32_t* rt_wk = nullptr;    // [waves][slots]
 };
 
 }  // namespace sg
@@ -207,6 +217,15 @@ struct sg_op {
     sg::DevBuf<double> mf_ef, mf_ek6;
     sg::DevBuf<int16_t> mf_sdir[3];
     double mf_ekL[6] = {}, mf_ekU[6] = {};
+    // row-tiled kernel (wide input bases): built when the pattern and the
+    // basis fit it, used while rt_on; rt_ent maps its value slots to CSR
+    // entries, for refreshing svals when the values change
+    bool rt_built = false, rt_on = false;
+    int rt_nch = 0;
+    sg::DevBuf<int32_t> rt_lptr, rt_wk;
+    sg::DevBuf<uint32_t> rt_lij;
+    sg::DevBuf<double> rt_lm;
+    sg::DevBuf<int64_t> rt_ent;
     // host copies used by the setup of the preconditioner
     std::vector<int32_t> h_rowptr, h_col;
     std::vector<int64_t> h_graph_ptr;           // mesh graph (overlap growth)
@@ -227,6 +246,12 @@ struct sg_op {
             k.ek6 = mf_uniform ? nullptr : mf_ek6.p;
             for (int q = 0; q < 6; ++q) { k.ekL[q] = mf_ekL[q]; k.ekU[q] = mf_ekU[q]; }
         }
+        k.rowt = rt_built && rt_on && split < 0 && group < 0;
+        if (k.rowt) {
+            k.sruns = sruns[0].p; k.sslot = sslot[0].p; k.svals = svals.p;
+            k.rt_nch = rt_nch; k.rt_lptr = rt_lptr.p; k.rt_lij = rt_lij.p; k.rt_lm = rt_lm.p;
+            k.rt_wk = rt_wk.p;
+        }
         return k;
     }
 };
@@ -238,6 +263,12 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
 // matvec.hip: pick a specialised kernel for this basis/pattern and build its
 // wave-tiled ELL copy of the values (no-op when none applies).
 void build_ell(sg_op* op, hipStream_t s);
+// matvec.hip: build the row-tiled kernel's staging, lists and value copy
+// when the basis is wide (L > 32) and the pattern fits; false otherwise.
+bool build_row_tiled(sg_op* op, hipStream_t s);
+// matvec.hip: copy op->vals into the row-tiled value layout (after the
+// values change; no-op when the kernel is not built).
+void refresh_row_tiled(sg_op* op, hipStream_t s);
 // triples.hip: upload a basis' triple table.
 void upload_triples(const sg_basis& b, TriplesDev& tr, hipStream_t s);
 // triples.hip: graded multi-indices of total degree <= p (count in `count`).

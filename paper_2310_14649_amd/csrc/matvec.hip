@@ -904,6 +904,162 @@ void kron_matvec_group_kernel(int n, int ntiles, const int32_t* __restrict__ run
 }
 }  // namespace grp
 
+// ---------------------------------------------------------------------------
+// Row-tiled kernel for wide input bases (L > 32 input terms, P <= 48 output
+// modes, at most 7 entries per row), e.g. the degree-2p coefficient fields of
+// a Newton Jacobian.  One work-group per tile of 64 rows, one lane per row:
+//   - the tile's neighbour rows are staged once in LDS by output column
+//     ([j][slot]), so lane a reads X[b_e, j] at its own slot of column j;
+//   - its K values pass through LDS in chunks of 8 input terms
+//     ([entry][term][lane], two buffers, the next chunk's loads in flight
+//     under the current chunk's products);
+//   - in each chunk, each of the 16 waves owns up to 3 output modes k
+//     (assigned on the host, chunk by chunk, to balance the chunk's triple
+//     counts, since the waves meet at a barrier after every chunk), takes
+//     their running sums from LDS into registers, walks the list of the
+//     chunk's triples (i, j, k) of its modes, forming
+//         y_k += m_ijk sum_e K_i[a, b_e] X[b_e, j],
+//     and puts the sums back.  The list is the same for every lane: it is
+//     read in batches of 8 entries (scalar loads, one wait per batch), and
+//     each LDS access is lane-contiguous (K, sums) or a row's own slot (X).
+// Every lane does T * 7 FMAs per row with 14 LDS reads each; the one-wave-
+// per-row kernel does the same work with lane-dependent (conflicting) LDS
+// addresses.
+namespace rowt {
+constexpr int RB = 64, S = 7, NW = 16, KS = 3, IC = 8, TB = 8;
+constexpr int kSlots = 256;                       // staged neighbour rows of one tile
+constexpr int kXs = kSlots + 1;                   // doubles per staged column (odd: spreads banks)
+constexpr int kThreads = 64 * NW;
+constexpr int kChunk = S * IC * RB;               // doubles of one K chunk
+constexpr int kPer = (kChunk + kThreads - 1) / kThreads;
+constexpr int kYs = RB + 1;                       // doubles per mode row of the sums
+static_assert(RB == split::RB, "the tile staging is the split kernel's one-tile staging");
+inline size_t lds_bytes(int P) {
+    return ((size_t)P * kXs + 2 * (size_t)kChunk + (size_t)P * kYs) * sizeof(double);
+}
+
+__global__ __launch_bounds__(kThreads) void kron_matvec_rowtile_kernel(
+    int n, int P, int L, int nch, const int32_t* __restrict__ runs,
+    const int16_t* __restrict__ sslot, const double* __restrict__ svals,
+    const int32_t* __restrict__ lptr, const uint32_t* __restrict__ lij,
+    const double* __restrict__ lm, const int32_t* __restrict__ wk, const double* __restrict__ X,
+    double* Y, double alpha, double beta, const double* C) {
+    using split::kRuns;
+    extern __shared__ __align__(16) double rl[];
+    double* Xs = rl;                                  // [P][kXs]
+    double* Kb = rl + (size_t)P * kXs;                // [2][S][IC][RB]
+    double* Ys = Kb + 2 * (size_t)kChunk;             // [P][kYs] running sums
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tile = blockIdx.x;
+    const int32_t* rw = runs + (size_t)tile * split::kRunWords;
+    int rrow[kRuns], rsl[kRuns];
+#pragma unroll
+    for (int u = 0; u < kRuns; ++u) {
+        rrow[u] = rw[u];
+        rsl[u] = rw[kRuns + u];
+    }
+    const int nslot = rw[2 * kRuns];
+    // neighbour rows, column by column (a run of slots is a run of rows, so
+    // consecutive threads read consecutive words of X)
+    for (int q = tid; q < nslot * P; q += kThreads) {
+        const int sl = q / P, j = q - sl * P;
+        int r = rrow[0] + (sl - rsl[0]);
+#pragma unroll
+        for (int u = 1; u < kRuns; ++u) r = (sl >= rsl[u]) ? rrow[u] + (sl - rsl[u]) : r;
+        Xs[(size_t)j * kXs + sl] = X[(size_t)r * P + j];
+    }
+    for (int q = tid; q < P * kYs; q += kThreads) Ys[q] = 0.0;
+    int xo[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) xo[e] = sslot[((size_t)tile * S + e) * RB + lane];
+    const double* kt = svals + (size_t)tile * S * L * RB;   // [S][L][RB]
+    const uint64_t* lmb = reinterpret_cast<const uint64_t*>(lm);
+    static_assert(TB == 8, "the batch barrier below names 8 entries");
+    double v[kPer];
+    auto kload = [&](int c) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int q = tid + u * kThreads;
+            const int qq = q < kChunk ? q : 0;
+            const int e = qq / (IC * RB), il = (qq / RB) % IC, ln = qq % RB;
+            const int i = c * IC + il;
+            v[u] = (q < kChunk && i < L) ? kt[((size_t)e * L + i) * RB + ln] : 0.0;
+        }
+    };
+    auto kstore = [&](double* buf) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int q = tid + u * kThreads;
+            if (q < kChunk) buf[q] = v[u];
+        }
+    };
+    kload(0);
+    kstore(Kb);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const double* cur = Kb + (size_t)(c & 1) * kChunk + lane;
+        const bool more = c + 1 < nch;
+        if (more) kload(c + 1);
+        // this chunk's modes of the wave (each mode has one owner per chunk;
+        // the barrier at the end of a chunk orders the hand-over)
+        int ks[KS];
+        double y[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            ks[s] = wk[((size_t)c * NW + wave) * KS + s];
+            y[s] = ks[s] >= 0 ? Ys[(size_t)ks[s] * kYs + lane] : 0.0;
+        }
+        const int t1 = lptr[c * NW + wave + 1];
+        for (int tb = lptr[c * NW + wave]; tb < t1; tb += TB) {
+            // a batch of list entries (the list array is padded by TB
+            // entries, so the batch never reads past it)
+            uint32_t wv[TB];
+            uint64_t mb[TB];
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                wv[u] = lij[tb + u];
+                mb[u] = lmb[tb + u];
+            }
+            // all of the batch's scalar loads are taken here, with one wait
+            // (the compiler would otherwise move each load to its use)
+            asm volatile("" ::"s"(wv[0]), "s"(wv[1]), "s"(wv[2]), "s"(wv[3]), "s"(wv[4]),
+                         "s"(wv[5]), "s"(wv[6]), "s"(wv[7]), "s"(mb[0]), "s"(mb[1]), "s"(mb[2]),
+                         "s"(mb[3]), "s"(mb[4]), "s"(mb[5]), "s"(mb[6]), "s"(mb[7]));
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                if (tb + u >= t1) break;
+                const double* kb = cur + (wv[u] & 0xffu) * RB;
+                const double* xb = Xs + (size_t)((wv[u] >> 8) & 0xffu) * kXs;
+                double x = 0.0;
+#pragma unroll
+                for (int e = 0; e < S; ++e) x = fma(kb[e * IC * RB], xb[xo[e]], x);
+                const double m = __longlong_as_double((long long)mb[u]);
+                const uint32_t sl = wv[u] >> 16;
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    if (sl == (uint32_t)s) y[s] = fma(m, x, y[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (ks[s] >= 0) Ys[(size_t)ks[s] * kYs + lane] = y[s];
+        if (more) kstore(Kb + (size_t)((c + 1) & 1) * kChunk);
+        __syncthreads();
+    }
+    // the tile's outputs, row-major (contiguous stores)
+    const int row0 = tile * RB;
+    const int rows = min(RB, n - row0);
+    for (int q = tid; q < rows * P; q += kThreads) {
+        const int r = q / P, k = q - r * P;
+        const size_t o = (size_t)row0 * P + q;
+        double outv = alpha * Ys[(size_t)k * kYs + r];
+        if (beta != 0.0) outv = fma(beta, C[o], outv);   // C may alias Y: read before the write
+        Y[o] = outv;
+    }
+}
+}  // namespace rowt
+
 // ELL copy: entry id of every (tile, slot, lane) position, -1 for padding.
 __global__ void ell_fill_kernel(int64_t npos, int L, int S, int RW, const int64_t* __restrict__ ent,
                                 const double* __restrict__ vals, double* __restrict__ evals) {
@@ -1213,7 +1369,10 @@ void build_ell(sg_op* op, hipStream_t s) {
             break;
         }
     }
-    if (id < 0) return;
+    if (id < 0) {
+        build_row_tiled(op, s);
+        return;
+    }
     const Spec sp = kSpecs[id];
     const int RW = 64 / sp.IG;
     const int n = op->n;
@@ -1242,6 +1401,98 @@ void build_ell(sg_op* op, hipStream_t s) {
     op->spec = id;
     op->ell_S = sp.S;
     op->ell_RW = RW;
+}
+
+bool build_row_tiled(sg_op* op, hipStream_t s) {
+    using namespace rowt;
+    const sg_basis& b = op->basis;
+    const int P = op->P, L = op->L, n = op->n;
+    op->rt_built = op->rt_on = false;
+    if (n == 0 || L <= 32 || P > NW * KS || op->max_row > S || b.tk.empty()) return false;
+    if (op->split >= 0 || op->group >= 0) return false;
+    int lds_max = 0;
+    HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device));
+    if (lds_bytes(P) > (size_t)lds_max) return false;
+    std::vector<int32_t> runs;
+    std::vector<int16_t> slot;
+    if (!split_staging(op, S, 1, runs, slot)) return false;
+    // per chunk of input terms: the chunk's output modes to (wave, slot),
+    // largest triple count in the chunk first, each to the least loaded wave
+    // with a free slot; then per (chunk, wave) the wave's triples ordered by
+    // (i, j, k), entry = (i - chunk start) | j << 8 | slot << 16
+    const int nch = (L + IC - 1) / IC;
+    std::vector<int> tord(b.tk.size());
+    for (size_t t = 0; t < tord.size(); ++t) tord[t] = (int)t;
+    std::sort(tord.begin(), tord.end(), [&](int x, int y) {
+        if (b.ti[x] != b.ti[y]) return b.ti[x] < b.ti[y];
+        if (b.tj[x] != b.tj[y]) return b.tj[x] < b.tj[y];
+        return b.tk[x] < b.tk[y];
+    });
+    std::vector<int32_t> wk((size_t)nch * NW * KS, -1);
+    std::vector<int32_t> lptr;
+    std::vector<uint32_t> lij;
+    std::vector<double> lm;
+    for (int c = 0; c < nch; ++c) {
+        std::vector<int> cnt(P, 0), kw(P, -1), ksl(P, -1);
+        for (int t : tord)
+            if (b.ti[t] / IC == c) ++cnt[b.tk[t]];
+        std::vector<int> order(P);
+        for (int k = 0; k < P; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cnt[x] > cnt[y]; });
+        std::vector<int> load(NW, 0), used(NW, 0);
+        for (int k : order) {
+            if (cnt[k] == 0) continue;
+            int best = -1;
+            for (int w = 0; w < NW; ++w)
+                if (used[w] < KS && (best < 0 || load[w] < load[best])) best = w;
+            if (best < 0) return false;
+            kw[k] = best;
+            ksl[k] = used[best];
+            wk[((size_t)c * NW + best) * KS + used[best]++] = k;
+            load[best] += cnt[k];
+        }
+        for (int w = 0; w < NW; ++w) {
+            lptr.push_back((int32_t)lij.size());
+            for (int t : tord) {
+                if (b.ti[t] / IC != c || kw[b.tk[t]] != w) continue;
+                lij.push_back((uint32_t)(b.ti[t] % IC) | ((uint32_t)b.tj[t] << 8) |
+                              ((uint32_t)ksl[b.tk[t]] << 16));
+                lm.push_back(b.tv[t]);
+            }
+        }
+    }
+    lptr.push_back((int32_t)lij.size());
+    lij.resize(lij.size() + TB, 0u);                  // batches read up to TB entries ahead
+    lm.resize(lm.size() + TB, 0.0);
+    const int tiles = (n + RB - 1) / RB;
+    std::vector<int64_t> ent((size_t)tiles * S * RB, -1);
+    for (int a = 0; a < n; ++a) {
+        const int t = a / RB, r = a % RB;
+        int q = 0;
+        for (int e = op->h_rowptr[a]; e < op->h_rowptr[a + 1]; ++e, ++q)
+            ent[((size_t)t * S + q) * RB + r] = e;
+    }
+    op->sruns[0].upload(runs, s);
+    op->sslot[0].upload(slot, s);
+    op->rt_lptr.upload(lptr, s);
+    op->rt_lij.upload(lij, s);
+    op->rt_lm.upload(lm, s);
+    op->rt_wk.upload(wk, s);
+    op->rt_ent.upload(ent, s);
+    op->svals.alloc((size_t)tiles * S * RB * L);
+    op->rt_nch = nch;
+    op->rt_built = op->rt_on = true;
+    refresh_row_tiled(op, s);
+    HIP_OK(hipStreamSynchronize(s));   // the host vectors are freed on return
+    return true;
+}
+
+void refresh_row_tiled(sg_op* op, hipStream_t s) {
+    if (!op->rt_built) return;
+    const int64_t npos = (int64_t)((op->n + rowt::RB - 1) / rowt::RB) * rowt::S * rowt::RB;
+    ell_fill_kernel<<<(unsigned)((npos * op->L + 255) / 256), 256, 0, s>>>(
+        npos, op->L, rowt::S, rowt::RB, op->rt_ent.p, op->vals.p, op->svals.p);
+    HIP_LAUNCH_OK();
 }
 
 void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X, double* Y,
@@ -1274,6 +1525,14 @@ void kron_matvec(const KronCsr& A, int L, const TriplesDev& tr, const double* X,
             case 3: launch_spec<3>(A, X, Y, alpha, beta, C, s); break;
             default: SG_THROW(SG_ERR_INVALID_ARG, "bad matvec specialisation %d", A.spec);
         }
+        HIP_LAUNCH_OK();
+        return;
+    }
+    if (A.rowt) {
+        const int tiles = (A.n + rowt::RB - 1) / rowt::RB;
+        rowt::kron_matvec_rowtile_kernel<<<tiles, rowt::kThreads, rowt::lds_bytes(P), s>>>(
+            A.n, P, L, A.rt_nch, A.sruns, A.sslot, A.svals, A.rt_lptr, A.rt_lij, A.rt_lm, A.rt_wk,
+            X, Y, alpha, beta, C);
         HIP_LAUNCH_OK();
         return;
     }
@@ -1388,11 +1647,25 @@ extern "C" int sg_matvec_matrix_free(sg_op* op, int enable, void* stream) {
     });
 }
 
+extern "C" int sg_matvec_row_tiled(sg_op* op, int enable) {
+    return guarded([&]() -> int {
+        SG_REQUIRE(op != nullptr, "op is NULL");
+        check_device(op->device);
+        if (enable && !op->rt_built)
+            SG_THROW(SG_ERR_UNSUPPORTED, "the operator has no row-tiled matvec");
+        if (op->rt_on != (enable != 0)) graph_cache_purge(op);
+        op->rt_on = enable != 0;
+        return SG_OK;
+    });
+}
+
 extern "C" int sg_matvec_kernel(const sg_op* op, int* kind) {
     return guarded([&]() -> int {
         SG_REQUIRE(op && kind, "null argument");
         if (op->mf_on && op->split >= 0)
             *kind = SG_MV_MATRIX_FREE;
+        else if (op->rt_built && op->rt_on && op->split < 0 && op->group < 0)
+            *kind = SG_MV_ROW_TILED;
         else if (op->group >= 0)
             *kind = SG_MV_GROUPED;
         else if (op->split >= 0)

@@ -244,6 +244,7 @@ std::unique_ptr<sg_op> make_op(const MeshPattern& mp, int n, const sg_basis& jb,
     op->F.alloc(n);
     op->afact.upload(jb.afact, s);
     upload_triples(jb, op->tr, s);
+    build_row_tiled(op.get(), s);      // wide bases (L2 > 32): the row-tiled matvec
     return op;
 }
 
@@ -261,6 +262,8 @@ void nl_eval(sg_nl* nl, const double* U, double* R, hipStream_t s) {
                                                  nl->ed.ek.p, nl->w1.p, nl->yt.p, nl->j1->vals.p,
                                                  nl->jac->vals.p);
     HIP_LAUNCH_OK();
+    refresh_row_tiled(nl->j1.get(), s);
+    refresh_row_tiled(nl->jac.get(), s);
     if (R) kron_matvec(nl->j1->csr(), nl->L2, nl->j1->tr, U, R, -1.0, 1.0, nl->B.p, s);
 }
 

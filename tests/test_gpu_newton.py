@@ -127,6 +127,44 @@ def test_picard_matches_oracle(case):
     assert _rel(U, U_newton) < 1e-8
 
 
+def test_row_tiled_matvec_matches_oracle_and_wide_kernel():
+    """The Jacobian and secant operators of config 4's basis (L2 = 210,
+    P = 35) take the row-tiled kernel; on 6 tiles of 64 rows with a ragged
+    last tile (19 x 19 nodes) J V and K1 V match the oracle, and the
+    one-wave-per-row kernel (the same sums in another order) to 1e-13."""
+    _cuda()
+    pr = make_problem("c4", nc=20, sub=(2, 2))
+    onl_pr = _oracle(pr)
+    rng = np.random.default_rng(11)
+    U = 0.4 * rng.standard_normal((onl_pr.n, onl_pr.P))
+    V = rng.standard_normal((onl_pr.n, onl_pr.P))
+    with GpuNewton(pr) as g:
+        jop, mop = B.sg_nl_jac_op(g.nl), B.sg_nl_mean_op(g.nl)
+        assert B.sg_matvec_kernel(jop) == "row_tiled"
+        assert B.sg_matvec_kernel(mop) == "row_tiled"
+        R = _host(g.residual(_dev(U)), U.shape)
+        out = {}
+        for on in (True, False):
+            B.sg_matvec_row_tiled(jop, on)
+            B.sg_matvec_row_tiled(mop, on)
+            assert B.sg_matvec_kernel(jop) == ("row_tiled" if on else "wide")
+            JV = _host(g.jac_apply(_dev(V)), V.shape)
+            KV = torch.empty(onl_pr.n * onl_pr.P, dtype=torch.float64, device="cuda")
+            B.sg_matvec(mop, _dev(V), KV)
+            out[on] = (JV, _host(KV, V.shape))
+        B.sg_matvec_row_tiled(jop, True)
+        B.sg_matvec_row_tiled(mop, True)
+        R2 = _host(g.residual(_dev(U)), U.shape)
+    print(f"[gpu] row-tiled vs wide: J V {_rel(out[True][0], out[False][0]):.1e}, "
+          f"K1 V {_rel(out[True][1], out[False][1]):.1e}", flush=True)
+    assert _rel(R, onl_pr.residual(U)) < 1e-12
+    assert np.array_equal(R, R2)
+    assert _rel(out[True][0], (onl_pr.jacobian(U) @ V.ravel()).reshape(V.shape)) < 1e-12
+    assert _rel(out[True][1], (onl_pr.secant(U) @ V.ravel()).reshape(V.shape)) < 1e-12
+    assert _rel(out[True][0], out[False][0]) < 1e-13
+    assert _rel(out[True][1], out[False][1]) < 1e-13
+
+
 def test_jacobian_at_zero_is_the_linear_operator():
     """kappa(0) = 1, kappa'(0) = 0: J(0) = sum_i K_i (x) G_i of the linear problem."""
     _cuda()
