@@ -538,6 +538,38 @@ def bench_config3(args, torch) -> dict:
 SWEEP_SHAPES = [(2, 1), (4, 1), (2, 2), (4, 2), (6, 2), (3, 3), (4, 3), (2, 4), (4, 4)]
 
 
+def jac_apply_part(g, launches: int, torch) -> dict:
+    """The Newton Jacobian apply J V of a GpuNewton handle (at the last
+    evaluated U), timed alone after a flush (time_launches), against the
+    matvec's algorithmic bytes for its L2 values per entry."""
+    from paper_2310_14649_amd import binding as B
+    jop = B.sg_nl_jac_op(g.nl)
+    n, P, L, nnz = B.sg_op_info(jop)
+    V = torch.randn(n * P, dtype=torch.float64, device="cuda")
+    Y = g.new_vec()
+    mean_ms, med_ms = time_launches(lambda: B.sg_nl_jac_apply(g.nl, V, Y), launches, torch)
+    b = matvec_bytes(n, nnz, L, P)
+    gbs = b / (mean_ms * 1e-3) / 1e9
+    return {"kernel": B.sg_matvec_kernel(jop), "L": L, "P": P, "n": n, "nnz": nnz,
+            "us": round(mean_ms * 1e3, 2), "median_us": round(med_ms * 1e3, 2), "bytes": b,
+            "GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def jac_only(args, torch) -> dict:
+    """Config 4's Jacobian apply alone (for counters): the residual at a
+    seeded U sets the operator's values, then the flushed launches."""
+    from paper_2310_14649_amd.inputs import make_problem
+    from paper_2310_14649_amd.solver import GpuNewton
+    pr = make_problem("c4")
+    with GpuNewton(pr) as g:
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        U = 0.3 * torch.randn(g.n * g.P, dtype=torch.float64, device="cuda", generator=gen)
+        g.residual(U)
+        out = jac_apply_part(g, args.mv_launches, torch)
+    out["jac_only"] = True
+    return out
+
+
 def bench_newton(args, torch):
     """Config 4: Newton-FGMRES to ||R||/||F|| <= 1e-8 from the zero guess on
     the base draw, then the learned guess: training data from the solver,
@@ -558,6 +590,7 @@ def bench_newton(args, torch):
             U, info = g.solve(tol=1e-8)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["jacobian_apply"] = jac_apply_part(g, 20, torch)
         # the coarse hierarchy rebuilt at every Newton step instead of once
         g.solve(tol=1e-8, amg_rebuild=1)
         torch.cuda.synchronize()
@@ -660,6 +693,8 @@ def main() -> int:
                     help="RAS apply path: autotuned per precision, or forced")
     ap.add_argument("--ras-only", action="store_true",
                     help="time only one RAS apply (precision --part-prec) and print its figures")
+    ap.add_argument("--jac-only", action="store_true",
+                    help="time config 4's Newton Jacobian apply alone (flushed launches)")
     ap.add_argument("--amg-only", action="store_true",
                     help="time only one AMG V-cycle (precision --part-prec) and print its figures")
     ap.add_argument("--part-prec", default="bf16", choices=["fp64", "fp32", "bf16"])
@@ -701,6 +736,9 @@ def main() -> int:
 
     B.lib()
     torch.cuda.set_device(0)
+    if args.jac_only:
+        print(json.dumps(jac_only(args, torch)))
+        return 0
     pr = make_problem(args.config)
     log(f"[bench] config {args.config}: n={pr.mesh.n} M={pr.M} p={pr.p} subdomains={pr.n_sub}")
     if args.sweep:
