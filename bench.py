@@ -582,7 +582,7 @@ def bench_newton(args, torch):
 
     out = {}
     pr = make_problem("c4")
-    with GpuNewton(pr, ortho=args.ortho) as g:
+    with GpuNewton(pr, ortho=args.ortho, ras_path=args.newton_ras) as g:
         U, info = g.solve(tol=1e-8)                      # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -601,6 +601,7 @@ def bench_newton(args, torch):
         ms_rb = (time.perf_counter() - t0) * 1e3 / args.steps
     out["coarse_rebuilt_every_step"] = dict(ms=round(ms_rb, 3), krylov_its=info_rb["krylov_its"],
                                             ms_setup=round(info_rb["ms_setup"], 3))
+    out["ras_path"] = args.newton_ras
     out["zero_guess"] = dict(ms=round(ms, 3), steps=info["steps"], krylov_its=info["krylov_its"],
                              relres=info["relres"], ms_eval=round(info["ms_eval"], 3),
                              ms_setup=round(info["ms_setup"], 3),
@@ -610,7 +611,7 @@ def bench_newton(args, torch):
     # the paper's model kappa(u) = 1 + u: its Picard linearisation (stopped at
     # ||dU|| <= 1e-6 ||U||, the paper's criterion) against Newton (to
     # ||R|| / ||F|| <= 1e-8), both from the zero guess
-    with GpuNewton(pr, a1=1.0, a2=0.0, ortho=args.ortho) as gp:
+    with GpuNewton(pr, a1=1.0, a2=0.0, ortho=args.ortho, ras_path=args.newton_ras) as gp:
         res, sol = {}, {}
         for meth, kw in (("newton", dict(tol=1e-8)),
                          ("picard", dict(tol=1e-14, du_tol=1e-6, method="picard",
@@ -635,7 +636,7 @@ def bench_newton(args, torch):
         f"{res['picard']['krylov_its']} its; difference {res['picard_vs_newton_rel_diff']:.2e}")
     if args.learned_draws <= 0:
         return out
-    lg = LearnedGuess("c4", max_batch=16, seed=0, ortho=args.ortho)
+    lg = LearnedGuess("c4", max_batch=16, seed=0, ortho=args.ortho, ras_path=args.newton_ras)
     try:
         ds = lg.generate(draw_params(args.learned_draws, seed=0))
         lg.fit_output_scale(ds)
@@ -711,6 +712,9 @@ def main() -> int:
     ap.add_argument("--parts", type=int, default=1,
                     help="also time one RAS apply and one AMG V-cycle of the mixed solver alone")
     ap.add_argument("--newton", type=int, default=1, help="also time config 4 (Newton)")
+    ap.add_argument("--newton-ras", default="auto",
+                    choices=["auto", "sweep", "dense", "dense32", "fused"],
+                    help="RAS apply path of the config-4 solves (auto: the autotuner's pick)")
     ap.add_argument("--geometric", type=int, default=1,
                     help="also time config 1 with the geometric coarse space (ratios 16, 32)")
     ap.add_argument("--faithful", type=int, default=1,

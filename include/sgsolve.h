@@ -592,6 +592,9 @@ typedef struct {
     int amg_rebuild;     /* coarse-solver rebuild interval in steps (>= 0) */
     int method;          /* SG_NEWTON or SG_PICARD                       */
     double du_tol;       /* stop on ||lambda d|| <= du_tol ||U|| (0: off) */
+    int ras_path;        /* RAS apply path, kept through the refactorisations:
+                            0 sweep, 1..3 as in ras_select, -1 the fastest
+                            of ras_autotune at the first step            */
 } sg_newton_opts;
 
 enum { SG_NEWTON = 0, SG_PICARD = 1 };

@@ -48,11 +48,14 @@ class KrylovStats(C.Structure):
                 ("history", _f64p), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
+NL_RAS_PATHS = {"auto": -1, "sweep": 0, "dense": 1, "dense32": 2, "fused": 3}
+
+
 class NewtonOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int), ("tol", C.c_double), ("eta_max", C.c_double),
                 ("restart", C.c_int), ("max_it", C.c_int), ("omega", C.c_double),
                 ("use_graph", C.c_int), ("ortho", C.c_int), ("amg_rebuild", C.c_int),
-                ("method", C.c_int), ("du_tol", C.c_double)]
+                ("method", C.c_int), ("du_tol", C.c_double), ("ras_path", C.c_int)]
 
 
 SG_NEWTON, SG_PICARD = 0, 1
@@ -656,11 +659,14 @@ def newton_solve(nl, owner: np.ndarray, n_sub: int, overlap: int, prec: int, coa
                  restart: int = 50, max_it: int = 1000, omega: float = 0.0,
                  use_graph: bool = False, history_cap: int = 64, ortho: str = "mgs",
                  amg_rebuild: int = 0, method: str = "newton", du_tol: float = 0.0,
-                 stream=None):
-    """method "newton" or "picard"; du_tol > 0 also stops on ||lambda d|| <= du_tol ||U||."""
+                 ras_path: str = "sweep", stream=None):
+    """method "newton" or "picard"; du_tol > 0 also stops on ||lambda d|| <= du_tol ||U||;
+    ras_path "sweep", "dense", "dense32", "fused" or "auto" (ras_autotune at the
+    first step)."""
     owner = np.ascontiguousarray(owner, dtype=np.int32)
     opts = NewtonOpts(max_steps, tol, eta_max, restart, max_it, omega, 1 if use_graph else 0,
-                      ORTHO[ortho], amg_rebuild, NL_METHODS[method], du_tol)
+                      ORTHO[ortho], amg_rebuild, NL_METHODS[method], du_tol,
+                      NL_RAS_PATHS[ras_path])
     hist = np.zeros(history_cap, dtype=np.float64)
     kits = np.zeros(history_cap, dtype=np.int32)
     st = NewtonStats()

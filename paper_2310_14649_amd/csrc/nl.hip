@@ -599,6 +599,7 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
         SG_REQUIRE(opts->method == SG_NEWTON || opts->method == SG_PICARD,
                    "method must be SG_NEWTON or SG_PICARD");
         SG_REQUIRE(opts->du_tol >= 0.0, "du_tol must be >= 0");
+        SG_REQUIRE(opts->ras_path >= -1 && opts->ras_path <= 3, "ras_path outside [-1,3]");
         const bool picard = opts->method == SG_PICARD;
         const size_t need = newton_ws(nl->n, nl->P, n_sub, coarse, opts->restart);
         if (!ws || ws_bytes < need)
@@ -661,6 +662,12 @@ int newton_solve(sg_nl* nl, const int32_t* owner, int n_sub, int overlap, sg_pre
                 check_status(ras_setup(nl->j1.get(), owner, n_sub, overlap, prec, &r, stream),
                              "ras_setup");
                 ras.reset(r);
+                // the apply path chosen once; a refactorisation keeps it (and
+                // rebuilds the dense rows of a dense path)
+                if (opts->ras_path < 0)
+                    check_status(ras_autotune(ras.get(), 3, nullptr, stream), "ras_autotune");
+                else if (opts->ras_path > 0)
+                    check_status(ras_select(ras.get(), opts->ras_path, stream), "ras_select");
             } else {
                 check_status(ras_refactor(ras.get(), nl->j1.get(), stream), "ras_refactor");
             }

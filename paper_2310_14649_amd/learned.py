@@ -69,7 +69,7 @@ class LearnedGuess:
 
     def __init__(self, name: str = "c4", nc: Optional[int] = None, max_batch: int = 16,
                  channels: Optional[List[int]] = None, seed: int = 0, prec: str = "fp64",
-                 ortho: str = "mgs"):
+                 ortho: str = "mgs", ras_path: str = "sweep"):
         import torch
         self.torch = torch
         self.name = name
@@ -78,7 +78,7 @@ class LearnedGuess:
         self.mesh = self.base.mesh
         self.M, self.P = self.base.M, None
         self.H = self.W = self.mesh.nc - 1
-        self.solver = GpuNewton(self.base, prec=prec, ortho=ortho)
+        self.solver = GpuNewton(self.base, prec=prec, ortho=ortho, ras_path=ras_path)
         self.P = self.solver.P
         self.channels = list(channels or [1 + self.M, 64, 64, 64, self.P])
         assert self.channels[0] == 1 + self.M and self.channels[-1] == self.P

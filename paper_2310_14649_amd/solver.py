@@ -196,12 +196,13 @@ class GpuNewton:
     def __init__(self, pr: Problem, a2: float = 0.5, prec: str = "fp64", coarse: str = "amg",
                  overlap: Optional[int] = None, owner: Optional[np.ndarray] = None,
                  n_sub: Optional[int] = None, stream=None, a1: float = 0.0,
-                 ortho: str = "mgs"):
+                 ortho: str = "mgs", ras_path: str = "sweep"):
         import torch
         self.torch = torch
         self.pr = pr
         self.stream = stream
         self.ortho = ortho
+        self.ras_path = ras_path         # default of solve(): see binding.newton_solve
         self.basis = self.nl = None
         m = pr.mesh
         self.basis = B.sg_build_triples(pr.M, pr.p_in, pr.p)
@@ -240,15 +241,16 @@ class GpuNewton:
     def solve(self, U0=None, tol: float = 1e-8, max_steps: int = 30, restart: Optional[int] = None,
               max_it: int = 1000, eta_max: float = 1e-2, omega: float = 0.0,
               use_graph: bool = False, amg_rebuild: int = 0, method: str = "newton",
-              du_tol: float = 0.0):
+              du_tol: float = 0.0, ras_path: Optional[str] = None):
         restart = self.pr.restart if restart is None else restart
+        ras_path = self.ras_path if ras_path is None else ras_path
         U = self.new_vec() if U0 is None else U0.clone()
         info = B.newton_solve(self.nl, self.owner, self.n_sub, self.overlap, B.PREC[self.prec],
                               COARSE[self.coarse], U, self.workspace(restart), max_steps=max_steps,
                               tol=tol, eta_max=eta_max, restart=restart, max_it=max_it,
                               omega=omega, use_graph=use_graph, amg_rebuild=amg_rebuild,
                               method=method, du_tol=du_tol, ortho=self.ortho,
-                              stream=self.stream)
+                              ras_path=ras_path, stream=self.stream)
         return U, info
 
     def close(self):

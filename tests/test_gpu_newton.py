@@ -233,6 +233,24 @@ def test_newton_matches_oracle(case, coarse, ortho):
     assert len(h) == info["steps"] + 1 and np.all(np.diff(h) < 0)
 
 
+@pytest.mark.parametrize("ras_path", ["dense", "dense32", "auto"])
+def test_newton_with_dense_ras_matches_oracle(ras_path):
+    """The RAS apply path chosen for the solve (dense inverse rows, or the
+    autotuner's pick at the first step) is kept through the refactorisations
+    of later steps: the same fixed point as the oracle's Newton, and the
+    same step count."""
+    _cuda()
+    pr = _problem("m4p3")
+    onl_pr = _oracle(pr)
+    U_ref, info_ref = onl.newton(onl_pr, tol=1e-12)
+    with GpuNewton(pr, ortho="block3") as g:
+        U, info = g.solve(tol=1e-12, restart=30, ras_path=ras_path, use_graph=True)
+        U = _host(U, U_ref.shape)
+    assert info["converged"], info
+    assert info["steps"] >= 2 and abs(info["steps"] - info_ref.steps) <= 1
+    assert _rel(U, U_ref) < 1e-8
+
+
 def test_newton_config4_converges_and_is_reproducible():
     """The benchmark workload: N_c = 128, M = 4, P = 35, 8 x 8 subdomains,
     FGMRES(50) with RAS + SA-AMG, to ||R||/||F|| <= 1e-8."""
