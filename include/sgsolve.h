@@ -189,9 +189,10 @@ int sg_matvec_kernel(const sg_op* op, int* kind);
  * built for input bases with L > 32 terms and P <= 48 output modes, on
  * patterns of at most 7 entries per row whose neighbour rows form at most 4
  * runs of at most 256 rows per tile (lattice-ordered P1 meshes), e.g. the
- * Jacobian and secant operators of sg_nl_setup; SG_ERR_UNSUPPORTED when
- * enabling an operator without it.  Cached graphs of the operator are
- * dropped on a change.  Host call. */
+ * Jacobian and secant operators of sg_nl_setup (the handles that
+ * sg_nl_jac_op and sg_nl_mean_op return may be passed, cast from const);
+ * SG_ERR_UNSUPPORTED when enabling an operator without it.  Cached graphs of
+ * the operator are dropped on a change.  Host call. */
 int sg_matvec_row_tiled(sg_op* op, int enable);
 /* sg_matvec_matrix_free -- apply the operator without reading its stored
  * values (the matrix-free approach the paper names as future work, Sec. 5):
