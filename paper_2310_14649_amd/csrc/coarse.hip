@@ -17,7 +17,6 @@
 #include <cmath>
 #include <map>
 #include <numeric>
-#include <thread>
 #include <tuple>
 #include <type_traits>
 
@@ -539,65 +538,36 @@ inline void gemm_acc(int P, const double* A, const double* B, double* C) {
         }
 }
 
-// Rows of C = A B are independent: they are formed on host threads (the
-// P x P block products dominate the hierarchy's setup), each row with the
-// same arithmetic and order as one thread would use, then concatenated.
 Bsr bsr_mul(const Bsr& A, const Bsr& B) {
     const int P = A.P;
-    const size_t bs = (size_t)P * P;
     Bsr C;
     C.nr = A.nr; C.nc = B.nc; C.P = P;
     C.ptr.assign(A.nr + 1, 0);
-    std::vector<std::vector<int32_t>> rcol(A.nr);
-    std::vector<std::vector<double>> rval(A.nr);
-    auto rows = [&](int s0, int s1) {
-        for (int s = s0; s < s1; ++s) {
-            std::map<int, size_t> slot;
-            std::vector<double> blocks;
-            for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
-                int t = A.col[q];
-                for (int q2 = B.ptr[t]; q2 < B.ptr[t + 1]; ++q2) {
-                    int u = B.col[q2];
-                    auto it = slot.find(u);
-                    size_t idx;
-                    if (it == slot.end()) {
-                        idx = slot.size();
-                        slot[u] = idx;
-                        blocks.resize((idx + 1) * bs, 0.0);
-                    } else {
-                        idx = it->second;
-                    }
-                    gemm_acc(P, A.blk(q), B.blk(q2), blocks.data() + idx * bs);
+    std::vector<double> acc;
+    for (int s = 0; s < A.nr; ++s) {
+        std::map<int, size_t> slot;
+        std::vector<double> blocks;
+        for (int q = A.ptr[s]; q < A.ptr[s + 1]; ++q) {
+            int t = A.col[q];
+            for (int q2 = B.ptr[t]; q2 < B.ptr[t + 1]; ++q2) {
+                int u = B.col[q2];
+                auto it = slot.find(u);
+                size_t idx;
+                if (it == slot.end()) {
+                    idx = slot.size();
+                    slot[u] = idx;
+                    blocks.resize((idx + 1) * (size_t)P * P, 0.0);
+                } else {
+                    idx = it->second;
                 }
-            }
-            rval[s].reserve(slot.size() * bs);
-            for (auto& kv : slot) {
-                rcol[s].push_back(kv.first);
-                rval[s].insert(rval[s].end(), blocks.begin() + kv.second * bs,
-                               blocks.begin() + (kv.second + 1) * bs);
+                gemm_acc(P, A.blk(q), B.blk(q2), blocks.data() + idx * (size_t)P * P);
             }
         }
-    };
-    // block products in the whole product, and threads at about 2e6
-    // multiply-adds each (at most 16)
-    int64_t prods = 0;
-    for (int q = 0; q < (int)A.col.size(); ++q) prods += B.ptr[A.col[q] + 1] - B.ptr[A.col[q]];
-    const int64_t fmas = prods * (int64_t)P * P * P;
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nt = (int)std::min<int64_t>({(int64_t)hw, 16, 1 + fmas / 2000000,
-                                           (int64_t)std::max(1, A.nr)});
-    if (nt <= 1) {
-        rows(0, A.nr);
-    } else {
-        std::vector<std::thread> th;
-        th.reserve(nt);
-        for (int k = 0; k < nt; ++k)
-            th.emplace_back(rows, (int)((int64_t)A.nr * k / nt), (int)((int64_t)A.nr * (k + 1) / nt));
-        for (auto& t : th) t.join();
-    }
-    for (int s = 0; s < A.nr; ++s) {
-        C.col.insert(C.col.end(), rcol[s].begin(), rcol[s].end());
-        C.val.insert(C.val.end(), rval[s].begin(), rval[s].end());
+        for (auto& kv : slot) {
+            C.col.push_back(kv.first);
+            C.val.insert(C.val.end(), blocks.begin() + kv.second * (size_t)P * P,
+                         blocks.begin() + (kv.second + 1) * (size_t)P * P);
+        }
         C.ptr[s + 1] = (int32_t)C.col.size();
     }
     return C;
